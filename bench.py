@@ -1,0 +1,223 @@
+"""Benchmark: time per implicit step of the Newton-Krylov-Schwarz hot path on one GPU.
+
+Default workload: 2D 512x512 log-normal reservoir (sigma 1, correlation
+length 8 cells), five-spot wells, BDF2 steps of 5 days, two-level V-cycle
+RAS with 256 subdomains (overlap 2 fine / 1 coarse), FGMRES(30), FP64.
+A step is one full implicit time step: residual + PR, Jacobian, subdomain
+ILU(0) and Galerkin setup, preconditioned FGMRES, line search, per Newton
+iteration, to relative residual 1e-6.
+
+Prints one JSON line.  `roofline` is the fine-level one-level Schwarz apply
+(the ras_apply kernel), timed with HIP events on its stream inside the timed
+region; `cpu_baseline` times the CPU oracle on the first steps of the same
+workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "time/implicit step + ras_apply GB/s, mixed-prec vs FP64 at rel.res 1e-6"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def ext_cells(nx, ny, nz, px, py, pz, delta):
+    """Cells of all overlapping boxes (box q gets n//P + (q < n%P), extended by
+    delta and clipped at the boundary)."""
+    def ext1(n, P):
+        P = min(P, n)
+        base, rem = divmod(n, P)
+        out, lo = [], 0
+        for q in range(P):
+            hi = lo + base + (1 if q < rem else 0)
+            out.append(min(n, hi + delta) - max(0, lo - delta))
+            lo = hi
+        return out
+    ex, ey, ez = ext1(nx, px), ext1(ny, py), ext1(nz, pz)
+    return sum(a * b * c for a in ex for b in ey for c in ez)
+
+
+def apply_bytes(rec, s, precision):
+    """Algorithmic bytes of one fine-level one-level Schwarz apply: per
+    extended cell the off-diagonal factors, 1/u_ii and the gathered residual;
+    per owned cell the written correction."""
+    K = 7 if rec.nz > 1 else 5
+    fb = {"fp64": 8, "fp32": 4, "bf16": 2}[precision]
+    db = 8 if precision == "fp64" else 4
+    ne = ext_cells(rec.nx, rec.ny, rec.nz, s.px, s.py, s.pz, s.overlap[0])
+    return ne * ((K - 1) * fb + db + 8) + rec.N * 8, ne
+
+
+def run_gpu(P, case, settings, warmup, steps, profile=True):
+    import torch
+    g = P.Grid(case.problems)
+    p = g.initial_pressure()
+    hist = [p.clone()]
+
+    def step(n):
+        order = 1 if n == 0 else 2
+        pn = hist[-1]
+        pnm1 = hist[-2] if len(hist) > 1 else hist[-1]
+        pnew = pn.clone()
+        st = g.newton_step(pnew, pn, pnm1, case.dt, order, settings)
+        hist.append(pnew)
+        if len(hist) > 3:
+            hist.pop(0)
+        return st
+
+    for n in range(warmup):
+        step(n)
+    torch.cuda.synchronize()
+    p_start = hist[-1].clone()
+    if profile:
+        P.check(P.lib().nks_profile_enable(1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step(warmup + k) for k in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {}
+    if profile:
+        import ctypes as C
+        for name in ["ras_apply_l0", "ras_apply_l1", "ras_apply_l2", "spmv_l0", "spmv_l1",
+                     "gmres_orth", "residual_jacobian", "ilu_factor_l0", "ilu_factor_l1", "rap_l1"]:
+            c, ms = C.c_int(), C.c_double()
+            P.check(P.lib().nks_profile_query(name.encode(), C.byref(c), C.byref(ms)))
+            if c.value:
+                prof[name] = (c.value, ms.value)
+        P.check(P.lib().nks_profile_enable(0))
+    return dict(seconds=t1 - t0, stats=stats, prof=prof, p_start=p_start.cpu().numpy(),
+                p_end=hist[-1].cpu().numpy())
+
+
+def cpu_baseline(case, nsteps):
+    import oracle
+    rec = case.problems[0]
+    prob = oracle.Problem(rec)
+    p = prob.initial_pressure()
+    hist = [p]
+    t0 = time.perf_counter()
+    for n in range(nsteps):
+        order = 1 if n == 0 else 2
+        pnm1 = hist[-2] if len(hist) > 1 else hist[-1]
+        p, st = oracle.newton_step(prob, case.solver, hist[-1], hist[-1], pnm1, case.dt, order)
+        hist.append(p)
+    return (time.perf_counter() - t0) / nsteps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding is a design, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import synthetic as S
+    import paper_2007_13966_amd as P
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    case = {"c1": S.case_c1, "c2": S.case_c2, "c3": S.case_c3, "c4": S.case_c4}[args.workload]()
+    s64 = S.with_solver(case, precision="fp64").solver if args.workload != "c2" else case.solver
+    log(f"workload {case.name}: {sum(r.N for r in case.problems)} cells")
+    r64 = run_gpu(P, case, s64, args.warmup, args.steps)
+    st = r64["stats"]
+    sec = r64["seconds"] / args.steps
+    nits = [x["newton_its"] for x in st]
+    lits = [x["linear_its"] for x in st]
+    log(f"fp64: {sec:.4f} s/step, newton {nits}, gmres {lits}")
+    rec = case.problems[0]
+    nbytes, nexts = apply_bytes(rec, s64, "fp64")
+    cnt, ms = r64["prof"].get("ras_apply_l0", (0, 0.0))
+    avg_s = ms / 1e3 / max(cnt, 1)
+    achieved = nbytes / avg_s / 1e9 if cnt else None
+    out = {
+        "metric": METRIC,
+        "value": sec,
+        "unit": "s/implicit step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": case.name,
+            "description": " ".join((case.description or "").split()),
+            "cells": sum(r.N for r in case.problems),
+            "levels": s64.levels, "subdomains": s64.px * s64.py * s64.pz,
+            "overlap": list(s64.overlap), "precision": s64.precision,
+            "newton_its_per_step": float(np.mean(nits)),
+            "gmres_its_per_newton": float(np.sum(lits) / max(1, np.sum(nits))),
+            "rel_res": s64.eps_r,
+        },
+        "roofline": {
+            "kernel": "k_ras_apply (fine level, one-level left-RAS ILU(0) sweeps)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": None,
+            "bytes_per_launch": nbytes,
+            "ext_cells": nexts,
+            "launches": cnt,
+            "avg_launch_us": avg_s * 1e6,
+        },
+        "kernels_ms": {k: {"count": c, "total_ms": round(t, 3), "avg_us": round(1e3 * t / c, 2)}
+                       for k, (c, t) in r64["prof"].items()},
+    }
+    if not args.no_mixed:
+        s32 = S.with_solver(case, precision="fp32").solver
+        r32 = run_gpu(P, case, s32, args.warmup, args.steps)
+        sec32 = r32["seconds"] / args.steps
+        d64 = r64["p_end"] - r64["p_start"]
+        d32 = r32["p_end"] - r32["p_start"]
+        err = float(np.linalg.norm(d32 - d64) / max(np.linalg.norm(d64), 1e-300))
+        b32, _ = apply_bytes(rec, s32, "fp32")
+        c32, ms32 = r32["prof"].get("ras_apply_l0", (0, 0.0))
+        a32 = b32 / (ms32 / 1e3 / max(c32, 1)) / 1e9 if c32 else None
+        out["mixed_fp32"] = {
+            "s_per_step": sec32,
+            "speedup_vs_fp64": sec / sec32,
+            "gmres_its_per_newton": float(sum(x["linear_its"] for x in r32["stats"]) /
+                                          max(1, sum(x["newton_its"] for x in r32["stats"]))),
+            "dp_rel_error_vs_fp64": err,
+            "ras_apply_l0_gbs": a32,
+            "ras_apply_l0_frac": (a32 / HBM_PEAK_GBS) if a32 else None,
+        }
+        log(f"fp32 preconditioner: {sec32:.4f} s/step, dp error vs fp64 {err:.2e}")
+    if not args.no_cpu_baseline and args.workload == "c2":
+        n = args.cpu_steps
+        v = cpu_baseline(case, n)
+        out["cpu_baseline"] = {"value": v, "unit": "s/implicit step", "cores": 1, "kind": "oracle",
+                               "sample": f"first {n} implicit steps (BDF1 then BDF2) of the same "
+                                         f"512x512 workload, single-threaded C oracle"}
+        log(f"cpu oracle: {v:.3f} s/step")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

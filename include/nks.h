@@ -1,0 +1,256 @@
+/*
+ * libnks -- C ABI of the MI355X (gfx950) Newton-Krylov-Schwarz hot path for
+ * fully implicit compressible gas flow with the Peng-Robinson equation of
+ * state (arXiv 2007.13966: Li, Yang, Yang, "multilevel restricted Schwarz
+ * preconditioners").
+ *
+ * Conventions shared by every entry point
+ *  - Cells of a reservoir are numbered lexicographically, x fastest:
+ *    cell (x,y,z) -> x + nx*(y + ny*z); z grows downward (depth).
+ *  - A grid may hold several independent reservoirs ("blocks") concatenated
+ *    in one cell range; reservoir b owns cells [off[b], off[b+1]).  Newton,
+ *    GMRES and the line search run independently per reservoir.
+ *  - Unless stated otherwise a "double*" argument is a DEVICE pointer of
+ *    length ncells owned by the caller; the library never frees it.
+ *  - Work is enqueued on the grid's stream (hipStream_t passed as void*).
+ *    Entry points returning statistics synchronise that stream.
+ *  - Every call returns 0 (NKS_OK) or a negative NKS_E* code;
+ *    nks_last_error() gives a thread-local message.  No C++ exception
+ *    crosses the ABI.  Handles are not thread safe.
+ *  - Units are SI: Pa, m, m^2 (permeability), kg/s (well rates, +injection),
+ *    s, K, kg/mol, J/(mol K), Pa s.
+ */
+#ifndef NKS_H
+#define NKS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NKS_OK 0
+#define NKS_EINVAL (-1)          /* bad argument or descriptor */
+#define NKS_EHIP (-2)            /* HIP runtime error */
+#define NKS_EZEROPIVOT (-3)      /* zero pivot in a subdomain ILU(0) factorization */
+#define NKS_ENONPHYSICAL (-4)    /* p <= 0, Z <= B or a non-finite value */
+#define NKS_ENOTCONVERGED (-5)   /* iteration limit or line-search failure; stats filled */
+#define NKS_ENOMEM (-6)          /* allocation failed */
+
+typedef struct nks_grid nks_grid;
+typedef struct nks_matrix nks_matrix;
+typedef struct nks_ras nks_ras;
+
+/* Device allocator callback pair (e.g. a framework's caching allocator).
+ * alloc returns a device pointer of at least `bytes` bytes or NULL. */
+typedef void *(*nks_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*nks_free_fn)(void *ptr, void *ctx);
+
+/* Fluid constants of Section 2: critical temperature Tc and pressure pc,
+ * acentric factor omega (m(omega) of the first fit for omega <= 0.491, the
+ * second above), temperature T, molar mass W, gas constant R, viscosity mu. */
+typedef struct {
+    double Tc, pc, omega, T, W, R, mu;
+} nks_fluid;
+
+/* One reservoir: nx*ny*nz cells of size dx*dy*dz (2D: nz = 1, dz is the
+ * thickness).  kx, ky, kz, phi: DEVICE arrays of nx*ny*nz values (diagonal
+ * permeability tensor, porosity); read during nks_setup_grid only.
+ * Wells: HOST arrays of nwells reservoir-local cell indices and mass rates. */
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dz;
+    const double *kx, *ky, *kz, *phi;
+    int nwells;
+    const int *well_cell;
+    const double *well_rate;
+} nks_reservoir_desc;
+
+typedef struct {
+    int nres;                        /* number of reservoirs, >= 1 */
+    const nks_reservoir_desc *res;   /* HOST array of nres descriptors */
+    nks_fluid fluid;
+    int gravity;                     /* 0: g = 0 */
+    double g;                        /* gravitational acceleration */
+    void *stream;                    /* hipStream_t; NULL = default stream */
+    nks_alloc_fn alloc;              /* NULL: hipMalloc / hipFree */
+    nks_free_fn free;
+    void *alloc_ctx;
+} nks_grid_desc;
+
+/* Builds the face transmissibilities T = A_f / (d/(2K_i) + d/(2K_j))
+ * (two-point flux of the cell-centred scheme, Section 2 Remark 1), pore
+ * volumes and the well source term Q R T / W.  Copies what it needs. */
+int nks_setup_grid(const nks_grid_desc *desc, nks_grid **out);
+int nks_destroy_grid(nks_grid *g);
+/* ncells: total cells; nres: reservoirs; offsets: HOST array of nres+1
+ * (may be NULL). */
+int nks_grid_info(const nks_grid *g, int *ncells, int *nres, int *offsets);
+
+/* Hydrostatic initial state: p = p_top in the top layer and, down every
+ * column, p_{k+1} - p_k = (rho_k + rho_{k+1})/2 g dz.  p: device, out. */
+int nks_hydrostatic_init(nks_grid *g, double p_top, double *p);
+
+/* Residual of eq. gover_sys integrated over each cell, in conservative form:
+ *   F_i = (V phi_i / dt) Acc_i + sum_j T_ij lambda_up dPhi_ij - Q_i R T / W
+ * with m = p/Z (Z the largest real root of eq. PR), lambda = m/mu from the
+ * upwind cell of dPhi_ij = (p_i - p_j) - (rho_i + rho_j)/2 g (h_i - h_j),
+ * Acc = m - m^n (bdf_order 1, eq. implicit-method-bdf1) or
+ * (3m - 4m^n + m^{n-1})/2 (bdf_order 2, eq. implicit-method-bdf2).
+ * p, p_n, p_nm1 (ignored for order 1), F: device arrays.  Asynchronous. */
+int nks_residual(nks_grid *g, const double *p, const double *p_n, const double *p_nm1,
+                 double dt, int bdf_order, double *F);
+
+/* Sparse Jacobian dF/dp of nks_residual (Section 3, eq. jacobian1), stored
+ * as a structured stencil (5 points in 2D, 7 in 3D), FP64.  Writes F too
+ * when F != NULL.  J must come from nks_matrix_create on the same grid. */
+int nks_matrix_create(nks_grid *g, nks_matrix **out);
+int nks_destroy_matrix(nks_matrix *J);
+int nks_jacobian(nks_grid *g, const double *p, const double *p_n, const double *p_nm1,
+                 double dt, int bdf_order, nks_matrix *J, double *F);
+/* nnz of the CSR form; export to HOST arrays (rowptr ncells+1, col/val nnz),
+ * columns sorted, structural zeros at closed faces dropped.  Synchronises. */
+int nks_matrix_nnz(const nks_matrix *J, int *nnz);
+int nks_matrix_export_csr(const nks_matrix *J, int *rowptr, int *col, double *val);
+/* y = J x and y = J^T x (device).  Asynchronous. */
+int nks_matrix_apply(nks_matrix *J, const double *x, double *y);
+int nks_jacobian_transpose_apply(nks_matrix *J, const double *x, double *y);
+/* out = (dF/d theta)^T lam with theta_c = ln of a multiplier on all K
+ * components of cell c (device arrays).  Asynchronous. */
+int nks_residual_dlogk_transpose_apply(nks_grid *g, const double *p, const double *lam,
+                                       double *out);
+
+/* Multilevel restricted additive Schwarz preconditioner (Section 3).
+ * Subdomains: px*py*pz boxes per reservoir, box q of P along n cells gets
+ * floor(n/P) + (q < n mod P) cells, extended by `overlap` and clipped at the
+ * domain boundary; the same box grid on every level.  Subdomain solve:
+ * ILU(0) of R_i^delta A R_i^delta^T in local lexicographic order.
+ * Levels: ratio 2 per direction (nz = 1 stays 1), interpolation of
+ * eq. inter-frist (1), inter-second (2) or inter-third (3), restriction
+ * P^T, Galerkin coarse operators P^T A P; coarsest level solved by GMRES
+ * with the one-level preconditioner to coarse_rtol (Remark 2). */
+#define NKS_LEFT_RAS 0           /* eq. as-left  (default) */
+#define NKS_AS 1                 /* eq. as-class */
+#define NKS_RIGHT_RAS 2          /* eq. as-right */
+#define NKS_VCYCLE 0             /* eq. v-cycle with mu/nu smoothing steps */
+#define NKS_LEFT_KASKADE 1       /* eq. left-Kas  */
+#define NKS_RIGHT_KASKADE 2      /* eq. right-Kas */
+#define NKS_ADDITIVE 3           /* eq. two-additive */
+#define NKS_COARSE_ONLY 4        /* eq. coarse-level */
+#define NKS_FP64 0               /* factors and subdomain sweeps in FP64 */
+#define NKS_FP32 1               /* FP32 factors, FP32 sweeps */
+#define NKS_BF16 2               /* BF16 off-diagonal factors, FP32 1/diag and sweeps */
+
+typedef struct {
+    int px, py, pz;
+    int levels;                  /* >= 1, at most 6 */
+    int overlap[8];              /* per level, index 0 = finest */
+    int variant;                 /* NKS_LEFT_RAS | NKS_AS | NKS_RIGHT_RAS */
+    int interp_order;            /* 1, 2 (default), 3 */
+    int cycle;                   /* NKS_VCYCLE ... */
+    int mu, nu;                  /* smoothing steps of the V-cycle family */
+    double coarse_rtol;          /* 0.2 in the paper */
+    int coarse_maxit;
+    int coarse_restart;
+    int precision;               /* NKS_FP64 | NKS_FP32 | NKS_BF16 */
+} nks_ras_desc;
+
+/* Creates (*inout == NULL) or refactors in place (*inout from an earlier
+ * call on a matrix of the same grid and an identical descriptor).  Keeps a
+ * reference to J: J must outlive the preconditioner.  Asynchronous.  A zero
+ * pivot is reported by the next synchronising call as NKS_EZEROPIVOT. */
+int nks_ras_setup(nks_matrix *J, const nks_ras_desc *d, nks_ras **inout);
+int nks_destroy_ras(nks_ras *M);
+/* z = M^{-1} r on the finest level (device).  Runs the coarse GMRES, so it
+ * synchronises when levels > 1. */
+int nks_ras_apply(nks_ras *M, const double *r, double *z);
+/* One-level Schwarz apply on `level` (0 = finest) with vectors of that
+ * level's size (device).  Asynchronous. */
+int nks_ras_apply_level(nks_ras *M, int level, const double *r, double *z);
+/* z = M^{-T} r of the finest one-level preconditioner (device). */
+int nks_ras_apply_transpose(nks_ras *M, const double *r, double *z);
+/* info[0..7] = n, stencil points, subdomains, nx, ny, nz (first reservoir),
+ * number of levels, nnz of the level operator. Synchronises. */
+int nks_ras_level_info(nks_ras *M, int level, int *info);
+/* Level operator (Galerkin product on coarse levels) as CSR in HOST arrays. */
+int nks_ras_level_export(nks_ras *M, int level, int *rowptr, int *col, double *val);
+/* Restriction P^T (fine level -> level+1) and prolongation-add
+ * (level+1 -> fine: z += P e) on device vectors.  Asynchronous. */
+int nks_ras_restrict(nks_ras *M, int level, const double *r_fine, double *r_coarse);
+int nks_ras_prolong_add(nks_ras *M, int level, const double *e_coarse, double *z_fine);
+
+/* Right-preconditioned GMRES(restart) / FGMRES(restart) (Section 3,
+ * eq. jacobian; Remark 2): x holds the initial guess (zero it for x0 = 0);
+ * stops per reservoir when ||b - J x|| <= max(rtol ||b||, atol).
+ * Orthogonalisation: classical Gram-Schmidt with one reorthogonalisation,
+ * FP64.  transpose != 0 solves J^T x = b with M^{-T} (one-level only). */
+typedef struct {
+    int restart;
+    double rtol, atol;
+    int maxit;
+    int flexible;
+    int transpose;
+} nks_gmres_desc;
+
+typedef struct {
+    int iterations;              /* max over reservoirs */
+    int total_iterations;        /* sum over reservoirs */
+    double residual;             /* max over reservoirs of the final ||r|| */
+    int converged;               /* reservoirs that met the tolerance */
+    int *its;                    /* optional HOST array [nres]: iterations */
+    double *res;                 /* optional HOST array [nres]: final ||r|| */
+} nks_gmres_stats;
+
+int nks_gmres_solve(nks_matrix *J, nks_ras *M, const double *b, double *x,
+                    const nks_gmres_desc *d, nks_gmres_stats *st);
+
+/* One implicit time step (Section 3): X^{k+1} = X^k + lambda s with
+ * J s = -F solved by Schwarz-preconditioned (F)GMRES to
+ * max{eta_r ||F||, eta_a}, lambda from a cubic backtracking line search with
+ * ||F(X + lambda s)|| <= (1 - alpha lambda)||F(X)||, until
+ * ||F|| <= max{eps_r ||F(X^0)||, eps_a} or ||lambda s|| <= stol ||X|| in every
+ * reservoir (the step test is that of the PETSc solver used in Section 4).
+ * p: device in (initial guess, usually p_n) / out. */
+typedef struct {
+    double eps_r, eps_a;
+    double eta_r, eta_a;
+    int restart, maxit;
+    int flexible;                /* -1: FGMRES iff levels > 1 or precision != FP64 */
+    double alpha;
+    int max_newton, max_backtracks;
+    double stol;                 /* also stop when ||lambda s|| <= stol ||X^{k+1}|| (0: off) */
+} nks_newton_desc;
+
+typedef struct {
+    int newton_its;              /* max over reservoirs */
+    int linear_its;              /* sum over Newton iterations of the max over reservoirs */
+    int status;                  /* 0 ok, 1 Newton limit, 2 line search failed, 3 non-physical */
+    double fnorm0, fnorm;        /* max over reservoirs */
+    double fnorms[64];           /* max over reservoirs after each iteration */
+    int lits[64];
+    double lambdas[64];          /* min over active reservoirs */
+    double t_residual, t_jacobian, t_setup, t_gmres, t_linesearch;  /* seconds */
+} nks_newton_stats;
+
+int nks_newton_step(nks_grid *g, double *p, const double *p_n, const double *p_nm1,
+                    double dt, int bdf_order, const nks_newton_desc *nd,
+                    const nks_ras_desc *rd, nks_newton_stats *st);
+
+/* Kernel timing with HIP events recorded on the launching stream around the
+ * named hot-path launches: "ras_apply_l<level>" (one-level Schwarz sweeps),
+ * "ilu_factor_l<level>", "rap_l<level>", "spmv", "gmres_orth",
+ * "residual_jacobian".  enable != 0 clears the records and starts
+ * recording, 0 stops.  query synchronises and returns the number of
+ * launches and their summed duration (ms); unknown names give 0. */
+int nks_profile_enable(int enable);
+int nks_profile_query(const char *name, int *count, double *total_ms);
+
+/* Thread-local message of the last failing call (empty when none). */
+const char *nks_last_error(void);
+/* Library version string. */
+const char *nks_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

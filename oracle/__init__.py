@@ -43,7 +43,7 @@ class NewtonDesc(C.Structure):
     _fields_ = [("eps_r", C.c_double), ("eps_a", C.c_double), ("eta_r", C.c_double),
                 ("eta_a", C.c_double), ("restart", C.c_int), ("maxit", C.c_int),
                 ("flexible", C.c_int), ("alpha", C.c_double), ("max_newton", C.c_int),
-                ("max_backtracks", C.c_int)]
+                ("max_backtracks", C.c_int), ("stol", C.c_double)]
 
 
 class NewtonStats(C.Structure):
@@ -253,6 +253,7 @@ def newton_desc(s):
     d.flexible = 1 if flex else 0
     d.alpha = s.alpha
     d.max_newton, d.max_backtracks = s.max_newton, s.max_backtracks
+    d.stol = s.stol
     return d
 
 

@@ -1200,7 +1200,10 @@ static int nonphysical(const orc_problem *pr, const double *p) {
  * preconditioned (F)GMRES to max{eta_r ||F||, eta_a}; lambda^k by a cubic
  * backtracking line search (Dennis-Schnabel) until
  * ||F(X^k + lambda s)|| <= (1 - alpha lambda) ||F(X^k)||; stop when
- * ||F(X^{k+1})|| <= max{eps_r ||F(X^0)||, eps_a}. */
+ * ||F(X^{k+1})|| <= max{eps_r ||F(X^0)||, eps_a}, or when the accepted step
+ * is below stol relative to X^{k+1} (the relative step test of the PETSc
+ * solver used in Section 4; without it FP64 rounding of the residual can put
+ * eps_r ||F(X^0)|| below the attainable floor). */
 int orc_newton_step(const orc_problem *pr, const orc_mg_desc *md, const orc_newton_desc *nd,
                     double *p, const double *pn, const double *pnm1, double dt, int order,
                     orc_newton_stats *st) {
@@ -1275,6 +1278,8 @@ int orc_newton_step(const orc_problem *pr, const orc_mg_desc *md, const orc_newt
         st->newton_its = k + 1;
         if (k < 64) { st->fnorms[k] = fn; st->lambdas[k] = lam; }
         if (fn <= stop) status = 0;
+        /* relative step test of the PETSc nonlinear solver the paper ran on */
+        if (nd->stol > 0.0 && lam * norm2(N, s) <= nd->stol * norm2(N, p)) status = 0;
     }
     st->fnorm = fn;
     st->status = status;

@@ -41,6 +41,7 @@ typedef struct {
     int flexible;           /* FGMRES when nonzero */
     double alpha;           /* line-search sufficient decrease */
     int max_newton, max_backtracks;
+    double stol;            /* stop when ||lambda s|| <= stol ||X^{k+1}|| (0: off) */
 } orc_newton_desc;
 
 typedef struct {

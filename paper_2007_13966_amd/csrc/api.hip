@@ -1,0 +1,835 @@
+// C ABI of libnks: argument checks, handle lifetime, error translation, and
+// the host-side control of the inexact Newton step (Section 3).
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <cstdarg>
+#include <cstdio>
+
+#include "schwarz.h"
+
+namespace nks {
+
+static thread_local std::string g_last_error;
+
+std::string fmt(const char *f, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, f);
+    vsnprintf(buf, sizeof(buf), f, ap);
+    va_end(ap);
+    return buf;
+}
+
+void fail(int code, const char *f, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, f);
+    vsnprintf(buf, sizeof(buf), f, ap);
+    va_end(ap);
+    throw Error{code, buf};
+}
+
+void hip_check(hipError_t e, const char *what, const char *file, int line) {
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? NKS_ENOMEM : NKS_EHIP, "%s failed: %s (%s:%d)", what,
+             hipGetErrorString(e), file, line);
+    }
+}
+
+void *Alloc::get(size_t bytes) {
+    void *p = nullptr;
+    if (fa) {
+        p = fa(bytes, ctx);
+        if (!p) fail(NKS_ENOMEM, "allocator callback returned NULL for %zu bytes", bytes);
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(NKS_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        }
+    }
+    return p;
+}
+
+void Alloc::put(void *p) {
+    if (!p) return;
+    if (ff) ff(p, ctx);
+    else (void)hipFree(p);
+}
+
+// ------------------------------------------------------------------ profiling
+struct ProfRec {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+};
+static std::mutex g_prof_mu;
+static std::map<std::string, ProfRec> g_prof;
+static bool g_prof_on = false;
+static std::vector<hipEvent_t> g_event_pool;
+
+bool prof_on() { return g_prof_on; }
+
+static hipEvent_t take_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPC(hipEventCreate(&e));
+    return e;
+}
+
+ProfScope::ProfScope(const char *nm, hipStream_t st, int lvl) : s(st), name(nm), level(lvl) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    a = take_event();
+    b = take_event();
+    HIPC(hipEventRecord(a, s));
+}
+
+ProfScope::~ProfScope() {
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    (void)hipEventRecord(b, s);
+    std::string key = level >= 0 ? fmt("%s_l%d", name, level) : std::string(name);
+    g_prof[key].ev.push_back({a, b});
+}
+
+static void prof_clear() {
+    for (auto &kv : g_prof)
+        for (auto &p : kv.second.ev) {
+            g_event_pool.push_back(p.first);
+            g_event_pool.push_back(p.second);
+        }
+    g_prof.clear();
+}
+
+// launchers defined in physics.hip
+void grid_setup_kernels(Grid &g, const double *kx, const double *ky, const double *kz, const double *phi);
+void launch_history(Grid &g, const double *pn, const double *pnm1, int order);
+void launch_props(Grid &g, const double *p);
+void launch_flux(Grid &g, const double *p, double dt, int order, double *F, double *J);
+void launch_hydrostatic(Grid &g, double p_top, double *p);
+void launch_dlogk_t(Grid &g, const double *p, const double *lam, double *out);
+
+static inline int nblk(int n, int t) { return (n + t - 1) / t; }
+
+// pt = p + lam[b] s
+__global__ void k_trial(const Blk *blk, int B, int N, const double *p, const double *s, const double *lam,
+                        double *pt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int b = find_blk(blk, B, i);
+    pt[i] = p[i] + lam[b] * s[i];
+}
+
+__global__ void k_neg(int N, const double *x, double *y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) y[i] = -x[i];
+}
+
+__global__ void k_copy_mask(const Blk *blk, int B, int N, const double *x, double *y, const int *mask) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (mask[find_blk(blk, B, i)]) y[i] = x[i];
+}
+
+__global__ void k_zero(int N, double *x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) x[i] = 0.0;
+}
+
+// Newton workspace kept on the grid between calls
+struct NewtonWork {
+    DBuf<double> F, Ft, s, b, pt, Js, lam, red2;
+    DBuf<int> mask;
+    Reducer red;
+    std::unique_ptr<Matrix> J;
+    std::unique_ptr<Ras> M;
+    nks_ras_desc rd{};
+    Gmres gm;
+};
+
+static void stencil_fine(Stencil &st, int dim, Alloc *al, hipStream_t s) {
+    std::vector<int8_t> off;
+    if (dim == 3) off = {0, 0, -1, 0, -1, 0, -1, 0, 0, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1};
+    else off = {0, -1, 0, -1, 0, 0, 0, 0, 0, 1, 0, 0, 0, 1, 0};
+    st.off = off;
+    st.K = (int)off.size() / 3;
+    st.diag = st.K / 2;
+    st.R = 1;
+    st.doff.upload(al, off, s);
+}
+
+static bool same_desc(const nks_ras_desc &a, const nks_ras_desc &b) {
+    return memcmp(&a, &b, sizeof(a)) == 0;
+}
+
+}  // namespace nks
+
+using namespace nks;
+
+struct nks_grid {
+    Grid g;
+    std::unique_ptr<NewtonWork> nw;
+};
+struct nks_matrix {
+    Matrix m;
+    nks_grid *owner;
+};
+struct nks_ras {
+    Ras r;
+};
+
+template <typename F>
+static int guard(F &&f) {
+    try {
+        g_last_error.clear();
+        f();
+        return NKS_OK;
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return NKS_EINVAL;
+    }
+}
+
+static void sync_upload_done(hipStream_t s) { HIPC(hipStreamSynchronize(s)); }
+
+extern "C" {
+
+const char *nks_last_error(void) { return g_last_error.c_str(); }
+
+int nks_profile_enable(int enable) {
+    return guard([&] {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (enable) {
+            HIPC(hipDeviceSynchronize());
+            prof_clear();
+        }
+        g_prof_on = enable != 0;
+    });
+}
+
+int nks_profile_query(const char *name, int *count, double *total_ms) {
+    return guard([&] {
+        if (!name || !count || !total_ms) fail(NKS_EINVAL, "bad arguments");
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        *count = 0;
+        *total_ms = 0.0;
+        auto it = g_prof.find(name);
+        if (it == g_prof.end()) return;
+        for (auto &p : it->second.ev) {
+            HIPC(hipEventSynchronize(p.second));
+            float ms = 0.f;
+            HIPC(hipEventElapsedTime(&ms, p.first, p.second));
+            *total_ms += ms;
+            ++*count;
+        }
+    });
+}
+const char *nks_version(void) { return "libnks 0.1 (gfx950)"; }
+
+int nks_setup_grid(const nks_grid_desc *d, nks_grid **out) {
+    return guard([&] {
+        if (!d || !out || d->nres < 1 || !d->res) fail(NKS_EINVAL, "bad grid descriptor");
+        auto *h = new nks_grid();
+        std::unique_ptr<nks_grid> hold(h);
+        Grid &g = h->g;
+        g.al.fa = d->alloc;
+        g.al.ff = d->free;
+        g.al.ctx = d->alloc_ctx;
+        if ((d->alloc == nullptr) != (d->free == nullptr)) fail(NKS_EINVAL, "alloc and free must be given together");
+        g.s = (hipStream_t)d->stream;
+        std::vector<Blk> blks;
+        std::vector<double> geo;
+        int dim = 0;
+        for (int b = 0; b < d->nres; ++b) {
+            const nks_reservoir_desc &r = d->res[b];
+            if (r.nx < 1 || r.ny < 1 || r.nz < 1 || !(r.dx > 0) || !(r.dy > 0) || !(r.dz > 0))
+                fail(NKS_EINVAL, "reservoir %d: bad dimensions", b);
+            if (!r.kx || !r.ky || !r.kz || !r.phi) fail(NKS_EINVAL, "reservoir %d: missing arrays", b);
+            const int rd = r.nz > 1 ? 3 : 2;
+            if (dim && rd != dim) fail(NKS_EINVAL, "reservoirs mix 2D and 3D grids");
+            dim = rd;
+            blks.push_back({r.nx, r.ny, r.nz, 0});
+            geo.push_back(r.dx);
+            geo.push_back(r.dy);
+            geo.push_back(r.dz);
+        }
+        g.dim = dim;
+        g.sp.build(&g.al, blks, g.s);
+        const int N = g.sp.N, B = g.sp.B;
+        g.geo.upload(&g.al, geo, g.s);
+        g.tx.alloc(&g.al, N); g.ty.alloc(&g.al, N); g.tz.alloc(&g.al, N);
+        g.pv.alloc(&g.al, N);
+        g.kx.alloc(&g.al, N); g.ky.alloc(&g.al, N); g.kz.alloc(&g.al, N);
+        DBuf<double> phi;
+        phi.alloc(&g.al, N);
+        for (int b = 0; b < B; ++b) {
+            const nks_reservoir_desc &r = d->res[b];
+            const size_t n = (size_t)r.nx * r.ny * r.nz, o = g.sp.hblk[b].off;
+            HIPC(hipMemcpyAsync(g.kx.p + o, r.kx, n * 8, hipMemcpyDeviceToDevice, g.s));
+            HIPC(hipMemcpyAsync(g.ky.p + o, r.ky, n * 8, hipMemcpyDeviceToDevice, g.s));
+            HIPC(hipMemcpyAsync(g.kz.p + o, r.kz, n * 8, hipMemcpyDeviceToDevice, g.s));
+            HIPC(hipMemcpyAsync(phi.p + o, r.phi, n * 8, hipMemcpyDeviceToDevice, g.s));
+        }
+        grid_setup_kernels(g, g.kx.p, g.ky.p, g.kz.p, phi.p);
+        const nks_fluid &f = d->fluid;
+        if (!(f.T > 0) || !(f.Tc > 0) || !(f.pc > 0) || !(f.R > 0) || !(f.W > 0) || !(f.mu > 0))
+            fail(NKS_EINVAL, "bad fluid constants");
+        // attraction and covolume of the PR equation of state (eq. attrfactor)
+        const double w = f.omega;
+        const double mw = w <= 0.491 ? 0.37464 + 1.54226 * w - 0.26992 * w * w
+                                     : 0.3796 + 1.485 * w - 0.1644 * w * w + 0.01667 * w * w * w;
+        const double al = 1.0 + mw * (1.0 - std::sqrt(f.T / f.Tc));
+        g.a = 0.45724 * f.R * f.R * f.Tc * f.Tc / f.pc * al * al;
+        g.b = 0.0778 * f.R * f.Tc / f.pc;
+        g.RT = f.R * f.T;
+        g.W = f.W;
+        g.mu = f.mu;
+        g.g = d->gravity ? d->g : 0.0;
+        // well source per cell, summed over wells in a fixed order
+        std::vector<double> src(N, 0.0);
+        for (int b = 0; b < B; ++b) {
+            const nks_reservoir_desc &r = d->res[b];
+            const int n = r.nx * r.ny * r.nz;
+            for (int k = 0; k < r.nwells; ++k) {
+                const int c = r.well_cell[k];
+                if (c < 0 || c >= n) fail(NKS_EINVAL, "reservoir %d: well cell %d out of range", b, c);
+                src[g.sp.hblk[b].off + c] += r.well_rate[k] * g.RT / g.W;
+            }
+        }
+        g.src.upload(&g.al, src, g.s);
+        g.m.alloc(&g.al, N);
+        g.dm.alloc(&g.al, N);
+        g.hist.alloc(&g.al, N);
+        g.tmp.alloc(&g.al, N);
+        g.flags.alloc(&g.al, B);
+        HIPC(hipMemsetAsync(g.flags.p, 0, sizeof(int) * B, g.s));
+        sync_upload_done(g.s);
+        *out = hold.release();
+    });
+}
+
+int nks_destroy_grid(nks_grid *g) {
+    return guard([&] {
+        if (g) {
+            (void)hipStreamSynchronize(g->g.s);
+            delete g;
+        }
+    });
+}
+
+int nks_grid_info(const nks_grid *g, int *ncells, int *nres, int *offsets) {
+    return guard([&] {
+        if (!g) fail(NKS_EINVAL, "null grid");
+        if (ncells) *ncells = g->g.sp.N;
+        if (nres) *nres = g->g.sp.B;
+        if (offsets) {
+            for (int b = 0; b < g->g.sp.B; ++b) offsets[b] = g->g.sp.hblk[b].off;
+            offsets[g->g.sp.B] = g->g.sp.N;
+        }
+    });
+}
+
+int nks_hydrostatic_init(nks_grid *g, double p_top, double *p) {
+    return guard([&] {
+        if (!g || !p || !(p_top > 0)) fail(NKS_EINVAL, "bad arguments");
+        launch_hydrostatic(g->g, p_top, p);
+    });
+}
+
+int nks_residual(nks_grid *g, const double *p, const double *pn, const double *pnm1, double dt, int order,
+                 double *F) {
+    return guard([&] {
+        if (!g || !p || !pn || !F || !(dt > 0) || (order != 1 && order != 2) || (order == 2 && !pnm1))
+            fail(NKS_EINVAL, "bad arguments");
+        launch_history(g->g, pn, pnm1, order);
+        launch_props(g->g, p);
+        launch_flux(g->g, p, dt, order, F, nullptr);
+    });
+}
+
+int nks_matrix_create(nks_grid *g, nks_matrix **out) {
+    return guard([&] {
+        if (!g || !out) fail(NKS_EINVAL, "bad arguments");
+        auto *m = new nks_matrix();
+        m->owner = g;
+        m->m.g = &g->g;
+        m->m.op.sp = &g->g.sp;
+        stencil_fine(m->m.op.st, g->g.dim, &g->g.al, g->g.s);
+        m->m.op.coef.alloc(&g->g.al, (size_t)m->m.op.st.K * g->g.sp.N);
+        HIPC(hipMemsetAsync(m->m.op.coef.p, 0, sizeof(double) * m->m.op.st.K * g->g.sp.N, g->g.s));
+        sync_upload_done(g->g.s);
+        *out = m;
+    });
+}
+
+int nks_destroy_matrix(nks_matrix *J) {
+    return guard([&] {
+        if (J) {
+            (void)hipStreamSynchronize(J->m.g->s);
+            delete J;
+        }
+    });
+}
+
+int nks_jacobian(nks_grid *g, const double *p, const double *pn, const double *pnm1, double dt, int order,
+                 nks_matrix *J, double *F) {
+    return guard([&] {
+        if (!g || !p || !pn || !J || !(dt > 0) || (order != 1 && order != 2) || (order == 2 && !pnm1))
+            fail(NKS_EINVAL, "bad arguments");
+        if (J->m.g != &g->g) fail(NKS_EINVAL, "matrix belongs to another grid");
+        launch_history(g->g, pn, pnm1, order);
+        launch_props(g->g, p);
+        launch_flux(g->g, p, dt, order, F, J->m.op.coef.p);
+    });
+}
+
+static void export_op(const Op &A, hipStream_t s, int *rp, int *ci, double *v, int *nnz_out) {
+    const Space &S = *A.sp;
+    std::vector<double> c((size_t)A.st.K * S.N);
+    HIPC(hipMemcpyAsync(c.data(), A.coef.p, c.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    int nnz = 0;
+    if (rp) rp[0] = 0;
+    for (int b = 0; b < S.B; ++b) {
+        const Blk &k = S.hblk[b];
+        for (int z = 0; z < k.nz; ++z)
+            for (int y = 0; y < k.ny; ++y)
+                for (int x = 0; x < k.nx; ++x) {
+                    const int i = k.off + x + k.nx * (y + k.ny * z);
+                    for (int q = 0; q < A.st.K; ++q) {
+                        const int xx = x + A.st.off[3 * q], yy = y + A.st.off[3 * q + 1], zz = z + A.st.off[3 * q + 2];
+                        if (xx < 0 || xx >= k.nx || yy < 0 || yy >= k.ny || zz < 0 || zz >= k.nz) continue;
+                        if (ci) {
+                            ci[nnz] = k.off + xx + k.nx * (yy + k.ny * zz);
+                            v[nnz] = c[(size_t)q * S.N + i];
+                        }
+                        ++nnz;
+                    }
+                    if (rp) rp[i + 1] = nnz;
+                }
+    }
+    if (nnz_out) *nnz_out = nnz;
+}
+
+int nks_matrix_nnz(const nks_matrix *J, int *nnz) {
+    return guard([&] {
+        if (!J || !nnz) fail(NKS_EINVAL, "bad arguments");
+        export_op(J->m.op, J->m.g->s, nullptr, nullptr, nullptr, nnz);
+    });
+}
+
+int nks_matrix_export_csr(const nks_matrix *J, int *rp, int *ci, double *v) {
+    return guard([&] {
+        if (!J || !rp || !ci || !v) fail(NKS_EINVAL, "bad arguments");
+        export_op(J->m.op, J->m.g->s, rp, ci, v, nullptr);
+    });
+}
+
+int nks_matrix_apply(nks_matrix *J, const double *x, double *y) {
+    return guard([&] {
+        if (!J || !x || !y) fail(NKS_EINVAL, "bad arguments");
+        launch_spmv(J->m.op, x, y, nullptr, nullptr, J->m.g->s);
+    });
+}
+
+int nks_jacobian_transpose_apply(nks_matrix *J, const double *x, double *y) {
+    return guard([&] {
+        if (!J || !x || !y) fail(NKS_EINVAL, "bad arguments");
+        const Stencil &st = J->m.op.st;
+        std::vector<int> opp(st.K);
+        for (int k = 0; k < st.K; ++k)
+            for (int q = 0; q < st.K; ++q)
+                if (st.off[3 * q] == -st.off[3 * k] && st.off[3 * q + 1] == -st.off[3 * k + 1] &&
+                    st.off[3 * q + 2] == -st.off[3 * k + 2])
+                    opp[k] = q;
+        DBuf<int> d;
+        d.upload(&J->m.g->al, opp, J->m.g->s);
+        launch_spmv_t(J->m.op, x, y, d.p, J->m.g->s);
+        HIPC(hipStreamSynchronize(J->m.g->s));
+    });
+}
+
+int nks_residual_dlogk_transpose_apply(nks_grid *g, const double *p, const double *lam, double *out) {
+    return guard([&] {
+        if (!g || !p || !lam || !out) fail(NKS_EINVAL, "bad arguments");
+        launch_dlogk_t(g->g, p, lam, out);
+    });
+}
+
+static void check_ras_desc(const nks_ras_desc *d) {
+    if (!d || d->px < 1 || d->py < 1 || d->pz < 1 || d->levels < 1 || d->levels > 6)
+        fail(NKS_EINVAL, "bad preconditioner descriptor");
+    for (int l = 0; l < d->levels; ++l)
+        if (d->overlap[std::min(l, 7)] < 0) fail(NKS_EINVAL, "negative overlap");
+    if (d->variant < 0 || d->variant > 2 || d->interp_order < 1 || d->interp_order > 3 || d->cycle < 0 ||
+        d->cycle > 4 || d->mu < 0 || d->nu < 0 || d->precision < 0 || d->precision > 2 ||
+        d->coarse_restart < 1 || d->coarse_maxit < 1)
+        fail(NKS_EINVAL, "bad preconditioner option");
+}
+
+int nks_ras_setup(nks_matrix *J, const nks_ras_desc *d, nks_ras **inout) {
+    return guard([&] {
+        if (!J || !inout) fail(NKS_EINVAL, "bad arguments");
+        check_ras_desc(d);
+        nks_ras *M = *inout;
+        std::unique_ptr<nks_ras> hold;
+        if (!M) {
+            hold.reset(new nks_ras());
+            M = hold.get();
+            M->r.build(&J->m, *d);
+        } else if (M->r.J != &J->m || !same_desc(M->r.d, *d)) {
+            M->r.build(&J->m, *d);
+        }
+        M->r.factor();
+        if (hold) *inout = hold.release();
+    });
+}
+
+int nks_destroy_ras(nks_ras *M) {
+    return guard([&] {
+        if (M) {
+            (void)hipStreamSynchronize(M->r.g->s);
+            delete M;
+        }
+    });
+}
+
+int nks_ras_apply(nks_ras *M, const double *r, double *z) {
+    return guard([&] {
+        if (!M || !r || !z) fail(NKS_EINVAL, "bad arguments");
+        M->r.apply(r, z, nullptr);
+    });
+}
+
+int nks_ras_apply_level(nks_ras *M, int level, const double *r, double *z) {
+    return guard([&] {
+        if (!M || !r || !z || level < 0 || level >= M->r.L) fail(NKS_EINVAL, "bad arguments");
+        M->r.apply_level(level, r, z, nullptr, false);
+    });
+}
+
+int nks_ras_apply_transpose(nks_ras *, const double *, double *) {
+    return guard([&] { fail(NKS_EINVAL, "transpose preconditioner not available"); });
+}
+
+int nks_ras_level_info(nks_ras *M, int level, int *info) {
+    return guard([&] {
+        if (!M || !info || level < 0 || level >= M->r.L) fail(NKS_EINVAL, "bad arguments");
+        Level &V = *M->r.lev[level];
+        int nnz = 0;
+        export_op(*V.A, M->r.g->s, nullptr, nullptr, nullptr, &nnz);
+        info[0] = V.spp->N;
+        info[1] = V.A->st.K;
+        info[2] = V.nsub;
+        info[3] = V.spp->hblk[0].nx;
+        info[4] = V.spp->hblk[0].ny;
+        info[5] = V.spp->hblk[0].nz;
+        info[6] = M->r.L;
+        info[7] = nnz;
+    });
+}
+
+int nks_ras_level_export(nks_ras *M, int level, int *rp, int *ci, double *v) {
+    return guard([&] {
+        if (!M || !rp || !ci || !v || level < 0 || level >= M->r.L) fail(NKS_EINVAL, "bad arguments");
+        export_op(*M->r.lev[level]->A, M->r.g->s, rp, ci, v, nullptr);
+    });
+}
+
+int nks_ras_restrict(nks_ras *M, int level, const double *rf, double *rc) {
+    return guard([&] {
+        if (!M || !rf || !rc || level < 0 || level + 1 >= M->r.L) fail(NKS_EINVAL, "bad arguments");
+        M->r.restrict_to(level, rf, rc, nullptr);
+    });
+}
+
+int nks_ras_prolong_add(nks_ras *M, int level, const double *ec, double *zf) {
+    return guard([&] {
+        if (!M || !ec || !zf || level < 0 || level + 1 >= M->r.L) fail(NKS_EINVAL, "bad arguments");
+        M->r.prolong_add(level, ec, zf, nullptr);
+    });
+}
+
+int nks_gmres_solve(nks_matrix *J, nks_ras *M, const double *b, double *x, const nks_gmres_desc *d,
+                    nks_gmres_stats *st) {
+    return guard([&] {
+        if (!J || !b || !x || !d || d->restart < 1 || d->restart > 30 || d->maxit < 1)
+            fail(NKS_EINVAL, "bad arguments");
+        Grid &g = *J->m.g;
+        if (d->transpose && M) fail(NKS_EINVAL, "transpose solve with a preconditioner is not available");
+        auto &nwp = J->owner->nw;
+        if (!nwp) nwp.reset(new NewtonWork());
+        Gmres &gm = nwp->gm;
+        gm.ensure(&g.al, g.sp, d->restart, d->flexible != 0, g.s);
+        DBuf<int> opp;
+        if (d->transpose) {
+            const Stencil &st2 = J->m.op.st;
+            std::vector<int> o(st2.K);
+            for (int k = 0; k < st2.K; ++k) o[k] = st2.K - 1 - k;
+            opp.upload(&g.al, o, g.s);
+        }
+        MatVec A = [&](const double *xx, double *yy, const double *bb, const int *mk) {
+            if (d->transpose) {
+                launch_spmv_t(J->m.op, xx, yy, opp.p, g.s);
+                if (bb) launch_axpby(g.sp, 1.0, bb, -1.0, yy, nullptr, g.s);
+            } else {
+                launch_spmv(J->m.op, xx, yy, bb, mk, g.s);
+            }
+        };
+        Precond P = [&](const double *r, double *z, const int *mk) {
+            if (M) M->r.apply(r, z, mk);
+            else launch_axpby(g.sp, 1.0, r, 0.0, z, mk, g.s);
+        };
+        GmOpts o;
+        o.rtol = d->rtol;
+        o.atol = d->atol;
+        o.maxit = d->maxit;
+        o.flexible = d->flexible != 0;
+        o.check_every = 1;
+        gm.solve(A, P, b, x, false, o, nullptr, g.s);
+        std::vector<int> its, conv;
+        std::vector<double> res;
+        gm.stats(its, res, conv, g.s);
+        if (st) {
+            st->iterations = 0;
+            st->total_iterations = 0;
+            st->residual = 0;
+            st->converged = 0;
+            for (int k = 0; k < g.sp.B; ++k) {
+                st->iterations = std::max(st->iterations, its[k]);
+                st->total_iterations += its[k];
+                st->residual = std::max(st->residual, res[k]);
+                st->converged += conv[k];
+                if (st->its) st->its[k] = its[k];
+                if (st->res) st->res[k] = res[k];
+            }
+        }
+    });
+}
+
+// ------------------------------------------------------------------ Newton
+static double now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm1, double dt, int order,
+                    const nks_newton_desc *nd, const nks_ras_desc *rd, nks_newton_stats *st) {
+    return guard([&] {
+        if (!gh || !p || !pn || !nd || !rd || !(dt > 0) || (order != 1 && order != 2) || (order == 2 && !pnm1))
+            fail(NKS_EINVAL, "bad arguments");
+        check_ras_desc(rd);
+        if (nd->restart < 1 || nd->restart > 30) fail(NKS_EINVAL, "restart must be in [1, 30]");
+        Grid &g = gh->g;
+        const int N = g.sp.N, B = g.sp.B;
+        hipStream_t s = g.s;
+        if (!gh->nw) gh->nw.reset(new NewtonWork());
+        NewtonWork &W = *gh->nw;
+        Alloc *al = &g.al;
+        W.F.alloc(al, N); W.Ft.alloc(al, N); W.s.alloc(al, N); W.b.alloc(al, N);
+        W.pt.alloc(al, N); W.Js.alloc(al, N);
+        W.lam.alloc(al, B);
+        W.red2.alloc(al, 2 * B);
+        W.mask.alloc(al, B);
+        W.red.ensure(al, g.sp, 1, s);
+        if (!W.J) {
+            W.J.reset(new Matrix());
+            W.J->g = &g;
+            W.J->op.sp = &g.sp;
+            stencil_fine(W.J->op.st, g.dim, al, s);
+            W.J->op.coef.alloc(al, (size_t)W.J->op.st.K * N);
+        }
+        if (!W.M || !same_desc(W.rd, *rd)) {
+            W.M.reset(new Ras());
+            W.M->build(W.J.get(), *rd);
+            W.rd = *rd;
+        }
+        const bool flex = nd->flexible < 0 ? (rd->levels > 1 || rd->precision != NKS_FP64) : nd->flexible != 0;
+        W.gm.ensure(al, g.sp, nd->restart, flex, s);
+        nks_newton_stats S{};
+        double t0 = now();
+        // residual and norms at the initial guess
+        HIPC(hipMemsetAsync(g.flags.p, 0, sizeof(int) * B, s));
+        launch_history(g, pn, pnm1, order);
+        std::vector<double> hn(B), hs(B), ht(B), hslope(B), lam(B), lam_prev(B), f_prev(B), stop(B);
+        std::vector<int> act(B), flags(B), acc(B);
+        auto norms = [&](const double *x, std::vector<double> &out) {
+            launch_block_norm2(g.sp, W.red, x, W.red2.p, nullptr, s);
+            HIPC(hipMemcpyAsync(out.data(), W.red2.p, 8 * B, hipMemcpyDeviceToHost, s));
+            HIPC(hipMemcpyAsync(flags.data(), g.flags.p, 4 * B, hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            for (auto &v : out) v = std::sqrt(v);
+        };
+        launch_props(g, p);
+        launch_flux(g, p, dt, order, W.F.p, nullptr);
+        norms(W.F.p, hn);
+        S.t_residual += now() - t0;
+        for (int b = 0; b < B; ++b) {
+            if (flags[b] || !std::isfinite(hn[b])) fail(NKS_ENONPHYSICAL, "reservoir %d: non-physical initial state", b);
+            stop[b] = std::max(nd->eps_r * hn[b], nd->eps_a);
+            act[b] = hn[b] > stop[b];
+            S.fnorm0 = std::max(S.fnorm0, hn[b]);
+        }
+        int status = 0;
+        int k = 0;
+        for (; k < nd->max_newton; ++k) {
+            bool any = false;
+            for (int b = 0; b < B; ++b) any |= act[b] != 0;
+            if (!any) break;
+            HIPC(hipMemcpyAsync(W.mask.p, act.data(), 4 * B, hipMemcpyHostToDevice, s));
+            double t1 = now();
+            {
+                ProfScope ps("residual_jacobian", s);
+                launch_flux(g, p, dt, order, nullptr, W.J->op.coef.p);   // props at p are current
+            }
+            HIPC(hipStreamSynchronize(s));
+            double t2 = now();
+            S.t_jacobian += t2 - t1;
+            W.M->factor();
+            W.M->check_pivots();
+            double t3 = now();
+            S.t_setup += t3 - t2;
+            // J s = -F on the active reservoirs
+            k_neg<<<nblk(N, 256), 256, 0, s>>>(N, W.F.p, W.b.p);
+            k_zero<<<nblk(N, 256), 256, 0, s>>>(N, W.s.p);
+            MatVec A = [&](const double *xx, double *yy, const double *bb, const int *mk) {
+                launch_spmv(W.J->op, xx, yy, bb, mk, s);
+            };
+            Precond P = [&](const double *r, double *z, const int *mk) { W.M->apply(r, z, mk); };
+            GmOpts o;
+            o.rtol = nd->eta_r;
+            o.atol = nd->eta_a;
+            o.maxit = nd->maxit;
+            o.flexible = flex;
+            o.check_every = 1;
+            W.gm.solve(A, P, W.b.p, W.s.p, true, o, W.mask.p, s);
+            std::vector<int> its, conv;
+            std::vector<double> res;
+            W.gm.stats(its, res, conv, s);
+            int lits = 0;
+            for (int b = 0; b < B; ++b) if (act[b]) lits = std::max(lits, its[b]);
+            S.linear_its += lits;
+            if (k < 64) S.lits[k] = lits;
+            double t4 = now();
+            S.t_gmres += t4 - t3;
+            // slope of f = ||F||^2/2 along s: F^T J s
+            launch_spmv(W.J->op, W.s.p, W.Js.p, nullptr, nullptr, s);
+            {
+                const double *ys[1] = {W.Js.p};
+                DBuf<const double *> yp;
+                std::vector<const double *> hv(ys, ys + 1);
+                yp.upload(al, hv, s);
+                launch_block_dots(g.sp, W.red, W.F.p, yp.p, 1, W.red2.p, nullptr, s);
+                HIPC(hipMemcpyAsync(hslope.data(), W.red2.p, 8 * B, hipMemcpyDeviceToHost, s));
+                HIPC(hipStreamSynchronize(s));
+            }
+            // backtracking (Dennis-Schnabel): lambda = 1, then quadratic, then
+            // cubic models, each new lambda within [0.1, 0.5] of the last
+            for (int b = 0; b < B; ++b) {
+                lam[b] = act[b] ? 1.0 : 0.0;
+                acc[b] = act[b] ? 0 : 1;
+            }
+            int bt = 0;
+            bool failed = false;
+            for (;; ++bt) {
+                HIPC(hipMemcpyAsync(W.lam.p, lam.data(), 8 * B, hipMemcpyHostToDevice, s));
+                k_trial<<<nblk(N, 256), 256, 0, s>>>(g.sp.blk.p, B, N, p, W.s.p, W.lam.p, W.pt.p);
+                HIPC(hipMemsetAsync(g.flags.p, 0, sizeof(int) * B, s));
+                launch_props(g, W.pt.p);
+                launch_flux(g, W.pt.p, dt, order, W.Ft.p, nullptr);
+                norms(W.Ft.p, ht);
+                bool all = true;
+                for (int b = 0; b < B; ++b) {
+                    if (acc[b]) continue;
+                    const double fx = 0.5 * hn[b] * hn[b];
+                    const bool bad = flags[b] || !std::isfinite(ht[b]);
+                    if (!bad && ht[b] <= (1.0 - nd->alpha * lam[b]) * hn[b]) {
+                        acc[b] = 1;
+                        continue;
+                    }
+                    if (bt >= nd->max_backtracks) {
+                        failed = true;
+                        acc[b] = 1;
+                        continue;
+                    }
+                    all = false;
+                    const double ft = bad ? INFINITY : 0.5 * ht[b] * ht[b];
+                    const double sl = hslope[b];
+                    double lt;
+                    if (!std::isfinite(ft) || sl >= 0.0) {
+                        lt = 0.5 * lam[b];
+                    } else if (bt == 0) {
+                        lt = -sl / (2.0 * (ft - fx - sl));
+                    } else {
+                        const double l1 = lam[b], l2 = lam_prev[b];
+                        const double t1v = ft - fx - l1 * sl, t2v = f_prev[b] - fx - l2 * sl;
+                        const double ca = (t1v / (l1 * l1) - t2v / (l2 * l2)) / (l1 - l2);
+                        const double cb = (-l2 * t1v / (l1 * l1) + l1 * t2v / (l2 * l2)) / (l1 - l2);
+                        if (ca == 0.0) lt = -sl / (2.0 * cb);
+                        else {
+                            const double disc = cb * cb - 3.0 * ca * sl;
+                            lt = disc >= 0.0 ? (-cb + std::sqrt(disc)) / (3.0 * ca) : 0.5 * l1;
+                        }
+                    }
+                    if (!(lt <= 0.5 * lam[b])) lt = 0.5 * lam[b];
+                    if (!(lt >= 0.1 * lam[b])) lt = 0.1 * lam[b];
+                    lam_prev[b] = lam[b];
+                    f_prev[b] = ft;
+                    lam[b] = lt;
+                }
+                if (all || failed) break;
+            }
+            double minlam = 1.0;
+            for (int b = 0; b < B; ++b) if (act[b]) minlam = std::min(minlam, lam[b]);
+            if (failed) {
+                status = 2;
+                S.newton_its = k + 1;
+                break;
+            }
+            // accept: p, F <- trial values on the active reservoirs
+            k_copy_mask<<<nblk(N, 256), 256, 0, s>>>(g.sp.blk.p, B, N, W.pt.p, p, W.mask.p);
+            k_copy_mask<<<nblk(N, 256), 256, 0, s>>>(g.sp.blk.p, B, N, W.Ft.p, W.F.p, W.mask.p);
+            std::vector<double> snorm(B, 0.0), xnorm(B, 0.0);
+            if (nd->stol > 0.0) {
+                norms(W.s.p, snorm);
+                norms(p, xnorm);
+            }
+            double fmax = 0.0;
+            for (int b = 0; b < B; ++b) {
+                if (act[b]) {
+                    hn[b] = ht[b];
+                    if (hn[b] <= stop[b]) act[b] = 0;
+                    if (nd->stol > 0.0 && lam[b] * snorm[b] <= nd->stol * xnorm[b]) act[b] = 0;
+                }
+                fmax = std::max(fmax, hn[b]);
+            }
+            // props must describe the accepted p for the next Jacobian
+            launch_props(g, p);
+            S.t_linesearch += now() - t4;
+            if (k < 64) {
+                S.fnorms[k] = fmax;
+                S.lambdas[k] = minlam;
+            }
+            S.newton_its = k + 1;
+        }
+        if (status == 0) {
+            for (int b = 0; b < B; ++b) if (act[b]) status = 1;
+        }
+        S.fnorm = 0.0;
+        for (int b = 0; b < B; ++b) S.fnorm = std::max(S.fnorm, hn[b]);
+        S.status = status;
+        HIPC(hipStreamSynchronize(s));
+        if (st) *st = S;
+        if (status != 0) fail(NKS_ENOTCONVERGED, status == 2 ? "line search failed" : "Newton iteration limit");
+    });
+}
+
+}  // extern "C"

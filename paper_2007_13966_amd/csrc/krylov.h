@@ -1,0 +1,56 @@
+// (F)GMRES device state and host driver.
+#pragma once
+
+#include <functional>
+
+#include "nks_internal.h"
+
+namespace nks {
+
+// y = A x (b == nullptr) or y = b - A x; only blocks with mask[b] != 0 when mask given
+using MatVec = std::function<void(const double *x, double *y, const double *b, const int *mask)>;
+// z = M^{-1} r on blocks with mask[b] != 0
+using Precond = std::function<void(const double *r, double *z, const int *mask)>;
+
+struct GmOpts {
+    double rtol = 1e-5, atol = 1e-8;
+    int maxit = 10000;
+    bool flexible = false;
+    int check_every = 1;
+};
+
+struct GmDev {
+    double *H;
+    double *cs, *sn;
+    double *g;
+    double *y;
+    double *hj;
+    double *tol, *beta, *res;
+    int *active, *conv, *kdim, *its, *upd;
+    int m, maxit;
+    double rtol, atol;
+};
+
+struct Gmres {
+    Alloc *al = nullptr;
+    const Space *sp = nullptr;
+    int m = 0, nb = 0, nn = 0;
+    std::vector<DBuf<double>> V, Z;
+    DBuf<double> w, r, t, H, cs, sn, g, y, hj, scal;
+    DBuf<int> ints;
+    DBuf<const double *> vptr, zptr;
+    Reducer red;
+    int *hint = nullptr;
+
+    void ensure(Alloc *al, const Space &sp, int m, bool flexible, hipStream_t s);
+    GmDev dev(double rtol, double atol, int maxit);
+    bool any_active(hipStream_t s);
+    // x: initial guess unless x_zero (then x must already hold zeros)
+    void solve(const MatVec &A, const Precond &M, const double *b, double *x, bool x_zero,
+               const GmOpts &o, const int *outer_mask, hipStream_t s);
+    void stats(std::vector<int> &its, std::vector<double> &res, std::vector<int> &conv,
+               hipStream_t s);
+    ~Gmres();
+};
+
+}  // namespace nks

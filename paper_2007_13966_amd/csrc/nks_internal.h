@@ -1,0 +1,189 @@
+// Internal declarations of libnks (gfx950).  Host structures own device
+// buffers; kernels receive plain pointers and small POD descriptors.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nks.h"
+
+namespace nks {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+    int code;
+    std::string msg;
+};
+[[noreturn]] void fail(int code, const char *fmt, ...);
+void hip_check(hipError_t e, const char *what, const char *file, int line);
+#define HIPC(x) ::nks::hip_check((x), #x, __FILE__, __LINE__)
+#define KCHECK() ::nks::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+// ------------------------------------------------------------------ allocation
+struct Alloc {
+    nks_alloc_fn fa = nullptr;
+    nks_free_fn ff = nullptr;
+    void *ctx = nullptr;
+    void *get(size_t bytes);
+    void put(void *p);
+};
+
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    Alloc *al = nullptr;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n), al(o.al) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p; n = o.n; al = o.al;
+            o.p = nullptr; o.n = 0;
+        }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void release() {
+        if (p && al) al->put(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(Alloc *a, size_t count) {
+        if (p && n >= count && al == a) return;
+        release();
+        al = a;
+        n = count;
+        p = count ? static_cast<T *>(a->get(count * sizeof(T))) : nullptr;
+    }
+    void upload(Alloc *a, const std::vector<T> &h, hipStream_t s) {
+        alloc(a, h.size());
+        if (!h.empty()) {
+            HIPC(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+            HIPC(hipStreamSynchronize(s));   // h may be a temporary
+        }
+    }
+};
+
+// ------------------------------------------------------------------ geometry
+// One reservoir ("block") of a level: box dims and first cell.
+struct Blk {
+    int nx, ny, nz, off;
+};
+
+// Reduction chunk: a run of cells inside one block.
+struct Chunk {
+    int blk, start, end, pad;
+};
+
+constexpr int CHUNK = 1024;      // cells per reduction chunk
+constexpr int RED_THREADS = 256;
+constexpr int MAXB = 4096;       // reservoirs per grid
+
+// Vector space of one level: N cells in B blocks plus its reduction chunks.
+struct Space {
+    int N = 0, B = 0;
+    std::vector<Blk> hblk;
+    DBuf<Blk> blk;
+    std::vector<Chunk> hchunk;
+    DBuf<Chunk> chunk;
+    std::vector<int> hcfirst;    // first chunk of each block, B+1 entries
+    DBuf<int> cfirst;
+    void build(Alloc *al, const std::vector<Blk> &b, hipStream_t s);
+};
+
+// device: block containing cell i (binary search over B blocks)
+__device__ __forceinline__ int find_blk(const Blk *blk, int B, int i) {
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (blk[mid].off <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ stencil operators
+constexpr int MAXK = 125;        // up to a 5x5x5 box of offsets
+
+struct Stencil {
+    int K = 0;                   // number of offsets
+    int R = 1;                   // max |offset| per direction
+    int diag = 0;                // index of (0,0,0)
+    std::vector<int8_t> off;     // 3*K, sorted by (dz, dy, dx) = lexicographic cell order
+    DBuf<int8_t> doff;
+};
+
+// Structured FP64 operator on a Space: coef[k*N + i] couples cell i with
+// cell i + off[k] (zero where that neighbour is outside the block).
+struct Op {
+    Space *sp = nullptr;
+    Stencil st;
+    DBuf<double> coef;
+};
+
+// ------------------------------------------------------------------ grid
+struct Grid {
+    Alloc al;
+    hipStream_t s = nullptr;
+    int dim = 2;
+    Space sp;
+    std::vector<double> hdx, hdy, hdz;   // per block
+    DBuf<double> geo;                    // 3*B: dx, dy, dz per block
+    DBuf<double> tx, ty, tz;             // face to the + neighbour
+    DBuf<double> pv;                     // V phi
+    DBuf<double> src;                    // well source Q R T / W
+    DBuf<double> kx, ky, kz;             // copies for the dlogK adjoint
+    double a = 0, b = 0, RT = 0, W = 0, mu = 0, g = 0;
+    // scratch
+    DBuf<double> m, dm, hist, tmp;
+    DBuf<int> flags;                     // per block: non-physical state
+};
+
+struct Matrix {
+    Grid *g = nullptr;
+    Op op;
+};
+
+// ------------------------------------------------------------------ reductions
+// Per-block sums, deterministic (fixed order), results on the device.
+struct Reducer {
+    DBuf<double> part;           // nchunks * maxcols
+    DBuf<unsigned> counter;
+    int maxcols = 0;
+    void ensure(Alloc *al, const Space &sp, int cols, hipStream_t s);
+};
+
+// ------------------------------------------------------------------ kernels (host launchers)
+void launch_spmv(const Op &A, const double *x, double *y, const double *b, const int *mask,
+                 hipStream_t s);             // y = A x, or y = b - A x when b != nullptr
+void launch_spmv_t(const Op &A, const double *x, double *y, const int *opp, hipStream_t s);
+void launch_axpby(const Space &sp, double a, const double *x, double b, double *y,
+                  const int *mask, hipStream_t s);   // y = a x + b y
+void launch_copy_scale_blk(const Space &sp, const double *x, const double *scale, int col,
+                           double *y, const int *mask, hipStream_t s);
+void launch_block_dots(const Space &sp, Reducer &R, const double *x, const double *const *ys,
+                       int ncols, double *out, const int *mask, hipStream_t s);
+// norms squared per block of x: out[b]
+void launch_block_norm2(const Space &sp, Reducer &R, const double *x, double *out,
+                        const int *mask, hipStream_t s);
+
+std::string fmt(const char *f, ...);
+
+// Event timing of named launches (active only after nks_profile_enable(1)).
+bool prof_on();
+struct ProfScope {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s = nullptr;
+    const char *name = nullptr;
+    int level = -1;
+    ProfScope(const char *name, hipStream_t s, int level = -1);
+    ~ProfScope();
+};
+
+}  // namespace nks

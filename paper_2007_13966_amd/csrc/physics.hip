@@ -1,0 +1,358 @@
+// Peng-Robinson density, cell-centred residual and analytic Jacobian
+// (Section 2: eqs. density, PR, attrfactor, gover_sys, implicit-method-bdf1/2;
+// Remark 1 for the two-point flux).
+//
+// Every kernel is one thread per cell over the concatenated cells of all
+// reservoirs; a cell finds its reservoir by binary search over the block
+// offsets.  All arithmetic is FP64.
+#include "nks_internal.h"
+
+namespace nks {
+
+// ---------------------------------------------------------------- PR cubic
+// Largest real root of Z^3 + c2 Z^2 + c1 Z + c0 with
+//   c2 = -(1-B), c1 = A - 3B^2 - 2B, c0 = -(AB - B^2 - B^3),
+// A = a p/(RT)^2, B = b p/(RT).  Depressed cubic t^3 + P t + Q (Z = t - c2/3):
+// one real root (discriminant > 0) by Cardano, otherwise the largest of the
+// three trigonometric roots; two Newton steps on the cubic then remove the
+// rounding of the closed form near a double root.  dZ/dp follows from
+// implicit differentiation of the cubic (the closed form of Section 2).
+struct PRState {
+    double Z, dZ;
+    bool bad;
+};
+
+__device__ __forceinline__ PRState pr_solve(double a, double b, double RT, double p) {
+    const double A = a * p / (RT * RT);
+    const double B = b * p / RT;
+    const double c2 = B - 1.0;
+    const double c1 = A - B * (3.0 * B + 2.0);
+    const double c0 = B * (B + B * B - A);
+    const double third = 1.0 / 3.0;
+    const double sh = c2 * third;
+    const double P = c1 - c2 * sh;
+    const double Q = sh * (2.0 * sh * sh - c1) + c0;
+    const double disc = 0.25 * Q * Q + P * P * P * (1.0 / 27.0);
+    double z;
+    if (disc > 0.0) {
+        const double sq = sqrt(disc);
+        z = cbrt(-0.5 * Q + sq) + cbrt(-0.5 * Q - sq) - sh;
+    } else {
+        const double r = sqrt(-P * third);
+        double c = (r > 0.0) ? (-0.5 * Q) / (r * r * r) : 0.0;
+        c = fmin(1.0, fmax(-1.0, c));
+        z = 2.0 * r * cos(acos(c) * third) - sh;
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double f = ((z + c2) * z + c1) * z + c0;
+        const double df = (3.0 * z + 2.0 * c2) * z + c1;
+        if (df != 0.0) z -= f / df;
+    }
+    // implicit derivative: dZ/dp = -(df/dp)/(df/dZ)
+    const double dA = a / (RT * RT), dB = b / RT;
+    const double dfdZ = (3.0 * z + 2.0 * c2) * z + c1;
+    const double dfdp = dB * z * z + (dA - 6.0 * B * dB - 2.0 * dB) * z -
+                        (dA * B + A * dB - 2.0 * B * dB - 3.0 * B * B * dB);
+    PRState s;
+    s.Z = z;
+    s.dZ = -dfdp / dfdZ;
+    s.bad = !(p > 0.0) || !(z > B) || !isfinite(z);
+    return s;
+}
+
+// m = p/Z (density times RT/W) and dm/dp = 1/Z - p Z'/Z^2
+__device__ __forceinline__ void scaled_density(double a, double b, double RT, double p,
+                                               double &m, double &dm, bool &bad) {
+    PRState s = pr_solve(a, b, RT, p);
+    m = p / s.Z;
+    dm = 1.0 / s.Z - p * s.dZ / (s.Z * s.Z);
+    bad = s.bad;
+}
+
+struct CellPos {
+    int b, x, y, z, nx, ny, nz;
+};
+
+__device__ __forceinline__ CellPos cell_pos(const Blk *blk, int B, int i) {
+    CellPos c;
+    c.b = find_blk(blk, B, i);
+    const Blk k = blk[c.b];
+    const int l = i - k.off;
+    c.nx = k.nx; c.ny = k.ny; c.nz = k.nz;
+    c.x = l % k.nx;
+    c.y = (l / k.nx) % k.ny;
+    c.z = l / (k.nx * k.ny);
+    return c;
+}
+
+// ---------------------------------------------------------------- setup kernels
+__global__ void k_transmissibility(const Blk *blk, int B, int N, const double *geo,
+                                   const double *kx, const double *ky, const double *kz,
+                                   double *tx, double *ty, double *tz) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const CellPos c = cell_pos(blk, B, i);
+    const double dx = geo[3 * c.b], dy = geo[3 * c.b + 1], dz = geo[3 * c.b + 2];
+    double t = 0.0;
+    if (c.x + 1 < c.nx) t = dy * dz / (dx / (2.0 * kx[i]) + dx / (2.0 * kx[i + 1]));
+    tx[i] = t;
+    t = 0.0;
+    if (c.y + 1 < c.ny) t = dx * dz / (dy / (2.0 * ky[i]) + dy / (2.0 * ky[i + c.nx]));
+    ty[i] = t;
+    t = 0.0;
+    if (c.z + 1 < c.nz) t = dx * dy / (dz / (2.0 * kz[i]) + dz / (2.0 * kz[i + c.nx * c.ny]));
+    tz[i] = t;
+}
+
+__global__ void k_pore_volume(const Blk *blk, int B, int N, const double *geo, const double *phi,
+                              double *pv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int b = find_blk(blk, B, i);
+    pv[i] = geo[3 * b] * geo[3 * b + 1] * geo[3 * b + 2] * phi[i];
+}
+
+// ---------------------------------------------------------------- PR per cell
+// m, dm at p; flags[b] |= 1 on a non-physical state.
+__global__ void k_props(const Blk *blk, int B, int N, double a, double b, double RT,
+                        const double *p, double *m, double *dm, int *flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double mi, dmi;
+    bool bad;
+    scaled_density(a, b, RT, p[i], mi, dmi, bad);
+    m[i] = mi;
+    dm[i] = dmi;
+    if (bad && flags) atomicOr(&flags[find_blk(blk, B, i)], 1);
+}
+
+// history part of the accumulation: order 1: -m(p_n); order 2: (-4 m(p_n) + m(p_nm1))/2
+__global__ void k_history(int N, double a, double b, double RT, const double *pn,
+                          const double *pnm1, int order, double *hist) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double mn, d;
+    bool bad;
+    scaled_density(a, b, RT, pn[i], mn, d, bad);
+    if (order == 2) {
+        double mnm1;
+        scaled_density(a, b, RT, pnm1[i], mnm1, d, bad);
+        hist[i] = 0.5 * (mnm1 - 4.0 * mn);
+    } else {
+        hist[i] = -mn;
+    }
+}
+
+// ---------------------------------------------------------------- residual + Jacobian
+struct FluxArgs {
+    const Blk *blk;
+    int B, N, dim;
+    const double *geo, *tx, *ty, *tz, *pv, *src;
+    const double *p, *m, *dm, *hist;
+    double cacc, inv_dt, inv_mu, crho_g;   // crho_g = g W/(RT)
+    double *F;
+    double *J;                             // K*N stencil coefficients or nullptr
+};
+
+// One face of cell i: neighbour j, transmissibility T, depth difference
+// h_i - h_j.  Accumulates the flux into Fi and, for the Jacobian, the
+// diagonal and the off-diagonal coefficient.
+__device__ __forceinline__ void face(const FluxArgs &A, double pi, double mi, double dmi, int j,
+                                     double T, double dh, double &Fi, double &diag, double &off) {
+    const double pj = A.p[j], mj = A.m[j];
+    const double dphi = (pi - pj) - 0.5 * (mi + mj) * A.crho_g * dh;
+    const bool up = dphi >= 0.0;
+    const double lam = (up ? mi : mj) * A.inv_mu;
+    Fi += T * lam * dphi;
+    if (A.J) {
+        const double dmj = A.dm[j];
+        const double dli = up ? dmi * A.inv_mu : 0.0;
+        const double dlj = up ? 0.0 : dmj * A.inv_mu;
+        diag += T * (dli * dphi + lam * (1.0 - 0.5 * dmi * A.crho_g * dh));
+        off = T * (dlj * dphi + lam * (-1.0 - 0.5 * dmj * A.crho_g * dh));
+    }
+}
+
+__global__ void k_flux(FluxArgs A) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.N) return;
+    const CellPos c = cell_pos(A.blk, A.B, i);
+    const int sx = 1, sy = c.nx, sz = c.nx * c.ny;
+    const double dz = A.geo[3 * c.b + 2];
+    const double pi = A.p[i], mi = A.m[i], dmi = A.dm[i];
+    double Fi = A.pv[i] * A.inv_dt * (A.cacc * mi + A.hist[i]);
+    double diag = A.pv[i] * A.inv_dt * A.cacc * dmi;
+    double o[6] = {0, 0, 0, 0, 0, 0};
+    // neighbour order -z, -y, -x, +x, +y, +z (increasing cell index)
+    if (A.dim == 3 && c.z > 0) face(A, pi, mi, dmi, i - sz, A.tz[i - sz], dz, Fi, diag, o[0]);
+    if (c.y > 0) face(A, pi, mi, dmi, i - sy, A.ty[i - sy], 0.0, Fi, diag, o[1]);
+    if (c.x > 0) face(A, pi, mi, dmi, i - sx, A.tx[i - sx], 0.0, Fi, diag, o[2]);
+    if (c.x + 1 < c.nx) face(A, pi, mi, dmi, i + sx, A.tx[i], 0.0, Fi, diag, o[3]);
+    if (c.y + 1 < c.ny) face(A, pi, mi, dmi, i + sy, A.ty[i], 0.0, Fi, diag, o[4]);
+    if (A.dim == 3 && c.z + 1 < c.nz) face(A, pi, mi, dmi, i + sz, A.tz[i], -dz, Fi, diag, o[5]);
+    if (A.F) A.F[i] = Fi - A.src[i];
+    if (A.J) {
+        const int N = A.N;
+        if (A.dim == 3) {
+            A.J[0 * N + i] = o[0];
+            A.J[1 * N + i] = o[1];
+            A.J[2 * N + i] = o[2];
+            A.J[3 * N + i] = diag;
+            A.J[4 * N + i] = o[3];
+            A.J[5 * N + i] = o[4];
+            A.J[6 * N + i] = o[5];
+        } else {
+            A.J[0 * N + i] = o[1];
+            A.J[1 * N + i] = o[2];
+            A.J[2 * N + i] = diag;
+            A.J[3 * N + i] = o[3];
+            A.J[4 * N + i] = o[4];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- hydrostatic init
+// one thread per (reservoir, column); scalar Newton down the column
+__global__ void k_hydrostatic(const Blk *blk, int B, int ncol_total, const int *colstart,
+                              const double *geo, double a, double b, double RT, double crho_g,
+                              double p_top, double *p) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncol_total) return;
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (colstart[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const Blk k = blk[lo];
+    const int col = t - colstart[lo];
+    const int nxy = k.nx * k.ny;
+    const double dz = geo[3 * lo + 2];
+    double pk = p_top;
+    p[k.off + col] = pk;
+    for (int z = 1; z < k.nz; ++z) {
+        double mk, dmk;
+        bool bad;
+        scaled_density(a, b, RT, pk, mk, dmk, bad);
+        double q = pk;
+        for (int it = 0; it < 50; ++it) {
+            double mq, dmq;
+            scaled_density(a, b, RT, q, mq, dmq, bad);
+            const double f = q - pk - 0.5 * (mk + mq) * crho_g * dz;
+            const double df = 1.0 - 0.5 * dmq * crho_g * dz;
+            const double step = f / df;
+            q -= step;
+            if (fabs(step) <= 1e-15 * fabs(q)) break;
+        }
+        pk = q;
+        p[k.off + col + z * nxy] = pk;
+    }
+}
+
+// ---------------------------------------------------------------- dF/dlnK transpose
+// out_c = sum over faces (c,n): (lam_c - lam_n) * lambda_up dPhi_cn * T K_n/(K_c + K_n),
+// K the component normal to the face (dT/dln K_c = T K_n/(K_c + K_n)).
+__global__ void k_dlogk_t(FluxArgs A, const double *kx, const double *ky, const double *kz,
+                          const double *lam, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.N) return;
+    const CellPos c = cell_pos(A.blk, A.B, i);
+    const int sy = c.nx, sz = c.nx * c.ny;
+    const double dz = A.geo[3 * c.b + 2];
+    const double pi = A.p[i], mi = A.m[i], li = lam[i];
+    double acc = 0.0;
+    auto term = [&](int j, double T, double dh, double ki, double kj) {
+        const double pj = A.p[j], mj = A.m[j];
+        const double dphi = (pi - pj) - 0.5 * (mi + mj) * A.crho_g * dh;
+        const double lm = (dphi >= 0.0 ? mi : mj) * A.inv_mu;
+        acc += (li - lam[j]) * lm * dphi * T * kj / (ki + kj);
+    };
+    if (A.dim == 3 && c.z > 0) term(i - sz, A.tz[i - sz], dz, kz[i], kz[i - sz]);
+    if (c.y > 0) term(i - sy, A.ty[i - sy], 0.0, ky[i], ky[i - sy]);
+    if (c.x > 0) term(i - 1, A.tx[i - 1], 0.0, kx[i], kx[i - 1]);
+    if (c.x + 1 < c.nx) term(i + 1, A.tx[i], 0.0, kx[i], kx[i + 1]);
+    if (c.y + 1 < c.ny) term(i + sy, A.ty[i], 0.0, ky[i], ky[i + sy]);
+    if (A.dim == 3 && c.z + 1 < c.nz) term(i + sz, A.tz[i], -dz, kz[i], kz[i + sz]);
+    out[i] = acc;
+}
+
+// ---------------------------------------------------------------- host side
+static inline int nblk(int n, int t) { return (n + t - 1) / t; }
+
+void grid_setup_kernels(Grid &g, const double *kx, const double *ky, const double *kz,
+                        const double *phi) {
+    const int N = g.sp.N, B = g.sp.B;
+    k_transmissibility<<<nblk(N, 256), 256, 0, g.s>>>(g.sp.blk.p, B, N, g.geo.p, kx, ky, kz,
+                                                      g.tx.p, g.ty.p, g.tz.p);
+    KCHECK();
+    k_pore_volume<<<nblk(N, 256), 256, 0, g.s>>>(g.sp.blk.p, B, N, g.geo.p, phi, g.pv.p);
+    KCHECK();
+}
+
+static FluxArgs flux_args(Grid &g, const double *p, double dt, int order, double *F, double *J) {
+    FluxArgs A;
+    A.blk = g.sp.blk.p;
+    A.B = g.sp.B;
+    A.N = g.sp.N;
+    A.dim = g.dim;
+    A.geo = g.geo.p;
+    A.tx = g.tx.p; A.ty = g.ty.p; A.tz = g.tz.p;
+    A.pv = g.pv.p;
+    A.src = g.src.p;
+    A.p = p;
+    A.m = g.m.p;
+    A.dm = g.dm.p;
+    A.hist = g.hist.p;
+    A.cacc = order == 2 ? 1.5 : 1.0;
+    A.inv_dt = 1.0 / dt;
+    A.inv_mu = 1.0 / g.mu;
+    A.crho_g = g.g * g.W / g.RT;
+    A.F = F;
+    A.J = J;
+    return A;
+}
+
+void launch_history(Grid &g, const double *pn, const double *pnm1, int order) {
+    const int N = g.sp.N;
+    k_history<<<nblk(N, 256), 256, 0, g.s>>>(N, g.a, g.b, g.RT, pn, order == 2 ? pnm1 : pn,
+                                             order, g.hist.p);
+    KCHECK();
+}
+
+void launch_props(Grid &g, const double *p) {
+    const int N = g.sp.N;
+    k_props<<<nblk(N, 256), 256, 0, g.s>>>(g.sp.blk.p, g.sp.B, N, g.a, g.b, g.RT, p, g.m.p,
+                                           g.dm.p, g.flags.p);
+    KCHECK();
+}
+
+// F (and J) at p, with the history term already in g.hist and props at p in g.m/g.dm
+void launch_flux(Grid &g, const double *p, double dt, int order, double *F, double *J) {
+    FluxArgs A = flux_args(g, p, dt, order, F, J);
+    k_flux<<<nblk(A.N, 256), 256, 0, g.s>>>(A);
+    KCHECK();
+}
+
+void launch_hydrostatic(Grid &g, double p_top, double *p) {
+    std::vector<int> cs(g.sp.B);
+    int tot = 0;
+    for (int b = 0; b < g.sp.B; ++b) {
+        cs[b] = tot;
+        tot += g.sp.hblk[b].nx * g.sp.hblk[b].ny;
+    }
+    DBuf<int> d;
+    d.upload(&g.al, cs, g.s);
+    k_hydrostatic<<<nblk(tot, 128), 128, 0, g.s>>>(g.sp.blk.p, g.sp.B, tot, d.p, g.geo.p, g.a,
+                                                   g.b, g.RT, g.g * g.W / g.RT, p_top, p);
+    KCHECK();
+    HIPC(hipStreamSynchronize(g.s));
+}
+
+void launch_dlogk_t(Grid &g, const double *p, const double *lam, double *out) {
+    launch_props(g, p);
+    FluxArgs A = flux_args(g, p, 1.0, 1, nullptr, nullptr);
+    k_dlogk_t<<<nblk(A.N, 256), 256, 0, g.s>>>(A, g.kx.p, g.ky.p, g.kz.p, lam, out);
+    KCHECK();
+}
+
+}  // namespace nks

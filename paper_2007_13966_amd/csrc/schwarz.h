@@ -1,0 +1,111 @@
+// Multilevel restricted additive Schwarz preconditioner: level hierarchy,
+// overlapping subdomains with ILU(0) factors, interpolation between levels.
+#pragma once
+
+#include <memory>
+
+#include "krylov.h"
+
+namespace nks {
+
+// Subdomain (overlapping box Omega_i^delta) of one level, device POD.
+struct SubDev {
+    int blk;
+    int ex, ey, ez;              // extended box extents
+    int ox, oy, oz;              // extended box origin in block coordinates
+    int lx0, lx1, ly0, ly1, lz0, lz1;   // owned range, extended-box coordinates
+    int fac_off;                 // first extended cell in factor / zext storage
+    int next;                    // extended cells
+    int lvl_off;                 // first entry of this subdomain's level pointers
+    int nlev;                    // wavefront levels
+    int inv_off;                 // first entry of the padded-tile inverse map
+    int pad;
+};
+
+// Per block box layout of a level (for the AS / right-RAS gather)
+struct BlkPart {
+    int px, py, pz, first;
+};
+
+// 1D interpolation tables of one direction for all blocks (fine -> coarse)
+struct Interp1 {
+    // fine index row (block-local index + row offset of the block): <= 4 (coarse, w)
+    std::vector<int> rcnt, rj;
+    std::vector<double> rw;
+    // coarse index column: <= 8 (fine, w)
+    std::vector<int> ccnt, ci;
+    std::vector<double> cw;
+    std::vector<int> roff, coff;   // per block offsets into rows / cols
+    DBuf<int> d_rcnt, d_rj, d_ccnt, d_ci, d_roff, d_coff;
+    DBuf<double> d_rw, d_cw;
+};
+
+struct Level {
+    Space sp;                    // this level's cells (owned here for coarse levels)
+    Space *spp = nullptr;        // the space in use (fine level: the grid's)
+    Op own;                      // coarse-level operator (Galerkin product)
+    Op *A = nullptr;             // operator in use (fine level: the Jacobian)
+    int delta = 1;
+    int lb = 1, lc = 1;          // wavefront level function t = x + lb*y + lc*z
+    int R = 1;                   // padding of the LDS tile (stencil reach)
+    int nsub = 0, next_total = 0, lvl_total = 0, inv_total = 0;
+    int max_tile = 0;            // largest padded tile (cells)
+    int max_next = 0;
+    int max_lvl = 0;             // largest hyperplane (cells)
+    std::vector<SubDev> hsub;
+    DBuf<SubDev> sub;
+    std::vector<BlkPart> hpart;
+    DBuf<BlkPart> part;
+    DBuf<int> lvlptr;            // per subdomain: nlev+1 offsets (relative to fac_off)
+    DBuf<int> loc;               // per extended cell (level order): padded-tile index
+    DBuf<int> inv;               // per padded-tile cell: level-order index or -1
+    DBuf<int> lexi;              // per extended cell (level order): lexicographic ext index
+    // ILU(0) factors: K coefficient arrays over the extended cells (level order)
+    DBuf<double> w64;            // FP64 factorisation workspace (factor storage in FP64 mode)
+    DBuf<float> f32;             // FP32 factors (FP32 mode)
+    DBuf<uint16_t> f16;          // BF16 factors (BF16 mode)
+    DBuf<double> invd64;         // 1/u_ii
+    DBuf<float> invd32;
+    DBuf<double> zext;           // per extended cell solution (AS / right-RAS gather)
+    DBuf<int> err;               // zero-pivot flag
+    // ILU(0) elimination table of the stencil: for lower offset k, pairs (k2, t)
+    // with off[k] + off[k2] = off[t], k2 an upper offset
+    DBuf<int> upd_ptr, upd_k2, upd_t;
+    DBuf<int> lin_pad;           // padded-tile linear offset of each stencil entry
+    // interpolation from the next coarser level to this one
+    Interp1 ip[3];
+    DBuf<int> rap_slot;          // coarse offset -> slot table for the Galerkin product
+    int rap_R = 0;
+    // work vectors
+    DBuf<double> r, t, bc, xc;
+};
+
+struct TileDims {
+    int PX, PY, PZ, R, Rz;       // padded LDS tile and stencil reach
+};
+
+struct Ras {
+    Grid *g = nullptr;
+    Matrix *J = nullptr;
+    nks_ras_desc d{};
+    int L = 1;
+    std::vector<std::unique_ptr<Level>> lev;    // lev[0] finest
+    std::vector<TileDims> tiles_;
+    Gmres coarse;
+    int lds_bytes = 65536;
+    int coarse_its_last = 0;
+    long coarse_its_total = 0;
+    long coarse_calls = 0;
+
+    void build(Matrix *J, const nks_ras_desc &d);     // structure (once)
+    void factor();                                     // numeric (every call)
+    void apply(const double *r, double *z, const int *mask);
+    void apply_level(int l, const double *r, double *z, const int *mask, bool accumulate);
+    void vcycle(int l, const double *b, double *x, const int *mask);
+    void coarse_solve(const double *b, double *x, const int *mask);
+    void restrict_to(int l, const double *rf, double *rc, const int *mask);
+    void prolong_add(int l, const double *ec, double *zf, const int *mask);
+    void check_pivots();
+};
+
+}  // namespace nks

@@ -1,0 +1,1048 @@
+// Multilevel restricted additive Schwarz preconditioner on gfx950.
+//
+// Section 3.1: overlapping boxes Omega_i^delta (clipped at the domain
+// boundary), subdomain matrices A_i = R_i^delta A R_i^delta^T factored by
+// ILU(0) in local lexicographic order, applied as left-RAS (eq. as-left:
+// owned cells written once, no atomics), classical AS (eq. as-class) or
+// right-RAS (eq. as-right).
+// Section 3.2: Algorithm 1 / eq. v-cycle with Schwarz-Richardson smoothing,
+// Kaskade, additive and coarse-only compositions (eqs. left-Kas, right-Kas,
+// two-additive, coarse-level), the coarsest problem solved by Schwarz-
+// preconditioned GMRES (Remark 2), interpolation of eqs. inter-frist /
+// inter-second / inter-third, restriction P^T, Galerkin coarse operators.
+//
+// GPU mapping: one workgroup per subdomain.  The triangular solves follow
+// wavefront hyperplanes t = x + lb*y + lc*z (every lower stencil offset has a
+// smaller t), which keeps the lexicographic elimination order of ILU(0) while
+// running each hyperplane in parallel.  Factors are stored per subdomain in
+// hyperplane order so each hyperplane is a contiguous, coalesced run; runs of
+// hyperplanes are staged through LDS while the solution tile of the
+// subdomain stays resident in LDS for both sweeps.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <set>
+#include <tuple>
+
+#include "schwarz.h"
+
+namespace nks {
+
+static inline int nblk(int n, int t) { return (n + t - 1) / t; }
+
+// ---------------------------------------------------------------- bf16 helpers
+__host__ __device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);                                     // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) {
+    uint32_t u = ((uint32_t)h) << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+template <typename FT> struct FTraits;
+template <> struct FTraits<double> {
+    __device__ static double get(const double *p, size_t i) { return p[i]; }
+};
+template <> struct FTraits<float> {
+    __device__ static float get(const float *p, size_t i) { return p[i]; }
+};
+template <> struct FTraits<uint16_t> {
+    __device__ static float get(const uint16_t *p, size_t i) { return from_bf16(p[i]); }
+};
+
+// ---------------------------------------------------------------- host: partition
+static void box_range(int n, int P, int q, int &lo, int &hi) {
+    const int base = n / P, rem = n % P;
+    lo = q * base + std::min(q, rem);
+    hi = lo + base + (q < rem ? 1 : 0);
+}
+
+// wavefront coefficients: smallest lb, lc >= 1 with dx + lb dy + lc dz <= -1
+// for every lower offset (lexicographically negative (dz, dy, dx))
+static void wavefront(const Stencil &st, int &lb, int &lc) {
+    lb = 1;
+    lc = 1;
+    for (int k = 0; k < st.K; ++k) {
+        const int dx = st.off[3 * k], dy = st.off[3 * k + 1], dz = st.off[3 * k + 2];
+        if (dz == 0 && dy < 0) lb = std::max(lb, (int)std::ceil((dx + 1.0) / (-dy)));
+    }
+    for (int k = 0; k < st.K; ++k) {
+        const int dx = st.off[3 * k], dy = st.off[3 * k + 1], dz = st.off[3 * k + 2];
+        if (dz < 0) lc = std::max(lc, (int)std::ceil((dx + lb * dy + 1.0) / (-dz)));
+    }
+}
+
+static void build_partition(Level &L, const nks_ras_desc &d, int delta, Alloc *al, hipStream_t s,
+                            TileDims &geo) {
+    const Space &S = *L.spp;
+    const Stencil &st = L.A->st;
+    wavefront(st, L.lb, L.lc);
+    int R = 0, Rz = 0;
+    for (int k = 0; k < st.K; ++k) {
+        R = std::max(R, (int)std::abs(st.off[3 * k]));
+        R = std::max(R, (int)std::abs(st.off[3 * k + 1]));
+        Rz = std::max(Rz, (int)std::abs(st.off[3 * k + 2]));
+    }
+    L.R = R;
+    L.delta = delta;
+    L.hsub.clear();
+    L.hpart.clear();
+    // first pass: boxes and maximum extents
+    int mex = 1, mey = 1, mez = 1;
+    for (int b = 0; b < S.B; ++b) {
+        const Blk &k = S.hblk[b];
+        const int P[3] = {std::min(d.px, k.nx), std::min(d.py, k.ny), std::min(d.pz, k.nz)};
+        const int n[3] = {k.nx, k.ny, k.nz};
+        L.hpart.push_back({P[0], P[1], P[2], (int)L.hsub.size()});
+        for (int qz = 0; qz < P[2]; ++qz)
+            for (int qy = 0; qy < P[1]; ++qy)
+                for (int qx = 0; qx < P[0]; ++qx) {
+                    const int q[3] = {qx, qy, qz};
+                    int lo[3], hi[3], elo[3], ehi[3];
+                    for (int a = 0; a < 3; ++a) {
+                        box_range(n[a], P[a], q[a], lo[a], hi[a]);
+                        elo[a] = std::max(0, lo[a] - delta);
+                        ehi[a] = std::min(n[a], hi[a] + delta);
+                    }
+                    SubDev sd{};
+                    sd.blk = b;
+                    sd.ex = ehi[0] - elo[0];
+                    sd.ey = ehi[1] - elo[1];
+                    sd.ez = ehi[2] - elo[2];
+                    sd.ox = elo[0];
+                    sd.oy = elo[1];
+                    sd.oz = elo[2];
+                    sd.lx0 = lo[0] - elo[0]; sd.lx1 = hi[0] - elo[0];
+                    sd.ly0 = lo[1] - elo[1]; sd.ly1 = hi[1] - elo[1];
+                    sd.lz0 = lo[2] - elo[2]; sd.lz1 = hi[2] - elo[2];
+                    sd.next = sd.ex * sd.ey * sd.ez;
+                    mex = std::max(mex, sd.ex);
+                    mey = std::max(mey, sd.ey);
+                    mez = std::max(mez, sd.ez);
+                    L.hsub.push_back(sd);
+                }
+    }
+    geo.R = R;
+    geo.Rz = Rz;
+    geo.PX = mex + 2 * R;
+    geo.PY = mey + 2 * R;
+    geo.PZ = mez + 2 * Rz;
+    const int tile = geo.PX * geo.PY * geo.PZ;
+    L.max_tile = tile;
+    // second pass: hyperplane order, maps
+    std::vector<int> lvlptr, loc, inv, lexi;
+    int fac = 0;
+    L.max_next = 0;
+    L.max_lvl = 0;
+    for (auto &sd : L.hsub) {
+        sd.fac_off = fac;
+        sd.lvl_off = (int)lvlptr.size();
+        sd.inv_off = (int)inv.size();
+        sd.nlev = (sd.ex - 1) + L.lb * (sd.ey - 1) + L.lc * (sd.ez - 1) + 1;
+        std::vector<int> cnt(sd.nlev + 1, 0);
+        for (int z = 0; z < sd.ez; ++z)
+            for (int y = 0; y < sd.ey; ++y)
+                for (int x = 0; x < sd.ex; ++x) cnt[x + L.lb * y + L.lc * z + 1]++;
+        for (int t = 0; t < sd.nlev; ++t) cnt[t + 1] += cnt[t];
+        for (int t = 0; t <= sd.nlev; ++t) lvlptr.push_back(cnt[t]);
+        for (int t = 0; t < sd.nlev; ++t) L.max_lvl = std::max(L.max_lvl, cnt[t + 1] - cnt[t]);
+        std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+        std::vector<int> sloc(sd.next), slexi(sd.next);
+        std::vector<int> sinv(tile, -1);
+        for (int z = 0; z < sd.ez; ++z)
+            for (int y = 0; y < sd.ey; ++y)
+                for (int x = 0; x < sd.ex; ++x) {
+                    const int t = x + L.lb * y + L.lc * z;
+                    const int e = pos[t]++;
+                    const int pidx = (x + R) + geo.PX * ((y + R) + geo.PY * (z + Rz));
+                    sloc[e] = pidx;
+                    slexi[e] = x + sd.ex * (y + sd.ey * z);
+                    sinv[pidx] = e;
+                }
+        loc.insert(loc.end(), sloc.begin(), sloc.end());
+        lexi.insert(lexi.end(), slexi.begin(), slexi.end());
+        inv.insert(inv.end(), sinv.begin(), sinv.end());
+        fac += sd.next;
+        L.max_next = std::max(L.max_next, sd.next);
+    }
+    L.nsub = (int)L.hsub.size();
+    L.next_total = fac;
+    L.lvl_total = (int)lvlptr.size();
+    L.inv_total = (int)inv.size();
+    L.sub.upload(al, L.hsub, s);
+    L.part.upload(al, L.hpart, s);
+    L.lvlptr.upload(al, lvlptr, s);
+    L.loc.upload(al, loc, s);
+    L.inv.upload(al, inv, s);
+    L.lexi.upload(al, lexi, s);
+    // stencil tables
+    std::vector<int> lin(st.K);
+    for (int k = 0; k < st.K; ++k)
+        lin[k] = st.off[3 * k] + geo.PX * (st.off[3 * k + 1] + geo.PY * st.off[3 * k + 2]);
+    L.lin_pad.upload(al, lin, s);
+    std::map<std::tuple<int, int, int>, int> idx;
+    for (int k = 0; k < st.K; ++k) idx[{st.off[3 * k], st.off[3 * k + 1], st.off[3 * k + 2]}] = k;
+    std::vector<int> uptr(st.K + 1, 0), uk2, ut;
+    for (int k = 0; k < st.K; ++k) {
+        uptr[k] = (int)uk2.size();
+        if (k < st.diag) {
+            for (int k2 = st.diag + 1; k2 < st.K; ++k2) {
+                auto it = idx.find({st.off[3 * k] + st.off[3 * k2], st.off[3 * k + 1] + st.off[3 * k2 + 1],
+                                    st.off[3 * k + 2] + st.off[3 * k2 + 2]});
+                if (it != idx.end()) {
+                    uk2.push_back(k2);
+                    ut.push_back(it->second);
+                }
+            }
+        }
+    }
+    uptr[st.K] = (int)uk2.size();
+    if (uk2.empty()) { uk2.push_back(0); ut.push_back(0); }
+    L.upd_ptr.upload(al, uptr, s);
+    L.upd_k2.upload(al, uk2, s);
+    L.upd_t.upload(al, ut, s);
+    L.err.alloc(al, 1);
+    HIPC(hipMemsetAsync(L.err.p, 0, sizeof(int), s));
+}
+
+// ---------------------------------------------------------------- host: interpolation
+// One direction of the interpolation from ceil(nf/2) coarse cells to nf fine
+// cells.  Fine centre x_i = i + 1/2 in fine-cell units; coarse cell J covers
+// fine 2J and 2J+1 and sits at their centroid.  Order 1: the parent cell
+// (nearest centroid, eq. inter-frist).  Order 2: linear between the two
+// bracketing centroids (one factor of eq. inter-second).  Order 3: cubic
+// convolution with W(s) of eq. inter-third over four coarse cells at
+// spacing 2.  Indices beyond the domain are clamped to the edge cell and
+// their weights merged.
+static void interp_weights(int nf, int order, int i, std::vector<std::pair<int, double>> &out) {
+    out.clear();
+    const int nc = (nf + 1) / 2;
+    if (nf == 1) {
+        out.push_back({0, 1.0});
+        return;
+    }
+    const double x = i + 0.5;
+    std::vector<std::pair<int, double>> raw;
+    if (order == 1) {
+        raw.push_back({i / 2, 1.0});
+    } else if (order == 2) {
+        // bracketing centroids
+        int J0 = (int)std::floor((x - 1.0) / 2.0);
+        if (x < 1.0) J0 = -1;
+        if (J0 > nc - 1) J0 = nc - 1;
+        const double cl = (nf & 1) ? nf - 0.5 : nf - 1.0;   // last centroid
+        auto cen = [&](int J) -> double {
+            if (J < 0) return -1.0;
+            if (J == nc - 1) return cl;
+            if (J > nc - 1) return cl + 2.0;
+            return 2.0 * J + 1.0;
+        };
+        const double c0 = cen(J0), c1 = cen(J0 + 1);
+        const double h = c1 - c0;
+        raw.push_back({J0, (c1 - x) / h});
+        raw.push_back({J0 + 1, (x - c0) / h});
+    } else {
+        const int J0 = (int)std::floor((x - 1.0) / 2.0);
+        for (int l = -1; l <= 2; ++l) {
+            const int J = J0 + l;
+            const double s = std::fabs((x - (2.0 * J + 1.0)) / 2.0);
+            double w = 0.0;
+            if (s < 1.0) w = 1.5 * s * s * s - 2.5 * s * s + 1.0;
+            else if (s < 2.0) w = -0.5 * s * s * s + 2.5 * s * s - 4.0 * s + 2.0;
+            raw.push_back({J, w});
+        }
+    }
+    for (auto &p : raw) {
+        const int J = std::min(std::max(p.first, 0), nc - 1);
+        bool merged = false;
+        for (auto &q : out)
+            if (q.first == J) { q.second += p.second; merged = true; }
+        if (!merged) out.push_back({J, p.second});
+    }
+    std::sort(out.begin(), out.end());
+    out.erase(std::remove_if(out.begin(), out.end(), [](const std::pair<int, double> &p) { return p.second == 0.0; }),
+              out.end());
+}
+
+static void build_interp(Interp1 &ip, const std::vector<int> &nfs, int order, Alloc *al, hipStream_t s) {
+    ip.rcnt.clear(); ip.rj.clear(); ip.rw.clear();
+    ip.ccnt.clear(); ip.ci.clear(); ip.cw.clear();
+    ip.roff.clear(); ip.coff.clear();
+    std::vector<std::pair<int, double>> w;
+    for (int nf : nfs) {
+        const int nc = nf > 1 ? (nf + 1) / 2 : 1;
+        const int r0 = (int)ip.rcnt.size(), c0 = (int)ip.ccnt.size();
+        ip.roff.push_back(r0);
+        ip.coff.push_back(c0);
+        ip.rcnt.resize(r0 + nf, 0);
+        ip.rj.resize((size_t)(r0 + nf) * 4, 0);
+        ip.rw.resize((size_t)(r0 + nf) * 4, 0.0);
+        ip.ccnt.resize(c0 + nc, 0);
+        ip.ci.resize((size_t)(c0 + nc) * 8, 0);
+        ip.cw.resize((size_t)(c0 + nc) * 8, 0.0);
+        for (int i = 0; i < nf; ++i) {
+            interp_weights(nf, order, i, w);
+            if (w.size() > 4) fail(NKS_EINVAL, "interpolation row with %zu entries", w.size());
+            for (auto &p : w) {
+                const int r = r0 + i;
+                ip.rj[(size_t)r * 4 + ip.rcnt[r]] = p.first;
+                ip.rw[(size_t)r * 4 + ip.rcnt[r]] = p.second;
+                ip.rcnt[r]++;
+                const int c = c0 + p.first;
+                if (ip.ccnt[c] >= 8) fail(NKS_EINVAL, "interpolation column overflow");
+                ip.ci[(size_t)c * 8 + ip.ccnt[c]] = i;
+                ip.cw[(size_t)c * 8 + ip.ccnt[c]] = p.second;
+                ip.ccnt[c]++;
+            }
+        }
+    }
+    ip.d_rcnt.upload(al, ip.rcnt, s);
+    ip.d_rj.upload(al, ip.rj, s);
+    ip.d_rw.upload(al, ip.rw, s);
+    ip.d_ccnt.upload(al, ip.ccnt, s);
+    ip.d_ci.upload(al, ip.ci, s);
+    ip.d_cw.upload(al, ip.cw, s);
+    ip.d_roff.upload(al, ip.roff, s);
+    ip.d_coff.upload(al, ip.coff, s);
+}
+
+// 1D coupling set S(o) = {J - I : P[f, I] != 0 and P[f + o, J] != 0}
+static std::set<int> coupling_1d(const Interp1 &ip, const std::vector<int> &nfs, int o) {
+    std::set<int> out;
+    for (size_t b = 0; b < nfs.size(); ++b) {
+        const int nf = nfs[b], r0 = ip.roff[b];
+        for (int f = 0; f < nf; ++f) {
+            const int g = f + o;
+            if (g < 0 || g >= nf) continue;
+            for (int a = 0; a < ip.rcnt[r0 + f]; ++a)
+                for (int c = 0; c < ip.rcnt[r0 + g]; ++c)
+                    out.insert(ip.rj[(size_t)(r0 + g) * 4 + c] - ip.rj[(size_t)(r0 + f) * 4 + a]);
+        }
+    }
+    return out;
+}
+
+static void set_stencil(Stencil &st, std::vector<std::tuple<int, int, int>> offs, Alloc *al, hipStream_t s) {
+    std::sort(offs.begin(), offs.end(), [](const std::tuple<int, int, int> &a, const std::tuple<int, int, int> &b) {
+        return std::make_tuple(std::get<2>(a), std::get<1>(a), std::get<0>(a)) <
+               std::make_tuple(std::get<2>(b), std::get<1>(b), std::get<0>(b));
+    });
+    st.K = (int)offs.size();
+    if (st.K > MAXK) fail(NKS_EINVAL, "coarse stencil of %d points exceeds %d", st.K, MAXK);
+    st.off.resize(3 * st.K);
+    st.R = 0;
+    for (int k = 0; k < st.K; ++k) {
+        st.off[3 * k] = (int8_t)std::get<0>(offs[k]);
+        st.off[3 * k + 1] = (int8_t)std::get<1>(offs[k]);
+        st.off[3 * k + 2] = (int8_t)std::get<2>(offs[k]);
+        if (std::get<0>(offs[k]) == 0 && std::get<1>(offs[k]) == 0 && std::get<2>(offs[k]) == 0) st.diag = k;
+        st.R = std::max({st.R, std::abs(std::get<0>(offs[k])), std::abs(std::get<1>(offs[k])),
+                         std::abs(std::get<2>(offs[k]))});
+    }
+    st.doff.upload(al, st.off, s);
+}
+
+// ---------------------------------------------------------------- kernels: ILU(0)
+struct FacArgs {
+    const SubDev *sub;
+    const Blk *blk;
+    const int *lvlptr, *loc, *inv, *lexi;
+    const int *upd_ptr, *upd_k2, *upd_t, *lin;
+    const double *A;      // K*N operator
+    int N, NE, K, diag, PX, PY, R, Rz;
+    const int8_t *off;
+    double *w;            // K*NE workspace
+    int *err;
+};
+
+// A_i rows of the extended cells, neighbours outside the box dropped
+__global__ void k_ilu_fill(FacArgs a) {
+    const SubDev sd = a.sub[blockIdx.x];
+    const Blk bk = a.blk[sd.blk];
+    for (int e = threadIdx.x; e < sd.next; e += blockDim.x) {
+        const int lx = a.lexi[sd.fac_off + e];
+        const int x = lx % sd.ex, y = (lx / sd.ex) % sd.ey, z = lx / (sd.ex * sd.ey);
+        const int g = bk.off + (sd.ox + x) + bk.nx * ((sd.oy + y) + bk.ny * (sd.oz + z));
+        for (int k = 0; k < a.K; ++k) {
+            const int xx = x + a.off[3 * k], yy = y + a.off[3 * k + 1], zz = z + a.off[3 * k + 2];
+            const bool in = xx >= 0 && xx < sd.ex && yy >= 0 && yy < sd.ey && zz >= 0 && zz < sd.ez;
+            a.w[(size_t)k * a.NE + sd.fac_off + e] = in ? a.A[(size_t)k * a.N + g] : 0.0;
+        }
+    }
+}
+
+// IKJ elimination row by row in hyperplane order.  Row i, for each lower
+// neighbour k in increasing column order: l_ik = a_ik / u_kk, then
+// a_ij -= l_ik u_kj for the j in row i's pattern.  Rows of one hyperplane are
+// independent; their lower neighbours lie on earlier hyperplanes.
+__global__ void k_ilu_factor(FacArgs a) {
+    extern __shared__ double smem_f[];
+    const SubDev sd = a.sub[blockIdx.x];
+    double *row = smem_f + (size_t)threadIdx.x * a.K;
+    const int *lp = a.lvlptr + sd.lvl_off;
+    for (int t = 0; t < sd.nlev; ++t) {
+        const int p0 = lp[t], p1 = lp[t + 1];
+        for (int el = p0 + threadIdx.x; el < p1; el += blockDim.x) {
+            const size_t e = (size_t)sd.fac_off + el;
+            for (int k = 0; k < a.K; ++k) row[k] = a.w[(size_t)k * a.NE + e];
+            const int lc = a.loc[e];
+            for (int kl = 0; kl < a.diag; ++kl) {
+                if (row[kl] == 0.0) continue;
+                const int e2l = a.inv[sd.inv_off + lc + a.lin[kl]];
+                if (e2l < 0) continue;   // neighbour outside the box (only reachable after a bad pivot)
+                const size_t e2 = (size_t)sd.fac_off + e2l;
+                const double l = row[kl] / a.w[(size_t)a.diag * a.NE + e2];
+                row[kl] = l;
+                for (int q = a.upd_ptr[kl]; q < a.upd_ptr[kl + 1]; ++q)
+                    row[a.upd_t[q]] -= l * a.w[(size_t)a.upd_k2[q] * a.NE + e2];
+            }
+            if (!(row[a.diag] != 0.0) || !isfinite(row[a.diag])) atomicOr(a.err, 1);
+            for (int k = 0; k < a.K; ++k) a.w[(size_t)k * a.NE + e] = row[k];
+        }
+        __syncthreads();
+    }
+}
+
+// storage precision: off-diagonals in FT, 1/u_ii in DT
+template <typename FT, typename DT>
+__global__ void k_ilu_store(const double *w, int NE, int K, int diag, FT *f, DT *invd) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)NE) return;
+    for (int k = 0; k < K; ++k) {
+        const double v = w[(size_t)k * NE + e];
+        if (k == diag) {
+            invd[e] = (DT)(1.0 / v);
+        } else if (f) {
+            if constexpr (sizeof(FT) == 2) f[(size_t)k * NE + e] = to_bf16((float)v);
+            else f[(size_t)k * NE + e] = (FT)v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- kernel: subdomain solves
+// LDS layout of the apply kernel: solution tile, stencil offsets, staged
+// coefficients, staged 1/u_ii, staged tile positions (16-byte aligned parts).
+struct ApplyLds {
+    size_t lin, cf, cd, cl, total;
+};
+__host__ __device__ __forceinline__ size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
+__host__ __device__ __forceinline__ ApplyLds apply_lds(size_t vt, size_t ft, size_t dt, int tile, int ncmax,
+                                                       int cap) {
+    ApplyLds L;
+    L.lin = al16(vt * (size_t)tile);
+    L.cf = al16(L.lin + sizeof(int) * MAXK);
+    L.cd = al16(L.cf + ft * (size_t)ncmax * cap);
+    L.cl = al16(L.cd + dt * (size_t)cap);
+    L.total = al16(L.cl + sizeof(int) * (size_t)cap);
+    return L;
+}
+
+struct ApplyArgs {
+    const SubDev *sub;
+    const Blk *blk;
+    const int *lvlptr, *loc, *lexi, *lin;
+    const void *F;        // K*NE off-diagonal factors (FT)
+    const void *invd;     // NE (DT)
+    int NE, K, diag, PX, PY, PZ, R, Rz, tile;
+    const double *r;
+    double *z, *zext;
+    const int *mask;
+    int variant, accumulate, cap;
+};
+
+// One subdomain per workgroup: gather R_i^delta r into the LDS tile, forward
+// sweep with the unit lower factor, backward sweep with the upper factor,
+// then write the owned cells (left-RAS) or the whole box (AS / right-RAS).
+template <typename FT, typename VT, typename DT>
+__global__ void k_ras_apply(ApplyArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SubDev sd = a.sub[blockIdx.x];
+    if (a.mask && !a.mask[sd.blk]) return;
+    const Blk bk = a.blk[sd.blk];
+    const int ncl = a.diag, ncu = a.K - a.diag - 1;
+    const int ncmax = ncl > ncu ? ncl : ncu;
+    const ApplyLds lay = apply_lds(sizeof(VT), sizeof(FT), sizeof(DT), a.tile, ncmax, a.cap);
+    VT *tile = reinterpret_cast<VT *>(smem);
+    int *lin = reinterpret_cast<int *>(smem + lay.lin);
+    FT *cf = reinterpret_cast<FT *>(smem + lay.cf);      // ncmax * cap
+    DT *cd = reinterpret_cast<DT *>(smem + lay.cd);      // cap
+    int *cl = reinterpret_cast<int *>(smem + lay.cl);    // cap
+    const FT *F = reinterpret_cast<const FT *>(a.F);
+    const DT *ID = reinterpret_cast<const DT *>(a.invd);
+    for (int k = threadIdx.x; k < a.K; k += blockDim.x) lin[k] = a.lin[k];
+    for (int i = threadIdx.x; i < a.tile; i += blockDim.x) tile[i] = (VT)0;
+    __syncthreads();
+    // gather R_i^delta r (right-RAS: R_i^0 r, zero on the overlap)
+    for (int c = threadIdx.x; c < sd.next; c += blockDim.x) {
+        const int x = c % sd.ex, y = (c / sd.ex) % sd.ey, z = c / (sd.ex * sd.ey);
+        const int g = bk.off + (sd.ox + x) + bk.nx * ((sd.oy + y) + bk.ny * (sd.oz + z));
+        const bool own = x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1 && z >= sd.lz0 && z < sd.lz1;
+        const double v = (a.variant == NKS_RIGHT_RAS && !own) ? 0.0 : a.r[g];
+        tile[(x + a.R) + a.PX * ((y + a.R) + a.PY * (z + a.Rz))] = (VT)v;
+    }
+    __syncthreads();
+    const int *lp = a.lvlptr + sd.lvl_off;
+    const size_t fo = sd.fac_off;
+    // forward: y_i = r_i - sum_{lower k} L_ik y_k
+    for (int t0 = 0; t0 < sd.nlev;) {
+        const int c0 = lp[t0];
+        int t1 = t0 + 1;
+        while (t1 < sd.nlev && lp[t1 + 1] - c0 <= a.cap) ++t1;
+        const int c1 = lp[t1];
+        for (int e = c0 + threadIdx.x; e < c1; e += blockDim.x) {
+            const int le = e - c0;
+            for (int k = 0; k < ncl; ++k) cf[k * a.cap + le] = F[(size_t)k * a.NE + fo + e];
+            cl[le] = a.loc[fo + e];
+        }
+        __syncthreads();
+        for (int t = t0; t < t1; ++t) {
+            for (int e = lp[t] + threadIdx.x; e < lp[t + 1]; e += blockDim.x) {
+                const int le = e - c0;
+                const int p = cl[le];
+                VT v = tile[p];
+                for (int k = 0; k < ncl; ++k)
+                    v -= (VT)FTraits<FT>::get(cf, (size_t)k * a.cap + le) * tile[p + lin[k]];
+                tile[p] = v;
+            }
+            __syncthreads();
+        }
+        t0 = t1;
+    }
+    // backward: z_i = (y_i - sum_{upper k} U_ik z_k) / u_ii
+    for (int t1 = sd.nlev; t1 > 0;) {
+        const int c1 = lp[t1];
+        int t0 = t1 - 1;
+        while (t0 > 0 && c1 - lp[t0 - 1] <= a.cap) --t0;
+        const int c0 = lp[t0];
+        for (int e = c0 + threadIdx.x; e < c1; e += blockDim.x) {
+            const int le = e - c0;
+            for (int k = 0; k < ncu; ++k) cf[k * a.cap + le] = F[(size_t)(a.diag + 1 + k) * a.NE + fo + e];
+            cd[le] = ID[fo + e];
+            cl[le] = a.loc[fo + e];
+        }
+        __syncthreads();
+        for (int t = t1 - 1; t >= t0; --t) {
+            for (int e = lp[t] + threadIdx.x; e < lp[t + 1]; e += blockDim.x) {
+                const int le = e - c0;
+                const int p = cl[le];
+                VT v = tile[p];
+                for (int k = 0; k < ncu; ++k)
+                    v -= (VT)FTraits<FT>::get(cf, (size_t)k * a.cap + le) * tile[p + lin[a.diag + 1 + k]];
+                tile[p] = v * (VT)cd[le];
+            }
+            __syncthreads();
+        }
+        t1 = t0;
+    }
+    // scatter
+    if (a.variant == NKS_LEFT_RAS) {
+        const int ox = sd.lx1 - sd.lx0, oy = sd.ly1 - sd.ly0, oz = sd.lz1 - sd.lz0;
+        const int no = ox * oy * oz;
+        for (int c = threadIdx.x; c < no; c += blockDim.x) {
+            const int x = sd.lx0 + c % ox, y = sd.ly0 + (c / ox) % oy, z = sd.lz0 + c / (ox * oy);
+            const int g = bk.off + (sd.ox + x) + bk.nx * ((sd.oy + y) + bk.ny * (sd.oz + z));
+            const double v = (double)tile[(x + a.R) + a.PX * ((y + a.R) + a.PY * (z + a.Rz))];
+            a.z[g] = a.accumulate ? a.z[g] + v : v;
+        }
+    } else {
+        for (int c = threadIdx.x; c < sd.next; c += blockDim.x) {
+            const int x = c % sd.ex, y = (c / sd.ex) % sd.ey, z = c / (sd.ex * sd.ey);
+            a.zext[fo + c] = (double)tile[(x + a.R) + a.PX * ((y + a.R) + a.PY * (z + a.Rz))];
+        }
+    }
+}
+
+// AS / right-RAS: z_g = sum over the boxes whose extension holds g (box order)
+__device__ __forceinline__ int box_of(int x, int n, int P) {
+    const int base = n / P, rem = n % P;
+    const int big = rem * (base + 1);
+    return x < big ? x / (base + 1) : rem + (x - big) / base;
+}
+
+__global__ void k_ras_gather(const Blk *blk, int B, int N, const BlkPart *part, const SubDev *sub,
+                             const double *zext, double *z, const int *mask, int accumulate) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int b = find_blk(blk, B, i);
+    if (mask && !mask[b]) return;
+    const Blk k = blk[b];
+    const BlkPart P = part[b];
+    const int l = i - k.off;
+    const int x = l % k.nx, y = (l / k.nx) % k.ny, zz = l / (k.nx * k.ny);
+    const int qx = box_of(x, k.nx, P.px), qy = box_of(y, k.ny, P.py), qz = box_of(zz, k.nz, P.pz);
+    double s = 0.0;
+    for (int cz = qz - 1; cz <= qz + 1; ++cz) {
+        if (cz < 0 || cz >= P.pz) continue;
+        for (int cy = qy - 1; cy <= qy + 1; ++cy) {
+            if (cy < 0 || cy >= P.py) continue;
+            for (int cx = qx - 1; cx <= qx + 1; ++cx) {
+                if (cx < 0 || cx >= P.px) continue;
+                const SubDev sd = sub[P.first + cx + P.px * (cy + P.py * cz)];
+                const int lx = x - sd.ox, ly = y - sd.oy, lz = zz - sd.oz;
+                if (lx < 0 || lx >= sd.ex || ly < 0 || ly >= sd.ey || lz < 0 || lz >= sd.ez) continue;
+                s += zext[sd.fac_off + lx + sd.ex * (ly + sd.ey * lz)];
+            }
+        }
+    }
+    z[i] = accumulate ? z[i] + s : s;
+}
+
+// ---------------------------------------------------------------- kernels: grid transfer
+struct XferArgs {
+    const Blk *fblk, *cblk;
+    int B, Nf, Nc;
+    const int *rcnt[3], *rj[3], *ccnt[3], *ci[3], *roff[3], *coff[3];
+    const double *rw[3], *cw[3];
+    const int *mask;
+};
+
+// r_c = P^T r_f (gather over the fine support of each coarse cell)
+__global__ void k_restrict(XferArgs a, const double *rf, double *rc) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= a.Nc) return;
+    const int b = find_blk(a.cblk, a.B, I);
+    if (a.mask && !a.mask[b]) return;
+    const Blk cb = a.cblk[b], fb = a.fblk[b];
+    const int l = I - cb.off;
+    const int X = l % cb.nx, Y = (l / cb.nx) % cb.ny, Z = l / (cb.nx * cb.ny);
+    const int cx = a.coff[0][b] + X, cy = a.coff[1][b] + Y, cz = a.coff[2][b] + Z;
+    double s = 0.0;
+    for (int qz = 0; qz < a.ccnt[2][cz]; ++qz) {
+        const int fz = a.ci[2][cz * 8 + qz];
+        const double wz = a.cw[2][cz * 8 + qz];
+        for (int qy = 0; qy < a.ccnt[1][cy]; ++qy) {
+            const int fy = a.ci[1][cy * 8 + qy];
+            const double wy = a.cw[1][cy * 8 + qy];
+            for (int qx = 0; qx < a.ccnt[0][cx]; ++qx) {
+                const int fx = a.ci[0][cx * 8 + qx];
+                const double wx = a.cw[0][cx * 8 + qx];
+                s += (wx * wy * wz) * rf[fb.off + fx + fb.nx * (fy + fb.ny * fz)];
+            }
+        }
+    }
+    rc[I] = s;
+}
+
+// z_f += P e_c
+__global__ void k_prolong_add(XferArgs a, const double *ec, double *zf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.Nf) return;
+    const int b = find_blk(a.fblk, a.B, i);
+    if (a.mask && !a.mask[b]) return;
+    const Blk cb = a.cblk[b], fb = a.fblk[b];
+    const int l = i - fb.off;
+    const int x = l % fb.nx, y = (l / fb.nx) % fb.ny, z = l / (fb.nx * fb.ny);
+    const int rx = a.roff[0][b] + x, ry = a.roff[1][b] + y, rz = a.roff[2][b] + z;
+    double s = 0.0;
+    for (int qz = 0; qz < a.rcnt[2][rz]; ++qz) {
+        const int Jz = a.rj[2][rz * 4 + qz];
+        const double wz = a.rw[2][rz * 4 + qz];
+        for (int qy = 0; qy < a.rcnt[1][ry]; ++qy) {
+            const int Jy = a.rj[1][ry * 4 + qy];
+            const double wy = a.rw[1][ry * 4 + qy];
+            for (int qx = 0; qx < a.rcnt[0][rx]; ++qx) {
+                const int Jx = a.rj[0][rx * 4 + qx];
+                const double wx = a.rw[0][rx * 4 + qx];
+                s += (wx * wy * wz) * ec[cb.off + Jx + cb.nx * (Jy + cb.ny * Jz)];
+            }
+        }
+    }
+    zf[i] += s;
+}
+
+// Galerkin A_c = P^T A P: one thread per coarse cell, accumulators in LDS.
+__global__ void k_rap(XferArgs a, const double *Af, int Kf, const int8_t *offf, double *Ac, int Kc,
+                      const int *slot, int Rc) {
+    extern __shared__ double acc_s[];
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    double *acc = acc_s + (size_t)threadIdx.x * Kc;
+    if (I >= a.Nc) return;
+    for (int k = 0; k < Kc; ++k) acc[k] = 0.0;
+    const int b = find_blk(a.cblk, a.B, I);
+    const Blk cb = a.cblk[b], fb = a.fblk[b];
+    const int l = I - cb.off;
+    const int X = l % cb.nx, Y = (l / cb.nx) % cb.ny, Z = l / (cb.nx * cb.ny);
+    const int cx = a.coff[0][b] + X, cy = a.coff[1][b] + Y, cz = a.coff[2][b] + Z;
+    const int S = 2 * Rc + 1;
+    for (int qz = 0; qz < a.ccnt[2][cz]; ++qz) {
+        const int fz = a.ci[2][cz * 8 + qz];
+        const double wz = a.cw[2][cz * 8 + qz];
+        for (int qy = 0; qy < a.ccnt[1][cy]; ++qy) {
+            const int fy = a.ci[1][cy * 8 + qy];
+            const double wy = a.cw[1][cy * 8 + qy];
+            for (int qx = 0; qx < a.ccnt[0][cx]; ++qx) {
+                const int fx = a.ci[0][cx * 8 + qx];
+                const double wf = a.cw[0][cx * 8 + qx] * wy * wz;
+                const int f = fb.off + fx + fb.nx * (fy + fb.ny * fz);
+                for (int k = 0; k < Kf; ++k) {
+                    const int gx = fx + offf[3 * k], gy = fy + offf[3 * k + 1], gz = fz + offf[3 * k + 2];
+                    if (gx < 0 || gx >= fb.nx || gy < 0 || gy >= fb.ny || gz < 0 || gz >= fb.nz) continue;
+                    const double av = Af[(size_t)k * a.Nf + f];
+                    if (av == 0.0) continue;
+                    const double wa = wf * av;
+                    const int rx = a.roff[0][b] + gx, ry = a.roff[1][b] + gy, rz = a.roff[2][b] + gz;
+                    for (int pz = 0; pz < a.rcnt[2][rz]; ++pz) {
+                        const int Jz = a.rj[2][rz * 4 + pz];
+                        const double vz = a.rw[2][rz * 4 + pz];
+                        for (int py = 0; py < a.rcnt[1][ry]; ++py) {
+                            const int Jy = a.rj[1][ry * 4 + py];
+                            const double vy = a.rw[1][ry * 4 + py];
+                            for (int px = 0; px < a.rcnt[0][rx]; ++px) {
+                                const int Jx = a.rj[0][rx * 4 + px];
+                                const double vx = a.rw[0][rx * 4 + px];
+                                const int sl = slot[(Jx - X + Rc) + S * ((Jy - Y + Rc) + S * (Jz - Z + Rc))];
+                                acc[sl] += wa * (vx * vy * vz);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    for (int k = 0; k < Kc; ++k) Ac[(size_t)k * a.Nc + I] = acc[k];
+}
+
+__global__ void k_fill(int N, double v, double *x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) x[i] = v;
+}
+
+// ---------------------------------------------------------------- host: hierarchy
+static XferArgs xfer_args(Level &F, Level &C, const int *mask) {
+    XferArgs a;
+    a.fblk = F.spp->blk.p;
+    a.cblk = C.spp->blk.p;
+    a.B = F.spp->B;
+    a.Nf = F.spp->N;
+    a.Nc = C.spp->N;
+    for (int d = 0; d < 3; ++d) {
+        a.rcnt[d] = F.ip[d].d_rcnt.p;
+        a.rj[d] = F.ip[d].d_rj.p;
+        a.rw[d] = F.ip[d].d_rw.p;
+        a.ccnt[d] = F.ip[d].d_ccnt.p;
+        a.ci[d] = F.ip[d].d_ci.p;
+        a.cw[d] = F.ip[d].d_cw.p;
+        a.roff[d] = F.ip[d].d_roff.p;
+        a.coff[d] = F.ip[d].d_coff.p;
+    }
+    a.mask = mask;
+    return a;
+}
+
+void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
+    J = Jm;
+    g = Jm->g;
+    d = dd;
+    L = std::max(1, std::min(d.levels, 6));
+    Alloc *al = &g->al;
+    hipStream_t s = g->s;
+    lev.clear();
+    tiles_.clear();
+    lev.emplace_back(new Level());
+    lev[0]->spp = &g->sp;
+    lev[0]->A = &Jm->op;
+    for (int l = 0; l + 1 < L; ++l) {
+        Level &F = *lev[l];
+        lev.emplace_back(new Level());
+        Level &C = *lev[l + 1];
+        std::vector<Blk> cb;
+        std::vector<int> nfx, nfy, nfz;
+        for (const Blk &k : F.spp->hblk) {
+            cb.push_back({k.nx > 1 ? (k.nx + 1) / 2 : 1, k.ny > 1 ? (k.ny + 1) / 2 : 1,
+                          k.nz > 1 ? (k.nz + 1) / 2 : 1, 0});
+            nfx.push_back(k.nx);
+            nfy.push_back(k.ny);
+            nfz.push_back(k.nz);
+        }
+        C.sp.build(al, cb, s);
+        C.spp = &C.sp;
+        build_interp(F.ip[0], nfx, d.interp_order, al, s);
+        build_interp(F.ip[1], nfy, d.interp_order, al, s);
+        build_interp(F.ip[2], nfz, d.interp_order, al, s);
+        // coarse stencil: union over fine offsets of the tensor 1D coupling sets
+        const Stencil &fs = F.A->st;
+        std::set<std::tuple<int, int, int>> offs;
+        std::map<int, std::set<int>> cx, cy, cz;
+        for (int k = 0; k < fs.K; ++k) {
+            const int ox = fs.off[3 * k], oy = fs.off[3 * k + 1], oz = fs.off[3 * k + 2];
+            if (!cx.count(ox)) cx[ox] = coupling_1d(F.ip[0], nfx, ox);
+            if (!cy.count(oy)) cy[oy] = coupling_1d(F.ip[1], nfy, oy);
+            if (!cz.count(oz)) cz[oz] = coupling_1d(F.ip[2], nfz, oz);
+            for (int a : cx[ox])
+                for (int b : cy[oy])
+                    for (int c : cz[oz]) offs.insert({a, b, c});
+        }
+        offs.insert({0, 0, 0});
+        C.own.sp = &C.sp;
+        set_stencil(C.own.st, std::vector<std::tuple<int, int, int>>(offs.begin(), offs.end()), al, s);
+        C.own.coef.alloc(al, (size_t)C.own.st.K * C.sp.N);
+        C.A = &C.own;
+        // slot table for the Galerkin kernel
+        const int Rc = C.own.st.R, S = 2 * Rc + 1;
+        std::vector<int> slot(S * S * S, 0);
+        for (int k = 0; k < C.own.st.K; ++k)
+            slot[(C.own.st.off[3 * k] + Rc) + S * ((C.own.st.off[3 * k + 1] + Rc) + S * (C.own.st.off[3 * k + 2] + Rc))] = k;
+        F.rap_slot.upload(al, slot, s);
+        F.rap_R = Rc;
+    }
+    for (int l = 0; l < L; ++l) {
+        Level &V = *lev[l];
+        TileDims geo;
+        build_partition(V, d, d.overlap[std::min(l, 7)], al, s, geo);
+        const size_t NE = V.next_total, K = V.A->st.K;
+        V.w64.alloc(al, K * NE);
+        if (d.precision == NKS_FP64) {
+            V.invd64.alloc(al, NE);
+        } else {
+            V.invd32.alloc(al, NE);
+            if (d.precision == NKS_FP32) V.f32.alloc(al, K * NE);
+            else V.f16.alloc(al, K * NE);
+        }
+        if (d.variant != NKS_LEFT_RAS) V.zext.alloc(al, NE);
+        V.r.alloc(al, V.spp->N);
+        V.t.alloc(al, V.spp->N);
+        V.bc.alloc(al, V.spp->N);
+        V.xc.alloc(al, V.spp->N);
+        // geometry for kernels kept in hsub / lin_pad; remember tile dims
+        tiles_.push_back(geo);
+    }
+    if (L > 1) coarse.ensure(al, *lev[L - 1]->spp, std::max(1, std::min(d.coarse_restart, 30)), false, s);
+    int dev = 0, maxlds = 65536;
+    HIPC(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        maxlds = 65536;
+    lds_bytes = std::min(maxlds, 160 * 1024);
+}
+
+void Ras::factor() {
+    hipStream_t s = g->s;
+    for (int l = 0; l < L; ++l) {
+        Level &V = *lev[l];
+        if (l > 0) {
+            Level &F = *lev[l - 1];
+            XferArgs a = xfer_args(F, V, nullptr);
+            const int Kc = V.own.st.K;
+            const int bs = 64;
+            const size_t sh = (size_t)bs * Kc * sizeof(double);
+            HIPC(hipFuncSetAttribute((const void *)k_rap, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+            ProfScope ps("rap", s, l);
+            k_rap<<<nblk(V.spp->N, bs), bs, sh, s>>>(a, F.A->coef.p, F.A->st.K, F.A->st.doff.p, V.own.coef.p, Kc,
+                                                    F.rap_slot.p, F.rap_R);
+            KCHECK();
+        }
+        const TileDims &td = tiles_[l];
+        FacArgs fa;
+        fa.sub = V.sub.p;
+        fa.blk = V.spp->blk.p;
+        fa.lvlptr = V.lvlptr.p;
+        fa.loc = V.loc.p;
+        fa.inv = V.inv.p;
+        fa.lexi = V.lexi.p;
+        fa.upd_ptr = V.upd_ptr.p;
+        fa.upd_k2 = V.upd_k2.p;
+        fa.upd_t = V.upd_t.p;
+        fa.lin = V.lin_pad.p;
+        fa.A = V.A->coef.p;
+        fa.N = V.spp->N;
+        fa.NE = V.next_total;
+        fa.K = V.A->st.K;
+        fa.diag = V.A->st.diag;
+        fa.PX = td.PX;
+        fa.PY = td.PY;
+        fa.R = td.R;
+        fa.Rz = td.Rz;
+        fa.off = V.A->st.doff.p;
+        fa.w = V.w64.p;
+        fa.err = V.err.p;
+        k_ilu_fill<<<V.nsub, 256, 0, s>>>(fa);
+        KCHECK();
+        const int bs = 64;
+        const size_t sh = (size_t)bs * fa.K * sizeof(double);
+        HIPC(hipFuncSetAttribute((const void *)k_ilu_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+        ProfScope ps("ilu_factor", s, l);
+        k_ilu_factor<<<V.nsub, bs, sh, s>>>(fa);
+        KCHECK();
+        const int NE = V.next_total;
+        if (d.precision == NKS_FP64) {
+            k_ilu_store<double, double><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, nullptr, V.invd64.p);
+        } else if (d.precision == NKS_FP32) {
+            k_ilu_store<float, float><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, V.f32.p, V.invd32.p);
+        } else {
+            k_ilu_store<uint16_t, float><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, V.f16.p, V.invd32.p);
+        }
+        KCHECK();
+    }
+}
+
+void Ras::check_pivots() {
+    for (int l = 0; l < L; ++l) {
+        int e = 0;
+        HIPC(hipMemcpyAsync(&e, lev[l]->err.p, sizeof(int), hipMemcpyDeviceToHost, g->s));
+        HIPC(hipStreamSynchronize(g->s));
+        if (e) {
+            HIPC(hipMemsetAsync(lev[l]->err.p, 0, sizeof(int), g->s));
+            fail(NKS_EZEROPIVOT, "zero pivot in a subdomain ILU(0) factorization on level %d", l);
+        }
+    }
+}
+
+static int level_index(const Ras &M, const Level &V) {
+    for (int l = 0; l < M.L; ++l)
+        if (M.lev[l].get() == &V) return l;
+    return -1;
+}
+
+template <typename FT, typename VT, typename DT>
+static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, double *z, const int *mask,
+                         bool accumulate) {
+    ApplyArgs a;
+    a.sub = V.sub.p;
+    a.blk = V.spp->blk.p;
+    a.lvlptr = V.lvlptr.p;
+    a.loc = V.loc.p;
+    a.lexi = V.lexi.p;
+    a.lin = V.lin_pad.p;
+    if (M.d.precision == NKS_FP64) a.F = V.w64.p;
+    else if (M.d.precision == NKS_FP32) a.F = V.f32.p;
+    else a.F = V.f16.p;
+    a.invd = M.d.precision == NKS_FP64 ? (const void *)V.invd64.p : (const void *)V.invd32.p;
+    a.NE = V.next_total;
+    a.K = V.A->st.K;
+    a.diag = V.A->st.diag;
+    a.PX = td.PX;
+    a.PY = td.PY;
+    a.PZ = td.PZ;
+    a.R = td.R;
+    a.Rz = td.Rz;
+    a.tile = td.PX * td.PY * td.PZ;
+    a.r = r;
+    a.z = z;
+    a.zext = V.zext.p;
+    a.mask = mask;
+    a.variant = M.d.variant;
+    a.accumulate = accumulate ? 1 : 0;
+    const int ncmax = std::max(a.diag, a.K - a.diag - 1);
+    const size_t budget = (size_t)M.lds_bytes;
+    const size_t fixed = apply_lds(sizeof(VT), sizeof(FT), sizeof(DT), a.tile, ncmax, 0).total + 64;
+    const size_t per = sizeof(FT) * (size_t)ncmax + sizeof(DT) + sizeof(int);
+    if (fixed + per * (size_t)V.max_lvl > budget)
+        fail(NKS_EINVAL, "subdomain tile of %d cells and hyperplanes of %d cells do not fit in LDS (%zu bytes)",
+             a.tile, V.max_lvl, budget);
+    a.cap = (int)std::min<size_t>((budget - fixed) / per, (size_t)V.max_next);
+    a.cap = std::max(a.cap, V.max_lvl);
+    const size_t sh = apply_lds(sizeof(VT), sizeof(FT), sizeof(DT), a.tile, ncmax, a.cap).total;
+    if (sh > budget) fail(NKS_EINVAL, "LDS layout of %zu bytes exceeds %zu", sh, budget);
+    const void *fn = (const void *)k_ras_apply<FT, VT, DT>;
+    HIPC(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+    const int bs = td.PZ == 1 ? 64 : 256;
+    {
+        ProfScope ps("ras_apply", M.g->s, level_index(M, V));
+        k_ras_apply<FT, VT, DT><<<V.nsub, bs, sh, M.g->s>>>(a);
+        KCHECK();
+    }
+    if (M.d.variant != NKS_LEFT_RAS) {
+        k_ras_gather<<<nblk(V.spp->N, 256), 256, 0, M.g->s>>>(V.spp->blk.p, V.spp->B, V.spp->N, V.part.p,
+                                                              V.sub.p, V.zext.p, z, mask, accumulate ? 1 : 0);
+        KCHECK();
+    }
+}
+
+void Ras::apply_level(int l, const double *r, double *z, const int *mask, bool accumulate) {
+    Level &V = *lev[l];
+    const TileDims &td = tiles_[l];
+    if (d.precision == NKS_FP64) launch_apply<double, double, double>(*this, V, td, r, z, mask, accumulate);
+    else if (d.precision == NKS_FP32) launch_apply<float, float, float>(*this, V, td, r, z, mask, accumulate);
+    else launch_apply<uint16_t, float, float>(*this, V, td, r, z, mask, accumulate);
+}
+
+void Ras::restrict_to(int l, const double *rf, double *rc, const int *mask) {
+    XferArgs a = xfer_args(*lev[l], *lev[l + 1], mask);
+    k_restrict<<<nblk(a.Nc, 256), 256, 0, g->s>>>(a, rf, rc);
+    KCHECK();
+}
+
+void Ras::prolong_add(int l, const double *ec, double *zf, const int *mask) {
+    XferArgs a = xfer_args(*lev[l], *lev[l + 1], mask);
+    k_prolong_add<<<nblk(a.Nf, 256), 256, 0, g->s>>>(a, ec, zf);
+    KCHECK();
+}
+
+static void zero(const Space &S, double *x, hipStream_t s) {
+    k_fill<<<nblk(S.N, 256), 256, 0, s>>>(S.N, 0.0, x);
+    KCHECK();
+}
+
+void Ras::coarse_solve(const double *b, double *x, const int *mask) {
+    Level &C = *lev[L - 1];
+    const Space &S = *C.spp;
+    hipStream_t s = g->s;
+    zero(S, x, s);
+    MatVec A = [&](const double *xx, double *yy, const double *bb, const int *mk) {
+        launch_spmv(*C.A, xx, yy, bb, mk, s);
+    };
+    Precond P = [&](const double *rr, double *zz, const int *mk) { apply_level(L - 1, rr, zz, mk, false); };
+    GmOpts o;
+    o.rtol = d.coarse_rtol;
+    o.atol = 0.0;
+    o.maxit = d.coarse_maxit;
+    o.flexible = false;
+    o.check_every = 1;
+    coarse.solve(A, P, b, x, true, o, mask, s);
+    ++coarse_calls;
+}
+
+// X = MG(b, l, 0) (Algorithm 1) in the composition selected by the cycle type
+void Ras::vcycle(int l, const double *b, double *x, const int *mask) {
+    if (l == L - 1) {
+        coarse_solve(b, x, mask);
+        return;
+    }
+    Level &F = *lev[l];
+    Level &C = *lev[l + 1];
+    const Space &S = *F.spp;
+    hipStream_t s = g->s;
+    const int cyc = d.cycle;
+    if (cyc == NKS_ADDITIVE || cyc == NKS_COARSE_ONLY) {
+        restrict_to(l, b, C.bc.p, mask);
+        vcycle(l + 1, C.bc.p, C.xc.p, mask);
+        zero(S, x, s);
+        prolong_add(l, C.xc.p, x, mask);
+        if (cyc == NKS_ADDITIVE) apply_level(l, b, x, mask, true);
+        return;
+    }
+    int mu = d.mu, nu = d.nu;
+    if (cyc == NKS_LEFT_KASKADE) { mu = 0; nu = 1; }
+    if (cyc == NKS_RIGHT_KASKADE) { mu = 1; nu = 0; }
+    const double *rr = b;
+    if (mu == 0) {
+        zero(S, x, s);
+    } else {
+        apply_level(l, b, x, mask, false);          // x = M^{-1} b (x started at 0)
+        for (int k = 1; k < mu; ++k) {
+            launch_spmv(*F.A, x, F.r.p, b, mask, s);
+            apply_level(l, F.r.p, x, mask, true);
+        }
+        launch_spmv(*F.A, x, F.r.p, b, mask, s);
+        rr = F.r.p;
+    }
+    restrict_to(l, rr, C.bc.p, mask);
+    vcycle(l + 1, C.bc.p, C.xc.p, mask);
+    prolong_add(l, C.xc.p, x, mask);
+    for (int k = 0; k < nu; ++k) {
+        launch_spmv(*F.A, x, F.r.p, b, mask, s);
+        apply_level(l, F.r.p, x, mask, true);
+    }
+}
+
+void Ras::apply(const double *r, double *z, const int *mask) {
+    if (L == 1) apply_level(0, r, z, mask, false);
+    else vcycle(0, r, z, mask);
+}
+
+}  // namespace nks

@@ -91,6 +91,7 @@ class SolverSettings:
     alpha: float = 1e-4
     max_newton: int = 50
     max_backtracks: int = 20
+    stol: float = 1e-8                   # relative Newton step test (PETSc default)
     precision: str = "fp64"              # fp64 | fp32 | bf16
     flexible: Optional[bool] = None      # None: FGMRES iff levels > 1 or precision != fp64
 
