@@ -57,7 +57,10 @@ class TorchAllocator:
                                                       self.stream)
 
         def _free(ptr, ctx):
-            torch.cuda.caching_allocator_delete(ptr)
+            # frees can arrive while the interpreter shuts down
+            tc = getattr(torch, "cuda", None)
+            if tc is not None and getattr(tc, "caching_allocator_delete", None) is not None:
+                tc.caching_allocator_delete(ptr)
 
         self.alloc = L.ALLOC_FN(_alloc)
         self.free = L.FREE_FN(_free)
@@ -93,6 +96,28 @@ def newton_desc(s):
     return d
 
 
+class _Ordered:
+    """Orders a library call on the grid stream after the caller's current
+    stream, and the caller's stream after the call."""
+
+    def __init__(self, grid):
+        self.grid = grid
+
+    def __enter__(self):
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.grid.device)
+        if cur.cuda_stream != self.grid.stream.cuda_stream:
+            self.grid.stream.wait_stream(cur)
+        return self
+
+    def __exit__(self, *exc):
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.grid.device)
+        if cur.cuda_stream != self.grid.stream.cuda_stream:
+            cur.wait_stream(self.grid.stream)
+        return False
+
+
 class Grid:
     """nks_grid over one or more reservoirs (synthetic.configs.Problem records)."""
 
@@ -102,7 +127,9 @@ class Grid:
             problems = [problems]
         self.problems = list(problems)
         self.device = torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # the library works on its own stream (default priority): graph capture
+        # is not available on the legacy default stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         keep = []
         res = (L.nks_reservoir_desc * len(problems))()
         for k, pr in enumerate(problems):
@@ -173,13 +200,15 @@ class Grid:
     # -- entry points
     def hydrostatic(self, p_top):
         p = self.zeros()
-        check(lib().nks_hydrostatic_init(self.h, float(p_top), _vp(p)))
+        with _Ordered(self):
+            check(lib().nks_hydrostatic_init(self.h, float(p_top), _vp(p)))
         return p
 
     def residual(self, p, pn, pnm1=None, dt=86400.0, order=1, out=None):
         F = self.zeros() if out is None else out
-        check(lib().nks_residual(self.h, _vp(p), _vp(pn), _vp(pnm1 if pnm1 is not None else pn),
-                                 float(dt), int(order), _vp(F)))
+        with _Ordered(self):
+            check(lib().nks_residual(self.h, _vp(p), _vp(pn), _vp(pnm1 if pnm1 is not None else pn),
+                                     float(dt), int(order), _vp(F)))
         return F
 
     def matrix(self):
@@ -187,20 +216,23 @@ class Grid:
 
     def jacobian(self, p, pn, pnm1=None, dt=86400.0, order=1, J=None, F=None):
         J = J if J is not None else Matrix(self)
-        check(lib().nks_jacobian(self.h, _vp(p), _vp(pn), _vp(pnm1 if pnm1 is not None else pn),
-                                 float(dt), int(order), J.h, _vp(F)))
+        with _Ordered(self):
+            check(lib().nks_jacobian(self.h, _vp(p), _vp(pn), _vp(pnm1 if pnm1 is not None else pn),
+                                     float(dt), int(order), J.h, _vp(F)))
         return J
 
     def residual_dlogk_t(self, p, lam):
         out = self.zeros()
-        check(lib().nks_residual_dlogk_transpose_apply(self.h, _vp(p), _vp(lam), _vp(out)))
+        with _Ordered(self):
+            check(lib().nks_residual_dlogk_transpose_apply(self.h, _vp(p), _vp(lam), _vp(out)))
         return out
 
     def newton_step(self, p, pn, pnm1, dt, order, settings, raise_on_fail=True):
         st = L.nks_newton_stats()
         nd, rd = newton_desc(settings), ras_desc(settings)
-        code = lib().nks_newton_step(self.h, _vp(p), _vp(pn), _vp(pnm1 if pnm1 is not None else pn),
-                                     float(dt), int(order), C.byref(nd), C.byref(rd), C.byref(st))
+        with _Ordered(self):
+            code = lib().nks_newton_step(self.h, _vp(p), _vp(pn), _vp(pnm1 if pnm1 is not None else pn),
+                                         float(dt), int(order), C.byref(nd), C.byref(rd), C.byref(st))
         if code != 0 and (raise_on_fail or code != -5):
             check(code)
         k = st.newton_its
@@ -239,12 +271,14 @@ class Matrix:
 
     def apply(self, x, out=None):
         y = self.grid.zeros() if out is None else out
-        check(lib().nks_matrix_apply(self.h, _vp(x), _vp(y)))
+        with _Ordered(self.grid):
+            check(lib().nks_matrix_apply(self.h, _vp(x), _vp(y)))
         return y
 
     def apply_transpose(self, x, out=None):
         y = self.grid.zeros() if out is None else out
-        check(lib().nks_jacobian_transpose_apply(self.h, _vp(x), _vp(y)))
+        with _Ordered(self.grid):
+            check(lib().nks_jacobian_transpose_apply(self.h, _vp(x), _vp(y)))
         return y
 
 
@@ -261,7 +295,8 @@ class Ras:
     def setup(self, J=None):
         J = J or self.J
         self.J = J
-        check(lib().nks_ras_setup(J.h, C.byref(self.desc), C.byref(self.h)))
+        with _Ordered(self.grid):
+            check(lib().nks_ras_setup(J.h, C.byref(self.desc), C.byref(self.h)))
         return self
 
     def __del__(self):
@@ -283,21 +318,25 @@ class Ras:
 
     def apply(self, r, out=None):
         z = self.grid.zeros() if out is None else out
-        check(lib().nks_ras_apply(self.h, _vp(r), _vp(z)))
+        with _Ordered(self.grid):
+            check(lib().nks_ras_apply(self.h, _vp(r), _vp(z)))
         return z
 
     def apply_level(self, level, r, out=None):
         z = self._vec(level) if out is None else out
-        check(lib().nks_ras_apply_level(self.h, int(level), _vp(r), _vp(z)))
+        with _Ordered(self.grid):
+            check(lib().nks_ras_apply_level(self.h, int(level), _vp(r), _vp(z)))
         return z
 
     def restrict(self, level, rf):
         rc = self._vec(level + 1)
-        check(lib().nks_ras_restrict(self.h, int(level), _vp(rf), _vp(rc)))
+        with _Ordered(self.grid):
+            check(lib().nks_ras_restrict(self.h, int(level), _vp(rf), _vp(rc)))
         return rc
 
     def prolong_add(self, level, ec, zf):
-        check(lib().nks_ras_prolong_add(self.h, int(level), _vp(ec), _vp(zf)))
+        with _Ordered(self.grid):
+            check(lib().nks_ras_prolong_add(self.h, int(level), _vp(ec), _vp(zf)))
         return zf
 
     def level_export(self, level):
@@ -322,7 +361,8 @@ def gmres_solve(J, M, b, x=None, restart=30, rtol=1e-5, atol=1e-8, maxit=10000, 
     res = (C.c_double * grid.B)()
     st.its = C.cast(its, C.POINTER(C.c_int))
     st.res = C.cast(res, C.POINTER(C.c_double))
-    check(lib().nks_gmres_solve(J.h, M.h if M is not None else None, _vp(b), _vp(x),
-                                C.byref(d), C.byref(st)))
+    with _Ordered(grid):
+        check(lib().nks_gmres_solve(J.h, M.h if M is not None else None, _vp(b), _vp(x),
+                                    C.byref(d), C.byref(st)))
     return x, dict(iterations=st.iterations, total=st.total_iterations, residual=st.residual,
                    converged=st.converged, its=list(its), res=list(res))

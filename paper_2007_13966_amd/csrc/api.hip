@@ -71,6 +71,16 @@ static std::vector<hipEvent_t> g_event_pool;
 
 bool prof_on() { return g_prof_on; }
 
+void set_lds(const void *fn, size_t bytes) {
+    static std::mutex mu;
+    static std::map<const void *, size_t> done;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = done.find(fn);
+    if (it != done.end() && it->second >= bytes) return;
+    HIPC(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    done[fn] = bytes;
+}
+
 static hipEvent_t take_event() {
     if (!g_event_pool.empty()) {
         hipEvent_t e = g_event_pool.back();
@@ -84,6 +94,8 @@ static hipEvent_t take_event() {
 
 ProfScope::ProfScope(const char *nm, hipStream_t st, int lvl) : s(st), name(nm), level(lvl) {
     if (!g_prof_on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     a = take_event();
     b = take_event();

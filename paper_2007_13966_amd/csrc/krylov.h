@@ -17,6 +17,7 @@ struct GmOpts {
     int maxit = 10000;
     bool flexible = false;
     int check_every = 1;
+    int graph_chunk = 0;   // > 0: replay captured chunks of this many iterations (A and M must be capturable)
 };
 
 struct GmDev {
@@ -27,6 +28,8 @@ struct GmDev {
     double *hj;
     double *tol, *beta, *res;
     int *active, *conv, *kdim, *its, *upd;
+    int *flag;        // host-mapped, 4 slots of nb: iteration j (slot j%3) and restart (slot 3) activity
+    int nb;
     int m, maxit;
     double rtol, atol;
 };
@@ -41,6 +44,15 @@ struct Gmres {
     DBuf<const double *> vptr, zptr;
     Reducer red;
     int *hint = nullptr;
+    volatile int *hflag = nullptr;   // mapped pinned flags (host view)
+    int *dflag = nullptr;            // device view
+    int flag_b = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // captured iteration chunks (valid while the buffers behind A and M are)
+    std::vector<hipGraphExec_t> gexec;
+    int gchunk = 0;
+    bool graphs_ok = true;
+    void invalidate_graphs();
 
     void ensure(Alloc *al, const Space &sp, int m, bool flexible, hipStream_t s);
     GmDev dev(double rtol, double atol, int maxit);

@@ -22,8 +22,11 @@ void Space::build(Alloc *al, const std::vector<Blk> &b, hipStream_t s) {
     for (int k = 0; k < B; ++k) {
         hblk[k].off = N;
         const int n = b[k].nx * b[k].ny * b[k].nz;
+        // at most MAXCH chunks per block, at least CHUNK cells each
+        int nch = std::max(1, std::min(MAXCH, (n + CHUNK - 1) / CHUNK));
+        const int cs = (n + nch - 1) / nch;
         hcfirst[k] = (int)hchunk.size();
-        for (int c = 0; c < n; c += CHUNK) hchunk.push_back({k, N + c, N + std::min(n, c + CHUNK), 0});
+        for (int c = 0; c < n; c += cs) hchunk.push_back({k, N + c, N + std::min(n, c + cs), 0});
         N += n;
     }
     hcfirst[B] = (int)hchunk.size();
@@ -33,7 +36,7 @@ void Space::build(Alloc *al, const std::vector<Blk> &b, hipStream_t s) {
 }
 
 void Reducer::ensure(Alloc *al, const Space &sp, int cols, hipStream_t s) {
-    const size_t need = (size_t)sp.hchunk.size() * std::max(cols, 1);
+    const size_t need = 2 * (size_t)sp.hchunk.size() * std::max(cols, 1);
     if (part.n < need) part.alloc(al, need);
     if (!counter.p) {
         counter.alloc(al, 1);
@@ -146,263 +149,327 @@ __global__ void k_scale_blk(const Blk *blk, int B, int N, const double *x, const
 }
 
 // ---------------------------------------------------------------- reductions
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-    // wavefront reduce by shuffles, then across the (<= 4) wavefronts
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+// Reductions run in two fixed-order stages with no grid-wide fence: a
+// workgroup per chunk writes up to MAXCOL column partials (butterfly
+// wavefront sums, then the waves in order); the next kernel's workgroups
+// each reduce the partials of their own reservoir in their prologue (chunk q
+// to thread q, butterfly, waves in order), so every workgroup of a reservoir
+// obtains bitwise the same totals, independent of the other reservoirs.  The
+// first chunk of each reservoir commits shared state.
+constexpr int MAXCOL = 32;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// column sums of this workgroup's registers into part_row[0..nc)
+__device__ __forceinline__ void chunk_columns(const double (&acc)[MAXCOL], int nc, double *part_row) {
+    __shared__ double sh[4][MAXCOL];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[w] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-        for (int k = 0; k < nw; ++k) t += sh[k];
-    }
-    return t;   // valid in thread 0
-}
-
-__device__ __forceinline__ double coherent_load(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Returns true in every thread of the last workgroup to arrive.
-__device__ __forceinline__ bool last_block(unsigned *counter, int nblocks) {
-    __shared__ int is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned t = atomicAdd(counter, 1u);
-        is_last = (t == (unsigned)(nblocks - 1));
+#pragma unroll
+    for (int c = 0; c < MAXCOL; ++c) {
+        if (c < nc) {
+            const double v = wave_sum(acc[c]);
+            if (lane == 0) sh[w][c] = v;
+        }
     }
     __syncthreads();
-    if (is_last) __threadfence();
-    return is_last;
-}
-
-// Final per-block sums of `cols` partial columns into out[b*cols + c]; the
-// last workgroup calls this, then resets the counter.
-__device__ void finish_sums(const Chunk *, const int *cfirst, int B, int cols, const double *part,
-                            double *out) {
-    for (int t = threadIdx.x; t < B * cols; t += blockDim.x) {
-        const int b = t / cols, c = t % cols;
-        double s = 0.0;
-        for (int q = cfirst[b]; q < cfirst[b + 1]; ++q) s += coherent_load(&part[(size_t)q * cols + c]);
-        out[t] = s;
+    if ((int)threadIdx.x < nc) {
+        double t = 0.0;
+        const int nw = blockDim.x >> 6;
+        for (int k = 0; k < nw; ++k) t += sh[k][threadIdx.x];
+        part_row[threadIdx.x] = t;
     }
 }
 
-// dots of x with ncols vectors ys[c] per block: out[b*ncols + c]
-__global__ void k_block_dots(const Chunk *chunks, int nch, const int *cfirst, int B,
-                             const double *x, const double *const *ys, int ncols, double *part,
-                             unsigned *counter, double *out, const int *mask, int square) {
-    __shared__ double sh[8];
+// totals of the nc partial columns of reservoir b (chunks [q0, q1), at most
+// blockDim chunks) into out[0..nc) in LDS, visible to the whole workgroup
+__device__ __forceinline__ void block_totals(const double *part, int q0, int q1, int nc, double *out) {
+    __shared__ double sh[4][MAXCOL];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = q0 + (int)threadIdx.x;
+    double v[MAXCOL];
+#pragma unroll
+    for (int c = 0; c < MAXCOL; ++c) v[c] = (c < nc && q < q1) ? part[(size_t)q * nc + c] : 0.0;
+#pragma unroll
+    for (int c = 0; c < MAXCOL; ++c) {
+        if (c < nc) {
+            const double t = wave_sum(v[c]);
+            if (lane == 0) sh[w][c] = t;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+        double t = 0.0;
+        const int nw = blockDim.x >> 6;
+        for (int k = 0; k < nw; ++k) t += sh[k][threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+// partial dots of x with ncols vectors ys[c] (or ||x||^2 when square)
+__global__ void __launch_bounds__(RED_THREADS) k_partials(const Chunk *chunks, const double *x,
+                                                          const double *const *ys, int ncols, double *part,
+                                                          const int *mask, int square) {
     const Chunk ch = chunks[blockIdx.x];
     const bool on = !mask || mask[ch.blk];
-    for (int c = 0; c < ncols; ++c) {
-        double v = 0.0;
-        if (on) {
-            const double *y = square ? x : ys[c];
-            for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) v += x[i] * y[i];
+    double acc[MAXCOL];
+#pragma unroll
+    for (int c = 0; c < MAXCOL; ++c) acc[c] = 0.0;
+    if (on) {
+        for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
+            const double xi = x[i];
+            if (square) {
+                acc[0] += xi * xi;
+            } else {
+#pragma unroll
+                for (int c = 0; c < MAXCOL; ++c)
+                    if (c < ncols) acc[c] += xi * ys[c][i];
+            }
         }
-        v = block_sum(v, sh);
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * ncols + c] = v;
     }
-    if (last_block(counter, nch)) {
-        finish_sums(chunks, cfirst, B, ncols, part, out);
-        __syncthreads();
-        if (threadIdx.x == 0) *counter = 0u;
-    }
+    chunk_columns(acc, ncols, part + (size_t)blockIdx.x * ncols);
+}
+
+// one workgroup per reservoir: out[b*ncols + c]
+__global__ void __launch_bounds__(RED_THREADS) k_totals(const int *cfirst, const double *part, int ncols,
+                                                        double *out) {
+    __shared__ double tot[MAXCOL];
+    const int b = blockIdx.x;
+    block_totals(part, cfirst[b], cfirst[b + 1], ncols, tot);
+    if ((int)threadIdx.x < ncols) out[(size_t)b * ncols + threadIdx.x] = tot[threadIdx.x];
 }
 
 void launch_block_dots(const Space &sp, Reducer &R, const double *x, const double *const *ys,
                        int ncols, double *out, const int *mask, hipStream_t s) {
-    k_block_dots<<<(int)sp.hchunk.size(), RED_THREADS, 0, s>>>(
-        sp.chunk.p, (int)sp.hchunk.size(), sp.cfirst.p, sp.B, x, ys, ncols, R.part.p,
-        R.counter.p, out, mask, 0);
+    if (ncols > MAXCOL) fail(NKS_EINVAL, "at most %d columns per reduction", MAXCOL);
+    k_partials<<<(int)sp.hchunk.size(), RED_THREADS, 0, s>>>(sp.chunk.p, x, ys, ncols, R.part.p, mask, 0);
+    KCHECK();
+    k_totals<<<sp.B, RED_THREADS, 0, s>>>(sp.cfirst.p, R.part.p, ncols, out);
     KCHECK();
 }
 
 void launch_block_norm2(const Space &sp, Reducer &R, const double *x, double *out, const int *mask,
                         hipStream_t s) {
-    k_block_dots<<<(int)sp.hchunk.size(), RED_THREADS, 0, s>>>(
-        sp.chunk.p, (int)sp.hchunk.size(), sp.cfirst.p, sp.B, x, nullptr, 1, R.part.p,
-        R.counter.p, out, mask, 1);
+    k_partials<<<(int)sp.hchunk.size(), RED_THREADS, 0, s>>>(sp.chunk.p, x, nullptr, 1, R.part.p, mask, 1);
+    KCHECK();
+    k_totals<<<sp.B, RED_THREADS, 0, s>>>(sp.cfirst.p, R.part.p, 1, out);
     KCHECK();
 }
 
 // ---------------------------------------------------------------- GMRES kernels
-
-// ||r||^2 per block -> epilogue decides who iterates in the new cycle.
-// set_tol: r == b (x0 = 0) so the same norm also sets tol = max(rtol||b||, atol).
-__global__ void k_gm_start(const Chunk *chunks, int nch, const int *cfirst, int B, const double *r,
-                           double *part, unsigned *counter, GmDev st, const int *outer,
-                           int set_tol, int first) {
-    __shared__ double sh[8];
+// Start of a cycle: beta = ||r|| per reservoir (from the norm partials), who
+// iterates, and v_0 = r / beta.  set_tol: r == b (x0 = 0), so tol =
+// max(rtol ||b||, atol) comes from the same norm.
+__global__ void __launch_bounds__(RED_THREADS) k_gm_begin(const Chunk *chunks, const int *cfirst,
+                                                          const double *part, const double *r, double *v0,
+                                                          GmDev st, const int *outer, int set_tol, int first) {
+    __shared__ double tot[MAXCOL];
     const Chunk ch = chunks[blockIdx.x];
-    double v = 0.0;
-    for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) v += r[i] * r[i];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = v;
-    if (last_block(counter, nch)) {
-        for (int b = threadIdx.x; b < B; b += blockDim.x) {
-            double s = 0.0;
-            for (int q = cfirst[b]; q < cfirst[b + 1]; ++q) s += coherent_load(&part[q]);
-            const double beta = sqrt(s);
-            if (first) {
-                st.its[b] = 0;
-                st.conv[b] = (outer && !outer[b]) ? 1 : 0;
-            }
-            if (set_tol) st.tol[b] = fmax(st.rtol * beta, st.atol);
-            st.beta[b] = beta;
-            st.res[b] = beta;
-            st.kdim[b] = 0;
-            for (int k = 0; k <= st.m; ++k) st.g[(size_t)b * (st.m + 1) + k] = 0.0;
-            st.g[(size_t)b * (st.m + 1)] = beta;
-            int act = 0;
-            if (!st.conv[b]) {
-                if (beta <= st.tol[b]) st.conv[b] = 1;
-                else if (st.its[b] < st.maxit) act = 1;
-            }
-            st.active[b] = act;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) *counter = 0u;
+    const int b = ch.blk;
+    const int q0 = cfirst[b];
+    block_totals(part, q0, cfirst[b + 1], 1, tot);
+    const double beta = sqrt(tot[0]);
+    const bool lead = (int)blockIdx.x == q0;
+    const int its = first ? 0 : st.its[b];
+    const int conv0 = first ? ((outer && !outer[b]) ? 1 : 0) : st.conv[b];
+    const double tol = set_tol ? fmax(st.rtol * beta, st.atol) : st.tol[b];
+    int conv = conv0, act = 0;
+    if (!conv) {
+        if (beta <= tol) conv = 1;
+        else if (its < st.maxit) act = 1;
+    }
+    if (act)
+        for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) v0[i] = r[i] / beta;
+    if (lead && threadIdx.x == 0) {
+        st.its[b] = its;
+        st.conv[b] = conv;
+        st.tol[b] = tol;
+        st.beta[b] = beta;
+        st.res[b] = beta;
+        st.kdim[b] = 0;
+        for (int k = 0; k <= st.m; ++k) st.g[(size_t)b * (st.m + 1) + k] = 0.0;
+        st.g[(size_t)b * (st.m + 1)] = beta;
+        st.active[b] = act;
+        st.flag[3 * st.nb + b] = act;
     }
 }
 
-// tol from ||b|| (when x0 != 0)
-__global__ void k_gm_tol(const Chunk *chunks, int nch, const int *cfirst, int B, const double *bv,
-                         double *part, unsigned *counter, GmDev st) {
-    __shared__ double sh[8];
+__global__ void __launch_bounds__(RED_THREADS) k_gm_norm_partials(const Chunk *chunks, const double *r,
+                                                                  double *part) {
     const Chunk ch = chunks[blockIdx.x];
-    double v = 0.0;
-    for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) v += bv[i] * bv[i];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = v;
-    if (last_block(counter, nch)) {
-        for (int b = threadIdx.x; b < B; b += blockDim.x) {
-            double s = 0.0;
-            for (int q = cfirst[b]; q < cfirst[b + 1]; ++q) s += coherent_load(&part[q]);
-            st.tol[b] = fmax(st.rtol * sqrt(s), st.atol);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) *counter = 0u;
-    }
+    double acc[MAXCOL];
+    acc[0] = 0.0;
+    for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) acc[0] += r[i] * r[i];
+    chunk_columns(acc, 1, part + blockIdx.x);
 }
 
-// Pass of classical Gram-Schmidt on column j: h = V[0..j]^T w (per block),
-// accumulated into H[:, j] (first pass overwrites).
-__global__ void k_gm_dots(const Chunk *chunks, int nch, const int *cfirst, int B, const double *w,
-                          const double *const *V, int j, double *part, unsigned *counter, GmDev st,
-                          int first_pass) {
-    __shared__ double sh[8];
+// tol from ||b|| (x0 != 0), lead chunk of each reservoir
+__global__ void __launch_bounds__(RED_THREADS) k_gm_tol(const Chunk *chunks, const int *cfirst, const double *part,
+                                                        GmDev st) {
+    __shared__ double tot[MAXCOL];
     const Chunk ch = chunks[blockIdx.x];
-    const bool on = st.active[ch.blk];
+    const int q0 = cfirst[ch.blk];
+    if ((int)blockIdx.x != q0) return;
+    block_totals(part, q0, cfirst[ch.blk + 1], 1, tot);
+    if (threadIdx.x == 0) st.tol[ch.blk] = fmax(st.rtol * sqrt(tot[0]), st.atol);
+}
+
+// CGS pass 1 partials: V[0..j]^T w
+__global__ void __launch_bounds__(RED_THREADS) k_gm_dots(const Chunk *chunks, const double *w,
+                                                         const double *const *V, int j, double *part, GmDev st) {
+    const Chunk ch = chunks[blockIdx.x];
     const int nc = j + 1;
-    for (int c = 0; c < nc; ++c) {
-        double v = 0.0;
-        if (on) {
-            const double *vc = V[c];
-            for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) v += w[i] * vc[i];
+    double acc[MAXCOL];
+#pragma unroll
+    for (int c = 0; c < MAXCOL; ++c) acc[c] = 0.0;
+    if (st.active[ch.blk]) {
+        for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
+            const double wi = w[i];
+#pragma unroll
+            for (int c = 0; c < MAXCOL; ++c)
+                if (c < nc) acc[c] += wi * V[c][i];
         }
-        v = block_sum(v, sh);
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * nc + c] = v;
     }
-    if (last_block(counter, nch)) {
-        for (int t = threadIdx.x; t < B * nc; t += blockDim.x) {
-            const int b = t / nc, c = t % nc;
-            if (!st.active[b]) continue;
-            double s = 0.0;
-            for (int q = cfirst[b]; q < cfirst[b + 1]; ++q) s += coherent_load(&part[(size_t)q * nc + c]);
-            st.hj[(size_t)b * (st.m + 1) + c] = s;
-            double &h = st.H[((size_t)b * (st.m + 1) + c) * st.m + j];
-            h = first_pass ? s : h + s;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) *counter = 0u;
-    }
+    chunk_columns(acc, nc, part + (size_t)blockIdx.x * nc);
 }
 
-// w -= sum_c hj[c] V[c]; on the last pass also ||w||^2, then the Givens step.
-__global__ void k_gm_update(const Chunk *chunks, int nch, const int *cfirst, int B, double *w,
-                            const double *const *V, int j, double *part, unsigned *counter,
-                            GmDev st, int last_pass) {
-    __shared__ double sh[8];
-    __shared__ double hc[32];
+// h1 = totals of pass 1 (lead chunk stores H[:, j] = h1); w -= V h1; pass 2 partials V^T w
+__global__ void __launch_bounds__(RED_THREADS) k_gm_update_dots(const Chunk *chunks, const int *cfirst, double *w,
+                                                                const double *const *V, int j,
+                                                                const double *pin, double *pout, GmDev st) {
+    __shared__ double hc[MAXCOL];
     const Chunk ch = chunks[blockIdx.x];
-    const bool on = st.active[ch.blk];
-    const int nc = j + 1;
-    if (threadIdx.x < nc && on) hc[threadIdx.x] = st.hj[(size_t)ch.blk * (st.m + 1) + threadIdx.x];
-    __syncthreads();
-    double v = 0.0;
+    const int b = ch.blk, nc = j + 1;
+    const bool on = st.active[b];
+    if (on) block_totals(pin, cfirst[b], cfirst[b + 1], nc, hc);
+    if (on && (int)blockIdx.x == cfirst[b] && (int)threadIdx.x < nc)
+        st.H[((size_t)b * (st.m + 1) + threadIdx.x) * st.m + j] = hc[threadIdx.x];
+    double acc[MAXCOL];
+#pragma unroll
+    for (int c = 0; c < MAXCOL; ++c) acc[c] = 0.0;
+    if (on) {
+        for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
+            double vv[MAXCOL];
+            double t = w[i];
+#pragma unroll
+            for (int c = 0; c < MAXCOL; ++c)
+                if (c < nc) {
+                    vv[c] = V[c][i];
+                    t -= hc[c] * vv[c];
+                }
+            w[i] = t;
+#pragma unroll
+            for (int c = 0; c < MAXCOL; ++c)
+                if (c < nc) acc[c] += t * vv[c];
+        }
+    }
+    chunk_columns(acc, nc, pout + (size_t)blockIdx.x * nc);
+}
+
+// h2 = totals of pass 2 (lead chunk adds to H[:, j]); w -= V h2; ||w||^2 partials
+__global__ void __launch_bounds__(RED_THREADS) k_gm_update_norm(const Chunk *chunks, const int *cfirst, double *w,
+                                                                const double *const *V, int j,
+                                                                const double *pin, double *pout, GmDev st) {
+    __shared__ double hc[MAXCOL];
+    const Chunk ch = chunks[blockIdx.x];
+    const int b = ch.blk, nc = j + 1;
+    const bool on = st.active[b];
+    if (on) block_totals(pin, cfirst[b], cfirst[b + 1], nc, hc);
+    if (on && (int)blockIdx.x == cfirst[b] && (int)threadIdx.x < nc)
+        st.H[((size_t)b * (st.m + 1) + threadIdx.x) * st.m + j] += hc[threadIdx.x];
+    double acc[MAXCOL];
+    acc[0] = 0.0;
     if (on) {
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
             double t = w[i];
-            for (int c = 0; c < nc; ++c) t -= hc[c] * V[c][i];
+#pragma unroll
+            for (int c = 0; c < MAXCOL; ++c)
+                if (c < nc) t -= hc[c] * V[c][i];
             w[i] = t;
-            v += t * t;
+            acc[0] += t * t;
         }
     }
-    if (!last_pass) return;
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = v;
-    if (last_block(counter, nch)) {
-        for (int b = threadIdx.x; b < B; b += blockDim.x) {
-            if (!st.active[b]) continue;
-            double s = 0.0;
-            for (int q = cfirst[b]; q < cfirst[b + 1]; ++q) s += coherent_load(&part[q]);
-            const double hn = sqrt(s);
-            const int m = st.m;
-            double *H = st.H + (size_t)b * (m + 1) * m;
-            double *cs = st.cs + (size_t)b * m, *sn = st.sn + (size_t)b * m;
-            double *g = st.g + (size_t)b * (m + 1);
-            H[(j + 1) * m + j] = hn;
-            for (int k = 0; k < j; ++k) {
-                const double a0 = H[k * m + j], a1 = H[(k + 1) * m + j];
-                H[k * m + j] = cs[k] * a0 + sn[k] * a1;
-                H[(k + 1) * m + j] = -sn[k] * a0 + cs[k] * a1;
-            }
-            const double a0 = H[j * m + j], a1 = hn;
-            const double den = sqrt(a0 * a0 + a1 * a1);
-            cs[j] = den > 0.0 ? a0 / den : 1.0;
-            sn[j] = den > 0.0 ? a1 / den : 0.0;
-            H[j * m + j] = den;
-            H[(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            st.its[b] += 1;
-            st.kdim[b] = j + 1;
-            st.hj[(size_t)b * (m + 1) + m] = hn;   // for the normalisation of v_{j+1}
-            const double res = fabs(g[j + 1]);
-            st.res[b] = res;
-            if (res <= st.tol[b] || hn == 0.0) {
-                st.conv[b] = 1;
-                st.active[b] = 0;
-            } else if (st.its[b] >= st.maxit || j + 1 == m) {
-                st.active[b] = 0;   // restart (or stop at maxit)
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) *counter = 0u;
-    }
+    chunk_columns(acc, 1, pout + blockIdx.x);
 }
 
-// v_{j+1} = w / h_{j+1,j} for blocks still iterating
+// h_{j+1,j} = ||w|| from the partials and the Givens step of column j: one
+// workgroup per reservoir, thread 0 updates the shared state (single writer).
+__global__ void __launch_bounds__(RED_THREADS) k_gm_givens(const int *cfirst, int j, int slot, const double *pin,
+                                                           GmDev st) {
+    __shared__ double tot[MAXCOL];
+    const int b = blockIdx.x;
+    if (!st.active[b]) {
+        if (threadIdx.x == 0) st.flag[slot * st.nb + b] = 0;
+        return;
+    }
+    block_totals(pin, cfirst[b], cfirst[b + 1], 1, tot);
+    if (threadIdx.x != 0) return;
+    const double hn = sqrt(tot[0]);
+    const int m = st.m;
+    double *H = st.H + (size_t)b * (m + 1) * m;
+    double *cs = st.cs + (size_t)b * m, *sn = st.sn + (size_t)b * m;
+    double *g = st.g + (size_t)b * (m + 1);
+    // column j and the previous rotations in registers (independent loads)
+    double hc[MAXCOL + 1], cc[MAXCOL], ss[MAXCOL];
+#pragma unroll
+    for (int k = 0; k < MAXCOL; ++k) {
+        hc[k] = k <= j ? H[k * m + j] : 0.0;
+        cc[k] = k < j ? cs[k] : 1.0;
+        ss[k] = k < j ? sn[k] : 0.0;
+    }
+    hc[MAXCOL] = 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXCOL - 1; ++k) {
+        if (k < j) {
+            const double a0 = hc[k], a1 = hc[k + 1];
+            hc[k] = cc[k] * a0 + ss[k] * a1;
+            hc[k + 1] = -ss[k] * a0 + cc[k] * a1;
+        }
+    }
+    double a0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXCOL; ++k)
+        if (k == j) a0 = hc[k];
+    const double den = sqrt(a0 * a0 + hn * hn);
+    const double c = den > 0.0 ? a0 / den : 1.0;
+    const double sg = den > 0.0 ? hn / den : 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXCOL; ++k)
+        if (k < j) H[k * m + j] = hc[k];
+    H[j * m + j] = den;
+    H[(j + 1) * m + j] = 0.0;
+    cs[j] = c;
+    sn[j] = sg;
+    const double gj = g[j];
+    g[j + 1] = -sg * gj;
+    g[j] = c * gj;
+    st.its[b] += 1;
+    st.kdim[b] = j + 1;
+    st.hj[(size_t)b * (m + 1) + m] = hn;   // normalisation of v_{j+1}
+    const double res = fabs(g[j + 1]);
+    st.res[b] = res;
+    int act = 1;
+    if (res <= st.tol[b] || hn == 0.0) {
+        st.conv[b] = 1;
+        act = 0;
+    } else if (st.its[b] >= st.maxit || j + 1 == m) {
+        act = 0;   // restart (or stop at maxit)
+    }
+    st.active[b] = act;
+    st.flag[slot * st.nb + b] = act;
+}
+
+// v_{j+1} = w / h_{j+1,j} for reservoirs still iterating
 __global__ void k_gm_next(const Blk *blk, int B, int N, const double *w, double *vn, GmDev st) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int b = find_blk(blk, B, i);
     if (!st.active[b]) return;
     vn[i] = w[i] / st.hj[(size_t)b * (st.m + 1) + st.m];
-}
-
-// v_0 = r / beta for blocks iterating in this cycle
-__global__ void k_gm_v0(const Blk *blk, int B, int N, const double *r, double *v0, GmDev st) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int b = find_blk(blk, B, i);
-    if (!st.active[b]) return;
-    v0[i] = r[i] / st.beta[b];
 }
 
 // back substitution H y = g over the kdim leading columns of each block
@@ -441,6 +508,7 @@ void Gmres::ensure(Alloc *al_, const Space &sp_, int m_, bool flexible, hipStrea
     sp = &sp_;
     const int B = sp_.B, N = sp_.N;
     if (m_ != m || B != nb || N != nn || (flexible && Z.empty())) {
+        invalidate_graphs();
         m = m_;
         nb = B;
         nn = N;
@@ -472,11 +540,26 @@ void Gmres::ensure(Alloc *al_, const Space &sp_, int m_, bool flexible, hipStrea
         if (hint) HIPC(hipHostFree(hint));
         HIPC(hipHostMalloc((void **)&hint, sizeof(int) * 2 * B + sizeof(double) * 2 * B));
     }
-    red.ensure(al, sp_, m + 1, s);
+    if (!hflag || flag_b < B) {
+        if (hflag) HIPC(hipHostFree((void *)hflag));
+        int *h = nullptr;
+        HIPC(hipHostMalloc((void **)&h, 4 * sizeof(int) * B, hipHostMallocMapped));
+        HIPC(hipHostGetDevicePointer((void **)&dflag, h, 0));
+        for (int k = 0; k < 4 * B; ++k) h[k] = 0;
+        hflag = h;
+        flag_b = B;
+        if (!ev[0])
+            for (auto &e : ev) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    red.ensure(al, sp_, MAXCOL, s);
 }
 
 Gmres::~Gmres() {
+    invalidate_graphs();
     if (hint) (void)hipHostFree(hint);
+    if (hflag) (void)hipHostFree((void *)hflag);
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
 }
 
 GmDev Gmres::dev(double rtol, double atol, int maxit) {
@@ -486,6 +569,8 @@ GmDev Gmres::dev(double rtol, double atol, int maxit) {
     d.tol = scal.p; d.beta = scal.p + B; d.res = scal.p + 2 * B;
     d.active = ints.p; d.conv = ints.p + B; d.kdim = ints.p + 2 * B; d.its = ints.p + 3 * B;
     d.upd = ints.p + 4 * B;
+    d.flag = dflag;
+    d.nb = nb;
     d.m = m;
     d.maxit = maxit;
     d.rtol = rtol;
@@ -506,40 +591,88 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
     const int nch = (int)S.hchunk.size();
     GmDev st = dev(o.rtol, o.atol, o.maxit);
     const int NB = nblk(S.N, 256);
-    // r = b - A x (or b), tol, norms
+    double *P0 = red.part.p, *P1 = red.part.p + (size_t)nch * MAXCOL;
+    auto any_flag = [&](int slot) -> bool {
+        HIPC(hipEventSynchronize(ev[slot]));
+        for (int k = 0; k < nb; ++k)
+            if (hflag[slot * nb + k]) return true;
+        return false;
+    };
     const double *r0 = b;
     if (!x_zero) {
-        k_gm_tol<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, nch, S.cfirst.p, S.B, b, red.part.p,
-                                              red.counter.p, st);
+        k_gm_norm_partials<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, b, P0);
+        KCHECK();
+        k_gm_tol<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, P0, st);
         KCHECK();
         A(x, r.p, b, outer_mask);
         r0 = r.p;
     }
-    k_gm_start<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, nch, S.cfirst.p, S.B, r0, red.part.p,
-                                            red.counter.p, st, outer_mask, x_zero ? 1 : 0, 1);
+    k_gm_norm_partials<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, r0, P0);
     KCHECK();
+    k_gm_begin<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, P0, r0, V[0].p, st, outer_mask,
+                                            x_zero ? 1 : 0, 1);
+    KCHECK();
+    HIPC(hipEventRecord(ev[3], s));
     const double *const *Vp = vptr.p;
     const bool flex = o.flexible;
-    int cycles = 0;
-    while (any_active(s)) {
-        k_gm_v0<<<NB, 256, 0, s>>>(S.blk.p, S.B, S.N, r0, V[0].p, st);
-        KCHECK();
-        for (int j = 0; j < m; ++j) {
-            double *zj = flex ? Z[j].p : t.p;
-            M(V[j].p, zj, st.active);
-            A(zj, w.p, nullptr, st.active);
+    // one GMRES iteration j; its activity flags go to `slot`
+    auto iteration = [&](int j, int slot) {
+        double *zj = flex ? Z[j].p : t.p;
+        M(V[j].p, zj, st.active);
+        A(zj, w.p, nullptr, st.active);
+        {
             ProfScope ps("gmres_orth", s);
-            for (int pass = 0; pass < 2; ++pass) {
-                k_gm_dots<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, nch, S.cfirst.p, S.B, w.p, Vp, j,
-                                                      red.part.p, red.counter.p, st, pass == 0);
-                KCHECK();
-                k_gm_update<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, nch, S.cfirst.p, S.B, w.p, Vp,
-                                                        j, red.part.p, red.counter.p, st, pass == 1);
-                KCHECK();
-            }
-            k_gm_next<<<NB, 256, 0, s>>>(S.blk.p, S.B, S.N, w.p, V[j + 1].p, st);
+            k_gm_dots<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, w.p, Vp, j, P0, st);
             KCHECK();
-            if (j + 1 < m && ((j + 1) % o.check_every == 0) && !any_active(s)) break;
+            k_gm_update_dots<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, Vp, j, P0, P1, st);
+            KCHECK();
+            k_gm_update_norm<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, Vp, j, P1, P0, st);
+            KCHECK();
+        }
+        k_gm_givens<<<S.B, RED_THREADS, 0, s>>>(S.cfirst.p, j, slot, P0, st);
+        KCHECK();
+        k_gm_next<<<NB, 256, 0, s>>>(S.blk.p, S.B, S.N, w.p, V[j + 1].p, st);
+        KCHECK();
+    };
+    const int kc = (o.graph_chunk > 0 && graphs_ok && s != nullptr) ? std::min(o.graph_chunk, m) : 0;
+    if (kc && kc != gchunk) invalidate_graphs();
+    gchunk = kc;
+    const int nchunk = kc ? (m + kc - 1) / kc : m;
+    if (kc && (int)gexec.size() < nchunk) gexec.resize(nchunk, nullptr);
+    auto launch_chunk = [&](int c) {
+        const int j0 = kc ? c * kc : c, j1 = kc ? std::min(m, j0 + kc) : c + 1;
+        if (!kc) {
+            iteration(j0, c % 3);
+            return;
+        }
+        if (!gexec[c]) {
+            hipGraph_t gr = nullptr;
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+                (void)hipGetLastError();
+                graphs_ok = false;   // e.g. the legacy default stream: plain launches from now on
+                for (int j = j0; j < j1; ++j) iteration(j, c % 3);
+                return;
+            }
+            try {
+                for (int j = j0; j < j1; ++j) iteration(j, c % 3);
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &gr);
+                if (gr) (void)hipGraphDestroy(gr);
+                throw;
+            }
+            HIPC(hipStreamEndCapture(s, &gr));
+            HIPC(hipGraphInstantiate(&gexec[c], gr, nullptr, nullptr, 0));
+            HIPC(hipGraphDestroy(gr));
+        }
+        HIPC(hipGraphLaunch(gexec[c], s));
+    };
+    while (any_flag(3)) {
+        for (int c = 0; c < nchunk; ++c) {
+            launch_chunk(c);
+            HIPC(hipEventRecord(ev[c % 3], s));
+            // look-ahead: stop once an earlier chunk left no reservoir active
+            const int back = kc ? 1 : 2;
+            if (c >= back && !any_flag((c - back) % 3)) break;
         }
         k_gm_solve_y<<<nblk(S.B, 64), 64, 0, s>>>(S.B, st);
         KCHECK();
@@ -550,16 +683,22 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
             k_gm_combine<<<NB, 256, 0, s>>>(S.blk.p, S.B, S.N, Vp, w.p, st, 0);
             KCHECK();
             M(w.p, t.p, st.upd);
-            // x += t on updated blocks
-            launch_axpby(S, 1.0, t.p, 1.0, x, st.upd, s);
+            launch_axpby(S, 1.0, t.p, 1.0, x, st.upd, s);   // x += M^{-1} V y
         }
-        ++cycles;
         A(x, r.p, b, nullptr);
         r0 = r.p;
-        k_gm_start<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, nch, S.cfirst.p, S.B, r0, red.part.p,
-                                                red.counter.p, st, outer_mask, 0, 0);
+        k_gm_norm_partials<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, r0, P0);
         KCHECK();
+        k_gm_begin<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, P0, r0, V[0].p, st, outer_mask, 0, 0);
+        KCHECK();
+        HIPC(hipEventRecord(ev[3], s));
     }
+}
+
+void Gmres::invalidate_graphs() {
+    for (auto &g : gexec)
+        if (g) (void)hipGraphExecDestroy(g);
+    gexec.clear();
 }
 
 void Gmres::stats(std::vector<int> &its, std::vector<double> &res, std::vector<int> &conv,

@@ -82,7 +82,8 @@ struct Chunk {
     int blk, start, end, pad;
 };
 
-constexpr int CHUNK = 1024;      // cells per reduction chunk
+constexpr int CHUNK = 256;       // minimum cells per reduction chunk
+constexpr int MAXCH = 256;       // at most this many chunks per reservoir (one per reduction thread)
 constexpr int RED_THREADS = 256;
 constexpr int MAXB = 4096;       // reservoirs per grid
 
@@ -174,6 +175,9 @@ void launch_block_norm2(const Space &sp, Reducer &R, const double *x, double *ou
                         const int *mask, hipStream_t s);
 
 std::string fmt(const char *f, ...);
+
+// Raise a kernel's dynamic LDS limit once per (kernel, size) instead of per launch.
+void set_lds(const void *fn, size_t bytes);
 
 // Event timing of named launches (active only after nks_profile_enable(1)).
 bool prof_on();

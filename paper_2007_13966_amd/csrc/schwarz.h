@@ -52,6 +52,7 @@ struct Level {
     int max_tile = 0;            // largest padded tile (cells)
     int max_next = 0;
     int max_lvl = 0;             // largest hyperplane (cells)
+    int max_nlev = 0;            // most hyperplanes of a subdomain
     std::vector<SubDev> hsub;
     DBuf<SubDev> sub;
     std::vector<BlkPart> hpart;
@@ -61,9 +62,16 @@ struct Level {
     DBuf<int> inv;               // per padded-tile cell: level-order index or -1
     DBuf<int> lexi;              // per extended cell (level order): lexicographic ext index
     // ILU(0) factors: K coefficient arrays over the extended cells (level order)
-    DBuf<double> w64;            // FP64 factorisation workspace (factor storage in FP64 mode)
+    DBuf<double> w64;            // FP64 factorisation workspace (hyperplane order)
+    DBuf<double> f64;            // FP64 factors (FP64 mode)
     DBuf<float> f32;             // FP32 factors (FP32 mode)
     DBuf<uint16_t> f16;          // BF16 factors (BF16 mode)
+    DBuf<int> lexg;              // per extended cell (hyperplane order): lexicographic storage slot
+    // 2D levels use the register-wavefront sweep: factors stored in
+    // lexicographic order, stencil mapped onto a 5-point cross or 5x5 box
+    bool rows2d = false;
+    int box = 0;
+    DBuf<int> slotmap;           // box slot -> stencil index (-1: absent)
     DBuf<double> invd64;         // 1/u_ii
     DBuf<float> invd32;
     DBuf<double> zext;           // per extended cell solution (AS / right-RAS gather)
@@ -93,6 +101,7 @@ struct Ras {
     std::vector<TileDims> tiles_;
     Gmres coarse;
     int lds_bytes = 65536;
+    int graph_chunk = 4;         // coarse GMRES iterations per captured graph (0: plain launches)
     int coarse_its_last = 0;
     long coarse_its_total = 0;
     long coarse_calls = 0;

@@ -136,10 +136,11 @@ static void build_partition(Level &L, const nks_ras_desc &d, int delta, Alloc *a
     const int tile = geo.PX * geo.PY * geo.PZ;
     L.max_tile = tile;
     // second pass: hyperplane order, maps
-    std::vector<int> lvlptr, loc, inv, lexi;
+    std::vector<int> lvlptr, loc, inv, lexi, lexg;
     int fac = 0;
     L.max_next = 0;
     L.max_lvl = 0;
+    L.max_nlev = 0;
     for (auto &sd : L.hsub) {
         sd.fac_off = fac;
         sd.lvl_off = (int)lvlptr.size();
@@ -152,6 +153,7 @@ static void build_partition(Level &L, const nks_ras_desc &d, int delta, Alloc *a
         for (int t = 0; t < sd.nlev; ++t) cnt[t + 1] += cnt[t];
         for (int t = 0; t <= sd.nlev; ++t) lvlptr.push_back(cnt[t]);
         for (int t = 0; t < sd.nlev; ++t) L.max_lvl = std::max(L.max_lvl, cnt[t + 1] - cnt[t]);
+        L.max_nlev = std::max(L.max_nlev, sd.nlev);
         std::vector<int> pos(cnt.begin(), cnt.end() - 1);
         std::vector<int> sloc(sd.next), slexi(sd.next);
         std::vector<int> sinv(tile, -1);
@@ -167,6 +169,7 @@ static void build_partition(Level &L, const nks_ras_desc &d, int delta, Alloc *a
                 }
         loc.insert(loc.end(), sloc.begin(), sloc.end());
         lexi.insert(lexi.end(), slexi.begin(), slexi.end());
+        for (int e = 0; e < sd.next; ++e) lexg.push_back(sd.fac_off + slexi[e]);
         inv.insert(inv.end(), sinv.begin(), sinv.end());
         fac += sd.next;
         L.max_next = std::max(L.max_next, sd.next);
@@ -181,6 +184,21 @@ static void build_partition(Level &L, const nks_ras_desc &d, int delta, Alloc *a
     L.loc.upload(al, loc, s);
     L.inv.upload(al, inv, s);
     L.lexi.upload(al, lexi, s);
+    L.lexg.upload(al, lexg, s);
+    // 2D register-wavefront eligibility: rows fit one wavefront, reach <= 2
+    L.rows2d = false;
+    if (Rz == 0 && mey <= 64 && R <= 2) {
+        std::vector<int> slot(25, -1);
+        bool cross = st.K == 5;
+        for (int k = 0; k < st.K; ++k) {
+            const int dx = st.off[3 * k], dy = st.off[3 * k + 1];
+            slot[(dx + 2) + 5 * (dy + 2)] = k;
+            if (std::abs(dx) + std::abs(dy) > 1) cross = false;
+        }
+        L.box = cross ? 0 : 1;
+        L.slotmap.upload(al, slot, s);
+        L.rows2d = true;
+    }
     // stencil tables
     std::vector<int> lin(st.K);
     for (int k = 0; k < st.K; ++k)
@@ -385,7 +403,9 @@ __global__ void k_ilu_factor(FacArgs a) {
     extern __shared__ double smem_f[];
     const SubDev sd = a.sub[blockIdx.x];
     double *row = smem_f + (size_t)threadIdx.x * a.K;
-    const int *lp = a.lvlptr + sd.lvl_off;
+    int *lp = reinterpret_cast<int *>(smem_f + (size_t)blockDim.x * a.K);
+    for (int t = threadIdx.x; t <= sd.nlev; t += blockDim.x) lp[t] = a.lvlptr[sd.lvl_off + t];
+    __syncthreads();
     for (int t = 0; t < sd.nlev; ++t) {
         const int p0 = lp[t], p1 = lp[t + 1];
         for (int el = p0 + threadIdx.x; el < p1; el += blockDim.x) {
@@ -411,16 +431,58 @@ __global__ void k_ilu_factor(FacArgs a) {
 
 // storage precision: off-diagonals in FT, 1/u_ii in DT
 template <typename FT, typename DT>
-__global__ void k_ilu_store(const double *w, int NE, int K, int diag, FT *f, DT *invd) {
+__global__ void k_ilu_store(const double *w, int NE, int K, int diag, FT *f, DT *invd, const int *perm) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (size_t)NE) return;
+    const size_t d = perm ? (size_t)perm[e] : e;
     for (int k = 0; k < K; ++k) {
         const double v = w[(size_t)k * NE + e];
         if (k == diag) {
-            invd[e] = (DT)(1.0 / v);
-        } else if (f) {
-            if constexpr (sizeof(FT) == 2) f[(size_t)k * NE + e] = to_bf16((float)v);
-            else f[(size_t)k * NE + e] = (FT)v;
+            invd[d] = (DT)(1.0 / v);
+        } else {
+            if constexpr (sizeof(FT) == 2) f[(size_t)k * NE + d] = to_bf16((float)v);
+            else f[(size_t)k * NE + d] = (FT)v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- staging helpers
+constexpr int STAGE_U = 16;   // independent loads in flight per thread while staging
+
+// dst[i] = src[i] for i < n, by the whole workgroup, STAGE_U loads in flight
+template <typename T, typename S>
+__device__ __forceinline__ void stage_copy(T *dst, const S *src, int n) {
+    const int bs = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < n; i0 += STAGE_U * bs) {
+        S v[STAGE_U];
+#pragma unroll
+        for (int u = 0; u < STAGE_U; ++u) {
+            const int i = i0 + u * bs;
+            if (i < n) v[u] = src[i];
+        }
+#pragma unroll
+        for (int u = 0; u < STAGE_U; ++u) {
+            const int i = i0 + u * bs;
+            if (i < n) dst[i] = (T)v[u];
+        }
+    }
+}
+
+// K segments of n elements: dst[k*dstride + j] = src[k*sstride + j]
+template <typename T, typename S>
+__device__ __forceinline__ void stage_copy_k(T *dst, int dstride, const S *src, size_t sstride, int K, int n) {
+    const int bs = blockDim.x, tot = K * n;
+    for (int i0 = threadIdx.x; i0 < tot; i0 += STAGE_U * bs) {
+        S v[STAGE_U];
+#pragma unroll
+        for (int u = 0; u < STAGE_U; ++u) {
+            const int i = i0 + u * bs;
+            if (i < tot) v[u] = src[(size_t)(i / n) * sstride + (i % n)];
+        }
+#pragma unroll
+        for (int u = 0; u < STAGE_U; ++u) {
+            const int i = i0 + u * bs;
+            if (i < tot) dst[(i / n) * dstride + (i % n)] = (T)v[u];
         }
     }
 }
@@ -429,14 +491,15 @@ __global__ void k_ilu_store(const double *w, int NE, int K, int diag, FT *f, DT 
 // LDS layout of the apply kernel: solution tile, stencil offsets, staged
 // coefficients, staged 1/u_ii, staged tile positions (16-byte aligned parts).
 struct ApplyLds {
-    size_t lin, cf, cd, cl, total;
+    size_t lin, lp, cf, cd, cl, total;
 };
 __host__ __device__ __forceinline__ size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
 __host__ __device__ __forceinline__ ApplyLds apply_lds(size_t vt, size_t ft, size_t dt, int tile, int ncmax,
-                                                       int cap) {
+                                                       int cap, int maxlev) {
     ApplyLds L;
     L.lin = al16(vt * (size_t)tile);
-    L.cf = al16(L.lin + sizeof(int) * MAXK);
+    L.lp = al16(L.lin + sizeof(int) * MAXK);
+    L.cf = al16(L.lp + sizeof(int) * (size_t)(maxlev + 1));
     L.cd = al16(L.cf + ft * (size_t)ncmax * cap);
     L.cl = al16(L.cd + dt * (size_t)cap);
     L.total = al16(L.cl + sizeof(int) * (size_t)cap);
@@ -447,6 +510,7 @@ struct ApplyArgs {
     const SubDev *sub;
     const Blk *blk;
     const int *lvlptr, *loc, *lexi, *lin;
+    int maxlev;           // most hyperplanes of any subdomain
     const void *F;        // K*NE off-diagonal factors (FT)
     const void *invd;     // NE (DT)
     int NE, K, diag, PX, PY, PZ, R, Rz, tile;
@@ -460,34 +524,50 @@ struct ApplyArgs {
 // sweep with the unit lower factor, backward sweep with the upper factor,
 // then write the owned cells (left-RAS) or the whole box (AS / right-RAS).
 template <typename FT, typename VT, typename DT>
-__global__ void k_ras_apply(ApplyArgs a) {
+__global__ void __launch_bounds__(256) k_ras_apply(ApplyArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const SubDev sd = a.sub[blockIdx.x];
     if (a.mask && !a.mask[sd.blk]) return;
     const Blk bk = a.blk[sd.blk];
     const int ncl = a.diag, ncu = a.K - a.diag - 1;
     const int ncmax = ncl > ncu ? ncl : ncu;
-    const ApplyLds lay = apply_lds(sizeof(VT), sizeof(FT), sizeof(DT), a.tile, ncmax, a.cap);
+    const ApplyLds lay = apply_lds(sizeof(VT), sizeof(FT), sizeof(DT), a.tile, ncmax, a.cap, a.maxlev);
     VT *tile = reinterpret_cast<VT *>(smem);
     int *lin = reinterpret_cast<int *>(smem + lay.lin);
+    int *lp = reinterpret_cast<int *>(smem + lay.lp);
     FT *cf = reinterpret_cast<FT *>(smem + lay.cf);      // ncmax * cap
     DT *cd = reinterpret_cast<DT *>(smem + lay.cd);      // cap
     int *cl = reinterpret_cast<int *>(smem + lay.cl);    // cap
     const FT *F = reinterpret_cast<const FT *>(a.F);
     const DT *ID = reinterpret_cast<const DT *>(a.invd);
     for (int k = threadIdx.x; k < a.K; k += blockDim.x) lin[k] = a.lin[k];
+    for (int t = threadIdx.x; t <= sd.nlev; t += blockDim.x) lp[t] = a.lvlptr[sd.lvl_off + t];
     for (int i = threadIdx.x; i < a.tile; i += blockDim.x) tile[i] = (VT)0;
     __syncthreads();
     // gather R_i^delta r (right-RAS: R_i^0 r, zero on the overlap)
-    for (int c = threadIdx.x; c < sd.next; c += blockDim.x) {
-        const int x = c % sd.ex, y = (c / sd.ex) % sd.ey, z = c / (sd.ex * sd.ey);
-        const int g = bk.off + (sd.ox + x) + bk.nx * ((sd.oy + y) + bk.ny * (sd.oz + z));
-        const bool own = x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1 && z >= sd.lz0 && z < sd.lz1;
-        const double v = (a.variant == NKS_RIGHT_RAS && !own) ? 0.0 : a.r[g];
-        tile[(x + a.R) + a.PX * ((y + a.R) + a.PY * (z + a.Rz))] = (VT)v;
+    for (int c0 = threadIdx.x; c0 < sd.next; c0 += STAGE_U * blockDim.x) {
+        double v[STAGE_U];
+#pragma unroll
+        for (int u = 0; u < STAGE_U; ++u) {
+            const int c = c0 + u * blockDim.x;
+            if (c < sd.next) {
+                const int x = c % sd.ex, y = (c / sd.ex) % sd.ey, z = c / (sd.ex * sd.ey);
+                const int g = bk.off + (sd.ox + x) + bk.nx * ((sd.oy + y) + bk.ny * (sd.oz + z));
+                v[u] = a.r[g];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < STAGE_U; ++u) {
+            const int c = c0 + u * blockDim.x;
+            if (c < sd.next) {
+                const int x = c % sd.ex, y = (c / sd.ex) % sd.ey, z = c / (sd.ex * sd.ey);
+                const bool own = x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1 && z >= sd.lz0 && z < sd.lz1;
+                tile[(x + a.R) + a.PX * ((y + a.R) + a.PY * (z + a.Rz))] =
+                    (VT)((a.variant == NKS_RIGHT_RAS && !own) ? 0.0 : v[u]);
+            }
+        }
     }
     __syncthreads();
-    const int *lp = a.lvlptr + sd.lvl_off;
     const size_t fo = sd.fac_off;
     // forward: y_i = r_i - sum_{lower k} L_ik y_k
     for (int t0 = 0; t0 < sd.nlev;) {
@@ -495,11 +575,8 @@ __global__ void k_ras_apply(ApplyArgs a) {
         int t1 = t0 + 1;
         while (t1 < sd.nlev && lp[t1 + 1] - c0 <= a.cap) ++t1;
         const int c1 = lp[t1];
-        for (int e = c0 + threadIdx.x; e < c1; e += blockDim.x) {
-            const int le = e - c0;
-            for (int k = 0; k < ncl; ++k) cf[k * a.cap + le] = F[(size_t)k * a.NE + fo + e];
-            cl[le] = a.loc[fo + e];
-        }
+        stage_copy_k(cf, a.cap, F + fo + c0, (size_t)a.NE, ncl, c1 - c0);
+        stage_copy(cl, a.loc + fo + c0, c1 - c0);
         __syncthreads();
         for (int t = t0; t < t1; ++t) {
             for (int e = lp[t] + threadIdx.x; e < lp[t + 1]; e += blockDim.x) {
@@ -520,12 +597,9 @@ __global__ void k_ras_apply(ApplyArgs a) {
         int t0 = t1 - 1;
         while (t0 > 0 && c1 - lp[t0 - 1] <= a.cap) --t0;
         const int c0 = lp[t0];
-        for (int e = c0 + threadIdx.x; e < c1; e += blockDim.x) {
-            const int le = e - c0;
-            for (int k = 0; k < ncu; ++k) cf[k * a.cap + le] = F[(size_t)(a.diag + 1 + k) * a.NE + fo + e];
-            cd[le] = ID[fo + e];
-            cl[le] = a.loc[fo + e];
-        }
+        stage_copy_k(cf, a.cap, F + (size_t)(a.diag + 1) * a.NE + fo + c0, (size_t)a.NE, ncu, c1 - c0);
+        stage_copy(cd, ID + fo + c0, c1 - c0);
+        stage_copy(cl, a.loc + fo + c0, c1 - c0);
         __syncthreads();
         for (int t = t1 - 1; t >= t0; --t) {
             for (int e = lp[t] + threadIdx.x; e < lp[t + 1]; e += blockDim.x) {
@@ -555,6 +629,260 @@ __global__ void k_ras_apply(ApplyArgs a) {
             const int x = c % sd.ex, y = (c / sd.ex) % sd.ey, z = c / (sd.ex * sd.ey);
             a.zext[fo + c] = (double)tile[(x + a.R) + a.PX * ((y + a.R) + a.PY * (z + a.Rz))];
         }
+    }
+}
+
+
+// ---------------------------------------------------------------- kernel: 2D register wavefront
+// One wavefront per subdomain, lane = row y of the extended box.  At step t
+// lane y handles cell x = t - LB*y (the hyperplane order), so every lower
+// neighbour (x+dx, y+dy) was produced by lane y+dy exactly
+// -(dx + LB*dy) steps earlier.  Each lane keeps its last H outputs in a
+// register ring and reads the rows below / above through DPP lane shifts;
+// only the factor coefficients and the right-hand side come from LDS.
+__device__ __forceinline__ float lane_shr(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_shl(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double lane_shr(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_shl(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// stencil shapes: 0 = 5-point cross (lb 1), 1 = 5x5 box (lb 3)
+template <int BOX> struct RowStencil;
+template <> struct RowStencil<0> {
+    static constexpr int LB = 1, H = 1, NS = 4, NL = 2;
+    // off-diagonal slots in increasing column order: (dx, dy)
+    static constexpr int DX[NS] = {0, -1, 1, 0};
+    static constexpr int DY[NS] = {-1, 0, 0, 1};
+};
+template <> struct RowStencil<1> {
+    static constexpr int LB = 3, H = 8, NS = 24, NL = 12;
+    static constexpr int DX[NS] = {-2, -1, 0, 1, 2, -2, -1, 0, 1, 2, -2, -1, 1, 2, -2, -1, 0, 1, 2, -2, -1, 0, 1, 2};
+    static constexpr int DY[NS] = {-2, -2, -2, -2, -2, -1, -1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2};
+};
+
+struct RowsArgs {
+    const SubDev *sub;
+    const Blk *blk;
+    const int *slotmap;   // 25 box slots -> stencil index or -1
+    const void *F;        // K*NE off-diagonal factors (FT), lexicographic per subdomain
+    const void *invd;     // NE (DT)
+    int NE;
+    const double *r;
+    double *z, *zext;
+    const int *mask;
+    int variant, accumulate;
+};
+
+// coefficients of one cell: N consecutive FT values (16-byte aligned runs)
+template <typename FT, typename VT, int N>
+__device__ __forceinline__ void load_run(const FT *p, VT (&out)[N]) {
+    static_assert((N * sizeof(FT)) % 16 == 0, "runs are whole 16-byte words");
+    constexpr int W = (int)(N * sizeof(FT) / 16);
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint4 u = q[w];
+        const FT *f = reinterpret_cast<const FT *>(&u);
+        constexpr int PER = (int)(16 / sizeof(FT));
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if constexpr (sizeof(FT) == 2) out[w * PER + k] = (VT)from_bf16(f[k]);
+            else out[w * PER + k] = (VT)f[k];
+        }
+    }
+}
+
+template <typename FT, typename VT, typename DT, int BOX>
+__global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
+    using S = RowStencil<BOX>;
+    constexpr int NS = S::NS, NL = S::NL, NU = NS - NL, LB = S::LB;
+    constexpr int PER = (int)(16 / sizeof(FT));
+    constexpr int NLP = (NL + PER - 1) / PER * PER, NUP = (NU + PER - 1) / PER * PER;
+    constexpr int NSP = NLP + NUP;   // padded run per cell: lower run, then upper run
+    constexpr int RU = 8;            // unroll = ring length (>= the deepest history used)
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SubDev sd = a.sub[blockIdx.x];
+    if (a.mask && !a.mask[sd.blk]) return;
+    const Blk bk = a.blk[sd.blk];
+    const int n = sd.next, ex = sd.ex, ey = sd.ey;
+    VT *rv = reinterpret_cast<VT *>(smem);
+    FT *cf = reinterpret_cast<FT *>(smem + al16(sizeof(VT) * (size_t)n));
+    static_assert(sizeof(FT) * NSP % 16 == 0, "cell runs are whole 16-byte words");
+    DT *id = reinterpret_cast<DT *>(smem + al16(sizeof(VT) * (size_t)n) + al16(sizeof(FT) * (size_t)NSP * n));
+    const FT *F = reinterpret_cast<const FT *>(a.F);
+    const DT *ID = reinterpret_cast<const DT *>(a.invd);
+    const size_t fo = sd.fac_off;
+    __shared__ int kmap[NSP];
+    if ((int)threadIdx.x < NSP) {
+        const int r = threadIdx.x;
+        int k = -1;
+        if (r < NL) k = a.slotmap[(S::DX[r] + 2) + 5 * (S::DY[r] + 2)];
+        else if (r >= NLP && r < NLP + NU)
+            k = a.slotmap[(S::DX[r - NLP + NL] + 2) + 5 * (S::DY[r - NLP + NL] + 2)];
+        kmap[r] = k;
+    }
+    __syncthreads();
+    // stage: coefficients cell-major (cf[c*NSP + slot], absent slots zero),
+    // 1/u_ii and R_i^delta r.  Thread t takes cells t, t+256, ...; every load
+    // of a group of CPT cells is issued before the first LDS store.
+    {
+        constexpr int CPT = BOX ? 2 : 8;
+        int ks[NSP];
+#pragma unroll
+        for (int q = 0; q < NSP; ++q) ks[q] = kmap[q];
+        for (int c0 = threadIdx.x; c0 < n; c0 += CPT * 256) {
+            FT v[CPT][NSP];
+            DT d[CPT];
+            double rr[CPT];
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = c0 + u * 256;
+                if (c < n) {
+#pragma unroll
+                    for (int q = 0; q < NSP; ++q) v[u][q] = ks[q] >= 0 ? F[(size_t)ks[q] * a.NE + fo + c] : (FT)0;
+                    d[u] = ID[fo + c];
+                    const int y = c / ex, x = c - y * ex;
+                    rr[u] = a.r[bk.off + (sd.ox + x) + bk.nx * (sd.oy + y + bk.ny * sd.oz)];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = c0 + u * 256;
+                if (c < n) {
+#pragma unroll
+                    for (int q = 0; q < NSP; ++q) cf[(size_t)c * NSP + q] = v[u][q];
+                    id[c] = d[u];
+                    const int y = c / ex, x = c - y * ex;
+                    const bool own = x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1;
+                    rv[c] = (VT)((a.variant == NKS_RIGHT_RAS && !own) ? 0.0 : rr[u]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {          // one wavefront sweeps; lane = row
+    const int y = threadIdx.x;
+    const int T = (ex - 1) + LB * (ey - 1) + 1;
+    // RB steps per block: every LDS read of a block is issued before its
+    // first step and every write after its last, so the loads overlap the
+    // dependent arithmetic of the previous block.
+    constexpr int RB = BOX ? 4 : 8;
+    // rings: own outputs, outputs of lane y-1 and y-2 (forward) / y+1, y+2 (backward)
+    VT r0[RU], r1[RU], r2[RU];
+#pragma unroll
+    for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
+    // forward: y_i = r_i - sum_{lower} L_ik y_k
+    for (int t0 = 0; t0 < T; t0 += RU) {
+#pragma unroll
+        for (int b0 = 0; b0 < RU; b0 += RB) {
+            VT co[RB][NLP], rin[RB], outv[RB];
+            int cc[RB];
+            bool aa[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int x = t0 + b0 + u - LB * y;
+                aa[u] = y < ey && x >= 0 && x < ex;
+                cc[u] = aa[u] ? y * ex + x : 0;
+                load_run<FT, VT, NLP>(cf + (size_t)cc[u] * NSP, co[u]);
+                rin[u] = rv[cc[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int uu = b0 + u;
+                VT v = rin[u];
+                // older terms first, the one-step-old terms (critical path) last
+#pragma unroll
+                for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+                    for (int q = 0; q < NL; ++q) {
+                        const int h = -(S::DX[q] + LB * S::DY[q]) - 1;
+                        if ((h == 0) != (pass == 1)) continue;
+                        const int slot = (uu - 1 - h + 2 * RU) % RU;
+                        const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == -1 ? r1[slot] : r2[slot]);
+                        v -= co[u][q] * val;
+                    }
+                }
+                const VT out = aa[u] ? v : (VT)0;
+                outv[u] = out;
+                r0[uu] = out;
+                r1[uu] = lane_shr(out);
+                r2[uu] = lane_shr(r1[uu]);
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u)
+                if (aa[u]) rv[cc[u]] = outv[u];
+        }
+    }
+    // backward: z_i = (y_i - sum_{upper} U_ik z_k) / u_ii
+#pragma unroll
+    for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
+    for (int t0 = 0; t0 < T; t0 += RU) {
+#pragma unroll
+        for (int b0 = 0; b0 < RU; b0 += RB) {
+            VT co[RB][NUP], rin[RB], dg[RB], outv[RB];
+            int cc[RB];
+            bool aa[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int x = (T - 1 - t0 - b0 - u) - LB * y;
+                aa[u] = y < ey && x >= 0 && x < ex;
+                cc[u] = aa[u] ? y * ex + x : 0;
+                load_run<FT, VT, NUP>(cf + (size_t)cc[u] * NSP + NLP, co[u]);
+                rin[u] = rv[cc[u]];
+                dg[u] = (VT)id[cc[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int uu = b0 + u;
+                VT v = rin[u];
+#pragma unroll
+                for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+                    for (int q = NL; q < NS; ++q) {
+                        const int h = S::DX[q] + LB * S::DY[q] - 1;
+                        if ((h == 0) != (pass == 1)) continue;
+                        const int slot = (uu - 1 - h + 2 * RU) % RU;
+                        const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == 1 ? r1[slot] : r2[slot]);
+                        v -= co[u][q - NL] * val;
+                    }
+                }
+                const VT out = aa[u] ? v * dg[u] : (VT)0;
+                outv[u] = out;
+                r0[uu] = out;
+                r1[uu] = lane_shl(out);
+                r2[uu] = lane_shl(r1[uu]);
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u)
+                if (aa[u]) rv[cc[u]] = outv[u];
+        }
+    }
+    }   // sweeping wavefront
+    __syncthreads();
+    // write back with all threads, x-contiguous (coalesced)
+    if (a.variant == NKS_LEFT_RAS) {
+        const int oxn = sd.lx1 - sd.lx0, oyn = sd.ly1 - sd.ly0;
+        for (int k = threadIdx.x; k < oxn * oyn; k += blockDim.x) {
+            const int x = sd.lx0 + k % oxn, y = sd.ly0 + k / oxn;
+            const size_t g = bk.off + (sd.ox + x) + bk.nx * (sd.oy + y + bk.ny * sd.oz);
+            const double v = (double)rv[y * ex + x];
+            a.z[g] = a.accumulate ? a.z[g] + v : v;
+        }
+    } else {
+        for (int c = threadIdx.x; c < n; c += blockDim.x) a.zext[fo + c] = (double)rv[c];
     }
 }
 
@@ -742,6 +1070,7 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     L = std::max(1, std::min(d.levels, 6));
     Alloc *al = &g->al;
     hipStream_t s = g->s;
+    coarse.invalidate_graphs();
     lev.clear();
     tiles_.clear();
     lev.emplace_back(new Level());
@@ -799,6 +1128,7 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
         V.w64.alloc(al, K * NE);
         if (d.precision == NKS_FP64) {
             V.invd64.alloc(al, NE);
+            V.f64.alloc(al, K * NE);
         } else {
             V.invd32.alloc(al, NE);
             if (d.precision == NKS_FP32) V.f32.alloc(al, K * NE);
@@ -830,7 +1160,7 @@ void Ras::factor() {
             const int Kc = V.own.st.K;
             const int bs = 64;
             const size_t sh = (size_t)bs * Kc * sizeof(double);
-            HIPC(hipFuncSetAttribute((const void *)k_rap, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+            set_lds((const void *)k_rap, sh);
             ProfScope ps("rap", s, l);
             k_rap<<<nblk(V.spp->N, bs), bs, sh, s>>>(a, F.A->coef.p, F.A->st.K, F.A->st.doff.p, V.own.coef.p, Kc,
                                                     F.rap_slot.p, F.rap_R);
@@ -863,18 +1193,19 @@ void Ras::factor() {
         k_ilu_fill<<<V.nsub, 256, 0, s>>>(fa);
         KCHECK();
         const int bs = 64;
-        const size_t sh = (size_t)bs * fa.K * sizeof(double);
-        HIPC(hipFuncSetAttribute((const void *)k_ilu_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+        const size_t sh = (size_t)bs * fa.K * sizeof(double) + sizeof(int) * (size_t)(V.max_nlev + 1);
+        set_lds((const void *)k_ilu_factor, sh);
         ProfScope ps("ilu_factor", s, l);
         k_ilu_factor<<<V.nsub, bs, sh, s>>>(fa);
         KCHECK();
         const int NE = V.next_total;
+        const int *perm = V.rows2d ? V.lexg.p : nullptr;
         if (d.precision == NKS_FP64) {
-            k_ilu_store<double, double><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, nullptr, V.invd64.p);
+            k_ilu_store<double, double><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, V.f64.p, V.invd64.p, perm);
         } else if (d.precision == NKS_FP32) {
-            k_ilu_store<float, float><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, V.f32.p, V.invd32.p);
+            k_ilu_store<float, float><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, V.f32.p, V.invd32.p, perm);
         } else {
-            k_ilu_store<uint16_t, float><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, V.f16.p, V.invd32.p);
+            k_ilu_store<uint16_t, float><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, V.f16.p, V.invd32.p, perm);
         }
         KCHECK();
     }
@@ -899,8 +1230,51 @@ static int level_index(const Ras &M, const Level &V) {
 }
 
 template <typename FT, typename VT, typename DT>
+static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int *mask, bool accumulate) {
+    RowsArgs a;
+    a.sub = V.sub.p;
+    a.blk = V.spp->blk.p;
+    a.slotmap = V.slotmap.p;
+    if (M.d.precision == NKS_FP64) a.F = V.f64.p;
+    else if (M.d.precision == NKS_FP32) a.F = V.f32.p;
+    else a.F = V.f16.p;
+    a.invd = M.d.precision == NKS_FP64 ? (const void *)V.invd64.p : (const void *)V.invd32.p;
+    a.NE = V.next_total;
+    a.r = r;
+    a.z = z;
+    a.zext = V.zext.p;
+    a.mask = mask;
+    a.variant = M.d.variant;
+    a.accumulate = accumulate ? 1 : 0;
+    const int per = (int)(16 / sizeof(FT));
+    auto pad = [&](int k) { return (k + per - 1) / per * per; };
+    const int NSP = V.box ? pad(RowStencil<1>::NL) + pad(RowStencil<1>::NS - RowStencil<1>::NL)
+                          : pad(RowStencil<0>::NL) + pad(RowStencil<0>::NS - RowStencil<0>::NL);
+    const size_t n = V.max_next;
+    const size_t sh = al16(sizeof(VT) * n) + al16(sizeof(FT) * NSP * n) + al16(sizeof(DT) * n);
+    if (sh > (size_t)M.lds_bytes) fail(NKS_EINVAL, "2D subdomain of %zu cells does not fit in LDS", n);
+    const void *fn = V.box ? (const void *)k_ras_rows<FT, VT, DT, 1> : (const void *)k_ras_rows<FT, VT, DT, 0>;
+    set_lds(fn, sh);
+    {
+        ProfScope ps("ras_apply", M.g->s, level_index(M, V));
+        if (V.box) k_ras_rows<FT, VT, DT, 1><<<V.nsub, 256, sh, M.g->s>>>(a);
+        else k_ras_rows<FT, VT, DT, 0><<<V.nsub, 256, sh, M.g->s>>>(a);
+        KCHECK();
+    }
+    if (M.d.variant != NKS_LEFT_RAS) {
+        k_ras_gather<<<nblk(V.spp->N, 256), 256, 0, M.g->s>>>(V.spp->blk.p, V.spp->B, V.spp->N, V.part.p,
+                                                              V.sub.p, V.zext.p, z, mask, accumulate ? 1 : 0);
+        KCHECK();
+    }
+}
+
+template <typename FT, typename VT, typename DT>
 static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, double *z, const int *mask,
                          bool accumulate) {
+    if (V.rows2d) {
+        launch_rows<FT, VT, DT>(M, V, r, z, mask, accumulate);
+        return;
+    }
     ApplyArgs a;
     a.sub = V.sub.p;
     a.blk = V.spp->blk.p;
@@ -908,7 +1282,7 @@ static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, 
     a.loc = V.loc.p;
     a.lexi = V.lexi.p;
     a.lin = V.lin_pad.p;
-    if (M.d.precision == NKS_FP64) a.F = V.w64.p;
+    if (M.d.precision == NKS_FP64) a.F = V.f64.p;
     else if (M.d.precision == NKS_FP32) a.F = V.f32.p;
     else a.F = V.f16.p;
     a.invd = M.d.precision == NKS_FP64 ? (const void *)V.invd64.p : (const void *)V.invd32.p;
@@ -929,17 +1303,18 @@ static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, 
     a.accumulate = accumulate ? 1 : 0;
     const int ncmax = std::max(a.diag, a.K - a.diag - 1);
     const size_t budget = (size_t)M.lds_bytes;
-    const size_t fixed = apply_lds(sizeof(VT), sizeof(FT), sizeof(DT), a.tile, ncmax, 0).total + 64;
+    a.maxlev = V.max_nlev;
+    const size_t fixed = apply_lds(sizeof(VT), sizeof(FT), sizeof(DT), a.tile, ncmax, 0, a.maxlev).total + 64;
     const size_t per = sizeof(FT) * (size_t)ncmax + sizeof(DT) + sizeof(int);
     if (fixed + per * (size_t)V.max_lvl > budget)
         fail(NKS_EINVAL, "subdomain tile of %d cells and hyperplanes of %d cells do not fit in LDS (%zu bytes)",
              a.tile, V.max_lvl, budget);
     a.cap = (int)std::min<size_t>((budget - fixed) / per, (size_t)V.max_next);
     a.cap = std::max(a.cap, V.max_lvl);
-    const size_t sh = apply_lds(sizeof(VT), sizeof(FT), sizeof(DT), a.tile, ncmax, a.cap).total;
+    const size_t sh = apply_lds(sizeof(VT), sizeof(FT), sizeof(DT), a.tile, ncmax, a.cap, a.maxlev).total;
     if (sh > budget) fail(NKS_EINVAL, "LDS layout of %zu bytes exceeds %zu", sh, budget);
     const void *fn = (const void *)k_ras_apply<FT, VT, DT>;
-    HIPC(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+    set_lds(fn, sh);
     const int bs = td.PZ == 1 ? 64 : 256;
     {
         ProfScope ps("ras_apply", M.g->s, level_index(M, V));
@@ -993,6 +1368,7 @@ void Ras::coarse_solve(const double *b, double *x, const int *mask) {
     o.maxit = d.coarse_maxit;
     o.flexible = false;
     o.check_every = 1;
+    o.graph_chunk = graph_chunk;
     coarse.solve(A, P, b, x, true, o, mask, s);
     ++coarse_calls;
 }
