@@ -26,6 +26,30 @@ sys.path.insert(0, HERE)
 METRIC = "time/implicit step + ras_apply GB/s, mixed-prec vs FP64 at rel.res 1e-6"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes moved per active fine-level launch of the FP64 2D sweep kernel on
+# the 512x512 workload, from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0 and
+# WRITE_SIZE x 1.0, the factors that make a 256 MiB device copy read and write
+# 256 MiB).  Valid only for the kernel source it was taken on: any edit of that
+# file drops it to null until the counters are taken again.
+PMC_TRAFFIC = {
+    "workload": "c2_512x512_twolevel_fp64",
+    "source": "paper_2007_13966_amd/csrc/schwarz.hip",
+    "sha1": "3a28ec9724619c19ce588794722edb34230c8242",
+    "fetch_kib": 8873.10, "fetch_scale": 2.0,
+    "write_kib": 2048.0, "write_scale": 1.0,
+}
+
+
+def pmc_traffic(workload):
+    import hashlib
+    t = PMC_TRAFFIC
+    if workload != t["workload"]:
+        return None
+    with open(os.path.join(HERE, t["source"]), "rb") as f:
+        if hashlib.sha1(f.read()).hexdigest() != t["sha1"]:
+            return None
+    return 1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -47,15 +71,35 @@ def ext_cells(nx, ny, nz, px, py, pz, delta):
     return sum(a * b * c for a in ex for b in ey for c in ez)
 
 
-def apply_bytes(rec, s, precision):
-    """Algorithmic bytes of one fine-level one-level Schwarz apply: per
-    extended cell the off-diagonal factors, 1/u_ii and the gathered residual;
-    per owned cell the written correction."""
-    K = 7 if rec.nz > 1 else 5
+def boxes(rec, s):
+    """Boxes per direction: from the tile edge when one is set, else the counts."""
+    n, t, P = (rec.nx, rec.ny, rec.nz), s.tile, (s.px, s.py, s.pz)
+    return [-(-n[a] // t[a]) if t[a] > 0 else P[a] for a in range(3)]
+
+
+def apply_bytes(recs, s, precision):
+    """Algorithmic bytes of one fine-level one-level Schwarz apply over all
+    reservoirs: per extended cell the off-diagonal factors, 1/u_ii and the
+    gathered residual; per owned cell the written correction."""
     fb = {"fp64": 8, "fp32": 4, "bf16": 2}[precision]
     db = 8 if precision == "fp64" else 4
-    ne = ext_cells(rec.nx, rec.ny, rec.nz, s.px, s.py, s.pz, s.overlap[0])
-    return ne * ((K - 1) * fb + db + 8) + rec.N * 8, ne
+    nbytes = nexts = 0
+    for rec in recs:
+        K = 7 if rec.nz > 1 else 5
+        ne = ext_cells(rec.nx, rec.ny, rec.nz, *boxes(rec, s), s.overlap[0])
+        nbytes += ne * ((K - 1) * fb + db + 8) + rec.N * 8
+        nexts += ne
+    return nbytes, nexts
+
+
+def launch_split(d):
+    """Active launches of the roofline kernel: the Krylov loop runs ahead of
+    its host-side convergence check, so a few launches per solve find every
+    reservoir masked out and exit at once (under half the median)."""
+    d = np.asarray(d)
+    if d.size == 0:
+        return d
+    return d[d >= np.median(d) / 2]
 
 
 def run_gpu(P, case, settings, warmup, steps, profile=True):
@@ -91,10 +135,12 @@ def run_gpu(P, case, settings, warmup, steps, profile=True):
         import ctypes as C
         for name in ["ras_apply_l0", "ras_apply_l1", "ras_apply_l2", "spmv_l0", "spmv_l1",
                      "gmres_orth", "residual_jacobian", "ilu_factor_l0", "ilu_factor_l1", "rap_l1"]:
-            c, ms = C.c_int(), C.c_double()
-            P.check(P.lib().nks_profile_query(name.encode(), C.byref(c), C.byref(ms)))
+            c = C.c_int()
+            P.check(P.lib().nks_profile_durations(name.encode(), None, 0, C.byref(c)))
             if c.value:
-                prof[name] = (c.value, ms.value)
+                buf = (C.c_double * c.value)()
+                P.check(P.lib().nks_profile_durations(name.encode(), buf, c.value, C.byref(c)))
+                prof[name] = np.array(buf[:])
         P.check(P.lib().nks_profile_enable(0))
     return dict(seconds=t1 - t0, stats=stats, prof=prof, p_start=p_start.cpu().numpy(),
                 p_end=hist[-1].cpu().numpy())
@@ -124,6 +170,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB five times (the "
+                         "reference kernel for scaling HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -136,19 +185,29 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        x = torch.arange(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 5}))
+        return
     case = {"c1": S.case_c1, "c2": S.case_c2, "c3": S.case_c3, "c4": S.case_c4}[args.workload]()
     s64 = S.with_solver(case, precision="fp64").solver if args.workload != "c2" else case.solver
     log(f"workload {case.name}: {sum(r.N for r in case.problems)} cells")
+    nbytes, nexts = apply_bytes(case.problems, s64, "fp64")
     r64 = run_gpu(P, case, s64, args.warmup, args.steps)
     st = r64["stats"]
     sec = r64["seconds"] / args.steps
     nits = [x["newton_its"] for x in st]
     lits = [x["linear_its"] for x in st]
     log(f"fp64: {sec:.4f} s/step, newton {nits}, gmres {lits}")
-    rec = case.problems[0]
-    nbytes, nexts = apply_bytes(rec, s64, "fp64")
-    cnt, ms = r64["prof"].get("ras_apply_l0", (0, 0.0))
-    avg_s = ms / 1e3 / max(cnt, 1)
+    allv = r64["prof"].get("ras_apply_l0", np.zeros(0))
+    act = launch_split(allv)
+    cnt = int(act.size)
+    avg_s = float(act.mean()) / 1e3 if cnt else 0.0
     achieved = nbytes / avg_s / 1e9 if cnt else None
     out = {
         "metric": METRIC,
@@ -167,7 +226,9 @@ def main():
             "workload": case.name,
             "description": " ".join((case.description or "").split()),
             "cells": sum(r.N for r in case.problems),
-            "levels": s64.levels, "subdomains": s64.px * s64.py * s64.pz,
+            "reservoirs": len(case.problems),
+            "levels": s64.levels,
+            "subdomains": int(sum(np.prod(boxes(r, s64)) for r in case.problems)),
             "overlap": list(s64.overlap), "precision": s64.precision,
             "newton_its_per_step": float(np.mean(nits)),
             "gmres_its_per_newton": float(np.sum(lits) / max(1, np.sum(nits))),
@@ -180,25 +241,27 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None,
+            "traffic": pmc_traffic(case.name),
             "bytes_per_launch": nbytes,
             "ext_cells": nexts,
             "launches": cnt,
+            "masked_launches": int(allv.size - cnt),
             "avg_launch_us": avg_s * 1e6,
         },
-        "kernels_ms": {k: {"count": c, "total_ms": round(t, 3), "avg_us": round(1e3 * t / c, 2)}
-                       for k, (c, t) in r64["prof"].items()},
+        "kernels_ms": {k: {"count": int(v.size), "total_ms": round(float(v.sum()), 3),
+                           "avg_us": round(1e3 * float(v.mean()), 2)}
+                       for k, v in r64["prof"].items()},
     }
     if not args.no_mixed:
         s32 = S.with_solver(case, precision="fp32").solver
+        b32, _ = apply_bytes(case.problems, s32, "fp32")
         r32 = run_gpu(P, case, s32, args.warmup, args.steps)
         sec32 = r32["seconds"] / args.steps
         d64 = r64["p_end"] - r64["p_start"]
         d32 = r32["p_end"] - r32["p_start"]
         err = float(np.linalg.norm(d32 - d64) / max(np.linalg.norm(d64), 1e-300))
-        b32, _ = apply_bytes(rec, s32, "fp32")
-        c32, ms32 = r32["prof"].get("ras_apply_l0", (0, 0.0))
-        a32 = b32 / (ms32 / 1e3 / max(c32, 1)) / 1e9 if c32 else None
+        act32 = launch_split(r32["prof"].get("ras_apply_l0", np.zeros(0)))
+        a32 = b32 / (float(act32.mean()) / 1e3) / 1e9 if act32.size else None
         out["mixed_fp32"] = {
             "s_per_step": sec32,
             "speedup_vs_fp64": sec / sec32,

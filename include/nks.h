@@ -153,6 +153,8 @@ typedef struct {
     int coarse_maxit;
     int coarse_restart;
     int precision;               /* NKS_FP64 | NKS_FP32 | NKS_BF16 */
+    int tx, ty, tz;              /* > 0: box edge in cells on the finest level, so each
+                                    reservoir gets ceil(n/t) boxes in that direction */
 } nks_ras_desc;
 
 /* Creates (*inout == NULL) or refactors in place (*inout from an earlier
@@ -209,7 +211,15 @@ int nks_gmres_solve(nks_matrix *J, nks_ras *M, const double *b, double *x,
  * max{eta_r ||F||, eta_a}, lambda from a cubic backtracking line search with
  * ||F(X + lambda s)|| <= (1 - alpha lambda)||F(X)||, until
  * ||F|| <= max{eps_r ||F(X^0)||, eps_a} or ||lambda s|| <= stol ||X|| in every
- * reservoir (the step test is that of the PETSc solver used in Section 4).
+ * reservoir (the step test is that of the PETSc solver used in Section 4), or,
+ * with floor_test, when ||F|| is at the binary64 rounding floor of its own
+ * evaluation, u || |J| |X| || (the componentwise bound of the stencil product
+ * that makes up the flux terms; needed where eps_r ||F(X^0)|| is below what
+ * binary64 can resolve).  The
+ * step test is also taken on the full step before the line search: a full step
+ * that small is taken as it is (lambda = 1, no decrease test, since at the
+ * FP64 rounding floor ||F|| cannot decrease) and the reservoir stops.  Each
+ * reservoir stops on its own; the call returns when all have.
  * p: device in (initial guess, usually p_n) / out. */
 typedef struct {
     double eps_r, eps_a;
@@ -218,7 +228,10 @@ typedef struct {
     int flexible;                /* -1: FGMRES iff levels > 1 or precision != FP64 */
     double alpha;
     int max_newton, max_backtracks;
-    double stol;                 /* also stop when ||lambda s|| <= stol ||X^{k+1}|| (0: off) */
+    double stol;                 /* also stop after a full step with ||s|| <= stol ||X^k||
+                                    or when ||lambda s|| <= stol ||X^{k+1}|| (0: off) */
+    int floor_test;              /* nonzero: also stop when ||F(X)|| <= u || |J(X)| |X| ||,
+                                    u = 2^-53, the rounding floor of evaluating F */
 } nks_newton_desc;
 
 typedef struct {
@@ -236,14 +249,21 @@ int nks_newton_step(nks_grid *g, double *p, const double *p_n, const double *p_n
                     double dt, int bdf_order, const nks_newton_desc *nd,
                     const nks_ras_desc *rd, nks_newton_stats *st);
 
-/* Kernel timing with HIP events recorded on the launching stream around the
- * named hot-path launches: "ras_apply_l<level>" (one-level Schwarz sweeps),
- * "ilu_factor_l<level>", "rap_l<level>", "spmv", "gmres_orth",
- * "residual_jacobian".  enable != 0 clears the records and starts
- * recording, 0 stops.  query synchronises and returns the number of
- * launches and their summed duration (ms); unknown names give 0. */
+/* Kernel timing with HIP events on the launching stream.  Single-kernel
+ * records carry the events on the dispatch itself (the kernel's own
+ * execution time): "ras_apply_l<level>" (one-level Schwarz sweeps),
+ * "ilu_factor_l<level>", "rap_l<level>", "spmv_l<0|1>" (7-or-fewer-point /
+ * wider stencils).  Span records bracket several kernels: "gmres_orth",
+ * "residual_jacobian".  Launches inside captured graphs are not recorded.
+ * enable != 0 clears the records and starts recording, 0 stops.  query
+ * synchronises and returns the number of launches and their summed duration
+ * (ms); unknown names give 0.  durations writes the first min(cap, count)
+ * per-launch durations (ms, launch order) to host array ms and the record
+ * count to *count, so a caller can separate dispatches that found every
+ * reservoir masked out (speculative Krylov iterations past convergence). */
 int nks_profile_enable(int enable);
 int nks_profile_query(const char *name, int *count, double *total_ms);
+int nks_profile_durations(const char *name, double *ms, int cap, int *count);
 
 /* Thread-local message of the last failing call (empty when none). */
 const char *nks_last_error(void);

@@ -36,14 +36,14 @@ class MgDesc(C.Structure):
                 ("overlap", C.c_int * 8), ("variant", C.c_int), ("subsolve", C.c_int),
                 ("interp_order", C.c_int), ("cycle", C.c_int), ("mu", C.c_int), ("nu", C.c_int),
                 ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int),
-                ("coarse_restart", C.c_int)]
+                ("coarse_restart", C.c_int), ("tx", C.c_int), ("ty", C.c_int), ("tz", C.c_int)]
 
 
 class NewtonDesc(C.Structure):
     _fields_ = [("eps_r", C.c_double), ("eps_a", C.c_double), ("eta_r", C.c_double),
                 ("eta_a", C.c_double), ("restart", C.c_int), ("maxit", C.c_int),
                 ("flexible", C.c_int), ("alpha", C.c_double), ("max_newton", C.c_int),
-                ("max_backtracks", C.c_int), ("stol", C.c_double)]
+                ("max_backtracks", C.c_int), ("stol", C.c_double), ("floor_test", C.c_int)]
 
 
 class NewtonStats(C.Structure):
@@ -242,6 +242,7 @@ def mg_desc(s):
     d.coarse_rtol = s.coarse_rtol
     d.coarse_maxit = s.coarse_maxit
     d.coarse_restart = s.coarse_restart
+    d.tx, d.ty, d.tz = s.tile
     return d
 
 
@@ -254,6 +255,7 @@ def newton_desc(s):
     d.alpha = s.alpha
     d.max_newton, d.max_backtracks = s.max_newton, s.max_backtracks
     d.stol = s.stol
+    d.floor_test = 1 if s.floor_test else 0
     return d
 
 

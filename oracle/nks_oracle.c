@@ -754,8 +754,8 @@ static void box_range(int n, int P, int q, int *lo, int *hi) {
     *hi = *lo + base + (q < rem ? 1 : 0);
 }
 
-static void build_subdomains(level *lv, const orc_mg_desc *d, int delta) {
-    int P[3] = {d->px, d->py, d->pz};
+static void build_subdomains(level *lv, const int *Pbox, int delta) {
+    int P[3] = {Pbox[0], Pbox[1], Pbox[2]};
     int n[3] = {lv->nx, lv->ny, lv->nz};
     for (int k = 0; k < 3; ++k) if (P[k] > n[k]) P[k] = n[k];
     lv->nsub = P[0] * P[1] * P[2];
@@ -1071,10 +1071,15 @@ orc_mg *orc_mg_new(int nx, int ny, int nz, int n, const int *rp, const int *ci,
         cl->A = csr_matmul(&Pt, &AP);
         csr_free(&AP); csr_free(&Pt);
     }
+    /* the same box grid on every level: box counts from the finest level */
+    int Pbox[3] = {d->px, d->py, d->pz};
+    int t[3] = {d->tx, d->ty, d->tz}, nf[3] = {nx, ny, nz};
+    for (int k = 0; k < 3; ++k)
+        if (t[k] > 0) Pbox[k] = (nf[k] + t[k] - 1) / t[k];
     for (int l = 0; l < mg->L; ++l) {
         level *lv = &mg->lev[l];
         int delta = d->overlap[l < 8 ? l : 7];
-        build_subdomains(lv, d, delta);
+        build_subdomains(lv, Pbox, delta);
         factor_subdomains(lv, d);
         for (int k = 0; k < 4; ++k) mg->work[l][k] = (double *)xcalloc(lv->n, sizeof(double));
     }
@@ -1200,10 +1205,19 @@ static int nonphysical(const orc_problem *pr, const double *p) {
  * preconditioned (F)GMRES to max{eta_r ||F||, eta_a}; lambda^k by a cubic
  * backtracking line search (Dennis-Schnabel) until
  * ||F(X^k + lambda s)|| <= (1 - alpha lambda) ||F(X^k)||; stop when
- * ||F(X^{k+1})|| <= max{eps_r ||F(X^0)||, eps_a}, or when the accepted step
- * is below stol relative to X^{k+1} (the relative step test of the PETSc
- * solver used in Section 4; without it FP64 rounding of the residual can put
- * eps_r ||F(X^0)|| below the attainable floor). */
+ * ||F(X^{k+1})|| <= max{eps_r ||F(X^0)||, eps_a}, or when the step is below
+ * stol relative to the iterate (the relative step test of the PETSc solver
+ * used in Section 4; without it FP64 rounding of the residual can put
+ * eps_r ||F(X^0)|| below the attainable floor).  The step test is taken on the
+ * full Newton step before the line search too: a full step that small is taken
+ * as it is (lambda = 1, no decrease test, since at the rounding floor ||F||
+ * cannot decrease) and Newton stops.
+ *
+ * Rounding floor (floor_test): the flux part of F is a stencil product in X
+ * for frozen mobilities, so evaluating F in binary64 carries an error of
+ * order u |J| |X| per cell (the componentwise bound of a matrix-vector
+ * product; u = 2^-53).  When ||F(X^k)|| <= u || |J(X^k)| |X^k| || the iterate
+ * solves F = 0 as well as F can be evaluated, and Newton stops there. */
 int orc_newton_step(const orc_problem *pr, const orc_mg_desc *md, const orc_newton_desc *nd,
                     double *p, const double *pn, const double *pnm1, double dt, int order,
                     orc_newton_stats *st) {
@@ -1226,6 +1240,15 @@ int orc_newton_step(const orc_problem *pr, const orc_mg_desc *md, const orc_newt
     if (f0 <= stop) status = 0;
     for (int k = 0; k < nd->max_newton && status != 0; ++k) {
         orc_jacobian(pr, p, pn, pnm1, dt, order, rp, ci, v);
+        if (nd->floor_test) {
+            double fl = 0.0;
+            for (int i = 0; i < N; ++i) {
+                double a = 0.0;
+                for (int q = rp[i]; q < rp[i + 1]; ++q) a += fabs(v[q]) * fabs(p[ci[q]]);
+                fl += a * a;
+            }
+            if (fn <= ldexp(sqrt(fl), -53)) { status = 0; break; }
+        }
         orc_mg *M = orc_mg_new(pr->nx, pr->ny, pr->nz, N, rp, ci, v, md);
         for (int i = 0; i < N; ++i) { b[i] = -F[i]; s[i] = 0.0; }
         double lres;
@@ -1236,6 +1259,7 @@ int orc_newton_step(const orc_problem *pr, const orc_mg_desc *md, const orc_newt
         orc_mg_free(M);
         st->linear_its += lits;
         if (k < 64) st->lits[k] = lits;
+        const int small = nd->stol > 0.0 && norm2(N, s) <= nd->stol * norm2(N, p);
         /* line search on ||F||, merit f = ||F||^2 / 2 with slope F^T J s */
         orc_csr_matvec(N, rp, ci, v, s, Js);
         double fx = 0.5 * fn * fn, slope = dot(N, F, Js);
@@ -1249,7 +1273,7 @@ int orc_newton_step(const orc_problem *pr, const orc_mg_desc *md, const orc_newt
                 orc_residual(pr, pt, pn, pnm1, dt, order, Ft);
                 ft_norm = norm2(N, Ft);
             }
-            if (ft_norm <= (1.0 - nd->alpha * lam) * fn) { ok = 1; break; }
+            if ((small && isfinite(ft_norm)) || ft_norm <= (1.0 - nd->alpha * lam) * fn) { ok = 1; break; }
             if (bt == nd->max_backtracks) break;
             double ft = 0.5 * ft_norm * ft_norm, lt;
             if (!isfinite(ft) || slope >= 0.0) {
@@ -1277,7 +1301,7 @@ int orc_newton_step(const orc_problem *pr, const orc_mg_desc *md, const orc_newt
         fn = ft_norm;
         st->newton_its = k + 1;
         if (k < 64) { st->fnorms[k] = fn; st->lambdas[k] = lam; }
-        if (fn <= stop) status = 0;
+        if (fn <= stop || (small && lam == 1.0)) status = 0;
         /* relative step test of the PETSc nonlinear solver the paper ran on */
         if (nd->stol > 0.0 && lam * norm2(N, s) <= nd->stol * norm2(N, p)) status = 0;
     }

@@ -32,6 +32,7 @@ typedef struct {
     double coarse_rtol;     /* coarsest GMRES relative tolerance */
     int coarse_maxit;
     int coarse_restart;
+    int tx, ty, tz;         /* > 0: box edge in cells on the finest level (boxes = ceil(n/t)) */
 } orc_mg_desc;
 
 typedef struct {
@@ -42,6 +43,7 @@ typedef struct {
     double alpha;           /* line-search sufficient decrease */
     int max_newton, max_backtracks;
     double stol;            /* stop when ||lambda s|| <= stol ||X^{k+1}|| (0: off) */
+    int floor_test;         /* nonzero: also stop when ||F|| <= u || |J| |X| || */
 } orc_newton_desc;
 
 typedef struct {

@@ -82,6 +82,7 @@ def ras_desc(s):
     d.coarse_maxit = s.coarse_maxit
     d.coarse_restart = s.coarse_restart
     d.precision = PRECISIONS[s.precision]
+    d.tx, d.ty, d.tz = s.tile
     return d
 
 
@@ -93,6 +94,7 @@ def newton_desc(s):
     d.alpha = s.alpha
     d.max_newton, d.max_backtracks = s.max_newton, s.max_backtracks
     d.stol = s.stol
+    d.floor_test = 1 if s.floor_test else 0
     return d
 
 

@@ -44,7 +44,8 @@ class nks_ras_desc(C.Structure):
                 ("overlap", C.c_int * 8), ("variant", C.c_int), ("interp_order", C.c_int),
                 ("cycle", C.c_int), ("mu", C.c_int), ("nu", C.c_int),
                 ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int),
-                ("coarse_restart", C.c_int), ("precision", C.c_int)]
+                ("coarse_restart", C.c_int), ("precision", C.c_int),
+                ("tx", C.c_int), ("ty", C.c_int), ("tz", C.c_int)]
 
 
 class nks_gmres_desc(C.Structure):
@@ -62,7 +63,7 @@ class nks_newton_desc(C.Structure):
     _fields_ = [("eps_r", C.c_double), ("eps_a", C.c_double), ("eta_r", C.c_double),
                 ("eta_a", C.c_double), ("restart", C.c_int), ("maxit", C.c_int),
                 ("flexible", C.c_int), ("alpha", C.c_double), ("max_newton", C.c_int),
-                ("max_backtracks", C.c_int), ("stol", C.c_double)]
+                ("max_backtracks", C.c_int), ("stol", C.c_double), ("floor_test", C.c_int)]
 
 
 class nks_newton_stats(C.Structure):
@@ -107,6 +108,7 @@ PROTOTYPES = {
                         C.POINTER(nks_ras_desc), C.POINTER(nks_newton_stats)],
     "nks_profile_enable": [_I],
     "nks_profile_query": [C.c_char_p, _IP, _DP],
+    "nks_profile_durations": [C.c_char_p, _DP, _I, _IP],
     "nks_last_error": [],
     "nks_version": [],
 }

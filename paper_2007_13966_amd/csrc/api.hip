@@ -110,6 +110,18 @@ ProfScope::~ProfScope() {
     g_prof[key].ev.push_back({a, b});
 }
 
+bool prof_pair(const char *nm, int lvl, hipStream_t s, hipEvent_t *a, hipEvent_t *b) {
+    if (!g_prof_on) return false;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return false;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    *a = take_event();
+    *b = take_event();
+    std::string key = lvl >= 0 ? fmt("%s_l%d", nm, lvl) : std::string(nm);
+    g_prof[key].ev.push_back({*a, *b});
+    return true;
+}
+
 static void prof_clear() {
     for (auto &kv : g_prof)
         for (auto &p : kv.second.ev) {
@@ -228,21 +240,38 @@ int nks_profile_enable(int enable) {
     });
 }
 
+// per-launch durations of one record (ms); synchronises on each event
+static std::vector<double> prof_durations(const char *name) {
+    std::vector<double> out;
+    auto it = g_prof.find(name);
+    if (it == g_prof.end()) return out;
+    for (auto &p : it->second.ev) {
+        HIPC(hipEventSynchronize(p.second));
+        float ms = 0.f;
+        HIPC(hipEventElapsedTime(&ms, p.first, p.second));
+        out.push_back(ms);
+    }
+    return out;
+}
+
 int nks_profile_query(const char *name, int *count, double *total_ms) {
     return guard([&] {
         if (!name || !count || !total_ms) fail(NKS_EINVAL, "bad arguments");
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        *count = 0;
+        std::vector<double> d = prof_durations(name);
+        *count = (int)d.size();
         *total_ms = 0.0;
-        auto it = g_prof.find(name);
-        if (it == g_prof.end()) return;
-        for (auto &p : it->second.ev) {
-            HIPC(hipEventSynchronize(p.second));
-            float ms = 0.f;
-            HIPC(hipEventElapsedTime(&ms, p.first, p.second));
-            *total_ms += ms;
-            ++*count;
-        }
+        for (double x : d) *total_ms += x;
+    });
+}
+
+int nks_profile_durations(const char *name, double *ms, int cap, int *count) {
+    return guard([&] {
+        if (!name || !count || cap < 0 || (cap > 0 && !ms)) fail(NKS_EINVAL, "bad arguments");
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        std::vector<double> d = prof_durations(name);
+        *count = (int)d.size();
+        for (int i = 0; i < cap && i < (int)d.size(); ++i) ms[i] = d[i];
     });
 }
 const char *nks_version(void) { return "libnks 0.1 (gfx950)"; }
@@ -484,7 +513,7 @@ static void check_ras_desc(const nks_ras_desc *d) {
         if (d->overlap[std::min(l, 7)] < 0) fail(NKS_EINVAL, "negative overlap");
     if (d->variant < 0 || d->variant > 2 || d->interp_order < 1 || d->interp_order > 3 || d->cycle < 0 ||
         d->cycle > 4 || d->mu < 0 || d->nu < 0 || d->precision < 0 || d->precision > 2 ||
-        d->coarse_restart < 1 || d->coarse_maxit < 1)
+        d->coarse_restart < 1 || d->coarse_maxit < 1 || d->tx < 0 || d->ty < 0 || d->tz < 0)
         fail(NKS_EINVAL, "bad preconditioner option");
 }
 
@@ -703,6 +732,23 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
                 launch_flux(g, p, dt, order, nullptr, W.J->op.coef.p);   // props at p are current
             }
             HIPC(hipStreamSynchronize(s));
+            // rounding floor: ||F|| <= u || |J| |p| || means p solves F = 0 as
+            // well as F can be evaluated in binary64
+            if (nd->floor_test) {
+                launch_spmv_abs(W.J->op, p, W.Js.p, s);
+                std::vector<double> fl(B);
+                norms(W.Js.p, fl);
+                bool changed = false, left = false;
+                for (int b = 0; b < B; ++b) {
+                    if (act[b] && hn[b] <= std::ldexp(fl[b], -53)) {
+                        act[b] = 0;
+                        changed = true;
+                    }
+                    left |= act[b] != 0;
+                }
+                if (!left) break;
+                if (changed) HIPC(hipMemcpyAsync(W.mask.p, act.data(), 4 * B, hipMemcpyHostToDevice, s));
+            }
             double t2 = now();
             S.t_jacobian += t2 - t1;
             W.M->factor();
@@ -732,6 +778,16 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             if (k < 64) S.lits[k] = lits;
             double t4 = now();
             S.t_gmres += t4 - t3;
+            // relative step test on the full Newton step: a step this small is
+            // taken as it is (lambda = 1, no decrease test, since at the
+            // rounding floor ||F|| cannot decrease) and the reservoir stops
+            std::vector<double> snorm(B, 0.0), xnorm(B, 0.0);
+            std::vector<int> small(B, 0);
+            if (nd->stol > 0.0) {
+                norms(W.s.p, snorm);
+                norms(p, xnorm);
+                for (int b = 0; b < B; ++b) small[b] = act[b] && snorm[b] <= nd->stol * xnorm[b];
+            }
             // slope of f = ||F||^2/2 along s: F^T J s
             launch_spmv(W.J->op, W.s.p, W.Js.p, nullptr, nullptr, s);
             {
@@ -763,7 +819,7 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
                     if (acc[b]) continue;
                     const double fx = 0.5 * hn[b] * hn[b];
                     const bool bad = flags[b] || !std::isfinite(ht[b]);
-                    if (!bad && ht[b] <= (1.0 - nd->alpha * lam[b]) * hn[b]) {
+                    if (!bad && ((small[b] && bt == 0) || ht[b] <= (1.0 - nd->alpha * lam[b]) * hn[b])) {
                         acc[b] = 1;
                         continue;
                     }
@@ -809,16 +865,12 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             // accept: p, F <- trial values on the active reservoirs
             k_copy_mask<<<nblk(N, 256), 256, 0, s>>>(g.sp.blk.p, B, N, W.pt.p, p, W.mask.p);
             k_copy_mask<<<nblk(N, 256), 256, 0, s>>>(g.sp.blk.p, B, N, W.Ft.p, W.F.p, W.mask.p);
-            std::vector<double> snorm(B, 0.0), xnorm(B, 0.0);
-            if (nd->stol > 0.0) {
-                norms(W.s.p, snorm);
-                norms(p, xnorm);
-            }
+            if (nd->stol > 0.0) norms(p, xnorm);
             double fmax = 0.0;
             for (int b = 0; b < B; ++b) {
                 if (act[b]) {
                     hn[b] = ht[b];
-                    if (hn[b] <= stop[b]) act[b] = 0;
+                    if (hn[b] <= stop[b] || (small[b] && lam[b] == 1.0)) act[b] = 0;
                     if (nd->stol > 0.0 && lam[b] * snorm[b] <= nd->stol * xnorm[b]) act[b] = 0;
                 }
                 fmax = std::max(fmax, hn[b]);

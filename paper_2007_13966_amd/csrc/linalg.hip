@@ -74,6 +74,24 @@ __global__ void k_spmv(SpmvArgs a) {
     a.y[i] = a.b ? a.b[i] - s : s;
 }
 
+// y = |A| |x| (the componentwise magnitude of the product)
+__global__ void k_spmv_abs(SpmvArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    const int bi = find_blk(a.blk, a.B, i);
+    const Blk k = a.blk[bi];
+    const int l = i - k.off;
+    const int x = l % k.nx, y = (l / k.nx) % k.ny, z = l / (k.nx * k.ny);
+    double s = 0.0;
+    for (int q = 0; q < a.K; ++q) {
+        const int dx = a.off[3 * q], dy = a.off[3 * q + 1], dz = a.off[3 * q + 2];
+        const int xx = x + dx, yy = y + dy, zz = z + dz;
+        if (xx < 0 || xx >= k.nx || yy < 0 || yy >= k.ny || zz < 0 || zz >= k.nz) continue;
+        s += fabs(a.coef[(size_t)q * a.N + i]) * fabs(a.x[i + dx + k.nx * (dy + k.ny * dz)]);
+    }
+    a.y[i] = s;
+}
+
 // y = A^T x: y_i = sum_q A[opp(q)][i + off_q] x[i + off_q]
 __global__ void k_spmv_t(SpmvArgs a, const int *opp) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -111,8 +129,13 @@ static SpmvArgs spmv_args(const Op &A, const double *x, double *y, const double 
 void launch_spmv(const Op &A, const double *x, double *y, const double *b, const int *mask,
                  hipStream_t s) {
     SpmvArgs a = spmv_args(A, x, y, b, mask);
-    ProfScope ps("spmv", s, A.st.K <= 7 ? 0 : 1);
-    k_spmv<<<nblk(a.N, 256), 256, 0, s>>>(a);
+    launch_timed("spmv", A.st.K <= 7 ? 0 : 1, k_spmv, dim3(nblk(a.N, 256)), dim3(256), 0, s, a);
+    KCHECK();
+}
+
+void launch_spmv_abs(const Op &A, const double *x, double *y, hipStream_t s) {
+    SpmvArgs a = spmv_args(A, x, y, nullptr, nullptr);
+    k_spmv_abs<<<nblk(a.N, 256), 256, 0, s>>>(a);
     KCHECK();
 }
 

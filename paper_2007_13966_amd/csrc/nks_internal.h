@@ -2,6 +2,7 @@
 // buffers; kernels receive plain pointers and small POD descriptors.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -164,6 +165,7 @@ struct Reducer {
 void launch_spmv(const Op &A, const double *x, double *y, const double *b, const int *mask,
                  hipStream_t s);             // y = A x, or y = b - A x when b != nullptr
 void launch_spmv_t(const Op &A, const double *x, double *y, const int *opp, hipStream_t s);
+void launch_spmv_abs(const Op &A, const double *x, double *y, hipStream_t s);
 void launch_axpby(const Space &sp, double a, const double *x, double b, double *y,
                   const int *mask, hipStream_t s);   // y = a x + b y
 void launch_copy_scale_blk(const Space &sp, const double *x, const double *scale, int col,
@@ -181,6 +183,8 @@ void set_lds(const void *fn, size_t bytes);
 
 // Event timing of named launches (active only after nks_profile_enable(1)).
 bool prof_on();
+// Events around a span of stream work (several kernels); includes any idle
+// time between them.
 struct ProfScope {
     hipEvent_t a = nullptr, b = nullptr;
     hipStream_t s = nullptr;
@@ -189,5 +193,19 @@ struct ProfScope {
     ProfScope(const char *name, hipStream_t s, int level = -1);
     ~ProfScope();
 };
+
+// An event pair to be bound to one kernel dispatch; false when profiling is
+// off or the stream is being captured.
+bool prof_pair(const char *name, int level, hipStream_t s, hipEvent_t *a, hipEvent_t *b);
+
+// Launch one kernel; while profiling, the events ride on the dispatch packet
+// itself, so the recorded time is the kernel's execution alone.
+template <typename... KArgs, typename... Args>
+inline void launch_timed(const char *name, int level, void (*kernel)(KArgs...), dim3 grid, dim3 block,
+                         size_t sh, hipStream_t s, Args... args) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (!prof_pair(name, level, s, &a, &b)) a = b = nullptr;
+    hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)sh, s, a, b, 0u, static_cast<KArgs>(args)...);
+}
 
 }  // namespace nks

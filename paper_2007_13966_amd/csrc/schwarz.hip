@@ -19,6 +19,7 @@
 // hyperplanes are staged through LDS while the solution tile of the
 // subdomain stays resident in LDS for both sweeps.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <map>
 #include <set>
@@ -78,8 +79,8 @@ static void wavefront(const Stencil &st, int &lb, int &lc) {
     }
 }
 
-static void build_partition(Level &L, const nks_ras_desc &d, int delta, Alloc *al, hipStream_t s,
-                            TileDims &geo) {
+static void build_partition(Level &L, const std::vector<std::array<int, 3>> &boxes, int delta, Alloc *al,
+                            hipStream_t s, TileDims &geo) {
     const Space &S = *L.spp;
     const Stencil &st = L.A->st;
     wavefront(st, L.lb, L.lc);
@@ -97,7 +98,7 @@ static void build_partition(Level &L, const nks_ras_desc &d, int delta, Alloc *a
     int mex = 1, mey = 1, mez = 1;
     for (int b = 0; b < S.B; ++b) {
         const Blk &k = S.hblk[b];
-        const int P[3] = {std::min(d.px, k.nx), std::min(d.py, k.ny), std::min(d.pz, k.nz)};
+        const int P[3] = {std::min(boxes[b][0], k.nx), std::min(boxes[b][1], k.ny), std::min(boxes[b][2], k.nz)};
         const int n[3] = {k.nx, k.ny, k.nz};
         L.hpart.push_back({P[0], P[1], P[2], (int)L.hsub.size()});
         for (int qz = 0; qz < P[2]; ++qz)
@@ -1120,10 +1121,18 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
         F.rap_slot.upload(al, slot, s);
         F.rap_R = Rc;
     }
+    // the same box grid on every level: box counts per reservoir from the finest level
+    std::vector<std::array<int, 3>> boxes;
+    for (const Blk &k : lev[0]->spp->hblk) {
+        const int t[3] = {d.tx, d.ty, d.tz}, n[3] = {k.nx, k.ny, k.nz}, p[3] = {d.px, d.py, d.pz};
+        std::array<int, 3> bx;
+        for (int a = 0; a < 3; ++a) bx[a] = t[a] > 0 ? (n[a] + t[a] - 1) / t[a] : p[a];
+        boxes.push_back(bx);
+    }
     for (int l = 0; l < L; ++l) {
         Level &V = *lev[l];
         TileDims geo;
-        build_partition(V, d, d.overlap[std::min(l, 7)], al, s, geo);
+        build_partition(V, boxes, d.overlap[std::min(l, 7)], al, s, geo);
         const size_t NE = V.next_total, K = V.A->st.K;
         V.w64.alloc(al, K * NE);
         if (d.precision == NKS_FP64) {
@@ -1161,9 +1170,8 @@ void Ras::factor() {
             const int bs = 64;
             const size_t sh = (size_t)bs * Kc * sizeof(double);
             set_lds((const void *)k_rap, sh);
-            ProfScope ps("rap", s, l);
-            k_rap<<<nblk(V.spp->N, bs), bs, sh, s>>>(a, F.A->coef.p, F.A->st.K, F.A->st.doff.p, V.own.coef.p, Kc,
-                                                    F.rap_slot.p, F.rap_R);
+            launch_timed("rap", l, k_rap, dim3(nblk(V.spp->N, bs)), dim3(bs), sh, s, a, F.A->coef.p, F.A->st.K,
+                         F.A->st.doff.p, V.own.coef.p, Kc, F.rap_slot.p, F.rap_R);
             KCHECK();
         }
         const TileDims &td = tiles_[l];
@@ -1195,8 +1203,7 @@ void Ras::factor() {
         const int bs = 64;
         const size_t sh = (size_t)bs * fa.K * sizeof(double) + sizeof(int) * (size_t)(V.max_nlev + 1);
         set_lds((const void *)k_ilu_factor, sh);
-        ProfScope ps("ilu_factor", s, l);
-        k_ilu_factor<<<V.nsub, bs, sh, s>>>(fa);
+        launch_timed("ilu_factor", l, k_ilu_factor, dim3(V.nsub), dim3(bs), sh, s, fa);
         KCHECK();
         const int NE = V.next_total;
         const int *perm = V.rows2d ? V.lexg.p : nullptr;
@@ -1253,14 +1260,10 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     const size_t n = V.max_next;
     const size_t sh = al16(sizeof(VT) * n) + al16(sizeof(FT) * NSP * n) + al16(sizeof(DT) * n);
     if (sh > (size_t)M.lds_bytes) fail(NKS_EINVAL, "2D subdomain of %zu cells does not fit in LDS", n);
-    const void *fn = V.box ? (const void *)k_ras_rows<FT, VT, DT, 1> : (const void *)k_ras_rows<FT, VT, DT, 0>;
-    set_lds(fn, sh);
-    {
-        ProfScope ps("ras_apply", M.g->s, level_index(M, V));
-        if (V.box) k_ras_rows<FT, VT, DT, 1><<<V.nsub, 256, sh, M.g->s>>>(a);
-        else k_ras_rows<FT, VT, DT, 0><<<V.nsub, 256, sh, M.g->s>>>(a);
-        KCHECK();
-    }
+    void (*fn)(RowsArgs) = V.box ? k_ras_rows<FT, VT, DT, 1> : k_ras_rows<FT, VT, DT, 0>;
+    set_lds((const void *)fn, sh);
+    launch_timed("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(256), sh, M.g->s, a);
+    KCHECK();
     if (M.d.variant != NKS_LEFT_RAS) {
         k_ras_gather<<<nblk(V.spp->N, 256), 256, 0, M.g->s>>>(V.spp->blk.p, V.spp->B, V.spp->N, V.part.p,
                                                               V.sub.p, V.zext.p, z, mask, accumulate ? 1 : 0);
@@ -1317,8 +1320,7 @@ static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, 
     set_lds(fn, sh);
     const int bs = td.PZ == 1 ? 64 : 256;
     {
-        ProfScope ps("ras_apply", M.g->s, level_index(M, V));
-        k_ras_apply<FT, VT, DT><<<V.nsub, bs, sh, M.g->s>>>(a);
+        launch_timed("ras_apply", level_index(M, V), k_ras_apply<FT, VT, DT>, dim3(V.nsub), dim3(bs), sh, M.g->s, a);
         KCHECK();
     }
     if (M.d.variant != NKS_LEFT_RAS) {

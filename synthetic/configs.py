@@ -72,6 +72,7 @@ class SolverSettings:
     py: int = 4
     pz: int = 1
     overlap: Tuple[int, ...] = (1,)      # finest level first
+    tile: Tuple[int, int, int] = (0, 0, 0)   # > 0: box edge in cells (boxes per reservoir = ceil(n/t))
     levels: int = 1
     interp_order: int = 2                # 1 nearest, 2 bilinear, 3 bicubic
     cycle: str = "vcycle"                # vcycle | left_kaskade | right_kaskade | additive | coarse_only
@@ -91,7 +92,8 @@ class SolverSettings:
     alpha: float = 1e-4
     max_newton: int = 50
     max_backtracks: int = 20
-    stol: float = 1e-8                   # relative Newton step test (PETSc default)
+    stol: float = 0.0                    # relative Newton step test (PETSc's; 0 = off)
+    floor_test: bool = True              # stop at the FP64 rounding floor u || |J| |X| ||
     precision: str = "fp64"              # fp64 | fp32 | bf16
     flexible: Optional[bool] = None      # None: FGMRES iff levels > 1 or precision != fp64
 
@@ -212,7 +214,8 @@ def case_c4(nres=64, nmin=64, nmax=256, tile=16, overlap=1):
         wc, wr = _wells([_lin(n, n, a[0], a[1]), _lin(n, n, c[0], c[1])], [1e-3, -1e-3])
         probs.append(Problem(n, n, 1, 10.0, 10.0, 10.0, k.copy(), k.copy(), k.copy(),
                              np.full(n * n, 0.2), wc, wr))
-    s = SolverSettings(px=tile, py=tile, pz=1, overlap=(overlap, 1), levels=2, precision="fp32")
+    s = SolverSettings(px=1, py=1, pz=1, tile=(tile, tile, 0), overlap=(overlap, 1), levels=2,
+                       precision="fp32")
     return Case(f"c4_batch{nres}_2d_fp32prec", probs, 5 * DAY, 3, s, case_c4.__doc__)
 
 

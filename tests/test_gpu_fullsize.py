@@ -1,0 +1,96 @@
+"""GPU parity at the benchmark workloads' full sizes, in the launch
+configuration the benchmark times: one implicit step on the GPU through the
+libnks C ABI against the FP64 CPU oracle, reservoir by reservoir (a sample of
+the batch where the whole batch would take the oracle minutes).
+
+The bar: the pressure change of the step agrees to 1e-6 relative, and the
+GPU's pressure is at least as converged, judged by the oracle's own residual:
+||F(p_gpu)|| <= max(1e-8 ||F(p_n)||, 2 ||F(p_oracle)||).  The second term
+applies where binary64 cannot resolve 1e-8 of the initial residual: both sides
+then stop at the rounding floor u || |J| |p| ||."""
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic as S
+
+pytestmark = pytest.mark.gpu
+PARITY = dict(eps_r=1e-8, eps_a=1e-6)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def nks():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2007_13966_amd as P
+    P.lib()
+    return P
+
+
+def _gpu_first_step(nks, case):
+    g = nks.Grid(case.problems)
+    p0 = g.initial_pressure()
+    p = p0.clone()
+    st = g.newton_step(p, p0, p0, case.dt, 1, case.solver)
+    return g.split(p0), g.split(p), st
+
+
+def _check(orc, case, k, p0g, pg):
+    rec = case.problems[k]
+    prob = orc.Problem(rec)
+    q0 = prob.initial_pressure()
+    assert np.max(np.abs(p0g - q0)) <= 1e-9 * np.max(np.abs(q0)), "initial state"
+    q, st = orc.newton_step(prob, case.solver, q0, q0, q0, case.dt, 1)
+    assert st["status"] == 0, st
+    dq, dg = q - q0, pg - q0
+    err = np.linalg.norm(dg - dq) / np.linalg.norm(dq)
+    f0 = np.linalg.norm(prob.residual(q0, q0, q0, case.dt, 1))
+    fg = np.linalg.norm(prob.residual(pg, q0, q0, case.dt, 1))
+    fo = np.linalg.norm(prob.residual(q, q0, q0, case.dt, 1))
+    say(f"  reservoir {k} ({rec.nx}x{rec.ny}x{rec.nz}): dp error {err:.2e}, ||F|| gpu {fg:.3e} "
+        f"oracle {fo:.3e} initial {f0:.3e}")
+    assert err <= 1e-6
+    assert fg <= max(1e-8 * f0, 2.0 * fo, case.solver.eps_a)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c2_first_step(nks, orc, precision):
+    case = S.with_solver(S.case_c2(), precision=precision, **PARITY)
+    say("c2", precision)
+    p0, p, st = _gpu_first_step(nks, case)
+    say("  gpu", st["newton_its"], "newton,", st["linear_its"], "gmres")
+    _check(orc, case, 0, p0[0], p[0])
+
+
+def test_c3_first_step(nks, orc):
+    case = S.with_solver(S.case_c3(), **PARITY)
+    say("c3", case.solver.precision)
+    p0, p, st = _gpu_first_step(nks, case)
+    say("  gpu", st["newton_its"], "newton,", st["linear_its"], "gmres")
+    _check(orc, case, 0, p0[0], p[0])
+
+
+def test_c4_batch_first_step(nks, orc):
+    case = S.with_solver(S.case_c4(), **PARITY)
+    say("c4", len(case.problems), "reservoirs,", case.solver.precision)
+    p0, p, st = _gpu_first_step(nks, case)
+    say("  gpu", st["newton_its"], "newton,", st["linear_its"], "gmres")
+    sizes = [r.N for r in case.problems]
+    sample = sorted({0, 18, int(np.argmax(sizes)), int(np.argmin(sizes)), len(sizes) - 1})
+    for k in sample:
+        _check(orc, case, k, p0[k], p[k])
+
+
+def test_c5_first_step(nks, orc):
+    case = S.with_solver(S.case_c5(), **PARITY)
+    say("c5")
+    p0, p, st = _gpu_first_step(nks, case)
+    say("  gpu", st["newton_its"], "newton,", st["linear_its"], "gmres")
+    _check(orc, case, 0, p0[0], p[0])

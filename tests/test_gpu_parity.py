@@ -303,6 +303,39 @@ def test_batched_equals_unbatched(nks, orc):
             assert np.array_equal(part, hist_s[n]), (k, n)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 2e-5)])
+def test_batched_uneven_tile_apply_parity(nks, orc, precision, tol):
+    # uneven reservoirs in one batch, boxes set by a tile edge, two-level V-cycle
+    # with a fixed number of coarse iterations; each reservoir against its own oracle
+    recs = [S.small_case(nx=n, ny=m, seed=s, rate=2e-3).problems[0]
+            for n, m, s in [(37, 29, 1), (64, 50, 2), (20, 20, 3), (9, 33, 4)]]
+    settings = S.SolverSettings(px=1, py=1, tile=(12, 12, 0), levels=2, overlap=(2, 1),
+                                coarse_rtol=0.0, coarse_maxit=5, precision=precision)
+    settings64 = S.SolverSettings(px=1, py=1, tile=(12, 12, 0), levels=2, overlap=(2, 1),
+                                  coarse_rtol=0.0, coarse_maxit=5)
+    g = nks.Grid(recs)
+    ps, pns, Js, rs = [], [], [], []
+    for k, rec in enumerate(recs):
+        op = orc.Problem(rec)
+        p, pn, _ = _state(op, 20 + k)
+        ps.append(p)
+        pns.append(pn)
+        rs.append(np.cos(np.arange(op.N) * (k + 1)))
+    p = g.from_numpy(np.concatenate(ps))
+    pn = g.from_numpy(np.concatenate(pns))
+    J = g.jacobian(p, pn, pn, S.DAY, 1)
+    M = nks.Ras(J, settings)
+    zg = M.apply(g.from_numpy(np.concatenate(rs))).cpu().numpy()
+    for k, rec in enumerate(recs):
+        op = orc.Problem(rec)
+        Jo = op.jacobian(ps[k], pns[k], pns[k], S.DAY, 1)
+        zo = orc.Multilevel(rec, Jo, settings64).apply(rs[k])
+        part = zg[g.offsets[k]:g.offsets[k + 1]]
+        err = np.max(np.abs(part - zo)) / np.max(np.abs(zo))
+        say("reservoir", k, precision, "relative error", err)
+        assert err <= tol, (k, err)
+
+
 def test_determinism(nks, orc):
     case = S.small_case(nx=40, ny=40, px=4, py=4, levels=2, overlap=(1, 1), nsteps=1)
     h1, _, _ = _run_steps(nks, orc, case, 1)

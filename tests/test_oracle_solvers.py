@@ -134,6 +134,16 @@ def test_schwarz_exact_subsolves_match_definition(orc, variant, dims, P, delta):
     assert np.allclose(M, Md, rtol=1e-10, atol=1e-10 * np.abs(Md).max())
 
 
+def test_tile_option_sets_box_counts(orc):
+    # a box edge t gives ceil(n/t) boxes per direction, split as for an explicit count
+    dims = (11, 7, 1)
+    case, prob, J = _jac(orc, nx=dims[0], ny=dims[1], tile=(4, 3, 0), overlap=(1,), subsolve="lu")
+    mg = orc.Multilevel(prob.rec, J, case.solver)
+    M = _apply_dense(mg.apply, J.n)
+    Md = dense_schwarz(J.dense(), dims, (3, 3, 1), 1, "left_ras")
+    assert np.allclose(M, Md, rtol=1e-10, atol=1e-10 * np.abs(Md).max())
+
+
 def test_zero_overlap_is_block_jacobi(orc):
     # delta = 0: AS, left-RAS and right-RAS all reduce to block Jacobi
     ops = []
@@ -335,3 +345,27 @@ def test_newton_quadratic_convergence(orc):
     assert len(f) >= 4
     order = np.log(f[-1] / f[-2]) / np.log(f[-2] / f[-3])
     assert 1.8 < order < 2.6, f
+
+
+def test_newton_stops_at_rounding_floor(orc):
+    # eps_r far below what binary64 residuals can reach: with neither the
+    # rounding-floor test nor the relative step test the line search must
+    # fail at the floor; with either one Newton stops, and the pressure agrees
+    # with a solve stopped by the ordinary test at a reachable tolerance
+    case = S.small_case(nx=16, ny=12, seed=8, sigma=2.0, rate=2e-3, eps_r=1e-15, eps_a=0.0,
+                        eta_r=1e-12, eta_a=0.0)
+    prob = orc.Problem(case.problems[0])
+    p0 = prob.initial_pressure()
+    run = lambda **kw: orc.newton_step(prob, S.with_solver(case, **kw).solver, p0, p0, p0, case.dt, 1)
+    _, st_off = run(floor_test=False, stol=0.0)
+    assert st_off["status"] != 0
+    ref, st_ref = run(eps_r=1e-8, floor_test=False, stol=0.0)
+    assert st_ref["status"] == 0
+    for kw in (dict(floor_test=True, stol=0.0), dict(floor_test=False, stol=1e-8)):
+        p, st = run(**kw)
+        assert st["status"] == 0 and st["newton_its"] <= 6, kw
+        assert np.max(np.abs(p - ref)) <= 1e-9 * np.max(np.abs(ref - p0)), kw
+    # the floor test never fires while the residual is well above u |J| |p|
+    _, st_tight = run(eps_r=1e-6, floor_test=True)
+    _, st_plain = run(eps_r=1e-6, floor_test=False)
+    assert st_tight["newton_its"] == st_plain["newton_its"]
