@@ -25,6 +25,8 @@ sys.path.insert(0, HERE)
 
 METRIC = "time/implicit step + ras_apply GB/s, mixed-prec vs FP64 at rel.res 1e-6"
 HBM_PEAK_GBS = 8000.0
+WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128",
+             "batch64": "case_batch64", "3d96": "case_3d_96_adjoint"}
 
 # HBM bytes moved per active fine-level launch of the FP64 2D sweep kernel on
 # the 512x512 workload, from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0 and
@@ -32,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # 256 MiB).  Valid only for the kernel source it was taken on: any edit of that
 # file drops it to null until the counters are taken again.
 PMC_TRAFFIC = {
-    "workload": "c2_512x512_twolevel_fp64",
+    "workload": "2d_512x512_twolevel_fp64",
     "source": "paper_2007_13966_amd/csrc/schwarz.hip",
     "sha1": "3a28ec9724619c19ce588794722edb34230c8242",
     "fetch_kib": 8873.10, "fetch_scale": 2.0,
@@ -166,7 +168,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="2d512", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
@@ -194,8 +196,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 5}))
         return
-    case = {"c1": S.case_c1, "c2": S.case_c2, "c3": S.case_c3, "c4": S.case_c4}[args.workload]()
-    s64 = S.with_solver(case, precision="fp64").solver if args.workload != "c2" else case.solver
+    case = getattr(S, WORKLOADS[args.workload])()
+    s64 = S.with_solver(case, precision="fp64").solver
     log(f"workload {case.name}: {sum(r.N for r in case.problems)} cells")
     nbytes, nexts = apply_bytes(case.problems, s64, "fp64")
     r64 = run_gpu(P, case, s64, args.warmup, args.steps)
@@ -272,7 +274,7 @@ def main():
             "ras_apply_l0_frac": (a32 / HBM_PEAK_GBS) if a32 else None,
         }
         log(f"fp32 preconditioner: {sec32:.4f} s/step, dp error vs fp64 {err:.2e}")
-    if not args.no_cpu_baseline and args.workload == "c2":
+    if not args.no_cpu_baseline and args.workload == "2d512":
         n = args.cpu_steps
         v = cpu_baseline(case, n)
         out["cpu_baseline"] = {"value": v, "unit": "s/implicit step", "cores": 1, "kind": "oracle",

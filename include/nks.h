@@ -91,17 +91,18 @@ int nks_grid_info(const nks_grid *g, int *ncells, int *nres, int *offsets);
  * column, p_{k+1} - p_k = (rho_k + rho_{k+1})/2 g dz.  p: device, out. */
 int nks_hydrostatic_init(nks_grid *g, double p_top, double *p);
 
-/* Residual of eq. gover_sys integrated over each cell, in conservative form:
+/* Residual of the pressure form of the governing equation (Section 2)
+ * integrated over each cell, in conservative form:
  *   F_i = (V phi_i / dt) Acc_i + sum_j T_ij lambda_up dPhi_ij - Q_i R T / W
- * with m = p/Z (Z the largest real root of eq. PR), lambda = m/mu from the
+ * with m = p/Z (Z the largest real root of the PR cubic), lambda = m/mu from the
  * upwind cell of dPhi_ij = (p_i - p_j) - (rho_i + rho_j)/2 g (h_i - h_j),
- * Acc = m - m^n (bdf_order 1, eq. implicit-method-bdf1) or
- * (3m - 4m^n + m^{n-1})/2 (bdf_order 2, eq. implicit-method-bdf2).
+ * Acc = m - m^n (bdf_order 1, the BDF1 scheme of Section 2) or
+ * (3m - 4m^n + m^{n-1})/2 (bdf_order 2, the BDF2 scheme of Section 2).
  * p, p_n, p_nm1 (ignored for order 1), F: device arrays.  Asynchronous. */
 int nks_residual(nks_grid *g, const double *p, const double *p_n, const double *p_nm1,
                  double dt, int bdf_order, double *F);
 
-/* Sparse Jacobian dF/dp of nks_residual (Section 3, eq. jacobian1), stored
+/* Sparse Jacobian dF/dp of nks_residual (Section 3, the Jacobian entries), stored
  * as a structured stencil (5 points in 2D, 7 in 3D), FP64.  Writes F too
  * when F != NULL.  J must come from nks_matrix_create on the same grid. */
 int nks_matrix_create(nks_grid *g, nks_matrix **out);
@@ -125,18 +126,18 @@ int nks_residual_dlogk_transpose_apply(nks_grid *g, const double *p, const doubl
  * floor(n/P) + (q < n mod P) cells, extended by `overlap` and clipped at the
  * domain boundary; the same box grid on every level.  Subdomain solve:
  * ILU(0) of R_i^delta A R_i^delta^T in local lexicographic order.
- * Levels: ratio 2 per direction (nz = 1 stays 1), interpolation of
- * eq. inter-frist (1), inter-second (2) or inter-third (3), restriction
+ * Levels: ratio 2 per direction (nz = 1 stays 1), the first- (1),
+ * second- (2) or third-order (3) interpolation of Section 3.2, restriction
  * P^T, Galerkin coarse operators P^T A P; coarsest level solved by GMRES
  * with the one-level preconditioner to coarse_rtol (Remark 2). */
-#define NKS_LEFT_RAS 0           /* eq. as-left  (default) */
-#define NKS_AS 1                 /* eq. as-class */
-#define NKS_RIGHT_RAS 2          /* eq. as-right */
-#define NKS_VCYCLE 0             /* eq. v-cycle with mu/nu smoothing steps */
-#define NKS_LEFT_KASKADE 1       /* eq. left-Kas  */
-#define NKS_RIGHT_KASKADE 2      /* eq. right-Kas */
-#define NKS_ADDITIVE 3           /* eq. two-additive */
-#define NKS_COARSE_ONLY 4        /* eq. coarse-level */
+#define NKS_LEFT_RAS 0           /* Section 3.1 left-RAS (default) */
+#define NKS_AS 1                 /* Section 3.1 classical AS */
+#define NKS_RIGHT_RAS 2          /* Section 3.1 right-RAS */
+#define NKS_VCYCLE 0             /* Section 3.2 V-cycle, mu/nu smoothing steps */
+#define NKS_LEFT_KASKADE 1       /* Section 3.2 left Kaskade */
+#define NKS_RIGHT_KASKADE 2      /* Section 3.2 right Kaskade */
+#define NKS_ADDITIVE 3           /* Section 3.2 additive two-level */
+#define NKS_COARSE_ONLY 4        /* Section 3.2 coarse-only */
 #define NKS_FP64 0               /* factors and subdomain sweeps in FP64 */
 #define NKS_FP32 1               /* FP32 factors, FP32 sweeps */
 #define NKS_BF16 2               /* BF16 off-diagonal factors, FP32 1/diag and sweeps */
@@ -182,7 +183,7 @@ int nks_ras_restrict(nks_ras *M, int level, const double *r_fine, double *r_coar
 int nks_ras_prolong_add(nks_ras *M, int level, const double *e_coarse, double *z_fine);
 
 /* Right-preconditioned GMRES(restart) / FGMRES(restart) (Section 3,
- * eq. jacobian; Remark 2): x holds the initial guess (zero it for x0 = 0);
+ * the Jacobian system; Remark 2): x holds the initial guess (zero it for x0 = 0);
  * stops per reservoir when ||b - J x|| <= max(rtol ||b||, atol).
  * Orthogonalisation: classical Gram-Schmidt with one reorthogonalisation,
  * FP64.  transpose != 0 solves J^T x = b with M^{-T} (one-level only). */

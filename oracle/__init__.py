@@ -67,6 +67,9 @@ def lib():
             [C.c_double] * 7 + [C.c_int, C.c_double]
         L.orc_problem_free.argtypes = [C.c_void_p]
         L.orc_pr_params.argtypes = [C.c_double] * 5 + [_D] * 3
+        L.orc_acentric_terms.argtypes = [C.c_double, _D, _D]
+        L.orc_acentric.argtypes = [C.c_double] * 3
+        L.orc_acentric.restype = C.c_double
         L.orc_pr_z.argtypes = [C.c_double] * 5 + [_D, _D]
         L.orc_pr_z.restype = C.c_int
         L.orc_pr_eval.argtypes = [C.c_void_p, C.c_int, _D, _D, _D, _D, _D]
@@ -116,6 +119,16 @@ def _f64(a):
 
 def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def acentric_terms(Tr):
+    f0, f1 = C.c_double(), C.c_double()
+    lib().orc_acentric_terms(Tr, C.byref(f0), C.byref(f1))
+    return f0.value, f1.value
+
+
+def acentric(pc, Tc, Tb):
+    return lib().orc_acentric(pc, Tc, Tb)
 
 
 def pr_params(fluid):

@@ -2,20 +2,19 @@
  * Plain FP64 CPU oracle (test infrastructure only; see nks_oracle.h).
  *
  * Written from the paper's text in the order it presents the method:
- *   Section 2: Peng-Robinson density (eqs. density, PR, attrfactor, m(w)),
- *              pressure-form governing equation (eq. gover_sys) and dZ/dp,
- *              cell-centred finite differences (Remark 1), BDF1/BDF2
- *              (eqs. implicit-method-bdf1 / -bdf2).
- *   Section 3: inexact Newton with cubic line search (eq. newton_iterate and
- *              the sufficient-decrease test), right-preconditioned GMRES
- *              (eq. jacobian), stopping tests (eqs. linear_stop, nonlinear_stop),
+ *   Section 2: Peng-Robinson density (rho = cW, c = p/(ZRT), the Z cubic,
+ *              the criticality relations for a(T) and b, m(w)), the pressure
+ *              form of the governing equation and its dZ/dp, cell-centred
+ *              finite differences (Remark 1), the BDF1 and BDF2 schemes.
+ *   Section 3: inexact Newton with cubic line search (the Newton update and
+ *              the sufficient-decrease test), right-preconditioned GMRES on
+ *              the Jacobian system, the linear and nonlinear stopping tests,
  *              restriction matrices R_i^delta / R_i^0, classical AS, left-RAS,
- *              right-RAS (eqs. as-class, as-left, as-right), the multigrid
- *              V-cycle (Algorithm 1, eqs. two_level_preconditioner, v-cycle),
- *              Kaskade / additive / coarse-only compositions (eqs. left-Kas,
- *              right-Kas, two-additive, coarse-level), the iterative coarse
- *              solve with FGMRES outside (Remark 2) and the interpolation
- *              operators (eqs. inter-frist, inter-second, inter-third).
+ *              right-RAS (Section 3.1), the multigrid V-cycle (Algorithm 1 and
+ *              the two-level preconditioner built from it), the Kaskade,
+ *              additive and coarse-only compositions, the iterative coarse
+ *              solve with FGMRES outside (Remark 2) and the first-, second-
+ *              and third-order interpolation operators (Section 3.2).
  *   Section 4: stopping values and GMRES restart 30.
  *
  * Readings taken where the paper is silent (each also listed in the design
@@ -99,7 +98,7 @@ void orc_problem_free(orc_problem *pr) {
 /* Peng-Robinson equation of state (Section 2)                         */
 /* ------------------------------------------------------------------ */
 
-/* eq. attrfactor with m(w) from its first branch (0 <= w <= 0.491) or the
+/* the criticality relations for a(T) and b (Section 2) with m(w) from its first branch (0 <= w <= 0.491) or the
  * second branch (0.491 <= w <= 2.0). */
 void orc_pr_params(double Tc, double pc, double omega, double T, double R,
                    double *a, double *b, double *m) {
@@ -115,10 +114,26 @@ void orc_pr_params(double Tc, double pc, double omega, double T, double R,
     *m = mm;
 }
 
-/* Largest real root of eq. PR,
+/* Acentric factor from the normal boiling point (Section 2): the reduced
+ * vapour-pressure correlation ln(p_r) = f0(T_r) + w f1(T_r) with the two
+ * polynomials in (1 - T_r) printed there, solved for w at T_r = T_b/T_c where
+ * p = 1 atm. */
+void orc_acentric_terms(double Tr, double *f0, double *f1) {
+    double t = 1.0 - Tr;
+    *f0 = (-5.97616 * t + 1.29874 * pow(t, 1.5) - 0.60394 * pow(t, 2.5) - 1.06841 * pow(t, 5.0)) / Tr;
+    *f1 = (-5.03365 * t + 1.11505 * pow(t, 1.5) - 5.41217 * pow(t, 2.5) - 7.46628 * pow(t, 5.0)) / Tr;
+}
+
+double orc_acentric(double pc, double Tc, double Tb) {
+    double f0, f1;
+    orc_acentric_terms(Tb / Tc, &f0, &f1);
+    return (-log(pc / 101325.0) - f0) / f1;
+}
+
+/* Largest real root of the PR cubic (Section 2),
  *   Z^3 - (1-B) Z^2 + (A - 3B^2 - 2B) Z - (AB - B^2 - B^3) = 0,
  * by Cardano's formula (one real root) or the trigonometric form (three real
- * roots), then dZ/dp from the closed form printed after eq. gover_sys.
+ * roots), then dZ/dp from the closed form printed after the pressure form of the governing equation (Section 2).
  * Returns 0 on success, 1 if the root is non-physical (Z <= B or p <= 0). */
 int orc_pr_z(double a, double b, double T, double R, double p, double *Z, double *dZdp) {
     double RT = R * T;
@@ -163,7 +178,7 @@ int orc_pr_z(double a, double b, double T, double R, double p, double *Z, double
 }
 
 /* scaled density m = p/Z (rho = m W/(R T)) and dm/dp = (p/Z)(1/p - Z'/Z),
- * the coefficient of dp/dt in eq. gover_sys divided by phi */
+ * the coefficient of dp/dt in the pressure form of the governing equation (Section 2) divided by phi */
 static int pr_m(const orc_problem *pr, double p, double *m, double *dm) {
     double Z, dZ;
     int bad = orc_pr_z(pr->a, pr->b, pr->T, pr->R, p, &Z, &dZ);
@@ -237,8 +252,8 @@ static int neighbours(const orc_problem *pr, const double *tx, const double *ty,
     return c;
 }
 
-/* Accumulation term of BDF1 (eq. implicit-method-bdf1) or BDF2
- * (eq. implicit-method-bdf2) in conservative form: returns the bracket
+/* Accumulation term of BDF1 (the BDF1 scheme of Section 2) or BDF2
+ * (the BDF2 scheme of Section 2) in conservative form: returns the bracket
  * multiplying phi V / dt and its derivative with respect to p^{l+1}. */
 static void accumulation(const orc_problem *pr, int order, double p, double pn, double pnm1,
                          double *acc, double *dacc) {
@@ -256,7 +271,7 @@ static void accumulation(const orc_problem *pr, int order, double p, double pn, 
 }
 
 /* F_i = (V phi / dt) Acc_i + sum_j T_ij lambda_up dPhi_ij - Q_i R T / W,
- * the cell integral of eq. gover_sys; dPhi_ij = (p_i - p_j) - rho_avg g (h_i - h_j),
+ * the cell integral of the pressure form of the governing equation (Section 2); dPhi_ij = (p_i - p_j) - rho_avg g (h_i - h_j),
  * lambda = p/(mu Z) taken from the upwind cell of dPhi. */
 void orc_residual(const orc_problem *pr, const double *p, const double *pn, const double *pnm1,
                   double dt, int order, double *F) {
@@ -491,10 +506,10 @@ static csr csr_matmul(const csr *a, const csr *b) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Interpolation operators (Section 3, eqs. inter-frist/-second/-third) */
+/* Interpolation operators (Section 3.2, first/second/third order) */
 /* ------------------------------------------------------------------ */
 
-/* Cubic convolution weight W(s) of eq. inter-third (values at integer s by continuity). */
+/* Cubic convolution weight W(s) of the third-order interpolation of Section 3.2 (values at integer s by continuity). */
 static double keys_w(double s) {
     s = fabs(s);
     if (s < 1.0) return 1.5 * s * s * s - 2.5 * s * s + 1.0;
@@ -520,10 +535,10 @@ void orc_interp_1d(int nf, int order, int *rp, int *ci, double *w) {
         if (nf == 1) {
             cj[0] = 0; cw[0] = 1.0; cnt = 1;
         } else if (order == 1) {
-            /* nearest coarse centroid: the parent cell (eq. inter-frist) */
+            /* nearest coarse centroid: the parent cell (the first-order interpolation of Section 3.2) */
             cj[0] = i / 2; cw[0] = 1.0; cnt = 1;
         } else if (order == 2) {
-            /* eq. inter-second along one direction: linear between the two
+            /* the second-order interpolation of Section 3.2 along one direction: linear between the two
              * coarse centroids that bracket x (virtual ones at spacing 2
              * beyond the ends) */
             double cen_last = ((nf % 2) ? (nf - 0.5) : (nf - 1.0));
@@ -542,7 +557,7 @@ void orc_interp_1d(int nf, int order, int *rp, int *ci, double *w) {
             cj[1] = J0 + 1; cw[1] = (x - c0) / h;
             cnt = 2;
         } else {
-            /* eq. inter-third along one direction: 4 coarse cells J0-1..J0+2
+            /* the third-order interpolation of Section 3.2 along one direction: 4 coarse cells J0-1..J0+2
              * with weights W((x - c_J)/2) (uniform coarse spacing, even nf) */
             int J0 = (int)floor((x - 1.0) / 2.0);
             for (int l = -1; l <= 2; ++l) {
@@ -840,8 +855,8 @@ static void sub_solve(const subdomain *s, int subsolve, const double *r, double 
     else ilu0_solve_t(s->next, s->a.rp, s->a.ci, s->a.v, r, z);
 }
 
-/* z = M^{-1} r for the one-level preconditioner of eq. as-left (left-RAS:
- * sum_i R_i^0^T A_i^{-1} R_i^delta), eq. as-class (AS) or eq. as-right
+/* z = M^{-1} r for the one-level preconditioner of the left-RAS operator of Section 3.1 (left-RAS:
+ * sum_i R_i^0^T A_i^{-1} R_i^delta), the classical AS operator of Section 3.1 (AS) or the right-RAS operator of Section 3.1
  * (right-RAS: sum_i R_i^delta^T A_i^{-1} R_i^0).  trans applies M^{-T}. */
 static void onelevel_apply(const level *lv, const orc_mg_desc *d, const double *r, double *z, int trans) {
     int var = d->variant;
@@ -863,7 +878,7 @@ static void onelevel_apply(const level *lv, const orc_mg_desc *d, const double *
 }
 
 /* ------------------------------------------------------------------ */
-/* GMRES / FGMRES (Section 3, eq. jacobian; Remark 2)                  */
+/* GMRES / FGMRES (Section 3, the Jacobian system; Remark 2)                  */
 /* ------------------------------------------------------------------ */
 typedef void (*op_fn)(void *ctx, const double *x, double *y);
 
@@ -1012,7 +1027,7 @@ static void mg_cycle(orc_mg *mg, int li, const double *b, double *x) {
     int cyc = mg->d.cycle;
     for (int i = 0; i < n; ++i) x[i] = 0.0;
     if (cyc == 3 || cyc == 4) {
-        /* eq. two-additive: I P M0 P^T b + M b;  eq. coarse-level: I P M0 P^T b */
+        /* additive two-level form: I P M0 P^T b + M b;  coarse-only form: I P M0 P^T b */
         csr_matvec_t(n, cl->n, lv->P.rp, lv->P.ci, lv->P.v, b, bc);
         mg_cycle(mg, li + 1, bc, xc);
         orc_csr_matvec(n, lv->P.rp, lv->P.ci, lv->P.v, xc, x);
@@ -1023,8 +1038,8 @@ static void mg_cycle(orc_mg *mg, int li, const double *b, double *x) {
         return;
     }
     int mu = mg->d.mu, nu = mg->d.nu;
-    if (cyc == 1) { mu = 0; nu = 1; }        /* eq. left-Kas */
-    else if (cyc == 2) { mu = 1; nu = 0; }   /* eq. right-Kas */
+    if (cyc == 1) { mu = 0; nu = 1; }        /* left Kaskade */
+    else if (cyc == 2) { mu = 1; nu = 0; }   /* right Kaskade */
     /* presmoothing: Schwarz-preconditioned Richardson, mu sweeps */
     for (int s = 0; s < mu; ++s) {
         residual_update(lv, b, x, r);

@@ -67,6 +67,8 @@ void orc_problem_free(orc_problem *pr);
 /* PR-EOS */
 void orc_pr_params(double Tc, double pc, double omega, double T, double R,
                    double *a, double *b, double *m);
+void orc_acentric_terms(double Tr, double *f0, double *f1);
+double orc_acentric(double pc, double Tc, double Tb);
 int orc_pr_z(double a, double b, double T, double R, double p, double *Z, double *dZdp);
 void orc_pr_eval(const orc_problem *pr, int n, const double *p, double *Z, double *dZ,
                  double *msc, double *dmsc);

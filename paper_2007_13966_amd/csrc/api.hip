@@ -324,7 +324,7 @@ int nks_setup_grid(const nks_grid_desc *d, nks_grid **out) {
         const nks_fluid &f = d->fluid;
         if (!(f.T > 0) || !(f.Tc > 0) || !(f.pc > 0) || !(f.R > 0) || !(f.W > 0) || !(f.mu > 0))
             fail(NKS_EINVAL, "bad fluid constants");
-        // attraction and covolume of the PR equation of state (eq. attrfactor)
+        // attraction and covolume of the PR equation of state (the criticality relations for a(T) and b (Section 2))
         const double w = f.omega;
         const double mw = w <= 0.491 ? 0.37464 + 1.54226 * w - 0.26992 * w * w
                                      : 0.3796 + 1.485 * w - 0.1644 * w * w + 0.01667 * w * w * w;

@@ -1,5 +1,5 @@
 // Stencil SpMV, per-reservoir reductions and right-preconditioned
-// GMRES / FGMRES(m) (Section 3, eq. jacobian; Remark 2 for the flexible
+// GMRES / FGMRES(m) (Section 3, the Jacobian system; Remark 2 for the flexible
 // variant).  Orthogonalisation is classical Gram-Schmidt with one
 // reorthogonalisation pass (two fused multi-dot + update passes), FP64.
 // Every reduction is deterministic: per-chunk partial sums, then a fixed-

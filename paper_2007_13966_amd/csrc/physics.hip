@@ -1,6 +1,7 @@
 // Peng-Robinson density, cell-centred residual and analytic Jacobian
-// (Section 2: eqs. density, PR, attrfactor, gover_sys, implicit-method-bdf1/2;
-// Remark 1 for the two-point flux).
+// (Section 2: the PR density, Z cubic and criticality relations, the pressure
+// form of the governing equation, the BDF1/BDF2 schemes; Remark 1 for the
+// two-point flux).
 //
 // Every kernel is one thread per cell over the concatenated cells of all
 // reservoirs; a cell finds its reservoir by binary search over the block

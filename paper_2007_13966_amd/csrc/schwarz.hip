@@ -2,14 +2,13 @@
 //
 // Section 3.1: overlapping boxes Omega_i^delta (clipped at the domain
 // boundary), subdomain matrices A_i = R_i^delta A R_i^delta^T factored by
-// ILU(0) in local lexicographic order, applied as left-RAS (eq. as-left:
-// owned cells written once, no atomics), classical AS (eq. as-class) or
-// right-RAS (eq. as-right).
-// Section 3.2: Algorithm 1 / eq. v-cycle with Schwarz-Richardson smoothing,
-// Kaskade, additive and coarse-only compositions (eqs. left-Kas, right-Kas,
-// two-additive, coarse-level), the coarsest problem solved by Schwarz-
-// preconditioned GMRES (Remark 2), interpolation of eqs. inter-frist /
-// inter-second / inter-third, restriction P^T, Galerkin coarse operators.
+// ILU(0) in local lexicographic order, applied as left-RAS (owned cells
+// written once, no atomics), classical AS or right-RAS.
+// Section 3.2: Algorithm 1 / the V-cycle preconditioner with
+// Schwarz-Richardson smoothing, the Kaskade, additive and coarse-only
+// compositions, the coarsest problem solved by Schwarz-preconditioned GMRES
+// (Remark 2), first/second/third-order interpolation, restriction P^T and
+// Galerkin coarse operators.
 //
 // GPU mapping: one workgroup per subdomain.  The triangular solves follow
 // wavefront hyperplanes t = x + lb*y + lc*z (every lower stencil offset has a
@@ -234,10 +233,10 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
 // One direction of the interpolation from ceil(nf/2) coarse cells to nf fine
 // cells.  Fine centre x_i = i + 1/2 in fine-cell units; coarse cell J covers
 // fine 2J and 2J+1 and sits at their centroid.  Order 1: the parent cell
-// (nearest centroid, eq. inter-frist).  Order 2: linear between the two
-// bracketing centroids (one factor of eq. inter-second).  Order 3: cubic
-// convolution with W(s) of eq. inter-third over four coarse cells at
-// spacing 2.  Indices beyond the domain are clamped to the edge cell and
+// (nearest centroid, the first-order interpolation of Section 3.2).  Order 2:
+// linear between the two bracketing centroids (one factor of the second-order
+// interpolation).  Order 3: cubic convolution with the kernel W(s) of the
+// third-order interpolation over four coarse cells at spacing 2.  Indices beyond the domain are clamped to the edge cell and
 // their weights merged.
 static void interp_weights(int nf, int order, int i, std::vector<std::pair<int, double>> &out) {
     out.clear();

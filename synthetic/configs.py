@@ -4,11 +4,11 @@ Units are SI throughout.  Permeabilities are stored in m^2 (1 mD =
 9.869233e-16 m^2), rates in kg/s (positive = injection), times in seconds.
 
 The five workloads:
-  c1  2D 32x32, homogeneous 100 mD, one-level left-RAS 4x4 subdomains, overlap 1
-  c2  2D 512x512 log-normal (sigma 1, corr. length 8), five-spot, two-level V-cycle
-  c3  3D 128x128x64 layered log-normal (sigma 1.5), gravity, three-level, mixed precision
-  c4  64 independent 2D reservoirs, sides 64..256, FP32 preconditioner
-  c5  3D 96x96x48 channelised (1000 mD channels in 10 mD), gravity, adjoint gradient
+  case_2d_32          2D 32x32, homogeneous 100 mD, one-level left-RAS 4x4 subdomains, overlap 1
+  case_2d_512         2D 512x512 log-normal (sigma 1, corr. length 8), five-spot, two-level V-cycle
+  case_3d_128         3D 128x128x64 layered log-normal (sigma 1.5), gravity, three-level, mixed precision
+  case_batch64        64 independent 2D reservoirs, sides 64..256, FP32 preconditioner
+  case_3d_96_adjoint  3D 96x96x48 channelised (1000 mD channels in 10 mD), gravity, adjoint gradient
 """
 from dataclasses import dataclass, field, replace
 from typing import List, Optional, Tuple
@@ -133,7 +133,7 @@ def small_case(nx=8, ny=8, nz=1, seed=0, sigma=1.0, corr=3.0, gravity=False,
     return Case("small", [prob], dt, nsteps, s)
 
 
-def case_c1():
+def case_2d_32():
     """2D 32x32, homogeneous 100 mD, phi 0.2, p0 20 MPa, injector (0,0) and
     producer (31,31) at 1e-3 kg/s, no gravity, 2 steps of 1 day (BDF1 then BDF2),
     one-level left-RAS with 4x4 subdomains, overlap 1, ILU(0), FP64."""
@@ -144,10 +144,10 @@ def case_c1():
     prob = Problem(nx, ny, 1, 10.0, 10.0, 10.0, k.copy(), k.copy(), k.copy(),
                    np.full(N, 0.2), wc, wr)
     s = SolverSettings(px=4, py=4, pz=1, overlap=(1,), levels=1)
-    return Case("c1_32x32_onelevel", [prob], DAY, 2, s, case_c1.__doc__)
+    return Case("2d_32x32_onelevel", [prob], DAY, 2, s, case_2d_32.__doc__)
 
 
-def case_c2(n=512):
+def case_2d_512(n=512):
     """2D 512x512, ln K = ln(100 mD) + 1.0 G (corr. length 8 cells, seed 2),
     porosity U[0.1, 0.3] (seed 12), five-spot: centre injector +4e-3 kg/s and
     four corner producers -1e-3 kg/s, 10 steps of 5 days, two-level V-cycle,
@@ -162,7 +162,7 @@ def case_c2(n=512):
                     [4e-3, -1e-3, -1e-3, -1e-3, -1e-3])
     prob = Problem(nx, ny, 1, 10.0, 10.0, 10.0, k.copy(), k.copy(), k.copy(), phi, wc, wr)
     s = SolverSettings(px=16, py=16, pz=1, overlap=(2, 1), levels=2)
-    return Case(f"c2_{n}x{n}_twolevel_fp64", [prob], 5 * DAY, 10, s, case_c2.__doc__)
+    return Case(f"2d_{n}x{n}_twolevel_fp64", [prob], 5 * DAY, 10, s, case_2d_512.__doc__)
 
 
 def _column_wells(nx, ny, nz, inj_xy, prod_xy, rate):
@@ -176,7 +176,7 @@ def _column_wells(nx, ny, nz, inj_xy, prod_xy, rate):
     return _wells(cells, rates)
 
 
-def case_c3(nx=128, ny=128, nz=64, precision="fp32"):
+def case_3d_128(nx=128, ny=128, nz=64, precision="fp32"):
     """3D 128x128x64, per-layer mean K log-uniform in [10, 1000] mD, sigma 1.5,
     corr. length 8 (seed 3), kv = 0.1 kh, phi 0.2, gravity with hydrostatic
     initial state (20 MPa top layer), injector column (0,0,:) and producer
@@ -189,11 +189,11 @@ def case_c3(nx=128, ny=128, nz=64, precision="fp32"):
     prob = Problem(nx, ny, nz, 10.0, 10.0, 10.0, kh.copy(), kh.copy(), 0.1 * kh,
                    np.full(N, 0.2), wc, wr, gravity=True)
     s = SolverSettings(px=8, py=8, pz=4, overlap=(1, 1, 1), levels=3, precision=precision)
-    return Case(f"c3_{nx}x{ny}x{nz}_threelevel_{precision}", [prob], 5 * DAY, 5, s,
-                case_c3.__doc__)
+    return Case(f"3d_{nx}x{ny}x{nz}_threelevel_{precision}", [prob], 5 * DAY, 5, s,
+                case_3d_128.__doc__)
 
 
-def case_c4(nres=64, nmin=64, nmax=256, tile=16, overlap=1):
+def case_batch64(nres=64, nmin=64, nmax=256, tile=16, overlap=1):
     """64 independent 2D reservoirs, side n_b uniform in {64..256}, sigma_b
     uniform in [0.5, 2], corr. length 8, mean 100 mD, phi 0.2, one injector and
     one producer (+-1e-3 kg/s) at seeded cells at least n_b/4 apart
@@ -216,12 +216,12 @@ def case_c4(nres=64, nmin=64, nmax=256, tile=16, overlap=1):
                              np.full(n * n, 0.2), wc, wr))
     s = SolverSettings(px=1, py=1, pz=1, tile=(tile, tile, 0), overlap=(overlap, 1), levels=2,
                        precision="fp32")
-    return Case(f"c4_batch{nres}_2d_fp32prec", probs, 5 * DAY, 3, s, case_c4.__doc__)
+    return Case(f"batch{nres}_2d_fp32prec", probs, 5 * DAY, 3, s, case_batch64.__doc__)
 
 
-def case_c5(nx=96, ny=96, nz=48):
+def case_3d_96_adjoint(nx=96, ny=96, nz=48):
     """3D 96x96x48 channelised: 10 mD background with 8 sinusoidal 1000 mD
-    channels (seed 5), kv/kh 0.1, phi 0.2, gravity, column wells as in c3,
+    channels (seed 5), kv/kh 0.1, phi 0.2, gravity, column wells as in the 128x128x64 case,
     3 steps of 5 days, two-level FP64.  Objective: producer-column mean
     pressure at the final step; gradient with respect to ln K per cell."""
     kh = channel_perm(nx, ny, nz, 10.0, 1000.0, 8, 5).ravel() * MD
@@ -230,7 +230,7 @@ def case_c5(nx=96, ny=96, nz=48):
     prob = Problem(nx, ny, nz, 10.0, 10.0, 10.0, kh.copy(), kh.copy(), 0.1 * kh,
                    np.full(N, 0.2), wc, wr, gravity=True)
     s = SolverSettings(px=6, py=6, pz=3, overlap=(1, 1), levels=2)
-    return Case(f"c5_{nx}x{ny}x{nz}_adjoint", [prob], 5 * DAY, 3, s, case_c5.__doc__)
+    return Case(f"3d_{nx}x{ny}x{nz}_adjoint", [prob], 5 * DAY, 3, s, case_3d_96_adjoint.__doc__)
 
 
 def with_solver(case, **kw):

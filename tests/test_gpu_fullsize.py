@@ -61,25 +61,25 @@ def _check(orc, case, k, p0g, pg):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_c2_first_step(nks, orc, precision):
-    case = S.with_solver(S.case_c2(), precision=precision, **PARITY)
-    say("c2", precision)
+def test_2d_512_first_step(nks, orc, precision):
+    case = S.with_solver(S.case_2d_512(), precision=precision, **PARITY)
+    say("2d 512x512", precision)
     p0, p, st = _gpu_first_step(nks, case)
     say("  gpu", st["newton_its"], "newton,", st["linear_its"], "gmres")
     _check(orc, case, 0, p0[0], p[0])
 
 
-def test_c3_first_step(nks, orc):
-    case = S.with_solver(S.case_c3(), **PARITY)
-    say("c3", case.solver.precision)
+def test_3d_128_first_step(nks, orc):
+    case = S.with_solver(S.case_3d_128(), **PARITY)
+    say("3d 128x128x64", case.solver.precision)
     p0, p, st = _gpu_first_step(nks, case)
     say("  gpu", st["newton_its"], "newton,", st["linear_its"], "gmres")
     _check(orc, case, 0, p0[0], p[0])
 
 
-def test_c4_batch_first_step(nks, orc):
-    case = S.with_solver(S.case_c4(), **PARITY)
-    say("c4", len(case.problems), "reservoirs,", case.solver.precision)
+def test_batch64_first_step(nks, orc):
+    case = S.with_solver(S.case_batch64(), **PARITY)
+    say("batch", len(case.problems), "reservoirs,", case.solver.precision)
     p0, p, st = _gpu_first_step(nks, case)
     say("  gpu", st["newton_its"], "newton,", st["linear_its"], "gmres")
     sizes = [r.N for r in case.problems]
@@ -88,9 +88,9 @@ def test_c4_batch_first_step(nks, orc):
         _check(orc, case, k, p0[k], p[k])
 
 
-def test_c5_first_step(nks, orc):
-    case = S.with_solver(S.case_c5(), **PARITY)
-    say("c5")
+def test_3d_96_first_step(nks, orc):
+    case = S.with_solver(S.case_3d_96_adjoint(), **PARITY)
+    say("3d 96x96x48")
     p0, p, st = _gpu_first_step(nks, case)
     say("  gpu", st["newton_its"], "newton,", st["linear_its"], "gmres")
     _check(orc, case, 0, p0[0], p[0])

@@ -255,9 +255,9 @@ def _run_steps(nks, orc, case, nsteps, gpu=True):
 PARITY = dict(eps_r=1e-8, eps_a=1e-6)
 
 
-def test_newton_c1_end_to_end(nks, orc):
-    case = S.with_solver(S.case_c1(), **PARITY)
-    say("newton c1")
+def test_newton_2d_32_end_to_end(nks, orc):
+    case = S.with_solver(S.case_2d_32(), **PARITY)
+    say("newton 2d 32x32")
     hist_g, st_g, g = _run_steps(nks, orc, case, 2)
     (hist_o, st_o), = _run_steps(nks, orc, case, 2, gpu=False)
     op = orc.Problem(case.problems[0])

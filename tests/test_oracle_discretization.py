@@ -1,5 +1,5 @@
 """Pins of the oracle's finite-volume residual and Jacobian (Section 2,
-eqs. gover_sys, implicit-method-bdf1/-bdf2, Remark 1) against invariants that
+the pressure form of the governing equation, BDF1/BDF2, Remark 1) against invariants that
 hold whatever the implementation: zero residual at rest, hydrostatic
 equilibrium, discrete conservation, mirror symmetry, finite differences,
 and BDF temporal orders."""

@@ -1,5 +1,5 @@
-"""Pins of the oracle's Peng-Robinson evaluation (Section 2, eqs. PR, attrfactor
-and the dZ/dp closed form) against facts that do not come from the oracle:
+"""Pins of the oracle's Peng-Robinson evaluation (Section 2: the Z cubic,
+the criticality relations for a and b, the dZ/dp closed form) against facts that do not come from the oracle:
 companion-matrix roots of the cubic, the ideal-gas limit, the PR critical
 point, and finite differences of independently computed roots."""
 import numpy as np
@@ -120,3 +120,32 @@ def test_density_derivative_is_paper_coefficient(orc):
         mm = (pi - h) / roots_largest_real(*AB(fl, a, b, pi - h))
         assert abs(dm[i] - (mp - mm) / (2 * h)) < 1e-6 * abs(dm[i])
         assert abs(m[i] - pi / roots_largest_real(*AB(fl, a, b, pi))) < 1e-10 * m[i]
+
+
+def _golden(name):
+    import os
+    vals = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        for line in f:
+            line = line.split("#")[0].split()
+            if len(line) == 2:
+                vals[line[0]] = float(line[1])
+    return vals
+
+
+@pytest.mark.parametrize("omega", [0.0, 0.011, 0.2, 0.5, 1.0])
+def test_acentric_correlation_reproduces_pitzer_definition(orc, omega):
+    # Pitzer's definition: log10 p_r(T_r = 0.7) = -1 - omega.  The Section 2
+    # correlation ln p_r = f0 + omega f1 must reproduce it; a dropped or
+    # mistyped coefficient does not
+    f0, f1 = orc.acentric_terms(0.7)
+    assert abs((f0 + omega * f1) / np.log(10.0) - (-1.0 - omega)) < 1e-5
+
+
+def test_methane_acentric_factor_from_section4_data(orc):
+    g = _golden("methane_section4.txt")
+    w = orc.acentric(g["pc"], g["Tc"], g["Tb"])
+    assert g["omega_table_lo"] - 1e-3 <= w <= g["omega_table_hi"] + 1e-3
+    # at T_b the correlation returns p = 1 atm by construction
+    f0, f1 = orc.acentric_terms(g["Tb"] / g["Tc"])
+    assert abs(np.exp(f0 + w * f1) * g["pc"] - 101325.0) < 1e-6 * 101325.0

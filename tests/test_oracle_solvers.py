@@ -255,7 +255,7 @@ def _two_level_ops(orc, cycle, mu=1, nu=1, dims=(12, 10, 1), order=2):
 
 
 def test_vcycle_error_propagation_identity(orc):
-    # eq. two_level_preconditioner with mu = nu = 1:
+    # the two-level V-cycle preconditioner of Section 3.2 with mu = nu = 1:
     # I - A B = (I - A M)(I - A P A_c^{-1} P^T)(I - A M)
     A, B, M, C = _two_level_ops(orc, "vcycle")
     I = np.eye(A.shape[0])
@@ -267,10 +267,10 @@ def test_vcycle_error_propagation_identity(orc):
 def test_two_level_compositions(orc, cycle):
     A, B, M, C = _two_level_ops(orc, cycle, order=1 if cycle == "additive" else 2)
     ref = {
-        "left_kaskade": C + M - M @ A @ C,      # eq. left-Kas
-        "right_kaskade": M + C - C @ A @ M,     # eq. right-Kas
-        "additive": C + M,                      # eq. two-additive
-        "coarse_only": C,                       # eq. coarse-level
+        "left_kaskade": C + M - M @ A @ C,      # left Kaskade
+        "right_kaskade": M + C - C @ A @ M,     # right Kaskade
+        "additive": C + M,                      # additive
+        "coarse_only": C,                       # coarse only
     }[cycle]
     assert np.allclose(B, ref, rtol=1e-8, atol=1e-8 * np.abs(ref).max())
 
