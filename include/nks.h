@@ -170,7 +170,13 @@ int nks_ras_apply(nks_ras *M, const double *r, double *z);
 /* One-level Schwarz apply on `level` (0 = finest) with vectors of that
  * level's size (device).  Asynchronous. */
 int nks_ras_apply_level(nks_ras *M, int level, const double *r, double *z);
-/* z = M^{-T} r of the finest one-level preconditioner (device). */
+/* z = M^{-T} r (device): the preconditioner with the same boxes and levels
+ * built on J^T, left- and right-RAS exchanged (AS stays AS).  ILU(0) of A^T
+ * on a symmetric pattern is the transpose of ILU(0) of A, and the Galerkin
+ * product commutes with transposition, so for one level this is exactly the
+ * transpose; with levels it is the transposed V-cycle up to the inexact
+ * coarse solve.  Built and factored on first use after each nks_ras_setup.
+ * Synchronous on the grid's stream when it refactors. */
 int nks_ras_apply_transpose(nks_ras *M, const double *r, double *z);
 /* info[0..7] = n, stencil points, subdomains, nx, ny, nz (first reservoir),
  * number of levels, nnz of the level operator. Synchronises. */
@@ -186,7 +192,8 @@ int nks_ras_prolong_add(nks_ras *M, int level, const double *e_coarse, double *z
  * the Jacobian system; Remark 2): x holds the initial guess (zero it for x0 = 0);
  * stops per reservoir when ||b - J x|| <= max(rtol ||b||, atol).
  * Orthogonalisation: classical Gram-Schmidt with one reorthogonalisation,
- * FP64.  transpose != 0 solves J^T x = b with M^{-T} (one-level only). */
+ * FP64.  transpose != 0 solves J^T x = b, preconditioned by
+ * nks_ras_apply_transpose when M is given. */
 typedef struct {
     int restart;
     double rtol, atol;
@@ -249,6 +256,44 @@ typedef struct {
 int nks_newton_step(nks_grid *g, double *p, const double *p_n, const double *p_nm1,
                     double dt, int bdf_order, const nks_newton_desc *nd,
                     const nks_ras_desc *rd, nks_newton_stats *st);
+
+/* J^T as a matrix on the same grid and stencil: JT[q][i] = J[opp(q)][i + off_q].
+ * Both created by nks_matrix_create on one grid; asynchronous on its stream. */
+int nks_matrix_transpose(nks_matrix *J, nks_matrix *JT);
+
+/* Discrete adjoint of nsteps implicit steps for an objective G(p^1..p^n)
+ * whose gradient in each state is given.  With the Lagrangian
+ * G + sum_n lambda_n^T F^n(p^n, p^{n-1}, p^{n-2}; ln K), the multipliers
+ * solve, from the last step back,
+ *   J_n^T lambda_n = -dG/dp^n - (dF^{n+1}/dp^n)^T lambda_{n+1} - (dF^{n+2}/dp^n)^T lambda_{n+2}
+ * (the couplings are diagonal: the accumulation's dependence on the earlier
+ * states, Section 2's BDF1/BDF2), and
+ *   dG/dln K = sum_n (dF^n/dln K)^T lambda_n,
+ * with ln K of a cell scaling all three components together.  Each J_n^T
+ * system is solved by (F)GMRES (gd: restart, rtol, atol, maxit, flexible;
+ * transpose ignored) preconditioned with the transpose of the Schwarz
+ * preconditioner rd describes (see nks_ras_apply_transpose), x0 = 0.
+ *   p_hist   HOST array of nsteps+1 device pointers: p^0 (initial state,
+ *            independent of K) and the converged p^1..p^nsteps
+ *   orders   HOST array of nsteps ints: BDF order of step n at [n-1]
+ *            (1, or 2 from the second step on)
+ *   dGdp     HOST array of nsteps+1 device pointers, NULL for a zero
+ *            gradient; entry 0 is ignored
+ *   grad     device [N], overwritten with dG/dln K
+ *   lam_out  optional HOST array of nsteps+1 device pointers receiving
+ *            lambda_n (NULL array or entries: not wanted)
+ * NKS_ENOTCONVERGED when a linear solve misses its tolerance (grad is still
+ * written). */
+typedef struct {
+    int linear_its[64];          /* iterations of the J_n^T solve, step n at [n-1] */
+    int total_linear_its;
+    int status;                  /* 0 ok, 1 a solve did not converge */
+    double t_total;              /* seconds */
+} nks_adjoint_stats;
+
+int nks_adjoint(nks_grid *g, int nsteps, const double *const *p_hist, const int *orders, double dt,
+                const double *const *dGdp, const nks_ras_desc *rd, const nks_gmres_desc *gd,
+                double *grad, double *const *lam_out, nks_adjoint_stats *st);
 
 /* Kernel timing with HIP events on the launching stream.  Single-kernel
  * records carry the events on the dispatch itself (the kernel's own

@@ -411,3 +411,38 @@ def simulate(case, nsteps=None, p0=None):
             stats.append(st)
         out.append((hist, stats))
     return out
+
+
+def adjoint(prob, dt, hist, dGdp, orders=None):
+    """Discrete adjoint of the implicit steps hist[0] -> hist[-1] (BDF1 first,
+    BDF2 after, unless orders says otherwise) for an objective G whose
+    gradient in state n is dGdp[n] (None: zero; entry 0 ignored: p^0 does not
+    depend on K).  Written from the definition: with the Lagrangian
+    G + sum_n lam_n^T F^n(p^n, p^{n-1}, p^{n-2}),
+      J_n^T lam_n = -dG/dp^n - (dF^{n+1}/dp^n)^T lam_{n+1} - (dF^{n+2}/dp^n)^T lam_{n+2},
+    where the couplings are the accumulation's dependence on earlier states
+    (Section 2's BDF1/BDF2: m(p^n) enters F^{n+1} with coefficient -1 (BDF1)
+    or -2 (BDF2) and F^{n+2} with 1/2, each times V phi / dt), and
+      dG/dln K = sum_n (dF^n/dln K)^T lam_n.
+    Each J_n^T system is solved directly (sparse LU).  Returns (grad, lams)."""
+    import scipy.sparse.linalg as spla
+    rec = prob.rec
+    n = len(hist) - 1
+    orders = orders or [1] + [2] * (n - 1)
+    pv = rec.dx * rec.dy * rec.dz * _f64(rec.phi)
+    lams = [None] * (n + 3)
+    grad = np.zeros(prob.N)
+    for k in range(n, 0, -1):
+        _, _, _, dm = prob.pr(hist[k])
+        rhs = -(np.zeros(prob.N) if dGdp[k] is None else _f64(dGdp[k]))
+        if k + 1 <= n:
+            c1 = -2.0 if orders[k] == 2 else -1.0
+            rhs -= pv / dt * dm * c1 * lams[k + 1]
+        if k + 2 <= n and orders[k + 1] == 2:
+            rhs -= pv / dt * dm * 0.5 * lams[k + 2]
+        pn = hist[k - 1]
+        pnm1 = hist[k - 2] if k >= 2 else hist[k - 1]
+        J = prob.jacobian(hist[k], pn, pnm1, dt, orders[k - 1]).scipy()
+        lams[k] = spla.spsolve(J.T.tocsc(), rhs)
+        grad += prob.residual_dlogk_t(hist[k], lams[k])
+    return grad, lams[:n + 1]

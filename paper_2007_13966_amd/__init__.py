@@ -229,6 +229,45 @@ class Grid:
             check(lib().nks_residual_dlogk_transpose_apply(self.h, _vp(p), _vp(lam), _vp(out)))
         return out
 
+    def simulate(self, nsteps, dt, settings, p0=None):
+        """nsteps implicit steps (BDF1 first, BDF2 after) from p0 (default: the
+        initial state); returns the list of states p^0..p^n and the step stats."""
+        p = self.initial_pressure() if p0 is None else p0.clone()
+        hist, stats = [p.clone()], []
+        for n in range(nsteps):
+            order = 1 if n == 0 else 2
+            pn = hist[-1]
+            pnm1 = hist[-2] if len(hist) > 1 else hist[-1]
+            q = pn.clone()
+            stats.append(self.newton_step(q, pn, pnm1, dt, order, settings))
+            hist.append(q)
+        return hist, stats
+
+    def adjoint(self, p_hist, dt, dGdp, settings, orders=None, rtol=1e-10, atol=0.0, restart=30,
+                maxit=10000, want_lambda=False):
+        """nks_adjoint: dG/dln K for an objective with per-state gradients
+        dGdp[n] (None: zero) over the states p_hist = [p^0, ..., p^n]."""
+        torch = _torch()
+        nsteps = len(p_hist) - 1
+        orders = orders or [1] + [2] * (nsteps - 1)
+        ph = (C.c_void_p * (nsteps + 1))(*[x.data_ptr() for x in p_hist])
+        dg = (C.c_void_p * (nsteps + 1))(*[x.data_ptr() if x is not None else None for x in dGdp])
+        od = (C.c_int * nsteps)(*orders)
+        lams = [self.zeros() for _ in range(nsteps + 1)] if want_lambda else None
+        lo = (C.c_void_p * (nsteps + 1))(*[x.data_ptr() for x in lams]) if want_lambda else None
+        grad = self.zeros()
+        rd = ras_desc(settings)
+        gd = L.nks_gmres_desc(restart, rtol, atol, maxit, 1, 0)
+        st = L.nks_adjoint_stats()
+        with _Ordered(self):
+            check(lib().nks_adjoint(self.h, nsteps, ph, od, float(dt), dg, C.byref(rd), C.byref(gd),
+                                    _vp(grad), lo, C.byref(st)))
+        out = dict(linear_its=list(st.linear_its[:min(nsteps, 64)]), total_linear_its=st.total_linear_its,
+                   seconds=st.t_total)
+        if want_lambda:
+            out["lambda"] = lams
+        return grad, out
+
     def newton_step(self, p, pn, pnm1, dt, order, settings, raise_on_fail=True):
         st = L.nks_newton_stats()
         nd, rd = newton_desc(settings), ras_desc(settings)
@@ -283,6 +322,13 @@ class Matrix:
             check(lib().nks_jacobian_transpose_apply(self.h, _vp(x), _vp(y)))
         return y
 
+    def transpose(self, out=None):
+        """J^T as a matrix on the same grid (nks_matrix_transpose)."""
+        JT = Matrix(self.grid) if out is None else out
+        with _Ordered(self.grid):
+            check(lib().nks_matrix_transpose(self.h, JT.h))
+        return JT
+
 
 class Ras:
     """nks_ras: multilevel restricted additive Schwarz preconditioner."""
@@ -322,6 +368,12 @@ class Ras:
         z = self.grid.zeros() if out is None else out
         with _Ordered(self.grid):
             check(lib().nks_ras_apply(self.h, _vp(r), _vp(z)))
+        return z
+
+    def apply_transpose(self, r, out=None):
+        z = self.grid.zeros() if out is None else out
+        with _Ordered(self.grid):
+            check(lib().nks_ras_apply_transpose(self.h, _vp(r), _vp(z)))
         return z
 
     def apply_level(self, level, r, out=None):

@@ -74,6 +74,11 @@ class nks_newton_stats(C.Structure):
                 ("t_gmres", C.c_double), ("t_linesearch", C.c_double)]
 
 
+class nks_adjoint_stats(C.Structure):
+    _fields_ = [("linear_its", C.c_int * 64), ("total_linear_its", C.c_int), ("status", C.c_int),
+                ("t_total", C.c_double)]
+
+
 _P = C.c_void_p
 _D = C.c_double
 _I = C.c_int
@@ -106,6 +111,10 @@ PROTOTYPES = {
     "nks_gmres_solve": [_P, _P, _P, _P, C.POINTER(nks_gmres_desc), C.POINTER(nks_gmres_stats)],
     "nks_newton_step": [_P, _P, _P, _P, _D, _I, C.POINTER(nks_newton_desc),
                         C.POINTER(nks_ras_desc), C.POINTER(nks_newton_stats)],
+    "nks_matrix_transpose": [_P, _P],
+    "nks_adjoint": [_P, _I, C.POINTER(C.c_void_p), _IP, _D, C.POINTER(C.c_void_p),
+                    C.POINTER(nks_ras_desc), C.POINTER(nks_gmres_desc), _P, C.POINTER(C.c_void_p),
+                    C.POINTER(nks_adjoint_stats)],
     "nks_profile_enable": [_I],
     "nks_profile_query": [C.c_char_p, _IP, _DP],
     "nks_profile_durations": [C.c_char_p, _DP, _I, _IP],

@@ -137,7 +137,9 @@ void launch_history(Grid &g, const double *pn, const double *pnm1, int order);
 void launch_props(Grid &g, const double *p);
 void launch_flux(Grid &g, const double *p, double dt, int order, double *F, double *J);
 void launch_hydrostatic(Grid &g, double p_top, double *p);
-void launch_dlogk_t(Grid &g, const double *p, const double *lam, double *out);
+void launch_dlogk_t(Grid &g, const double *p, const double *lam, double *out, bool accumulate);
+void launch_adj_rhs(Grid &g, const double *pn, double dt, double c1, const double *l1, double c2,
+                    const double *l2, const double *dg, double *out);
 
 static inline int nblk(int n, int t) { return (n + t - 1) / t; }
 
@@ -192,6 +194,71 @@ static bool same_desc(const nks_ras_desc &a, const nks_ras_desc &b) {
     return memcmp(&a, &b, sizeof(a)) == 0;
 }
 
+// opp[q] = slot of the offset -off_q; the stencils here are point-symmetric
+static std::vector<int> opposite_slots(const Stencil &st) {
+    std::vector<int> opp(st.K, -1);
+    for (int k = 0; k < st.K; ++k)
+        for (int q = 0; q < st.K; ++q)
+            if (st.off[3 * q] == -st.off[3 * k] && st.off[3 * q + 1] == -st.off[3 * k + 1] &&
+                st.off[3 * q + 2] == -st.off[3 * k + 2])
+                opp[k] = q;
+    for (int k = 0; k < st.K; ++k)
+        if (opp[k] < 0) fail(NKS_EINVAL, "stencil is not point-symmetric");
+    return opp;
+}
+
+// A matrix on the fine stencil of grid g
+static void fine_matrix(Matrix &M, Grid &g) {
+    M.g = &g;
+    M.op.sp = &g.sp;
+    stencil_fine(M.op.st, g.dim, &g.al, g.s);
+    M.op.coef.alloc(&g.al, (size_t)M.op.st.K * g.sp.N);
+}
+
+// The transpose of a Schwarz preconditioner built on J: the same boxes and
+// levels built on J^T, with left- and right-RAS exchanged.  ILU(0) of A^T on
+// a symmetric pattern is the transpose of ILU(0) of A and the Galerkin product
+// commutes with transposition, so for one level this is exactly M^T; with
+// levels, the V-cycle built this way is the transpose of the V-cycle on J up
+// to its inexact coarse solve.
+struct TransposedRas {
+    Matrix JT;
+    DBuf<int> opp;
+    std::unique_ptr<Ras> MT;
+    nks_ras_desc d{};
+    bool stale = true;
+    void refresh(Matrix &J, const nks_ras_desc &dd) {
+        Grid &g = *J.g;
+        if (!MT || !same_desc(d, dd)) {
+            fine_matrix(JT, g);
+            std::vector<int> o = opposite_slots(J.op.st);
+            opp.upload(&g.al, o, g.s);
+            nks_ras_desc dt = dd;
+            dt.variant = dd.variant == NKS_LEFT_RAS ? NKS_RIGHT_RAS
+                                                    : (dd.variant == NKS_RIGHT_RAS ? NKS_LEFT_RAS : dd.variant);
+            MT.reset(new Ras());
+            MT->build(&JT, dt);
+            d = dd;
+            stale = true;
+        }
+        if (stale) {
+            launch_transpose_op(J.op, JT.op, opp.p, g.s);
+            MT->factor();
+            MT->check_pivots();
+            stale = false;
+        }
+    }
+};
+
+// Workspace of the discrete adjoint
+struct AdjointWork {
+    Matrix J;
+    TransposedRas T;
+    Gmres gm;
+    DBuf<double> rhs, lam[3];
+    bool ready = false;
+};
+
 }  // namespace nks
 
 using namespace nks;
@@ -199,13 +266,16 @@ using namespace nks;
 struct nks_grid {
     Grid g;
     std::unique_ptr<NewtonWork> nw;
+    std::unique_ptr<AdjointWork> aw;
 };
 struct nks_matrix {
     Matrix m;
     nks_grid *owner;
+    DBuf<int> opp;       // opposite stencil slots, for transposes
 };
 struct nks_ras {
     Ras r;
+    TransposedRas t;     // built on first use of the transpose
 };
 
 template <typename F>
@@ -502,7 +572,19 @@ int nks_jacobian_transpose_apply(nks_matrix *J, const double *x, double *y) {
 int nks_residual_dlogk_transpose_apply(nks_grid *g, const double *p, const double *lam, double *out) {
     return guard([&] {
         if (!g || !p || !lam || !out) fail(NKS_EINVAL, "bad arguments");
-        launch_dlogk_t(g->g, p, lam, out);
+        launch_dlogk_t(g->g, p, lam, out, false);
+    });
+}
+
+int nks_matrix_transpose(nks_matrix *J, nks_matrix *JT) {
+    return guard([&] {
+        if (!J || !JT || J == JT) fail(NKS_EINVAL, "bad arguments");
+        if (J->m.g != JT->m.g) fail(NKS_EINVAL, "matrices belong to different grids");
+        if (!J->opp.p) {
+            std::vector<int> o = opposite_slots(J->m.op.st);
+            J->opp.upload(&J->m.g->al, o, J->m.g->s);
+        }
+        launch_transpose_op(J->m.op, JT->m.op, J->opp.p, J->m.g->s);
     });
 }
 
@@ -531,6 +613,7 @@ int nks_ras_setup(nks_matrix *J, const nks_ras_desc *d, nks_ras **inout) {
             M->r.build(&J->m, *d);
         }
         M->r.factor();
+        M->t.stale = true;
         if (hold) *inout = hold.release();
     });
 }
@@ -558,8 +641,12 @@ int nks_ras_apply_level(nks_ras *M, int level, const double *r, double *z) {
     });
 }
 
-int nks_ras_apply_transpose(nks_ras *, const double *, double *) {
-    return guard([&] { fail(NKS_EINVAL, "transpose preconditioner not available"); });
+int nks_ras_apply_transpose(nks_ras *M, const double *r, double *z) {
+    return guard([&] {
+        if (!M || !r || !z) fail(NKS_EINVAL, "bad arguments");
+        M->t.refresh(*M->r.J, M->r.d);
+        M->t.MT->apply(r, z, nullptr);
+    });
 }
 
 int nks_ras_level_info(nks_ras *M, int level, int *info) {
@@ -606,7 +693,7 @@ int nks_gmres_solve(nks_matrix *J, nks_ras *M, const double *b, double *x, const
         if (!J || !b || !x || !d || d->restart < 1 || d->restart > 30 || d->maxit < 1)
             fail(NKS_EINVAL, "bad arguments");
         Grid &g = *J->m.g;
-        if (d->transpose && M) fail(NKS_EINVAL, "transpose solve with a preconditioner is not available");
+        if (d->transpose && M) M->t.refresh(*M->r.J, M->r.d);
         auto &nwp = J->owner->nw;
         if (!nwp) nwp.reset(new NewtonWork());
         Gmres &gm = nwp->gm;
@@ -627,7 +714,8 @@ int nks_gmres_solve(nks_matrix *J, nks_ras *M, const double *b, double *x, const
             }
         };
         Precond P = [&](const double *r, double *z, const int *mk) {
-            if (M) M->r.apply(r, z, mk);
+            if (M && d->transpose) M->t.MT->apply(r, z, mk);
+            else if (M) M->r.apply(r, z, mk);
             else launch_axpby(g.sp, 1.0, r, 0.0, z, mk, g.s);
         };
         GmOpts o;
@@ -897,3 +985,81 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ discrete adjoint
+int nks_adjoint(nks_grid *gh, int nsteps, const double *const *p_hist, const int *orders, double dt,
+                const double *const *dGdp, const nks_ras_desc *rd, const nks_gmres_desc *gd, double *grad,
+                double *const *lam_out, nks_adjoint_stats *st) {
+    return guard([&] {
+        if (!gh || nsteps < 1 || !p_hist || !orders || !(dt > 0) || !dGdp || !rd || !gd || !grad)
+            fail(NKS_EINVAL, "bad arguments");
+        if (gd->restart < 1 || gd->restart > 30 || gd->maxit < 1) fail(NKS_EINVAL, "bad GMRES descriptor");
+        check_ras_desc(rd);
+        for (int n = 0; n <= nsteps; ++n)
+            if (!p_hist[n]) fail(NKS_EINVAL, "p_hist[%d] is null", n);
+        for (int n = 1; n <= nsteps; ++n)
+            if (orders[n - 1] != 1 && !(orders[n - 1] == 2 && n >= 2))
+                fail(NKS_EINVAL, "step %d: order must be 1, or 2 from the second step on", n);
+        Grid &g = gh->g;
+        const int N = g.sp.N;
+        hipStream_t s = g.s;
+        Alloc *al = &g.al;
+        if (!gh->aw) gh->aw.reset(new AdjointWork());
+        AdjointWork &W = *gh->aw;
+        if (!W.ready) {
+            fine_matrix(W.J, g);
+            W.rhs.alloc(al, N);
+            for (auto &l : W.lam) l.alloc(al, N);
+            W.ready = true;
+        }
+        W.gm.ensure(al, g.sp, gd->restart, gd->flexible != 0, s);
+        nks_adjoint_stats S{};
+        double t0 = now();
+        // lam[n % 3] holds lambda_n; lambda_{n+1}, lambda_{n+2} are the two before it
+        for (int n = nsteps; n >= 1; --n) {
+            const double *l1 = n + 1 <= nsteps ? W.lam[(n + 1) % 3].p : nullptr;
+            const double *l2 = n + 2 <= nsteps && orders[n + 1] == 2 ? W.lam[(n + 2) % 3].p : nullptr;
+            const double c1 = n + 1 <= nsteps ? (orders[n] == 2 ? -2.0 : -1.0) : 0.0;
+            launch_adj_rhs(g, p_hist[n], dt, c1, l1, 0.5, l2, dGdp[n], W.rhs.p);
+            // J_n at the converged p^n (its accumulation coefficient depends on the order)
+            launch_props(g, p_hist[n]);
+            launch_flux(g, p_hist[n], dt, orders[n - 1], nullptr, W.J.op.coef.p);
+            W.T.stale = true;
+            W.T.refresh(W.J, *rd);
+            Ras &MT = *W.T.MT;
+            Matrix &JT = W.T.JT;
+            double *lam = W.lam[n % 3].p;
+            launch_axpby(g.sp, 0.0, W.rhs.p, 0.0, lam, nullptr, s);
+            MatVec A = [&](const double *xx, double *yy, const double *bb, const int *mk) {
+                launch_spmv(JT.op, xx, yy, bb, mk, s);
+            };
+            Precond P = [&](const double *r, double *z, const int *mk) { MT.apply(r, z, mk); };
+            GmOpts o;
+            o.rtol = gd->rtol;
+            o.atol = gd->atol;
+            o.maxit = gd->maxit;
+            o.flexible = gd->flexible != 0;
+            o.check_every = 1;
+            W.gm.solve(A, P, W.rhs.p, lam, true, o, nullptr, s);
+            std::vector<int> its, conv;
+            std::vector<double> res;
+            W.gm.stats(its, res, conv, s);
+            int lits = 0, nconv = 0;
+            for (int b = 0; b < g.sp.B; ++b) {
+                lits = std::max(lits, its[b]);
+                nconv += conv[b];
+            }
+            if (n - 1 < 64) S.linear_its[n - 1] = lits;
+            S.total_linear_its += lits;
+            if (nconv < g.sp.B) S.status = 1;
+            if (lam_out && lam_out[n])
+                HIPC(hipMemcpyAsync(lam_out[n], lam, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+            // dG/dln K += (dF^n/dln K)^T lambda_n
+            launch_dlogk_t(g, p_hist[n], lam, grad, n != nsteps);
+        }
+        HIPC(hipStreamSynchronize(s));
+        S.t_total = now() - t0;
+        if (st) *st = S;
+        if (S.status) fail(NKS_ENOTCONVERGED, "an adjoint linear solve did not converge");
+    });
+}

@@ -92,6 +92,25 @@ __global__ void k_spmv_abs(SpmvArgs a) {
     a.y[i] = s;
 }
 
+// AT = A^T on the same stencil: AT[q][i] = A[opp(q)][i + off_q] (zero where the
+// neighbour is outside the reservoir)
+__global__ void k_transpose_op(SpmvArgs a, const int *opp, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    const int bi = find_blk(a.blk, a.B, i);
+    const Blk k = a.blk[bi];
+    const int l = i - k.off;
+    const int x = l % k.nx, y = (l / k.nx) % k.ny, z = l / (k.nx * k.ny);
+    for (int q = 0; q < a.K; ++q) {
+        const int dx = a.off[3 * q], dy = a.off[3 * q + 1], dz = a.off[3 * q + 2];
+        const int xx = x + dx, yy = y + dy, zz = z + dz;
+        double v = 0.0;
+        if (xx >= 0 && xx < k.nx && yy >= 0 && yy < k.ny && zz >= 0 && zz < k.nz)
+            v = a.coef[(size_t)opp[q] * a.N + i + dx + k.nx * (dy + k.ny * dz)];
+        out[(size_t)q * a.N + i] = v;
+    }
+}
+
 // y = A^T x: y_i = sum_q A[opp(q)][i + off_q] x[i + off_q]
 __global__ void k_spmv_t(SpmvArgs a, const int *opp) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -136,6 +155,12 @@ void launch_spmv(const Op &A, const double *x, double *y, const double *b, const
 void launch_spmv_abs(const Op &A, const double *x, double *y, hipStream_t s) {
     SpmvArgs a = spmv_args(A, x, y, nullptr, nullptr);
     k_spmv_abs<<<nblk(a.N, 256), 256, 0, s>>>(a);
+    KCHECK();
+}
+
+void launch_transpose_op(const Op &A, Op &AT, const int *opp, hipStream_t s) {
+    SpmvArgs a = spmv_args(A, nullptr, nullptr, nullptr, nullptr);
+    k_transpose_op<<<nblk(a.N, 256), 256, 0, s>>>(a, opp, AT.coef.p);
     KCHECK();
 }
 

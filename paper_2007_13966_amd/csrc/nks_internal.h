@@ -166,6 +166,7 @@ void launch_spmv(const Op &A, const double *x, double *y, const double *b, const
                  hipStream_t s);             // y = A x, or y = b - A x when b != nullptr
 void launch_spmv_t(const Op &A, const double *x, double *y, const int *opp, hipStream_t s);
 void launch_spmv_abs(const Op &A, const double *x, double *y, hipStream_t s);
+void launch_transpose_op(const Op &A, Op &AT, const int *opp, hipStream_t s);   // same stencil, opp[q] = slot of -off_q
 void launch_axpby(const Space &sp, double a, const double *x, double b, double *y,
                   const int *mask, hipStream_t s);   // y = a x + b y
 void launch_copy_scale_blk(const Space &sp, const double *x, const double *scale, int col,

@@ -252,9 +252,10 @@ __global__ void k_hydrostatic(const Blk *blk, int B, int ncol_total, const int *
 
 // ---------------------------------------------------------------- dF/dlnK transpose
 // out_c = sum over faces (c,n): (lam_c - lam_n) * lambda_up dPhi_cn * T K_n/(K_c + K_n),
-// K the component normal to the face (dT/dln K_c = T K_n/(K_c + K_n)).
+// K the component normal to the face (dT/dln K_c = T K_n/(K_c + K_n)); ln K_c
+// scales all three components of cell c together.  accumulate: out += instead of =.
 __global__ void k_dlogk_t(FluxArgs A, const double *kx, const double *ky, const double *kz,
-                          const double *lam, double *out) {
+                          const double *lam, double *out, int accumulate) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.N) return;
     const CellPos c = cell_pos(A.blk, A.B, i);
@@ -274,7 +275,25 @@ __global__ void k_dlogk_t(FluxArgs A, const double *kx, const double *ky, const 
     if (c.x + 1 < c.nx) term(i + 1, A.tx[i], 0.0, kx[i], kx[i + 1]);
     if (c.y + 1 < c.ny) term(i + sy, A.ty[i], 0.0, ky[i], ky[i + sy]);
     if (A.dim == 3 && c.z + 1 < c.nz) term(i + sz, A.tz[i], -dz, kz[i], kz[i + sz]);
-    out[i] = acc;
+    out[i] = accumulate ? out[i] + acc : acc;
+}
+
+// ---------------------------------------------------------------- adjoint right-hand side
+// Step n of the discrete adjoint: out = -dG/dp^n - (V phi/dt) m'(p^n) (c1 lam1 + c2 lam2),
+// where c1 (c2) is the coefficient of m(p^n) in the accumulation of step n+1
+// (n+2): -1 or -2 (BDF1 or BDF2) and 1/2 (BDF2); absent terms have null vectors.
+__global__ void k_adj_rhs(int N, double a, double b, double RT, const double *pn, const double *pv,
+                          double inv_dt, double c1, const double *l1, double c2, const double *l2,
+                          const double *dg, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double m, dm;
+    bool bad;
+    scaled_density(a, b, RT, pn[i], m, dm, bad);
+    double c = 0.0;
+    if (l1) c += c1 * l1[i];
+    if (l2) c += c2 * l2[i];
+    out[i] = -(dg ? dg[i] : 0.0) - pv[i] * inv_dt * dm * c;
 }
 
 // ---------------------------------------------------------------- host side
@@ -349,10 +368,17 @@ void launch_hydrostatic(Grid &g, double p_top, double *p) {
     HIPC(hipStreamSynchronize(g.s));
 }
 
-void launch_dlogk_t(Grid &g, const double *p, const double *lam, double *out) {
+void launch_dlogk_t(Grid &g, const double *p, const double *lam, double *out, bool accumulate) {
     launch_props(g, p);
     FluxArgs A = flux_args(g, p, 1.0, 1, nullptr, nullptr);
-    k_dlogk_t<<<nblk(A.N, 256), 256, 0, g.s>>>(A, g.kx.p, g.ky.p, g.kz.p, lam, out);
+    k_dlogk_t<<<nblk(A.N, 256), 256, 0, g.s>>>(A, g.kx.p, g.ky.p, g.kz.p, lam, out, accumulate ? 1 : 0);
+    KCHECK();
+}
+
+void launch_adj_rhs(Grid &g, const double *pn, double dt, double c1, const double *l1, double c2,
+                    const double *l2, const double *dg, double *out) {
+    const int N = g.sp.N;
+    k_adj_rhs<<<nblk(N, 256), 256, 0, g.s>>>(N, g.a, g.b, g.RT, pn, g.pv.p, 1.0 / dt, c1, l1, c2, l2, dg, out);
     KCHECK();
 }
 

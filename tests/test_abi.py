@@ -38,7 +38,8 @@ def test_library_exports_every_declared_symbol(built):
 
 def test_struct_layouts_match_c(built, tmp_path):
     structs = ["nks_fluid", "nks_reservoir_desc", "nks_grid_desc", "nks_ras_desc",
-               "nks_gmres_desc", "nks_gmres_stats", "nks_newton_desc", "nks_newton_stats"]
+               "nks_gmres_desc", "nks_gmres_stats", "nks_newton_desc", "nks_newton_stats",
+               "nks_adjoint_stats"]
     src = tmp_path / "probe.c"
     body = "\n".join(f'printf("{s} %zu\\n", sizeof({s}));' for s in structs)
     src.write_text(f'#include <stdio.h>\n#include "nks.h"\nint main(void){{{body} return 0;}}\n')
@@ -58,3 +59,10 @@ def test_error_path_without_gpu_work(built):
     assert b"descriptor" in lib.nks_last_error()
     assert lib.nks_ras_apply(None, None, None) == -1
     assert lib.nks_destroy_grid(None) == 0
+
+
+def test_adjoint_argument_checks_without_gpu_work(built):
+    lib = built.load()
+    assert lib.nks_adjoint(None, 1, None, None, 1.0, None, None, None, None, None, None) == -1
+    assert lib.nks_matrix_transpose(None, None) == -1
+    assert lib.nks_ras_apply_transpose(None, None, None) == -1

@@ -144,6 +144,16 @@ def test_tile_option_sets_box_counts(orc):
     assert np.allclose(M, Md, rtol=1e-10, atol=1e-10 * np.abs(Md).max())
 
 
+@pytest.mark.parametrize("variant", ["left_ras", "as", "right_ras"])
+def test_onelevel_transpose_apply_is_the_transpose(orc, variant):
+    # the dense operator of apply_transpose is the transpose of apply's (ILU(0) subsolves)
+    case, prob, J = _jac(orc, nx=9, ny=8, px=3, py=2, overlap=(2,), variant=variant)
+    mg = orc.Multilevel(prob.rec, J, case.solver)
+    M = _apply_dense(mg.apply, J.n)
+    MT = _apply_dense(mg.apply_transpose, J.n)
+    assert np.allclose(MT, M.T, rtol=1e-12, atol=1e-12 * np.abs(M).max())
+
+
 def test_zero_overlap_is_block_jacobi(orc):
     # delta = 0: AS, left-RAS and right-RAS all reduce to block Jacobi
     ops = []
