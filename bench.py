@@ -172,6 +172,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the subdomain tile edge (8, 16, 32) and fine overlap (1, 2) with "
+                         "nks_ras_autotune at the initial state before timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB five times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
@@ -197,6 +200,18 @@ def main():
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 5}))
         return
     case = getattr(S, WORKLOADS[args.workload])()
+    tuning = None
+    if args.autotune:
+        g0 = P.Grid(case.problems)
+        p0 = g0.initial_pressure()
+        tuned, table = g0.autotune(p0, p0, p0, case.dt, 1, case.solver)
+        del g0
+        case = S.with_solver(case, tile=tuned.tile, overlap=tuned.overlap)
+        tuning = dict(tile=list(tuned.tile), overlap=list(tuned.overlap), table=table)
+        log(f"autotuned: tile {tuned.tile}, overlap {tuned.overlap}")
+        for e in table:
+            log(f"  tile {e['tile']:3d} overlap {e['overlap']}: ok {e['ok']} its {e['iterations']:3d} "
+                f"setup {e['setup_ms']:.2f} ms solve {e['solve_ms']:.2f} ms")
     s64 = S.with_solver(case, precision="fp64").solver
     log(f"workload {case.name}: {sum(r.N for r in case.problems)} cells")
     nbytes, nexts = apply_bytes(case.problems, s64, "fp64")
@@ -235,6 +250,8 @@ def main():
             "newton_its_per_step": float(np.mean(nits)),
             "gmres_its_per_newton": float(np.sum(lits) / max(1, np.sum(nits))),
             "rel_res": s64.eps_r,
+            "tile": list(s64.tile),
+            "autotune": tuning,
         },
         "roofline": {
             "kernel": "k_ras_apply (fine level, one-level left-RAS ILU(0) sweeps)",

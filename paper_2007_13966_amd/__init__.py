@@ -268,6 +268,32 @@ class Grid:
             out["lambda"] = lams
         return grad, out
 
+    def autotune(self, p, pn, pnm1, dt, order, settings, tiles=(8, 16, 32), overlaps=(1, 2), repeats=2,
+                 rtol=None, atol=None):
+        """nks_ras_autotune: returns (settings with the best tile and fine
+        overlap, list of per-candidate timings)."""
+        import dataclasses
+        rd = ras_desc(settings)
+        nd = newton_desc(settings)
+        flex = nd.flexible if nd.flexible >= 0 else int(settings.levels > 1 or settings.precision != "fp64")
+        gd = L.nks_gmres_desc(nd.restart, settings.eta_r if rtol is None else rtol,
+                              settings.eta_a if atol is None else atol, nd.maxit, flex, 0)
+        ti = (C.c_int * len(tiles))(*tiles)
+        ov = (C.c_int * len(overlaps))(*overlaps)
+        best = L.nks_ras_desc()
+        tab = (L.nks_autotune_entry * (len(tiles) * len(overlaps)))()
+        with _Ordered(self):
+            check(lib().nks_ras_autotune(self.h, _vp(p), _vp(pn), _vp(pnm1 if pnm1 is not None else pn),
+                                         float(dt), int(order), C.byref(rd), ti, len(tiles), ov,
+                                         len(overlaps), C.byref(gd), int(repeats), C.byref(best), tab))
+        ovl = list(settings.overlap)
+        ovl[0] = best.overlap[0]
+        tz = best.tz if best.tz > 0 else 0
+        tuned = dataclasses.replace(settings, tile=(best.tx, best.ty, tz), overlap=tuple(ovl))
+        table = [dict(tile=e.tile, overlap=e.overlap, ok=bool(e.ok), iterations=e.iterations,
+                      setup_ms=e.setup_ms, solve_ms=e.solve_ms) for e in tab]
+        return tuned, table
+
     def newton_step(self, p, pn, pnm1, dt, order, settings, raise_on_fail=True):
         st = L.nks_newton_stats()
         nd, rd = newton_desc(settings), ras_desc(settings)

@@ -1063,3 +1063,103 @@ int nks_adjoint(nks_grid *gh, int nsteps, const double *const *p_hist, const int
         if (S.status) fail(NKS_ENOTCONVERGED, "an adjoint linear solve did not converge");
     });
 }
+
+// ------------------------------------------------------------------ tile / overlap autotuner
+int nks_ras_autotune(nks_grid *gh, const double *p, const double *pn, const double *pnm1, double dt, int order,
+                     const nks_ras_desc *base, const int *tiles, int ntiles, const int *overlaps, int noverlaps,
+                     const nks_gmres_desc *gd, int repeats, nks_ras_desc *best, nks_autotune_entry *table) {
+    return guard([&] {
+        if (!gh || !p || !pn || !(dt > 0) || (order != 1 && order != 2) || (order == 2 && !pnm1) || !base ||
+            !tiles || ntiles < 1 || !overlaps || noverlaps < 1 || !gd || !best || repeats < 1)
+            fail(NKS_EINVAL, "bad arguments");
+        if (gd->restart < 1 || gd->restart > 30 || gd->maxit < 1) fail(NKS_EINVAL, "bad GMRES descriptor");
+        check_ras_desc(base);
+        for (int i = 0; i < ntiles; ++i)
+            if (tiles[i] < 1) fail(NKS_EINVAL, "tile edges must be positive");
+        for (int i = 0; i < noverlaps; ++i)
+            if (overlaps[i] < 0) fail(NKS_EINVAL, "overlaps must be non-negative");
+        Grid &g = gh->g;
+        const int N = g.sp.N;
+        hipStream_t s = g.s;
+        Alloc *al = &g.al;
+        // the first Newton system at the given state: J s = -F
+        Matrix J;
+        fine_matrix(J, g);
+        DBuf<double> F, b, x;
+        F.alloc(al, N);
+        b.alloc(al, N);
+        x.alloc(al, N);
+        launch_history(g, pn, pnm1 ? pnm1 : pn, order);
+        launch_props(g, p);
+        launch_flux(g, p, dt, order, F.p, J.op.coef.p);
+        launch_axpby(g.sp, -1.0, F.p, 0.0, b.p, nullptr, s);
+        Gmres gm;
+        gm.ensure(al, g.sp, gd->restart, gd->flexible != 0, s);
+        double best_t = INFINITY;
+        int k = 0;
+        bool any = false;
+        for (int it = 0; it < ntiles; ++it) {
+            for (int io = 0; io < noverlaps; ++io, ++k) {
+                nks_ras_desc d = *base;
+                d.tx = d.ty = tiles[it];
+                d.tz = g.dim == 3 ? tiles[it] : 0;
+                d.overlap[0] = overlaps[io];
+                nks_autotune_entry e{};
+                e.tile = tiles[it];
+                e.overlap = overlaps[io];
+                e.ok = 0;
+                try {
+                    Ras M;
+                    M.build(&J, d);
+                    double t_setup = 0, t_solve = 0;
+                    int its = 0;
+                    // repeats + 1 runs, the first untimed (LDS attributes, first touch)
+                    for (int r = 0; r <= repeats; ++r) {
+                        HIPC(hipStreamSynchronize(s));
+                        double t0 = now();
+                        M.factor();
+                        M.check_pivots();
+                        HIPC(hipStreamSynchronize(s));
+                        double t1 = now();
+                        launch_axpby(g.sp, 0.0, b.p, 0.0, x.p, nullptr, s);
+                        MatVec A = [&](const double *xx, double *yy, const double *bb, const int *mk) {
+                            launch_spmv(J.op, xx, yy, bb, mk, s);
+                        };
+                        Precond P = [&](const double *rr, double *zz, const int *mk) { M.apply(rr, zz, mk); };
+                        GmOpts o;
+                        o.rtol = gd->rtol;
+                        o.atol = gd->atol;
+                        o.maxit = gd->maxit;
+                        o.flexible = gd->flexible != 0;
+                        gm.solve(A, P, b.p, x.p, true, o, nullptr, s);
+                        std::vector<int> itv, conv;
+                        std::vector<double> res;
+                        gm.stats(itv, res, conv, s);
+                        double t2 = now();
+                        if (r > 0) {
+                            t_setup += t1 - t0;
+                            t_solve += t2 - t1;
+                        }
+                        its = 0;
+                        for (int q = 0; q < g.sp.B; ++q) its = std::max(its, itv[q]);
+                    }
+                    e.setup_ms = 1e3 * t_setup / repeats;
+                    e.solve_ms = 1e3 * t_solve / repeats;
+                    e.iterations = its;
+                    e.ok = 1;
+                    const double t = e.setup_ms + e.solve_ms;
+                    if (t < best_t) {
+                        best_t = t;
+                        *best = d;
+                        any = true;
+                    }
+                } catch (const Error &err) {
+                    (void)hipGetLastError();
+                    (void)hipStreamSynchronize(s);
+                }
+                if (table) table[k] = e;
+            }
+        }
+        if (!any) fail(NKS_EINVAL, "no candidate tile/overlap could be set up");
+    });
+}

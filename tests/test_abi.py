@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(built):
 def test_struct_layouts_match_c(built, tmp_path):
     structs = ["nks_fluid", "nks_reservoir_desc", "nks_grid_desc", "nks_ras_desc",
                "nks_gmres_desc", "nks_gmres_stats", "nks_newton_desc", "nks_newton_stats",
-               "nks_adjoint_stats"]
+               "nks_adjoint_stats", "nks_autotune_entry"]
     src = tmp_path / "probe.c"
     body = "\n".join(f'printf("{s} %zu\\n", sizeof({s}));' for s in structs)
     src.write_text(f'#include <stdio.h>\n#include "nks.h"\nint main(void){{{body} return 0;}}\n')
