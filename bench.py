@@ -136,7 +136,7 @@ def run_gpu(P, case, settings, warmup, steps, profile=True):
     if profile:
         import ctypes as C
         for name in ["ras_apply_l0", "ras_apply_l1", "ras_apply_l2", "spmv_l0", "spmv_l1",
-                     "gmres_orth", "residual_jacobian", "ilu_factor_l0", "ilu_factor_l1", "rap_l1"]:
+                     "gmres_arnoldi", "residual_jacobian", "ilu_factor_l0", "ilu_factor_l1", "rap_l1"]:
             c = C.c_int()
             P.check(P.lib().nks_profile_durations(name.encode(), None, 0, C.byref(c)))
             if c.value:
@@ -250,6 +250,7 @@ def main():
             "newton_its_per_step": float(np.mean(nits)),
             "gmres_its_per_newton": float(np.sum(lits) / max(1, np.sum(nits))),
             "rel_res": s64.eps_r,
+            "rel_res_reached": [x["fnorm"] / x["fnorm0"] for x in st],
             "tile": list(s64.tile),
             "autotune": tuning,
         },

@@ -724,7 +724,7 @@ int nks_gmres_solve(nks_matrix *J, nks_ras *M, const double *b, double *x, const
         o.maxit = d->maxit;
         o.flexible = d->flexible != 0;
         o.check_every = 1;
-        gm.solve(A, P, b, x, false, o, nullptr, g.s);
+        gm.solve(A, P, b, x, false, o, nullptr, g.s, d->transpose ? nullptr : &J->m.op);
         std::vector<int> its, conv;
         std::vector<double> res;
         gm.stats(its, res, conv, g.s);
@@ -856,7 +856,7 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             o.maxit = nd->maxit;
             o.flexible = flex;
             o.check_every = 1;
-            W.gm.solve(A, P, W.b.p, W.s.p, true, o, W.mask.p, s);
+            W.gm.solve(A, P, W.b.p, W.s.p, true, o, W.mask.p, s, &W.J->op);
             std::vector<int> its, conv;
             std::vector<double> res;
             W.gm.stats(its, res, conv, s);
@@ -1040,7 +1040,7 @@ int nks_adjoint(nks_grid *gh, int nsteps, const double *const *p_hist, const int
             o.maxit = gd->maxit;
             o.flexible = gd->flexible != 0;
             o.check_every = 1;
-            W.gm.solve(A, P, W.rhs.p, lam, true, o, nullptr, s);
+            W.gm.solve(A, P, W.rhs.p, lam, true, o, nullptr, s, &JT.op);
             std::vector<int> its, conv;
             std::vector<double> res;
             W.gm.stats(its, res, conv, s);
@@ -1131,7 +1131,7 @@ int nks_ras_autotune(nks_grid *gh, const double *p, const double *pn, const doub
                         o.atol = gd->atol;
                         o.maxit = gd->maxit;
                         o.flexible = gd->flexible != 0;
-                        gm.solve(A, P, b.p, x.p, true, o, nullptr, s);
+                        gm.solve(A, P, b.p, x.p, true, o, nullptr, s, &J.op);
                         std::vector<int> itv, conv;
                         std::vector<double> res;
                         gm.stats(itv, res, conv, s);

@@ -28,6 +28,7 @@ struct GmDev {
     double *hj;
     double *tol, *beta, *res;
     int *active, *conv, *kdim, *its, *upd;
+    int *active2;     // second activity buffer: iteration j reads buffer j%2, writes the other
     int *flag;        // host-mapped, 4 slots of nb: iteration j (slot j%3) and restart (slot 3) activity
     int nb;
     int m, maxit;
@@ -57,9 +58,11 @@ struct Gmres {
     void ensure(Alloc *al, const Space &sp, int m, bool flexible, hipStream_t s);
     GmDev dev(double rtol, double atol, int maxit);
     bool any_active(hipStream_t s);
-    // x: initial guess unless x_zero (then x must already hold zeros)
+    // x: initial guess unless x_zero (then x must already hold zeros).  Aop:
+    // the stencil operator behind A, when it is one (fuses the product with
+    // the first Gram-Schmidt pass); A is still used for residuals.
     void solve(const MatVec &A, const Precond &M, const double *b, double *x, bool x_zero,
-               const GmOpts &o, const int *outer_mask, hipStream_t s);
+               const GmOpts &o, const int *outer_mask, hipStream_t s, const Op *Aop = nullptr);
     void stats(std::vector<int> &its, std::vector<double> &res, std::vector<int> &conv,
                hipStream_t s);
     ~Gmres();

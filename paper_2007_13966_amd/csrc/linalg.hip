@@ -56,7 +56,46 @@ struct SpmvArgs {
     const int *mask;
 };
 
-__global__ void k_spmv(SpmvArgs a) {
+// Stencil offsets staged once per workgroup into LDS, (dx, dy, dz) packed in
+// the low three bytes of an int.  All threads must call it.
+__device__ __forceinline__ void stage_offsets(const int8_t *off, int K, int *sh) {
+    for (int q = threadIdx.x; q < K; q += blockDim.x)
+        sh[q] = (off[3 * q] & 0xff) | ((off[3 * q + 1] & 0xff) << 8) | ((off[3 * q + 2] & 0xff) << 16);
+    __syncthreads();
+}
+
+// sum_q coef[q][i] x[i + off_q] over the in-reservoir neighbours of cell i at
+// (cx, cy, cz), q in increasing order.  Loads are issued eight points at a
+// time from always-valid addresses (an outside neighbour reads x[i] and
+// contributes an exact zero), so the sum is the same as skipping them.
+__device__ __forceinline__ double stencil_dot(const int *sh, int K, const double *coef, size_t N,
+                                              const double *x, int i, int cx, int cy, int cz, const Blk &k) {
+    double s = 0.0;
+    const int nxy = k.nx * k.ny;
+    for (int q0 = 0; q0 < K; q0 += 8) {
+        double cv[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = min(q0 + u, K - 1);
+            const int o = sh[q];
+            const int dx = (int)(int8_t)(o & 0xff), dy = (int)(int8_t)((o >> 8) & 0xff),
+                      dz = (int)(int8_t)((o >> 16) & 0xff);
+            const bool in = q0 + u < K && (unsigned)(cx + dx) < (unsigned)k.nx &&
+                            (unsigned)(cy + dy) < (unsigned)k.ny && (unsigned)(cz + dz) < (unsigned)k.nz;
+            const int j = in ? i + dx + k.nx * dy + nxy * dz : i;
+            const double c = coef[(size_t)q * N + i];
+            xv[u] = x[j];
+            cv[u] = in ? c : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += cv[u] * xv[u];
+    }
+    return s;
+}
+
+__global__ void __launch_bounds__(256) k_spmv(SpmvArgs a) {
+    __shared__ int sh[MAXK];
+    stage_offsets(a.off, a.K, sh);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
     const int bi = find_blk(a.blk, a.B, i);
@@ -64,13 +103,7 @@ __global__ void k_spmv(SpmvArgs a) {
     const Blk k = a.blk[bi];
     const int l = i - k.off;
     const int x = l % k.nx, y = (l / k.nx) % k.ny, z = l / (k.nx * k.ny);
-    double s = 0.0;
-    for (int q = 0; q < a.K; ++q) {
-        const int dx = a.off[3 * q], dy = a.off[3 * q + 1], dz = a.off[3 * q + 2];
-        const int xx = x + dx, yy = y + dy, zz = z + dz;
-        if (xx < 0 || xx >= k.nx || yy < 0 || yy >= k.ny || zz < 0 || zz >= k.nz) continue;
-        s += a.coef[(size_t)q * a.N + i] * a.x[i + dx + k.nx * (dy + k.ny * dz)];
-    }
+    const double s = stencil_dot(sh, a.K, a.coef, a.N, a.x, i, x, y, z, k);
     a.y[i] = a.b ? a.b[i] - s : s;
 }
 
@@ -212,49 +245,73 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// column sums of this workgroup's registers into part_row[0..nc)
-__device__ __forceinline__ void chunk_columns(const double (&acc)[MAXCOL], int nc, double *part_row) {
-    __shared__ double sh[4][MAXCOL];
+// Row sums (16 lanes) by DPP moves: pair swap, quad swap, half-row mirror,
+// row mirror.  Every lane of a row ends with the same value, bitwise: each
+// step adds the same two operands in either order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double row_sum(double v) {
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return v;
+}
+
+// Sums over the workgroup (4 waves = 16 rows of 16 lanes) of v[c], c < NC:
+// row sums by DPP, the 16 row sums through LDS, added in row order by
+// thread c < nc into dst(c).  NC is a compile-time bound; columns past nc
+// hold zeros and are not stored.
+template <int NC, typename Store>
+__device__ __forceinline__ void workgroup_columns(double (&v)[NC], int nc, Store dst) {
+    __shared__ double sh[16][NC];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int c = 0; c < MAXCOL; ++c) {
-        if (c < nc) {
-            const double v = wave_sum(acc[c]);
-            if (lane == 0) sh[w][c] = v;
-        }
+    for (int c = 0; c < NC; ++c) v[c] = row_sum(v[c]);
+    if ((lane & 15) == 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sh[w * 4 + (lane >> 4)][c] = v[c];
     }
     __syncthreads();
     if ((int)threadIdx.x < nc) {
         double t = 0.0;
-        const int nw = blockDim.x >> 6;
-        for (int k = 0; k < nw; ++k) t += sh[k][threadIdx.x];
-        part_row[threadIdx.x] = t;
+        const int nr = (blockDim.x >> 6) * 4;
+        for (int k = 0; k < nr; ++k) t += sh[k][threadIdx.x];
+        dst(threadIdx.x, t);
     }
 }
 
+// column sums of this workgroup's registers into part[c * ns + blockIdx.x]
+// (column-major over the ns chunks, so the totals read coalesced)
+template <int NC>
+__device__ __forceinline__ void chunk_columns(const double (&acc)[MAXCOL], int nc, double *part, int ns) {
+    double v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = acc[c];
+    workgroup_columns<NC>(v, nc, [&](int c, double t) { part[(size_t)c * ns + blockIdx.x] = t; });
+}
+
 // totals of the nc partial columns of reservoir b (chunks [q0, q1), at most
-// blockDim chunks) into out[0..nc) in LDS, visible to the whole workgroup
-__device__ __forceinline__ void block_totals(const double *part, int q0, int q1, int nc, double *out) {
-    __shared__ double sh[4][MAXCOL];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+// blockDim chunks, column stride ns) into out[0..nc) in LDS, visible to the
+// whole workgroup.  Branch-free over the NC columns: every load has a valid
+// address (clamped column and chunk) and out-of-range values are zeroed.
+template <int NC>
+__device__ __forceinline__ void block_totals(const double *part, int q0, int q1, int nc, double *out, int ns) {
     const int q = q0 + (int)threadIdx.x;
-    double v[MAXCOL];
+    const bool qin = q < q1;
+    const int qq = qin ? q : q0;
+    double v[NC];
 #pragma unroll
-    for (int c = 0; c < MAXCOL; ++c) v[c] = (c < nc && q < q1) ? part[(size_t)q * nc + c] : 0.0;
-#pragma unroll
-    for (int c = 0; c < MAXCOL; ++c) {
-        if (c < nc) {
-            const double t = wave_sum(v[c]);
-            if (lane == 0) sh[w][c] = t;
-        }
+    for (int c = 0; c < NC; ++c) {
+        const double x = part[(size_t)min(c, max(nc - 1, 0)) * ns + qq];
+        v[c] = (c < nc && qin) ? x : 0.0;
     }
-    __syncthreads();
-    if ((int)threadIdx.x < nc) {
-        double t = 0.0;
-        const int nw = blockDim.x >> 6;
-        for (int k = 0; k < nw; ++k) t += sh[k][threadIdx.x];
-        out[threadIdx.x] = t;
-    }
+    workgroup_columns<NC>(v, nc, [&](int c, double t) { out[c] = t; });
     __syncthreads();
 }
 
@@ -279,15 +336,17 @@ __global__ void __launch_bounds__(RED_THREADS) k_partials(const Chunk *chunks, c
             }
         }
     }
-    chunk_columns(acc, ncols, part + (size_t)blockIdx.x * ncols);
+    if (ncols == 1) chunk_columns<1>(acc, 1, part, gridDim.x);
+    else chunk_columns<MAXCOL>(acc, ncols, part, gridDim.x);
 }
 
 // one workgroup per reservoir: out[b*ncols + c]
 __global__ void __launch_bounds__(RED_THREADS) k_totals(const int *cfirst, const double *part, int ncols,
-                                                        double *out) {
+                                                        double *out, int ns) {
     __shared__ double tot[MAXCOL];
     const int b = blockIdx.x;
-    block_totals(part, cfirst[b], cfirst[b + 1], ncols, tot);
+    if (ncols == 1) block_totals<1>(part, cfirst[b], cfirst[b + 1], 1, tot, ns);
+    else block_totals<MAXCOL>(part, cfirst[b], cfirst[b + 1], ncols, tot, ns);
     if ((int)threadIdx.x < ncols) out[(size_t)b * ncols + threadIdx.x] = tot[threadIdx.x];
 }
 
@@ -296,7 +355,7 @@ void launch_block_dots(const Space &sp, Reducer &R, const double *x, const doubl
     if (ncols > MAXCOL) fail(NKS_EINVAL, "at most %d columns per reduction", MAXCOL);
     k_partials<<<(int)sp.hchunk.size(), RED_THREADS, 0, s>>>(sp.chunk.p, x, ys, ncols, R.part.p, mask, 0);
     KCHECK();
-    k_totals<<<sp.B, RED_THREADS, 0, s>>>(sp.cfirst.p, R.part.p, ncols, out);
+    k_totals<<<sp.B, RED_THREADS, 0, s>>>(sp.cfirst.p, R.part.p, ncols, out, (int)sp.hchunk.size());
     KCHECK();
 }
 
@@ -304,7 +363,7 @@ void launch_block_norm2(const Space &sp, Reducer &R, const double *x, double *ou
                         hipStream_t s) {
     k_partials<<<(int)sp.hchunk.size(), RED_THREADS, 0, s>>>(sp.chunk.p, x, nullptr, 1, R.part.p, mask, 1);
     KCHECK();
-    k_totals<<<sp.B, RED_THREADS, 0, s>>>(sp.cfirst.p, R.part.p, 1, out);
+    k_totals<<<sp.B, RED_THREADS, 0, s>>>(sp.cfirst.p, R.part.p, 1, out, (int)sp.hchunk.size());
     KCHECK();
 }
 
@@ -319,7 +378,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_begin(const Chunk *chunks, c
     const Chunk ch = chunks[blockIdx.x];
     const int b = ch.blk;
     const int q0 = cfirst[b];
-    block_totals(part, q0, cfirst[b + 1], 1, tot);
+    block_totals<1>(part, q0, cfirst[b + 1], 1, tot, gridDim.x);
     const double beta = sqrt(tot[0]);
     const bool lead = (int)blockIdx.x == q0;
     const int its = first ? 0 : st.its[b];
@@ -352,7 +411,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_norm_partials(const Chunk *c
     double acc[MAXCOL];
     acc[0] = 0.0;
     for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) acc[0] += r[i] * r[i];
-    chunk_columns(acc, 1, part + blockIdx.x);
+    chunk_columns<1>(acc, 1, part, gridDim.x);
 }
 
 // tol from ||b|| (x0 != 0), lead chunk of each reservoir
@@ -362,38 +421,92 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_tol(const Chunk *chunks, con
     const Chunk ch = chunks[blockIdx.x];
     const int q0 = cfirst[ch.blk];
     if ((int)blockIdx.x != q0) return;
-    block_totals(part, q0, cfirst[ch.blk + 1], 1, tot);
+    block_totals<1>(part, q0, cfirst[ch.blk + 1], 1, tot, gridDim.x);
     if (threadIdx.x == 0) st.tol[ch.blk] = fmax(st.rtol * sqrt(tot[0]), st.atol);
 }
 
-// CGS pass 1 partials: V[0..j]^T w
-__global__ void __launch_bounds__(RED_THREADS) k_gm_dots(const Chunk *chunks, const double *w,
-                                                         const double *const *V, int j, double *part, GmDev st) {
+// Krylov vector pointers by value (kernel arguments land in scalar registers)
+struct VPtrs {
+    const double *p[MAXCOL];
+};
+
+// One Arnoldi step j of classical Gram-Schmidt with one reorthogonalisation
+// (CGS2) takes three kernels after the preconditioner:
+//   spmv_dots    w = A z_j and the pass-1 partials V[0..j]^T w
+//                (or gm_dots when A is not a stencil operator);
+//   update_dots  h1 = pass-1 totals (the lead chunk stores H[:, j] = h1),
+//                w -= V h1, pass-2 partials V^T w and w.w;
+//   finish       h2 = pass-2 totals, h_{j+1,j} = sqrt(w.w - h2.h2) (w is
+//                already orthogonal to V to working precision, so h2 is a
+//                rounding-size correction and the subtraction loses nothing),
+//                v_{j+1} = (w - V h2) / h_{j+1,j}; the lead chunk adds h2 to
+//                H[:, j] and applies the Givens rotations.
+// Activity flags are double-buffered: iteration j reads act_j and only the
+// lead chunk of a reservoir writes act_{j+1}, so no workgroup reads a flag
+// that another rewrites in the same kernel.
+
+// pass-1 partials of w = A z with V[0..j] (stencil operator, chunk grid)
+__global__ void __launch_bounds__(RED_THREADS) k_gm_spmv_dots(const Chunk *chunks, SpmvArgs a, VPtrs V, int j,
+                                                              double *part, const int *act) {
+    __shared__ int sh[MAXK];
+    stage_offsets(a.off, a.K, sh);
     const Chunk ch = chunks[blockIdx.x];
     const int nc = j + 1;
     double acc[MAXCOL];
 #pragma unroll
     for (int c = 0; c < MAXCOL; ++c) acc[c] = 0.0;
-    if (st.active[ch.blk]) {
+    if (act[ch.blk]) {
+        const Blk k = a.blk[ch.blk];
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
+            double vv[MAXCOL];
+#pragma unroll
+            for (int c = 0; c < MAXCOL; ++c)
+                if (c < nc) vv[c] = V.p[c][i];
+            const int l = i - k.off;
+            const int x = l % k.nx, y = (l / k.nx) % k.ny, z = l / (k.nx * k.ny);
+            const double wi = stencil_dot(sh, a.K, a.coef, a.N, a.x, i, x, y, z, k);
+            a.y[i] = wi;
+#pragma unroll
+            for (int c = 0; c < MAXCOL; ++c)
+                if (c < nc) acc[c] += wi * vv[c];
+        }
+    }
+    chunk_columns<MAXCOL>(acc, nc, part, gridDim.x);
+}
+
+// pass-1 partials V[0..j]^T w (w from a generic operator)
+__global__ void __launch_bounds__(RED_THREADS) k_gm_dots(const Chunk *chunks, const double *w, VPtrs V, int j,
+                                                         double *part, const int *act) {
+    const Chunk ch = chunks[blockIdx.x];
+    const int nc = j + 1;
+    double acc[MAXCOL];
+#pragma unroll
+    for (int c = 0; c < MAXCOL; ++c) acc[c] = 0.0;
+    if (act[ch.blk]) {
+        for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
+            double vv[MAXCOL];
+#pragma unroll
+            for (int c = 0; c < MAXCOL; ++c)
+                if (c < nc) vv[c] = V.p[c][i];
             const double wi = w[i];
 #pragma unroll
             for (int c = 0; c < MAXCOL; ++c)
-                if (c < nc) acc[c] += wi * V[c][i];
+                if (c < nc) acc[c] += wi * vv[c];
         }
     }
-    chunk_columns(acc, nc, part + (size_t)blockIdx.x * nc);
+    chunk_columns<MAXCOL>(acc, nc, part, gridDim.x);
 }
 
-// h1 = totals of pass 1 (lead chunk stores H[:, j] = h1); w -= V h1; pass 2 partials V^T w
+// h1 = pass-1 totals (lead chunk stores H[:, j]); w -= V h1; pass-2 partials
+// V^T w in columns 0..j and w.w in column j+1
 __global__ void __launch_bounds__(RED_THREADS) k_gm_update_dots(const Chunk *chunks, const int *cfirst, double *w,
-                                                                const double *const *V, int j,
-                                                                const double *pin, double *pout, GmDev st) {
+                                                                VPtrs V, int j, const double *pin, double *pout,
+                                                                GmDev st, const int *act) {
     __shared__ double hc[MAXCOL];
     const Chunk ch = chunks[blockIdx.x];
     const int b = ch.blk, nc = j + 1;
-    const bool on = st.active[b];
-    if (on) block_totals(pin, cfirst[b], cfirst[b + 1], nc, hc);
+    const bool on = act[b];
+    if (on) block_totals<MAXCOL>(pin, cfirst[b], cfirst[b + 1], nc, hc, gridDim.x);
     if (on && (int)blockIdx.x == cfirst[b] && (int)threadIdx.x < nc)
         st.H[((size_t)b * (st.m + 1) + threadIdx.x) * st.m + j] = hc[threadIdx.x];
     double acc[MAXCOL];
@@ -402,92 +515,93 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_update_dots(const Chunk *chu
     if (on) {
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
             double vv[MAXCOL];
+#pragma unroll
+            for (int c = 0; c < MAXCOL; ++c)
+                if (c < nc) vv[c] = V.p[c][i];
             double t = w[i];
 #pragma unroll
             for (int c = 0; c < MAXCOL; ++c)
-                if (c < nc) {
-                    vv[c] = V[c][i];
-                    t -= hc[c] * vv[c];
-                }
+                if (c < nc) t -= hc[c] * vv[c];
             w[i] = t;
 #pragma unroll
-            for (int c = 0; c < MAXCOL; ++c)
+            for (int c = 0; c < MAXCOL - 1; ++c)
                 if (c < nc) acc[c] += t * vv[c];
+#pragma unroll
+            for (int c = 1; c < MAXCOL; ++c)
+                if (c == nc) acc[c] += t * t;
         }
     }
-    chunk_columns(acc, nc, pout + (size_t)blockIdx.x * nc);
+    chunk_columns<MAXCOL>(acc, nc + 1, pout, gridDim.x);
 }
 
-// h2 = totals of pass 2 (lead chunk adds to H[:, j]); w -= V h2; ||w||^2 partials
-__global__ void __launch_bounds__(RED_THREADS) k_gm_update_norm(const Chunk *chunks, const int *cfirst, double *w,
-                                                                const double *const *V, int j,
-                                                                const double *pin, double *pout, GmDev st) {
+// h2 and w.w from the pass-2 partials; v_{j+1} = (w - V h2) / h_{j+1,j};
+// the lead chunk of each reservoir updates H, the rotations and the
+// residual estimate, and decides act_{j+1} and the host flag (single writer).
+__global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, const int *cfirst, const double *w,
+                                                           VPtrs V, int j, const double *pin, double *vn, GmDev st,
+                                                           const int *act, int *act_next, int slot) {
     __shared__ double hc[MAXCOL];
     const Chunk ch = chunks[blockIdx.x];
     const int b = ch.blk, nc = j + 1;
-    const bool on = st.active[b];
-    if (on) block_totals(pin, cfirst[b], cfirst[b + 1], nc, hc);
-    if (on && (int)blockIdx.x == cfirst[b] && (int)threadIdx.x < nc)
-        st.H[((size_t)b * (st.m + 1) + threadIdx.x) * st.m + j] += hc[threadIdx.x];
-    double acc[MAXCOL];
-    acc[0] = 0.0;
-    if (on) {
+    const bool on = act[b];
+    const bool lead = (int)blockIdx.x == cfirst[b];
+    if (!on) {
+        if (lead && threadIdx.x == 0) {
+            act_next[b] = 0;
+            st.flag[slot * st.nb + b] = 0;
+        }
+        return;
+    }
+    block_totals<MAXCOL>(pin, cfirst[b], cfirst[b + 1], nc + 1, hc, gridDim.x);
+    double h2sq = 0.0;
+    for (int c = 0; c < nc; ++c) h2sq += hc[c] * hc[c];
+    const double hn = sqrt(fmax(hc[nc] - h2sq, 0.0));
+    if (hn > 0.0) {
+        const double inv = 1.0 / hn;
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
+            double vv[MAXCOL];
+#pragma unroll
+            for (int c = 0; c < MAXCOL; ++c)
+                if (c < nc) vv[c] = V.p[c][i];
             double t = w[i];
 #pragma unroll
             for (int c = 0; c < MAXCOL; ++c)
-                if (c < nc) t -= hc[c] * V[c][i];
-            w[i] = t;
-            acc[0] += t * t;
+                if (c < nc) t -= hc[c] * vv[c];
+            vn[i] = t * inv;
         }
     }
-    chunk_columns(acc, 1, pout + blockIdx.x);
-}
-
-// h_{j+1,j} = ||w|| from the partials and the Givens step of column j: one
-// workgroup per reservoir, thread 0 updates the shared state (single writer).
-__global__ void __launch_bounds__(RED_THREADS) k_gm_givens(const int *cfirst, int j, int slot, const double *pin,
-                                                           GmDev st) {
-    __shared__ double tot[MAXCOL];
-    const int b = blockIdx.x;
-    if (!st.active[b]) {
-        if (threadIdx.x == 0) st.flag[slot * st.nb + b] = 0;
-        return;
-    }
-    block_totals(pin, cfirst[b], cfirst[b + 1], 1, tot);
-    if (threadIdx.x != 0) return;
-    const double hn = sqrt(tot[0]);
+    if (!lead || threadIdx.x != 0) return;
     const int m = st.m;
     double *H = st.H + (size_t)b * (m + 1) * m;
     double *cs = st.cs + (size_t)b * m, *sn = st.sn + (size_t)b * m;
     double *g = st.g + (size_t)b * (m + 1);
-    // column j and the previous rotations in registers (independent loads)
-    double hc[MAXCOL + 1], cc[MAXCOL], ss[MAXCOL];
+    // column j (h1 + h2) and the previous rotations in registers
+    double hcol[MAXCOL + 1], cc[MAXCOL], ss[MAXCOL];
 #pragma unroll
     for (int k = 0; k < MAXCOL; ++k) {
-        hc[k] = k <= j ? H[k * m + j] : 0.0;
+        hcol[k] = k <= j ? H[k * m + j] + hc[k] : 0.0;
         cc[k] = k < j ? cs[k] : 1.0;
         ss[k] = k < j ? sn[k] : 0.0;
     }
-    hc[MAXCOL] = 0.0;
+    hcol[MAXCOL] = 0.0;
 #pragma unroll
     for (int k = 0; k < MAXCOL - 1; ++k) {
         if (k < j) {
-            const double a0 = hc[k], a1 = hc[k + 1];
-            hc[k] = cc[k] * a0 + ss[k] * a1;
-            hc[k + 1] = -ss[k] * a0 + cc[k] * a1;
+            const double a0 = hcol[k], a1 = hcol[k + 1];
+            hcol[k] = cc[k] * a0 + ss[k] * a1;
+            hcol[k + 1] = -ss[k] * a0 + cc[k] * a1;
         }
     }
     double a0 = 0.0;
 #pragma unroll
     for (int k = 0; k < MAXCOL; ++k)
-        if (k == j) a0 = hc[k];
+        if (k == j) a0 = hcol[k];
     const double den = sqrt(a0 * a0 + hn * hn);
     const double c = den > 0.0 ? a0 / den : 1.0;
     const double sg = den > 0.0 ? hn / den : 0.0;
 #pragma unroll
     for (int k = 0; k < MAXCOL; ++k)
-        if (k < j) H[k * m + j] = hc[k];
+        if (k < j) H[k * m + j] = hcol[k];
     H[j * m + j] = den;
     H[(j + 1) * m + j] = 0.0;
     cs[j] = c;
@@ -497,27 +611,17 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_givens(const int *cfirst, in
     g[j] = c * gj;
     st.its[b] += 1;
     st.kdim[b] = j + 1;
-    st.hj[(size_t)b * (m + 1) + m] = hn;   // normalisation of v_{j+1}
     const double res = fabs(g[j + 1]);
     st.res[b] = res;
-    int act = 1;
+    int nxt = 1;
     if (res <= st.tol[b] || hn == 0.0) {
         st.conv[b] = 1;
-        act = 0;
+        nxt = 0;
     } else if (st.its[b] >= st.maxit || j + 1 == m) {
-        act = 0;   // restart (or stop at maxit)
+        nxt = 0;   // restart (or stop at maxit)
     }
-    st.active[b] = act;
-    st.flag[slot * st.nb + b] = act;
-}
-
-// v_{j+1} = w / h_{j+1,j} for reservoirs still iterating
-__global__ void k_gm_next(const Blk *blk, int B, int N, const double *w, double *vn, GmDev st) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int b = find_blk(blk, B, i);
-    if (!st.active[b]) return;
-    vn[i] = w[i] / st.hj[(size_t)b * (st.m + 1) + st.m];
+    act_next[b] = nxt;
+    st.flag[slot * st.nb + b] = nxt;
 }
 
 // back substitution H y = g over the kdim leading columns of each block
@@ -578,7 +682,7 @@ void Gmres::ensure(Alloc *al_, const Space &sp_, int m_, bool flexible, hipStrea
         y.alloc(al, (size_t)B * m);
         hj.alloc(al, (size_t)B * (m + 1));
         scal.alloc(al, (size_t)B * 3);
-        ints.alloc(al, (size_t)B * 5);
+        ints.alloc(al, (size_t)B * 6);
         std::vector<const double *> hv(m + 1), hz(std::max(m, 1));
         for (int k = 0; k <= m; ++k) hv[k] = V[k].p;
         for (int k = 0; k < (int)Z.size(); ++k) hz[k] = Z[k].p;
@@ -617,6 +721,7 @@ GmDev Gmres::dev(double rtol, double atol, int maxit) {
     d.tol = scal.p; d.beta = scal.p + B; d.res = scal.p + 2 * B;
     d.active = ints.p; d.conv = ints.p + B; d.kdim = ints.p + 2 * B; d.its = ints.p + 3 * B;
     d.upd = ints.p + 4 * B;
+    d.active2 = ints.p + 5 * B;
     d.flag = dflag;
     d.nb = nb;
     d.m = m;
@@ -634,7 +739,7 @@ bool Gmres::any_active(hipStream_t s) {
 }
 
 void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x, bool x_zero,
-                  const GmOpts &o, const int *outer_mask, hipStream_t s) {
+                  const GmOpts &o, const int *outer_mask, hipStream_t s, const Op *Aop) {
     const Space &S = *sp;
     const int nch = (int)S.hchunk.size();
     GmDev st = dev(o.rtol, o.atol, o.maxit);
@@ -662,24 +767,29 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
     KCHECK();
     HIPC(hipEventRecord(ev[3], s));
     const double *const *Vp = vptr.p;
+    VPtrs vps{};
+    for (int k = 0; k <= m && k < MAXCOL; ++k) vps.p[k] = V[k].p;
     const bool flex = o.flexible;
     // one GMRES iteration j; its activity flags go to `slot`
     auto iteration = [&](int j, int slot) {
         double *zj = flex ? Z[j].p : t.p;
-        M(V[j].p, zj, st.active);
-        A(zj, w.p, nullptr, st.active);
-        {
-            ProfScope ps("gmres_orth", s);
-            k_gm_dots<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, w.p, Vp, j, P0, st);
+        const int *act = (j & 1) ? st.active2 : st.active;
+        int *act_next = (j & 1) ? st.active : st.active2;
+        M(V[j].p, zj, act);
+        ProfScope ps("gmres_arnoldi", s);
+        if (Aop) {
+            SpmvArgs sa = spmv_args(*Aop, zj, w.p, nullptr, nullptr);
+            k_gm_spmv_dots<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, vps, j, P0, act);
             KCHECK();
-            k_gm_update_dots<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, Vp, j, P0, P1, st);
-            KCHECK();
-            k_gm_update_norm<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, Vp, j, P1, P0, st);
+        } else {
+            A(zj, w.p, nullptr, act);
+            k_gm_dots<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, w.p, vps, j, P0, act);
             KCHECK();
         }
-        k_gm_givens<<<S.B, RED_THREADS, 0, s>>>(S.cfirst.p, j, slot, P0, st);
+        k_gm_update_dots<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vps, j, P0, P1, st, act);
         KCHECK();
-        k_gm_next<<<NB, 256, 0, s>>>(S.blk.p, S.B, S.N, w.p, V[j + 1].p, st);
+        k_gm_finish<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vps, j, P1, V[j + 1].p, st, act,
+                                                act_next, slot);
         KCHECK();
     };
     const int kc = (o.graph_chunk > 0 && graphs_ok && s != nullptr) ? std::min(o.graph_chunk, m) : 0;

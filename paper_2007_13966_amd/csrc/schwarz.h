@@ -79,6 +79,8 @@ struct Level {
     // ILU(0) elimination table of the stencil: for lower offset k, pairs (k2, t)
     // with off[k] + off[k2] = off[t], k2 an upper offset
     DBuf<int> upd_ptr, upd_k2, upd_t;
+    int nupd = 0;                // entries of upd_k2 / upd_t
+    int max_upd = 0;             // most updates of one lower entry
     DBuf<int> lin_pad;           // padded-tile linear offset of each stencil entry
     // interpolation from the next coarser level to this one
     Interp1 ip[3];

@@ -221,6 +221,9 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
         }
     }
     uptr[st.K] = (int)uk2.size();
+    L.nupd = (int)uk2.size();
+    L.max_upd = 0;
+    for (int k = 0; k < st.K; ++k) L.max_upd = std::max(L.max_upd, uptr[k + 1] - uptr[k]);
     if (uk2.empty()) { uk2.push_back(0); ut.push_back(0); }
     L.upd_ptr.upload(al, uptr, s);
     L.upd_k2.upload(al, uk2, s);
@@ -426,6 +429,109 @@ __global__ void k_ilu_factor(FacArgs a) {
             for (int k = 0; k < a.K; ++k) a.w[(size_t)k * a.NE + e] = row[k];
         }
         __syncthreads();
+    }
+}
+
+// The same elimination with the whole box in LDS (2D boxes): the rows of
+// A_i (gathered from the operator as k_ilu_fill does), the padded-tile
+// inverse map, the level pointers and the elimination tables are staged
+// once; the hyperplanes are eliminated in place and the factors written back.
+// MAXL / MAXQ bound the lower stencil entries and the updates per lower entry
+// (5-point cross: 2 / 1; 5x5 box: 12 / 12).  The row loop is branch-free: a
+// lower neighbour's index and pivot are read up front (earlier hyperplanes
+// are final), and the update lists are padded by repeating their last entry,
+// which rewrites the same value.
+// LDS: K*max_next doubles, then ints: tile + (nlev+1) + K + (K+1) + 2*nupd + next.
+template <int MAXL, int MAXQ>
+__global__ void __launch_bounds__(64) k_ilu_factor_lds(FacArgs a, int max_next, int tile, int nupd) {
+    extern __shared__ double smem_f[];
+    const SubDev sd = a.sub[blockIdx.x];
+    const Blk bk = a.blk[sd.blk];
+    const int K = a.K, n = sd.next, diag = a.diag;
+    double *W = smem_f;
+    int *inv = reinterpret_cast<int *>(W + (size_t)K * max_next);
+    int *lp = inv + tile;
+    int *lin = lp + (sd.nlev + 1);
+    int *uptr = lin + K;
+    int *ut = uptr + (K + 1);
+    int *uk = ut + nupd;
+    int *loc = uk + nupd;
+    for (int i = threadIdx.x; i < tile; i += blockDim.x) inv[i] = a.inv[sd.inv_off + i];
+    for (int i = threadIdx.x; i <= sd.nlev; i += blockDim.x) lp[i] = a.lvlptr[sd.lvl_off + i];
+    for (int i = threadIdx.x; i < K; i += blockDim.x) lin[i] = a.lin[i];
+    for (int i = threadIdx.x; i <= K; i += blockDim.x) uptr[i] = a.upd_ptr[i];
+    for (int i = threadIdx.x; i < nupd; i += blockDim.x) {
+        ut[i] = a.upd_t[i];
+        uk[i] = a.upd_k2[i];
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) loc[i] = a.loc[sd.fac_off + i];
+    // rows of A_i: neighbours outside the box dropped
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int lx = a.lexi[sd.fac_off + e];
+        const int x = lx % sd.ex, y = (lx / sd.ex) % sd.ey, z = lx / (sd.ex * sd.ey);
+        const int g = bk.off + (sd.ox + x) + bk.nx * ((sd.oy + y) + bk.ny * (sd.oz + z));
+        for (int k0 = 0; k0 < K; k0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = min(k0 + u, K - 1);
+                const int xx = x + a.off[3 * k], yy = y + a.off[3 * k + 1], zz = z + a.off[3 * k + 2];
+                const bool in = xx >= 0 && xx < sd.ex && yy >= 0 && yy < sd.ey && zz >= 0 && zz < sd.ez;
+                v[u] = in ? a.A[(size_t)k * a.N + g] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < K) W[(size_t)(k0 + u) * n + e] = v[u];
+        }
+    }
+    __syncthreads();
+    for (int t = 0; t < sd.nlev; ++t) {
+        for (int el = lp[t] + threadIdx.x; el < lp[t + 1]; el += blockDim.x) {
+            const int lc = loc[el];
+            int e2v[MAXL];
+            double piv[MAXL];
+#pragma unroll
+            for (int kl = 0; kl < MAXL; ++kl) e2v[kl] = inv[lc + lin[min(kl, diag - 1)]];
+#pragma unroll
+            for (int kl = 0; kl < MAXL; ++kl) piv[kl] = W[(size_t)diag * n + max(e2v[kl], 0)];
+#pragma unroll
+            for (int kl = 0; kl < MAXL; ++kl) {
+                if (kl < diag) {
+                    const double aik = W[(size_t)kl * n + el];
+                    const int e2 = max(e2v[kl], 0);
+                    // e2v < 0: neighbour outside the box (only reachable after a bad pivot)
+                    const bool on = aik != 0.0 && e2v[kl] >= 0;
+                    const double l = on ? aik / piv[kl] : 0.0;
+                    if (on) W[(size_t)kl * n + el] = l;
+                    const int q0 = uptr[kl], cnt = uptr[kl + 1] - q0;
+                    if (cnt > 0) {
+                        int tq[MAXQ], kq[MAXQ];
+#pragma unroll
+                        for (int q = 0; q < MAXQ; ++q) {
+                            const int qq = q0 + min(q, cnt - 1);
+                            tq[q] = ut[qq];
+                            kq[q] = uk[qq];
+                        }
+                        double uv[MAXQ], rv[MAXQ];
+#pragma unroll
+                        for (int q = 0; q < MAXQ; ++q) {
+                            uv[q] = W[(size_t)kq[q] * n + e2];
+                            rv[q] = W[(size_t)tq[q] * n + el];
+                        }
+#pragma unroll
+                        for (int q = 0; q < MAXQ; ++q)
+                            if (on) W[(size_t)tq[q] * n + el] = rv[q] - l * uv[q];
+                    }
+                }
+            }
+            const double d = W[(size_t)diag * n + el];
+            if (!(d != 0.0) || !isfinite(d)) atomicOr(a.err, 1);
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < K * n; i += blockDim.x) {
+        const int k = i / n, e = i - k * n;
+        a.w[(size_t)k * a.NE + sd.fac_off + e] = W[i];
     }
 }
 
@@ -1197,13 +1303,27 @@ void Ras::factor() {
         fa.off = V.A->st.doff.p;
         fa.w = V.w64.p;
         fa.err = V.err.p;
-        k_ilu_fill<<<V.nsub, 256, 0, s>>>(fa);
-        KCHECK();
         const int bs = 64;
-        const size_t sh = (size_t)bs * fa.K * sizeof(double) + sizeof(int) * (size_t)(V.max_nlev + 1);
-        set_lds((const void *)k_ilu_factor, sh);
-        launch_timed("ilu_factor", l, k_ilu_factor, dim3(V.nsub), dim3(bs), sh, s, fa);
-        KCHECK();
+        const size_t sh_lds = sizeof(double) * (size_t)fa.K * V.max_next +
+                              sizeof(int) * ((size_t)V.max_tile + V.max_nlev + 1 + 2 * (size_t)fa.K + 1 +
+                                             2 * (size_t)V.nupd + V.max_next);
+        void (*flds)(FacArgs, int, int, int) = nullptr;
+        if (fa.diag <= 2 && V.max_upd <= 1) flds = k_ilu_factor_lds<2, 1>;
+        else if (fa.diag <= 12 && V.max_upd <= 12) flds = k_ilu_factor_lds<12, 12>;
+        if (flds && sh_lds <= (size_t)lds_bytes) {
+            // the whole box fits in LDS (2D): fill and eliminate there
+            set_lds((const void *)flds, sh_lds);
+            launch_timed("ilu_factor", l, flds, dim3(V.nsub), dim3(bs), sh_lds, s, fa, V.max_next, V.max_tile,
+                         V.nupd);
+            KCHECK();
+        } else {
+            k_ilu_fill<<<V.nsub, 256, 0, s>>>(fa);
+            KCHECK();
+            const size_t sh = (size_t)bs * fa.K * sizeof(double) + sizeof(int) * (size_t)(V.max_nlev + 1);
+            set_lds((const void *)k_ilu_factor, sh);
+            launch_timed("ilu_factor", l, k_ilu_factor, dim3(V.nsub), dim3(bs), sh, s, fa);
+            KCHECK();
+        }
         const int NE = V.next_total;
         const int *perm = V.rows2d ? V.lexg.p : nullptr;
         if (d.precision == NKS_FP64) {
@@ -1370,7 +1490,7 @@ void Ras::coarse_solve(const double *b, double *x, const int *mask) {
     o.flexible = false;
     o.check_every = 1;
     o.graph_chunk = graph_chunk;
-    coarse.solve(A, P, b, x, true, o, mask, s);
+    coarse.solve(A, P, b, x, true, o, mask, s, C.A);
     ++coarse_calls;
 }
 
