@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--interp-order", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="interpolation order between levels (0: the workload's own)")
     ap.add_argument("--autotune", action="store_true",
                     help="choose the subdomain tile edge (8, 16, 32) and fine overlap (1, 2) with "
                          "nks_ras_autotune at the initial state before timing")
@@ -200,6 +202,8 @@ def main():
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 5}))
         return
     case = getattr(S, WORKLOADS[args.workload])()
+    if args.interp_order:
+        case = S.with_solver(case, interp_order=args.interp_order)
     tuning = None
     if args.autotune:
         g0 = P.Grid(case.problems)
@@ -245,6 +249,7 @@ def main():
             "cells": sum(r.N for r in case.problems),
             "reservoirs": len(case.problems),
             "levels": s64.levels,
+            "interp_order": s64.interp_order,
             "subdomains": int(sum(np.prod(boxes(r, s64)) for r in case.problems)),
             "overlap": list(s64.overlap), "precision": s64.precision,
             "newton_its_per_step": float(np.mean(nits)),

@@ -829,6 +829,7 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
             launch_chunk(c);
             HIPC(hipEventRecord(ev[c % 3], s));
             // look-ahead: stop once an earlier chunk left no reservoir active
+            // (with graphs one chunk: each graph launch costs a boundary)
             const int back = kc ? 1 : 2;
             if (c >= back && !any_flag((c - back) % 3)) break;
         }

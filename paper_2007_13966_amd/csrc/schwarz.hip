@@ -689,8 +689,20 @@ __global__ void __launch_bounds__(256) k_ras_apply(ApplyArgs a) {
                 const int le = e - c0;
                 const int p = cl[le];
                 VT v = tile[p];
-                for (int k = 0; k < ncl; ++k)
-                    v -= (VT)FTraits<FT>::get(cf, (size_t)k * a.cap + le) * tile[p + lin[k]];
+                // eight terms at a time, every load issued before the first
+                // product (a padded term adds an exact zero)
+                for (int k0 = 0; k0 < ncl; k0 += 8) {
+                    VT cv[8], tv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int k = min(k0 + u, ncl - 1);
+                        const VT c = (VT)FTraits<FT>::get(cf, (size_t)k * a.cap + le);
+                        tv[u] = tile[p + lin[k]];
+                        cv[u] = k0 + u < ncl ? c : (VT)0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v -= cv[u] * tv[u];
+                }
                 tile[p] = v;
             }
             __syncthreads();
@@ -712,8 +724,18 @@ __global__ void __launch_bounds__(256) k_ras_apply(ApplyArgs a) {
                 const int le = e - c0;
                 const int p = cl[le];
                 VT v = tile[p];
-                for (int k = 0; k < ncu; ++k)
-                    v -= (VT)FTraits<FT>::get(cf, (size_t)k * a.cap + le) * tile[p + lin[a.diag + 1 + k]];
+                for (int k0 = 0; k0 < ncu; k0 += 8) {
+                    VT cv[8], tv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int k = min(k0 + u, ncu - 1);
+                        const VT c = (VT)FTraits<FT>::get(cf, (size_t)k * a.cap + le);
+                        tv[u] = tile[p + lin[a.diag + 1 + k]];
+                        cv[u] = k0 + u < ncu ? c : (VT)0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v -= cv[u] * tv[u];
+                }
                 tile[p] = v * (VT)cd[le];
             }
             __syncthreads();
@@ -879,7 +901,11 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
         }
     }
     __syncthreads();
-    if (threadIdx.x < 64) {          // one wavefront sweeps; lane = row
+    // one wavefront sweeps, lane = row.  For the 5-point cross, lanes past
+    // the box's rows stay disabled (no LDS traffic; a DPP read from them
+    // returns zero, the value of a row outside the box); for the 5x5 box all
+    // lanes run, which measures faster
+    if ((int)threadIdx.x < (BOX ? 64 : min(64, ey))) {
     const int y = threadIdx.x;
     const int T = (ex - 1) + LB * (ey - 1) + 1;
     // RB steps per block: every LDS read of a block is issued before its
@@ -1437,7 +1463,10 @@ static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, 
     if (sh > budget) fail(NKS_EINVAL, "LDS layout of %zu bytes exceeds %zu", sh, budget);
     const void *fn = (const void *)k_ras_apply<FT, VT, DT>;
     set_lds(fn, sh);
-    const int bs = td.PZ == 1 ? 64 : 256;
+    // enough threads for the widest hyperplane: small boxes with wide
+    // stencils have many short hyperplanes, where one wavefront's barriers
+    // are the cheap ones
+    const int bs = V.max_lvl <= 64 ? 64 : (V.max_lvl <= 128 ? 128 : 256);
     {
         launch_timed("ras_apply", level_index(M, V), k_ras_apply<FT, VT, DT>, dim3(V.nsub), dim3(bs), sh, M.g->s, a);
         KCHECK();

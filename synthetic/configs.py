@@ -182,13 +182,17 @@ def case_3d_128(nx=128, ny=128, nz=64, precision="fp32"):
     initial state (20 MPa top layer), injector column (0,0,:) and producer
     column (127,127,:) at 1e-3 kg/s split over layers, 5 steps of 5 days,
     three-level V-cycle, 8x8x4 subdomains on every level, overlap 1,
-    FP32 or BF16 ILU factors with FP64 FGMRES(30) and residual."""
+    first-order interpolation, FP32 or BF16 ILU factors with FP64 FGMRES(30)
+    and residual."""
     kh = layered_perm(nx, ny, nz, 10.0, 1000.0, 1.5, 8.0, 3).ravel() * MD
     N = nx * ny * nz
     wc, wr = _column_wells(nx, ny, nz, (0, 0), (nx - 1, ny - 1), 1e-3)
     prob = Problem(nx, ny, nz, 10.0, 10.0, 10.0, kh.copy(), kh.copy(), 0.1 * kh,
                    np.full(N, 0.2), wc, wr, gravity=True)
-    s = SolverSettings(px=8, py=8, pz=4, overlap=(1, 1, 1), levels=3, precision=precision)
+    # first-order interpolation: in 3D the Galerkin products of the
+    # second-order one grow to ~63-125-point stencils, 3.4x slower per step
+    s = SolverSettings(px=8, py=8, pz=4, overlap=(1, 1, 1), levels=3, precision=precision,
+                       interp_order=1)
     return Case(f"3d_{nx}x{ny}x{nz}_threelevel_{precision}", [prob], 5 * DAY, 5, s,
                 case_3d_128.__doc__)
 
@@ -222,14 +226,14 @@ def case_batch64(nres=64, nmin=64, nmax=256, tile=16, overlap=1):
 def case_3d_96_adjoint(nx=96, ny=96, nz=48):
     """3D 96x96x48 channelised: 10 mD background with 8 sinusoidal 1000 mD
     channels (seed 5), kv/kh 0.1, phi 0.2, gravity, column wells as in the 128x128x64 case,
-    3 steps of 5 days, two-level FP64.  Objective: producer-column mean
+    3 steps of 5 days, two-level FP64, first-order interpolation.  Objective: producer-column mean
     pressure at the final step; gradient with respect to ln K per cell."""
     kh = channel_perm(nx, ny, nz, 10.0, 1000.0, 8, 5).ravel() * MD
     N = nx * ny * nz
     wc, wr = _column_wells(nx, ny, nz, (0, 0), (nx - 1, ny - 1), 1e-3)
     prob = Problem(nx, ny, nz, 10.0, 10.0, 10.0, kh.copy(), kh.copy(), 0.1 * kh,
                    np.full(N, 0.2), wc, wr, gravity=True)
-    s = SolverSettings(px=6, py=6, pz=3, overlap=(1, 1), levels=2)
+    s = SolverSettings(px=6, py=6, pz=3, overlap=(1, 1), levels=2, interp_order=1)
     return Case(f"3d_{nx}x{ny}x{nz}_adjoint", [prob], 5 * DAY, 3, s, case_3d_96_adjoint.__doc__)
 
 
