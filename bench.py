@@ -8,8 +8,8 @@ ILU(0) and Galerkin setup, preconditioned FGMRES, line search, per Newton
 iteration, to relative residual 1e-6.
 
 Prints one JSON line.  `roofline` is the fine-level one-level Schwarz apply
-(the ras_apply kernel), timed with HIP events on its stream inside the timed
-region; `cpu_baseline` times the CPU oracle on the first steps of the same
+(the 2D sweep kernel), timed with HIP events bound to its dispatches inside
+the timed region; `cpu_baseline` times the CPU oracle on the first steps of the same
 workload.
 """
 import argparse
@@ -36,8 +36,8 @@ WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128
 PMC_TRAFFIC = {
     "workload": "2d_512x512_twolevel_fp64",
     "source": "paper_2007_13966_amd/csrc/schwarz.hip",
-    "sha1": "3a28ec9724619c19ce588794722edb34230c8242",
-    "fetch_kib": 8873.10, "fetch_scale": 2.0,
+    "sha1": "01324324290caec31f8516fbb3c9938134e05760",
+    "fetch_kib": 8866.2, "fetch_scale": 2.0,
     "write_kib": 2048.0, "write_scale": 1.0,
 }
 
@@ -260,7 +260,7 @@ def main():
             "autotune": tuning,
         },
         "roofline": {
-            "kernel": "k_ras_apply (fine level, one-level left-RAS ILU(0) sweeps)",
+            "kernel": "k_ras_rows<double> (fine level 2D sweeps: one-level left-RAS, ILU(0) factors)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
