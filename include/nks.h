@@ -205,7 +205,9 @@ typedef struct {
 typedef struct {
     int iterations;              /* max over reservoirs */
     int total_iterations;        /* sum over reservoirs */
-    double residual;             /* max over reservoirs of the final ||r|| */
+    double residual;             /* max over reservoirs of the final residual norm (the
+                                    GMRES estimate |g_{k+1}| when every reservoir converged
+                                    inside a cycle; the recomputed ||b - J x|| otherwise) */
     int converged;               /* reservoirs that met the tolerance */
     int *its;                    /* optional HOST array [nres]: iterations */
     double *res;                 /* optional HOST array [nres]: final ||r|| */

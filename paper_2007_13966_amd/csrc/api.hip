@@ -172,11 +172,32 @@ __global__ void k_zero(int N, double *x) {
 struct NewtonWork {
     DBuf<double> F, Ft, s, b, pt, Js, lam, red2;
     DBuf<int> mask;
+    DBuf<const double *> ysp;     // {Js}: the slope reduction's column
     Reducer red;
     std::unique_ptr<Matrix> J;
     std::unique_ptr<Ras> M;
     nks_ras_desc rd{};
     Gmres gm;
+    // pinned host staging for the per-reservoir scalars (asynchronous copies):
+    // doubles norms[B], slope[B], lam[B]; ints flags[B], mask[B]
+    void *hpin = nullptr;
+    int hpin_b = 0;
+    double *h_norm = nullptr, *h_slope = nullptr, *h_lam = nullptr;
+    int *h_flags = nullptr, *h_mask = nullptr;
+    void pin(int B) {
+        if (hpin && hpin_b >= B) return;
+        if (hpin) HIPC(hipHostFree(hpin));
+        HIPC(hipHostMalloc(&hpin, (size_t)B * (3 * sizeof(double) + 2 * sizeof(int))));
+        hpin_b = B;
+        h_norm = static_cast<double *>(hpin);
+        h_slope = h_norm + B;
+        h_lam = h_slope + B;
+        h_flags = reinterpret_cast<int *>(h_lam + B);
+        h_mask = h_flags + B;
+    }
+    ~NewtonWork() {
+        if (hpin) (void)hipHostFree(hpin);
+    }
 };
 
 static void stencil_fine(Stencil &st, int dim, Alloc *al, hipStream_t s) {
@@ -769,6 +790,7 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
         W.red2.alloc(al, 2 * B);
         W.mask.alloc(al, B);
         W.red.ensure(al, g.sp, 1, s);
+        W.pin(B);
         if (!W.J) {
             W.J.reset(new Matrix());
             W.J->g = &g;
@@ -783,6 +805,10 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
         }
         const bool flex = nd->flexible < 0 ? (rd->levels > 1 || rd->precision != NKS_FP64) : nd->flexible != 0;
         W.gm.ensure(al, g.sp, nd->restart, flex, s);
+        {
+            std::vector<const double *> hv(1, W.Js.p);
+            W.ysp.upload(al, hv, s);
+        }
         nks_newton_stats S{};
         double t0 = now();
         // residual and norms at the initial guess
@@ -790,12 +816,23 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
         launch_history(g, pn, pnm1, order);
         std::vector<double> hn(B), hs(B), ht(B), hslope(B), lam(B), lam_prev(B), f_prev(B), stop(B);
         std::vector<int> act(B), flags(B), acc(B);
+        // per-reservoir norms and non-physical flags: one round trip through
+        // pinned memory (it also completes any copy queued before it)
         auto norms = [&](const double *x, std::vector<double> &out) {
             launch_block_norm2(g.sp, W.red, x, W.red2.p, nullptr, s);
-            HIPC(hipMemcpyAsync(out.data(), W.red2.p, 8 * B, hipMemcpyDeviceToHost, s));
-            HIPC(hipMemcpyAsync(flags.data(), g.flags.p, 4 * B, hipMemcpyDeviceToHost, s));
+            HIPC(hipMemcpyAsync(W.h_norm, W.red2.p, 8 * B, hipMemcpyDeviceToHost, s));
+            HIPC(hipMemcpyAsync(W.h_flags, g.flags.p, 4 * B, hipMemcpyDeviceToHost, s));
             HIPC(hipStreamSynchronize(s));
-            for (auto &v : out) v = std::sqrt(v);
+            for (int b = 0; b < B; ++b) {
+                out[b] = std::sqrt(W.h_norm[b]);
+                flags[b] = W.h_flags[b];
+            }
+        };
+        // the host copies are staged in pinned memory; every upload is
+        // followed by a round trip before its staging slot is written again
+        auto upload_mask = [&]() {
+            for (int b = 0; b < B; ++b) W.h_mask[b] = act[b];
+            HIPC(hipMemcpyAsync(W.mask.p, W.h_mask, 4 * B, hipMemcpyHostToDevice, s));
         };
         launch_props(g, p);
         launch_flux(g, p, dt, order, W.F.p, nullptr);
@@ -813,13 +850,12 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             bool any = false;
             for (int b = 0; b < B; ++b) any |= act[b] != 0;
             if (!any) break;
-            HIPC(hipMemcpyAsync(W.mask.p, act.data(), 4 * B, hipMemcpyHostToDevice, s));
+            upload_mask();
             double t1 = now();
             {
                 ProfScope ps("residual_jacobian", s);
                 launch_flux(g, p, dt, order, nullptr, W.J->op.coef.p);   // props at p are current
             }
-            HIPC(hipStreamSynchronize(s));
             // rounding floor: ||F|| <= u || |J| |p| || means p solves F = 0 as
             // well as F can be evaluated in binary64
             if (nd->floor_test) {
@@ -835,12 +871,12 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
                     left |= act[b] != 0;
                 }
                 if (!left) break;
-                if (changed) HIPC(hipMemcpyAsync(W.mask.p, act.data(), 4 * B, hipMemcpyHostToDevice, s));
+                if (changed) upload_mask();
             }
             double t2 = now();
             S.t_jacobian += t2 - t1;
+            // factor; zero pivots are read back after the solve (with its stats)
             W.M->factor();
-            W.M->check_pivots();
             double t3 = now();
             S.t_setup += t3 - t2;
             // J s = -F on the active reservoirs
@@ -860,6 +896,7 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             std::vector<int> its, conv;
             std::vector<double> res;
             W.gm.stats(its, res, conv, s);
+            W.M->check_pivots();
             int lits = 0;
             for (int b = 0; b < B; ++b) if (act[b]) lits = std::max(lits, its[b]);
             S.linear_its += lits;
@@ -876,17 +913,11 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
                 norms(p, xnorm);
                 for (int b = 0; b < B; ++b) small[b] = act[b] && snorm[b] <= nd->stol * xnorm[b];
             }
-            // slope of f = ||F||^2/2 along s: F^T J s
+            // slope of f = ||F||^2/2 along s: F^T J s, read back with the
+            // first trial norm (no round trip of its own)
             launch_spmv(W.J->op, W.s.p, W.Js.p, nullptr, nullptr, s);
-            {
-                const double *ys[1] = {W.Js.p};
-                DBuf<const double *> yp;
-                std::vector<const double *> hv(ys, ys + 1);
-                yp.upload(al, hv, s);
-                launch_block_dots(g.sp, W.red, W.F.p, yp.p, 1, W.red2.p, nullptr, s);
-                HIPC(hipMemcpyAsync(hslope.data(), W.red2.p, 8 * B, hipMemcpyDeviceToHost, s));
-                HIPC(hipStreamSynchronize(s));
-            }
+            launch_block_dots(g.sp, W.red, W.F.p, W.ysp.p, 1, W.red2.p + B, nullptr, s);
+            HIPC(hipMemcpyAsync(W.h_slope, W.red2.p + B, 8 * B, hipMemcpyDeviceToHost, s));
             // backtracking (Dennis-Schnabel): lambda = 1, then quadratic, then
             // cubic models, each new lambda within [0.1, 0.5] of the last
             for (int b = 0; b < B; ++b) {
@@ -896,12 +927,15 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             int bt = 0;
             bool failed = false;
             for (;; ++bt) {
-                HIPC(hipMemcpyAsync(W.lam.p, lam.data(), 8 * B, hipMemcpyHostToDevice, s));
+                for (int b = 0; b < B; ++b) W.h_lam[b] = lam[b];
+                HIPC(hipMemcpyAsync(W.lam.p, W.h_lam, 8 * B, hipMemcpyHostToDevice, s));
                 k_trial<<<nblk(N, 256), 256, 0, s>>>(g.sp.blk.p, B, N, p, W.s.p, W.lam.p, W.pt.p);
                 HIPC(hipMemsetAsync(g.flags.p, 0, sizeof(int) * B, s));
                 launch_props(g, W.pt.p);
                 launch_flux(g, W.pt.p, dt, order, W.Ft.p, nullptr);
                 norms(W.Ft.p, ht);
+                if (bt == 0)
+                    for (int b = 0; b < B; ++b) hslope[b] = W.h_slope[b];
                 bool all = true;
                 for (int b = 0; b < B; ++b) {
                     if (acc[b]) continue;

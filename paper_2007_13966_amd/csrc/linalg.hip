@@ -401,7 +401,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_begin(const Chunk *chunks, c
         for (int k = 0; k <= st.m; ++k) st.g[(size_t)b * (st.m + 1) + k] = 0.0;
         st.g[(size_t)b * (st.m + 1)] = beta;
         st.active[b] = act;
-        st.flag[3 * st.nb + b] = act;
+        st.flag[3 * st.nb + b] = act ? 1 : (conv ? 2 : 0);
     }
 }
 
@@ -548,7 +548,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
     if (!on) {
         if (lead && threadIdx.x == 0) {
             act_next[b] = 0;
-            st.flag[slot * st.nb + b] = 0;
+            st.flag[slot * st.nb + b] = st.conv[b] ? 2 : 0;
         }
         return;
     }
@@ -621,7 +621,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
         nxt = 0;   // restart (or stop at maxit)
     }
     act_next[b] = nxt;
-    st.flag[slot * st.nb + b] = nxt;
+    st.flag[slot * st.nb + b] = nxt ? 1 : (st.conv[b] ? 2 : 0);
 }
 
 // back substitution H y = g over the kdim leading columns of each block
@@ -745,11 +745,18 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
     GmDev st = dev(o.rtol, o.atol, o.maxit);
     const int NB = nblk(S.N, 256);
     double *P0 = red.part.p, *P1 = red.part.p + (size_t)nch * MAXCOL;
+    // host flags per reservoir: 1 iterating, 2 converged, 0 stopped for a
+    // restart (or at maxit)
     auto any_flag = [&](int slot) -> bool {
         HIPC(hipEventSynchronize(ev[slot]));
         for (int k = 0; k < nb; ++k)
-            if (hflag[slot * nb + k]) return true;
+            if (hflag[slot * nb + k] == 1) return true;
         return false;
+    };
+    auto all_converged = [&](int slot) -> bool {
+        for (int k = 0; k < nb; ++k)
+            if (hflag[slot * nb + k] != 2) return false;
+        return true;
     };
     const double *r0 = b;
     if (!x_zero) {
@@ -824,14 +831,25 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
         }
         HIPC(hipGraphLaunch(gexec[c], s));
     };
-    while (any_flag(3)) {
+    for (;;) {
+        // The first chunk of a cycle is queued before the cycle's start flag
+        // is read (a cycle with nothing to do runs it as no-ops).  The cycle
+        // ends when a finished chunk leaves no reservoir iterating; when all
+        // of them converged, the solve ends without recomputing the residual.
+        bool finished = false;
         for (int c = 0; c < nchunk; ++c) {
             launch_chunk(c);
             HIPC(hipEventRecord(ev[c % 3], s));
-            // look-ahead: stop once an earlier chunk left no reservoir active
-            // (with graphs one chunk: each graph launch costs a boundary)
+            if (c == 0 && !any_flag(3)) {
+                finished = true;
+                break;
+            }
+            // look-ahead (with graphs one chunk: each graph launch costs a boundary)
             const int back = kc ? 1 : 2;
-            if (c >= back && !any_flag((c - back) % 3)) break;
+            if (c >= back && !any_flag((c - back) % 3)) {
+                finished = all_converged((c - back) % 3);
+                break;
+            }
         }
         k_gm_solve_y<<<nblk(S.B, 64), 64, 0, s>>>(S.B, st);
         KCHECK();
@@ -844,6 +862,7 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
             M(w.p, t.p, st.upd);
             launch_axpby(S, 1.0, t.p, 1.0, x, st.upd, s);   // x += M^{-1} V y
         }
+        if (finished) break;
         A(x, r.p, b, nullptr);
         r0 = r.p;
         k_gm_norm_partials<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, r0, P0);

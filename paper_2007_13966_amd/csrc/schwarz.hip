@@ -1364,15 +1364,15 @@ void Ras::factor() {
 }
 
 void Ras::check_pivots() {
-    for (int l = 0; l < L; ++l) {
-        int e = 0;
-        HIPC(hipMemcpyAsync(&e, lev[l]->err.p, sizeof(int), hipMemcpyDeviceToHost, g->s));
-        HIPC(hipStreamSynchronize(g->s));
-        if (e) {
+    std::vector<int> e(L, 0);
+    for (int l = 0; l < L; ++l)
+        HIPC(hipMemcpyAsync(&e[l], lev[l]->err.p, sizeof(int), hipMemcpyDeviceToHost, g->s));
+    HIPC(hipStreamSynchronize(g->s));
+    for (int l = 0; l < L; ++l)
+        if (e[l]) {
             HIPC(hipMemsetAsync(lev[l]->err.p, 0, sizeof(int), g->s));
             fail(NKS_EZEROPIVOT, "zero pivot in a subdomain ILU(0) factorization on level %d", l);
         }
-    }
 }
 
 static int level_index(const Ras &M, const Level &V) {
