@@ -556,6 +556,66 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
     double h2sq = 0.0;
     for (int c = 0; c < nc; ++c) h2sq += hc[c] * hc[c];
     const double hn = sqrt(fmax(hc[nc] - h2sq, 0.0));
+    // the lead chunk's first thread applies the rotations before its share
+    // of the vector work (the Givens step needs only the totals)
+    if (lead && threadIdx.x == 0) {
+        const int m = st.m;
+        double *H = st.H + (size_t)b * (m + 1) * m;
+        double *cs = st.cs + (size_t)b * m, *sn = st.sn + (size_t)b * m;
+        double *g = st.g + (size_t)b * (m + 1);
+        // column j (h1 + h2) and the previous rotations in registers; every
+        // load has a valid (clamped) address, out-of-range values are replaced
+        double hcol[MAXCOL + 1], cc[MAXCOL], ss[MAXCOL];
+        const int jm = max(j - 1, 0);
+#pragma unroll
+        for (int k = 0; k < MAXCOL; ++k) {
+            const int kk = min(k, j);
+            const double hv = H[(size_t)kk * m + j] + hc[kk];
+            const double cv = cs[min(k, jm)], sv = sn[min(k, jm)];
+            hcol[k] = k <= j ? hv : 0.0;
+            cc[k] = k < j ? cv : 1.0;
+            ss[k] = k < j ? sv : 0.0;
+        }
+        hcol[MAXCOL] = 0.0;
+        const double gj = g[j];
+#pragma unroll
+        for (int k = 0; k < MAXCOL - 1; ++k) {
+            if (k < j) {
+                const double a0 = hcol[k], a1 = hcol[k + 1];
+                hcol[k] = cc[k] * a0 + ss[k] * a1;
+                hcol[k + 1] = -ss[k] * a0 + cc[k] * a1;
+            }
+        }
+        double a0 = 0.0;
+#pragma unroll
+        for (int k = 0; k < MAXCOL; ++k)
+            if (k == j) a0 = hcol[k];
+        const double den = sqrt(a0 * a0 + hn * hn);
+        const double c = den > 0.0 ? a0 / den : 1.0;
+        const double sg = den > 0.0 ? hn / den : 0.0;
+#pragma unroll
+        for (int k = 0; k < MAXCOL; ++k)
+            if (k < j) H[(size_t)k * m + j] = hcol[k];
+        H[(size_t)j * m + j] = den;
+        H[(size_t)(j + 1) * m + j] = 0.0;
+        cs[j] = c;
+        sn[j] = sg;
+        g[j + 1] = -sg * gj;
+        g[j] = c * gj;
+        st.its[b] += 1;
+        st.kdim[b] = j + 1;
+        const double res = fabs(g[j + 1]);
+        st.res[b] = res;
+        int nxt = 1;
+        if (res <= st.tol[b] || hn == 0.0) {
+            st.conv[b] = 1;
+            nxt = 0;
+        } else if (st.its[b] >= st.maxit || j + 1 == m) {
+            nxt = 0;   // restart (or stop at maxit)
+        }
+        act_next[b] = nxt;
+        st.flag[slot * st.nb + b] = nxt ? 1 : (st.conv[b] ? 2 : 0);
+    }
     if (hn > 0.0) {
         const double inv = 1.0 / hn;
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
@@ -570,58 +630,6 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
             vn[i] = t * inv;
         }
     }
-    if (!lead || threadIdx.x != 0) return;
-    const int m = st.m;
-    double *H = st.H + (size_t)b * (m + 1) * m;
-    double *cs = st.cs + (size_t)b * m, *sn = st.sn + (size_t)b * m;
-    double *g = st.g + (size_t)b * (m + 1);
-    // column j (h1 + h2) and the previous rotations in registers
-    double hcol[MAXCOL + 1], cc[MAXCOL], ss[MAXCOL];
-#pragma unroll
-    for (int k = 0; k < MAXCOL; ++k) {
-        hcol[k] = k <= j ? H[k * m + j] + hc[k] : 0.0;
-        cc[k] = k < j ? cs[k] : 1.0;
-        ss[k] = k < j ? sn[k] : 0.0;
-    }
-    hcol[MAXCOL] = 0.0;
-#pragma unroll
-    for (int k = 0; k < MAXCOL - 1; ++k) {
-        if (k < j) {
-            const double a0 = hcol[k], a1 = hcol[k + 1];
-            hcol[k] = cc[k] * a0 + ss[k] * a1;
-            hcol[k + 1] = -ss[k] * a0 + cc[k] * a1;
-        }
-    }
-    double a0 = 0.0;
-#pragma unroll
-    for (int k = 0; k < MAXCOL; ++k)
-        if (k == j) a0 = hcol[k];
-    const double den = sqrt(a0 * a0 + hn * hn);
-    const double c = den > 0.0 ? a0 / den : 1.0;
-    const double sg = den > 0.0 ? hn / den : 0.0;
-#pragma unroll
-    for (int k = 0; k < MAXCOL; ++k)
-        if (k < j) H[k * m + j] = hcol[k];
-    H[j * m + j] = den;
-    H[(j + 1) * m + j] = 0.0;
-    cs[j] = c;
-    sn[j] = sg;
-    const double gj = g[j];
-    g[j + 1] = -sg * gj;
-    g[j] = c * gj;
-    st.its[b] += 1;
-    st.kdim[b] = j + 1;
-    const double res = fabs(g[j + 1]);
-    st.res[b] = res;
-    int nxt = 1;
-    if (res <= st.tol[b] || hn == 0.0) {
-        st.conv[b] = 1;
-        nxt = 0;
-    } else if (st.its[b] >= st.maxit || j + 1 == m) {
-        nxt = 0;   // restart (or stop at maxit)
-    }
-    act_next[b] = nxt;
-    st.flag[slot * st.nb + b] = nxt ? 1 : (st.conv[b] ? 2 : 0);
 }
 
 // back substitution H y = g over the kdim leading columns of each block
