@@ -297,6 +297,24 @@ def main():
             "ras_apply_l0_frac": (a32 / HBM_PEAK_GBS) if a32 else None,
         }
         log(f"fp32 preconditioner: {sec32:.4f} s/step, dp error vs fp64 {err:.2e}")
+        sb = S.with_solver(case, precision="bf16").solver
+        bb, _ = apply_bytes(case.problems, sb, "bf16")
+        rb = run_gpu(P, case, sb, args.warmup, args.steps)
+        secb = rb["seconds"] / args.steps
+        db = rb["p_end"] - rb["p_start"]
+        errb = float(np.linalg.norm(db - d64) / max(np.linalg.norm(d64), 1e-300))
+        actb = launch_split(rb["prof"].get("ras_apply_l0", np.zeros(0)))
+        ab = bb / (float(actb.mean()) / 1e3) / 1e9 if actb.size else None
+        out["mixed_bf16"] = {
+            "s_per_step": secb,
+            "speedup_vs_fp64": sec / secb,
+            "gmres_its_per_newton": float(sum(x["linear_its"] for x in rb["stats"]) /
+                                          max(1, sum(x["newton_its"] for x in rb["stats"]))),
+            "dp_rel_error_vs_fp64": errb,
+            "ras_apply_l0_gbs": ab,
+            "ras_apply_l0_frac": (ab / HBM_PEAK_GBS) if ab else None,
+        }
+        log(f"bf16 factors: {secb:.4f} s/step, dp error vs fp64 {errb:.2e}")
     if not args.no_cpu_baseline and args.workload == "2d512":
         n = args.cpu_steps
         v = cpu_baseline(case, n)
