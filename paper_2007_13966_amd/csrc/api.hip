@@ -173,6 +173,7 @@ struct NewtonWork {
     DBuf<double> F, Ft, s, b, pt, Js, lam, red2;
     DBuf<int> mask;
     DBuf<const double *> ysp;     // {Js}: the slope reduction's column
+    const double *ysp_host = nullptr;
     Reducer red;
     std::unique_ptr<Matrix> J;
     std::unique_ptr<Ras> M;
@@ -805,9 +806,10 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
         }
         const bool flex = nd->flexible < 0 ? (rd->levels > 1 || rd->precision != NKS_FP64) : nd->flexible != 0;
         W.gm.ensure(al, g.sp, nd->restart, flex, s);
-        {
+        if (W.ysp_host != W.Js.p) {
             std::vector<const double *> hv(1, W.Js.p);
             W.ysp.upload(al, hv, s);
+            W.ysp_host = W.Js.p;
         }
         nks_newton_stats S{};
         double t0 = now();

@@ -698,7 +698,8 @@ void Gmres::ensure(Alloc *al_, const Space &sp_, int m_, bool flexible, hipStrea
         vptr.upload(al, hv, s);
         zptr.upload(al, hz, s);
         if (hint) HIPC(hipHostFree(hint));
-        HIPC(hipHostMalloc((void **)&hint, sizeof(int) * 2 * B + sizeof(double) * 2 * B));
+        // pinned staging for stats(): the 6*B ints, then the 3*B doubles
+        HIPC(hipHostMalloc((void **)&hint, sizeof(int) * 6 * B + sizeof(double) * 3 * B + 64));
     }
     if (!hflag || flag_b < B) {
         if (hflag) HIPC(hipHostFree((void *)hflag));
@@ -890,14 +891,16 @@ void Gmres::invalidate_graphs() {
 void Gmres::stats(std::vector<int> &its, std::vector<double> &res, std::vector<int> &conv,
                   hipStream_t s) {
     const int B = nb;
-    std::vector<int> hi(5 * B);
-    std::vector<double> hd(3 * B);
-    HIPC(hipMemcpyAsync(hi.data(), ints.p, sizeof(int) * 5 * B, hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(hd.data(), scal.p, sizeof(double) * 3 * B, hipMemcpyDeviceToHost, s));
+    // through pinned memory: a pageable destination costs a host round trip per copy
+    int *hi = hint;
+    double *hd = reinterpret_cast<double *>(
+        reinterpret_cast<char *>(hint) + ((sizeof(int) * 6 * B + 63) / 64) * 64);
+    HIPC(hipMemcpyAsync(hi, ints.p, sizeof(int) * 5 * B, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(hd, scal.p, sizeof(double) * 3 * B, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    its.assign(hi.begin() + 3 * B, hi.begin() + 4 * B);
-    conv.assign(hi.begin() + B, hi.begin() + 2 * B);
-    res.assign(hd.begin() + 2 * B, hd.begin() + 3 * B);
+    its.assign(hi + 3 * B, hi + 4 * B);
+    conv.assign(hi + B, hi + 2 * B);
+    res.assign(hd + 2 * B, hd + 3 * B);
 }
 
 }  // namespace nks

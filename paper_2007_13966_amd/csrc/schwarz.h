@@ -117,6 +117,8 @@ struct Ras {
     void restrict_to(int l, const double *rf, double *rc, const int *mask);
     void prolong_add(int l, const double *ec, double *zf, const int *mask);
     void check_pivots();
+    int *hpiv = nullptr;         // pinned staging for the per-level zero-pivot flags
+    ~Ras();
 };
 
 }  // namespace nks

@@ -1363,13 +1363,17 @@ void Ras::factor() {
     }
 }
 
+Ras::~Ras() {
+    if (hpiv) (void)hipHostFree(hpiv);
+}
+
 void Ras::check_pivots() {
-    std::vector<int> e(L, 0);
+    if (!hpiv) HIPC(hipHostMalloc((void **)&hpiv, sizeof(int) * 8));
     for (int l = 0; l < L; ++l)
-        HIPC(hipMemcpyAsync(&e[l], lev[l]->err.p, sizeof(int), hipMemcpyDeviceToHost, g->s));
+        HIPC(hipMemcpyAsync(hpiv + l, lev[l]->err.p, sizeof(int), hipMemcpyDeviceToHost, g->s));
     HIPC(hipStreamSynchronize(g->s));
     for (int l = 0; l < L; ++l)
-        if (e[l]) {
+        if (hpiv[l]) {
             HIPC(hipMemsetAsync(lev[l]->err.p, 0, sizeof(int), g->s));
             fail(NKS_EZEROPIVOT, "zero pivot in a subdomain ILU(0) factorization on level %d", l);
         }
