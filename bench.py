@@ -2,7 +2,7 @@
 
 Default workload: 2D 512x512 log-normal reservoir (sigma 1, correlation
 length 8 cells), five-spot wells, BDF2 steps of 5 days, two-level V-cycle
-RAS with 256 subdomains (overlap 2 fine / 1 coarse), FGMRES(30), FP64.
+RAS with 256 subdomains (overlap 2 on both levels), FGMRES(30), FP64.
 A step is one full implicit time step: residual + PR, Jacobian, subdomain
 ILU(0) and Galerkin setup, preconditioned FGMRES, line search, per Newton
 iteration, to relative residual 1e-6.
@@ -102,6 +102,25 @@ def launch_split(d):
     if d.size == 0:
         return d
     return d[d >= np.median(d) / 2]
+
+
+def level_bytes(P, case, s, level):
+    """Algorithmic bytes of one FP64 one-level apply on `level` (coarse
+    levels: the same boxes on the coarsened grids, that level's overlap and
+    its Galerkin stencil size from the library)."""
+    g = P.Grid(case.problems)
+    p0 = g.initial_pressure()
+    J = g.jacobian(p0, p0, None, case.dt, 1)
+    info = P.Ras(J, s).level_info(level)
+    K, n = info["K"], info["n"]
+    ne = 0
+    for rec in case.problems:
+        d = [rec.nx, rec.ny, rec.nz]
+        for _ in range(level):
+            d = [-(-x // 2) if (x > 1 or k < 2) else 1 for k, x in enumerate(d)]
+        nb = boxes(rec, s)
+        ne += ext_cells(d[0], d[1], d[2], *nb, s.overlap[min(level, len(s.overlap) - 1)])
+    return ne * ((K - 1) * 8 + 8 + 8) + n * 8, K
 
 
 def run_gpu(P, case, settings, warmup, steps, profile=True):
@@ -273,10 +292,23 @@ def main():
             "masked_launches": int(allv.size - cnt),
             "avg_launch_us": avg_s * 1e6,
         },
+        "roofline_coarse": None,
         "kernels_ms": {k: {"count": int(v.size), "total_ms": round(float(v.sum()), 3),
                            "avg_us": round(1e3 * float(v.mean()), 2)}
                        for k, v in r64["prof"].items()},
     }
+    if s64.levels > 1:
+        # the coarsest-but-one level's sweeps run inside every coarse GMRES
+        # iteration and take most of the apply time
+        cb, ck = level_bytes(P, case, s64, 1)
+        cl = launch_split(r64["prof"].get("ras_apply_l1", np.zeros(0)))
+        ca = cb / (float(cl.mean()) / 1e3) / 1e9 if cl.size else None
+        out["roofline_coarse"] = {
+            "kernel": f"level-1 one-level sweeps ({ck}-point Galerkin stencil), launches outside graphs",
+            "bound": "hbm", "achieved": ca, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (ca / HBM_PEAK_GBS) if ca else None, "bytes_per_launch": cb,
+            "launches": int(cl.size), "avg_launch_us": float(cl.mean()) * 1e3 if cl.size else None,
+        }
     if not args.no_mixed:
         s32 = S.with_solver(case, precision="fp32").solver
         b32, _ = apply_bytes(case.problems, s32, "fp32")
