@@ -5,6 +5,7 @@
 // Every reduction is deterministic: per-chunk partial sums, then a fixed-
 // order sum per reservoir done by the last workgroup to finish.
 #include <functional>
+#include <type_traits>
 
 #include "krylov.h"
 
@@ -288,8 +289,9 @@ __device__ __forceinline__ void workgroup_columns(double (&v)[NC], int nc, Store
 
 // column sums of this workgroup's registers into part[c * ns + blockIdx.x]
 // (column-major over the ns chunks, so the totals read coalesced)
-template <int NC>
-__device__ __forceinline__ void chunk_columns(const double (&acc)[MAXCOL], int nc, double *part, int ns) {
+template <int NC, int M>
+__device__ __forceinline__ void chunk_columns(const double (&acc)[M], int nc, double *part, int ns) {
+    static_assert(NC <= M, "column bound exceeds the register array");
     double v[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) v[c] = acc[c];
@@ -446,101 +448,105 @@ struct VPtrs {
 // that another rewrites in the same kernel.
 
 // pass-1 partials of w = A z with V[0..j] (stencil operator, chunk grid)
+template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_gm_spmv_dots(const Chunk *chunks, SpmvArgs a, VPtrs V, int j,
                                                               double *part, const int *act) {
     __shared__ int sh[MAXK];
     stage_offsets(a.off, a.K, sh);
     const Chunk ch = chunks[blockIdx.x];
     const int nc = j + 1;
-    double acc[MAXCOL];
+    double acc[NC];
 #pragma unroll
-    for (int c = 0; c < MAXCOL; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     if (act[ch.blk]) {
         const Blk k = a.blk[ch.blk];
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
-            double vv[MAXCOL];
+            double vv[NC];
 #pragma unroll
-            for (int c = 0; c < MAXCOL; ++c)
+            for (int c = 0; c < NC; ++c)
                 if (c < nc) vv[c] = V.p[c][i];
             const int l = i - k.off;
             const int x = l % k.nx, y = (l / k.nx) % k.ny, z = l / (k.nx * k.ny);
             const double wi = stencil_dot(sh, a.K, a.coef, a.N, a.x, i, x, y, z, k);
             a.y[i] = wi;
 #pragma unroll
-            for (int c = 0; c < MAXCOL; ++c)
+            for (int c = 0; c < NC; ++c)
                 if (c < nc) acc[c] += wi * vv[c];
         }
     }
-    chunk_columns<MAXCOL>(acc, nc, part, gridDim.x);
+    chunk_columns<NC>(acc, nc, part, gridDim.x);
 }
 
 // pass-1 partials V[0..j]^T w (w from a generic operator)
+template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_gm_dots(const Chunk *chunks, const double *w, VPtrs V, int j,
                                                          double *part, const int *act) {
     const Chunk ch = chunks[blockIdx.x];
     const int nc = j + 1;
-    double acc[MAXCOL];
+    double acc[NC];
 #pragma unroll
-    for (int c = 0; c < MAXCOL; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     if (act[ch.blk]) {
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
-            double vv[MAXCOL];
+            double vv[NC];
 #pragma unroll
-            for (int c = 0; c < MAXCOL; ++c)
+            for (int c = 0; c < NC; ++c)
                 if (c < nc) vv[c] = V.p[c][i];
             const double wi = w[i];
 #pragma unroll
-            for (int c = 0; c < MAXCOL; ++c)
+            for (int c = 0; c < NC; ++c)
                 if (c < nc) acc[c] += wi * vv[c];
         }
     }
-    chunk_columns<MAXCOL>(acc, nc, part, gridDim.x);
+    chunk_columns<NC>(acc, nc, part, gridDim.x);
 }
 
 // h1 = pass-1 totals (lead chunk stores H[:, j]); w -= V h1; pass-2 partials
 // V^T w in columns 0..j and w.w in column j+1
+template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_gm_update_dots(const Chunk *chunks, const int *cfirst, double *w,
                                                                 VPtrs V, int j, const double *pin, double *pout,
                                                                 GmDev st, const int *act) {
-    __shared__ double hc[MAXCOL];
+    __shared__ double hc[NC];
     const Chunk ch = chunks[blockIdx.x];
     const int b = ch.blk, nc = j + 1;
     const bool on = act[b];
-    if (on) block_totals<MAXCOL>(pin, cfirst[b], cfirst[b + 1], nc, hc, gridDim.x);
+    if (on) block_totals<NC>(pin, cfirst[b], cfirst[b + 1], nc, hc, gridDim.x);
     if (on && (int)blockIdx.x == cfirst[b] && (int)threadIdx.x < nc)
         st.H[((size_t)b * (st.m + 1) + threadIdx.x) * st.m + j] = hc[threadIdx.x];
-    double acc[MAXCOL];
+    double acc[NC];
 #pragma unroll
-    for (int c = 0; c < MAXCOL; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     if (on) {
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
-            double vv[MAXCOL];
+            double vv[NC];
 #pragma unroll
-            for (int c = 0; c < MAXCOL; ++c)
+            for (int c = 0; c < NC; ++c)
                 if (c < nc) vv[c] = V.p[c][i];
             double t = w[i];
 #pragma unroll
-            for (int c = 0; c < MAXCOL; ++c)
+            for (int c = 0; c < NC; ++c)
                 if (c < nc) t -= hc[c] * vv[c];
             w[i] = t;
 #pragma unroll
-            for (int c = 0; c < MAXCOL - 1; ++c)
+            for (int c = 0; c < NC - 1; ++c)
                 if (c < nc) acc[c] += t * vv[c];
 #pragma unroll
-            for (int c = 1; c < MAXCOL; ++c)
+            for (int c = 1; c < NC; ++c)
                 if (c == nc) acc[c] += t * t;
         }
     }
-    chunk_columns<MAXCOL>(acc, nc + 1, pout, gridDim.x);
+    chunk_columns<NC>(acc, nc + 1, pout, gridDim.x);
 }
 
 // h2 and w.w from the pass-2 partials; v_{j+1} = (w - V h2) / h_{j+1,j};
 // the lead chunk of each reservoir updates H, the rotations and the
 // residual estimate, and decides act_{j+1} and the host flag (single writer).
+template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, const int *cfirst, const double *w,
                                                            VPtrs V, int j, const double *pin, double *vn, GmDev st,
                                                            const int *act, int *act_next, int slot) {
-    __shared__ double hc[MAXCOL];
+    __shared__ double hc[NC];
     const Chunk ch = chunks[blockIdx.x];
     const int b = ch.blk, nc = j + 1;
     const bool on = act[b];
@@ -552,7 +558,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
         }
         return;
     }
-    block_totals<MAXCOL>(pin, cfirst[b], cfirst[b + 1], nc + 1, hc, gridDim.x);
+    block_totals<NC>(pin, cfirst[b], cfirst[b + 1], nc + 1, hc, gridDim.x);
     double h2sq = 0.0;
     for (int c = 0; c < nc; ++c) h2sq += hc[c] * hc[c];
     const double hn = sqrt(fmax(hc[nc] - h2sq, 0.0));
@@ -565,10 +571,10 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
         double *g = st.g + (size_t)b * (m + 1);
         // column j (h1 + h2) and the previous rotations in registers; every
         // load has a valid (clamped) address, out-of-range values are replaced
-        double hcol[MAXCOL + 1], cc[MAXCOL], ss[MAXCOL];
+        double hcol[NC + 1], cc[NC], ss[NC];
         const int jm = max(j - 1, 0);
 #pragma unroll
-        for (int k = 0; k < MAXCOL; ++k) {
+        for (int k = 0; k < NC; ++k) {
             const int kk = min(k, j);
             const double hv = H[(size_t)kk * m + j] + hc[kk];
             const double cv = cs[min(k, jm)], sv = sn[min(k, jm)];
@@ -576,10 +582,10 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
             cc[k] = k < j ? cv : 1.0;
             ss[k] = k < j ? sv : 0.0;
         }
-        hcol[MAXCOL] = 0.0;
+        hcol[NC] = 0.0;
         const double gj = g[j];
 #pragma unroll
-        for (int k = 0; k < MAXCOL - 1; ++k) {
+        for (int k = 0; k < NC - 1; ++k) {
             if (k < j) {
                 const double a0 = hcol[k], a1 = hcol[k + 1];
                 hcol[k] = cc[k] * a0 + ss[k] * a1;
@@ -588,13 +594,13 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
         }
         double a0 = 0.0;
 #pragma unroll
-        for (int k = 0; k < MAXCOL; ++k)
+        for (int k = 0; k < NC; ++k)
             if (k == j) a0 = hcol[k];
         const double den = sqrt(a0 * a0 + hn * hn);
         const double c = den > 0.0 ? a0 / den : 1.0;
         const double sg = den > 0.0 ? hn / den : 0.0;
 #pragma unroll
-        for (int k = 0; k < MAXCOL; ++k)
+        for (int k = 0; k < NC; ++k)
             if (k < j) H[(size_t)k * m + j] = hcol[k];
         H[(size_t)j * m + j] = den;
         H[(size_t)(j + 1) * m + j] = 0.0;
@@ -619,17 +625,29 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
     if (hn > 0.0) {
         const double inv = 1.0 / hn;
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
-            double vv[MAXCOL];
+            double vv[NC];
 #pragma unroll
-            for (int c = 0; c < MAXCOL; ++c)
+            for (int c = 0; c < NC; ++c)
                 if (c < nc) vv[c] = V.p[c][i];
             double t = w[i];
 #pragma unroll
-            for (int c = 0; c < MAXCOL; ++c)
+            for (int c = 0; c < NC; ++c)
                 if (c < nc) t -= hc[c] * vv[c];
             vn[i] = t * inv;
         }
     }
+}
+
+// Calls f with the smallest compiled column bound (4, 8, 16, MAXCOL) that
+// holds `cols` columns: the Arnoldi kernels' register arrays and reductions
+// scale with the bound, not with MAXCOL.
+template <typename F>
+static void with_columns(int cols, F &&f) {
+    if (cols <= 4) f(std::integral_constant<int, 4>{});
+    else if (cols <= 8) f(std::integral_constant<int, 8>{});
+    else if (cols <= 16) f(std::integral_constant<int, 16>{});
+    else if (cols <= MAXCOL) f(std::integral_constant<int, MAXCOL>{});
+    else fail(NKS_EINVAL, "%d Krylov columns exceed %d", cols, MAXCOL);
 }
 
 // back substitution H y = g over the kdim leading columns of each block
@@ -664,6 +682,7 @@ __global__ void k_gm_combine(const Blk *blk, int B, int N, const double *const *
 
 // ---------------------------------------------------------------- host driver
 void Gmres::ensure(Alloc *al_, const Space &sp_, int m_, bool flexible, hipStream_t s) {
+    if (m_ < 1 || m_ + 2 > MAXCOL) fail(NKS_EINVAL, "restart %d outside [1, %d]", m_, MAXCOL - 2);
     al = al_;
     sp = &sp_;
     const int B = sp_.B, N = sp_.N;
@@ -793,20 +812,24 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
         int *act_next = (j & 1) ? st.active : st.active2;
         M(V[j].p, zj, act);
         ProfScope ps("gmres_arnoldi", s);
-        if (Aop) {
-            SpmvArgs sa = spmv_args(*Aop, zj, w.p, nullptr, nullptr);
-            k_gm_spmv_dots<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, vps, j, P0, act);
+        // pass 2 carries j + 2 columns (V[0..j]^T w and w.w)
+        with_columns(j + 2, [&](auto bound) {
+            constexpr int NC = decltype(bound)::value;
+            if (Aop) {
+                SpmvArgs sa = spmv_args(*Aop, zj, w.p, nullptr, nullptr);
+                k_gm_spmv_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, vps, j, P0, act);
+                KCHECK();
+            } else {
+                A(zj, w.p, nullptr, act);
+                k_gm_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, w.p, vps, j, P0, act);
+                KCHECK();
+            }
+            k_gm_update_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vps, j, P0, P1, st, act);
             KCHECK();
-        } else {
-            A(zj, w.p, nullptr, act);
-            k_gm_dots<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, w.p, vps, j, P0, act);
+            k_gm_finish<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vps, j, P1, V[j + 1].p, st,
+                                                        act, act_next, slot);
             KCHECK();
-        }
-        k_gm_update_dots<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vps, j, P0, P1, st, act);
-        KCHECK();
-        k_gm_finish<<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vps, j, P1, V[j + 1].p, st, act,
-                                                act_next, slot);
-        KCHECK();
+        });
     };
     const int kc = (o.graph_chunk > 0 && graphs_ok && s != nullptr) ? std::min(o.graph_chunk, m) : 0;
     if (kc && kc != gchunk) invalidate_graphs();
