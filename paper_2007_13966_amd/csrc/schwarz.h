@@ -68,9 +68,9 @@ struct Level {
     DBuf<uint16_t> f16;          // BF16 factors (BF16 mode)
     DBuf<int> lexg;              // per extended cell (hyperplane order): lexicographic storage slot
     // 2D levels use the register-wavefront sweep: factors stored in
-    // lexicographic order, stencil mapped onto a 5-point cross or 5x5 box
+    // lexicographic order, stencil mapped onto a row template
     bool rows2d = false;
-    int box = 0;
+    int box = 0;                 // 0: 5-point cross, 1: 5x5 box, 2: 21-point (5x5 without corners)
     DBuf<int> slotmap;           // box slot -> stencil index (-1: absent)
     DBuf<double> invd64;         // 1/u_ii
     DBuf<float> invd32;

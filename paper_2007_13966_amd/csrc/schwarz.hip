@@ -195,7 +195,10 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
             slot[(dx + 2) + 5 * (dy + 2)] = k;
             if (std::abs(dx) + std::abs(dy) > 1) cross = false;
         }
-        L.box = cross ? 0 : 1;
+        bool corner = false;
+        for (int k = 0; k < st.K; ++k)
+            if (std::abs(st.off[3 * k]) == 2 && std::abs(st.off[3 * k + 1]) == 2) corner = true;
+        L.box = cross ? 0 : (corner ? 1 : 2);
         L.slotmap.upload(al, slot, s);
         L.rows2d = true;
     }
@@ -787,7 +790,9 @@ __device__ __forceinline__ double lane_shl(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// stencil shapes: 0 = 5-point cross (lb 1), 1 = 5x5 box (lb 3)
+// stencil shapes: 0 = 5-point cross (lb 1), 1 = 5x5 box (lb 3), 2 = the
+// 21-point stencil (5x5 without its corners, lb 3: the Galerkin product of
+// the 5-point operator with second-order interpolation)
 template <int BOX> struct RowStencil;
 template <> struct RowStencil<0> {
     static constexpr int LB = 1, H = 1, NS = 4, NL = 2;
@@ -800,6 +805,20 @@ template <> struct RowStencil<1> {
     static constexpr int DX[NS] = {-2, -1, 0, 1, 2, -2, -1, 0, 1, 2, -2, -1, 1, 2, -2, -1, 0, 1, 2, -2, -1, 0, 1, 2};
     static constexpr int DY[NS] = {-2, -2, -2, -2, -2, -1, -1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2};
 };
+template <> struct RowStencil<2> {
+    static constexpr int LB = 3, H = 8, NS = 20, NL = 10;
+    static constexpr int DX[NS] = {-1, 0, 1, -2, -1, 0, 1, 2, -2, -1, 1, 2, -2, -1, 0, 1, 2, -1, 0, 1};
+    static constexpr int DY[NS] = {-2, -2, -2, -1, -1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2};
+};
+
+// padded per-cell factor run of a row template: lower run, then upper run,
+// each a whole number of 16-byte words of FT
+template <int BOX, typename FT>
+constexpr int row_run() {
+    constexpr int PER = (int)(16 / sizeof(FT));
+    return (RowStencil<BOX>::NL + PER - 1) / PER * PER +
+           (RowStencil<BOX>::NS - RowStencil<BOX>::NL + PER - 1) / PER * PER;
+}
 
 struct RowsArgs {
     const SubDev *sub;
@@ -1015,6 +1034,131 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
         }
     } else {
         for (int c = threadIdx.x; c < n; c += blockDim.x) a.zext[fo + c] = (double)rv[c];
+    }
+}
+
+// ---------------------------------------------------------------- kernel: 2D ILU(0) wavefront
+// ILU(0) of one 2D box per workgroup on the sweeps' schedule: lane y factors
+// row y of the box, cell x = t - LB*y at step t, so the row of every lower
+// neighbour was finished at an earlier step (by this lane or by a lane
+// below).  Rows are staged cell-major in LDS in the row template's slot
+// order, then u_ii and 1/u_ii; the row being factored lives in registers.
+// IKJ elimination over the lower slots in increasing column order:
+// l = a_iq / u_qq (as a product with the stored reciprocal), then
+// a_ij -= l u_qj for every upper slot of the neighbour's row whose column is
+// a template slot of row i.  Slots absent from the stencil take no
+// elimination and are stored as zero, so fill outside the pattern never
+// reaches a factor.  Factors are written k-major in lexicographic order.
+struct IluRowsArgs {
+    const SubDev *sub;
+    const Blk *blk;
+    const int *slotmap;   // 25 box slots -> stencil index or -1
+    const double *A;      // K*N operator
+    int N, NE, diag;
+    double *w;            // K*NE factors (lexicographic per subdomain)
+    int *err;
+};
+
+// template slot of offset (dx, dy): NS for the diagonal, -1 outside
+template <int BOX>
+__host__ __device__ constexpr int row_slot(int dx, int dy) {
+    if (dx == 0 && dy == 0) return RowStencil<BOX>::NS;
+    for (int q = 0; q < RowStencil<BOX>::NS; ++q)
+        if (RowStencil<BOX>::DX[q] == dx && RowStencil<BOX>::DY[q] == dy) return q;
+    return -1;
+}
+
+// LDS: next * (NS + 2) doubles
+template <int BOX>
+__global__ void __launch_bounds__(256) k_ilu_rows(IluRowsArgs a) {
+    using S = RowStencil<BOX>;
+    constexpr int NS = S::NS, NL = S::NL, LB = S::LB;
+    constexpr int RL = NS + 2;   // row length in doubles: off-diagonals, u_ii, 1/u_ii
+    static_assert(RL % 2 == 0, "rows are whole 16-byte words");
+    extern __shared__ __align__(16) double Wr[];
+    __shared__ int kmap[NS + 1];
+    const SubDev sd = a.sub[blockIdx.x];
+    const Blk bk = a.blk[sd.blk];
+    const int n = sd.next, ex = sd.ex, ey = sd.ey;
+    if ((int)threadIdx.x <= NS) {
+        const int q = threadIdx.x, qq = min(q, NS - 1);
+        kmap[q] = q == NS ? a.diag : a.slotmap[(S::DX[qq] + 2) + 5 * (S::DY[qq] + 2)];
+    }
+    __syncthreads();
+    // rows of A_i: neighbours outside the box and absent slots zero
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const int y = c / ex, x = c - y * ex;
+        const size_t g = (size_t)bk.off + (sd.ox + x) + (size_t)bk.nx * (sd.oy + y + (size_t)bk.ny * sd.oz);
+        double v[NS + 1];
+#pragma unroll
+        for (int q = 0; q <= NS; ++q) {
+            const int dx = q < NS ? S::DX[q] : 0, dy = q < NS ? S::DY[q] : 0;
+            const int k = kmap[q];
+            const bool in = k >= 0 && x + dx >= 0 && x + dx < ex && y + dy >= 0 && y + dy < ey;
+            const double av = a.A[(size_t)max(k, 0) * a.N + g];
+            v[q] = in ? av : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q <= NS; ++q) Wr[(size_t)c * RL + q] = v[q];
+        Wr[(size_t)c * RL + NS + 1] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int y = threadIdx.x;
+        unsigned pm = 0;   // slots present in the stencil (uniform)
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+            if (kmap[q] >= 0) pm |= 1u << q;
+        const int T = (ex - 1) + LB * (ey - 1) + 1;
+        int bad = 0;
+        for (int t = 0; t < T; ++t) {
+            const int x = t - LB * y;
+            const bool act = y < ey && x >= 0 && x < ex;
+            const int c = act ? y * ex + x : 0;
+            double r[NS + 1];
+#pragma unroll
+            for (int q = 0; q <= NS; ++q) r[q] = Wr[(size_t)c * RL + q];
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                const int xk = x + S::DX[q];
+                const bool in = act && ((pm >> q) & 1u) && xk >= 0 && xk < ex && y + S::DY[q] >= 0;
+                // branch-free: every read has a valid (clamped) address and
+                // an absent neighbour's l is cleared bitwise
+                const int ck = min(max(c + S::DX[q] + S::DY[q] * ex, 0), n - 1);
+                const double l = __longlong_as_double(__double_as_longlong(r[q] * Wr[(size_t)ck * RL + NS + 1]) &
+                                                      (in ? ~0ll : 0ll));
+                r[q] = l;
+#pragma unroll
+                for (int p = NL; p < NS; ++p) {
+                    const int tg = row_slot<BOX>(S::DX[q] + S::DX[p], S::DY[q] + S::DY[p]);
+                    if (tg < 0) continue;
+                    r[tg] -= l * Wr[(size_t)ck * RL + p];
+                }
+            }
+            const double u = r[NS];
+            if (act) {
+                if (!(u != 0.0) || !isfinite(u)) bad = 1;
+#pragma unroll
+                for (int q = 0; q < NS; ++q) Wr[(size_t)c * RL + q] = ((pm >> q) & 1u) ? r[q] : 0.0;
+                Wr[(size_t)c * RL + NS] = u;
+                Wr[(size_t)c * RL + NS + 1] = 1.0 / u;
+            }
+            // the next step reads rows that lanes of this wavefront wrote
+            // above: LDS operations of one wavefront complete in order, the
+            // fences keep the compiler from moving reads above those writes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (bad) atomicOr(a.err, 1);
+    }
+    __syncthreads();
+    // factors out, k-major, cells contiguous
+    const size_t fo = sd.fac_off;
+    for (int i = threadIdx.x; i < (NS + 1) * n; i += blockDim.x) {
+        const int q = i / n, c = i - q * n;
+        const int k = kmap[q];
+        if (k >= 0) a.w[(size_t)k * a.NE + fo + c] = Wr[(size_t)c * RL + q];
     }
 }
 
@@ -1330,6 +1474,21 @@ void Ras::factor() {
         fa.w = V.w64.p;
         fa.err = V.err.p;
         const int bs = 64;
+        const int *perm = V.rows2d ? V.lexg.p : nullptr;
+        const int rl = V.box == 0 ? RowStencil<0>::NS + 2 : (V.box == 1 ? RowStencil<1>::NS + 2 : RowStencil<2>::NS + 2);
+        const size_t sh_rows = sizeof(double) * (size_t)rl * V.max_next;
+        if (V.rows2d && sh_rows <= (size_t)lds_bytes) {
+            // 2D box in LDS, factored on the sweeps' wavefront schedule;
+            // factors come out in lexicographic order
+            IluRowsArgs ia{V.sub.p, V.spp->blk.p, V.slotmap.p, V.A->coef.p, V.spp->N, V.next_total,
+                           V.A->st.diag, V.w64.p, V.err.p};
+            void (*fr)(IluRowsArgs) =
+                V.box == 0 ? k_ilu_rows<0> : (V.box == 1 ? k_ilu_rows<1> : k_ilu_rows<2>);
+            set_lds((const void *)fr, sh_rows);
+            launch_timed("ilu_factor", l, fr, dim3(V.nsub), dim3(256), sh_rows, s, ia);
+            KCHECK();
+            perm = nullptr;
+        } else {
         const size_t sh_lds = sizeof(double) * (size_t)fa.K * V.max_next +
                               sizeof(int) * ((size_t)V.max_tile + V.max_nlev + 1 + 2 * (size_t)fa.K + 1 +
                                              2 * (size_t)V.nupd + V.max_next);
@@ -1350,8 +1509,8 @@ void Ras::factor() {
             launch_timed("ilu_factor", l, k_ilu_factor, dim3(V.nsub), dim3(bs), sh, s, fa);
             KCHECK();
         }
+        }
         const int NE = V.next_total;
-        const int *perm = V.rows2d ? V.lexg.p : nullptr;
         if (d.precision == NKS_FP64) {
             k_ilu_store<double, double><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, V.f64.p, V.invd64.p, perm);
         } else if (d.precision == NKS_FP32) {
@@ -1402,14 +1561,12 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     a.mask = mask;
     a.variant = M.d.variant;
     a.accumulate = accumulate ? 1 : 0;
-    const int per = (int)(16 / sizeof(FT));
-    auto pad = [&](int k) { return (k + per - 1) / per * per; };
-    const int NSP = V.box ? pad(RowStencil<1>::NL) + pad(RowStencil<1>::NS - RowStencil<1>::NL)
-                          : pad(RowStencil<0>::NL) + pad(RowStencil<0>::NS - RowStencil<0>::NL);
+    const int NSP = V.box == 0 ? row_run<0, FT>() : (V.box == 1 ? row_run<1, FT>() : row_run<2, FT>());
     const size_t n = V.max_next;
     const size_t sh = al16(sizeof(VT) * n) + al16(sizeof(FT) * NSP * n) + al16(sizeof(DT) * n);
     if (sh > (size_t)M.lds_bytes) fail(NKS_EINVAL, "2D subdomain of %zu cells does not fit in LDS", n);
-    void (*fn)(RowsArgs) = V.box ? k_ras_rows<FT, VT, DT, 1> : k_ras_rows<FT, VT, DT, 0>;
+    void (*fn)(RowsArgs) = V.box == 0 ? k_ras_rows<FT, VT, DT, 0>
+                                      : (V.box == 1 ? k_ras_rows<FT, VT, DT, 1> : k_ras_rows<FT, VT, DT, 2>);
     set_lds((const void *)fn, sh);
     launch_timed("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(256), sh, M.g->s, a);
     KCHECK();
