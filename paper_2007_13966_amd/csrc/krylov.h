@@ -39,7 +39,13 @@ struct Gmres {
     Alloc *al = nullptr;
     const Space *sp = nullptr;
     int m = 0, nb = 0, nn = 0;
-    std::vector<DBuf<double>> V, Z;
+    struct Col {
+        double *p = nullptr;   // a column of Vall
+    };
+    DBuf<double> Vall;         // Krylov basis, (m + 1) columns of stride ld
+    long ld = 0;
+    std::vector<Col> V;
+    std::vector<DBuf<double>> Z;
     DBuf<double> w, r, t, H, cs, sn, g, y, hj, scal;
     DBuf<int> ints;
     DBuf<const double *> vptr, zptr;

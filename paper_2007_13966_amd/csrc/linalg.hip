@@ -264,26 +264,63 @@ __device__ __forceinline__ double row_sum(double v) {
     return v;
 }
 
-// Sums over the workgroup (4 waves = 16 rows of 16 lanes) of v[c], c < NC:
-// row sums by DPP, the 16 row sums through LDS, added in row order by
-// thread c < nc into dst(c).  NC is a compile-time bound; columns past nc
-// hold zeros and are not stored.
+// Sums over TP consecutive lanes (TP = 8, 16, 32, 64): DPP quad swaps and
+// row mirrors inside a row of 16 lanes, then lane shuffles across rows and
+// across the two halves of the wavefront.  Each step adds two operands that
+// the partner lane adds in the other order, so every lane of a group ends
+// with the same value, bitwise.
+template <int TP>
+__device__ __forceinline__ double group_sum(double v) {
+    static_assert(TP == 8 || TP == 16 || TP == 32 || TP == 64, "lane group of 8, 16, 32 or 64");
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0x141>(v);
+    if constexpr (TP >= 16) v += dpp_mov<0x140>(v);
+    if constexpr (TP >= 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (TP >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// Sums over the workgroup (RED_THREADS threads) of v[c], c < NC; thread
+// (c, s) with s == 0 passes column c < nc to dst(c, total).
+// NC <= 2: row sums by DPP, the 16 row sums (4 waves x 4 rows) through LDS,
+// added in row order.  NC >= 4: the values go through LDS column-major, TP =
+// RED_THREADS / NC consecutive threads add one column's entries in a fixed
+// order and finish with a lane-group sum, so the work per thread grows with
+// NC, not with NC times the reduction depth.
 template <int NC, typename Store>
-__device__ __forceinline__ void workgroup_columns(double (&v)[NC], int nc, Store dst) {
-    __shared__ double sh[16][NC];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+__device__ __forceinline__ void workgroup_columns(const double (&v)[NC], int nc, Store dst) {
+    if constexpr (NC <= 2) {
+        __shared__ double sh[16][NC];
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        double r[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) v[c] = row_sum(v[c]);
-    if ((lane & 15) == 0) {
+        for (int c = 0; c < NC; ++c) r[c] = row_sum(v[c]);
+        if ((lane & 15) == 0) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sh[w * 4 + (lane >> 4)][c] = v[c];
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nc) {
-        double t = 0.0;
-        const int nr = (blockDim.x >> 6) * 4;
-        for (int k = 0; k < nr; ++k) t += sh[k][threadIdx.x];
-        dst(threadIdx.x, t);
+            for (int c = 0; c < NC; ++c) sh[w * 4 + (lane >> 4)][c] = r[c];
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nc) {
+            double t = 0.0;
+            const int nr = (blockDim.x >> 6) * 4;
+            for (int k = 0; k < nr; ++k) t += sh[k][threadIdx.x];
+            dst(threadIdx.x, t);
+        }
+    } else {
+        constexpr int TP = RED_THREADS / NC;
+        constexpr int LD = RED_THREADS + 2;   // column stride, off the LDS bank period
+        __shared__ double sh[NC * LD];
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sh[c * LD + t] = v[c];
+        __syncthreads();
+        const int c = t / TP, q = t - c * TP;
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) a += sh[c * LD + q + TP * k];
+        a = group_sum<TP>(a);
+        if (q == 0 && c < nc) dst(c, a);
     }
 }
 
@@ -299,21 +336,40 @@ __device__ __forceinline__ void chunk_columns(const double (&acc)[M], int nc, do
 }
 
 // totals of the nc partial columns of reservoir b (chunks [q0, q1), at most
-// blockDim chunks, column stride ns) into out[0..nc) in LDS, visible to the
-// whole workgroup.  Branch-free over the NC columns: every load has a valid
+// RED_THREADS chunks, column stride ns) into out[0..NC) in LDS (zero past
+// nc), visible to the whole workgroup.  Branch-free: every load has a valid
 // address (clamped column and chunk) and out-of-range values are zeroed.
+// NC >= 4: TP = RED_THREADS / NC consecutive threads share a column, each
+// adding every TP-th chunk, then a lane-group sum.
 template <int NC>
 __device__ __forceinline__ void block_totals(const double *part, int q0, int q1, int nc, double *out, int ns) {
-    const int q = q0 + (int)threadIdx.x;
-    const bool qin = q < q1;
-    const int qq = qin ? q : q0;
-    double v[NC];
+    static_assert(MAXCH <= RED_THREADS, "one reduction thread per chunk");
+    if constexpr (NC <= 2) {
+        const int q = q0 + (int)threadIdx.x;
+        const bool qin = q < q1;
+        const int qq = qin ? q : q0;
+        double v[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const double x = part[(size_t)min(c, max(nc - 1, 0)) * ns + qq];
-        v[c] = (c < nc && qin) ? x : 0.0;
+        for (int c = 0; c < NC; ++c) {
+            const double x = part[(size_t)min(c, max(nc - 1, 0)) * ns + qq];
+            v[c] = (c < nc && qin) ? x : 0.0;
+        }
+        workgroup_columns<NC>(v, nc, [&](int c, double t) { out[c] = t; });
+        if ((int)threadIdx.x >= nc && (int)threadIdx.x < NC) out[threadIdx.x] = 0.0;
+    } else {
+        constexpr int TP = RED_THREADS / NC;
+        const int c = (int)threadIdx.x / TP, s = (int)threadIdx.x - c * TP;
+        const double *col = part + (size_t)min(c, max(nc - 1, 0)) * ns;
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int q = q0 + s + TP * k;
+            const double x = col[min(q, q1 - 1)];
+            a += q < q1 ? x : 0.0;
+        }
+        a = group_sum<TP>(a);
+        if (s == 0) out[c] = c < nc ? a : 0.0;
     }
-    workgroup_columns<NC>(v, nc, [&](int c, double t) { out[c] = t; });
     __syncthreads();
 }
 
@@ -427,10 +483,6 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_tol(const Chunk *chunks, con
     if (threadIdx.x == 0) st.tol[ch.blk] = fmax(st.rtol * sqrt(tot[0]), st.atol);
 }
 
-// Krylov vector pointers by value (kernel arguments land in scalar registers)
-struct VPtrs {
-    const double *p[MAXCOL];
-};
 
 // One Arnoldi step j of classical Gram-Schmidt with one reorthogonalisation
 // (CGS2) takes three kernels after the preconditioner:
@@ -449,7 +501,7 @@ struct VPtrs {
 
 // pass-1 partials of w = A z with V[0..j] (stencil operator, chunk grid)
 template <int NC>
-__global__ void __launch_bounds__(RED_THREADS) k_gm_spmv_dots(const Chunk *chunks, SpmvArgs a, VPtrs V, int j,
+__global__ void __launch_bounds__(RED_THREADS) k_gm_spmv_dots(const Chunk *chunks, SpmvArgs a, const double *V, long ld, int j,
                                                               double *part, const int *act) {
     __shared__ int sh[MAXK];
     stage_offsets(a.off, a.K, sh);
@@ -464,7 +516,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_spmv_dots(const Chunk *chunk
             double vv[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
-                if (c < nc) vv[c] = V.p[c][i];
+                if (c < nc) vv[c] = V[(size_t)c * ld + i];
             const int l = i - k.off;
             const int x = l % k.nx, y = (l / k.nx) % k.ny, z = l / (k.nx * k.ny);
             const double wi = stencil_dot(sh, a.K, a.coef, a.N, a.x, i, x, y, z, k);
@@ -479,7 +531,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_spmv_dots(const Chunk *chunk
 
 // pass-1 partials V[0..j]^T w (w from a generic operator)
 template <int NC>
-__global__ void __launch_bounds__(RED_THREADS) k_gm_dots(const Chunk *chunks, const double *w, VPtrs V, int j,
+__global__ void __launch_bounds__(RED_THREADS) k_gm_dots(const Chunk *chunks, const double *w, const double *V, long ld, int j,
                                                          double *part, const int *act) {
     const Chunk ch = chunks[blockIdx.x];
     const int nc = j + 1;
@@ -491,7 +543,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_dots(const Chunk *chunks, co
             double vv[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
-                if (c < nc) vv[c] = V.p[c][i];
+                if (c < nc) vv[c] = V[(size_t)c * ld + i];
             const double wi = w[i];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
@@ -505,7 +557,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_dots(const Chunk *chunks, co
 // V^T w in columns 0..j and w.w in column j+1
 template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_gm_update_dots(const Chunk *chunks, const int *cfirst, double *w,
-                                                                VPtrs V, int j, const double *pin, double *pout,
+                                                                const double *V, long ld, int j, const double *pin, double *pout,
                                                                 GmDev st, const int *act) {
     __shared__ double hc[NC];
     const Chunk ch = chunks[blockIdx.x];
@@ -522,7 +574,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_update_dots(const Chunk *chu
             double vv[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
-                if (c < nc) vv[c] = V.p[c][i];
+                if (c < nc) vv[c] = V[(size_t)c * ld + i];
             double t = w[i];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
@@ -544,7 +596,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_update_dots(const Chunk *chu
 // residual estimate, and decides act_{j+1} and the host flag (single writer).
 template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, const int *cfirst, const double *w,
-                                                           VPtrs V, int j, const double *pin, double *vn, GmDev st,
+                                                           const double *V, long ld, int j, const double *pin, double *vn, GmDev st,
                                                            const int *act, int *act_next, int slot) {
     __shared__ double hc[NC];
     const Chunk ch = chunks[blockIdx.x];
@@ -628,7 +680,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
             double vv[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
-                if (c < nc) vv[c] = V.p[c][i];
+                if (c < nc) vv[c] = V[(size_t)c * ld + i];
             double t = w[i];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
@@ -693,8 +745,12 @@ void Gmres::ensure(Alloc *al_, const Space &sp_, int m_, bool flexible, hipStrea
         nn = N;
         V.clear();
         Z.clear();
+        // one allocation for the basis: column k at Vall + k * ld, ld a
+        // multiple of 64 doubles, so kernels address it from one pointer
+        ld = ((long)N + 63) / 64 * 64;
+        Vall.alloc(al, (size_t)(m + 1) * ld);
         V.resize(m + 1);
-        for (auto &v : V) v.alloc(al, N);
+        for (int k = 0; k <= m; ++k) V[k].p = Vall.p + (size_t)k * ld;
         if (flexible) {
             Z.resize(m);
             for (auto &z : Z) z.alloc(al, N);
@@ -802,8 +858,7 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
     KCHECK();
     HIPC(hipEventRecord(ev[3], s));
     const double *const *Vp = vptr.p;
-    VPtrs vps{};
-    for (int k = 0; k <= m && k < MAXCOL; ++k) vps.p[k] = V[k].p;
+    const double *vb = V[0].p;   // the basis: m + 1 columns of stride ld
     const bool flex = o.flexible;
     // one GMRES iteration j; its activity flags go to `slot`
     auto iteration = [&](int j, int slot) {
@@ -817,16 +872,16 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
             constexpr int NC = decltype(bound)::value;
             if (Aop) {
                 SpmvArgs sa = spmv_args(*Aop, zj, w.p, nullptr, nullptr);
-                k_gm_spmv_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, vps, j, P0, act);
+                k_gm_spmv_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, vb, ld, j, P0, act);
                 KCHECK();
             } else {
                 A(zj, w.p, nullptr, act);
-                k_gm_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, w.p, vps, j, P0, act);
+                k_gm_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, w.p, vb, ld, j, P0, act);
                 KCHECK();
             }
-            k_gm_update_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vps, j, P0, P1, st, act);
+            k_gm_update_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vb, ld, j, P0, P1, st, act);
             KCHECK();
-            k_gm_finish<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vps, j, P1, V[j + 1].p, st,
+            k_gm_finish<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vb, ld, j, P1, V[j + 1].p, st,
                                                         act, act_next, slot);
             KCHECK();
         });
