@@ -610,6 +610,30 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
         }
         return;
     }
+    // the lead chunk stages H[:, j] (h1), the previous rotations and g[j]
+    // in LDS, one value per thread, while the partial totals load
+    __shared__ double gv[3 * NC + 1];
+    const int m = st.m;
+    double *H = st.H + (size_t)b * (m + 1) * m;
+    double *cs = st.cs + (size_t)b * m, *sn = st.sn + (size_t)b * m;
+    double *g = st.g + (size_t)b * (m + 1);
+    if (lead) {
+        const int t = threadIdx.x, jm = max(j - 1, 0);
+        if (t < NC) {
+            gv[t] = H[(size_t)min(t, j) * m + j];
+            gv[NC + t] = cs[min(t, jm)];
+            gv[2 * NC + t] = sn[min(t, jm)];
+        } else if (t == NC) {
+            gv[3 * NC] = g[j];
+        }
+    }
+    // the lead thread's scalars, loaded ahead of the reduction
+    int its0 = 0;
+    double tol0 = 0.0;
+    if (lead && threadIdx.x == 0) {
+        its0 = st.its[b];
+        tol0 = st.tol[b];
+    }
     block_totals<NC>(pin, cfirst[b], cfirst[b + 1], nc + 1, hc, gridDim.x);
     double h2sq = 0.0;
     for (int c = 0; c < nc; ++c) h2sq += hc[c] * hc[c];
@@ -617,25 +641,17 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
     // the lead chunk's first thread applies the rotations before its share
     // of the vector work (the Givens step needs only the totals)
     if (lead && threadIdx.x == 0) {
-        const int m = st.m;
-        double *H = st.H + (size_t)b * (m + 1) * m;
-        double *cs = st.cs + (size_t)b * m, *sn = st.sn + (size_t)b * m;
-        double *g = st.g + (size_t)b * (m + 1);
-        // column j (h1 + h2) and the previous rotations in registers; every
-        // load has a valid (clamped) address, out-of-range values are replaced
+        // column j (h1 + h2) and the previous rotations in registers;
+        // out-of-range entries are replaced
         double hcol[NC + 1], cc[NC], ss[NC];
-        const int jm = max(j - 1, 0);
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            const int kk = min(k, j);
-            const double hv = H[(size_t)kk * m + j] + hc[kk];
-            const double cv = cs[min(k, jm)], sv = sn[min(k, jm)];
-            hcol[k] = k <= j ? hv : 0.0;
-            cc[k] = k < j ? cv : 1.0;
-            ss[k] = k < j ? sv : 0.0;
+            hcol[k] = k <= j ? gv[k] + hc[k] : 0.0;
+            cc[k] = k < j ? gv[NC + k] : 1.0;
+            ss[k] = k < j ? gv[2 * NC + k] : 0.0;
         }
         hcol[NC] = 0.0;
-        const double gj = g[j];
+        const double gj = gv[3 * NC];
 #pragma unroll
         for (int k = 0; k < NC - 1; ++k) {
             if (k < j) {
@@ -660,19 +676,22 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
         sn[j] = sg;
         g[j + 1] = -sg * gj;
         g[j] = c * gj;
-        st.its[b] += 1;
+        // an active reservoir has not converged before this iteration
+        const int its1 = its0 + 1;
+        st.its[b] = its1;
         st.kdim[b] = j + 1;
-        const double res = fabs(g[j + 1]);
+        const double res = fabs(sg * gj);
         st.res[b] = res;
-        int nxt = 1;
-        if (res <= st.tol[b] || hn == 0.0) {
+        int nxt = 1, conv = 0;
+        if (res <= tol0 || hn == 0.0) {
+            conv = 1;
             st.conv[b] = 1;
             nxt = 0;
-        } else if (st.its[b] >= st.maxit || j + 1 == m) {
+        } else if (its1 >= st.maxit || j + 1 == m) {
             nxt = 0;   // restart (or stop at maxit)
         }
         act_next[b] = nxt;
-        st.flag[slot * st.nb + b] = nxt ? 1 : (st.conv[b] ? 2 : 0);
+        st.flag[slot * st.nb + b] = nxt ? 1 : (conv ? 2 : 0);
     }
     if (hn > 0.0) {
         const double inv = 1.0 / hn;
