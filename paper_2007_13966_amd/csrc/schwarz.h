@@ -19,7 +19,8 @@ struct SubDev {
     int lvl_off;                 // first entry of this subdomain's level pointers
     int nlev;                    // wavefront levels
     int inv_off;                 // first entry of the padded-tile inverse map
-    int pad;
+    int gorg;                    // global index of the extended box's origin cell
+    int gnx;                     // row stride (cells) of its block
 };
 
 // Per block box layout of a level (for the AS / right-RAS gather)
@@ -72,6 +73,7 @@ struct Level {
     bool rows2d = false;
     int box = 0;                 // 0: 5-point cross, 1: 5x5 box, 2: 21-point (5x5 without corners)
     DBuf<int> slotmap;           // box slot -> stencil index (-1: absent)
+    std::vector<int> hslot;      // host copy of slotmap
     DBuf<double> invd64;         // 1/u_ii
     DBuf<float> invd32;
     DBuf<double> zext;           // per extended cell solution (AS / right-RAS gather)

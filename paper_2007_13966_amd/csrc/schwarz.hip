@@ -56,6 +56,51 @@ template <> struct FTraits<uint16_t> {
     __device__ static float get(const uint16_t *p, size_t i) { return from_bf16(p[i]); }
 };
 
+// ---------------------------------------------------------------- row templates (2D levels)
+// stencil shapes: 0 = 5-point cross (lb 1), 1 = 5x5 box (lb 3), 2 = the
+// 21-point stencil (5x5 without its corners, lb 3: the Galerkin product of
+// the 5-point operator with second-order interpolation)
+template <int BOX> struct RowStencil;
+template <> struct RowStencil<0> {
+    static constexpr int LB = 1, H = 1, NS = 4, NL = 2;
+    // off-diagonal slots in increasing column order: (dx, dy)
+    static constexpr int DX[NS] = {0, -1, 1, 0};
+    static constexpr int DY[NS] = {-1, 0, 0, 1};
+};
+template <> struct RowStencil<1> {
+    static constexpr int LB = 3, H = 8, NS = 24, NL = 12;
+    static constexpr int DX[NS] = {-2, -1, 0, 1, 2, -2, -1, 0, 1, 2, -2, -1, 1, 2, -2, -1, 0, 1, 2, -2, -1, 0, 1, 2};
+    static constexpr int DY[NS] = {-2, -2, -2, -2, -2, -1, -1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2};
+};
+template <> struct RowStencil<2> {
+    static constexpr int LB = 3, H = 8, NS = 20, NL = 10;
+    static constexpr int DX[NS] = {-1, 0, 1, -2, -1, 0, 1, 2, -2, -1, 1, 2, -2, -1, 0, 1, 2, -1, 0, 1};
+    static constexpr int DY[NS] = {-2, -2, -2, -1, -1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2};
+};
+
+// padded per-cell factor run of a row template: lower run, then upper run,
+// each a whole number of 16-byte words of FT
+template <int BOX, typename FT>
+constexpr int row_run() {
+    constexpr int PER = (int)(16 / sizeof(FT));
+    return (RowStencil<BOX>::NL + PER - 1) / PER * PER +
+           (RowStencil<BOX>::NS - RowStencil<BOX>::NL + PER - 1) / PER * PER;
+}
+
+// stencil index of every slot of the padded run (lower run, then upper
+// run), from the 25 box slots of the level's stencil; -1 for absent slots
+// and padding
+template <int BOX, typename FT>
+static void row_kmap(const std::vector<int> &slot, int (&kmap)[32]) {
+    using S = RowStencil<BOX>;
+    constexpr int PER = (int)(16 / sizeof(FT));
+    constexpr int NL = S::NL, NU = S::NS - S::NL;
+    constexpr int NLP = (NL + PER - 1) / PER * PER;
+    for (int r = 0; r < 32; ++r) kmap[r] = -1;
+    for (int q = 0; q < NL; ++q) kmap[q] = slot[(S::DX[q] + 2) + 5 * (S::DY[q] + 2)];
+    for (int q = 0; q < NU; ++q) kmap[NLP + q] = slot[(S::DX[NL + q] + 2) + 5 * (S::DY[NL + q] + 2)];
+}
+
 // ---------------------------------------------------------------- host: partition
 static void box_range(int n, int P, int q, int &lo, int &hi) {
     const int base = n / P, rem = n % P;
@@ -94,7 +139,7 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
     L.hsub.clear();
     L.hpart.clear();
     // first pass: boxes and maximum extents
-    int mex = 1, mey = 1, mez = 1;
+    int mex = 1, mey = 1, mez = 1, minex = 1 << 30;
     for (int b = 0; b < S.B; ++b) {
         const Blk &k = S.hblk[b];
         const int P[3] = {std::min(boxes[b][0], k.nx), std::min(boxes[b][1], k.ny), std::min(boxes[b][2], k.nz)};
@@ -122,7 +167,10 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
                     sd.ly0 = lo[1] - elo[1]; sd.ly1 = hi[1] - elo[1];
                     sd.lz0 = lo[2] - elo[2]; sd.lz1 = hi[2] - elo[2];
                     sd.next = sd.ex * sd.ey * sd.ez;
+                    sd.gorg = k.off + elo[0] + k.nx * (elo[1] + k.ny * elo[2]);
+                    sd.gnx = k.nx;
                     mex = std::max(mex, sd.ex);
+                    minex = std::min(minex, sd.ex);
                     mey = std::max(mey, sd.ey);
                     mez = std::max(mez, sd.ez);
                     L.hsub.push_back(sd);
@@ -198,9 +246,14 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
         bool corner = false;
         for (int k = 0; k < st.K; ++k)
             if (std::abs(st.off[3 * k]) == 2 && std::abs(st.off[3 * k + 1]) == 2) corner = true;
-        L.box = cross ? 0 : (corner ? 1 : 2);
-        L.slotmap.upload(al, slot, s);
-        L.rows2d = true;
+        const int box = cross ? 0 : (corner ? 1 : 2);
+        // the sweep's cell arithmetic needs boxes at least LB wide
+        if (minex >= (box == 0 ? RowStencil<0>::LB : RowStencil<1>::LB)) {
+            L.box = box;
+            L.slotmap.upload(al, slot, s);
+            L.hslot = slot;
+            L.rows2d = true;
+        }
     }
     // stencil tables
     std::vector<int> lin(st.K);
@@ -772,58 +825,24 @@ __global__ void __launch_bounds__(256) k_ras_apply(ApplyArgs a) {
 // register ring and reads the rows below / above through DPP lane shifts;
 // only the factor coefficients and the right-hand side come from LDS.
 __device__ __forceinline__ float lane_shr(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float lane_shl(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double lane_shr(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, true);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double lane_shl(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x130, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, true);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-// stencil shapes: 0 = 5-point cross (lb 1), 1 = 5x5 box (lb 3), 2 = the
-// 21-point stencil (5x5 without its corners, lb 3: the Galerkin product of
-// the 5-point operator with second-order interpolation)
-template <int BOX> struct RowStencil;
-template <> struct RowStencil<0> {
-    static constexpr int LB = 1, H = 1, NS = 4, NL = 2;
-    // off-diagonal slots in increasing column order: (dx, dy)
-    static constexpr int DX[NS] = {0, -1, 1, 0};
-    static constexpr int DY[NS] = {-1, 0, 0, 1};
-};
-template <> struct RowStencil<1> {
-    static constexpr int LB = 3, H = 8, NS = 24, NL = 12;
-    static constexpr int DX[NS] = {-2, -1, 0, 1, 2, -2, -1, 0, 1, 2, -2, -1, 1, 2, -2, -1, 0, 1, 2, -2, -1, 0, 1, 2};
-    static constexpr int DY[NS] = {-2, -2, -2, -2, -2, -1, -1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2};
-};
-template <> struct RowStencil<2> {
-    static constexpr int LB = 3, H = 8, NS = 20, NL = 10;
-    static constexpr int DX[NS] = {-1, 0, 1, -2, -1, 0, 1, 2, -2, -1, 1, 2, -2, -1, 0, 1, 2, -1, 0, 1};
-    static constexpr int DY[NS] = {-2, -2, -2, -1, -1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2};
-};
-
-// padded per-cell factor run of a row template: lower run, then upper run,
-// each a whole number of 16-byte words of FT
-template <int BOX, typename FT>
-constexpr int row_run() {
-    constexpr int PER = (int)(16 / sizeof(FT));
-    return (RowStencil<BOX>::NL + PER - 1) / PER * PER +
-           (RowStencil<BOX>::NS - RowStencil<BOX>::NL + PER - 1) / PER * PER;
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
 }
 
 struct RowsArgs {
     const SubDev *sub;
-    const Blk *blk;
-    const int *slotmap;   // 25 box slots -> stencil index or -1
     const void *F;        // K*NE off-diagonal factors (FT), lexicographic per subdomain
     const void *invd;     // NE (DT)
     int NE;
@@ -831,6 +850,7 @@ struct RowsArgs {
     double *z, *zext;
     const int *mask;
     int variant, accumulate;
+    int kmap[32];         // slot of the padded per-cell run -> stencil index (-1: absent or padding)
 };
 
 // coefficients of one cell: N consecutive FT values (16-byte aligned runs)
@@ -852,6 +872,18 @@ __device__ __forceinline__ void load_run(const FT *p, VT (&out)[N]) {
     }
 }
 
+// (x, y) of cell c of a box ex wide, by a float reciprocal: exact for
+// c < 2^16 and ex <= 64, where (c + 1/2) / ex stays 1/128 off integers
+__device__ __forceinline__ int row_of(int c, float inv_ex) { return (int)(((float)c + 0.5f) * inv_ex); }
+
+// Every instruction of the sweeping wavefront costs an issue slot (one
+// wavefront per SIMD), so the step loop keeps only the arithmetic, the LDS
+// traffic and the lane shifts: the cell of step t is cb + t, which stays in
+// the box for every t when the box is at least LB cells wide (steps outside
+// a row's range read a neighbouring row's cell and are masked; rows past
+// the box repeat the last row), stores of masked steps go to a spare slot,
+// and the stencil map arrives in the kernel arguments.  The upper factors and 1/u_ii are
+// staged by the other wavefronts while the forward sweep runs.
 template <typename FT, typename VT, typename DT, int BOX>
 __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
     using S = RowStencil<BOX>;
@@ -860,176 +892,199 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
     constexpr int NLP = (NL + PER - 1) / PER * PER, NUP = (NU + PER - 1) / PER * PER;
     constexpr int NSP = NLP + NUP;   // padded run per cell: lower run, then upper run
     constexpr int RU = 8;            // unroll = ring length (>= the deepest history used)
+    constexpr int CPT = 2;           // cells per staging thread per pass
+    static_assert(NSP <= 32, "stencil map fits the argument block");
     extern __shared__ __align__(16) unsigned char smem[];
     const SubDev sd = a.sub[blockIdx.x];
     if (a.mask && !a.mask[sd.blk]) return;
-    const Blk bk = a.blk[sd.blk];
     const int n = sd.next, ex = sd.ex, ey = sd.ey;
+    // LDS: rv[n + 1] (slot n takes the stores of masked steps), cf[n * NSP], id[n]
     VT *rv = reinterpret_cast<VT *>(smem);
-    FT *cf = reinterpret_cast<FT *>(smem + al16(sizeof(VT) * (size_t)n));
+    FT *cf = reinterpret_cast<FT *>(smem + al16(sizeof(VT) * (size_t)(n + 1)));
     static_assert(sizeof(FT) * NSP % 16 == 0, "cell runs are whole 16-byte words");
-    DT *id = reinterpret_cast<DT *>(smem + al16(sizeof(VT) * (size_t)n) + al16(sizeof(FT) * (size_t)NSP * n));
+    DT *id = reinterpret_cast<DT *>(smem + al16(sizeof(VT) * (size_t)(n + 1)) + al16(sizeof(FT) * (size_t)NSP * n));
     const FT *F = reinterpret_cast<const FT *>(a.F);
     const DT *ID = reinterpret_cast<const DT *>(a.invd);
     const size_t fo = sd.fac_off;
-    __shared__ int kmap[NSP];
-    if ((int)threadIdx.x < NSP) {
-        const int r = threadIdx.x;
-        int k = -1;
-        if (r < NL) k = a.slotmap[(S::DX[r] + 2) + 5 * (S::DY[r] + 2)];
-        else if (r >= NLP && r < NLP + NU)
-            k = a.slotmap[(S::DX[r - NLP + NL] + 2) + 5 * (S::DY[r - NLP + NL] + 2)];
-        kmap[r] = k;
-    }
-    __syncthreads();
-    // stage: coefficients cell-major (cf[c*NSP + slot], absent slots zero),
-    // 1/u_ii and R_i^delta r.  Thread t takes cells t, t+256, ...; every load
-    // of a group of CPT cells is issued before the first LDS store.
-    {
-        constexpr int CPT = BOX ? 2 : 8;
-        int ks[NSP];
+    const float inv_ex = 1.0f / (float)ex;
+    const int wid = threadIdx.x >> 6;
+    // stage: lower runs and R_i^delta r (all threads).  Absent slots and the
+    // padding load a valid address and store zero; every load of a pass is
+    // issued before its first LDS store.
+    for (int c0 = threadIdx.x; c0 < n; c0 += CPT * 256) {
+        FT v[CPT][NLP];
+        double rr[CPT];
 #pragma unroll
-        for (int q = 0; q < NSP; ++q) ks[q] = kmap[q];
-        for (int c0 = threadIdx.x; c0 < n; c0 += CPT * 256) {
-            FT v[CPT][NSP];
-            DT d[CPT];
-            double rr[CPT];
+        for (int u = 0; u < CPT; ++u) {
+            const int c = min(c0 + u * 256, n - 1);
 #pragma unroll
-            for (int u = 0; u < CPT; ++u) {
-                const int c = c0 + u * 256;
-                if (c < n) {
-#pragma unroll
-                    for (int q = 0; q < NSP; ++q) v[u][q] = ks[q] >= 0 ? F[(size_t)ks[q] * a.NE + fo + c] : (FT)0;
-                    d[u] = ID[fo + c];
-                    const int y = c / ex, x = c - y * ex;
-                    rr[u] = a.r[bk.off + (sd.ox + x) + bk.nx * (sd.oy + y + bk.ny * sd.oz)];
-                }
+            for (int q = 0; q < NLP; ++q) {
+                const int k = a.kmap[q];
+                const FT x = F[(size_t)max(k, 0) * a.NE + fo + c];
+                v[u][q] = k >= 0 ? x : (FT)0;
             }
+            const int y = row_of(c, inv_ex), x = c - y * ex;
+            rr[u] = a.r[(size_t)sd.gorg + x + (size_t)sd.gnx * y];
+        }
 #pragma unroll
-            for (int u = 0; u < CPT; ++u) {
-                const int c = c0 + u * 256;
-                if (c < n) {
+        for (int u = 0; u < CPT; ++u) {
+            const int c = c0 + u * 256;
+            if (c < n) {
 #pragma unroll
-                    for (int q = 0; q < NSP; ++q) cf[(size_t)c * NSP + q] = v[u][q];
-                    id[c] = d[u];
-                    const int y = c / ex, x = c - y * ex;
-                    const bool own = x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1;
-                    rv[c] = (VT)((a.variant == NKS_RIGHT_RAS && !own) ? 0.0 : rr[u]);
-                }
+                for (int q = 0; q < NLP; ++q) cf[(size_t)c * NSP + q] = v[u][q];
+                const int y = row_of(c, inv_ex), x = c - y * ex;
+                const bool own = x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1;
+                rv[c] = (VT)((a.variant == NKS_RIGHT_RAS && !own) ? 0.0 : rr[u]);
             }
         }
     }
     __syncthreads();
     // one wavefront sweeps, lane = row.  For the 5-point cross, lanes past
     // the box's rows stay disabled (no LDS traffic; a DPP read from them
-    // returns zero, the value of a row outside the box); for the 5x5 box all
-    // lanes run, which measures faster
-    if ((int)threadIdx.x < (BOX ? 64 : min(64, ey))) {
-    const int y = threadIdx.x;
+    // returns zero, the value of a row outside the box); for the box
+    // stencils all lanes run and rows past the box are masked.
     const int T = (ex - 1) + LB * (ey - 1) + 1;
+    const int y = threadIdx.x;
+    const bool rowok = y < ey;
+    const int ye = min(y, ey - 1);
+    const int tlo = rowok ? LB * y : (1 << 28);   // steps with x = t - LB*y inside the row
+    const int cb = ye * (ex - LB);                // cell of step t: cb + t (forward)
     // RB steps per block: every LDS read of a block is issued before its
     // first step and every write after its last, so the loads overlap the
     // dependent arithmetic of the previous block.
     constexpr int RB = BOX ? 4 : 8;
-    // rings: own outputs, outputs of lane y-1 and y-2 (forward) / y+1, y+2 (backward)
-    VT r0[RU], r1[RU], r2[RU];
+    if (wid == 0 && (BOX || rowok)) {
+        // rings: own outputs, outputs of lane y-1 and y-2
+        VT r0[RU], r1[RU], r2[RU];
 #pragma unroll
-    for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
-    // forward: y_i = r_i - sum_{lower} L_ik y_k
-    for (int t0 = 0; t0 < T; t0 += RU) {
+        for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
+        // forward: y_i = r_i - sum_{lower} L_ik y_k
+        for (int t0 = 0; t0 < T; t0 += RU) {
 #pragma unroll
-        for (int b0 = 0; b0 < RU; b0 += RB) {
-            VT co[RB][NLP], rin[RB], outv[RB];
-            int cc[RB];
-            bool aa[RB];
+            for (int b0 = 0; b0 < RU; b0 += RB) {
+                VT co[RB][NLP], rin[RB], outv[RB];
+                int cc[RB];
+                bool aa[RB];
 #pragma unroll
-            for (int u = 0; u < RB; ++u) {
-                const int x = t0 + b0 + u - LB * y;
-                aa[u] = y < ey && x >= 0 && x < ex;
-                cc[u] = aa[u] ? y * ex + x : 0;
-                load_run<FT, VT, NLP>(cf + (size_t)cc[u] * NSP, co[u]);
-                rin[u] = rv[cc[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < RB; ++u) {
-                const int uu = b0 + u;
-                VT v = rin[u];
-                // older terms first, the one-step-old terms (critical path) last
-#pragma unroll
-                for (int pass = 0; pass < 2; ++pass) {
-#pragma unroll
-                    for (int q = 0; q < NL; ++q) {
-                        const int h = -(S::DX[q] + LB * S::DY[q]) - 1;
-                        if ((h == 0) != (pass == 1)) continue;
-                        const int slot = (uu - 1 - h + 2 * RU) % RU;
-                        const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == -1 ? r1[slot] : r2[slot]);
-                        v -= co[u][q] * val;
-                    }
+                for (int u = 0; u < RB; ++u) {
+                    const int t = t0 + b0 + u;
+                    aa[u] = (unsigned)(t - tlo) < (unsigned)ex;
+                    cc[u] = cb + t;   // in [0, n) for every step when ex >= LB
+                    load_run<FT, VT, NLP>(cf + (size_t)cc[u] * NSP, co[u]);
+                    rin[u] = rv[cc[u]];
                 }
-                const VT out = aa[u] ? v : (VT)0;
-                outv[u] = out;
-                r0[uu] = out;
-                r1[uu] = lane_shr(out);
-                r2[uu] = lane_shr(r1[uu]);
+#pragma unroll
+                for (int u = 0; u < RB; ++u) {
+                    const int uu = b0 + u;
+                    VT v = rin[u];
+                    // older terms first, the one-step-old terms (critical path) last
+#pragma unroll
+                    for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+                        for (int q = 0; q < NL; ++q) {
+                            const int h = -(S::DX[q] + LB * S::DY[q]) - 1;
+                            if ((h == 0) != (pass == 1)) continue;
+                            const int slot = (uu - 1 - h + 2 * RU) % RU;
+                            const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == -1 ? r1[slot] : r2[slot]);
+                            v -= co[u][q] * val;
+                        }
+                    }
+                    const VT out = aa[u] ? v : (VT)0;
+                    outv[u] = out;
+                    r0[uu] = out;
+                    r1[uu] = lane_shr(out);
+                    r2[uu] = lane_shr(r1[uu]);
+                }
+#pragma unroll
+                for (int u = 0; u < RB; ++u) rv[aa[u] ? cc[u] : n] = outv[u];
+            }
+        }
+    } else if (wid > 0) {
+        // the other wavefronts stage the upper runs and 1/u_ii meanwhile
+        for (int c0 = threadIdx.x - 64; c0 < n; c0 += CPT * 192) {
+            FT v[CPT][NUP];
+            DT d[CPT];
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = min(c0 + u * 192, n - 1);
+#pragma unroll
+                for (int q = 0; q < NUP; ++q) {
+                    const int k = a.kmap[NLP + q];
+                    const FT x = F[(size_t)max(k, 0) * a.NE + fo + c];
+                    v[u][q] = k >= 0 ? x : (FT)0;
+                }
+                d[u] = ID[fo + c];
             }
 #pragma unroll
-            for (int u = 0; u < RB; ++u)
-                if (aa[u]) rv[cc[u]] = outv[u];
+            for (int u = 0; u < CPT; ++u) {
+                const int c = c0 + u * 192;
+                if (c < n) {
+#pragma unroll
+                    for (int q = 0; q < NUP; ++q) cf[(size_t)c * NSP + NLP + q] = v[u][q];
+                    id[c] = d[u];
+                }
+            }
         }
     }
-    // backward: z_i = (y_i - sum_{upper} U_ik z_k) / u_ii
+    __syncthreads();
+    if (wid == 0 && (BOX || rowok)) {
+        // backward: z_i = (y_i - sum_{upper} U_ik z_k) / u_ii, step t at cell cb + (T - 1 - t)
+        VT r0[RU], r1[RU], r2[RU];
 #pragma unroll
-    for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
-    for (int t0 = 0; t0 < T; t0 += RU) {
+        for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
+        const int cbb = cb + T - 1;
+        const int tlob = rowok ? T - LB * y - ex : (1 << 28);   // x = T - 1 - t - LB*y in [0, ex)
+        for (int t0 = 0; t0 < T; t0 += RU) {
 #pragma unroll
-        for (int b0 = 0; b0 < RU; b0 += RB) {
-            VT co[RB][NUP], rin[RB], dg[RB], outv[RB];
-            int cc[RB];
-            bool aa[RB];
+            for (int b0 = 0; b0 < RU; b0 += RB) {
+                VT co[RB][NUP], rin[RB], dg[RB], outv[RB];
+                int cc[RB];
+                bool aa[RB];
 #pragma unroll
-            for (int u = 0; u < RB; ++u) {
-                const int x = (T - 1 - t0 - b0 - u) - LB * y;
-                aa[u] = y < ey && x >= 0 && x < ex;
-                cc[u] = aa[u] ? y * ex + x : 0;
-                load_run<FT, VT, NUP>(cf + (size_t)cc[u] * NSP + NLP, co[u]);
-                rin[u] = rv[cc[u]];
-                dg[u] = (VT)id[cc[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < RB; ++u) {
-                const int uu = b0 + u;
-                VT v = rin[u];
-#pragma unroll
-                for (int pass = 0; pass < 2; ++pass) {
-#pragma unroll
-                    for (int q = NL; q < NS; ++q) {
-                        const int h = S::DX[q] + LB * S::DY[q] - 1;
-                        if ((h == 0) != (pass == 1)) continue;
-                        const int slot = (uu - 1 - h + 2 * RU) % RU;
-                        const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == 1 ? r1[slot] : r2[slot]);
-                        v -= co[u][q - NL] * val;
-                    }
+                for (int u = 0; u < RB; ++u) {
+                    const int t = t0 + b0 + u;
+                    aa[u] = (unsigned)(t - tlob) < (unsigned)ex;
+                    cc[u] = cbb - t;
+                    load_run<FT, VT, NUP>(cf + (size_t)cc[u] * NSP + NLP, co[u]);
+                    rin[u] = rv[cc[u]];
+                    dg[u] = (VT)id[cc[u]];
                 }
-                const VT out = aa[u] ? v * dg[u] : (VT)0;
-                outv[u] = out;
-                r0[uu] = out;
-                r1[uu] = lane_shl(out);
-                r2[uu] = lane_shl(r1[uu]);
-            }
 #pragma unroll
-            for (int u = 0; u < RB; ++u)
-                if (aa[u]) rv[cc[u]] = outv[u];
+                for (int u = 0; u < RB; ++u) {
+                    const int uu = b0 + u;
+                    VT v = rin[u];
+#pragma unroll
+                    for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+                        for (int q = NL; q < NS; ++q) {
+                            const int h = S::DX[q] + LB * S::DY[q] - 1;
+                            if ((h == 0) != (pass == 1)) continue;
+                            const int slot = (uu - 1 - h + 2 * RU) % RU;
+                            const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == 1 ? r1[slot] : r2[slot]);
+                            v -= co[u][q - NL] * val;
+                        }
+                    }
+                    const VT out = aa[u] ? v * dg[u] : (VT)0;
+                    outv[u] = out;
+                    r0[uu] = out;
+                    r1[uu] = lane_shl(out);
+                    r2[uu] = lane_shl(r1[uu]);
+                }
+#pragma unroll
+                for (int u = 0; u < RB; ++u) rv[aa[u] ? cc[u] : n] = outv[u];
+            }
         }
     }
-    }   // sweeping wavefront
     __syncthreads();
     // write back with all threads, x-contiguous (coalesced)
     if (a.variant == NKS_LEFT_RAS) {
         const int oxn = sd.lx1 - sd.lx0, oyn = sd.ly1 - sd.ly0;
+        const float inv_oxn = 1.0f / (float)oxn;
         for (int k = threadIdx.x; k < oxn * oyn; k += blockDim.x) {
-            const int x = sd.lx0 + k % oxn, y = sd.ly0 + k / oxn;
-            const size_t g = bk.off + (sd.ox + x) + bk.nx * (sd.oy + y + bk.ny * sd.oz);
-            const double v = (double)rv[y * ex + x];
+            const int yy = row_of(k, inv_oxn), xx = k - yy * oxn;
+            const int x = sd.lx0 + xx, yb = sd.ly0 + yy;
+            const size_t g = (size_t)sd.gorg + x + (size_t)sd.gnx * yb;
+            const double v = (double)rv[yb * ex + x];
             a.z[g] = a.accumulate ? a.z[g] + v : v;
         }
     } else {
@@ -1548,8 +1603,9 @@ template <typename FT, typename VT, typename DT>
 static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int *mask, bool accumulate) {
     RowsArgs a;
     a.sub = V.sub.p;
-    a.blk = V.spp->blk.p;
-    a.slotmap = V.slotmap.p;
+    if (V.box == 0) row_kmap<0, FT>(V.hslot, a.kmap);
+    else if (V.box == 1) row_kmap<1, FT>(V.hslot, a.kmap);
+    else row_kmap<2, FT>(V.hslot, a.kmap);
     if (M.d.precision == NKS_FP64) a.F = V.f64.p;
     else if (M.d.precision == NKS_FP32) a.F = V.f32.p;
     else a.F = V.f16.p;
@@ -1563,7 +1619,8 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     a.accumulate = accumulate ? 1 : 0;
     const int NSP = V.box == 0 ? row_run<0, FT>() : (V.box == 1 ? row_run<1, FT>() : row_run<2, FT>());
     const size_t n = V.max_next;
-    const size_t sh = al16(sizeof(VT) * n) + al16(sizeof(FT) * NSP * n) + al16(sizeof(DT) * n);
+    const size_t sh = al16(sizeof(VT) * (n + 1)) + al16(sizeof(FT) * NSP * n) + al16(sizeof(DT) * n);
+    if (V.max_next >= (1 << 16)) fail(NKS_EINVAL, "2D subdomain of %zu cells exceeds 65535", n);
     if (sh > (size_t)M.lds_bytes) fail(NKS_EINVAL, "2D subdomain of %zu cells does not fit in LDS", n);
     void (*fn)(RowsArgs) = V.box == 0 ? k_ras_rows<FT, VT, DT, 0>
                                       : (V.box == 1 ? k_ras_rows<FT, VT, DT, 1> : k_ras_rows<FT, VT, DT, 2>);
