@@ -18,6 +18,7 @@ struct GmOpts {
     bool flexible = false;
     int check_every = 1;
     int graph_chunk = 0;   // > 0: replay captured chunks of this many iterations (A and M must be capturable)
+    bool single_pass = false;   // classical Gram-Schmidt without reorthogonalisation (loose solves)
 };
 
 struct GmDev {

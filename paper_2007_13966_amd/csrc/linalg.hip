@@ -495,14 +495,18 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_tol(const Chunk *chunks, con
 //                rounding-size correction and the subtraction loses nothing),
 //                v_{j+1} = (w - V h2) / h_{j+1,j}; the lead chunk adds h2 to
 //                H[:, j] and applies the Givens rotations.
+// The single-pass form (classical Gram-Schmidt without reorthogonalisation,
+// for short solves to a loose tolerance) takes two: spmv_dots also sums w.w,
+// and finish takes h = pass-1 totals and h_{j+1,j} = sqrt(w.w - h.h).
 // Activity flags are double-buffered: iteration j reads act_j and only the
 // lead chunk of a reservoir writes act_{j+1}, so no workgroup reads a flag
 // that another rewrites in the same kernel.
 
-// pass-1 partials of w = A z with V[0..j] (stencil operator, chunk grid)
+// pass-1 partials of w = A z with V[0..j] (stencil operator, chunk grid);
+// ww: w.w in column j+1 as well
 template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_gm_spmv_dots(const Chunk *chunks, SpmvArgs a, const double *V, long ld, int j,
-                                                              double *part, const int *act) {
+                                                              double *part, const int *act, int ww) {
     __shared__ int sh[MAXK];
     stage_offsets(a.off, a.K, sh);
     const Chunk ch = chunks[blockIdx.x];
@@ -524,15 +528,19 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_spmv_dots(const Chunk *chunk
 #pragma unroll
             for (int c = 0; c < NC; ++c)
                 if (c < nc) acc[c] += wi * vv[c];
+#pragma unroll
+            for (int c = 1; c < NC; ++c)
+                if (c == nc && ww) acc[c] += wi * wi;
         }
     }
-    chunk_columns<NC>(acc, nc, part, gridDim.x);
+    chunk_columns<NC>(acc, nc + (ww ? 1 : 0), part, gridDim.x);
 }
 
-// pass-1 partials V[0..j]^T w (w from a generic operator)
+// pass-1 partials V[0..j]^T w (w from a generic operator); ww: w.w in
+// column j+1 as well
 template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_gm_dots(const Chunk *chunks, const double *w, const double *V, long ld, int j,
-                                                         double *part, const int *act) {
+                                                         double *part, const int *act, int ww) {
     const Chunk ch = chunks[blockIdx.x];
     const int nc = j + 1;
     double acc[NC];
@@ -548,9 +556,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_dots(const Chunk *chunks, co
 #pragma unroll
             for (int c = 0; c < NC; ++c)
                 if (c < nc) acc[c] += wi * vv[c];
+#pragma unroll
+            for (int c = 1; c < NC; ++c)
+                if (c == nc && ww) acc[c] += wi * wi;
         }
     }
-    chunk_columns<NC>(acc, nc, part, gridDim.x);
+    chunk_columns<NC>(acc, nc + (ww ? 1 : 0), part, gridDim.x);
 }
 
 // h1 = pass-1 totals (lead chunk stores H[:, j]); w -= V h1; pass-2 partials
@@ -597,7 +608,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_update_dots(const Chunk *chu
 template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, const int *cfirst, const double *w,
                                                            const double *V, long ld, int j, const double *pin, double *vn, GmDev st,
-                                                           const int *act, int *act_next, int slot) {
+                                                           const int *act, int *act_next, int slot, int single) {
     __shared__ double hc[NC];
     const Chunk ch = chunks[blockIdx.x];
     const int b = ch.blk, nc = j + 1;
@@ -620,7 +631,8 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
     if (lead) {
         const int t = threadIdx.x, jm = max(j - 1, 0);
         if (t < NC) {
-            gv[t] = H[(size_t)min(t, j) * m + j];
+            // single pass: column j holds nothing yet (h comes from pin)
+            gv[t] = single ? 0.0 : H[(size_t)min(t, j) * m + j];
             gv[NC + t] = cs[min(t, jm)];
             gv[2 * NC + t] = sn[min(t, jm)];
         } else if (t == NC) {
@@ -889,19 +901,23 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
         // pass 2 carries j + 2 columns (V[0..j]^T w and w.w)
         with_columns(j + 2, [&](auto bound) {
             constexpr int NC = decltype(bound)::value;
+            const int one = o.single_pass ? 1 : 0;
             if (Aop) {
                 SpmvArgs sa = spmv_args(*Aop, zj, w.p, nullptr, nullptr);
-                k_gm_spmv_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, vb, ld, j, P0, act);
+                k_gm_spmv_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, vb, ld, j, P0, act, one);
                 KCHECK();
             } else {
                 A(zj, w.p, nullptr, act);
-                k_gm_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, w.p, vb, ld, j, P0, act);
+                k_gm_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, w.p, vb, ld, j, P0, act, one);
                 KCHECK();
             }
-            k_gm_update_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vb, ld, j, P0, P1, st, act);
-            KCHECK();
-            k_gm_finish<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vb, ld, j, P1, V[j + 1].p, st,
-                                                        act, act_next, slot);
+            if (!one) {
+                k_gm_update_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vb, ld, j, P0, P1, st,
+                                                                 act);
+                KCHECK();
+            }
+            k_gm_finish<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vb, ld, j, one ? P0 : P1,
+                                                        V[j + 1].p, st, act, act_next, slot, one);
             KCHECK();
         });
     };

@@ -1737,6 +1737,8 @@ void Ras::coarse_solve(const double *b, double *x, const int *mask) {
     o.flexible = false;
     o.check_every = 1;
     o.graph_chunk = graph_chunk;
+    // one Gram-Schmidt pass: a handful of iterations to a loose tolerance
+    o.single_pass = true;
     coarse.solve(A, P, b, x, true, o, mask, s, C.A);
     ++coarse_calls;
 }
