@@ -185,7 +185,7 @@ def cpu_baseline(case, nsteps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=9)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="2d512", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -8,6 +8,7 @@
 #include <type_traits>
 
 #include "krylov.h"
+#include "reduce.h"
 
 namespace nks {
 
@@ -232,147 +233,12 @@ __global__ void k_scale_blk(const Blk *blk, int B, int N, const double *x, const
 
 // ---------------------------------------------------------------- reductions
 // Reductions run in two fixed-order stages with no grid-wide fence: a
-// workgroup per chunk writes up to MAXCOL column partials (butterfly
-// wavefront sums, then the waves in order); the next kernel's workgroups
-// each reduce the partials of their own reservoir in their prologue (chunk q
-// to thread q, butterfly, waves in order), so every workgroup of a reservoir
-// obtains bitwise the same totals, independent of the other reservoirs.  The
-// first chunk of each reservoir commits shared state.
-constexpr int MAXCOL = 32;
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Row sums (16 lanes) by DPP moves: pair swap, quad swap, half-row mirror,
-// row mirror.  Every lane of a row ends with the same value, bitwise: each
-// step adds the same two operands in either order.
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double row_sum(double v) {
-    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
-    v += dpp_mov<0x141>(v);   // row_half_mirror
-    v += dpp_mov<0x140>(v);   // row_mirror
-    return v;
-}
-
-// Sums over TP consecutive lanes (TP = 8, 16, 32, 64): DPP quad swaps and
-// row mirrors inside a row of 16 lanes, then lane shuffles across rows and
-// across the two halves of the wavefront.  Each step adds two operands that
-// the partner lane adds in the other order, so every lane of a group ends
-// with the same value, bitwise.
-template <int TP>
-__device__ __forceinline__ double group_sum(double v) {
-    static_assert(TP == 8 || TP == 16 || TP == 32 || TP == 64, "lane group of 8, 16, 32 or 64");
-    v += dpp_mov<0xB1>(v);
-    v += dpp_mov<0x4E>(v);
-    v += dpp_mov<0x141>(v);
-    if constexpr (TP >= 16) v += dpp_mov<0x140>(v);
-    if constexpr (TP >= 32) v += __shfl_xor(v, 16, 64);
-    if constexpr (TP >= 64) v += __shfl_xor(v, 32, 64);
-    return v;
-}
-
-// Sums over the workgroup (RED_THREADS threads) of v[c], c < NC; thread
-// (c, s) with s == 0 passes column c < nc to dst(c, total).
-// NC <= 2: row sums by DPP, the 16 row sums (4 waves x 4 rows) through LDS,
-// added in row order.  NC >= 4: the values go through LDS column-major, TP =
-// RED_THREADS / NC consecutive threads add one column's entries in a fixed
-// order and finish with a lane-group sum, so the work per thread grows with
-// NC, not with NC times the reduction depth.
-template <int NC, typename Store>
-__device__ __forceinline__ void workgroup_columns(const double (&v)[NC], int nc, Store dst) {
-    if constexpr (NC <= 2) {
-        __shared__ double sh[16][NC];
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        double r[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) r[c] = row_sum(v[c]);
-        if ((lane & 15) == 0) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) sh[w * 4 + (lane >> 4)][c] = r[c];
-        }
-        __syncthreads();
-        if ((int)threadIdx.x < nc) {
-            double t = 0.0;
-            const int nr = (blockDim.x >> 6) * 4;
-            for (int k = 0; k < nr; ++k) t += sh[k][threadIdx.x];
-            dst(threadIdx.x, t);
-        }
-    } else {
-        constexpr int TP = RED_THREADS / NC;
-        constexpr int LD = RED_THREADS + 2;   // column stride, off the LDS bank period
-        __shared__ double sh[NC * LD];
-        const int t = threadIdx.x;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) sh[c * LD + t] = v[c];
-        __syncthreads();
-        const int c = t / TP, q = t - c * TP;
-        double a = 0.0;
-#pragma unroll
-        for (int k = 0; k < NC; ++k) a += sh[c * LD + q + TP * k];
-        a = group_sum<TP>(a);
-        if (q == 0 && c < nc) dst(c, a);
-    }
-}
-
-// column sums of this workgroup's registers into part[c * ns + blockIdx.x]
-// (column-major over the ns chunks, so the totals read coalesced)
-template <int NC, int M>
-__device__ __forceinline__ void chunk_columns(const double (&acc)[M], int nc, double *part, int ns) {
-    static_assert(NC <= M, "column bound exceeds the register array");
-    double v[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) v[c] = acc[c];
-    workgroup_columns<NC>(v, nc, [&](int c, double t) { part[(size_t)c * ns + blockIdx.x] = t; });
-}
-
-// totals of the nc partial columns of reservoir b (chunks [q0, q1), at most
-// RED_THREADS chunks, column stride ns) into out[0..NC) in LDS (zero past
-// nc), visible to the whole workgroup.  Branch-free: every load has a valid
-// address (clamped column and chunk) and out-of-range values are zeroed.
-// NC >= 4: TP = RED_THREADS / NC consecutive threads share a column, each
-// adding every TP-th chunk, then a lane-group sum.
-template <int NC>
-__device__ __forceinline__ void block_totals(const double *part, int q0, int q1, int nc, double *out, int ns) {
-    static_assert(MAXCH <= RED_THREADS, "one reduction thread per chunk");
-    if constexpr (NC <= 2) {
-        const int q = q0 + (int)threadIdx.x;
-        const bool qin = q < q1;
-        const int qq = qin ? q : q0;
-        double v[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double x = part[(size_t)min(c, max(nc - 1, 0)) * ns + qq];
-            v[c] = (c < nc && qin) ? x : 0.0;
-        }
-        workgroup_columns<NC>(v, nc, [&](int c, double t) { out[c] = t; });
-        if ((int)threadIdx.x >= nc && (int)threadIdx.x < NC) out[threadIdx.x] = 0.0;
-    } else {
-        constexpr int TP = RED_THREADS / NC;
-        const int c = (int)threadIdx.x / TP, s = (int)threadIdx.x - c * TP;
-        const double *col = part + (size_t)min(c, max(nc - 1, 0)) * ns;
-        double a = 0.0;
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const int q = q0 + s + TP * k;
-            const double x = col[min(q, q1 - 1)];
-            a += q < q1 ? x : 0.0;
-        }
-        a = group_sum<TP>(a);
-        if (s == 0) out[c] = c < nc ? a : 0.0;
-    }
-    __syncthreads();
-}
-
+// workgroup per chunk writes up to MAXCOL column partials (column sums over
+// the workgroup); the next kernel's workgroups each reduce the partials of
+// their own reservoir in their prologue, in a fixed order, so every
+// workgroup of a reservoir obtains bitwise the same totals, independent of
+// the other reservoirs.  The first chunk of each reservoir commits shared
+// state.  The workgroup sums live in reduce.h.
 // partial dots of x with ncols vectors ys[c] (or ||x||^2 when square)
 __global__ void __launch_bounds__(RED_THREADS) k_partials(const Chunk *chunks, const double *x,
                                                           const double *const *ys, int ncols, double *part,
@@ -451,6 +317,8 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_begin(const Chunk *chunks, c
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) v0[i] = r[i] / beta;
     if (lead && threadIdx.x == 0) {
         st.its[b] = its;
+        st.its0[b] = its;
+        st.gj2[b] = beta;   // g_0 of the cycle (step parity 0)
         st.conv[b] = conv;
         st.tol[b] = tol;
         st.beta[b] = beta;
@@ -508,13 +376,15 @@ template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_gm_spmv_dots(const Chunk *chunks, SpmvArgs a, const double *V, long ld, int j,
                                                               double *part, const int *act, int ww) {
     __shared__ int sh[MAXK];
-    stage_offsets(a.off, a.K, sh);
     const Chunk ch = chunks[blockIdx.x];
+    // an inactive reservoir's partials are never read
+    if (!act[ch.blk]) return;
+    stage_offsets(a.off, a.K, sh);
     const int nc = j + 1;
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    if (act[ch.blk]) {
+    {
         const Blk k = a.blk[ch.blk];
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
             double vv[NC];
@@ -542,11 +412,12 @@ template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_gm_dots(const Chunk *chunks, const double *w, const double *V, long ld, int j,
                                                          double *part, const int *act, int ww) {
     const Chunk ch = chunks[blockIdx.x];
+    if (!act[ch.blk]) return;   // an inactive reservoir's partials are never read
     const int nc = j + 1;
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    if (act[ch.blk]) {
+    {
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
             double vv[NC];
 #pragma unroll
@@ -574,8 +445,9 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_update_dots(const Chunk *chu
     const Chunk ch = chunks[blockIdx.x];
     const int b = ch.blk, nc = j + 1;
     const bool on = act[b];
-    if (on) block_totals<NC>(pin, cfirst[b], cfirst[b + 1], nc, hc, gridDim.x);
-    if (on && (int)blockIdx.x == cfirst[b] && (int)threadIdx.x < nc)
+    if (!on) return;   // an inactive reservoir's partials are never read
+    block_totals<NC>(pin, cfirst[b], cfirst[b + 1], nc, hc, gridDim.x);
+    if ((int)blockIdx.x == cfirst[b] && (int)threadIdx.x < nc)
         st.H[((size_t)b * (st.m + 1) + threadIdx.x) * st.m + j] = hc[threadIdx.x];
     double acc[NC];
 #pragma unroll
@@ -795,8 +667,8 @@ void Gmres::ensure(Alloc *al_, const Space &sp_, int m_, bool flexible, hipStrea
         g.alloc(al, (size_t)B * (m + 1));
         y.alloc(al, (size_t)B * m);
         hj.alloc(al, (size_t)B * (m + 1));
-        scal.alloc(al, (size_t)B * 3);
-        ints.alloc(al, (size_t)B * 6);
+        scal.alloc(al, (size_t)B * 5);
+        ints.alloc(al, (size_t)B * 7);
         std::vector<const double *> hv(m + 1), hz(std::max(m, 1));
         for (int k = 0; k <= m; ++k) hv[k] = V[k].p;
         for (int k = 0; k < (int)Z.size(); ++k) hz[k] = Z[k].p;
@@ -838,6 +710,8 @@ GmDev Gmres::dev(double rtol, double atol, int maxit) {
     d.upd = ints.p + 4 * B;
     d.active2 = ints.p + 5 * B;
     d.flag = dflag;
+    d.gj2 = scal.p + 3 * B;
+    d.its0 = ints.p + 6 * B;
     d.nb = nb;
     d.m = m;
     d.maxit = maxit;
@@ -891,11 +765,27 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
     const double *const *Vp = vptr.p;
     const double *vb = V[0].p;   // the basis: m + 1 columns of stride ld
     const bool flex = o.flexible;
+    const bool fuse = o.fused && o.single_pass && Aop && !flex;
     // one GMRES iteration j; its activity flags go to `slot`
     auto iteration = [&](int j, int slot) {
         double *zj = flex ? Z[j].p : t.p;
         const int *act = (j & 1) ? st.active2 : st.active;
         int *act_next = (j & 1) ? st.active : st.active2;
+        if (fuse) {
+            // z_j is in place: the plain preconditioner for j = 0, the fused
+            // launch of step j-1 otherwise
+            if (j == 0) M(V[0].p, zj, act);
+            ProfScope ps("gmres_arnoldi", s);
+            with_columns(j + 2, [&](auto bound) {
+                constexpr int NC = decltype(bound)::value;
+                SpmvArgs sa = spmv_args(*Aop, zj, w.p, nullptr, nullptr);
+                k_gm_spmv_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, V[0].p, ld, j, P0, act, 1);
+                KCHECK();
+            });
+            GmFuse f{S.cfirst.p, P0, nch, w.p, Vall.p, ld, st, j, act, act_next, slot, zj};
+            o.fused(f);
+            return;
+        }
         M(V[j].p, zj, act);
         ProfScope ps("gmres_arnoldi", s);
         // pass 2 carries j + 2 columns (V[0..j]^T w and w.w)

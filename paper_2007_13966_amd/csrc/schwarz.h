@@ -114,6 +114,8 @@ struct Ras {
     void factor();                                     // numeric (every call)
     void apply(const double *r, double *z, const int *mask);
     void apply_level(int l, const double *r, double *z, const int *mask, bool accumulate);
+    // the coarse GMRES's fused step: finish of Arnoldi step f.j and z_{j+1} (2D row levels, left-RAS)
+    void apply_fused(int l, const GmFuse &f);
     void vcycle(int l, const double *b, double *x, const int *mask);
     void coarse_solve(const double *b, double *x, const int *mask);
     void restrict_to(int l, const double *rf, double *rc, const int *mask);
