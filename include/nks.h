@@ -323,7 +323,8 @@ int nks_ras_autotune(nks_grid *g, const double *p, const double *p_n, const doub
  * records carry the events on the dispatch itself (the kernel's own
  * execution time): "ras_apply_l<level>" (one-level Schwarz sweeps),
  * "ilu_factor_l<level>", "rap_l<level>", "spmv_l<0|1>" (7-or-fewer-point /
- * wider stencils).  Span records bracket several kernels: "gmres_arnoldi"
+ * wider stencils), "coarse_fused_l<level>" (a coarse GMRES step: the
+ * Arnoldi finish fused with the next sweep).  Span records bracket several kernels: "gmres_arnoldi"
  * (the Arnoldi step after the preconditioner), "residual_jacobian".  Launches inside captured graphs are not recorded.
  * enable != 0 clears the records and starts recording, 0 stops.  query
  * synchronises and returns the number of launches and their summed duration
@@ -332,6 +333,10 @@ int nks_ras_autotune(nks_grid *g, const double *p, const double *p_n, const doub
  * count to *count, so a caller can separate dispatches that found every
  * reservoir masked out (speculative Krylov iterations past convergence). */
 int nks_profile_enable(int enable);
+/* Restrict recording to the named records (comma-separated, e.g.
+ * "ras_apply_l0,ras_apply_l1"); NULL or "" records every name.  Launches
+ * outside the set take no events and no host bookkeeping. */
+int nks_profile_filter(const char *names);
 int nks_profile_query(const char *name, int *count, double *total_ms);
 int nks_profile_durations(const char *name, double *ms, int cap, int *count);
 

@@ -124,6 +124,7 @@ PROTOTYPES = {
                          C.POINTER(nks_gmres_desc), _I, C.POINTER(nks_ras_desc),
                          C.POINTER(nks_autotune_entry)],
     "nks_profile_enable": [_I],
+    "nks_profile_filter": [C.c_char_p],
     "nks_profile_query": [C.c_char_p, _IP, _DP],
     "nks_profile_durations": [C.c_char_p, _DP, _I, _IP],
     "nks_last_error": [],

@@ -3,6 +3,7 @@
 #include <chrono>
 #include <cmath>
 #include <map>
+#include <set>
 #include <mutex>
 #include <cstdarg>
 #include <cstdio>
@@ -67,7 +68,10 @@ struct ProfRec {
 static std::mutex g_prof_mu;
 static std::map<std::string, ProfRec> g_prof;
 static bool g_prof_on = false;
+static std::set<std::string> g_prof_keep;   // record names kept (empty: all)
 static std::vector<hipEvent_t> g_event_pool;
+
+static bool prof_wanted(const std::string &key) { return g_prof_keep.empty() || g_prof_keep.count(key) != 0; }
 
 bool prof_on() { return g_prof_on; }
 
@@ -94,6 +98,7 @@ static hipEvent_t take_event() {
 
 ProfScope::ProfScope(const char *nm, hipStream_t st, int lvl) : s(st), name(nm), level(lvl) {
     if (!g_prof_on) return;
+    if (!prof_wanted(level >= 0 ? fmt("%s_l%d", name, level) : std::string(name))) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -112,12 +117,13 @@ ProfScope::~ProfScope() {
 
 bool prof_pair(const char *nm, int lvl, hipStream_t s, hipEvent_t *a, hipEvent_t *b) {
     if (!g_prof_on) return false;
+    std::string key = lvl >= 0 ? fmt("%s_l%d", nm, lvl) : std::string(nm);
+    if (!prof_wanted(key)) return false;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return false;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     *a = take_event();
     *b = take_event();
-    std::string key = lvl >= 0 ? fmt("%s_l%d", nm, lvl) : std::string(nm);
     g_prof[key].ev.push_back({*a, *b});
     return true;
 }
@@ -329,6 +335,24 @@ int nks_profile_enable(int enable) {
             prof_clear();
         }
         g_prof_on = enable != 0;
+    });
+}
+
+int nks_profile_filter(const char *names) {
+    return guard([&] {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_keep.clear();
+        if (!names) return;
+        std::string cur;
+        for (const char *c = names;; ++c) {
+            if (*c == ',' || *c == '\0') {
+                if (!cur.empty()) g_prof_keep.insert(cur);
+                cur.clear();
+                if (*c == '\0') break;
+            } else {
+                cur.push_back(*c);
+            }
+        }
     });
 }
 
