@@ -56,56 +56,54 @@ struct SpmvArgs {
     const double *x, *b;
     double *y;
     const int *mask;
+    int offp[MAXK];   // the offsets, (dx, dy, dz) packed in the low three bytes of an int
 };
 
-// Stencil offsets staged once per workgroup into LDS, (dx, dy, dz) packed in
-// the low three bytes of an int.  All threads must call it.
-__device__ __forceinline__ void stage_offsets(const int8_t *off, int K, int *sh) {
-    for (int q = threadIdx.x; q < K; q += blockDim.x)
-        sh[q] = (off[3 * q] & 0xff) | ((off[3 * q + 1] & 0xff) << 8) | ((off[3 * q + 2] & 0xff) << 16);
-    __syncthreads();
-}
+// Stencil point batch: a 5- or 7-point stencil in one batch of 8, a 21-point
+// one in one batch of 24, wider ones in several.
+static inline int stencil_batch(int K) { return K <= 8 ? 8 : 24; }
 
-// sum_q coef[q][i] x[i + off_q] over the in-reservoir neighbours of cell i at
-// (cx, cy, cz), q in increasing order.  Loads are issued eight points at a
-// time from always-valid addresses (an outside neighbour reads x[i] and
-// contributes an exact zero), so the sum is the same as skipping them.
-__device__ __forceinline__ double stencil_dot(const int *sh, int K, const double *coef, size_t N,
-                                              const double *x, int i, int cx, int cy, int cz, const Blk &k) {
+// sum_q coef[q][i] x[i + off_q] over the neighbours of cell i, q in
+// increasing order.  Every operator the library builds (Jacobian, Galerkin
+// products, transposes) stores an exact zero for a neighbour outside the
+// reservoir, so the neighbour index is only clamped into the reservoir's
+// cells and the product is 0 x (a finite value), as if the point were
+// skipped.  Loads are issued B points at a time; the linear offsets of the
+// points are uniform (scalar) and the coefficient rows are addressed from
+// scalar bases.
+template <int B>
+__device__ __forceinline__ double stencil_dot(const int *offp, int K, const double *coef, size_t N,
+                                              const double *x, int i, const Blk &k) {
     double s = 0.0;
-    const int nxy = k.nx * k.ny;
-    for (int q0 = 0; q0 < K; q0 += 8) {
-        double cv[8], xv[8];
+    const int nx = k.nx, nxy = k.nx * k.ny;
+    const int lo = k.off, hi = k.off + nxy * k.nz - 1;
+    for (int q0 = 0; q0 < K; q0 += B) {
+        double cv[B], xv[B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < B; ++u) {
             const int q = min(q0 + u, K - 1);
-            const int o = sh[q];
+            const int o = offp[q];
             const int dx = (int)(int8_t)(o & 0xff), dy = (int)(int8_t)((o >> 8) & 0xff),
                       dz = (int)(int8_t)((o >> 16) & 0xff);
-            const bool in = q0 + u < K && (unsigned)(cx + dx) < (unsigned)k.nx &&
-                            (unsigned)(cy + dy) < (unsigned)k.ny && (unsigned)(cz + dz) < (unsigned)k.nz;
-            const int j = in ? i + dx + k.nx * dy + nxy * dz : i;
+            const int j = min(max(i + dx + nx * dy + nxy * dz, lo), hi);
             const double c = coef[(size_t)q * N + i];
             xv[u] = x[j];
-            cv[u] = in ? c : 0.0;
+            cv[u] = q0 + u < K ? c : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s += cv[u] * xv[u];
+        for (int u = 0; u < B; ++u) s += cv[u] * xv[u];
     }
     return s;
 }
 
+template <int BS>
 __global__ void __launch_bounds__(256) k_spmv(SpmvArgs a) {
-    __shared__ int sh[MAXK];
-    stage_offsets(a.off, a.K, sh);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
     const int bi = find_blk(a.blk, a.B, i);
     if (a.mask && !a.mask[bi]) return;
     const Blk k = a.blk[bi];
-    const int l = i - k.off;
-    const int x = l % k.nx, y = (l / k.nx) % k.ny, z = l / (k.nx * k.ny);
-    const double s = stencil_dot(sh, a.K, a.coef, a.N, a.x, i, x, y, z, k);
+    const double s = stencil_dot<BS>(a.offp, a.K, a.coef, a.N, a.x, i, k);
     a.y[i] = a.b ? a.b[i] - s : s;
 }
 
@@ -172,6 +170,12 @@ static SpmvArgs spmv_args(const Op &A, const double *x, double *y, const double 
     a.N = A.sp->N;
     a.K = A.st.K;
     a.off = A.st.doff.p;
+    if (A.st.K > MAXK) fail(NKS_EINVAL, "stencil of %d points exceeds %d", A.st.K, MAXK);
+    for (int q = 0; q < MAXK; ++q) {
+        const int qq = std::min(q, A.st.K - 1);
+        a.offp[q] = (A.st.off[3 * qq] & 0xff) | ((A.st.off[3 * qq + 1] & 0xff) << 8) |
+                    ((A.st.off[3 * qq + 2] & 0xff) << 16);
+    }
     a.coef = A.coef.p;
     a.x = x;
     a.b = b;
@@ -183,7 +187,10 @@ static SpmvArgs spmv_args(const Op &A, const double *x, double *y, const double 
 void launch_spmv(const Op &A, const double *x, double *y, const double *b, const int *mask,
                  hipStream_t s) {
     SpmvArgs a = spmv_args(A, x, y, b, mask);
-    launch_timed("spmv", A.st.K <= 7 ? 0 : 1, k_spmv, dim3(nblk(a.N, 256)), dim3(256), 0, s, a);
+    if (stencil_batch(a.K) == 8)
+        launch_timed("spmv", A.st.K <= 7 ? 0 : 1, k_spmv<8>, dim3(nblk(a.N, 256)), dim3(256), 0, s, a);
+    else
+        launch_timed("spmv", A.st.K <= 7 ? 0 : 1, k_spmv<24>, dim3(nblk(a.N, 256)), dim3(256), 0, s, a);
     KCHECK();
 }
 
@@ -372,14 +379,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_tol(const Chunk *chunks, con
 
 // pass-1 partials of w = A z with V[0..j] (stencil operator, chunk grid);
 // ww: w.w in column j+1 as well
-template <int NC>
+template <int NC, int BS>
 __global__ void __launch_bounds__(RED_THREADS) k_gm_spmv_dots(const Chunk *chunks, SpmvArgs a, const double *V, long ld, int j,
                                                               double *part, const int *act, int ww) {
-    __shared__ int sh[MAXK];
     const Chunk ch = chunks[blockIdx.x];
     // an inactive reservoir's partials are never read
     if (!act[ch.blk]) return;
-    stage_offsets(a.off, a.K, sh);
     const int nc = j + 1;
     double acc[NC];
 #pragma unroll
@@ -391,9 +396,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_spmv_dots(const Chunk *chunk
 #pragma unroll
             for (int c = 0; c < NC; ++c)
                 if (c < nc) vv[c] = V[(size_t)c * ld + i];
-            const int l = i - k.off;
-            const int x = l % k.nx, y = (l / k.nx) % k.ny, z = l / (k.nx * k.ny);
-            const double wi = stencil_dot(sh, a.K, a.coef, a.N, a.x, i, x, y, z, k);
+            const double wi = stencil_dot<BS>(a.offp, a.K, a.coef, a.N, a.x, i, k);
             a.y[i] = wi;
 #pragma unroll
             for (int c = 0; c < NC; ++c)
@@ -779,7 +782,10 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
             with_columns(j + 2, [&](auto bound) {
                 constexpr int NC = decltype(bound)::value;
                 SpmvArgs sa = spmv_args(*Aop, zj, w.p, nullptr, nullptr);
-                k_gm_spmv_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, V[0].p, ld, j, P0, act, 1);
+                if (stencil_batch(sa.K) == 8)
+                    k_gm_spmv_dots<NC, 8><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, V[0].p, ld, j, P0, act, 1);
+                else
+                    k_gm_spmv_dots<NC, 24><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, V[0].p, ld, j, P0, act, 1);
                 KCHECK();
             });
             GmFuse f{S.cfirst.p, P0, nch, w.p, Vall.p, ld, st, j, act, act_next, slot, zj};
@@ -794,7 +800,10 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
             const int one = o.single_pass ? 1 : 0;
             if (Aop) {
                 SpmvArgs sa = spmv_args(*Aop, zj, w.p, nullptr, nullptr);
-                k_gm_spmv_dots<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, vb, ld, j, P0, act, one);
+                if (stencil_batch(sa.K) == 8)
+                    k_gm_spmv_dots<NC, 8><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, vb, ld, j, P0, act, one);
+                else
+                    k_gm_spmv_dots<NC, 24><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, vb, ld, j, P0, act, one);
                 KCHECK();
             } else {
                 A(zj, w.p, nullptr, act);
