@@ -36,8 +36,8 @@ WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128
 PMC_TRAFFIC = {
     "workload": "2d_512x512_twolevel_fp64",
     "source": "paper_2007_13966_amd/csrc/schwarz.hip",
-    "sha1": "01324324290caec31f8516fbb3c9938134e05760",
-    "fetch_kib": 8866.2, "fetch_scale": 2.0,
+    "sha1": "d99595fa4ff0d6bfa6e9eab484e55f14487e2084",
+    "fetch_kib": 8818.9, "fetch_scale": 2.0,
     "write_kib": 2048.0, "write_scale": 1.0,
 }
 
