@@ -1603,6 +1603,7 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         maxlds = 65536;
     lds_bytes = std::min(maxlds, 160 * 1024);
+    if (hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) num_cus = 256;
 }
 
 void Ras::factor() {
@@ -1874,10 +1875,13 @@ void Ras::coarse_solve(const double *b, double *x, const int *mask) {
     o.flexible = false;
     o.check_every = 1;
     o.graph_chunk = graph_chunk;
-    // one Gram-Schmidt pass: a handful of iterations to a loose tolerance;
-    // on a 2D row level each step's finish runs inside the next sweep
+    // one Gram-Schmidt pass: a handful of iterations to a loose tolerance.
+    // On a 2D row level with no more boxes than CUs, each step's finish runs
+    // inside the next sweep: one round of workgroups pays the fused
+    // kernel's longer prologue once.  With more boxes the workgroups run in
+    // rounds, each paying it again, and the separate finish kernel is faster.
     o.single_pass = true;
-    if (C.rows2d && d.variant == NKS_LEFT_RAS)
+    if (C.rows2d && d.variant == NKS_LEFT_RAS && C.nsub <= num_cus)
         o.fused = [&](const GmFuse &f) { apply_fused(L - 1, f); };
     coarse.solve(A, P, b, x, true, o, mask, s, C.A);
     ++coarse_calls;
