@@ -124,8 +124,7 @@ def level_bytes(P, case, s, level):
 
 
 ROOFLINE_RECORDS = ["ras_apply_l0", "ras_apply_l1"]
-BREAKDOWN_RECORDS = ["ras_apply_l0", "ras_apply_l1", "ras_apply_l2", "coarse_fused_l1", "coarse_fused_l2",
-                     "spmv_l0", "spmv_l1", "gmres_arnoldi", "residual_jacobian", "ilu_factor_l0",
+BREAKDOWN_RECORDS = ["ras_apply_l0", "ras_apply_l1", "ras_apply_l2", "spmv_l0", "spmv_l1", "gmres_arnoldi", "residual_jacobian", "ilu_factor_l0",
                      "ilu_factor_l1", "ilu_factor_l2", "rap_l1", "rap_l2"]
 
 

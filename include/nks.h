@@ -323,8 +323,7 @@ int nks_ras_autotune(nks_grid *g, const double *p, const double *p_n, const doub
  * records carry the events on the dispatch itself (the kernel's own
  * execution time): "ras_apply_l<level>" (one-level Schwarz sweeps),
  * "ilu_factor_l<level>", "rap_l<level>", "spmv_l<0|1>" (7-or-fewer-point /
- * wider stencils), "coarse_fused_l<level>" (a coarse GMRES step: the
- * Arnoldi finish fused with the next sweep).  Span records bracket several kernels: "gmres_arnoldi"
+ * wider stencils).  Span records bracket several kernels: "gmres_arnoldi"
  * (the Arnoldi step after the preconditioner), "residual_jacobian".  Launches inside captured graphs are not recorded.
  * enable != 0 clears the records and starts recording, 0 stops.  query
  * synchronises and returns the number of launches and their summed duration

@@ -23,33 +23,11 @@ struct GmDev {
     int *active, *conv, *kdim, *its, *upd;
     int *active2;     // second activity buffer: iteration j reads buffer j%2, writes the other
     int *flag;        // host-mapped, 4 slots of nb: iteration j (slot j%3) and restart (slot 3) activity
-    double *gj2;      // 2*nb: g_j before its rotation, by step parity (read by every workgroup
-                      // of the fused form while the lead one rotates g)
-    int *its0;        // iterations at the start of the cycle
     int nb;
     int m, maxit;
     double rtol, atol;
 };
 
-// The fused single-pass form: the preconditioner launch of step j+1 also
-// finishes step j (totals of the partials, the Givens step by every
-// workgroup, v_{j+1} = (w - V h) / h_{j+1,j} on the fly, state written by
-// the lead workgroup of each reservoir) and writes z_{j+1} = M^{-1} v_{j+1}.
-struct GmFuse {
-    const int *cfirst;   // reservoir -> first chunk of the partials
-    const double *pin;   // step j partials: V^T w in columns 0..j, w.w in column j+1
-    int ns;              // chunks (column stride of pin)
-    const double *w;     // w = A z_j
-    double *V;           // basis, column stride ld; v_{j+1} goes to column j+1
-    long ld;
-    GmDev st;
-    int j;
-    const int *act;      // activity of step j
-    int *act_next;       // activity of step j+1
-    int slot;            // host flag slot
-    double *z;           // z_{j+1} (owned cells)
-};
-using FusedPrecond = std::function<void(const GmFuse &f)>;
 
 struct GmOpts {
     double rtol = 1e-5, atol = 1e-8;
@@ -58,8 +36,6 @@ struct GmOpts {
     int check_every = 1;
     int graph_chunk = 0;   // > 0: replay captured chunks of this many iterations (A and M must be capturable)
     bool single_pass = false;   // classical Gram-Schmidt without reorthogonalisation (loose solves)
-    FusedPrecond fused;         // with single_pass, a stencil operator and right preconditioning:
-                                // the finish of each step runs inside the next preconditioner launch
 };
 
 struct Gmres {

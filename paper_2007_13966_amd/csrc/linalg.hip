@@ -1,9 +1,10 @@
 // Stencil SpMV, per-reservoir reductions and right-preconditioned
 // GMRES / FGMRES(m) (Section 3, the Jacobian system; Remark 2 for the flexible
 // variant).  Orthogonalisation is classical Gram-Schmidt with one
-// reorthogonalisation pass (two fused multi-dot + update passes), FP64.
-// Every reduction is deterministic: per-chunk partial sums, then a fixed-
-// order sum per reservoir done by the last workgroup to finish.
+// reorthogonalisation pass (CGS2), or a single pass for short solves to a
+// loose tolerance, FP64.  Every reduction is deterministic: per-chunk
+// partial sums, then a fixed-order sum per reservoir by every workgroup of
+// the next kernel.
 #include <functional>
 #include <type_traits>
 
@@ -324,8 +325,6 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_begin(const Chunk *chunks, c
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) v0[i] = r[i] / beta;
     if (lead && threadIdx.x == 0) {
         st.its[b] = its;
-        st.its0[b] = its;
-        st.gj2[b] = beta;   // g_0 of the cycle (step parity 0)
         st.conv[b] = conv;
         st.tol[b] = tol;
         st.beta[b] = beta;
@@ -670,8 +669,8 @@ void Gmres::ensure(Alloc *al_, const Space &sp_, int m_, bool flexible, hipStrea
         g.alloc(al, (size_t)B * (m + 1));
         y.alloc(al, (size_t)B * m);
         hj.alloc(al, (size_t)B * (m + 1));
-        scal.alloc(al, (size_t)B * 5);
-        ints.alloc(al, (size_t)B * 7);
+        scal.alloc(al, (size_t)B * 3);
+        ints.alloc(al, (size_t)B * 6);
         std::vector<const double *> hv(m + 1), hz(std::max(m, 1));
         for (int k = 0; k <= m; ++k) hv[k] = V[k].p;
         for (int k = 0; k < (int)Z.size(); ++k) hz[k] = Z[k].p;
@@ -713,8 +712,6 @@ GmDev Gmres::dev(double rtol, double atol, int maxit) {
     d.upd = ints.p + 4 * B;
     d.active2 = ints.p + 5 * B;
     d.flag = dflag;
-    d.gj2 = scal.p + 3 * B;
-    d.its0 = ints.p + 6 * B;
     d.nb = nb;
     d.m = m;
     d.maxit = maxit;
@@ -768,30 +765,11 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
     const double *const *Vp = vptr.p;
     const double *vb = V[0].p;   // the basis: m + 1 columns of stride ld
     const bool flex = o.flexible;
-    const bool fuse = o.fused && o.single_pass && Aop && !flex;
     // one GMRES iteration j; its activity flags go to `slot`
     auto iteration = [&](int j, int slot) {
         double *zj = flex ? Z[j].p : t.p;
         const int *act = (j & 1) ? st.active2 : st.active;
         int *act_next = (j & 1) ? st.active : st.active2;
-        if (fuse) {
-            // z_j is in place: the plain preconditioner for j = 0, the fused
-            // launch of step j-1 otherwise
-            if (j == 0) M(V[0].p, zj, act);
-            ProfScope ps("gmres_arnoldi", s);
-            with_columns(j + 2, [&](auto bound) {
-                constexpr int NC = decltype(bound)::value;
-                SpmvArgs sa = spmv_args(*Aop, zj, w.p, nullptr, nullptr);
-                if (stencil_batch(sa.K) == 8)
-                    k_gm_spmv_dots<NC, 8><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, V[0].p, ld, j, P0, act, 1);
-                else
-                    k_gm_spmv_dots<NC, 24><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, sa, V[0].p, ld, j, P0, act, 1);
-                KCHECK();
-            });
-            GmFuse f{S.cfirst.p, P0, nch, w.p, Vall.p, ld, st, j, act, act_next, slot, zj};
-            o.fused(f);
-            return;
-        }
         M(V[j].p, zj, act);
         ProfScope ps("gmres_arnoldi", s);
         // pass 2 carries j + 2 columns (V[0..j]^T w and w.w)

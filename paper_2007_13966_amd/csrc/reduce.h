@@ -1,7 +1,7 @@
-// Workgroup reductions shared by the Krylov kernels and the fused
-// preconditioner: DPP lane-group sums, column sums over a workgroup, and the
-// totals of per-chunk partial sums (two-stage, fence-free reductions: the
-// partials of one kernel are summed by every workgroup of the next).
+// Workgroup reductions of the Krylov kernels: DPP lane-group sums, column
+// sums over a workgroup, and the totals of per-chunk partial sums (two-stage,
+// fence-free reductions: the partials of one kernel are summed by every
+// workgroup of the next).
 #pragma once
 
 #include "nks_internal.h"

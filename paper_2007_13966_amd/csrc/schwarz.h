@@ -105,7 +105,6 @@ struct Ras {
     std::vector<TileDims> tiles_;
     Gmres coarse;
     int lds_bytes = 65536;
-    int num_cus = 256;           // compute units of the device
     int graph_chunk = 4;         // coarse GMRES iterations per captured graph (0: plain launches)
     int coarse_its_last = 0;
     long coarse_its_total = 0;
@@ -115,8 +114,6 @@ struct Ras {
     void factor();                                     // numeric (every call)
     void apply(const double *r, double *z, const int *mask);
     void apply_level(int l, const double *r, double *z, const int *mask, bool accumulate);
-    // the coarse GMRES's fused step: finish of Arnoldi step f.j and z_{j+1} (2D row levels, left-RAS)
-    void apply_fused(int l, const GmFuse &f);
     void vcycle(int l, const double *b, double *x, const int *mask);
     void coarse_solve(const double *b, double *x, const int *mask);
     void restrict_to(int l, const double *rf, double *rc, const int *mask);

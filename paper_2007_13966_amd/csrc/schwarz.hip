@@ -25,7 +25,6 @@
 #include <tuple>
 
 #include "schwarz.h"
-#include "reduce.h"
 
 namespace nks {
 
@@ -852,8 +851,6 @@ struct RowsArgs {
     const int *mask;
     int variant, accumulate;
     int kmap[32];         // slot of the padded per-cell run -> stencil index (-1: absent or padding)
-    GmFuse gm;            // fused form: the Arnoldi finish of step gm.j, right-hand side v_{j+1}
-    const BlkPart *bpart; // fused form: reservoir -> first subdomain (the lead workgroup)
 };
 
 // coefficients of one cell: N consecutive FT values (16-byte aligned runs)
@@ -887,16 +884,7 @@ __device__ __forceinline__ int row_of(int c, float inv_ex) { return (int)(((floa
 // the box repeat the last row), stores of masked steps go to a spare slot,
 // and the stencil map arrives in the kernel arguments.  The upper factors and 1/u_ii are
 // staged by the other wavefronts while the forward sweep runs.
-//
-// GM (the fused single-pass GMRES form, left-RAS): before the sweep, every
-// workgroup sums the partials of Arnoldi step j (h = V^T w, w.w), rotates
-// column j by the previous Givens rotations and decides whether step j+1
-// runs, all in the same order, so every workgroup of a reservoir reaches the
-// same decision; the reservoir's lead workgroup alone writes H, the
-// rotations, g, the counters and the flags.  The right-hand side is then
-// v_{j+1} = (w - V h) / h_{j+1,j}, formed on the extended box while staging,
-// and its owned cells are written to column j+1 of the basis.
-template <typename FT, typename VT, typename DT, int BOX, bool GM>
+template <typename FT, typename VT, typename DT, int BOX>
 __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
     using S = RowStencil<BOX>;
     constexpr int NS = S::NS, NL = S::NL, NU = NS - NL, LB = S::LB;
@@ -908,94 +896,7 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
     static_assert(NSP <= 32, "stencil map fits the argument block");
     extern __shared__ __align__(16) unsigned char smem[];
     const SubDev sd = a.sub[blockIdx.x];
-    __shared__ double gh[GM ? MAXCOL + 1 : 1];       // step j totals: h in 0..j, w.w in j+1
-    __shared__ double gr[GM ? 2 * MAXCOL + 2 : 1];   // previous rotations (c, s), g_j, 1/h_{j+1,j}
-    __shared__ int gnext;
-    double hinv = 0.0;
-    if constexpr (GM) {
-        const GmFuse &f = a.gm;
-        const int b = sd.blk, j = f.j, nc = j + 1, m = f.st.m;
-        const bool lead = (int)blockIdx.x == a.bpart[b].first;
-        if (!f.act[b]) {
-            if (lead && threadIdx.x == 0) {
-                f.act_next[b] = 0;
-                f.st.flag[f.slot * f.st.nb + b] = f.st.conv[b] ? 2 : 0;
-            }
-            return;
-        }
-        double *cs = f.st.cs + (size_t)b * m, *sn = f.st.sn + (size_t)b * m;
-        {
-            const int t = threadIdx.x, jm = max(j - 1, 0);
-            if (t < MAXCOL) {
-                gr[t] = cs[min(t, jm)];
-                gr[MAXCOL + t] = sn[min(t, jm)];
-            } else if (t == MAXCOL) {
-                gr[2 * MAXCOL] = f.st.gj2[(size_t)(j & 1) * f.st.nb + b];
-            }
-        }
-        int its1 = 0;
-        double tol = 0.0;
-        if (threadIdx.x == 0) {
-            its1 = f.st.its0[b] + j + 1;
-            tol = f.st.tol[b];
-        }
-        block_totals<MAXCOL>(f.pin, f.cfirst[b], f.cfirst[b + 1], nc + 1, gh, f.ns);
-        if (threadIdx.x == 0) {
-            double h2 = 0.0;
-            for (int c = 0; c < nc; ++c) h2 += gh[c] * gh[c];
-            const double hn = sqrt(fmax(gh[nc] - h2, 0.0));
-            double hcol[MAXCOL + 1];
-#pragma unroll
-            for (int k = 0; k < MAXCOL; ++k) hcol[k] = k <= j ? gh[k] : 0.0;
-            hcol[MAXCOL] = 0.0;
-#pragma unroll
-            for (int k = 0; k < MAXCOL - 1; ++k) {
-                if (k < j) {
-                    const double a0 = hcol[k], a1 = hcol[k + 1], cc = gr[k], ss = gr[MAXCOL + k];
-                    hcol[k] = cc * a0 + ss * a1;
-                    hcol[k + 1] = -ss * a0 + cc * a1;
-                }
-            }
-            double a0 = 0.0;
-#pragma unroll
-            for (int k = 0; k < MAXCOL; ++k)
-                if (k == j) a0 = hcol[k];
-            const double den = sqrt(a0 * a0 + hn * hn);
-            const double c = den > 0.0 ? a0 / den : 1.0;
-            const double sg = den > 0.0 ? hn / den : 0.0;
-            const double gj = gr[2 * MAXCOL];
-            const double res = fabs(sg * gj);
-            const bool conv = res <= tol || hn == 0.0;
-            const int nxt = (!conv && its1 < f.st.maxit && j + 1 < m) ? 1 : 0;
-            if (lead) {
-                double *H = f.st.H + (size_t)b * (m + 1) * m;
-                double *g = f.st.g + (size_t)b * (m + 1);
-#pragma unroll
-                for (int k = 0; k < MAXCOL; ++k)
-                    if (k < j) H[(size_t)k * m + j] = hcol[k];
-                H[(size_t)j * m + j] = den;
-                H[(size_t)(j + 1) * m + j] = 0.0;
-                cs[j] = c;
-                sn[j] = sg;
-                g[j] = c * gj;
-                g[j + 1] = -sg * gj;
-                f.st.gj2[(size_t)((j + 1) & 1) * f.st.nb + b] = -sg * gj;
-                f.st.its[b] = its1;
-                f.st.kdim[b] = j + 1;
-                f.st.res[b] = res;
-                if (conv) f.st.conv[b] = 1;
-                f.act_next[b] = nxt;
-                f.st.flag[f.slot * f.st.nb + b] = nxt ? 1 : (conv ? 2 : 0);
-            }
-            gr[2 * MAXCOL + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
-            gnext = nxt;
-        }
-        __syncthreads();
-        if (!gnext) return;   // converged, restart or maxit: no v_{j+1}, no sweep
-        hinv = gr[2 * MAXCOL + 1];
-    } else {
-        if (a.mask && !a.mask[sd.blk]) return;
-    }
+    if (a.mask && !a.mask[sd.blk]) return;
     const int n = sd.next, ex = sd.ex, ey = sd.ey;
     // LDS: rv[n + 1] (slot n takes the stores of masked steps), cf[n * NSP], id[n]
     VT *rv = reinterpret_cast<VT *>(smem);
@@ -1023,21 +924,7 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
                 v[u][q] = k >= 0 ? x : (FT)0;
             }
             const int y = row_of(c, inv_ex), x = c - y * ex;
-            const size_t g = (size_t)sd.gorg + x + (size_t)sd.gnx * y;
-            if constexpr (GM) {
-                // v_{j+1} = (w - V h) / h_{j+1,j}; every load issued before the sums
-                const GmFuse &f = a.gm;
-                double vk[MAXCOL];
-#pragma unroll
-                for (int k = 0; k < MAXCOL; ++k) vk[k] = k <= f.j ? f.V[(size_t)k * f.ld + g] : 0.0;
-                double t = f.w[g];
-#pragma unroll
-                for (int k = 0; k < MAXCOL; ++k)
-                    if (k <= f.j) t -= gh[k] * vk[k];
-                rr[u] = t * hinv;
-            } else {
-                rr[u] = a.r[g];
-            }
+            rr[u] = a.r[(size_t)sd.gorg + x + (size_t)sd.gnx * y];
         }
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
@@ -1048,9 +935,6 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
                 const int y = row_of(c, inv_ex), x = c - y * ex;
                 const bool own = x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1;
                 rv[c] = (VT)((a.variant == NKS_RIGHT_RAS && !own) ? 0.0 : rr[u]);
-                if constexpr (GM) {
-                    if (own) a.gm.V[(size_t)(a.gm.j + 1) * a.gm.ld + (size_t)sd.gorg + x + (size_t)sd.gnx * y] = rr[u];
-                }
             }
         }
     }
@@ -1603,7 +1487,6 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         maxlds = 65536;
     lds_bytes = std::min(maxlds, 160 * 1024);
-    if (hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) num_cus = 256;
 }
 
 void Ras::factor() {
@@ -1717,8 +1600,7 @@ static int level_index(const Ras &M, const Level &V) {
 }
 
 template <typename FT, typename VT, typename DT>
-static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int *mask, bool accumulate,
-                        const GmFuse *gm = nullptr) {
+static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int *mask, bool accumulate) {
     RowsArgs a{};
     a.sub = V.sub.p;
     if (V.box == 0) row_kmap<0, FT>(V.hslot, a.kmap);
@@ -1740,22 +1622,10 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     const size_t sh = al16(sizeof(VT) * (n + 1)) + al16(sizeof(FT) * NSP * n) + al16(sizeof(DT) * n);
     if (V.max_next >= (1 << 16)) fail(NKS_EINVAL, "2D subdomain of %zu cells exceeds 65535", n);
     if (sh > (size_t)M.lds_bytes) fail(NKS_EINVAL, "2D subdomain of %zu cells does not fit in LDS", n);
-    void (*fn)(RowsArgs) = nullptr;
-    if (gm) {
-        if (M.d.variant != NKS_LEFT_RAS) fail(NKS_EINVAL, "the fused coarse form needs left-RAS");
-        a.gm = *gm;
-        a.bpart = V.part.p;
-        a.z = gm->z;
-        a.mask = nullptr;
-        a.accumulate = 0;
-        fn = V.box == 0 ? k_ras_rows<FT, VT, DT, 0, true>
-                        : (V.box == 1 ? k_ras_rows<FT, VT, DT, 1, true> : k_ras_rows<FT, VT, DT, 2, true>);
-    } else {
-        fn = V.box == 0 ? k_ras_rows<FT, VT, DT, 0, false>
-                        : (V.box == 1 ? k_ras_rows<FT, VT, DT, 1, false> : k_ras_rows<FT, VT, DT, 2, false>);
-    }
+    void (*fn)(RowsArgs) = V.box == 0 ? k_ras_rows<FT, VT, DT, 0>
+                                      : (V.box == 1 ? k_ras_rows<FT, VT, DT, 1> : k_ras_rows<FT, VT, DT, 2>);
     set_lds((const void *)fn, sh);
-    launch_timed(gm ? "coarse_fused" : "ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(256), sh, M.g->s, a);
+    launch_timed("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(256), sh, M.g->s, a);
     KCHECK();
     if (M.d.variant != NKS_LEFT_RAS) {
         k_ras_gather<<<nblk(V.spp->N, 256), 256, 0, M.g->s>>>(V.spp->blk.p, V.spp->B, V.spp->N, V.part.p,
@@ -1834,14 +1704,6 @@ void Ras::apply_level(int l, const double *r, double *z, const int *mask, bool a
     else launch_apply<uint16_t, float, float>(*this, V, td, r, z, mask, accumulate);
 }
 
-void Ras::apply_fused(int l, const GmFuse &f) {
-    Level &V = *lev[l];
-    if (!V.rows2d) fail(NKS_EINVAL, "the fused coarse form needs a 2D row level");
-    if (d.precision == NKS_FP64) launch_rows<double, double, double>(*this, V, nullptr, f.z, nullptr, false, &f);
-    else if (d.precision == NKS_FP32) launch_rows<float, float, float>(*this, V, nullptr, f.z, nullptr, false, &f);
-    else launch_rows<uint16_t, float, float>(*this, V, nullptr, f.z, nullptr, false, &f);
-}
-
 void Ras::restrict_to(int l, const double *rf, double *rc, const int *mask) {
     XferArgs a = xfer_args(*lev[l], *lev[l + 1], mask);
     k_restrict<<<nblk(a.Nc, 256), 256, 0, g->s>>>(a, rf, rc);
@@ -1875,14 +1737,8 @@ void Ras::coarse_solve(const double *b, double *x, const int *mask) {
     o.flexible = false;
     o.check_every = 1;
     o.graph_chunk = graph_chunk;
-    // one Gram-Schmidt pass: a handful of iterations to a loose tolerance.
-    // On a 2D row level with no more boxes than CUs, each step's finish runs
-    // inside the next sweep: one round of workgroups pays the fused
-    // kernel's longer prologue once.  With more boxes the workgroups run in
-    // rounds, each paying it again, and the separate finish kernel is faster.
+    // one Gram-Schmidt pass: a handful of iterations to a loose tolerance
     o.single_pass = true;
-    if (C.rows2d && d.variant == NKS_LEFT_RAS && C.nsub <= num_cus)
-        o.fused = [&](const GmFuse &f) { apply_fused(L - 1, f); };
     coarse.solve(A, P, b, x, true, o, mask, s, C.A);
     ++coarse_calls;
 }

@@ -191,6 +191,25 @@ def test_multilevel_apply_parity(nks, orc, cycle):
     assert np.max(np.abs(zg - zo)) <= 1e-9 * np.max(np.abs(zo))
 
 
+def test_multilevel_many_coarse_boxes_parity(nks, orc):
+    # 17 x 17 = 289 boxes on each level, more than the 256 CUs of the device:
+    # the box kernels run in several rounds of workgroups
+    cfg = dict(nx=120, ny=120, nz=1, px=17, py=17, levels=2, overlap=(1, 1),
+               coarse_rtol=0.0, coarse_maxit=6)
+    say("multilevel, 289 coarse boxes")
+    case = S.small_case(**cfg)
+    rec = case.problems[0]
+    op = orc.Problem(rec)
+    p, pn, _ = _state(op, 12)
+    Jo = op.jacobian(p, pn, pn, case.dt, 1)
+    r = np.sin(0.3 * np.arange(op.N))
+    zo = orc.Multilevel(rec, Jo, case.solver).apply(r)
+    g = nks.Grid([rec])
+    M = nks.Ras(_gpu_jac(nks, g, p, pn, case.dt), case.solver)
+    zg = M.apply(g.from_numpy(r)).cpu().numpy()
+    assert np.max(np.abs(zg - zo)) <= 1e-9 * np.max(np.abs(zo))
+
+
 def test_three_level_3d_apply_parity(nks, orc):
     cfg = dict(nx=16, ny=16, nz=8, px=2, py=2, pz=2, levels=3, overlap=(1, 1, 1), gravity=True,
                coarse_rtol=0.0, coarse_maxit=4, kv_ratio=0.1)
