@@ -20,7 +20,7 @@ struct SubDev {
     int nlev;                    // wavefront levels
     int inv_off;                 // first entry of the padded-tile inverse map
     int gorg;                    // global index of the extended box's origin cell
-    int gnx;                     // row stride (cells) of its block
+    int gnx, gny;                // row and column counts of its block (strides of y and z)
 };
 
 // Per block box layout of a level (for the AS / right-RAS gather)
@@ -71,6 +71,10 @@ struct Level {
     // 2D levels use the register-wavefront sweep: factors stored in
     // lexicographic order, stencil mapped onto a row template
     bool rows2d = false;
+    // 3D levels with the 7-point stencil and at most 64 (y, z) rows per box use
+    // the one-wavefront 3D sweep; factors stored in lexicographic order
+    bool rows3d = false;
+    std::vector<int> hkmap3;     // 3D sweep: lower (z, y, x) and upper (x, y, z) slots -> stencil index
     int box = 0;                 // 0: 5-point cross, 1: 5x5 box, 2: 21-point (5x5 without corners)
     DBuf<int> slotmap;           // box slot -> stencil index (-1: absent)
     std::vector<int> hslot;      // host copy of slotmap

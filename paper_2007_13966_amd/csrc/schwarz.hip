@@ -169,6 +169,7 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
                     sd.next = sd.ex * sd.ey * sd.ez;
                     sd.gorg = k.off + elo[0] + k.nx * (elo[1] + k.ny * elo[2]);
                     sd.gnx = k.nx;
+                    sd.gny = k.ny;
                     mex = std::max(mex, sd.ex);
                     minex = std::min(minex, sd.ex);
                     mey = std::max(mey, sd.ey);
@@ -253,6 +254,23 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
             L.slotmap.upload(al, slot, s);
             L.hslot = slot;
             L.rows2d = true;
+        }
+    }
+    // 3D one-wavefront sweep: the 7-point stencil, at most 64 (y, z) rows and
+    // 64 cells per row per box
+    L.rows3d = false;
+    if (Rz == 1 && R == 1 && st.K == 7 && mey * mez <= 64 && mex <= 64) {
+        bool cross = true;
+        for (int k = 0; k < st.K; ++k)
+            if (std::abs(st.off[3 * k]) + std::abs(st.off[3 * k + 1]) + std::abs(st.off[3 * k + 2]) > 1) cross = false;
+        if (cross) {
+            auto find = [&](int dx, int dy, int dz) {
+                for (int k = 0; k < st.K; ++k)
+                    if (st.off[3 * k] == dx && st.off[3 * k + 1] == dy && st.off[3 * k + 2] == dz) return k;
+                return -1;
+            };
+            L.hkmap3 = {find(0, 0, -1), find(0, -1, 0), find(-1, 0, 0), find(1, 0, 0), find(0, 1, 0), find(0, 0, 1)};
+            L.rows3d = true;
         }
     }
     // stencil tables
@@ -840,6 +858,15 @@ __device__ __forceinline__ double lane_shl(double v) {
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
+// the value of lane src_addr / 4 (a lane permute through the LDS crossbar)
+__device__ __forceinline__ float lane_from(float v, int src_addr) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src_addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_from(double v, int src_addr) {
+    const int lo = __builtin_amdgcn_ds_bpermute(src_addr, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src_addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
 
 struct RowsArgs {
     const SubDev *sub;
@@ -1085,6 +1112,161 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
             const int x = sd.lx0 + xx, yb = sd.ly0 + yy;
             const size_t g = (size_t)sd.gorg + x + (size_t)sd.gnx * yb;
             const double v = (double)rv[yb * ex + x];
+            a.z[g] = a.accumulate ? a.z[g] + v : v;
+        }
+    } else {
+        for (int c = threadIdx.x; c < n; c += blockDim.x) a.zext[fo + c] = (double)rv[c];
+    }
+}
+
+// ---------------------------------------------------------------- kernel: 3D one-wavefront sweep
+// 3D boxes with the 7-point stencil and at most 64 (y, z) rows: lane
+// r = y + ey*z owns row (y, z), and step t handles x = t - y - z, so the
+// three lower neighbours of a cell were produced one step earlier: by this
+// lane (x-1), by lane r-1 (y-1, through a DPP lane shift) and by lane r-ey
+// (z-1, through a lane permute).  Neighbours outside the box have zero
+// factors (they are dropped from A_i), so what those lanes hold only has to
+// be finite; rows past the box and steps outside a row's range are masked
+// to zero.  The backward sweep mirrors this with the upper neighbours.
+// Factors, 1/u_ii and R_i^delta r are staged in LDS as in the 2D sweep.
+struct Rows3Args {
+    const SubDev *sub;
+    const void *F;        // K*NE off-diagonal factors (FT), lexicographic per subdomain
+    const void *invd;     // NE (DT)
+    int NE;
+    const double *r;
+    double *z, *zext;
+    const int *mask;
+    int variant, accumulate;
+    int kmap[16];         // run slot -> stencil index: lower (z, y, x) then upper (x, y, z); -1 padding
+};
+
+template <typename FT, typename VT, typename DT>
+__global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
+    constexpr int PER = (int)(16 / sizeof(FT));
+    constexpr int NLP = (3 + PER - 1) / PER * PER;   // lower run: Lz, Ly, Lx, padding
+    constexpr int NSP = 2 * NLP;                     // then the upper run: Ux, Uy, Uz, padding
+    constexpr int RB = 8;                            // steps per block of LDS reads
+    constexpr int CPT = 2;
+    extern __shared__ __align__(16) unsigned char smem3[];
+    const SubDev sd = a.sub[blockIdx.x];
+    if (a.mask && !a.mask[sd.blk]) return;
+    const int n = sd.next, ex = sd.ex, ey = sd.ey, ez = sd.ez, nrow = ey * ez;
+    VT *rv = reinterpret_cast<VT *>(smem3);
+    FT *cf = reinterpret_cast<FT *>(smem3 + al16(sizeof(VT) * (size_t)(n + 1)));
+    DT *id = reinterpret_cast<DT *>(smem3 + al16(sizeof(VT) * (size_t)(n + 1)) + al16(sizeof(FT) * (size_t)NSP * n));
+    const FT *F = reinterpret_cast<const FT *>(a.F);
+    const DT *ID = reinterpret_cast<const DT *>(a.invd);
+    const size_t fo = sd.fac_off;
+    const float inv_ex = 1.0f / (float)ex, inv_ey = 1.0f / (float)ey;
+    // stage every cell's runs, 1/u_ii and R_i^delta r; every load of a pass
+    // is issued before its first LDS store
+    for (int c0 = threadIdx.x; c0 < n; c0 += CPT * 256) {
+        FT v[CPT][NSP];
+        DT d[CPT];
+        double rr[CPT];
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = min(c0 + u * 256, n - 1);
+#pragma unroll
+            for (int q = 0; q < NSP; ++q) {
+                const int k = a.kmap[q];
+                const FT x = F[(size_t)max(k, 0) * a.NE + fo + c];
+                v[u][q] = k >= 0 ? x : (FT)0;
+            }
+            d[u] = ID[fo + c];
+            const int row = row_of(c, inv_ex), x = c - row * ex;
+            const int z = row_of(row, inv_ey), y = row - z * ey;
+            rr[u] = a.r[(size_t)sd.gorg + x + (size_t)sd.gnx * (y + (size_t)sd.gny * z)];
+        }
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = c0 + u * 256;
+            if (c < n) {
+#pragma unroll
+                for (int q = 0; q < NSP; ++q) cf[(size_t)c * NSP + q] = v[u][q];
+                id[c] = d[u];
+                const int row = row_of(c, inv_ex), x = c - row * ex;
+                const int z = row_of(row, inv_ey), y = row - z * ey;
+                const bool own = x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1 && z >= sd.lz0 && z < sd.lz1;
+                rv[c] = (VT)((a.variant == NKS_RIGHT_RAS && !own) ? 0.0 : rr[u]);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int r = threadIdx.x;
+        const bool rowok = r < nrow;
+        const int rr0 = rowok ? r : 0;
+        const int z = rr0 / ey, y = rr0 - z * ey;
+        const int T = (ex - 1) + (ey - 1) + (ez - 1) + 1;
+        const int lo = rowok ? y + z : (1 << 28);     // steps with x inside the row
+        const int cb = ex * rr0 - y - z;              // cell of forward step t: cb + t
+        const int pz_f = ((r - ey) & 63) << 2, pz_b = ((r + ey) & 63) << 2;   // permute sources
+        // forward: y_i = r_i - Lz y_(z-1) - Ly y_(y-1) - Lx y_(x-1)
+        VT prev = (VT)0;
+        for (int t0 = 0; t0 < T; t0 += RB) {
+            VT co[RB][NLP], rin[RB];
+            int cc[RB];
+            bool aa[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int t = t0 + u;
+                aa[u] = (unsigned)(t - lo) < (unsigned)ex;
+                cc[u] = min(max(cb + t, 0), n - 1);
+                load_run<FT, VT, NLP>(cf + (size_t)cc[u] * NSP, co[u]);
+                rin[u] = rv[cc[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const VT yp = lane_shr(prev), zp = lane_from(prev, pz_f);
+                VT v = rin[u];
+                v -= co[u][0] * zp;
+                v -= co[u][1] * yp;
+                v -= co[u][2] * prev;
+                prev = aa[u] ? v : (VT)0;
+                rv[aa[u] ? cc[u] : n] = prev;
+            }
+        }
+        // backward: z_i = (y_i - Ux z_(x+1) - Uy z_(y+1) - Uz z_(z+1)) / u_ii, step t at x = T-1-t - y - z
+        prev = (VT)0;
+        const int lob = rowok ? T - ex - y - z : (1 << 28);
+        const int cbb = cb + T - 1;
+        for (int t0 = 0; t0 < T; t0 += RB) {
+            VT co[RB][NLP], rin[RB], dg[RB];
+            int cc[RB];
+            bool aa[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int t = t0 + u;
+                aa[u] = (unsigned)(t - lob) < (unsigned)ex;
+                cc[u] = min(max(cbb - t, 0), n - 1);
+                load_run<FT, VT, NLP>(cf + (size_t)cc[u] * NSP + NLP, co[u]);
+                rin[u] = rv[cc[u]];
+                dg[u] = (VT)id[cc[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const VT yn = lane_shl(prev), zn = lane_from(prev, pz_b);
+                VT v = rin[u];
+                v -= co[u][0] * prev;
+                v -= co[u][1] * yn;
+                v -= co[u][2] * zn;
+                prev = aa[u] ? v * dg[u] : (VT)0;
+                rv[aa[u] ? cc[u] : n] = prev;
+            }
+        }
+    }
+    __syncthreads();
+    if (a.variant == NKS_LEFT_RAS) {
+        const int oxn = sd.lx1 - sd.lx0, oyn = sd.ly1 - sd.ly0, ozn = sd.lz1 - sd.lz0;
+        const float inv_oxn = 1.0f / (float)oxn, inv_oyn = 1.0f / (float)oyn;
+        for (int k = threadIdx.x; k < oxn * oyn * ozn; k += blockDim.x) {
+            const int row = row_of(k, inv_oxn), xx = k - row * oxn;
+            const int zz = row_of(row, inv_oyn), yy = row - zz * oyn;
+            const int x = sd.lx0 + xx, y = sd.ly0 + yy, z = sd.lz0 + zz;
+            const size_t g = (size_t)sd.gorg + x + (size_t)sd.gnx * (y + (size_t)sd.gny * z);
+            const double v = (double)rv[x + ex * (y + ey * z)];
             a.z[g] = a.accumulate ? a.z[g] + v : v;
         }
     } else {
@@ -1489,6 +1671,8 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     lds_bytes = std::min(maxlds, 160 * 1024);
 }
 
+static bool use_rows3d(const Ras &M, const Level &V);
+
 void Ras::factor() {
     hipStream_t s = g->s;
     for (int l = 0; l < L; ++l) {
@@ -1529,7 +1713,7 @@ void Ras::factor() {
         fa.w = V.w64.p;
         fa.err = V.err.p;
         const int bs = 64;
-        const int *perm = V.rows2d ? V.lexg.p : nullptr;
+        const int *perm = (V.rows2d || use_rows3d(*this, V)) ? V.lexg.p : nullptr;
         const int rl = V.box == 0 ? RowStencil<0>::NS + 2 : (V.box == 1 ? RowStencil<1>::NS + 2 : RowStencil<2>::NS + 2);
         const size_t sh_rows = sizeof(double) * (size_t)rl * V.max_next;
         if (V.rows2d && sh_rows <= (size_t)lds_bytes) {
@@ -1634,11 +1818,65 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     }
 }
 
+// LDS of the 3D one-wavefront sweep for boxes of n cells: rv[n + 1], the
+// padded lower and upper runs, 1/u_ii
+static size_t rows3d_lds(int precision, size_t n) {
+    const size_t ft = precision == NKS_FP64 ? 8 : (precision == NKS_FP32 ? 4 : 2);
+    const size_t vt = precision == NKS_FP64 ? 8 : 4, dt = vt;
+    const size_t per = 16 / ft, nlp = (3 + per - 1) / per * per;
+    return al16(vt * (n + 1)) + al16(ft * 2 * nlp * n) + al16(dt * n);
+}
+
+// whether a level runs the 3D one-wavefront sweep (its factors are then
+// stored in lexicographic order)
+static bool use_rows3d(const Ras &M, const Level &V) {
+    return V.rows3d && V.max_next < (1 << 16) && rows3d_lds(M.d.precision, V.max_next) <= (size_t)M.lds_bytes;
+}
+
+template <typename FT, typename VT, typename DT>
+static void launch_rows3d(Ras &M, Level &V, const double *r, double *z, const int *mask, bool accumulate) {
+    Rows3Args a{};
+    a.sub = V.sub.p;
+    constexpr int PER = (int)(16 / sizeof(FT));
+    constexpr int NLP = (3 + PER - 1) / PER * PER;
+    static_assert(2 * NLP <= 16, "run map fits the argument block");
+    for (int q = 0; q < 16; ++q) a.kmap[q] = -1;
+    for (int q = 0; q < 3; ++q) {
+        a.kmap[q] = V.hkmap3[q];
+        a.kmap[NLP + q] = V.hkmap3[3 + q];
+    }
+    if (M.d.precision == NKS_FP64) a.F = V.f64.p;
+    else if (M.d.precision == NKS_FP32) a.F = V.f32.p;
+    else a.F = V.f16.p;
+    a.invd = M.d.precision == NKS_FP64 ? (const void *)V.invd64.p : (const void *)V.invd32.p;
+    a.NE = V.next_total;
+    a.r = r;
+    a.z = z;
+    a.zext = V.zext.p;
+    a.mask = mask;
+    a.variant = M.d.variant;
+    a.accumulate = accumulate ? 1 : 0;
+    const size_t sh = rows3d_lds(M.d.precision, V.max_next);
+    void (*fn)(Rows3Args) = k_ras_rows3d<FT, VT, DT>;
+    set_lds((const void *)fn, sh);
+    launch_timed("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(256), sh, M.g->s, a);
+    KCHECK();
+    if (M.d.variant != NKS_LEFT_RAS) {
+        k_ras_gather<<<nblk(V.spp->N, 256), 256, 0, M.g->s>>>(V.spp->blk.p, V.spp->B, V.spp->N, V.part.p,
+                                                              V.sub.p, V.zext.p, z, mask, accumulate ? 1 : 0);
+        KCHECK();
+    }
+}
+
 template <typename FT, typename VT, typename DT>
 static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, double *z, const int *mask,
                          bool accumulate) {
     if (V.rows2d) {
         launch_rows<FT, VT, DT>(M, V, r, z, mask, accumulate);
+        return;
+    }
+    if (use_rows3d(M, V)) {
+        launch_rows3d<FT, VT, DT>(M, V, r, z, mask, accumulate);
         return;
     }
     ApplyArgs a;
