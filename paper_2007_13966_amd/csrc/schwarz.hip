@@ -87,6 +87,15 @@ constexpr int row_run() {
            (RowStencil<BOX>::NS - RowStencil<BOX>::NL + PER - 1) / PER * PER;
 }
 
+// LDS stride of a cell's run in FT elements: an odd number of 16-byte
+// words, so that the cells of one sweep step (ex - lb cells apart from lane
+// to lane) fall in distinct LDS bank groups whenever ex - lb is odd
+template <int BOX, typename FT>
+constexpr int row_stride() {
+    constexpr int R = row_run<BOX, FT>();
+    return (R * sizeof(FT) / 16) % 2 ? R : R + (int)(16 / sizeof(FT));
+}
+
 // stencil index of every slot of the padded run (lower run, then upper
 // run), from the 25 box slots of the level's stencil; -1 for absent slots
 // and padding
@@ -820,11 +829,27 @@ __global__ void __launch_bounds__(256) k_ras_apply(ApplyArgs a) {
     if (a.variant == NKS_LEFT_RAS) {
         const int ox = sd.lx1 - sd.lx0, oy = sd.ly1 - sd.ly0, oz = sd.lz1 - sd.lz0;
         const int no = ox * oy * oz;
-        for (int c = threadIdx.x; c < no; c += blockDim.x) {
-            const int x = sd.lx0 + c % ox, y = sd.ly0 + (c / ox) % oy, z = sd.lz0 + c / (ox * oy);
-            const int g = bk.off + (sd.ox + x) + bk.nx * ((sd.oy + y) + bk.ny * (sd.oz + z));
-            const double v = (double)tile[(x + a.R) + a.PX * ((y + a.R) + a.PY * (z + a.Rz))];
-            a.z[g] = a.accumulate ? a.z[g] + v : v;
+        // WB cells per thread per pass: with accumulation, every load of z
+        // is issued before the first store
+        constexpr int WB = 8;
+        const int bs = blockDim.x;
+        for (int c0 = threadIdx.x; c0 < no; c0 += WB * bs) {
+            int g[WB];
+            double v[WB];
+#pragma unroll
+            for (int u = 0; u < WB; ++u) {
+                const int c = min(c0 + u * bs, no - 1);
+                const int x = sd.lx0 + c % ox, y = sd.ly0 + (c / ox) % oy, z = sd.lz0 + c / (ox * oy);
+                g[u] = bk.off + (sd.ox + x) + bk.nx * ((sd.oy + y) + bk.ny * (sd.oz + z));
+                v[u] = (double)tile[(x + a.R) + a.PX * ((y + a.R) + a.PY * (z + a.Rz))];
+            }
+            if (a.accumulate) {
+#pragma unroll
+                for (int u = 0; u < WB; ++u) v[u] += a.z[g[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < WB; ++u)
+                if (c0 + u * bs < no) a.z[g[u]] = v[u];
         }
     } else {
         for (int c = threadIdx.x; c < sd.next; c += blockDim.x) {
@@ -903,6 +928,22 @@ __device__ __forceinline__ void load_run(const FT *p, VT (&out)[N]) {
 // c < 2^16 and ex <= 64, where (c + 1/2) / ex stays 1/128 off integers
 __device__ __forceinline__ int row_of(int c, float inv_ex) { return (int)(((float)c + 0.5f) * inv_ex); }
 
+// guard cells on each side of the sweeps' LDS arrays: the padded steps of
+// the last block and the look-ahead block read up to RU + RU/2 - 1 cells
+// past either end of a box (RU <= 16)
+constexpr int ROWS_PAD = 32;
+struct RowsLds {
+    size_t rv, cf, id, total;
+};
+__host__ __device__ inline RowsLds rows_lds(size_t vt, size_t ft, size_t dt, int nsp, size_t n) {
+    RowsLds L;
+    L.rv = 0;
+    L.cf = al16(vt * (n + 1 + 2 * ROWS_PAD));
+    L.id = L.cf + al16(ft * nsp * (n + 2 * ROWS_PAD));
+    L.total = L.id + al16(dt * (n + 2 * ROWS_PAD));
+    return L;
+}
+
 // Every instruction of the sweeping wavefront costs an issue slot (one
 // wavefront per SIMD), so the step loop keeps only the arithmetic, the LDS
 // traffic and the lane shifts: the cell of step t is cb + t, which stays in
@@ -918,18 +959,25 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
     constexpr int PER = (int)(16 / sizeof(FT));
     constexpr int NLP = (NL + PER - 1) / PER * PER, NUP = (NU + PER - 1) / PER * PER;
     constexpr int NSP = NLP + NUP;   // padded run per cell: lower run, then upper run
-    constexpr int RU = 8;            // unroll = ring length (>= the deepest history used)
-    constexpr int CPT = 2;           // cells per staging thread per pass
+    constexpr int CS = row_stride<BOX, FT>();   // LDS stride of a cell's run
+    constexpr int RU = BOX == 0 ? 16 : 8;   // unroll = ring length (>= the deepest history used)
+    // cells per staging thread per pass: a 36x36 cross-stencil box in one
+    // pass, so its loads pay the memory latency once
+    constexpr int CPT = BOX == 0 ? 6 : 2;
+    constexpr int CPU = 2;           // the same for the upper runs (staged during the forward sweep)
     static_assert(NSP <= 32, "stencil map fits the argument block");
     extern __shared__ __align__(16) unsigned char smem[];
     const SubDev sd = a.sub[blockIdx.x];
     if (a.mask && !a.mask[sd.blk]) return;
     const int n = sd.next, ex = sd.ex, ey = sd.ey;
-    // LDS: rv[n + 1] (slot n takes the stores of masked steps), cf[n * NSP], id[n]
-    VT *rv = reinterpret_cast<VT *>(smem);
-    FT *cf = reinterpret_cast<FT *>(smem + al16(sizeof(VT) * (size_t)(n + 1)));
+    // LDS: rv[n + 1] (slot n takes the stores of masked steps), cf[n * CS],
+    // id[n], each with ROWS_PAD guard cells on both sides for the padded
+    // steps at either end of a sweep
+    const RowsLds L = rows_lds(sizeof(VT), sizeof(FT), sizeof(DT), CS, n);
+    VT *rv = reinterpret_cast<VT *>(smem + L.rv) + ROWS_PAD;
+    FT *cf = reinterpret_cast<FT *>(smem + L.cf) + (size_t)ROWS_PAD * CS;
     static_assert(sizeof(FT) * NSP % 16 == 0, "cell runs are whole 16-byte words");
-    DT *id = reinterpret_cast<DT *>(smem + al16(sizeof(VT) * (size_t)(n + 1)) + al16(sizeof(FT) * (size_t)NSP * n));
+    DT *id = reinterpret_cast<DT *>(smem + L.id) + ROWS_PAD;
     const FT *F = reinterpret_cast<const FT *>(a.F);
     const DT *ID = reinterpret_cast<const DT *>(a.invd);
     const size_t fo = sd.fac_off;
@@ -958,7 +1006,7 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
             const int c = c0 + u * 256;
             if (c < n) {
 #pragma unroll
-                for (int q = 0; q < NLP; ++q) cf[(size_t)c * NSP + q] = v[u][q];
+                for (int q = 0; q < NLP; ++q) cf[(size_t)c * CS + q] = v[u][q];
                 const int y = row_of(c, inv_ex), x = c - y * ex;
                 const bool own = x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1;
                 rv[c] = (VT)((a.variant == NKS_RIGHT_RAS && !own) ? 0.0 : rr[u]);
@@ -976,63 +1024,74 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
     const int ye = min(y, ey - 1);
     const int tlo = rowok ? LB * y : (1 << 28);   // steps with x = t - LB*y inside the row
     const int cb = ye * (ex - LB);                // cell of step t: cb + t (forward)
-    // RB steps per block: every LDS read of a block is issued before its
-    // first step and every write after its last, so the loads overlap the
-    // dependent arithmetic of the previous block.
-    constexpr int RB = BOX ? 4 : 8;
+    // Blocks of RB steps, software pipelined: the LDS reads of the next
+    // block are issued before the arithmetic of the current one.  The reads
+    // may run ahead of the current block's stores because an active step
+    // reads only its own cell, which no other step writes.
+    constexpr int RB = RU / 2;
     if (wid == 0 && (BOX || rowok)) {
         // rings: own outputs, outputs of lane y-1 and y-2
         VT r0[RU], r1[RU], r2[RU];
 #pragma unroll
         for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
-        // forward: y_i = r_i - sum_{lower} L_ik y_k
-        for (int t0 = 0; t0 < T; t0 += RU) {
+        VT coA[RB][NLP], rinA[RB], coB[RB][NLP], rinB[RB];
+        int ccA[RB], ccB[RB];
+        bool aaA[RB], aaB[RB];
+        auto load = [&](int tb, VT(&co)[RB][NLP], VT(&rin)[RB], int(&cc)[RB], bool(&aa)[RB]) {
+            // cells cb + tb + u: within the guard cells for every padded step
+            const FT *cfb = cf + (ptrdiff_t)(cb + tb) * CS;
+            const VT *rvb = rv + (cb + tb);
 #pragma unroll
-            for (int b0 = 0; b0 < RU; b0 += RB) {
-                VT co[RB][NLP], rin[RB], outv[RB];
-                int cc[RB];
-                bool aa[RB];
-#pragma unroll
-                for (int u = 0; u < RB; ++u) {
-                    const int t = t0 + b0 + u;
-                    aa[u] = (unsigned)(t - tlo) < (unsigned)ex;
-                    cc[u] = cb + t;   // in [0, n) for every step when ex >= LB
-                    load_run<FT, VT, NLP>(cf + (size_t)cc[u] * NSP, co[u]);
-                    rin[u] = rv[cc[u]];
-                }
-#pragma unroll
-                for (int u = 0; u < RB; ++u) {
-                    const int uu = b0 + u;
-                    VT v = rin[u];
-                    // older terms first, the one-step-old terms (critical path) last
-#pragma unroll
-                    for (int pass = 0; pass < 2; ++pass) {
-#pragma unroll
-                        for (int q = 0; q < NL; ++q) {
-                            const int h = -(S::DX[q] + LB * S::DY[q]) - 1;
-                            if ((h == 0) != (pass == 1)) continue;
-                            const int slot = (uu - 1 - h + 2 * RU) % RU;
-                            const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == -1 ? r1[slot] : r2[slot]);
-                            v -= co[u][q] * val;
-                        }
-                    }
-                    const VT out = aa[u] ? v : (VT)0;
-                    outv[u] = out;
-                    r0[uu] = out;
-                    r1[uu] = lane_shr(out);
-                    r2[uu] = lane_shr(r1[uu]);
-                }
-#pragma unroll
-                for (int u = 0; u < RB; ++u) rv[aa[u] ? cc[u] : n] = outv[u];
+            for (int u = 0; u < RB; ++u) {
+                aa[u] = (unsigned)(tb + u - tlo) < (unsigned)ex;
+                cc[u] = cb + tb + u;
+                load_run<FT, VT, NLP>(cfb + u * CS, co[u]);
+                rin[u] = rvb[u];
             }
+        };
+        // forward: y_i = r_i - sum_{lower} L_ik y_k
+        auto step = [&](int b0, VT(&co)[RB][NLP], VT(&rin)[RB], int(&cc)[RB], bool(&aa)[RB]) {
+            VT outv[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int uu = b0 + u;
+                VT v = rin[u];
+                // older terms first, then the one-step-old terms of this lane,
+                // and last those that wait for a lane shift (the critical path)
+#pragma unroll
+                for (int pass = 0; pass < 3; ++pass) {
+#pragma unroll
+                    for (int q = 0; q < NL; ++q) {
+                        const int h = -(S::DX[q] + LB * S::DY[q]) - 1;
+                        if (pass != (h != 0 ? 0 : (S::DY[q] == 0 ? 1 : 2))) continue;
+                        const int slot = (uu - 1 - h + 2 * RU) % RU;
+                        const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == -1 ? r1[slot] : r2[slot]);
+                        v -= co[u][q] * val;
+                    }
+                }
+                const VT out = aa[u] ? v : (VT)0;
+                outv[u] = out;
+                r0[uu] = out;
+                r1[uu] = lane_shr(out);
+                r2[uu] = lane_shr(r1[uu]);
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u) rv[aa[u] ? cc[u] : n] = outv[u];
+        };
+        load(0, coA, rinA, ccA, aaA);
+        for (int t0 = 0; t0 < T; t0 += RU) {
+            load(t0 + RB, coB, rinB, ccB, aaB);
+            step(0, coA, rinA, ccA, aaA);
+            load(t0 + RU, coA, rinA, ccA, aaA);
+            step(RB, coB, rinB, ccB, aaB);
         }
     } else if (wid > 0) {
         // the other wavefronts stage the upper runs and 1/u_ii meanwhile
-        for (int c0 = threadIdx.x - 64; c0 < n; c0 += CPT * 192) {
-            FT v[CPT][NUP];
-            DT d[CPT];
+        for (int c0 = threadIdx.x - 64; c0 < n; c0 += CPU * 192) {
+            FT v[CPU][NUP];
+            DT d[CPU];
 #pragma unroll
-            for (int u = 0; u < CPT; ++u) {
+            for (int u = 0; u < CPU; ++u) {
                 const int c = min(c0 + u * 192, n - 1);
 #pragma unroll
                 for (int q = 0; q < NUP; ++q) {
@@ -1043,11 +1102,11 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
                 d[u] = ID[fo + c];
             }
 #pragma unroll
-            for (int u = 0; u < CPT; ++u) {
+            for (int u = 0; u < CPU; ++u) {
                 const int c = c0 + u * 192;
                 if (c < n) {
 #pragma unroll
-                    for (int q = 0; q < NUP; ++q) cf[(size_t)c * NSP + NLP + q] = v[u][q];
+                    for (int q = 0; q < NUP; ++q) cf[(size_t)c * CS + NLP + q] = v[u][q];
                     id[c] = d[u];
                 }
             }
@@ -1061,58 +1120,84 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
         for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
         const int cbb = cb + T - 1;
         const int tlob = rowok ? T - LB * y - ex : (1 << 28);   // x = T - 1 - t - LB*y in [0, ex)
-        for (int t0 = 0; t0 < T; t0 += RU) {
+        VT coA[RB][NUP], rinA[RB], dgA[RB], coB[RB][NUP], rinB[RB], dgB[RB];
+        int ccA[RB], ccB[RB];
+        bool aaA[RB], aaB[RB];
+        auto load = [&](int tb, VT(&co)[RB][NUP], VT(&rin)[RB], VT(&dg)[RB], int(&cc)[RB], bool(&aa)[RB]) {
+            // cells cbb - tb - u, addressed from the block's lowest cell
+            const int cl = cbb - tb - (RB - 1);
+            const FT *cfb = cf + (ptrdiff_t)cl * CS + NLP;
+            const VT *rvb = rv + cl;
+            const DT *idb = id + cl;
 #pragma unroll
-            for (int b0 = 0; b0 < RU; b0 += RB) {
-                VT co[RB][NUP], rin[RB], dg[RB], outv[RB];
-                int cc[RB];
-                bool aa[RB];
-#pragma unroll
-                for (int u = 0; u < RB; ++u) {
-                    const int t = t0 + b0 + u;
-                    aa[u] = (unsigned)(t - tlob) < (unsigned)ex;
-                    cc[u] = cbb - t;
-                    load_run<FT, VT, NUP>(cf + (size_t)cc[u] * NSP + NLP, co[u]);
-                    rin[u] = rv[cc[u]];
-                    dg[u] = (VT)id[cc[u]];
-                }
-#pragma unroll
-                for (int u = 0; u < RB; ++u) {
-                    const int uu = b0 + u;
-                    VT v = rin[u];
-#pragma unroll
-                    for (int pass = 0; pass < 2; ++pass) {
-#pragma unroll
-                        for (int q = NL; q < NS; ++q) {
-                            const int h = S::DX[q] + LB * S::DY[q] - 1;
-                            if ((h == 0) != (pass == 1)) continue;
-                            const int slot = (uu - 1 - h + 2 * RU) % RU;
-                            const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == 1 ? r1[slot] : r2[slot]);
-                            v -= co[u][q - NL] * val;
-                        }
-                    }
-                    const VT out = aa[u] ? v * dg[u] : (VT)0;
-                    outv[u] = out;
-                    r0[uu] = out;
-                    r1[uu] = lane_shl(out);
-                    r2[uu] = lane_shl(r1[uu]);
-                }
-#pragma unroll
-                for (int u = 0; u < RB; ++u) rv[aa[u] ? cc[u] : n] = outv[u];
+            for (int u = 0; u < RB; ++u) {
+                aa[u] = (unsigned)(tb + u - tlob) < (unsigned)ex;
+                cc[u] = cl + (RB - 1 - u);
+                load_run<FT, VT, NUP>(cfb + (RB - 1 - u) * CS, co[u]);
+                rin[u] = rvb[RB - 1 - u];
+                dg[u] = (VT)idb[RB - 1 - u];
             }
+        };
+        auto step = [&](int b0, VT(&co)[RB][NUP], VT(&rin)[RB], VT(&dg)[RB], int(&cc)[RB], bool(&aa)[RB]) {
+            VT outv[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int uu = b0 + u;
+                VT v = rin[u];
+#pragma unroll
+                for (int pass = 0; pass < 3; ++pass) {
+#pragma unroll
+                    for (int q = NL; q < NS; ++q) {
+                        const int h = S::DX[q] + LB * S::DY[q] - 1;
+                        if (pass != (h != 0 ? 0 : (S::DY[q] == 0 ? 1 : 2))) continue;
+                        const int slot = (uu - 1 - h + 2 * RU) % RU;
+                        const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == 1 ? r1[slot] : r2[slot]);
+                        v -= co[u][q - NL] * val;
+                    }
+                }
+                const VT out = aa[u] ? v * dg[u] : (VT)0;
+                outv[u] = out;
+                r0[uu] = out;
+                r1[uu] = lane_shl(out);
+                r2[uu] = lane_shl(r1[uu]);
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u) rv[aa[u] ? cc[u] : n] = outv[u];
+        };
+        load(0, coA, rinA, dgA, ccA, aaA);
+        for (int t0 = 0; t0 < T; t0 += RU) {
+            load(t0 + RB, coB, rinB, dgB, ccB, aaB);
+            step(0, coA, rinA, dgA, ccA, aaA);
+            load(t0 + RU, coA, rinA, dgA, ccA, aaA);
+            step(RB, coB, rinB, dgB, ccB, aaB);
         }
     }
     __syncthreads();
     // write back with all threads, x-contiguous (coalesced)
     if (a.variant == NKS_LEFT_RAS) {
-        const int oxn = sd.lx1 - sd.lx0, oyn = sd.ly1 - sd.ly0;
+        // WB cells per thread per pass: with accumulation, every load of z
+        // is issued before the first store
+        constexpr int WB = 4;
+        const int oxn = sd.lx1 - sd.lx0, no = oxn * (sd.ly1 - sd.ly0);
         const float inv_oxn = 1.0f / (float)oxn;
-        for (int k = threadIdx.x; k < oxn * oyn; k += blockDim.x) {
-            const int yy = row_of(k, inv_oxn), xx = k - yy * oxn;
-            const int x = sd.lx0 + xx, yb = sd.ly0 + yy;
-            const size_t g = (size_t)sd.gorg + x + (size_t)sd.gnx * yb;
-            const double v = (double)rv[yb * ex + x];
-            a.z[g] = a.accumulate ? a.z[g] + v : v;
+        for (int k0 = threadIdx.x; k0 < no; k0 += WB * 256) {
+            size_t g[WB];
+            double v[WB];
+#pragma unroll
+            for (int u = 0; u < WB; ++u) {
+                const int k = min(k0 + u * 256, no - 1);
+                const int yy = row_of(k, inv_oxn), xx = k - yy * oxn;
+                const int x = sd.lx0 + xx, yb = sd.ly0 + yy;
+                g[u] = (size_t)sd.gorg + x + (size_t)sd.gnx * yb;
+                v[u] = (double)rv[yb * ex + x];
+            }
+            if (a.accumulate) {
+#pragma unroll
+                for (int u = 0; u < WB; ++u) v[u] += a.z[g[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < WB; ++u)
+                if (k0 + u * 256 < no) a.z[g[u]] = v[u];
         }
     } else {
         for (int c = threadIdx.x; c < n; c += blockDim.x) a.zext[fo + c] = (double)rv[c];
@@ -1261,13 +1346,27 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
     if (a.variant == NKS_LEFT_RAS) {
         const int oxn = sd.lx1 - sd.lx0, oyn = sd.ly1 - sd.ly0, ozn = sd.lz1 - sd.lz0;
         const float inv_oxn = 1.0f / (float)oxn, inv_oyn = 1.0f / (float)oyn;
-        for (int k = threadIdx.x; k < oxn * oyn * ozn; k += blockDim.x) {
-            const int row = row_of(k, inv_oxn), xx = k - row * oxn;
-            const int zz = row_of(row, inv_oyn), yy = row - zz * oyn;
-            const int x = sd.lx0 + xx, y = sd.ly0 + yy, z = sd.lz0 + zz;
-            const size_t g = (size_t)sd.gorg + x + (size_t)sd.gnx * (y + (size_t)sd.gny * z);
-            const double v = (double)rv[x + ex * (y + ey * z)];
-            a.z[g] = a.accumulate ? a.z[g] + v : v;
+        constexpr int WB = 4;
+        const int no = oxn * oyn * ozn;
+        for (int k0 = threadIdx.x; k0 < no; k0 += WB * 256) {
+            size_t g[WB];
+            double v[WB];
+#pragma unroll
+            for (int u = 0; u < WB; ++u) {
+                const int k = min(k0 + u * 256, no - 1);
+                const int row = row_of(k, inv_oxn), xx = k - row * oxn;
+                const int zz = row_of(row, inv_oyn), yy = row - zz * oyn;
+                const int x = sd.lx0 + xx, y = sd.ly0 + yy, z = sd.lz0 + zz;
+                g[u] = (size_t)sd.gorg + x + (size_t)sd.gnx * (y + (size_t)sd.gny * z);
+                v[u] = (double)rv[x + ex * (y + ey * z)];
+            }
+            if (a.accumulate) {
+#pragma unroll
+                for (int u = 0; u < WB; ++u) v[u] += a.z[g[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < WB; ++u)
+                if (k0 + u * 256 < no) a.z[g[u]] = v[u];
         }
     } else {
         for (int c = threadIdx.x; c < n; c += blockDim.x) a.zext[fo + c] = (double)rv[c];
@@ -1801,9 +1900,9 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     a.mask = mask;
     a.variant = M.d.variant;
     a.accumulate = accumulate ? 1 : 0;
-    const int NSP = V.box == 0 ? row_run<0, FT>() : (V.box == 1 ? row_run<1, FT>() : row_run<2, FT>());
+    const int NSP = V.box == 0 ? row_stride<0, FT>() : (V.box == 1 ? row_stride<1, FT>() : row_stride<2, FT>());
     const size_t n = V.max_next;
-    const size_t sh = al16(sizeof(VT) * (n + 1)) + al16(sizeof(FT) * NSP * n) + al16(sizeof(DT) * n);
+    const size_t sh = rows_lds(sizeof(VT), sizeof(FT), sizeof(DT), NSP, n).total;
     if (V.max_next >= (1 << 16)) fail(NKS_EINVAL, "2D subdomain of %zu cells exceeds 65535", n);
     if (sh > (size_t)M.lds_bytes) fail(NKS_EINVAL, "2D subdomain of %zu cells does not fit in LDS", n);
     void (*fn)(RowsArgs) = V.box == 0 ? k_ras_rows<FT, VT, DT, 0>
