@@ -707,18 +707,22 @@ struct ApplyArgs {
     double *z, *zext;
     const int *mask;
     int variant, accumulate, cap;
+    int lin7[7];          // 7-point kernel: tile offsets of the stencil entries
 };
 
 // One subdomain per workgroup: gather R_i^delta r into the LDS tile, forward
 // sweep with the unit lower factor, backward sweep with the upper factor,
 // then write the owned cells (left-RAS) or the whole box (AS / right-RAS).
-template <typename FT, typename VT, typename DT>
+// NC = 3: the 7-point stencil (three lower and three upper terms, tile
+// offsets from the kernel arguments); NC = 0: any stencil, terms in blocks
+// of eight.
+template <typename FT, typename VT, typename DT, int NC>
 __global__ void __launch_bounds__(256) k_ras_apply(ApplyArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const SubDev sd = a.sub[blockIdx.x];
     if (a.mask && !a.mask[sd.blk]) return;
     const Blk bk = a.blk[sd.blk];
-    const int ncl = a.diag, ncu = a.K - a.diag - 1;
+    const int ncl = NC ? NC : a.diag, ncu = NC ? NC : a.K - a.diag - 1;
     const int ncmax = ncl > ncu ? ncl : ncu;
     const ApplyLds lay = apply_lds(sizeof(VT), sizeof(FT), sizeof(DT), a.tile, ncmax, a.cap, a.maxlev);
     VT *tile = reinterpret_cast<VT *>(smem);
@@ -772,6 +776,18 @@ __global__ void __launch_bounds__(256) k_ras_apply(ApplyArgs a) {
                 const int le = e - c0;
                 const int p = cl[le];
                 VT v = tile[p];
+                if constexpr (NC > 0) {
+                    VT cv[NC], tv[NC];
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        cv[k] = (VT)FTraits<FT>::get(cf, (size_t)k * a.cap + le);
+                        tv[k] = tile[p + a.lin7[k]];
+                    }
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) v -= cv[k] * tv[k];
+                    tile[p] = v;
+                    continue;
+                }
                 // eight terms at a time, every load issued before the first
                 // product (a padded term adds an exact zero)
                 for (int k0 = 0; k0 < ncl; k0 += 8) {
@@ -807,6 +823,18 @@ __global__ void __launch_bounds__(256) k_ras_apply(ApplyArgs a) {
                 const int le = e - c0;
                 const int p = cl[le];
                 VT v = tile[p];
+                if constexpr (NC > 0) {
+                    VT cv[NC], tv[NC];
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        cv[k] = (VT)FTraits<FT>::get(cf, (size_t)k * a.cap + le);
+                        tv[k] = tile[p + a.lin7[NC + 1 + k]];
+                    }
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) v -= cv[k] * tv[k];
+                    tile[p] = v * (VT)cd[le];
+                    continue;
+                }
                 for (int k0 = 0; k0 < ncu; k0 += 8) {
                     VT cv[8], tv[8];
 #pragma unroll
@@ -2016,14 +2044,23 @@ static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, 
     a.cap = std::max(a.cap, V.max_lvl);
     const size_t sh = apply_lds(sizeof(VT), sizeof(FT), sizeof(DT), a.tile, ncmax, a.cap, a.maxlev).total;
     if (sh > budget) fail(NKS_EINVAL, "LDS layout of %zu bytes exceeds %zu", sh, budget);
-    const void *fn = (const void *)k_ras_apply<FT, VT, DT>;
+    const bool seven = a.K == 7 && a.diag == 3;
+    if (seven)
+        for (int k = 0; k < 7; ++k) {
+            const int8_t *o = &V.A->st.off[3 * k];
+            a.lin7[k] = o[0] + td.PX * (o[1] + td.PY * o[2]);
+        }
+    const void *fn = seven ? (const void *)k_ras_apply<FT, VT, DT, 3> : (const void *)k_ras_apply<FT, VT, DT, 0>;
     set_lds(fn, sh);
     // enough threads for the widest hyperplane: small boxes with wide
     // stencils have many short hyperplanes, where one wavefront's barriers
     // are the cheap ones
     const int bs = V.max_lvl <= 64 ? 64 : (V.max_lvl <= 128 ? 128 : 256);
     {
-        launch_timed("ras_apply", level_index(M, V), k_ras_apply<FT, VT, DT>, dim3(V.nsub), dim3(bs), sh, M.g->s, a);
+        if (seven)
+            launch_timed("ras_apply", level_index(M, V), k_ras_apply<FT, VT, DT, 3>, dim3(V.nsub), dim3(bs), sh, M.g->s, a);
+        else
+            launch_timed("ras_apply", level_index(M, V), k_ras_apply<FT, VT, DT, 0>, dim3(V.nsub), dim3(bs), sh, M.g->s, a);
         KCHECK();
     }
     if (M.d.variant != NKS_LEFT_RAS) {
