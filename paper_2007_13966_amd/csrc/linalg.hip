@@ -608,19 +608,30 @@ static void with_columns(int cols, F &&f) {
 }
 
 // back substitution H y = g over the kdim leading columns of each block
-__global__ void k_gm_solve_y(int B, GmDev st) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+// Back substitution R y = g of the rotated Hessenberg matrix, one wavefront
+// per reservoir, by columns: lane i holds g_i and column entries H[i][c];
+// once y_c is known (lane c), every row above subtracts H[i][c] y_c.
+__global__ void __launch_bounds__(64) k_gm_solve_y(int B, GmDev st) {
+    constexpr int MR = MAXCOL - 2;   // largest restart
+    const int b = blockIdx.x, i = threadIdx.x;
     if (b >= B) return;
     const int m = st.m, k = st.kdim[b];
     const double *H = st.H + (size_t)b * (m + 1) * m;
-    const double *g = st.g + (size_t)b * (m + 1);
-    double *y = st.y + (size_t)b * m;
-    for (int r = k - 1; r >= 0; --r) {
-        double s = g[r];
-        for (int c = r + 1; c < k; ++c) s -= H[r * m + c] * y[c];
-        y[r] = s / H[r * m + r];
+    double gi = i < k ? st.g[(size_t)b * (m + 1) + i] : 0.0;
+    double hr[MR];
+#pragma unroll
+    for (int c = 0; c < MR; ++c) hr[c] = (i <= c && c < k) ? H[(size_t)i * m + c] : 0.0;
+    double yi = 0.0;
+#pragma unroll
+    for (int c = MR - 1; c >= 0; --c) {
+        if (c < k) {
+            const double yc = __shfl(gi, c) / __shfl(hr[c], c);
+            if (i < c) gi -= hr[c] * yc;
+            if (i == c) yi = yc;
+        }
     }
-    st.upd[b] = k > 0;
+    if (i < k) st.y[(size_t)b * m + i] = yi;
+    if (i == 0) st.upd[b] = k > 0;
 }
 
 // x += sum_{c < kdim} y[c] Zc   (or u = sum y[c] Vc when accumulate == 0)
@@ -801,10 +812,15 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
     const int kc = (o.graph_chunk > 0 && graphs_ok && s != nullptr) ? std::min(o.graph_chunk, m) : 0;
     if (kc && kc != gchunk) invalidate_graphs();
     gchunk = kc;
-    const int nchunk = kc ? (m + kc - 1) / kc : m;
+    // Captured chunks: a lead chunk of 2*kc iterations, then chunks of kc
+    // (each graph launch costs a boundary of several microseconds; the
+    // chunk queued past convergence, the look-ahead, runs as no-ops).
+    const int lead = kc ? std::min(m, 2 * kc) : 1, tail = kc ? kc : 1;
+    auto chunk_begin = [&](int c) { return c == 0 ? 0 : std::min(m, lead + (c - 1) * tail); };
+    const int nchunk = kc ? 1 + (m - lead + tail - 1) / tail : m;
     if (kc && (int)gexec.size() < nchunk) gexec.resize(nchunk, nullptr);
     auto launch_chunk = [&](int c) {
-        const int j0 = kc ? c * kc : c, j1 = kc ? std::min(m, j0 + kc) : c + 1;
+        const int j0 = kc ? chunk_begin(c) : c, j1 = kc ? chunk_begin(c + 1) : c + 1;
         if (!kc) {
             iteration(j0, c % 3);
             return;
@@ -850,7 +866,7 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
                 break;
             }
         }
-        k_gm_solve_y<<<nblk(S.B, 64), 64, 0, s>>>(S.B, st);
+        k_gm_solve_y<<<S.B, 64, 0, s>>>(S.B, st);
         KCHECK();
         if (flex) {
             k_gm_combine<<<NB, 256, 0, s>>>(S.blk.p, S.B, S.N, zptr.p, x, st, 1);
