@@ -36,8 +36,8 @@ WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128
 PMC_TRAFFIC = {
     "workload": "2d_512x512_twolevel_fp64",
     "source": "paper_2007_13966_amd/csrc/schwarz.hip",
-    "sha1": "d99595fa4ff0d6bfa6e9eab484e55f14487e2084",
-    "fetch_kib": 8818.9, "fetch_scale": 2.0,
+    "sha1": "692ead36faecac2a689b6531403372455cce9aae",
+    "fetch_kib": 8852.2, "fetch_scale": 2.0,
     "write_kib": 2048.0, "write_scale": 1.0,
 }
 
@@ -301,7 +301,9 @@ def main():
             "autotune": tuning,
         },
         "roofline": {
-            "kernel": "k_ras_rows<double> (fine level 2D sweeps: one-level left-RAS, ILU(0) factors)",
+            "kernel": ("k_ras_apply<double, double, double, 3> (fine level 3D 7-point sweeps: one-level left-RAS, "
+                       "ILU(0) factors)" if case.problems[0].nz > 1 else
+                       "k_ras_rows<double, double, double, 0> (fine level 2D sweeps: one-level left-RAS, ILU(0) factors)"),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
