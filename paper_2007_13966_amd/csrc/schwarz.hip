@@ -956,19 +956,21 @@ __device__ __forceinline__ void load_run(const FT *p, VT (&out)[N]) {
 // c < 2^16 and ex <= 64, where (c + 1/2) / ex stays 1/128 off integers
 __device__ __forceinline__ int row_of(int c, float inv_ex) { return (int)(((float)c + 0.5f) * inv_ex); }
 
+// Steps per unrolled sweep iteration (the register ring length) and the
 // guard cells on each side of the sweeps' LDS arrays: the padded steps of
-// the last block and the look-ahead block read up to RU + RU/2 - 1 cells
-// past either end of a box (RU <= 16)
-constexpr int ROWS_PAD = 32;
+// the last iteration and the look-ahead block read up to RU + RU/2 - 1
+// cells past either end of a box.
+__host__ __device__ constexpr int rows_unroll(int box) { return box == 0 ? 16 : 8; }
+__host__ __device__ constexpr int rows_pad(int box) { return rows_unroll(box) + rows_unroll(box) / 2; }
 struct RowsLds {
     size_t rv, cf, id, total;
 };
-__host__ __device__ inline RowsLds rows_lds(size_t vt, size_t ft, size_t dt, int nsp, size_t n) {
+__host__ __device__ inline RowsLds rows_lds(size_t vt, size_t ft, size_t dt, int cs, int pad, size_t n) {
     RowsLds L;
     L.rv = 0;
-    L.cf = al16(vt * (n + 1 + 2 * ROWS_PAD));
-    L.id = L.cf + al16(ft * nsp * (n + 2 * ROWS_PAD));
-    L.total = L.id + al16(dt * (n + 2 * ROWS_PAD));
+    L.cf = al16(vt * (n + 1 + 2 * pad));
+    L.id = L.cf + al16(ft * cs * (n + 2 * pad));
+    L.total = L.id + al16(dt * (n + 2 * pad));
     return L;
 }
 
@@ -988,7 +990,8 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
     constexpr int NLP = (NL + PER - 1) / PER * PER, NUP = (NU + PER - 1) / PER * PER;
     constexpr int NSP = NLP + NUP;   // padded run per cell: lower run, then upper run
     constexpr int CS = row_stride<BOX, FT>();   // LDS stride of a cell's run
-    constexpr int RU = BOX == 0 ? 16 : 8;   // unroll = ring length (>= the deepest history used)
+    constexpr int RU = rows_unroll(BOX);   // unroll = ring length (>= the deepest history used)
+    constexpr int PAD = rows_pad(BOX);
     // cells per staging thread per pass: a 36x36 cross-stencil box in one
     // pass, so its loads pay the memory latency once
     constexpr int CPT = BOX == 0 ? 6 : 2;
@@ -999,13 +1002,13 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
     if (a.mask && !a.mask[sd.blk]) return;
     const int n = sd.next, ex = sd.ex, ey = sd.ey;
     // LDS: rv[n + 1] (slot n takes the stores of masked steps), cf[n * CS],
-    // id[n], each with ROWS_PAD guard cells on both sides for the padded
-    // steps at either end of a sweep
-    const RowsLds L = rows_lds(sizeof(VT), sizeof(FT), sizeof(DT), CS, n);
-    VT *rv = reinterpret_cast<VT *>(smem + L.rv) + ROWS_PAD;
-    FT *cf = reinterpret_cast<FT *>(smem + L.cf) + (size_t)ROWS_PAD * CS;
+    // id[n], each with PAD guard cells on both sides for the padded steps
+    // at either end of a sweep
+    const RowsLds L = rows_lds(sizeof(VT), sizeof(FT), sizeof(DT), CS, PAD, n);
+    VT *rv = reinterpret_cast<VT *>(smem + L.rv) + PAD;
+    FT *cf = reinterpret_cast<FT *>(smem + L.cf) + (size_t)PAD * CS;
     static_assert(sizeof(FT) * NSP % 16 == 0, "cell runs are whole 16-byte words");
-    DT *id = reinterpret_cast<DT *>(smem + L.id) + ROWS_PAD;
+    DT *id = reinterpret_cast<DT *>(smem + L.id) + PAD;
     const FT *F = reinterpret_cast<const FT *>(a.F);
     const DT *ID = reinterpret_cast<const DT *>(a.invd);
     const size_t fo = sd.fac_off;
@@ -1930,7 +1933,7 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     a.accumulate = accumulate ? 1 : 0;
     const int NSP = V.box == 0 ? row_stride<0, FT>() : (V.box == 1 ? row_stride<1, FT>() : row_stride<2, FT>());
     const size_t n = V.max_next;
-    const size_t sh = rows_lds(sizeof(VT), sizeof(FT), sizeof(DT), NSP, n).total;
+    const size_t sh = rows_lds(sizeof(VT), sizeof(FT), sizeof(DT), NSP, rows_pad(V.box), n).total;
     if (V.max_next >= (1 << 16)) fail(NKS_EINVAL, "2D subdomain of %zu cells exceeds 65535", n);
     if (sh > (size_t)M.lds_bytes) fail(NKS_EINVAL, "2D subdomain of %zu cells does not fit in LDS", n);
     void (*fn)(RowsArgs) = V.box == 0 ? k_ras_rows<FT, VT, DT, 0>
