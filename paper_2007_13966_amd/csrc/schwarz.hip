@@ -265,10 +265,11 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
             L.rows2d = true;
         }
     }
-    // 3D one-wavefront sweep: the 7-point stencil, at most 64 (y, z) rows and
-    // 64 cells per row per box
+    // 3D row sweep: the 7-point stencil, rows of at most 64 cells, at most four
+    // slabs of z planes with at most 64 (y, z) rows each
     L.rows3d = false;
-    if (Rz == 1 && R == 1 && st.K == 7 && mey * mez <= 64 && mex <= 64) {
+    const int pzmin = 64 / std::max(mey, 1);
+    if (Rz == 1 && R == 1 && st.K == 7 && mey <= 64 && mex <= 64 && (mez + pzmin - 1) / pzmin <= 4) {
         bool cross = true;
         for (int k = 0; k < st.K; ++k)
             if (std::abs(st.off[3 * k]) + std::abs(st.off[3 * k + 1]) + std::abs(st.off[3 * k + 2]) > 1) cross = false;
@@ -280,6 +281,7 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
             };
             L.hkmap3 = {find(0, 0, -1), find(0, -1, 0), find(-1, 0, 0), find(1, 0, 0), find(0, 1, 0), find(0, 0, 1)};
             L.rows3d = true;
+            L.rows3d_multi = mey * mez > 64;
         }
     }
     // stencil tables
@@ -1236,8 +1238,9 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
 }
 
 // ---------------------------------------------------------------- kernel: 3D one-wavefront sweep
-// 3D boxes with the 7-point stencil and at most 64 (y, z) rows: lane
-// r = y + ey*z owns row (y, z), and step t handles x = t - y - z, so the
+// 3D boxes with the 7-point stencil and rows of at most 64 cells: lane
+// r = y + ey*z owns row (y, z) (boxes of more than 64 rows are split into
+// slabs of z planes, one wavefront each), and step t handles x = t - y - z, so the
 // three lower neighbours of a cell were produced one step earlier: by this
 // lane (x-1), by lane r-1 (y-1, through a DPP lane shift) and by lane r-ey
 // (z-1, through a lane permute).  Neighbours outside the box have zero
@@ -1257,17 +1260,19 @@ struct Rows3Args {
     int kmap[16];         // run slot -> stencil index: lower (z, y, x) then upper (x, y, z); -1 padding
 };
 
-template <typename FT, typename VT, typename DT>
+template <typename FT, typename VT, typename DT, bool MULTI>
 __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
     constexpr int PER = (int)(16 / sizeof(FT));
     constexpr int NLP = (3 + PER - 1) / PER * PER;   // lower run: Lz, Ly, Lx, padding
     constexpr int NSP = 2 * NLP;                     // then the upper run: Ux, Uy, Uz, padding
-    constexpr int RB = 8;                            // steps per block of LDS reads
+    constexpr int RB = MULTI ? 4 : 8;                // steps per block of LDS reads
     constexpr int CPT = 2;
     extern __shared__ __align__(16) unsigned char smem3[];
+    __shared__ int prog[2][4];                       // steps done per slab: forward, backward
     const SubDev sd = a.sub[blockIdx.x];
     if (a.mask && !a.mask[sd.blk]) return;
-    const int n = sd.next, ex = sd.ex, ey = sd.ey, ez = sd.ez, nrow = ey * ez;
+    const int n = sd.next, ex = sd.ex, ey = sd.ey, ez = sd.ez;
+    if (MULTI && threadIdx.x < 8) prog[threadIdx.x >> 2][threadIdx.x & 3] = 0;
     VT *rv = reinterpret_cast<VT *>(smem3);
     FT *cf = reinterpret_cast<FT *>(smem3 + al16(sizeof(VT) * (size_t)(n + 1)));
     DT *id = reinterpret_cast<DT *>(smem3 + al16(sizeof(VT) * (size_t)(n + 1)) + al16(sizeof(FT) * (size_t)NSP * n));
@@ -1310,19 +1315,38 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
         }
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
-        const int r = threadIdx.x;
-        const bool rowok = r < nrow;
-        const int rr0 = rowok ? r : 0;
-        const int z = rr0 / ey, y = rr0 - z * ey;
+    // MULTI: the box's z planes are split into slabs of pz planes, one
+    // sweeping wavefront each.  A slab's first plane takes its z-1 values
+    // from the LDS copy the slab below has written, after waiting for that
+    // wavefront's progress counter; the backward sweep mirrors this with the
+    // slab above.  Every wait ends: the lowest slab (forward) and the highest
+    // (backward) never wait, and a spin limit bounds each wait.
+    const int pz = MULTI ? 64 / ey : ez;          // planes per sweeping wavefront
+    const int W = MULTI ? (ez + pz - 1) / pz : 1;
+    const int w = threadIdx.x >> 6;
+    auto wait_for = [&](const int *p, int need) {
+        int spins = 0;
+        while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need && ++spins < (1 << 22))
+            __builtin_amdgcn_s_sleep(1);
+    };
+    if (w < W) {
+        const int r = threadIdx.x & 63;
+        const int zl = r / ey, y0 = r - zl * ey;
+        const int nzw = min(pz, ez - w * pz);        // planes of this slab
+        const bool rowok = zl < nzw;
+        const int y = rowok ? y0 : 0, z = w * pz + (rowok ? zl : 0);
+        const int exy = ex * ey;
         const int T = (ex - 1) + (ey - 1) + (ez - 1) + 1;
         const int lo = rowok ? y + z : (1 << 28);     // steps with x inside the row
-        const int cb = ex * rr0 - y - z;              // cell of forward step t: cb + t
+        const int cb = ex * (y + ey * z) - y - z;     // cell of forward step t: cb + t
         const int pz_f = ((r - ey) & 63) << 2, pz_b = ((r + ey) & 63) << 2;   // permute sources
+        const bool zfirst = MULTI && w > 0 && zl == 0;             // z-1 from the slab below
+        const bool zlast = MULTI && w < W - 1 && zl == nzw - 1;    // z+1 from the slab above
         // forward: y_i = r_i - Lz y_(z-1) - Ly y_(y-1) - Lx y_(x-1)
         VT prev = (VT)0;
         for (int t0 = 0; t0 < T; t0 += RB) {
-            VT co[RB][NLP], rin[RB];
+            if (MULTI && w > 0) wait_for(&prog[0][w - 1], min(t0 + RB, T));
+            VT co[RB][NLP], rin[RB], rz[RB];
             int cc[RB];
             bool aa[RB];
 #pragma unroll
@@ -1332,10 +1356,13 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
                 cc[u] = min(max(cb + t, 0), n - 1);
                 load_run<FT, VT, NLP>(cf + (size_t)cc[u] * NSP, co[u]);
                 rin[u] = rv[cc[u]];
+                if (MULTI) rz[u] = rv[max(cc[u] - exy, 0)];
             }
 #pragma unroll
             for (int u = 0; u < RB; ++u) {
-                const VT yp = lane_shr(prev), zp = lane_from(prev, pz_f);
+                const VT yp = lane_shr(prev);
+                VT zp = lane_from(prev, pz_f);
+                if (MULTI) zp = zfirst ? rz[u] : zp;
                 VT v = rin[u];
                 v -= co[u][0] * zp;
                 v -= co[u][1] * yp;
@@ -1343,13 +1370,15 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
                 prev = aa[u] ? v : (VT)0;
                 rv[aa[u] ? cc[u] : n] = prev;
             }
+            if (MULTI) __hip_atomic_store(&prog[0][w], t0 + RB, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         // backward: z_i = (y_i - Ux z_(x+1) - Uy z_(y+1) - Uz z_(z+1)) / u_ii, step t at x = T-1-t - y - z
         prev = (VT)0;
         const int lob = rowok ? T - ex - y - z : (1 << 28);
         const int cbb = cb + T - 1;
         for (int t0 = 0; t0 < T; t0 += RB) {
-            VT co[RB][NLP], rin[RB], dg[RB];
+            if (MULTI && w < W - 1) wait_for(&prog[1][w + 1], min(t0 + RB, T));
+            VT co[RB][NLP], rin[RB], dg[RB], rz[RB];
             int cc[RB];
             bool aa[RB];
 #pragma unroll
@@ -1360,10 +1389,13 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
                 load_run<FT, VT, NLP>(cf + (size_t)cc[u] * NSP + NLP, co[u]);
                 rin[u] = rv[cc[u]];
                 dg[u] = (VT)id[cc[u]];
+                if (MULTI) rz[u] = rv[min(cc[u] + exy, n - 1)];
             }
 #pragma unroll
             for (int u = 0; u < RB; ++u) {
-                const VT yn = lane_shl(prev), zn = lane_from(prev, pz_b);
+                const VT yn = lane_shl(prev);
+                VT zn = lane_from(prev, pz_b);
+                if (MULTI) zn = zlast ? rz[u] : zn;
                 VT v = rin[u];
                 v -= co[u][0] * prev;
                 v -= co[u][1] * yn;
@@ -1371,6 +1403,7 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
                 prev = aa[u] ? v * dg[u] : (VT)0;
                 rv[aa[u] ? cc[u] : n] = prev;
             }
+            if (MULTI) __hip_atomic_store(&prog[1][w], t0 + RB, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
     __syncthreads();
@@ -1987,7 +2020,7 @@ static void launch_rows3d(Ras &M, Level &V, const double *r, double *z, const in
     a.variant = M.d.variant;
     a.accumulate = accumulate ? 1 : 0;
     const size_t sh = rows3d_lds(M.d.precision, V.max_next);
-    void (*fn)(Rows3Args) = k_ras_rows3d<FT, VT, DT>;
+    void (*fn)(Rows3Args) = V.rows3d_multi ? k_ras_rows3d<FT, VT, DT, true> : k_ras_rows3d<FT, VT, DT, false>;
     set_lds((const void *)fn, sh);
     launch_timed("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(256), sh, M.g->s, a);
     KCHECK();

@@ -90,6 +90,10 @@ ONE_LEVEL = [
     dict(nx=11, ny=9, nz=8, px=2, py=2, pz=3, overlap=(1,), gravity=True),
     dict(nx=8, ny=8, nz=1, px=8, py=8, overlap=(0,)),     # one cell per box
     dict(nx=20, ny=7, nz=1, px=1, py=1, overlap=(1,)),    # one subdomain
+    # 3D boxes of more than 64 (y, z) rows: swept in slabs of z planes,
+    # one wavefront each (9x9x9 extended boxes: two slabs; 8x7x31: four)
+    dict(nx=16, ny=16, nz=16, px=2, py=2, pz=2, overlap=(1,), gravity=True),
+    dict(nx=14, ny=12, nz=60, px=2, py=2, pz=2, overlap=(1,)),
 ]
 
 
@@ -116,8 +120,9 @@ def test_one_level_apply_parity(nks, orc, cfg, variant):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 5e-2)])
-def test_mixed_precision_apply_error(nks, orc, prec, tol):
-    cfg = dict(nx=12, ny=10, nz=8, px=2, py=2, pz=2, overlap=(1,), gravity=True)
+@pytest.mark.parametrize("cfg", [dict(nx=12, ny=10, nz=8, px=2, py=2, pz=2, overlap=(1,), gravity=True),
+                                 dict(nx=16, ny=16, nz=16, px=2, py=2, pz=2, overlap=(1,), gravity=True)])
+def test_mixed_precision_apply_error(nks, orc, prec, tol, cfg):
     case = S.small_case(precision=prec, **cfg)
     case64 = S.small_case(**cfg)
     rec = case.problems[0]
