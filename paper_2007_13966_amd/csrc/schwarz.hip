@@ -1111,11 +1111,16 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
 #pragma unroll
             for (int u = 0; u < RB; ++u) rv[aa[u] ? cc[u] : n] = outv[u];
         };
+        // the scheduling barriers keep each block's reads ahead of the
+        // previous block's arithmetic (the scheduler would otherwise sink
+        // them next to their first use)
         load(0, coA, rinA, ccA, aaA);
         for (int t0 = 0; t0 < T; t0 += RU) {
             load(t0 + RB, coB, rinB, ccB, aaB);
+            __builtin_amdgcn_sched_barrier(0);
             step(0, coA, rinA, ccA, aaA);
             load(t0 + RU, coA, rinA, ccA, aaA);
+            __builtin_amdgcn_sched_barrier(0);
             step(RB, coB, rinB, ccB, aaB);
         }
     } else if (wid > 0) {
@@ -1200,8 +1205,10 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
         load(0, coA, rinA, dgA, ccA, aaA);
         for (int t0 = 0; t0 < T; t0 += RU) {
             load(t0 + RB, coB, rinB, dgB, ccB, aaB);
+            __builtin_amdgcn_sched_barrier(0);
             step(0, coA, rinA, dgA, ccA, aaA);
             load(t0 + RU, coA, rinA, dgA, ccA, aaA);
+            __builtin_amdgcn_sched_barrier(0);
             step(RB, coB, rinB, dgB, ccB, aaB);
         }
     }
