@@ -94,6 +94,8 @@ ONE_LEVEL = [
     # one wavefront each (9x9x9 extended boxes: two slabs; 8x7x31: four)
     dict(nx=16, ny=16, nz=16, px=2, py=2, pz=2, overlap=(1,), gravity=True),
     dict(nx=14, ny=12, nz=60, px=2, py=2, pz=2, overlap=(1,)),
+    dict(nx=4, ny=4, nz=4, px=4, py=4, pz=4, overlap=(0,)),   # one cell per 3D box
+    dict(nx=3, ny=12, nz=14, px=3, py=1, pz=1, overlap=(0,)),  # rows of one cell, three slabs
 ]
 
 
