@@ -36,8 +36,8 @@ WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128
 PMC_TRAFFIC = {
     "workload": "2d_512x512_twolevel_fp64",
     "source": "paper_2007_13966_amd/csrc/schwarz.hip",
-    "sha1": "692ead36faecac2a689b6531403372455cce9aae",
-    "fetch_kib": 8852.2, "fetch_scale": 2.0,
+    "sha1": "56b0414e5388746bfb95c1147ba3ea52510b10d3",
+    "fetch_kib": 8853.2, "fetch_scale": 2.0,
     "write_kib": 2048.0, "write_scale": 1.0,
 }
 
@@ -121,6 +121,25 @@ def level_bytes(P, case, s, level):
         nb = boxes(rec, s)
         ne += ext_cells(d[0], d[1], d[2], *nb, s.overlap[min(level, len(s.overlap) - 1)])
     return ne * ((K - 1) * 8 + 8 + 8) + n * 8, K
+
+
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """Device-to-device copy bandwidth (bytes read + written per second):
+    the attainable HBM rate on this GPU, beside the published peak."""
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del x, y
+    return 2 * 8 * n / sec / 1e9
 
 
 ROOFLINE_RECORDS = ["ras_apply_l0", "ras_apply_l1"]
@@ -317,6 +336,8 @@ def main():
             "avg_launch_us": avg_s * 1e6,
         },
         "roofline_coarse": None,
+        "roofline_spmv": None,
+        "stream_copy_gbs": None,
         # launches outside captured graphs, over 2 profiled steps after the timed ones
         "kernels_ms": {k: {"count": int(v.size), "total_ms": round(float(v.sum()), 3),
                            "avg_us": round(1e3 * float(v.mean()), 2)}
@@ -334,6 +355,20 @@ def main():
             "frac": (ca / HBM_PEAK_GBS) if ca else None, "bytes_per_launch": cb,
             "launches": int(cl.size), "avg_launch_us": float(cl.mean()) * 1e3 if cl.size else None,
         }
+    sp = r64["breakdown"].get("spmv_l0", np.zeros(0))
+    if sp.size and all(r.nz == 1 for r in case.problems):
+        # 2D: the 5-point launches are the fine level's residuals r = b - A x
+        # (the coarse operators have more points); per cell 5 coefficients,
+        # x, b and r
+        nb = sum(r.N for r in case.problems) * (5 * 8 + 24)
+        ga = nb / (float(sp.mean()) / 1e3) / 1e9
+        out["roofline_spmv"] = {
+            "kernel": "k_spmv<8> (fine-level residual b - A x, 5-point, FP64), 2 profiled steps",
+            "bound": "hbm", "achieved": ga, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ga / HBM_PEAK_GBS,
+            "bytes_per_launch": nb, "launches": int(sp.size), "avg_launch_us": float(sp.mean()) * 1e3,
+        }
+    out["stream_copy_gbs"] = copy_bandwidth(torch)
+    log(f"device copy: {out['stream_copy_gbs']:.0f} GB/s")
     if not args.no_mixed:
         s32 = S.with_solver(case, precision="fp32").solver
         b32, _ = apply_bytes(case.problems, s32, "fp32")
