@@ -71,8 +71,9 @@ struct Level {
     // 2D levels use the register-wavefront sweep: factors stored in
     // lexicographic order, stencil mapped onto a row template
     bool rows2d = false;
-    // 3D levels with the 7-point stencil and at most 64 (y, z) rows per box use
-    // the one-wavefront 3D sweep; factors stored in lexicographic order
+    // 3D levels with the 7-point stencil, rows of at most 64 cells and at most
+    // four slabs of at most 64 (y, z) rows per box use the 3D row sweep;
+    // factors stored in lexicographic order
     bool rows3d = false;
     bool rows3d_multi = false;   // more than 64 (y, z) rows: slabs of z planes, one wavefront each
     std::vector<int> hkmap3;     // 3D sweep: lower (z, y, x) and upper (x, y, z) slots -> stencil index

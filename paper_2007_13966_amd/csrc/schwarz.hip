@@ -1244,7 +1244,7 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
     }
 }
 
-// ---------------------------------------------------------------- kernel: 3D one-wavefront sweep
+// ---------------------------------------------------------------- kernel: 3D row sweep
 // 3D boxes with the 7-point stencil and rows of at most 64 cells: lane
 // r = y + ey*z owns row (y, z) (boxes of more than 64 rows are split into
 // slabs of z planes, one wavefront each), and step t handles x = t - y - z, so the
@@ -1988,7 +1988,7 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     }
 }
 
-// LDS of the 3D one-wavefront sweep for boxes of n cells: rv[n + 1], the
+// LDS of the 3D row sweep for boxes of n cells: rv[n + 1], the
 // padded lower and upper runs, 1/u_ii
 static size_t rows3d_lds(int precision, size_t n) {
     const size_t ft = precision == NKS_FP64 ? 8 : (precision == NKS_FP32 ? 4 : 2);
@@ -1997,7 +1997,7 @@ static size_t rows3d_lds(int precision, size_t n) {
     return al16(vt * (n + 1)) + al16(ft * 2 * nlp * n) + al16(dt * n);
 }
 
-// whether a level runs the 3D one-wavefront sweep (its factors are then
+// whether a level runs the 3D row sweep (its factors are then
 // stored in lexicographic order)
 static bool use_rows3d(const Ras &M, const Level &V) {
     return V.rows3d && V.max_next < (1 << 16) && rows3d_lds(M.d.precision, V.max_next) <= (size_t)M.lds_bytes;
