@@ -217,9 +217,14 @@ def test_multilevel_many_coarse_boxes_parity(nks, orc):
     assert np.max(np.abs(zg - zo)) <= 1e-9 * np.max(np.abs(zo))
 
 
-def test_three_level_3d_apply_parity(nks, orc):
-    cfg = dict(nx=16, ny=16, nz=8, px=2, py=2, pz=2, levels=3, overlap=(1, 1, 1), gravity=True,
-               coarse_rtol=0.0, coarse_maxit=4, kv_ratio=0.1)
+@pytest.mark.parametrize("cfg", [
+    dict(nx=16, ny=16, nz=8, px=2, py=2, pz=2, levels=3, overlap=(1, 1, 1)),
+    # fine boxes of 17^3 extended cells (hyperplane kernel), coarse boxes of
+    # 9^3 (the row sweep in two slabs of z planes)
+    dict(nx=32, ny=32, nz=32, px=2, py=2, pz=2, levels=2, overlap=(1, 1)),
+])
+def test_multilevel_3d_apply_parity(nks, orc, cfg):
+    cfg = dict(cfg, gravity=True, coarse_rtol=0.0, coarse_maxit=4, kv_ratio=0.1)
     case = S.small_case(**cfg)
     rec = case.problems[0]
     op = orc.Problem(rec)
