@@ -1525,21 +1525,32 @@ __global__ void __launch_bounds__(256) k_ilu_rows(IluRowsArgs a) {
             double r[NS + 1];
 #pragma unroll
             for (int q = 0; q <= NS; ++q) r[q] = Wr[(size_t)c * RL + q];
+            // every value of the lower neighbours' rows that the elimination
+            // uses is read before the first product (one LDS wait per step);
+            // branch-free: every read has a valid (clamped) address
+            double ip[NL], ur[NL][NS - NL];
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                const int ck = min(max(c + S::DX[q] + S::DY[q] * ex, 0), n - 1);
+                ip[q] = Wr[(size_t)ck * RL + NS + 1];
+#pragma unroll
+                for (int p = NL; p < NS; ++p)
+                    ur[q][p - NL] = row_slot<BOX>(S::DX[q] + S::DX[p], S::DY[q] + S::DY[p]) >= 0
+                                        ? Wr[(size_t)ck * RL + p] : 0.0;
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int q = 0; q < NL; ++q) {
                 const int xk = x + S::DX[q];
                 const bool in = act && ((pm >> q) & 1u) && xk >= 0 && xk < ex && y + S::DY[q] >= 0;
-                // branch-free: every read has a valid (clamped) address and
                 // an absent neighbour's l is cleared bitwise
-                const int ck = min(max(c + S::DX[q] + S::DY[q] * ex, 0), n - 1);
-                const double l = __longlong_as_double(__double_as_longlong(r[q] * Wr[(size_t)ck * RL + NS + 1]) &
-                                                      (in ? ~0ll : 0ll));
+                const double l = __longlong_as_double(__double_as_longlong(r[q] * ip[q]) & (in ? ~0ll : 0ll));
                 r[q] = l;
 #pragma unroll
                 for (int p = NL; p < NS; ++p) {
                     const int tg = row_slot<BOX>(S::DX[q] + S::DX[p], S::DY[q] + S::DY[p]);
                     if (tg < 0) continue;
-                    r[tg] -= l * Wr[(size_t)ck * RL + p];
+                    r[tg] -= l * ur[q][p - NL];
                 }
             }
             const double u = r[NS];
