@@ -522,13 +522,13 @@ __global__ void k_ilu_factor(FacArgs a) {
 // inverse map, the level pointers and the elimination tables are staged
 // once; the hyperplanes are eliminated in place and the factors written back.
 // MAXL / MAXQ bound the lower stencil entries and the updates per lower entry
-// (5-point cross: 2 / 1; 5x5 box: 12 / 12).  The row loop is branch-free: a
+// (5-point cross: 2 / 1; 7-point: 3 / 3; 5x5 box: 12 / 12).  The row loop is branch-free: a
 // lower neighbour's index and pivot are read up front (earlier hyperplanes
 // are final), and the update lists are padded by repeating their last entry,
 // which rewrites the same value.
 // LDS: K*max_next doubles, then ints: tile + (nlev+1) + K + (K+1) + 2*nupd + next.
 template <int MAXL, int MAXQ>
-__global__ void __launch_bounds__(64) k_ilu_factor_lds(FacArgs a, int max_next, int tile, int nupd) {
+__global__ void __launch_bounds__(256) k_ilu_factor_lds(FacArgs a, int max_next, int tile, int nupd) {
     extern __shared__ double smem_f[];
     const SubDev sd = a.sub[blockIdx.x];
     const Blk bk = a.blk[sd.blk];
@@ -1914,19 +1914,24 @@ void Ras::factor() {
                                              2 * (size_t)V.nupd + V.max_next);
         void (*flds)(FacArgs, int, int, int) = nullptr;
         if (fa.diag <= 2 && V.max_upd <= 1) flds = k_ilu_factor_lds<2, 1>;
+        else if (fa.diag <= 3 && V.max_upd <= 3) flds = k_ilu_factor_lds<3, 3>;
         else if (fa.diag <= 12 && V.max_upd <= 12) flds = k_ilu_factor_lds<12, 12>;
         if (flds && sh_lds <= (size_t)lds_bytes) {
             // the whole box fits in LDS (2D): fill and eliminate there
             set_lds((const void *)flds, sh_lds);
-            launch_timed("ilu_factor", l, flds, dim3(V.nsub), dim3(bs), sh_lds, s, fa, V.max_next, V.max_tile,
+            // enough rows in flight for the widest hyperplane and for staging the box
+            const int bsl = V.max_lvl <= 64 && V.max_next <= 512 ? 64 : 256;
+            launch_timed("ilu_factor", l, flds, dim3(V.nsub), dim3(bsl), sh_lds, s, fa, V.max_next, V.max_tile,
                          V.nupd);
             KCHECK();
         } else {
             k_ilu_fill<<<V.nsub, 256, 0, s>>>(fa);
             KCHECK();
-            const size_t sh = (size_t)bs * fa.K * sizeof(double) + sizeof(int) * (size_t)(V.max_nlev + 1);
+            // enough rows in flight for the widest hyperplane, up to 256
+            const int bsg = V.max_lvl <= 64 ? 64 : (V.max_lvl <= 128 ? 128 : 256);
+            const size_t sh = (size_t)bsg * fa.K * sizeof(double) + sizeof(int) * (size_t)(V.max_nlev + 1);
             set_lds((const void *)k_ilu_factor, sh);
-            launch_timed("ilu_factor", l, k_ilu_factor, dim3(V.nsub), dim3(bs), sh, s, fa);
+            launch_timed("ilu_factor", l, k_ilu_factor, dim3(V.nsub), dim3(bsg), sh, s, fa);
             KCHECK();
         }
         }
