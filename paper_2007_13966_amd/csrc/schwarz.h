@@ -111,6 +111,7 @@ struct Ras {
     std::vector<TileDims> tiles_;
     Gmres coarse;
     int lds_bytes = 65536;
+    int n_cu = 1;                // compute units of the device
     int graph_chunk = 4;         // coarse GMRES iterations per captured graph (0: plain launches)
     int coarse_its_last = 0;
     long coarse_its_total = 0;

@@ -21,6 +21,7 @@
 #include <array>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <set>
 #include <tuple>
 
@@ -984,8 +985,8 @@ __host__ __device__ inline RowsLds rows_lds(size_t vt, size_t ft, size_t dt, int
 // the box repeat the last row), stores of masked steps go to a spare slot,
 // and the stencil map arrives in the kernel arguments.  The upper factors and 1/u_ii are
 // staged by the other wavefronts while the forward sweep runs.
-template <typename FT, typename VT, typename DT, int BOX>
-__global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
+template <typename FT, typename VT, typename DT, int BOX, int NT>
+__global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
     using S = RowStencil<BOX>;
     constexpr int NS = S::NS, NL = S::NL, NU = NS - NL, LB = S::LB;
     constexpr int PER = (int)(16 / sizeof(FT));
@@ -994,10 +995,16 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
     constexpr int CS = row_stride<BOX, FT>();   // LDS stride of a cell's run
     constexpr int RU = rows_unroll(BOX);   // unroll = ring length (>= the deepest history used)
     constexpr int PAD = rows_pad(BOX);
+    // NT = 256: one wavefront sweeps while the other three stage the upper
+    // runs; NT = 64 (launches of many small boxes, several per CU): the one
+    // wavefront stages everything, then sweeps.
+    static_assert(NT == 256 || NT == 64, "one or four wavefronts");
+    constexpr bool ONE = NT == 64;
     // cells per staging thread per pass: a 36x36 cross-stencil box in one
     // pass, so its loads pay the memory latency once
-    constexpr int CPT = BOX == 0 ? 6 : 2;
+    constexpr int CPT = ONE ? 2 : (BOX == 0 ? 6 : 2);
     constexpr int CPU = 2;           // the same for the upper runs (staged during the forward sweep)
+    constexpr int NST = ONE ? NSP : NLP;   // slots staged before the forward sweep
     static_assert(NSP <= 32, "stencil map fits the argument block");
     extern __shared__ __align__(16) unsigned char smem[];
     const SubDev sd = a.sub[blockIdx.x];
@@ -1019,27 +1026,30 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
     // stage: lower runs and R_i^delta r (all threads).  Absent slots and the
     // padding load a valid address and store zero; every load of a pass is
     // issued before its first LDS store.
-    for (int c0 = threadIdx.x; c0 < n; c0 += CPT * 256) {
-        FT v[CPT][NLP];
+    for (int c0 = threadIdx.x; c0 < n; c0 += CPT * NT) {
+        FT v[CPT][NST];
         double rr[CPT];
+        DT dd[CPT];
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
-            const int c = min(c0 + u * 256, n - 1);
+            const int c = min(c0 + u * NT, n - 1);
 #pragma unroll
-            for (int q = 0; q < NLP; ++q) {
+            for (int q = 0; q < NST; ++q) {
                 const int k = a.kmap[q];
                 const FT x = F[(size_t)max(k, 0) * a.NE + fo + c];
                 v[u][q] = k >= 0 ? x : (FT)0;
             }
+            if (ONE) dd[u] = ID[fo + c];
             const int y = row_of(c, inv_ex), x = c - y * ex;
             rr[u] = a.r[(size_t)sd.gorg + x + (size_t)sd.gnx * y];
         }
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
-            const int c = c0 + u * 256;
+            const int c = c0 + u * NT;
             if (c < n) {
 #pragma unroll
-                for (int q = 0; q < NLP; ++q) cf[(size_t)c * CS + q] = v[u][q];
+                for (int q = 0; q < NST; ++q) cf[(size_t)c * CS + q] = v[u][q];
+                if (ONE) id[c] = dd[u];
                 const int y = row_of(c, inv_ex), x = c - y * ex;
                 const bool own = x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1;
                 rv[c] = (VT)((a.variant == NKS_RIGHT_RAS && !own) ? 0.0 : rr[u]);
@@ -1220,12 +1230,12 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
         constexpr int WB = 4;
         const int oxn = sd.lx1 - sd.lx0, no = oxn * (sd.ly1 - sd.ly0);
         const float inv_oxn = 1.0f / (float)oxn;
-        for (int k0 = threadIdx.x; k0 < no; k0 += WB * 256) {
+        for (int k0 = threadIdx.x; k0 < no; k0 += WB * NT) {
             size_t g[WB];
             double v[WB];
 #pragma unroll
             for (int u = 0; u < WB; ++u) {
-                const int k = min(k0 + u * 256, no - 1);
+                const int k = min(k0 + u * NT, no - 1);
                 const int yy = row_of(k, inv_oxn), xx = k - yy * oxn;
                 const int x = sd.lx0 + xx, yb = sd.ly0 + yy;
                 g[u] = (size_t)sd.gorg + x + (size_t)sd.gnx * yb;
@@ -1237,7 +1247,7 @@ __global__ void __launch_bounds__(256) k_ras_rows(RowsArgs a) {
             }
 #pragma unroll
             for (int u = 0; u < WB; ++u)
-                if (k0 + u * 256 < no) a.z[g[u]] = v[u];
+                if (k0 + u * NT < no) a.z[g[u]] = v[u];
         }
     } else {
         for (int c = threadIdx.x; c < n; c += blockDim.x) a.zext[fo + c] = (double)rv[c];
@@ -1850,6 +1860,8 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         maxlds = 65536;
     lds_bytes = std::min(maxlds, 160 * 1024);
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+        n_cu = 1;
 }
 
 static bool use_rows3d(const Ras &M, const Level &V);
@@ -1969,6 +1981,24 @@ static int level_index(const Ras &M, const Level &V) {
     return -1;
 }
 
+// workgroups of a kernel that fit on one CU at once (registers and LDS),
+// cached per kernel and LDS size
+static int rows_occupancy(const void *fn, int threads, size_t sh) {
+    static std::mutex mu;
+    static std::map<std::pair<const void *, size_t>, int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({fn, sh});
+    if (it != cache.end()) return it->second;
+    set_lds(fn, sh);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, sh) != hipSuccess) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    cache[{fn, sh}] = std::max(nb, 1);
+    return std::max(nb, 1);
+}
+
 template <typename FT, typename VT, typename DT>
 static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int *mask, bool accumulate) {
     RowsArgs a{};
@@ -1992,10 +2022,18 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     const size_t sh = rows_lds(sizeof(VT), sizeof(FT), sizeof(DT), NSP, rows_pad(V.box), n).total;
     if (V.max_next >= (1 << 16)) fail(NKS_EINVAL, "2D subdomain of %zu cells exceeds 65535", n);
     if (sh > (size_t)M.lds_bytes) fail(NKS_EINVAL, "2D subdomain of %zu cells does not fit in LDS", n);
-    void (*fn)(RowsArgs) = V.box == 0 ? k_ras_rows<FT, VT, DT, 0>
-                                      : (V.box == 1 ? k_ras_rows<FT, VT, DT, 1> : k_ras_rows<FT, VT, DT, 2>);
+    void (*fn4)(RowsArgs) = V.box == 0 ? k_ras_rows<FT, VT, DT, 0, 256>
+                                       : (V.box == 1 ? k_ras_rows<FT, VT, DT, 1, 256> : k_ras_rows<FT, VT, DT, 2, 256>);
+    void (*fn1)(RowsArgs) = V.box == 0 ? k_ras_rows<FT, VT, DT, 0, 64>
+                                       : (V.box == 1 ? k_ras_rows<FT, VT, DT, 1, 64> : k_ras_rows<FT, VT, DT, 2, 64>);
+    // One-wavefront workgroups when they let at least twice as many boxes
+    // sweep at once on a CU (the four-wavefront form is bound by its idle
+    // staging wavefronts' registers) and the launch has the boxes to use it.
+    const int occ4 = rows_occupancy((const void *)fn4, 256, sh), occ1 = rows_occupancy((const void *)fn1, 64, sh);
+    const bool one = occ1 >= 2 * occ4 && V.nsub > M.n_cu * occ4;
+    void (*fn)(RowsArgs) = one ? fn1 : fn4;
     set_lds((const void *)fn, sh);
-    launch_timed("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(256), sh, M.g->s, a);
+    launch_timed("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(one ? 64 : 256), sh, M.g->s, a);
     KCHECK();
     if (M.d.variant != NKS_LEFT_RAS) {
         k_ras_gather<<<nblk(V.spp->N, 256), 256, 0, M.g->s>>>(V.spp->blk.p, V.spp->B, V.spp->N, V.part.p,
