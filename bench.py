@@ -322,7 +322,7 @@ def main():
         "roofline": {
             "kernel": ("k_ras_apply<double, double, double, 3> (fine level 3D 7-point sweeps: one-level left-RAS, "
                        "ILU(0) factors)" if case.problems[0].nz > 1 else
-                       "k_ras_rows<double, double, double, 0> (fine level 2D sweeps: one-level left-RAS, ILU(0) factors)"),
+                       "k_ras_rows<double, double, double, 0, 256> (fine level 2D sweeps: one-level left-RAS, ILU(0) factors)"),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
