@@ -1905,7 +1905,6 @@ void Ras::factor() {
         fa.off = V.A->st.doff.p;
         fa.w = V.w64.p;
         fa.err = V.err.p;
-        const int bs = 64;
         const int *perm = (V.rows2d || use_rows3d(*this, V)) ? V.lexg.p : nullptr;
         const int rl = V.box == 0 ? RowStencil<0>::NS + 2 : (V.box == 1 ? RowStencil<1>::NS + 2 : RowStencil<2>::NS + 2);
         const size_t sh_rows = sizeof(double) * (size_t)rl * V.max_next;
