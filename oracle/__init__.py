@@ -36,7 +36,8 @@ class MgDesc(C.Structure):
                 ("overlap", C.c_int * 8), ("variant", C.c_int), ("subsolve", C.c_int),
                 ("interp_order", C.c_int), ("cycle", C.c_int), ("mu", C.c_int), ("nu", C.c_int),
                 ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int),
-                ("coarse_restart", C.c_int), ("tx", C.c_int), ("ty", C.c_int), ("tz", C.c_int)]
+                ("coarse_restart", C.c_int), ("tx", C.c_int), ("ty", C.c_int), ("tz", C.c_int),
+                ("fill", C.c_int)]
 
 
 class NewtonDesc(C.Structure):
@@ -256,6 +257,7 @@ def mg_desc(s):
     d.coarse_maxit = s.coarse_maxit
     d.coarse_restart = s.coarse_restart
     d.tx, d.ty, d.tz = s.tile
+    d.fill = s.fill
     return d
 
 

@@ -30,6 +30,8 @@
  */
 #include "nks_oracle.h"
 
+#include <limits.h>
+#include <stdio.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -662,6 +664,71 @@ void orc_ilu0(int n, const int *rp, const int *ci, double *v) {
     free(pos); free(dg);
 }
 
+/* Level-of-fill pattern of ILU(k) (Section 3.1's subdomain solver with k
+ * levels of fill): an original entry has level 0; eliminating row k < i from
+ * row i gives entry (i, j), j > k, the level lev(i,k) + lev(k,j) + 1, kept
+ * (as the minimum over k) when it is at most k_fill.  Rows are processed in
+ * order and the lower entries of a row in increasing column order, so every
+ * level used is final.  a is replaced by the expanded matrix: its own values,
+ * zero at the fill positions, columns sorted.  ILU(0) on that pattern is
+ * ILU(k). */
+static void iluk_pattern(csr *a, int kfill) {
+    const int n = a->n;
+    int *lev = (int *)xcalloc(n, sizeof(int));
+    double *val = (double *)xcalloc(n, sizeof(double));
+    int *touched = (int *)xcalloc(n, sizeof(int));
+    for (int j = 0; j < n; ++j) lev[j] = INT_MAX;
+    int cap = a->rp[n] * 2 + 16, nnz = 0;
+    int *rp = (int *)xcalloc(n + 1, sizeof(int));
+    int *ci = (int *)xcalloc(cap, sizeof(int));
+    int *lv = (int *)xcalloc(cap, sizeof(int));
+    double *v = (double *)xcalloc(cap, sizeof(double));
+    for (int i = 0; i < n; ++i) {
+        int nt = 0;
+        for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) {
+            lev[a->ci[k]] = 0;
+            val[a->ci[k]] = a->v[k];
+            touched[nt++] = a->ci[k];
+        }
+        for (int k = 0; k < i; ++k) {
+            if (lev[k] > kfill) continue;
+            for (int q = rp[k]; q < rp[k + 1]; ++q) {
+                const int j = ci[q];
+                if (j <= k) continue;
+                const int l = lev[k] + lv[q] + 1;
+                if (l <= kfill && l < lev[j]) {
+                    if (lev[j] == INT_MAX) touched[nt++] = j;
+                    lev[j] = l;
+                }
+            }
+        }
+        /* row i in increasing column order */
+        for (int j = 0; j < n; ++j) {
+            if (lev[j] > kfill) continue;
+            if (nnz == cap) {
+                cap *= 2;
+                ci = (int *)realloc(ci, (size_t)cap * sizeof(int));
+                lv = (int *)realloc(lv, (size_t)cap * sizeof(int));
+                v = (double *)realloc(v, (size_t)cap * sizeof(double));
+                if (!ci || !lv || !v) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+            }
+            ci[nnz] = j;
+            lv[nnz] = lev[j];
+            v[nnz++] = val[j];
+        }
+        rp[i + 1] = nnz;
+        for (int t = 0; t < nt; ++t) {
+            lev[touched[t]] = INT_MAX;
+            val[touched[t]] = 0.0;
+        }
+    }
+    free(a->rp); free(a->ci); free(a->v);
+    a->rp = rp;
+    a->ci = ci;
+    a->v = v;
+    free(lv); free(lev); free(val); free(touched);
+}
+
 /* Solve (L U) z = r with the factors of orc_ilu0 */
 void orc_ilu0_solve(int n, const int *rp, const int *ci, const double *v, const double *r, double *z) {
     for (int i = 0; i < n; ++i) {
@@ -842,6 +909,7 @@ static void factor_subdomains(level *lv, const orc_mg_desc *d) {
                     s->lu[(size_t)r * s->next + s->a.ci[k]] = s->a.v[k];
             dense_lu(s->next, s->lu, s->piv);
         } else {
+            if (d->fill > 0) iluk_pattern(&s->a, d->fill);
             orc_ilu0(s->next, s->a.rp, s->a.ci, s->a.v);
         }
         for (int c = 0; c < s->next; ++c) map[s->cells[c]] = -1;

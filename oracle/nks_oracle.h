@@ -33,6 +33,7 @@ typedef struct {
     int coarse_maxit;
     int coarse_restart;
     int tx, ty, tz;         /* > 0: box edge in cells on the finest level (boxes = ceil(n/t)) */
+    int fill;               /* subdomain ILU level of fill k (0: ILU(0)): ILU on the level-k pattern */
 } orc_mg_desc;
 
 typedef struct {

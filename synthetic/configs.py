@@ -78,6 +78,7 @@ class SolverSettings:
     cycle: str = "vcycle"                # vcycle | left_kaskade | right_kaskade | additive | coarse_only
     variant: str = "left_ras"            # left_ras | as | right_ras
     subsolve: str = "ilu0"               # ilu0 | lu (oracle only)
+    fill: int = 0                        # subdomain ILU level of fill k: ILU(k) (0: ILU(0))
     mu: int = 1
     nu: int = 1
     coarse_rtol: float = 0.2
