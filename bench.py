@@ -232,6 +232,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--fill", type=int, default=0, choices=[0, 1, 2],
+                    help="subdomain ILU level of fill k: ILU(k) instead of ILU(0)")
     ap.add_argument("--interp-order", type=int, default=0, choices=[0, 1, 2, 3],
                     help="interpolation order between levels (0: the workload's own)")
     ap.add_argument("--autotune", action="store_true",
@@ -264,6 +266,8 @@ def main():
     case = getattr(S, WORKLOADS[args.workload])()
     if args.interp_order:
         case = S.with_solver(case, interp_order=args.interp_order)
+    if args.fill:
+        case = S.with_solver(case, fill=args.fill)
     tuning = None
     if args.autotune:
         g0 = P.Grid(case.problems)
@@ -310,6 +314,7 @@ def main():
             "reservoirs": len(case.problems),
             "levels": s64.levels,
             "interp_order": s64.interp_order,
+            "ilu_fill": s64.fill,
             "subdomains": int(sum(np.prod(boxes(r, s64)) for r in case.problems)),
             "overlap": list(s64.overlap), "precision": s64.precision,
             "newton_its_per_step": float(np.mean(nits)),

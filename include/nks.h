@@ -156,6 +156,11 @@ typedef struct {
     int precision;               /* NKS_FP64 | NKS_FP32 | NKS_BF16 */
     int tx, ty, tz;              /* > 0: box edge in cells on the finest level, so each
                                     reservoir gets ceil(n/t) boxes in that direction */
+    int fill;                    /* subdomain ILU level of fill k, 0..4 (0: ILU(0)): ILU on
+                                    the level-k pattern of the stencil on an unbounded grid,
+                                    restricted to the box (an entry's level is the least number
+                                    of interior vertices on a path to it through smaller
+                                    cells); k > 0 runs the hyperplane kernels */
 } nks_ras_desc;
 
 /* Creates (*inout == NULL) or refactors in place (*inout from an earlier

@@ -83,6 +83,7 @@ def ras_desc(s):
     d.coarse_restart = s.coarse_restart
     d.precision = PRECISIONS[s.precision]
     d.tx, d.ty, d.tz = s.tile
+    d.fill = getattr(s, "fill", 0)
     return d
 
 

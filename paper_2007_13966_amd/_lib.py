@@ -45,7 +45,7 @@ class nks_ras_desc(C.Structure):
                 ("cycle", C.c_int), ("mu", C.c_int), ("nu", C.c_int),
                 ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int),
                 ("coarse_restart", C.c_int), ("precision", C.c_int),
-                ("tx", C.c_int), ("ty", C.c_int), ("tz", C.c_int)]
+                ("tx", C.c_int), ("ty", C.c_int), ("tz", C.c_int), ("fill", C.c_int)]
 
 
 class nks_gmres_desc(C.Structure):

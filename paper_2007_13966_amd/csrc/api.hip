@@ -641,7 +641,8 @@ static void check_ras_desc(const nks_ras_desc *d) {
         if (d->overlap[std::min(l, 7)] < 0) fail(NKS_EINVAL, "negative overlap");
     if (d->variant < 0 || d->variant > 2 || d->interp_order < 1 || d->interp_order > 3 || d->cycle < 0 ||
         d->cycle > 4 || d->mu < 0 || d->nu < 0 || d->precision < 0 || d->precision > 2 ||
-        d->coarse_restart < 1 || d->coarse_maxit < 1 || d->tx < 0 || d->ty < 0 || d->tz < 0)
+        d->coarse_restart < 1 || d->coarse_maxit < 1 || d->tx < 0 || d->ty < 0 || d->tz < 0 || d->fill < 0 ||
+        d->fill > 4)
         fail(NKS_EINVAL, "bad preconditioner option");
 }
 

@@ -46,6 +46,8 @@ struct Level {
     Space *spp = nullptr;        // the space in use (fine level: the grid's)
     Op own;                      // coarse-level operator (Galerkin product)
     Op *A = nullptr;             // operator in use (fine level: the Jacobian)
+    Stencil fst;                 // factor stencil: the operator's offsets plus ILU(k) fill
+    DBuf<int> amap;              // factor stencil entry -> operator stencil entry (-1: fill)
     int delta = 1;
     int lb = 1, lc = 1;          // wavefront level function t = x + lb*y + lc*z
     int R = 1;                   // padding of the LDS tile (stencil reach)

@@ -136,7 +136,10 @@ static void wavefront(const Stencil &st, int &lb, int &lc) {
 static void build_partition(Level &L, const std::vector<std::array<int, 3>> &boxes, int delta, Alloc *al,
                             hipStream_t s, TileDims &geo) {
     const Space &S = *L.spp;
-    const Stencil &st = L.A->st;
+    const Stencil &st = L.fst;
+    // the register sweeps and their factorisations hold the operator's
+    // pattern only: with ILU(k) fill the hyperplane kernels run
+    const bool nofill = L.fst.K == L.A->st.K;
     wavefront(st, L.lb, L.lc);
     int R = 0, Rz = 0;
     for (int k = 0; k < st.K; ++k) {
@@ -246,7 +249,7 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
     L.lexg.upload(al, lexg, s);
     // 2D register-wavefront eligibility: rows fit one wavefront, reach <= 2
     L.rows2d = false;
-    if (Rz == 0 && mey <= 64 && R <= 2) {
+    if (nofill && Rz == 0 && mey <= 64 && R <= 2) {
         std::vector<int> slot(25, -1);
         bool cross = st.K == 5;
         for (int k = 0; k < st.K; ++k) {
@@ -270,7 +273,7 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
     // slabs of z planes with at most 64 (y, z) rows each
     L.rows3d = false;
     const int pzmin = 64 / std::max(mey, 1);
-    if (Rz == 1 && R == 1 && st.K == 7 && mey <= 64 && mex <= 64 && (mez + pzmin - 1) / pzmin <= 4) {
+    if (nofill && Rz == 1 && R == 1 && st.K == 7 && mey <= 64 && mex <= 64 && (mez + pzmin - 1) / pzmin <= 4) {
         bool cross = true;
         for (int k = 0; k < st.K; ++k)
             if (std::abs(st.off[3 * k]) + std::abs(st.off[3 * k + 1]) + std::abs(st.off[3 * k + 2]) > 1) cross = false;
@@ -455,13 +458,59 @@ static void set_stencil(Stencil &st, std::vector<std::tuple<int, int, int>> offs
     st.doff.upload(al, st.off, s);
 }
 
+// Factor stencil of ILU(k): the level-of-fill pattern of a row on an
+// unbounded grid, where every row has the same pattern.  Eliminating the
+// lower entry a (level la) of a row with the upper entry b (level lb) of
+// row i+a gives the entry a+b the level la + lb + 1; the levels are iterated
+// to their fixed point and the entries of level <= fill kept.  On a box the
+// pattern is restricted to the cells inside it.  amap: factor entry ->
+// operator entry, -1 for fill.
+static void factor_stencil(const Stencil &op, int fill, Stencil &fst, std::vector<int> &amap, Alloc *al,
+                           hipStream_t s) {
+    using T3 = std::tuple<int, int, int>;
+    auto key = [](const T3 &t) { return std::make_tuple(std::get<2>(t), std::get<1>(t), std::get<0>(t)); };
+    const T3 zero{0, 0, 0};
+    std::map<T3, int> lev;
+    for (int k = 0; k < op.K; ++k) lev[{op.off[3 * k], op.off[3 * k + 1], op.off[3 * k + 2]}] = 0;
+    for (bool changed = fill > 0; changed;) {
+        changed = false;
+        std::vector<std::pair<T3, int>> cur(lev.begin(), lev.end());
+        for (auto &a : cur) {
+            if (!(key(a.first) < key(zero))) continue;   // lower entries
+            for (auto &b : cur) {
+                if (!(key(zero) < key(b.first))) continue;   // upper entries of the neighbour's row
+                const T3 c{std::get<0>(a.first) + std::get<0>(b.first), std::get<1>(a.first) + std::get<1>(b.first),
+                           std::get<2>(a.first) + std::get<2>(b.first)};
+                const int l = a.second + b.second + 1;
+                if (l > fill) continue;
+                auto it = lev.find(c);
+                if (it == lev.end() || it->second > l) {
+                    lev[c] = l;
+                    changed = true;
+                }
+            }
+        }
+        if (lev.size() > (size_t)MAXK) fail(NKS_EINVAL, "ILU(%d) pattern exceeds %d points", fill, MAXK);
+    }
+    std::vector<T3> offs;
+    for (auto &e : lev) offs.push_back(e.first);
+    set_stencil(fst, offs, al, s);
+    amap.assign(fst.K, -1);
+    for (int k = 0; k < fst.K; ++k)
+        for (int q = 0; q < op.K; ++q)
+            if (op.off[3 * q] == fst.off[3 * k] && op.off[3 * q + 1] == fst.off[3 * k + 1] &&
+                op.off[3 * q + 2] == fst.off[3 * k + 2])
+                amap[k] = q;
+}
+
 // ---------------------------------------------------------------- kernels: ILU(0)
 struct FacArgs {
     const SubDev *sub;
     const Blk *blk;
     const int *lvlptr, *loc, *inv, *lexi;
     const int *upd_ptr, *upd_k2, *upd_t, *lin;
-    const double *A;      // K*N operator
+    const double *A;      // operator coefficients, one array of N per operator entry
+    const int *amap;      // factor entry -> operator entry (-1: fill, starts at zero)
     int N, NE, K, diag, PX, PY, R, Rz;
     const int8_t *off;
     double *w;            // K*NE workspace
@@ -479,7 +528,8 @@ __global__ void k_ilu_fill(FacArgs a) {
         for (int k = 0; k < a.K; ++k) {
             const int xx = x + a.off[3 * k], yy = y + a.off[3 * k + 1], zz = z + a.off[3 * k + 2];
             const bool in = xx >= 0 && xx < sd.ex && yy >= 0 && yy < sd.ey && zz >= 0 && zz < sd.ez;
-            a.w[(size_t)k * a.NE + sd.fac_off + e] = in ? a.A[(size_t)k * a.N + g] : 0.0;
+            const int ka = a.amap[k];
+            a.w[(size_t)k * a.NE + sd.fac_off + e] = (in && ka >= 0) ? a.A[(size_t)ka * a.N + g] : 0.0;
         }
     }
 }
@@ -563,7 +613,8 @@ __global__ void __launch_bounds__(256) k_ilu_factor_lds(FacArgs a, int max_next,
                 const int k = min(k0 + u, K - 1);
                 const int xx = x + a.off[3 * k], yy = y + a.off[3 * k + 1], zz = z + a.off[3 * k + 2];
                 const bool in = xx >= 0 && xx < sd.ex && yy >= 0 && yy < sd.ey && zz >= 0 && zz < sd.ez;
-                v[u] = in ? a.A[(size_t)k * a.N + g] : 0.0;
+                const int ka = a.amap[k];
+                v[u] = (in && ka >= 0) ? a.A[(size_t)max(ka, 0) * a.N + g] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
@@ -1835,8 +1886,11 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     for (int l = 0; l < L; ++l) {
         Level &V = *lev[l];
         TileDims geo;
+        std::vector<int> amap;
+        factor_stencil(V.A->st, d.fill, V.fst, amap, al, s);
+        V.amap.upload(al, amap, s);
         build_partition(V, boxes, d.overlap[std::min(l, 7)], al, s, geo);
-        const size_t NE = V.next_total, K = V.A->st.K;
+        const size_t NE = V.next_total, K = V.fst.K;
         V.w64.alloc(al, K * NE);
         if (d.precision == NKS_FP64) {
             V.invd64.alloc(al, NE);
@@ -1896,13 +1950,14 @@ void Ras::factor() {
         fa.A = V.A->coef.p;
         fa.N = V.spp->N;
         fa.NE = V.next_total;
-        fa.K = V.A->st.K;
-        fa.diag = V.A->st.diag;
+        fa.amap = V.amap.p;
+        fa.K = V.fst.K;
+        fa.diag = V.fst.diag;
         fa.PX = td.PX;
         fa.PY = td.PY;
         fa.R = td.R;
         fa.Rz = td.Rz;
-        fa.off = V.A->st.doff.p;
+        fa.off = V.fst.doff.p;
         fa.w = V.w64.p;
         fa.err = V.err.p;
         const int *perm = (V.rows2d || use_rows3d(*this, V)) ? V.lexg.p : nullptr;
@@ -2114,8 +2169,8 @@ static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, 
     else a.F = V.f16.p;
     a.invd = M.d.precision == NKS_FP64 ? (const void *)V.invd64.p : (const void *)V.invd32.p;
     a.NE = V.next_total;
-    a.K = V.A->st.K;
-    a.diag = V.A->st.diag;
+    a.K = V.fst.K;
+    a.diag = V.fst.diag;
     a.PX = td.PX;
     a.PY = td.PY;
     a.PZ = td.PZ;
@@ -2143,7 +2198,7 @@ static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, 
     const bool seven = a.K == 7 && a.diag == 3;
     if (seven)
         for (int k = 0; k < 7; ++k) {
-            const int8_t *o = &V.A->st.off[3 * k];
+            const int8_t *o = &V.fst.off[3 * k];
             a.lin7[k] = o[0] + td.PX * (o[1] + td.PY * o[2]);
         }
     const void *fn = seven ? (const void *)k_ras_apply<FT, VT, DT, 3> : (const void *)k_ras_apply<FT, VT, DT, 0>;
