@@ -137,8 +137,8 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
                             hipStream_t s, TileDims &geo) {
     const Space &S = *L.spp;
     const Stencil &st = L.fst;
-    // the register sweeps and their factorisations hold the operator's
-    // pattern only: with ILU(k) fill the hyperplane kernels run
+    // the 3D register sweep holds the 7-point pattern only: with ILU(k) fill
+    // the hyperplane kernels run there
     const bool nofill = L.fst.K == L.A->st.K;
     wavefront(st, L.lb, L.lc);
     int R = 0, Rz = 0;
@@ -249,7 +249,7 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
     L.lexg.upload(al, lexg, s);
     // 2D register-wavefront eligibility: rows fit one wavefront, reach <= 2
     L.rows2d = false;
-    if (nofill && Rz == 0 && mey <= 64 && R <= 2) {
+    if (Rz == 0 && mey <= 64 && R <= 2) {
         std::vector<int> slot(25, -1);
         bool cross = st.K == 5;
         for (int k = 0; k < st.K; ++k) {
@@ -1505,8 +1505,10 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
     }
 }
 
-// ---------------------------------------------------------------- kernel: 2D ILU(0) wavefront
-// ILU(0) of one 2D box per workgroup on the sweeps' schedule: lane y factors
+// ---------------------------------------------------------------- kernel: 2D ILU wavefront
+// ILU on the factor stencil's pattern (the operator's for ILU(0), with the
+// level-of-fill slots for ILU(k); fill slots start at zero) of one 2D box
+// per workgroup on the sweeps' schedule: lane y factors
 // row y of the box, cell x = t - LB*y at step t, so the row of every lower
 // neighbour was finished at an earlier step (by this lane or by a lane
 // below).  Rows are staged cell-major in LDS in the row template's slot
@@ -1520,9 +1522,10 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
 struct IluRowsArgs {
     const SubDev *sub;
     const Blk *blk;
-    const int *slotmap;   // 25 box slots -> stencil index or -1
+    const int *slotmap;   // 25 box slots -> factor stencil index or -1
+    const int *amap;      // factor stencil index -> operator index (-1: fill, starts at zero)
     const double *A;      // K*N operator
-    int N, NE, diag;
+    int N, NE, diag;      // diag: factor stencil index of the diagonal
     double *w;            // K*NE factors (lexicographic per subdomain)
     int *err;
 };
@@ -1561,7 +1564,7 @@ __global__ void __launch_bounds__(256) k_ilu_rows(IluRowsArgs a) {
 #pragma unroll
         for (int q = 0; q <= NS; ++q) {
             const int dx = q < NS ? S::DX[q] : 0, dy = q < NS ? S::DY[q] : 0;
-            const int k = kmap[q];
+            const int k = kmap[q] >= 0 ? a.amap[kmap[q]] : -1;
             const bool in = k >= 0 && x + dx >= 0 && x + dx < ex && y + dy >= 0 && y + dy < ey;
             const double av = a.A[(size_t)max(k, 0) * a.N + g];
             v[q] = in ? av : 0.0;
@@ -1818,6 +1821,18 @@ static XferArgs xfer_args(Level &F, Level &C, const int *mask) {
     return a;
 }
 
+// LDS of the row sweep over the largest box of a 2D level in the given precision
+template <typename FT, typename VT, typename DT>
+static size_t rows_sweep_lds_t(const Level &V) {
+    const int cs = V.box == 0 ? row_stride<0, FT>() : (V.box == 1 ? row_stride<1, FT>() : row_stride<2, FT>());
+    return rows_lds(sizeof(VT), sizeof(FT), sizeof(DT), cs, rows_pad(V.box), (size_t)V.max_next).total;
+}
+static size_t rows_sweep_lds(const Level &V, int precision) {
+    if (precision == NKS_FP64) return rows_sweep_lds_t<double, double, double>(V);
+    if (precision == NKS_FP32) return rows_sweep_lds_t<float, float, float>(V);
+    return rows_sweep_lds_t<uint16_t, float, float>(V);
+}
+
 void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     J = Jm;
     g = Jm->g;
@@ -1916,6 +1931,10 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     lds_bytes = std::min(maxlds, 160 * 1024);
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
         n_cu = 1;
+    // a 2D level whose boxes do not fit the row sweep's LDS (ILU(k) fill
+    // widens a cell's run) takes the hyperplane kernels
+    for (auto &V : lev)
+        if (V->rows2d && rows_sweep_lds(*V, d.precision) > (size_t)lds_bytes) V->rows2d = false;
 }
 
 static bool use_rows3d(const Ras &M, const Level &V);
@@ -1966,8 +1985,8 @@ void Ras::factor() {
         if (V.rows2d && sh_rows <= (size_t)lds_bytes) {
             // 2D box in LDS, factored on the sweeps' wavefront schedule;
             // factors come out in lexicographic order
-            IluRowsArgs ia{V.sub.p, V.spp->blk.p, V.slotmap.p, V.A->coef.p, V.spp->N, V.next_total,
-                           V.A->st.diag, V.w64.p, V.err.p};
+            IluRowsArgs ia{V.sub.p, V.spp->blk.p, V.slotmap.p, V.amap.p, V.A->coef.p, V.spp->N, V.next_total,
+                           V.fst.diag, V.w64.p, V.err.p};
             void (*fr)(IluRowsArgs) =
                 V.box == 0 ? k_ilu_rows<0> : (V.box == 1 ? k_ilu_rows<1> : k_ilu_rows<2>);
             set_lds((const void *)fr, sh_rows);
