@@ -67,6 +67,8 @@ def lib():
         L.orc_problem_new.argtypes = [C.c_int] * 3 + [C.c_double] * 3 + [_D] * 4 + [C.c_int, _I, _D] + \
             [C.c_double] * 7 + [C.c_int, C.c_double]
         L.orc_problem_free.argtypes = [C.c_void_p]
+        L.orc_problem_set_bc.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double]
+        L.orc_problem_set_bc.restype = C.c_int
         L.orc_pr_params.argtypes = [C.c_double] * 5 + [_D] * 3
         L.orc_acentric_terms.argtypes = [C.c_double, _D, _D]
         L.orc_acentric.argtypes = [C.c_double] * 3
@@ -189,6 +191,9 @@ class Problem:
                                        _d(kx), _d(ky), _d(kz), _d(phi), len(wc), _i(wc), _d(wr),
                                        f.Tc, f.pc, f.omega, f.T, f.W, f.R, f.mu,
                                        1 if rec.gravity else 0, rec.g)
+        for f, (t, v) in enumerate(zip(rec.bc_type, rec.bc_value)):
+            if lib().orc_problem_set_bc(self.h, f, int(t), float(v)) != 0:
+                raise ValueError(f"bad boundary condition on face {f}: type {t}, value {v}")
         self.N = rec.N
 
     def __del__(self):

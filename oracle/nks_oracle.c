@@ -24,7 +24,9 @@
  * ties to the row cell; arithmetic-mean face density; depth h increasing with
  * the z index; linear stop with max{eta_r ||F||, eta_a}; restriction = P^T;
  * Galerkin coarse operators P^T A P; the same subdomain box grid on every
- * level; clamped interpolation at the domain boundary.
+ * level; clamped interpolation at the domain boundary; a Dirichlet face's
+ * state at the face centre, half a cell away; a Neumann face's density from
+ * the cell.
  *
  * No blocking, fusion or reordering beyond what the definitions state.
  */
@@ -56,6 +58,8 @@ struct orc_problem {
     double *wrate;
     double Tc, pc, omega, T, W, R, mu, g;
     double a, b, mpr;   /* PR a(T), b and m(omega) */
+    int bct[6];         /* boundary faces -x,+x,-y,+y,-z,+z: ORC_BC_* (zero: closed) */
+    double bcv[6];      /* p^D (Pa) or q^N (m/s, outward normal) */
 };
 
 orc_problem *orc_problem_new(int nx, int ny, int nz, double dx, double dy, double dz,
@@ -87,6 +91,17 @@ orc_problem *orc_problem_new(int nx, int ny, int nz, double dx, double dy, doubl
     pr->g = gravity ? g : 0.0;
     orc_pr_params(Tc, pc, omega, T, R, &pr->a, &pr->b, &pr->mpr);
     return pr;
+}
+
+/* Boundary condition of one outer face (Section 2: p = p^D on the Dirichlet
+ * part, v.n = q^N on the Neumann part, n the outward normal).  Returns 0, or
+ * -1 for a bad face index or type. */
+int orc_problem_set_bc(orc_problem *pr, int face, int type, double value) {
+    if (face < 0 || face > 5 || type < ORC_BC_CLOSED || type > ORC_BC_NEUMANN) return -1;
+    if (type == ORC_BC_DIRICHLET && !(value > 0.0)) return -1;
+    pr->bct[face] = type;
+    pr->bcv[face] = type == ORC_BC_CLOSED ? 0.0 : value;
+    return 0;
 }
 
 void orc_problem_free(orc_problem *pr) {
@@ -254,6 +269,53 @@ static int neighbours(const orc_problem *pr, const double *tx, const double *ty,
     return c;
 }
 
+/* Outer faces of cell i that carry a boundary condition.  A Dirichlet face
+ * holds the state p^D at the face centre, half a cell from the cell centre:
+ * transmissibility 2 K A / Delta (the one-sided form of the harmonic face
+ * rule), potential difference (p_i - p^D) - rho_avg g (h_i - h_face) with
+ * rho_avg the mean of the cell's and the face state's densities, mobility
+ * from the upwind side.  A Neumann face carries the prescribed outward
+ * Darcy velocity q^N: scaled mass flux m_i q^N A, the density taken from the
+ * cell.  Adds the outward flux to *F, its derivative in p_i to *dF and, if
+ * dlk is given, its derivative in ln K_i (a Dirichlet face's T is linear in
+ * K_i, a Neumann face's flux does not depend on K). */
+static void boundary_faces(const orc_problem *pr, int i, double pi, double *F, double *dF, double *dlk) {
+    int nx = pr->nx, ny = pr->ny, nxy = nx * ny;
+    int x = i % nx, y = (i / nx) % ny, z = i / nxy;
+    double c_rho = pr->W / (pr->R * pr->T);
+    double mi, dmi;
+    pr_m(pr, pi, &mi, &dmi);
+    for (int f = 0; f < 6; ++f) {
+        if (pr->bct[f] == ORC_BC_CLOSED) continue;
+        int on = f == 0 ? x == 0 : f == 1 ? x == nx - 1 : f == 2 ? y == 0 : f == 3 ? y == ny - 1
+                 : f == 4 ? z == 0 : z == pr->nz - 1;
+        if (!on) continue;
+        double area, delta, k, dh = 0.0;
+        if (f < 2) { area = pr->dy * pr->dz; delta = pr->dx; k = pr->kx[i]; }
+        else if (f < 4) { area = pr->dx * pr->dz; delta = pr->dy; k = pr->ky[i]; }
+        else {
+            area = pr->dx * pr->dy; delta = pr->dz; k = pr->kz[i];
+            dh = f == 4 ? 0.5 * pr->dz : -0.5 * pr->dz;   /* h_i - h_face, depth grows with z */
+        }
+        if (pr->bct[f] == ORC_BC_NEUMANN) {
+            *F += mi * pr->bcv[f] * area;
+            *dF += dmi * pr->bcv[f] * area;
+            continue;
+        }
+        double pd = pr->bcv[f], md, dmd;
+        pr_m(pr, pd, &md, &dmd);
+        double T = 2.0 * k * area / delta;
+        double rho_avg = 0.5 * (mi + md) * c_rho;
+        double dphi = (pi - pd) - rho_avg * pr->g * dh;
+        int up_i = dphi >= 0.0;
+        double lam = (up_i ? mi : md) / pr->mu;
+        double dlam = up_i ? dmi / pr->mu : 0.0;
+        *F += T * lam * dphi;
+        *dF += T * (dlam * dphi + lam * (1.0 - 0.5 * dmi * c_rho * pr->g * dh));
+        if (dlk) *dlk += T * lam * dphi;
+    }
+}
+
 /* Accumulation term of BDF1 (the BDF1 scheme of Section 2) or BDF2
  * (the BDF2 scheme of Section 2) in conservative form: returns the bracket
  * multiplying phi V / dt and its derivative with respect to p^{l+1}. */
@@ -302,6 +364,8 @@ void orc_residual(const orc_problem *pr, const double *p, const double *pn, cons
             double lam = (dphi >= 0.0 ? mi : mj) / pr->mu;
             Fi += tf[q] * lam * dphi;
         }
+        double dFb = 0.0;
+        boundary_faces(pr, i, p[i], &Fi, &dFb, NULL);
         F[i] = Fi;
     }
     for (int w = 0; w < pr->nw; ++w)
@@ -347,6 +411,8 @@ int orc_jacobian(const orc_problem *pr, const double *p, const double *pn, const
             diag += tf[q] * (dlam_i * dphi + lam * ddphi_i);
             off[q] = tf[q] * (dlam_j * dphi + lam * ddphi_j);
         }
+        double Fb = 0.0;
+        boundary_faces(pr, i, p[i], &Fb, &diag, NULL);
         /* neighbours come in increasing column order: -z,-y,-x, then diag, +x,+y,+z */
         int q = 0;
         for (; q < cnt && nb[q] < i; ++q) { ci[nnz] = nb[q]; v[nnz++] = off[q]; }
@@ -386,7 +452,8 @@ void orc_hydrostatic(const orc_problem *pr, double p_top, double *p) {
 
 /* (dF/d theta)^T lam with theta_c = ln of a multiplier on all K components of
  * cell c.  Only the face transmissibilities depend on K:
- * dT_ij/d theta_i = T_ij K_j / (K_i + K_j) (same direction component). */
+ * dT_ij/d theta_i = T_ij K_j / (K_i + K_j) (same direction component), and a
+ * Dirichlet boundary face's one-sided T, linear in K_i. */
 void orc_residual_dlogk_t(const orc_problem *pr, const double *p, const double *lam, double *out) {
     int N = pr->N, nx = pr->nx, ny = pr->ny, nz = pr->nz, nxy = nx * ny;
     double *tx = (double *)xcalloc(N, sizeof(double));
@@ -394,7 +461,11 @@ void orc_residual_dlogk_t(const orc_problem *pr, const double *p, const double *
     double *tz = (double *)xcalloc(N, sizeof(double));
     orc_transmissibility(pr, tx, ty, tz);
     double c_rho = pr->W / (pr->R * pr->T);
-    for (int i = 0; i < N; ++i) out[i] = 0.0;
+    for (int i = 0; i < N; ++i) {
+        double Fb = 0.0, dFb = 0.0, dlk = 0.0;
+        boundary_faces(pr, i, p[i], &Fb, &dFb, &dlk);
+        out[i] = lam[i] * dlk;
+    }
     for (int i = 0; i < N; ++i) {
         int x = i % nx, y = (i / nx) % ny, z = i / nxy;
         for (int d = 0; d < 3; ++d) {

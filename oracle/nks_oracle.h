@@ -64,6 +64,11 @@ orc_problem *orc_problem_new(int nx, int ny, int nz, double dx, double dy, doubl
                              double Tc, double pc, double omega, double T, double W,
                              double R, double mu, int gravity, double g);
 void orc_problem_free(orc_problem *pr);
+/* boundary condition types of the outer faces -x,+x,-y,+y,-z,+z */
+#define ORC_BC_CLOSED 0      /* no flow (the default) */
+#define ORC_BC_DIRICHLET 1   /* value: p^D in Pa */
+#define ORC_BC_NEUMANN 2     /* value: q^N = v.n in m/s, n the outward normal */
+int orc_problem_set_bc(orc_problem *pr, int face, int type, double value);
 
 /* PR-EOS */
 void orc_pr_params(double Tc, double pc, double omega, double T, double R,

@@ -54,6 +54,10 @@ class Problem:
     gravity: bool = False
     g: float = 9.80665
     p_init: float = 20e6    # uniform, or top-layer pressure when gravity is on
+    # outer faces -x, +x, -y, +y, -z, +z: 0 closed, 1 Dirichlet (value p^D, Pa),
+    # 2 Neumann (value q^N = v.n, m/s, n the outward normal: inflow < 0)
+    bc_type: Tuple[int, ...] = (0, 0, 0, 0, 0, 0)
+    bc_value: Tuple[float, ...] = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)
 
     @property
     def N(self):
