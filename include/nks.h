@@ -53,10 +53,23 @@ typedef struct {
     double Tc, pc, omega, T, W, R, mu;
 } nks_fluid;
 
+/* Boundary condition types of a reservoir's outer faces (Section 2: p = p^D
+ * on the Dirichlet part of the boundary, v.n = q^N on the Neumann part). */
+#define NKS_BC_CLOSED 0      /* no flow */
+#define NKS_BC_DIRICHLET 1   /* value: p^D in Pa (> 0), the state at the face centre */
+#define NKS_BC_NEUMANN 2     /* value: q^N = v.n in m/s, n the outward normal (inflow < 0) */
+
 /* One reservoir: nx*ny*nz cells of size dx*dy*dz (2D: nz = 1, dz is the
  * thickness).  kx, ky, kz, phi: DEVICE arrays of nx*ny*nz values (diagonal
  * permeability tensor, porosity); read during nks_setup_grid only.
- * Wells: HOST arrays of nwells reservoir-local cell indices and mass rates. */
+ * Wells: HOST arrays of nwells reservoir-local cell indices and mass rates.
+ * bc_type, bc_value: HOST arrays of 6 entries for the outer faces in the
+ * order -x, +x, -y, +y, -z, +z (the -z face is the top: depth grows with z),
+ * each NKS_BC_* with its value; NULL for both: every face closed.  A
+ * Dirichlet face flows through the one-sided transmissibility 2 K A / Delta
+ * of its cells; a Neumann face adds the scaled mass flux m q^N A of each of
+ * its cells, the density taken from the cell.  Read during nks_setup_grid
+ * only; a bad type or a non-positive p^D is NKS_EINVAL. */
 typedef struct {
     int nx, ny, nz;
     double dx, dy, dz;
@@ -64,6 +77,8 @@ typedef struct {
     int nwells;
     const int *well_cell;
     const double *well_rate;
+    const int *bc_type;
+    const double *bc_value;
 } nks_reservoir_desc;
 
 typedef struct {

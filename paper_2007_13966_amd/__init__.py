@@ -148,6 +148,13 @@ class Grid:
             r.nwells = len(wc)
             r.well_cell = wc.ctypes.data_as(C.POINTER(C.c_int))
             r.well_rate = wr.ctypes.data_as(C.POINTER(C.c_double))
+            bt = np.ascontiguousarray(getattr(pr, "bc_type", (0,) * 6), dtype=np.int32)
+            bv = np.ascontiguousarray(getattr(pr, "bc_value", (0.0,) * 6), dtype=np.float64)
+            if bt.size != 6 or bv.size != 6:
+                raise ValueError("bc_type and bc_value need 6 entries (-x, +x, -y, +y, -z, +z)")
+            keep += [bt, bv]
+            r.bc_type = bt.ctypes.data_as(C.POINTER(C.c_int))
+            r.bc_value = bv.ctypes.data_as(C.POINTER(C.c_double))
         fl = problems[0].fluid
         d = L.nks_grid_desc()
         d.nres = len(problems)

@@ -30,7 +30,8 @@ class nks_reservoir_desc(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("kx", C.c_void_p), ("ky", C.c_void_p), ("kz", C.c_void_p), ("phi", C.c_void_p),
                 ("nwells", C.c_int), ("well_cell", C.POINTER(C.c_int)),
-                ("well_rate", C.POINTER(C.c_double))]
+                ("well_rate", C.POINTER(C.c_double)),
+                ("bc_type", C.POINTER(C.c_int)), ("bc_value", C.POINTER(C.c_double))]
 
 
 class nks_grid_desc(C.Structure):

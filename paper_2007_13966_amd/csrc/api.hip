@@ -463,6 +463,30 @@ int nks_setup_grid(const nks_grid_desc *d, nks_grid **out) {
             }
         }
         g.src.upload(&g.al, src, g.s);
+        // outer-face boundary conditions, 6 per reservoir
+        std::vector<int> bct(6 * (size_t)B, NKS_BC_CLOSED);
+        std::vector<double> bcv(6 * (size_t)B, 0.0);
+        bool any_bc = false;
+        for (int b = 0; b < B; ++b) {
+            const nks_reservoir_desc &r = d->res[b];
+            if ((r.bc_type == nullptr) != (r.bc_value == nullptr))
+                fail(NKS_EINVAL, "reservoir %d: bc_type and bc_value must be given together", b);
+            if (!r.bc_type) continue;
+            for (int f = 0; f < 6; ++f) {
+                const int t = r.bc_type[f];
+                const double v = r.bc_value[f];
+                if (t < NKS_BC_CLOSED || t > NKS_BC_NEUMANN) fail(NKS_EINVAL, "reservoir %d face %d: bad type %d", b, f, t);
+                if (t == NKS_BC_DIRICHLET && !(v > 0.0)) fail(NKS_EINVAL, "reservoir %d face %d: p^D must be > 0", b, f);
+                if (t == NKS_BC_NEUMANN && !std::isfinite(v)) fail(NKS_EINVAL, "reservoir %d face %d: bad q^N", b, f);
+                bct[6 * b + f] = t;
+                bcv[6 * b + f] = t == NKS_BC_CLOSED ? 0.0 : v;
+                any_bc = any_bc || t != NKS_BC_CLOSED;
+            }
+        }
+        if (any_bc) {
+            g.bct.upload(&g.al, bct, g.s);
+            g.bcv.upload(&g.al, bcv, g.s);
+        }
         g.m.alloc(&g.al, N);
         g.dm.alloc(&g.al, N);
         g.hist.alloc(&g.al, N);

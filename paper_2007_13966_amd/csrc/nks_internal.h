@@ -140,7 +140,9 @@ struct Grid {
     DBuf<double> tx, ty, tz;             // face to the + neighbour
     DBuf<double> pv;                     // V phi
     DBuf<double> src;                    // well source Q R T / W
-    DBuf<double> kx, ky, kz;             // copies for the dlogK adjoint
+    DBuf<double> kx, ky, kz;             // copies for the dlogK adjoint and boundary faces
+    DBuf<int> bct;                       // 6*B boundary types (-x,+x,-y,+y,-z,+z), empty: all closed
+    DBuf<double> bcv;                    // 6*B boundary values
     double a = 0, b = 0, RT = 0, W = 0, mu = 0, g = 0;
     // scratch
     DBuf<double> m, dm, hist, tmp;

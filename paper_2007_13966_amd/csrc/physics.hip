@@ -154,7 +154,53 @@ struct FluxArgs {
     double cacc, inv_dt, inv_mu, crho_g;   // crho_g = g W/(RT)
     double *F;
     double *J;                             // K*N stencil coefficients or nullptr
+    // outer-face boundary conditions: 6 per block (-x,+x,-y,+y,-z,+z), or nullptr
+    const int *bct;
+    const double *bcv;
+    const double *kx, *ky, *kz;
+    double a, b, RT;                       // PR constants for the Dirichlet face states
 };
+
+// Outer faces of cell i with a boundary condition.  Dirichlet: the face
+// state p^D sits half a cell from the centre, one-sided transmissibility
+// 2 K A / Delta, face density the mean of the cell's and the face state's,
+// mobility from the upwind side; Neumann: scaled mass flux m_i q^N A through
+// the face (q^N along the outward normal).  Adds the outward flux to Fi, its
+// p_i derivative to diag and, for dF/dlnK, the part linear in K_i to dlk.
+__device__ __noinline__ void boundary_faces(const FluxArgs &A, const CellPos &c, int i, double pi, double mi,
+                                            double dmi, double &Fi, double &diag, double &dlk) {
+    const double dx = A.geo[3 * c.b], dy = A.geo[3 * c.b + 1], dz = A.geo[3 * c.b + 2];
+    const bool at[6] = {c.x == 0, c.x + 1 == c.nx, c.y == 0, c.y + 1 == c.ny, c.z == 0, c.z + 1 == c.nz};
+    for (int f = 0; f < 6; ++f) {
+        const int t = A.bct[6 * c.b + f];
+        if (t == 0 || !at[f]) continue;
+        const int ax = f >> 1;
+        const double area = ax == 0 ? dy * dz : (ax == 1 ? dx * dz : dx * dy);
+        const double v = A.bcv[6 * c.b + f];
+        if (t == 2) {
+            Fi += mi * v * area;
+            diag += dmi * v * area;
+            continue;
+        }
+        const double len = ax == 0 ? dx : (ax == 1 ? dy : dz);
+        const double K = ax == 0 ? A.kx[i] : (ax == 1 ? A.ky[i] : A.kz[i]);
+        const double T = 2.0 * K * area / len;
+        const double dh = f == 4 ? 0.5 * dz : (f == 5 ? -0.5 * dz : 0.0);   // h_i - h_face
+        double md, dmd;
+        bool bad;
+        scaled_density(A.a, A.b, A.RT, v, md, dmd, bad);
+        const double dphi = (pi - v) - 0.5 * (mi + md) * A.crho_g * dh;
+        const bool up = dphi >= 0.0;
+        const double lam = (up ? mi : md) * A.inv_mu;
+        Fi += T * lam * dphi;
+        diag += T * ((up ? dmi * A.inv_mu : 0.0) * dphi + lam * (1.0 - 0.5 * dmi * A.crho_g * dh));
+        dlk += T * lam * dphi;
+    }
+}
+
+__device__ __forceinline__ bool on_boundary(const CellPos &c) {
+    return c.x == 0 || c.x + 1 == c.nx || c.y == 0 || c.y + 1 == c.ny || c.z == 0 || c.z + 1 == c.nz;
+}
 
 // One face of cell i: neighbour j, transmissibility T, depth difference
 // h_i - h_j.  Accumulates the flux into Fi and, for the Jacobian, the
@@ -192,6 +238,10 @@ __global__ void k_flux(FluxArgs A) {
     if (c.x + 1 < c.nx) face(A, pi, mi, dmi, i + sx, A.tx[i], 0.0, Fi, diag, o[3]);
     if (c.y + 1 < c.ny) face(A, pi, mi, dmi, i + sy, A.ty[i], 0.0, Fi, diag, o[4]);
     if (A.dim == 3 && c.z + 1 < c.nz) face(A, pi, mi, dmi, i + sz, A.tz[i], -dz, Fi, diag, o[5]);
+    if (A.bct && on_boundary(c)) {
+        double dlk = 0.0;
+        boundary_faces(A, c, i, pi, mi, dmi, Fi, diag, dlk);
+    }
     if (A.F) A.F[i] = Fi - A.src[i];
     if (A.J) {
         const int N = A.N;
@@ -253,7 +303,9 @@ __global__ void k_hydrostatic(const Blk *blk, int B, int ncol_total, const int *
 // ---------------------------------------------------------------- dF/dlnK transpose
 // out_c = sum over faces (c,n): (lam_c - lam_n) * lambda_up dPhi_cn * T K_n/(K_c + K_n),
 // K the component normal to the face (dT/dln K_c = T K_n/(K_c + K_n)); ln K_c
-// scales all three components of cell c together.  accumulate: out += instead of =.
+// scales all three components of cell c together; a Dirichlet boundary face of
+// c adds lam_c times its flux (its one-sided T is linear in K_c).
+// accumulate: out += instead of =.
 __global__ void k_dlogk_t(FluxArgs A, const double *kx, const double *ky, const double *kz,
                           const double *lam, double *out, int accumulate) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -275,6 +327,12 @@ __global__ void k_dlogk_t(FluxArgs A, const double *kx, const double *ky, const 
     if (c.x + 1 < c.nx) term(i + 1, A.tx[i], 0.0, kx[i], kx[i + 1]);
     if (c.y + 1 < c.ny) term(i + sy, A.ty[i], 0.0, ky[i], ky[i + sy]);
     if (A.dim == 3 && c.z + 1 < c.nz) term(i + sz, A.tz[i], -dz, kz[i], kz[i + sz]);
+    if (A.bct && on_boundary(c)) {
+        // a Dirichlet face's transmissibility is linear in K_i
+        double Fb = 0.0, db = 0.0, dlk = 0.0;
+        boundary_faces(A, c, i, pi, mi, A.dm[i], Fb, db, dlk);
+        acc += li * dlk;
+    }
     out[i] = accumulate ? out[i] + acc : acc;
 }
 
@@ -329,6 +387,10 @@ static FluxArgs flux_args(Grid &g, const double *p, double dt, int order, double
     A.crho_g = g.g * g.W / g.RT;
     A.F = F;
     A.J = J;
+    A.bct = g.bct.p;
+    A.bcv = g.bcv.p;
+    A.kx = g.kx.p; A.ky = g.ky.p; A.kz = g.kz.p;
+    A.a = g.a; A.b = g.b; A.RT = g.RT;
     return A;
 }
 

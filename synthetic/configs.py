@@ -123,19 +123,37 @@ def _lin(nx, ny, x, y, z=0):
 
 def small_case(nx=8, ny=8, nz=1, seed=0, sigma=1.0, corr=3.0, gravity=False,
                rate=1e-3, px=2, py=2, pz=1, overlap=(1,), levels=1, dt=DAY,
-               nsteps=2, kv_ratio=1.0, p_init=20e6, kmean_md=100.0, **solver_kw):
+               nsteps=2, kv_ratio=1.0, p_init=20e6, kmean_md=100.0, bc=(), **solver_kw):
     """Small seeded problem for tests: log-normal K around kmean_md, porosity in
-    [0.1, 0.3], injector at the first cell and producer at the last."""
+    [0.1, 0.3], injector at the first cell and producer at the last (rate 0: no
+    wells).  bc: (face, type, value) triples for the outer faces."""
     shape = (nz, ny, nx)
     kh = lognormal_perm(shape, kmean_md * MD, sigma, corr, seed).ravel()
     rng = np.random.Generator(np.random.PCG64(seed + 7919))
     phi = rng.uniform(0.1, 0.3, size=nx * ny * nz)
     N = nx * ny * nz
-    wc, wr = _wells([0, N - 1], [rate, -rate])
+    wc, wr = _wells([0, N - 1], [rate, -rate]) if rate else _wells([], [])
+    bt, bv = [0] * 6, [0.0] * 6
+    for f, t, v in bc:
+        bt[f], bv[f] = t, v
     prob = Problem(nx, ny, nz, 10.0, 10.0, 10.0, kh.copy(), kh.copy(), kv_ratio * kh,
-                   phi, wc, wr, gravity=gravity, p_init=p_init)
+                   phi, wc, wr, gravity=gravity, p_init=p_init, bc_type=tuple(bt), bc_value=tuple(bv))
     s = SolverSettings(px=px, py=py, pz=pz, overlap=tuple(overlap), levels=levels, **solver_kw)
     return Case("small", [prob], dt, nsteps, s)
+
+
+def case_2d_flood(nx=64, ny=64, px=4, py=4, seed=4):
+    """Pressure-driven flood between two Dirichlet faces, the boundary regime
+    of the paper's first 2D test: gas at 1 atm and 298 K, p^D = 10 atm on the
+    -y face and 1 atm on the +y face, the x faces closed, no wells, no
+    gravity; log-normal K (100 mD, sigma 1); steps of 0.06 day.  The first
+    steps are strongly nonlinear (a tenfold pressure rise sweeps the domain)."""
+    case = small_case(nx=nx, ny=ny, nz=1, seed=seed, rate=0.0, px=px, py=py, overlap=(1,),
+                      dt=0.06 * DAY, nsteps=4, p_init=ATM,
+                      bc=((2, 1, 10 * ATM), (3, 1, ATM)))
+    prob = case.problems[0]
+    prob.fluid = replace(prob.fluid, T=298.0)
+    return replace(case, name=f"2d_{nx}x{ny}_flood_dirichlet", description=case_2d_flood.__doc__)
 
 
 def case_2d_32():
