@@ -26,7 +26,7 @@ sys.path.insert(0, HERE)
 METRIC = "time/implicit step + ras_apply GB/s, mixed-prec vs FP64 at rel.res 1e-6"
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128",
-             "batch64": "case_batch64", "3d96": "case_3d_96_adjoint"}
+             "batch64": "case_batch64", "3d96": "case_3d_96_adjoint", "flood512": "case_2d_flood_512"}
 
 # HBM bytes moved per active fine-level launch of the FP64 2D sweep kernel on
 # the 512x512 workload, from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0 and

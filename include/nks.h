@@ -48,9 +48,13 @@ typedef void (*nks_free_fn)(void *ptr, void *ctx);
 
 /* Fluid constants of Section 2: critical temperature Tc and pressure pc,
  * acentric factor omega (m(omega) of the first fit for omega <= 0.491, the
- * second above), temperature T, molar mass W, gas constant R, viscosity mu. */
+ * second above), temperature T, molar mass W, gas constant R, viscosity mu.
+ * Tb > 0 (0 < Tb < Tc): normal boiling point; omega is then computed from it
+ * by the correlation of Section 2 (omega = (-ln(pc / 1 atm) - f0(Tbr)) /
+ * f1(Tbr), Tbr = Tb/Tc) and the omega given is ignored.  Tb = 0: omega used. */
 typedef struct {
     double Tc, pc, omega, T, W, R, mu;
+    double Tb;
 } nks_fluid;
 
 /* Boundary condition types of a reservoir's outer faces (Section 2: p = p^D

@@ -136,7 +136,9 @@ def acentric(pc, Tc, Tb):
 
 def pr_params(fluid):
     a, b, m = C.c_double(), C.c_double(), C.c_double()
-    lib().orc_pr_params(fluid.Tc, fluid.pc, fluid.omega, fluid.T, fluid.R,
+    tb = getattr(fluid, "Tb", None)
+    omega = lib().orc_acentric(fluid.pc, fluid.Tc, tb) if tb else fluid.omega
+    lib().orc_pr_params(fluid.Tc, fluid.pc, omega, fluid.T, fluid.R,
                         C.byref(a), C.byref(b), C.byref(m))
     return a.value, b.value, m.value
 
@@ -187,9 +189,12 @@ class Problem:
         self._keep = [_f64(rec.kx), _f64(rec.ky), _f64(rec.kz), _f64(rec.phi),
                       _i32(rec.well_cells), _f64(rec.well_rates)]
         kx, ky, kz, phi, wc, wr = self._keep
+        # omega from the normal boiling point when the record gives one (Section 2)
+        tb = getattr(f, "Tb", None)
+        omega = lib().orc_acentric(f.pc, f.Tc, tb) if tb else f.omega
         self.h = lib().orc_problem_new(rec.nx, rec.ny, rec.nz, rec.dx, rec.dy, rec.dz,
                                        _d(kx), _d(ky), _d(kz), _d(phi), len(wc), _i(wc), _d(wr),
-                                       f.Tc, f.pc, f.omega, f.T, f.W, f.R, f.mu,
+                                       f.Tc, f.pc, omega, f.T, f.W, f.R, f.mu,
                                        1 if rec.gravity else 0, rec.g)
         for f, (t, v) in enumerate(zip(rec.bc_type, rec.bc_value)):
             if lib().orc_problem_set_bc(self.h, f, int(t), float(v)) != 0:

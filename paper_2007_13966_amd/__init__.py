@@ -159,7 +159,7 @@ class Grid:
         d = L.nks_grid_desc()
         d.nres = len(problems)
         d.res = res
-        d.fluid = L.nks_fluid(fl.Tc, fl.pc, fl.omega, fl.T, fl.W, fl.R, fl.mu)
+        d.fluid = L.nks_fluid(fl.Tc, fl.pc, fl.omega, fl.T, fl.W, fl.R, fl.mu, getattr(fl, "Tb", None) or 0.0)
         d.gravity = 1 if problems[0].gravity else 0
         d.g = problems[0].g
         d.stream = self.stream.cuda_stream

@@ -22,7 +22,7 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 class nks_fluid(C.Structure):
     _fields_ = [("Tc", C.c_double), ("pc", C.c_double), ("omega", C.c_double), ("T", C.c_double),
-                ("W", C.c_double), ("R", C.c_double), ("mu", C.c_double)]
+                ("W", C.c_double), ("R", C.c_double), ("mu", C.c_double), ("Tb", C.c_double)]
 
 
 class nks_reservoir_desc(C.Structure):

@@ -440,8 +440,18 @@ int nks_setup_grid(const nks_grid_desc *d, nks_grid **out) {
         const nks_fluid &f = d->fluid;
         if (!(f.T > 0) || !(f.Tc > 0) || !(f.pc > 0) || !(f.R > 0) || !(f.W > 0) || !(f.mu > 0))
             fail(NKS_EINVAL, "bad fluid constants");
+        // acentric factor from the normal boiling point (Section 2's
+        // correlation in the reduced boiling temperature) when Tb is given
+        double w = f.omega;
+        if (f.Tb != 0.0) {
+            if (!(f.Tb > 0.0) || !(f.Tb < f.Tc)) fail(NKS_EINVAL, "Tb must lie in (0, Tc)");
+            const double tr = f.Tb / f.Tc, u = 1.0 - tr;
+            const double u15 = u * std::sqrt(u), u25 = u15 * u, u5 = u25 * u25;
+            const double f0 = (-5.97616 * u + 1.29874 * u15 - 0.60394 * u25 - 1.06841 * u5) / tr;
+            const double f1 = (-5.03365 * u + 1.11505 * u15 - 5.41217 * u25 - 7.46628 * u5) / tr;
+            w = (-std::log(f.pc / 101325.0) - f0) / f1;
+        }
         // attraction and covolume of the PR equation of state (the criticality relations for a(T) and b (Section 2))
-        const double w = f.omega;
         const double mw = w <= 0.491 ? 0.37464 + 1.54226 * w - 0.26992 * w * w
                                      : 0.3796 + 1.485 * w - 0.1644 * w * w + 0.01667 * w * w * w;
         const double al = 1.0 + mw * (1.0 - std::sqrt(f.T / f.Tc));

@@ -8,6 +8,7 @@ transmissibility, no residual, no preconditioner.
 from .fields import gaussian_field, lognormal_perm, layered_perm, channel_perm  # noqa: F401
 from .configs import (  # noqa: F401
     MD, DAY, ATM, Fluid, Problem, SolverSettings, Case,
-    case_2d_32, case_2d_512, case_3d_128, case_batch64, case_3d_96_adjoint, case_2d_flood, small_case,
+    case_2d_32, case_2d_512, case_3d_128, case_batch64, case_3d_96_adjoint, case_2d_flood, case_2d_flood_512,
+    small_case,
     with_solver,
 )

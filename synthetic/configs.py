@@ -33,6 +33,7 @@ class Fluid:
     W: float = 0.016
     R: float = 8.3147295
     mu: float = 11.067e-3 * 1e-3   # 11.067e-3 cP
+    Tb: Optional[float] = None     # normal boiling point (K): omega is computed from it
 
 
 @dataclass
@@ -152,8 +153,18 @@ def case_2d_flood(nx=64, ny=64, px=4, py=4, seed=4):
                       dt=0.06 * DAY, nsteps=4, p_init=ATM,
                       bc=((2, 1, 10 * ATM), (3, 1, ATM)))
     prob = case.problems[0]
-    prob.fluid = replace(prob.fluid, T=298.0)
+    # the paper's methane constants (Section 4), omega from the boiling point
+    prob.fluid = replace(prob.fluid, T=298.0, Tc=190.58, pc=4.604e6, Tb=111.67)
     return replace(case, name=f"2d_{nx}x{ny}_flood_dirichlet", description=case_2d_flood.__doc__)
+
+
+def case_2d_flood_512():
+    """The Dirichlet flood at 512x512 with the 512x512 workload's solver: 16x16
+    subdomains, overlap 2 on both levels of a two-level V-cycle, FGMRES(30),
+    FP64; 10 steps of 0.06 day."""
+    case = case_2d_flood(512, 512, 16, 16)
+    case = with_solver(case, levels=2, overlap=(2, 2))
+    return replace(case, nsteps=10, description=case_2d_flood_512.__doc__)
 
 
 def case_2d_32():

@@ -68,6 +68,26 @@ def test_boundary_residual_jacobian_dlogk_parity(nks, orc, cfg):
     assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
 
 
+def test_acentric_from_boiling_point_parity(nks, orc):
+    # omega from Tb (Section 2's correlation) on both sides, at 20 MPa where Z
+    # is sensitive to it; a different omega changes the residual
+    from dataclasses import replace
+    case = S.small_case(nx=20, ny=17, seed=6, bc=((0, 1, 21e6),))
+    rec = case.problems[0]
+    rec.fluid = replace(rec.fluid, Tc=190.58, pc=4.604e6, Tb=111.67, omega=0.5)
+    op = orc.Problem(rec)
+    rng = np.random.default_rng(6)
+    p = 20e6 + 3e4 * rng.standard_normal(op.N)
+    pn = 20e6 + 1e4 * rng.standard_normal(op.N)
+    Fo = op.residual(p, pn, pn, case.dt, 1)
+    g = nks.Grid([rec])
+    Fg = g.residual(g.from_numpy(p), g.from_numpy(pn), g.from_numpy(pn), case.dt, 1).cpu().numpy()
+    assert np.max(np.abs(Fg - Fo)) <= 1e-12 * np.max(np.abs(Fo))
+    rec.fluid = replace(rec.fluid, Tb=None)
+    Fw = orc.Problem(rec).residual(p, pn, pn, case.dt, 1)
+    assert np.max(np.abs(Fw - Fo)) > 1e-8 * np.max(np.abs(Fo))
+
+
 def test_bad_boundary_rejected(nks):
     rec = S.small_case(nx=6, ny=5, bc=((0, 1, -5.0),)).problems[0]
     with pytest.raises(Exception, match="p\\^D"):
