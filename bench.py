@@ -36,8 +36,8 @@ WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128
 PMC_TRAFFIC = {
     "workload": "2d_512x512_twolevel_fp64",
     "source": "paper_2007_13966_amd/csrc/schwarz.hip",
-    "sha1": "4ae4b693d646d770e8db0d28a0d05b0e1feefbce",
-    "fetch_kib": 8853.9, "fetch_scale": 2.0,
+    "sha1": "bd18176ca6db1d999ee617170996baf2d32b8ea6",
+    "fetch_kib": 8854.2, "fetch_scale": 2.0,
     "write_kib": 2048.0, "write_scale": 1.0,
 }
 
