@@ -36,8 +36,8 @@ WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128
 PMC_TRAFFIC = {
     "workload": "2d_512x512_twolevel_fp64",
     "source": "paper_2007_13966_amd/csrc/schwarz.hip",
-    "sha1": "bd18176ca6db1d999ee617170996baf2d32b8ea6",
-    "fetch_kib": 8854.2, "fetch_scale": 2.0,
+    "sha1": "412546ad8237521c76a11623611ee6fb4fcfc343",
+    "fetch_kib": 8854.3, "fetch_scale": 2.0,
     "write_kib": 2048.0, "write_scale": 1.0,
 }
 
@@ -232,6 +232,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--lag", type=int, default=1,
+                    help="refactor the preconditioner every LAG Newton iterations")
     ap.add_argument("--fill", type=int, default=0, choices=[0, 1, 2],
                     help="subdomain ILU level of fill k: ILU(k) instead of ILU(0)")
     ap.add_argument("--interp-order", type=int, default=0, choices=[0, 1, 2, 3],
@@ -268,6 +270,8 @@ def main():
         case = S.with_solver(case, interp_order=args.interp_order)
     if args.fill:
         case = S.with_solver(case, fill=args.fill)
+    if args.lag != 1:
+        case = S.with_solver(case, lag=args.lag)
     tuning = None
     if args.autotune:
         g0 = P.Grid(case.problems)
@@ -315,6 +319,7 @@ def main():
             "levels": s64.levels,
             "interp_order": s64.interp_order,
             "ilu_fill": s64.fill,
+            "lag": s64.lag,
             "subdomains": int(sum(np.prod(boxes(r, s64)) for r in case.problems)),
             "overlap": list(s64.overlap), "precision": s64.precision,
             "newton_its_per_step": float(np.mean(nits)),

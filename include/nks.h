@@ -266,6 +266,11 @@ typedef struct {
                                     or when ||lambda s|| <= stol ||X^{k+1}|| (0: off) */
     int floor_test;              /* nonzero: also stop when ||F(X)|| <= u || |J(X)| |X| ||,
                                     u = 2^-53, the rounding floor of evaluating F */
+    int lag;                     /* >= 0: subdomain ILU factorisations at Newton iterations
+                                    0, lag, 2 lag, ... of the step (0 or 1: every one).  In
+                                    between, the factors of the last one are reused while
+                                    the operators stay current: the Jacobian on the finest
+                                    level and its Galerkin products below */
 } nks_newton_desc;
 
 typedef struct {

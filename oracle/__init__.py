@@ -44,7 +44,8 @@ class NewtonDesc(C.Structure):
     _fields_ = [("eps_r", C.c_double), ("eps_a", C.c_double), ("eta_r", C.c_double),
                 ("eta_a", C.c_double), ("restart", C.c_int), ("maxit", C.c_int),
                 ("flexible", C.c_int), ("alpha", C.c_double), ("max_newton", C.c_int),
-                ("max_backtracks", C.c_int), ("stol", C.c_double), ("floor_test", C.c_int)]
+                ("max_backtracks", C.c_int), ("stol", C.c_double), ("floor_test", C.c_int),
+                ("lag", C.c_int)]
 
 
 class NewtonStats(C.Structure):
@@ -281,6 +282,7 @@ def newton_desc(s):
     d.max_newton, d.max_backtracks = s.max_newton, s.max_backtracks
     d.stol = s.stol
     d.floor_test = 1 if s.floor_test else 0
+    d.lag = s.lag
     return d
 
 

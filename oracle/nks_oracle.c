@@ -900,6 +900,22 @@ struct orc_mg {
     double *work[MAXLEV][4];
 };
 
+/* Lagged refactorisation: the current Jacobian's values (same pattern) on the
+ * finest level and fresh Galerkin products P^T A P below it; the subdomain
+ * ILU factors of the last build are kept. */
+static void mg_refresh_operators(orc_mg *mg, const double *v) {
+    level *f = &mg->lev[0];
+    memcpy(f->A.v, v, (size_t)f->A.rp[f->A.n] * sizeof(double));
+    for (int l = 0; l + 1 < mg->L; ++l) {
+        level *fl = &mg->lev[l], *cl = &mg->lev[l + 1];
+        csr AP = csr_matmul(&fl->A, &fl->P);
+        csr Pt = csr_transpose(&fl->P);
+        csr_free(&cl->A);
+        cl->A = csr_matmul(&Pt, &AP);
+        csr_free(&AP); csr_free(&Pt);
+    }
+}
+
 /* box q of P boxes along n cells: floor(n/P) cells plus one for the first n mod P */
 static void box_range(int n, int P, int q, int *lo, int *hi) {
     int base = n / P, rem = n % P;
@@ -1392,6 +1408,7 @@ int orc_newton_step(const orc_problem *pr, const orc_mg_desc *md, const orc_newt
     double stop = nd->eps_r * f0 > nd->eps_a ? nd->eps_r * f0 : nd->eps_a;
     int status = 1;
     if (f0 <= stop) status = 0;
+    orc_mg *M = NULL;
     for (int k = 0; k < nd->max_newton && status != 0; ++k) {
         orc_jacobian(pr, p, pn, pnm1, dt, order, rp, ci, v);
         if (nd->floor_test) {
@@ -1403,14 +1420,18 @@ int orc_newton_step(const orc_problem *pr, const orc_mg_desc *md, const orc_newt
             }
             if (fn <= ldexp(sqrt(fl), -53)) { status = 0; break; }
         }
-        orc_mg *M = orc_mg_new(pr->nx, pr->ny, pr->nz, N, rp, ci, v, md);
+        if (!M || nd->lag <= 1 || k % nd->lag == 0) {
+            orc_mg_free(M);
+            M = orc_mg_new(pr->nx, pr->ny, pr->nz, N, rp, ci, v, md);
+        } else {
+            mg_refresh_operators(M, v);
+        }
         for (int i = 0; i < N; ++i) { b[i] = -F[i]; s[i] = 0.0; }
         double lres;
         int lits;
         double ltol_r = nd->eta_r, ltol_a = nd->eta_a;
         orc_gmres(N, rp, ci, v, M, 0, b, s, nd->restart, ltol_r, ltol_a, nd->maxit,
                   nd->flexible, &lres, &lits);
-        orc_mg_free(M);
         st->linear_its += lits;
         if (k < 64) st->lits[k] = lits;
         const int small = nd->stol > 0.0 && norm2(N, s) <= nd->stol * norm2(N, p);
@@ -1461,6 +1482,7 @@ int orc_newton_step(const orc_problem *pr, const orc_mg_desc *md, const orc_newt
     }
     st->fnorm = fn;
     st->status = status;
+    orc_mg_free(M);
     free(F); free(Ft); free(s); free(b); free(Js); free(pt); free(rp); free(ci); free(v);
     return status;
 }

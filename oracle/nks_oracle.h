@@ -45,6 +45,9 @@ typedef struct {
     int max_newton, max_backtracks;
     double stol;            /* stop when ||lambda s|| <= stol ||X^{k+1}|| (0: off) */
     int floor_test;         /* nonzero: also stop when ||F|| <= u || |J| |X| || */
+    int lag;                /* ILU factorisations at iterations 0, lag, 2 lag, ... (0 or 1:
+                               every one); in between the subdomain factors are kept while
+                               the operators (J and its Galerkin products) are current */
 } orc_newton_desc;
 
 typedef struct {

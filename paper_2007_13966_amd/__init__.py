@@ -96,6 +96,7 @@ def newton_desc(s):
     d.max_newton, d.max_backtracks = s.max_newton, s.max_backtracks
     d.stol = s.stol
     d.floor_test = 1 if s.floor_test else 0
+    d.lag = getattr(s, "lag", 1)
     return d
 
 

@@ -64,7 +64,8 @@ class nks_newton_desc(C.Structure):
     _fields_ = [("eps_r", C.c_double), ("eps_a", C.c_double), ("eta_r", C.c_double),
                 ("eta_a", C.c_double), ("restart", C.c_int), ("maxit", C.c_int),
                 ("flexible", C.c_int), ("alpha", C.c_double), ("max_newton", C.c_int),
-                ("max_backtracks", C.c_int), ("stol", C.c_double), ("floor_test", C.c_int)]
+                ("max_backtracks", C.c_int), ("stol", C.c_double), ("floor_test", C.c_int),
+                ("lag", C.c_int)]
 
 
 class nks_newton_stats(C.Structure):

@@ -838,6 +838,7 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             fail(NKS_EINVAL, "bad arguments");
         check_ras_desc(rd);
         if (nd->restart < 1 || nd->restart > 30) fail(NKS_EINVAL, "restart must be in [1, 30]");
+        if (nd->lag < 0) fail(NKS_EINVAL, "lag must be >= 0");
         Grid &g = gh->g;
         const int N = g.sp.N, B = g.sp.B;
         hipStream_t s = g.s;
@@ -936,8 +937,10 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             }
             double t2 = now();
             S.t_jacobian += t2 - t1;
-            // factor; zero pivots are read back after the solve (with its stats)
-            W.M->factor();
+            // coarse operators, and the subdomain factors every lag-th
+            // iteration (in between the last factors are kept); zero pivots
+            // are read back after the solve (with its stats)
+            W.M->factor(nd->lag <= 1 || k % nd->lag == 0);
             double t3 = now();
             S.t_setup += t3 - t2;
             // J s = -F on the active reservoirs

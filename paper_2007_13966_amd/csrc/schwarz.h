@@ -120,7 +120,8 @@ struct Ras {
     long coarse_calls = 0;
 
     void build(Matrix *J, const nks_ras_desc &d);     // structure (once)
-    void factor();                                     // numeric (every call)
+    void factor(bool ilu = true);                      // numeric: Galerkin products, and the
+                                                       // subdomain factors when ilu is set
     void apply(const double *r, double *z, const int *mask);
     void apply_level(int l, const double *r, double *z, const int *mask, bool accumulate);
     void vcycle(int l, const double *b, double *x, const int *mask);

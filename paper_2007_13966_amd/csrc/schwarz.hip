@@ -1939,7 +1939,7 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
 
 static bool use_rows3d(const Ras &M, const Level &V);
 
-void Ras::factor() {
+void Ras::factor(bool ilu) {
     hipStream_t s = g->s;
     for (int l = 0; l < L; ++l) {
         Level &V = *lev[l];
@@ -1954,6 +1954,7 @@ void Ras::factor() {
                          F.A->st.doff.p, V.own.coef.p, Kc, F.rap_slot.p, F.rap_R);
             KCHECK();
         }
+        if (!ilu) continue;
         const TileDims &td = tiles_[l];
         FacArgs fa;
         fa.sub = V.sub.p;

@@ -100,6 +100,7 @@ class SolverSettings:
     max_backtracks: int = 20
     stol: float = 0.0                    # relative Newton step test (PETSc's; 0 = off)
     floor_test: bool = True              # stop at the FP64 rounding floor u || |J| |X| ||
+    lag: int = 1                         # refactor the preconditioner every lag Newton iterations
     precision: str = "fp64"              # fp64 | fp32 | bf16
     flexible: Optional[bool] = None      # None: FGMRES iff levels > 1 or precision != fp64
 

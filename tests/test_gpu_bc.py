@@ -120,3 +120,30 @@ def test_dirichlet_flood_newton_parity(nks, orc, levels):
         assert err <= 1e-6
         assert abs(st_g[n - 1]["newton_its"] - st_o[n - 1]["newton_its"]) <= 1
     assert st_o[0]["newton_its"] >= 3          # the regime is nonlinear
+
+
+@pytest.mark.parametrize("lag,levels,flood", [(3, 1, True), (100, 2, False)])
+def test_lagged_factorisation_newton_parity(nks, orc, lag, levels, flood):
+    # subdomain factors refreshed every lag Newton iterations on both sides
+    if flood:
+        case = S.case_2d_flood(32, 28, 2, 2)
+    else:
+        case = S.small_case(nx=32, ny=28, px=2, py=2, rate=5e-2, dt=20 * S.DAY)
+    case = S.with_solver(case, lag=lag, levels=levels, overlap=(1,) * levels, **PARITY)
+    say("lagged newton", lag, levels)
+    g = nks.Grid(case.problems)
+    hist_g, st_g = [g.initial_pressure().cpu().numpy()], []
+    for n in range(2):
+        order = 1 if n == 0 else 2
+        pn = g.from_numpy(hist_g[-1])
+        pnm1 = g.from_numpy(hist_g[-2] if n > 0 else hist_g[-1])
+        p = pn.clone()
+        st_g.append(g.newton_step(p, pn, pnm1, case.dt, order, case.solver))
+        hist_g.append(p.cpu().numpy())
+    (hist_o, st_o), = orc.simulate(case, nsteps=2)
+    for n in range(1, 3):
+        err = np.linalg.norm((hist_g[n] - hist_g[0]) - (hist_o[n] - hist_o[0])) / np.linalg.norm(hist_o[n] - hist_o[0])
+        say("step", n, "err", err, "its", st_g[n - 1]["newton_its"], st_o[n - 1]["newton_its"],
+            st_g[n - 1]["linear_its"], st_o[n - 1]["linear_its"])
+        assert err <= 1e-6
+        assert abs(st_g[n - 1]["newton_its"] - st_o[n - 1]["newton_its"]) <= 1
