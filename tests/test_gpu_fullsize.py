@@ -69,6 +69,17 @@ def test_2d_512_first_step(nks, orc, precision):
     _check(orc, case, 0, p0[0], p[0])
 
 
+def test_flood_512_first_step(nks, orc):
+    # Dirichlet faces at 1 and 10 atm around gas at 1 atm: several Newton
+    # iterations in the first step
+    case = S.with_solver(S.case_2d_flood_512(), **PARITY)
+    say("2d 512x512 flood")
+    p0, p, st = _gpu_first_step(nks, case)
+    say("  gpu", st["newton_its"], "newton,", st["linear_its"], "gmres")
+    assert st["newton_its"] >= 2
+    _check(orc, case, 0, p0[0], p[0])
+
+
 def test_3d_128_first_step(nks, orc):
     case = S.with_solver(S.case_3d_128(), **PARITY)
     say("3d 128x128x64", case.solver.precision)
