@@ -198,8 +198,9 @@ int nks_ras_apply_level(nks_ras *M, int level, const double *r, double *z);
  * built on J^T, left- and right-RAS exchanged (AS stays AS).  ILU(0) of A^T
  * on a symmetric pattern is the transpose of ILU(0) of A, and the Galerkin
  * product commutes with transposition, so for one level this is exactly the
- * transpose; with levels it is the transposed V-cycle up to the inexact
- * coarse solve.  Built and factored on first use after each nks_ras_setup.
+ * transpose; with levels it is the transposed composition (the mu and nu
+ * smoothing counts trade places, left and right Kaskade exchange) up to the
+ * inexact coarse solve.  Built and factored on first use after each nks_ras_setup.
  * Synchronous on the grid's stream when it refactors. */
 int nks_ras_apply_transpose(nks_ras *M, const double *r, double *z);
 /* info[0..7] = n, stencil points, subdomains, nx, ny, nz (first reservoir),

@@ -1165,17 +1165,24 @@ static void coarse_solve(orc_mg *mg, const double *b, double *x, int trans) {
                mg->d.coarse_rtol, 0.0, mg->d.coarse_maxit, 0, NULL, NULL);
 }
 
-static void residual_update(const level *lv, const double *b, const double *x, double *r) {
-    orc_csr_matvec(lv->n, lv->A.rp, lv->A.ci, lv->A.v, x, r);
+/* r = b - A x, or b - A^T x when trans */
+static void residual_update(const level *lv, const double *b, const double *x, double *r, int trans) {
+    if (trans) csr_matvec_t(lv->n, lv->n, lv->A.rp, lv->A.ci, lv->A.v, x, r);
+    else orc_csr_matvec(lv->n, lv->A.rp, lv->A.ci, lv->A.v, x, r);
     for (int i = 0; i < lv->n; ++i) r[i] = b[i] - r[i];
 }
 
 /* X = MG(b, level, 0) of Algorithm 1 with the composition chosen by the
- * cycle type; lev indexes from the finest (0) down to the coarsest (L-1). */
-static void mg_cycle(orc_mg *mg, int li, const double *b, double *x) {
+ * cycle type; lev indexes from the finest (0) down to the coarsest (L-1).
+ * trans applies the transpose of that linear map (exact when the coarse
+ * solve is): every factor of the composition is transposed and their order
+ * reversed, so A, the smoother and the coarse solve become their transposes,
+ * P and P^T keep their places, and the mu pre- and nu post-smoothing steps
+ * trade places (left and right Kaskade exchange). */
+static void mg_cycle(orc_mg *mg, int li, const double *b, double *x, int trans) {
     level *lv = &mg->lev[li];
     int n = lv->n;
-    if (li == mg->L - 1) { coarse_solve(mg, b, x, 0); return; }
+    if (li == mg->L - 1) { coarse_solve(mg, b, x, trans); return; }
     level *cl = &mg->lev[li + 1];
     double *r = mg->work[li][0], *t = mg->work[li][1];
     double *bc = mg->work[li + 1][2], *xc = mg->work[li + 1][3];
@@ -1184,10 +1191,10 @@ static void mg_cycle(orc_mg *mg, int li, const double *b, double *x) {
     if (cyc == 3 || cyc == 4) {
         /* additive two-level form: I P M0 P^T b + M b;  coarse-only form: I P M0 P^T b */
         csr_matvec_t(n, cl->n, lv->P.rp, lv->P.ci, lv->P.v, b, bc);
-        mg_cycle(mg, li + 1, bc, xc);
+        mg_cycle(mg, li + 1, bc, xc, trans);
         orc_csr_matvec(n, lv->P.rp, lv->P.ci, lv->P.v, xc, x);
         if (cyc == 3) {
-            onelevel_apply(lv, &mg->d, b, t, 0);
+            onelevel_apply(lv, &mg->d, b, t, trans);
             for (int i = 0; i < n; ++i) x[i] += t[i];
         }
         return;
@@ -1195,22 +1202,23 @@ static void mg_cycle(orc_mg *mg, int li, const double *b, double *x) {
     int mu = mg->d.mu, nu = mg->d.nu;
     if (cyc == 1) { mu = 0; nu = 1; }        /* left Kaskade */
     else if (cyc == 2) { mu = 1; nu = 0; }   /* right Kaskade */
+    if (trans) { int tmp = mu; mu = nu; nu = tmp; }
     /* presmoothing: Schwarz-preconditioned Richardson, mu sweeps */
     for (int s = 0; s < mu; ++s) {
-        residual_update(lv, b, x, r);
-        onelevel_apply(lv, &mg->d, r, t, 0);
+        residual_update(lv, b, x, r, trans);
+        onelevel_apply(lv, &mg->d, r, t, trans);
         for (int i = 0; i < n; ++i) x[i] += t[i];
     }
     /* residual restriction with P^T, recursive correction, interpolation */
-    residual_update(lv, b, x, r);
+    residual_update(lv, b, x, r, trans);
     csr_matvec_t(n, cl->n, lv->P.rp, lv->P.ci, lv->P.v, r, bc);
-    mg_cycle(mg, li + 1, bc, xc);
+    mg_cycle(mg, li + 1, bc, xc, trans);
     orc_csr_matvec(n, lv->P.rp, lv->P.ci, lv->P.v, xc, t);
     for (int i = 0; i < n; ++i) x[i] += t[i];
     /* postsmoothing, nu sweeps */
     for (int s = 0; s < nu; ++s) {
-        residual_update(lv, b, x, r);
-        onelevel_apply(lv, &mg->d, r, t, 0);
+        residual_update(lv, b, x, r, trans);
+        onelevel_apply(lv, &mg->d, r, t, trans);
         for (int i = 0; i < n; ++i) x[i] += t[i];
     }
 }
@@ -1275,14 +1283,17 @@ void orc_mg_free(orc_mg *mg) {
 
 void orc_mg_apply(orc_mg *mg, const double *r, double *z) {
     if (mg->L == 1) onelevel_apply(&mg->lev[0], &mg->d, r, z, 0);
-    else mg_cycle(mg, 0, r, z);
+    else mg_cycle(mg, 0, r, z, 0);
 }
 
-/* M^{-T} for the one-level preconditioner (used by the adjoint):
+/* M^{-T} (used by the adjoint).  One level:
  * (sum R0^T A_i^{-1} Rd)^T = sum Rd^T A_i^{-T} R0, the right-RAS structure
- * on the transposed factors.  Multilevel transposes are not provided. */
+ * on the transposed factors.  Several levels: the transposed composition of
+ * mg_cycle, whose coarsest solve is GMRES on A_0^T with the transposed
+ * one-level preconditioner (the exact transpose when that solve converges). */
 void orc_mg_apply_transpose(orc_mg *mg, const double *r, double *z) {
-    onelevel_apply(&mg->lev[0], &mg->d, r, z, 1);
+    if (mg->L == 1) onelevel_apply(&mg->lev[0], &mg->d, r, z, 1);
+    else mg_cycle(mg, 0, r, z, 1);
 }
 
 void orc_mg_apply_onelevel(orc_mg *mg, int lev, const double *r, double *z) {

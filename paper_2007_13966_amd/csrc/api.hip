@@ -246,9 +246,11 @@ static void fine_matrix(Matrix &M, Grid &g) {
 // The transpose of a Schwarz preconditioner built on J: the same boxes and
 // levels built on J^T, with left- and right-RAS exchanged.  ILU(0) of A^T on
 // a symmetric pattern is the transpose of ILU(0) of A and the Galerkin product
-// commutes with transposition, so for one level this is exactly M^T; with
-// levels, the V-cycle built this way is the transpose of the V-cycle on J up
-// to its inexact coarse solve.
+// commutes with transposition, so for one level this is exactly M^T.  The
+// transpose of a multilevel composition reverses the order of its factors, so
+// the pre- and post-smoothing counts trade places and left and right Kaskade
+// exchange; the result is the transpose of the cycle on J up to its inexact
+// coarse solve.
 struct TransposedRas {
     Matrix JT;
     DBuf<int> opp;
@@ -264,6 +266,10 @@ struct TransposedRas {
             nks_ras_desc dt = dd;
             dt.variant = dd.variant == NKS_LEFT_RAS ? NKS_RIGHT_RAS
                                                     : (dd.variant == NKS_RIGHT_RAS ? NKS_LEFT_RAS : dd.variant);
+            dt.mu = dd.nu;
+            dt.nu = dd.mu;
+            dt.cycle = dd.cycle == NKS_LEFT_KASKADE ? NKS_RIGHT_KASKADE
+                                                    : (dd.cycle == NKS_RIGHT_KASKADE ? NKS_LEFT_KASKADE : dd.cycle);
             MT.reset(new Ras());
             MT->build(&JT, dt);
             d = dd;

@@ -227,6 +227,28 @@ def test_multilevel_apply_parity(nks, orc, cycle):
     assert np.max(np.abs(zg - zo)) <= 1e-9 * np.max(np.abs(zo))
 
 
+@pytest.mark.parametrize("cycle,mu,nu,levels", [("vcycle", 1, 2, 2), ("left_kaskade", 1, 1, 2),
+                                               ("vcycle", 1, 1, 3)])
+def test_multilevel_transpose_apply_parity(nks, orc, cycle, mu, nu, levels):
+    # M^{-T} of the multilevel preconditioner: the transposed composition
+    # (smoothing counts swapped, Kaskade sides exchanged) with a fixed number
+    # of coarse GMRES iterations on A_0^T, against the oracle's transposed cycle
+    cfg = dict(nx=48, ny=40, nz=1, px=4, py=4, levels=levels, overlap=(2,) + (1,) * (levels - 1),
+               cycle=cycle, mu=mu, nu=nu, coarse_rtol=0.0, coarse_maxit=6)
+    say("multilevel transpose", cycle, mu, nu, levels)
+    case = S.small_case(**cfg)
+    rec = case.problems[0]
+    op = orc.Problem(rec)
+    p, pn, _ = _state(op, 19)
+    Jo = op.jacobian(p, pn, pn, case.dt, 1)
+    r = np.cos(0.7 * np.arange(op.N))
+    zo = orc.Multilevel(rec, Jo, case.solver).apply_transpose(r)
+    g = nks.Grid([rec])
+    M = nks.Ras(_gpu_jac(nks, g, p, pn, case.dt), case.solver)
+    zg = M.apply_transpose(g.from_numpy(r)).cpu().numpy()
+    assert np.max(np.abs(zg - zo)) <= 1e-9 * np.max(np.abs(zo))
+
+
 def test_multilevel_many_coarse_boxes_parity(nks, orc):
     # 17 x 17 = 289 boxes on each level, more than the 256 CUs of the device:
     # the box kernels run in several rounds of workgroups

@@ -285,6 +285,26 @@ def test_two_level_compositions(orc, cycle):
     assert np.allclose(B, ref, rtol=1e-8, atol=1e-8 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("cycle,mu,nu,levels,variant", [
+    ("vcycle", 1, 1, 2, "left_ras"), ("vcycle", 1, 2, 2, "left_ras"), ("vcycle", 2, 1, 3, "as"),
+    ("left_kaskade", 1, 1, 2, "left_ras"), ("right_kaskade", 1, 1, 2, "right_ras"),
+    ("additive", 1, 1, 2, "left_ras"), ("coarse_only", 1, 1, 3, "left_ras")])
+def test_multilevel_transpose_apply_is_the_transpose(orc, cycle, mu, nu, levels, variant):
+    # with the coarsest solve converged to rounding the multilevel map is
+    # linear, and apply_transpose must be the transpose of its dense matrix:
+    # pre- and post-smoothing trade places, left and right Kaskade exchange
+    case, prob, J = _jac(orc, nx=12, ny=10, px=2, py=2, levels=levels, overlap=(1,) * levels,
+                         cycle=cycle, mu=mu, nu=nu, coarse_rtol=1e-14, coarse_maxit=400,
+                         variant=variant)
+    mg = orc.Multilevel(prob.rec, J, case.solver)
+    B = _apply_dense(mg.apply, J.n)
+    BT = _apply_dense(mg.apply_transpose, J.n)
+    assert np.allclose(BT, B.T, rtol=1e-8, atol=1e-8 * np.abs(B).max())
+    if cycle == "vcycle" and mu != nu:
+        # and it is not the cycle itself transposed term by term without the swap
+        assert not np.allclose(B, B.T, rtol=1e-3, atol=1e-3 * np.abs(B).max())
+
+
 # --------------------------------------------------------------- Krylov
 @pytest.mark.parametrize("dims", [(4, 4, 1), (6, 6, 1), (4, 4, 3)])
 def test_gmres_matches_dense_solve(orc, dims):
