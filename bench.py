@@ -1,16 +1,24 @@
 """Benchmark: time per implicit step of the Newton-Krylov-Schwarz hot path on one GPU.
 
-Default workload: 2D 512x512 log-normal reservoir (sigma 1, correlation
-length 8 cells), five-spot wells, BDF2 steps of 5 days, two-level V-cycle
-RAS with 256 subdomains (overlap 2 on both levels), FGMRES(30), FP64.
-A step is one full implicit time step: residual + PR, Jacobian, subdomain
-ILU(0) and Galerkin setup, preconditioned FGMRES, line search, per Newton
-iteration, to relative residual 1e-6.
+Default workload: 64 independent 2D reservoirs (sides 64..256, seeded
+log-normal permeability with sigma 0.5..2, one injector and one producer
+each), BDF2 steps of 5 days, a two-level V-cycle RAS whose subdomain tile and
+fine overlap are chosen by the library's autotuner, FP32 subdomain factors
+and sweeps inside FP64 FGMRES(30), FP64 residual, Jacobian and PR root.  The
+plain FP64 form and the BF16-factor form run on the same reservoirs beside it.
+A step is one full implicit time step of every reservoir: residual + PR,
+Jacobian, subdomain ILU(0) and Galerkin setup, preconditioned FGMRES, line
+search, per Newton iteration, to relative residual 1e-6 (or the binary64
+rounding floor of the residual, reported per step).
 
-Prints one JSON line.  `roofline` is the fine-level one-level Schwarz apply
+Prints one JSON line.  `value` is the configured precision form's mean time per
+step over the timed steps, which start from the initial state after the
+untimed warm-up steps.  `roofline` is the fine-level one-level Schwarz apply
 (the 2D sweep kernel), timed with HIP events bound to its dispatches inside
-the timed region; `cpu_baseline` times the CPU oracle on the first steps of the same
-workload.
+the timed region.  `cpu_baseline` runs the C oracle on every reservoir over
+the workload's own steps, one reservoir per worker process on the host's
+cores; its states also give each GPU form's pressure error against the
+oracle.
 """
 import argparse
 import json
@@ -117,7 +125,7 @@ def level_bytes(P, case, s, level):
     for rec in case.problems:
         d = [rec.nx, rec.ny, rec.nz]
         for _ in range(level):
-            d = [-(-x // 2) if (x > 1 or k < 2) else 1 for k, x in enumerate(d)]
+            d = [-(-x // s.ratio) if x > 1 else 1 for x in d]
         nb = boxes(rec, s)
         ne += ext_cells(d[0], d[1], d[2], *nb, s.overlap[min(level, len(s.overlap) - 1)])
     return ne * ((K - 1) * 8 + 8 + 8) + n * 8, K
@@ -143,26 +151,43 @@ def copy_bandwidth(torch, mib=1024, reps=5):
 
 
 ROOFLINE_RECORDS = ["ras_apply_l0", "ras_apply_l1"]
-BREAKDOWN_RECORDS = ["ras_apply_l0", "ras_apply_l1", "ras_apply_l2", "spmv_l0", "spmv_l1", "gmres_arnoldi", "residual_jacobian", "ilu_factor_l0",
-                     "ilu_factor_l1", "ilu_factor_l2", "rap_l1", "rap_l2"]
+BREAKDOWN_RECORDS = ["ras_apply_l0", "ras_apply_l1", "ras_apply_l2", "spmv_l0", "spmv_l1", "gmres_arnoldi",
+                     "residual_jacobian", "ilu_factor_l0", "ilu_factor_l1", "ilu_factor_l2", "rap_l1", "rap_l2"]
 
 
-def run_gpu(P, case, settings, warmup, steps, profile=True, breakdown_steps=2):
+def step_record(st):
+    """Per-step summary: Newton and FGMRES counts, the worst relative
+    residual reached over the reservoirs and why each reservoir stopped."""
+    reasons = {}
+    for w in st.get("stop_reason", []):
+        reasons[w] = reasons.get(w, 0) + 1
+    rr = st.get("rel_res") or [st["fnorm"] / st["fnorm0"] if st["fnorm0"] else 0.0]
+    return dict(newton=st["newton_its"], gmres=st["linear_its"], rel_res_max=float(max(rr)),
+                stop=reasons)
+
+
+def run_gpu(P, case, settings, warmup, steps, keep_states=0, profile=True, breakdown_steps=2):
+    """Warm-up steps from the initial state (untimed; the first keep_states
+    states kept for the oracle comparison), then `steps` timed steps from the
+    initial state again, then optional profiled steps for the breakdown."""
     import torch
     g = P.Grid(case.problems)
-    p = g.initial_pressure()
-    hist = [p.clone()]
+    p_init = g.initial_pressure()
 
-    def step(n):
-        order = 1 if n == 0 else 2
-        pn = hist[-1]
-        pnm1 = hist[-2] if len(hist) > 1 else hist[-1]
-        pnew = pn.clone()
-        st = g.newton_step(pnew, pn, pnm1, case.dt, order, settings)
-        hist.append(pnew)
-        if len(hist) > 3:
-            hist.pop(0)
-        return st
+    def trajectory():
+        hist = [p_init.clone()]
+
+        def step(n):
+            order = 1 if n == 0 else 2
+            pn = hist[-1]
+            pnm1 = hist[-2] if len(hist) > 1 else hist[-1]
+            pnew = pn.clone()
+            st = g.newton_step(pnew, pn, pnm1, case.dt, order, settings)
+            hist.append(pnew)
+            if len(hist) > 3:
+                hist.pop(0)
+            return st, pnew
+        return step
 
     def collect(names):
         import ctypes as C
@@ -176,10 +201,14 @@ def run_gpu(P, case, settings, warmup, steps, profile=True, breakdown_steps=2):
                 out[name] = np.array(buf[:])
         return out
 
-    for n in range(warmup):
-        step(n)
+    states = []
+    step = trajectory()
+    for n in range(max(warmup, keep_states)):
+        _, pnew = step(n)
+        if n < keep_states:
+            states.append(pnew.cpu().numpy())
     torch.cuda.synchronize()
-    p_start = hist[-1].clone()
+    step = trajectory()
     if profile:
         # inside the timed region only the sweeps behind the roofline figures
         # carry events; the other launches take no host bookkeeping
@@ -187,10 +216,9 @@ def run_gpu(P, case, settings, warmup, steps, profile=True, breakdown_steps=2):
         P.check(P.lib().nks_profile_enable(1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = [step(warmup + k) for k in range(steps)]
+    stats = [step(k)[0] for k in range(steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    p_end = hist[-1].cpu().numpy()
     prof, breakdown = {}, {}
     if profile:
         prof = collect(ROOFLINE_RECORDS)
@@ -200,47 +228,142 @@ def run_gpu(P, case, settings, warmup, steps, profile=True, breakdown_steps=2):
             P.check(P.lib().nks_profile_filter(None))
             P.check(P.lib().nks_profile_enable(1))
             for k in range(breakdown_steps):
-                step(warmup + steps + k)
+                step(steps + k)
             torch.cuda.synchronize()
             breakdown = collect(BREAKDOWN_RECORDS)
             P.check(P.lib().nks_profile_enable(0))
-    return dict(seconds=t1 - t0, stats=stats, prof=prof, breakdown=breakdown,
-                p_start=p_start.cpu().numpy(), p_end=p_end)
+    return dict(seconds=t1 - t0, stats=stats, prof=prof, breakdown=breakdown, states=states,
+                p_init=p_init.cpu().numpy(), offsets=g.offsets.copy())
 
 
-def cpu_baseline(case, nsteps):
+_ORACLE_CASE = None
+
+
+def _oracle_reservoir(args):
+    """One reservoir through the oracle: nsteps implicit steps from the
+    initial state; returns its states and per-step CPU seconds."""
     import oracle
-    rec = case.problems[0]
-    prob = oracle.Problem(rec)
+    b, nsteps = args
+    case = _ORACLE_CASE
+    prob = oracle.Problem(case.problems[b])
     p = prob.initial_pressure()
-    hist = [p]
-    t0 = time.perf_counter()
+    hist, secs = [p], []
     for n in range(nsteps):
         order = 1 if n == 0 else 2
         pnm1 = hist[-2] if len(hist) > 1 else hist[-1]
-        p, st = oracle.newton_step(prob, case.solver, hist[-1], hist[-1], pnm1, case.dt, order)
+        t0 = time.process_time()
+        p, _ = oracle.newton_step(prob, case.solver, hist[-1], hist[-1], pnm1, case.dt, order)
+        secs.append(time.process_time() - t0)
         hist.append(p)
-    return (time.perf_counter() - t0) / nsteps
+    return b, hist, secs
+
+
+def cpu_cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    # the GPU box's CPU share for one GPU
+    return max(1, min(n, 16))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_run(case, nsteps, workers):
+    """The oracle over every reservoir of the case (the configured solver,
+    FP64), one reservoir per worker process.  Runs before the GPU is touched
+    (the workers are forked from this process)."""
+    import multiprocessing as mp
+    global _ORACLE_CASE
+    _ORACLE_CASE = case
+    jobs = [(b, nsteps) for b in range(len(case.problems))]
+    # largest reservoirs first, so the pool drains evenly
+    jobs.sort(key=lambda j: -case.problems[j[0]].N)
+    t0 = time.perf_counter()
+    if workers > 1 and len(jobs) > 1:
+        with mp.get_context("fork").Pool(workers) as pool:
+            res = pool.map(_oracle_reservoir, jobs, chunksize=1)
+    else:
+        res = [_oracle_reservoir(j) for j in jobs]
+    wall = time.perf_counter() - t0
+    res.sort(key=lambda r: r[0])
+    states = [r[1] for r in res]
+    serial = sum(sum(r[2]) for r in res)
+    return dict(states=states, wall=wall, serial=serial, workers=workers if len(jobs) > 1 else 1)
+
+
+def oracle_errors(run, orc, nsteps):
+    """Pressure change error of a GPU form against the oracle, per reservoir
+    and step: ||dp_gpu - dp_orc|| / ||dp_orc|| with dp = p^n - p^0."""
+    off = run["offsets"]
+    worst, num, den = 0.0, 0.0, 0.0
+    for n in range(min(nsteps, len(run["states"]))):
+        pg = run["states"][n]
+        for b, hist in enumerate(orc["states"]):
+            a, z = off[b], off[b + 1]
+            dg = pg[a:z] - run["p_init"][a:z]
+            do = hist[n + 1] - hist[0]
+            e = float(np.linalg.norm(dg - do))
+            d = float(np.linalg.norm(do))
+            num += e * e
+            den += d * d
+            if d > 0:
+                worst = max(worst, e / d)
+    return dict(max_rel_dp_error=worst, rel_dp_error=float(np.sqrt(num / den)) if den > 0 else None,
+                steps_compared=min(nsteps, len(run["states"])))
+
+
+def form_summary(case, settings, run, steps, orc, ncheck):
+    sec = run["seconds"] / steps
+    nbytes, nexts = apply_bytes(case.problems, settings, settings.precision)
+    act = launch_split(run["prof"].get("ras_apply_l0", np.zeros(0)))
+    ach = nbytes / (float(act.mean()) / 1e3) / 1e9 if act.size else None
+    recs = [step_record(x) for x in run["stats"]]
+    out = {
+        "s_per_step": sec,
+        "newton_its_per_step": float(np.mean([r["newton"] for r in recs])),
+        "gmres_its_per_newton": float(sum(r["gmres"] for r in recs) / max(1, sum(r["newton"] for r in recs))),
+        "rel_res_reached_max": max(r["rel_res_max"] for r in recs),
+        "steps": recs,
+        "ras_apply_l0_gbs": ach,
+        "ras_apply_l0_frac": (ach / HBM_PEAK_GBS) if ach else None,
+        "ras_apply_l0_bytes": nbytes,
+    }
+    if orc is not None:
+        out["vs_oracle"] = oracle_errors(run, orc, ncheck)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=9)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="2d512", choices=list(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=3,
+                    help="timed implicit steps, from the initial state")
+    ap.add_argument("--warmup", type=int, default=3,
+                    help="untimed implicit steps from the initial state before the timed ones")
+    ap.add_argument("--workload", default="batch64", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle steps per reservoir (0: the workload's steps, at most 3)")
     ap.add_argument("--lag", type=int, default=1,
                     help="refactor the preconditioner every LAG Newton iterations")
     ap.add_argument("--fill", type=int, default=0, choices=[0, 1, 2],
                     help="subdomain ILU level of fill k: ILU(k) instead of ILU(0)")
     ap.add_argument("--interp-order", type=int, default=0, choices=[0, 1, 2, 3],
                     help="interpolation order between levels (0: the workload's own)")
-    ap.add_argument("--autotune", action="store_true",
+    ap.add_argument("--autotune", type=int, default=-1, choices=[-1, 0, 1],
                     help="choose the subdomain tile edge (8, 16, 32) and fine overlap (1, 2) with "
-                         "nks_ras_autotune at the initial state before timing")
+                         "nks_ras_autotune at the initial state (-1: on for the batch workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB five times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
@@ -251,6 +374,23 @@ def main():
         sys.exit(2)
 
     import synthetic as S
+    case = getattr(S, WORKLOADS[args.workload])()
+    if args.interp_order:
+        case = S.with_solver(case, interp_order=args.interp_order)
+    if args.fill:
+        case = S.with_solver(case, fill=args.fill)
+    if args.lag != 1:
+        case = S.with_solver(case, lag=args.lag)
+    ncheck = min(case.nsteps, 3) if args.cpu_steps <= 0 else args.cpu_steps
+
+    # the oracle first: its workers are forked before anything touches the GPU
+    orc = None
+    if not args.no_cpu_baseline and not args.copy_calibration:
+        workers = cpu_cores()
+        log(f"oracle: {len(case.problems)} reservoirs x {ncheck} steps on {workers} worker processes")
+        orc = oracle_run(case, ncheck, workers)
+        log(f"oracle: {orc['wall']:.1f} s wall, {orc['serial']:.1f} s CPU in all")
+
     import paper_2007_13966_amd as P
     import torch
     if not torch.cuda.is_available():
@@ -265,15 +405,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 5}))
         return
-    case = getattr(S, WORKLOADS[args.workload])()
-    if args.interp_order:
-        case = S.with_solver(case, interp_order=args.interp_order)
-    if args.fill:
-        case = S.with_solver(case, fill=args.fill)
-    if args.lag != 1:
-        case = S.with_solver(case, lag=args.lag)
+    autotune = args.autotune if args.autotune >= 0 else int(args.workload == "batch64")
     tuning = None
-    if args.autotune:
+    if autotune:
         g0 = P.Grid(case.problems)
         p0 = g0.initial_pressure()
         tuned, table = g0.autotune(p0, p0, p0, case.dt, 1, case.solver)
@@ -284,20 +418,30 @@ def main():
         for e in table:
             log(f"  tile {e['tile']:3d} overlap {e['overlap']}: ok {e['ok']} its {e['iterations']:3d} "
                 f"setup {e['setup_ms']:.2f} ms solve {e['solve_ms']:.2f} ms")
-    s64 = S.with_solver(case, precision="fp64").solver
-    log(f"workload {case.name}: {sum(r.N for r in case.problems)} cells")
-    nbytes, nexts = apply_bytes(case.problems, s64, "fp64")
-    r64 = run_gpu(P, case, s64, args.warmup, args.steps)
-    st = r64["stats"]
-    sec = r64["seconds"] / args.steps
-    nits = [x["newton_its"] for x in st]
-    lits = [x["linear_its"] for x in st]
-    log(f"fp64: {sec:.4f} s/step, newton {nits}, gmres {lits}")
-    allv = r64["prof"].get("ras_apply_l0", np.zeros(0))
+    head = case.solver.precision
+    forms = [head] if args.no_mixed else [head] + [f for f in ("fp64", "fp32", "bf16") if f != head]
+    log(f"workload {case.name}: {sum(r.N for r in case.problems)} cells, forms {forms}")
+    runs, summ = {}, {}
+    for f in forms:
+        sf = S.with_solver(case, precision=f).solver
+        runs[f] = run_gpu(P, case, sf, args.warmup, args.steps, keep_states=ncheck if orc else 0,
+                          breakdown_steps=2 if f == head else 0)
+        summ[f] = form_summary(case, sf, runs[f], args.steps, orc, ncheck)
+        e = summ[f].get("vs_oracle", {})
+        log(f"{f}: {summ[f]['s_per_step']:.4f} s/step, newton {[r['newton'] for r in summ[f]['steps']]}, "
+            f"gmres {[r['gmres'] for r in summ[f]['steps']]}, rel.res reached <= "
+            f"{summ[f]['rel_res_reached_max']:.2e}, dp error vs oracle {e.get('max_rel_dp_error')}")
+    s_head = S.with_solver(case, precision=head).solver
+    r_head = runs[head]
+    sec = summ[head]["s_per_step"]
+    nbytes, nexts = apply_bytes(case.problems, s_head, head)
+    allv = r_head["prof"].get("ras_apply_l0", np.zeros(0))
     act = launch_split(allv)
     cnt = int(act.size)
     avg_s = float(act.mean()) / 1e3 if cnt else 0.0
     achieved = nbytes / avg_s / 1e9 if cnt else None
+    tname = {"fp64": "double, double, double", "fp32": "float, float, float",
+             "bf16": "uint16_t, float, float"}[head]
     out = {
         "metric": METRIC,
         "value": sec,
@@ -309,30 +453,35 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head == "fp64" else f"f64 (outer, residual, PR) + {'f32' if head == 'fp32' else 'bf16/f32'} "
+                                              f"(subdomain factors and sweeps)",
         "data": "synthetic",
         "config": {
             "workload": case.name,
             "description": " ".join((case.description or "").split()),
             "cells": sum(r.N for r in case.problems),
             "reservoirs": len(case.problems),
-            "levels": s64.levels,
-            "interp_order": s64.interp_order,
-            "ilu_fill": s64.fill,
-            "lag": s64.lag,
-            "subdomains": int(sum(np.prod(boxes(r, s64)) for r in case.problems)),
-            "overlap": list(s64.overlap), "precision": s64.precision,
-            "newton_its_per_step": float(np.mean(nits)),
-            "gmres_its_per_newton": float(np.sum(lits) / max(1, np.sum(nits))),
-            "rel_res": s64.eps_r,
-            "rel_res_reached": [x["fnorm"] / x["fnorm0"] for x in st],
-            "tile": list(s64.tile),
+            "levels": s_head.levels,
+            "interp_order": s_head.interp_order,
+            "ilu_fill": s_head.fill,
+            "lag": s_head.lag,
+            "subdomains": int(sum(np.prod(boxes(r, s_head)) for r in case.problems)),
+            "overlap": list(s_head.overlap), "precision": head,
+            "tile": list(s_head.tile),
             "autotune": tuning,
+            "timed_steps": f"steps 1..{args.steps} from the initial state (BDF1 first, BDF2 after), "
+                           f"after {args.warmup} untimed warm-up steps from the same state",
+            "newton_its_per_step": summ[head]["newton_its_per_step"],
+            "gmres_its_per_newton": summ[head]["gmres_its_per_newton"],
+            "rel_res_target": s_head.eps_r,
+            "rel_res_reached_max": summ[head]["rel_res_reached_max"],
+            "per_step": summ[head]["steps"],
         },
+        "forms": summ,
         "roofline": {
-            "kernel": ("k_ras_apply<double, double, double, 3> (fine level 3D 7-point sweeps: one-level left-RAS, "
+            "kernel": (f"k_ras_apply<{tname}, 3> (fine level 3D 7-point sweeps: one-level left-RAS, "
                        "ILU(0) factors)" if case.problems[0].nz > 1 else
-                       "k_ras_rows<double, double, double, 0, 256> (fine level 2D sweeps: one-level left-RAS, ILU(0) factors)"),
+                       f"k_ras_rows<{tname}, 0, ...> (fine level 2D sweeps: one-level left-RAS, ILU(0) factors)"),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -351,21 +500,23 @@ def main():
         # launches outside captured graphs, over 2 profiled steps after the timed ones
         "kernels_ms": {k: {"count": int(v.size), "total_ms": round(float(v.sum()), 3),
                            "avg_us": round(1e3 * float(v.mean()), 2)}
-                       for k, v in r64["breakdown"].items()},
+                       for k, v in r_head["breakdown"].items()},
     }
-    if s64.levels > 1:
-        # the coarsest-but-one level's sweeps run inside every coarse GMRES
-        # iteration and take most of the apply time
-        cb, ck = level_bytes(P, case, s64, 1)
-        cl = launch_split(r64["prof"].get("ras_apply_l1", np.zeros(0)))
+    if "fp64" in summ and head != "fp64":
+        out["mixed_vs_fp64_speedup"] = summ["fp64"]["s_per_step"] / sec
+    if s_head.levels > 1:
+        # the coarse level's sweeps run inside every coarse GMRES iteration
+        cb, ck = level_bytes(P, case, S.with_solver(case, precision="fp64").solver, 1)
+        cl = launch_split(r_head["prof"].get("ras_apply_l1", np.zeros(0)))
         ca = cb / (float(cl.mean()) / 1e3) / 1e9 if cl.size else None
         out["roofline_coarse"] = {
-            "kernel": f"level-1 one-level sweeps ({ck}-point Galerkin stencil), launches outside graphs",
+            "kernel": f"level-1 one-level sweeps ({ck}-point Galerkin stencil), launches outside graphs; "
+                      f"bytes counted at FP64",
             "bound": "hbm", "achieved": ca, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (ca / HBM_PEAK_GBS) if ca else None, "bytes_per_launch": cb,
             "launches": int(cl.size), "avg_launch_us": float(cl.mean()) * 1e3 if cl.size else None,
         }
-    sp = r64["breakdown"].get("spmv_l0", np.zeros(0))
+    sp = r_head["breakdown"].get("spmv_l0", np.zeros(0))
     if sp.size and all(r.nz == 1 for r in case.problems):
         # 2D: the 5-point launches are the fine level's residuals r = b - A x
         # (the coarse operators have more points); per cell 5 coefficients,
@@ -379,51 +530,18 @@ def main():
         }
     out["stream_copy_gbs"] = copy_bandwidth(torch)
     log(f"device copy: {out['stream_copy_gbs']:.0f} GB/s")
-    if not args.no_mixed:
-        s32 = S.with_solver(case, precision="fp32").solver
-        b32, _ = apply_bytes(case.problems, s32, "fp32")
-        r32 = run_gpu(P, case, s32, args.warmup, args.steps, breakdown_steps=0)
-        sec32 = r32["seconds"] / args.steps
-        d64 = r64["p_end"] - r64["p_start"]
-        d32 = r32["p_end"] - r32["p_start"]
-        err = float(np.linalg.norm(d32 - d64) / max(np.linalg.norm(d64), 1e-300))
-        act32 = launch_split(r32["prof"].get("ras_apply_l0", np.zeros(0)))
-        a32 = b32 / (float(act32.mean()) / 1e3) / 1e9 if act32.size else None
-        out["mixed_fp32"] = {
-            "s_per_step": sec32,
-            "speedup_vs_fp64": sec / sec32,
-            "gmres_its_per_newton": float(sum(x["linear_its"] for x in r32["stats"]) /
-                                          max(1, sum(x["newton_its"] for x in r32["stats"]))),
-            "dp_rel_error_vs_fp64": err,
-            "ras_apply_l0_gbs": a32,
-            "ras_apply_l0_frac": (a32 / HBM_PEAK_GBS) if a32 else None,
+    if orc is not None:
+        out["cpu_baseline"] = {
+            "value": orc["wall"] / ncheck, "unit": "s/implicit step",
+            "cores": orc["workers"], "kind": "oracle",
+            "sample": f"all {len(case.problems)} reservoirs over steps 1..{ncheck} of the workload "
+                      f"(BDF1 then BDF2), the single-threaded C oracle (FP64, the same solver settings) "
+                      f"on one reservoir per worker process; wall time per step",
+            "cpu_model": cpu_model(),
+            "single_core_s_per_step": orc["serial"] / ncheck,
         }
-        log(f"fp32 preconditioner: {sec32:.4f} s/step, dp error vs fp64 {err:.2e}")
-        sb = S.with_solver(case, precision="bf16").solver
-        bb, _ = apply_bytes(case.problems, sb, "bf16")
-        rb = run_gpu(P, case, sb, args.warmup, args.steps, breakdown_steps=0)
-        secb = rb["seconds"] / args.steps
-        db = rb["p_end"] - rb["p_start"]
-        errb = float(np.linalg.norm(db - d64) / max(np.linalg.norm(d64), 1e-300))
-        actb = launch_split(rb["prof"].get("ras_apply_l0", np.zeros(0)))
-        ab = bb / (float(actb.mean()) / 1e3) / 1e9 if actb.size else None
-        out["mixed_bf16"] = {
-            "s_per_step": secb,
-            "speedup_vs_fp64": sec / secb,
-            "gmres_its_per_newton": float(sum(x["linear_its"] for x in rb["stats"]) /
-                                          max(1, sum(x["newton_its"] for x in rb["stats"]))),
-            "dp_rel_error_vs_fp64": errb,
-            "ras_apply_l0_gbs": ab,
-            "ras_apply_l0_frac": (ab / HBM_PEAK_GBS) if ab else None,
-        }
-        log(f"bf16 factors: {secb:.4f} s/step, dp error vs fp64 {errb:.2e}")
-    if not args.no_cpu_baseline and args.workload == "2d512":
-        n = args.cpu_steps
-        v = cpu_baseline(case, n)
-        out["cpu_baseline"] = {"value": v, "unit": "s/implicit step", "cores": 1, "kind": "oracle",
-                               "sample": f"first {n} implicit steps (BDF1 then BDF2) of the same "
-                                         f"512x512 workload, single-threaded C oracle"}
-        log(f"cpu oracle: {v:.3f} s/step")
+        log(f"cpu oracle: {orc['wall'] / ncheck:.3f} s/step on {orc['workers']} cores, "
+            f"{orc['serial'] / ncheck:.3f} s/step on one")
     print(json.dumps(out), flush=True)
 
 

@@ -95,7 +95,19 @@ typedef struct {
     nks_alloc_fn alloc;              /* NULL: hipMalloc / hipFree */
     nks_free_fn free;
     void *alloc_ctx;
+    int accum;                       /* NKS_ACCUM_CONSERVATIVE (0) or NKS_ACCUM_CHAIN_RULE */
 } nks_grid_desc;
+
+/* Accumulation forms of the residual.  Conservative: (V phi/dt) times
+ * m(p) - m(p^n) (BDF1) or (3 m(p) - 4 m(p^n) + m(p^{n-1}))/2 (BDF2), m = p/Z;
+ * it conserves mass step by step and its linearisation at p is the paper's
+ * coefficient.  Chain rule: the BDF1 and BDF2 equations of Section 2 as
+ * printed, (V phi/dt) m'(p) times p - p^n or (3p - 4p^n + p^{n-1})/2, with
+ * m'(p) = (p/Z)(1/p - Z'/Z) at the new level; its Jacobian adds m''(p) times
+ * that difference.  The discrete adjoint (nks_adjoint) is defined for the
+ * conservative form only. */
+#define NKS_ACCUM_CONSERVATIVE 0
+#define NKS_ACCUM_CHAIN_RULE 1
 
 /* Builds the face transmissibilities T = A_f / (d/(2K_i) + d/(2K_j))
  * (two-point flux of the cell-centred scheme, Section 2 Remark 1), pore
@@ -145,7 +157,7 @@ int nks_residual_dlogk_transpose_apply(nks_grid *g, const double *p, const doubl
  * floor(n/P) + (q < n mod P) cells, extended by `overlap` and clipped at the
  * domain boundary; the same box grid on every level.  Subdomain solve:
  * ILU(0) of R_i^delta A R_i^delta^T in local lexicographic order.
- * Levels: ratio 2 per direction (nz = 1 stays 1), the first- (1),
+ * Levels: ratio r per direction (nz = 1 stays 1), the first- (1),
  * second- (2) or third-order (3) interpolation of Section 3.2, restriction
  * P^T, Galerkin coarse operators P^T A P; coarsest level solved by GMRES
  * with the one-level preconditioner to coarse_rtol (Remark 2). */
@@ -179,13 +191,23 @@ typedef struct {
                                     the level-k pattern of the stencil on an unbounded grid,
                                     restricted to the box (an entry's level is the least number
                                     of interior vertices on a path to it through smaller
-                                    cells); k > 0 runs the hyperplane kernels */
+                                    cells); k > 0 runs the hyperplane kernels.  With boxes at
+                                    most k + 1 cells wide (2D) this is the exact LU of the box */
+    int ratio;                   /* coarse-to-fine mesh ratio per direction, 2..16 (0: 2;
+                                    Section 4.2 compares 2, 4, 8 and 16): coarse cell J covers
+                                    fine cells rJ .. min(rJ + r, n) - 1 and sits at their
+                                    centroid; orders 2 and 3 interpolate in the coordinate
+                                    linear between consecutive centroids */
 } nks_ras_desc;
 
 /* Creates (*inout == NULL) or refactors in place (*inout from an earlier
  * call on a matrix of the same grid and an identical descriptor).  Keeps a
  * reference to J: J must outlive the preconditioner.  Asynchronous.  A zero
- * pivot is reported by the next synchronising call as NKS_EZEROPIVOT. */
+ * pivot is reported by the next synchronising call as NKS_EZEROPIVOT.  The 3D
+ * sweeps of boxes split into slabs wait on their neighbouring slab with a
+ * spin limit; a wait that reaches it marks the level, and the next call that
+ * checks the factors (nks_gmres_solve, nks_newton_step, nks_adjoint) fails
+ * with NKS_EHIP instead of returning a correction built on stale values. */
 int nks_ras_setup(nks_matrix *J, const nks_ras_desc *d, nks_ras **inout);
 int nks_destroy_ras(nks_ras *M);
 /* z = M^{-1} r on the finest level (device).  Runs the coarse GMRES, so it
@@ -283,7 +305,15 @@ typedef struct {
     int lits[64];
     double lambdas[64];          /* min over active reservoirs */
     double t_residual, t_jacobian, t_setup, t_gmres, t_linesearch;  /* seconds */
+    int *stop_reason;            /* optional HOST array [nres] (caller-owned, NULL: not wanted):
+                                    why each reservoir stopped, NKS_STOP_* */
+    double *rel_res;             /* optional HOST array [nres]: final ||F|| / ||F(X^0)|| */
 } nks_newton_stats;
+
+#define NKS_STOP_NONE 0          /* still iterating when the call returned (limit or failure) */
+#define NKS_STOP_TOL 1           /* ||F|| <= max{eps_r ||F(X^0)||, eps_a} */
+#define NKS_STOP_FLOOR 2         /* ||F|| at the rounding floor u || |J| |X| || (floor_test) */
+#define NKS_STOP_STEP 3          /* the relative step test (stol) */
 
 int nks_newton_step(nks_grid *g, double *p, const double *p_n, const double *p_nm1,
                     double dt, int bdf_order, const nks_newton_desc *nd,

@@ -37,7 +37,7 @@ class MgDesc(C.Structure):
                 ("interp_order", C.c_int), ("cycle", C.c_int), ("mu", C.c_int), ("nu", C.c_int),
                 ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int),
                 ("coarse_restart", C.c_int), ("tx", C.c_int), ("ty", C.c_int), ("tz", C.c_int),
-                ("fill", C.c_int)]
+                ("fill", C.c_int), ("ratio", C.c_int)]
 
 
 class NewtonDesc(C.Structure):
@@ -70,6 +70,10 @@ def lib():
         L.orc_problem_free.argtypes = [C.c_void_p]
         L.orc_problem_set_bc.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double]
         L.orc_problem_set_bc.restype = C.c_int
+        L.orc_problem_set_accum.argtypes = [C.c_void_p, C.c_int]
+        L.orc_problem_set_accum.restype = C.c_int
+        L.orc_pr_z2.argtypes = [C.c_double] * 5 + [_D] * 4
+        L.orc_pr_z2.restype = C.c_int
         L.orc_pr_params.argtypes = [C.c_double] * 5 + [_D] * 3
         L.orc_acentric_terms.argtypes = [C.c_double, _D, _D]
         L.orc_acentric.argtypes = [C.c_double] * 3
@@ -98,6 +102,7 @@ def lib():
         L.orc_mg_sub_factors.argtypes = [C.c_void_p, C.c_int, C.c_int, _I, _I, _I, _I, _D]
         L.orc_csr_matvec.argtypes = [C.c_int, _I, _I, _D, _D, _D]
         L.orc_interp_1d.argtypes = [C.c_int, C.c_int, _I, _I, _D]
+        L.orc_interp_1d_r.argtypes = [C.c_int, C.c_int, C.c_int, _I, _I, _D]
         L.orc_ilu0.argtypes = [C.c_int, _I, _I, _D]
         L.orc_ilu0_solve.argtypes = [C.c_int, _I, _I, _D, _D, _D]
         L.orc_gmres.argtypes = [C.c_int, _I, _I, _D, C.c_void_p, C.c_int, _D, _D, C.c_int,
@@ -152,6 +157,16 @@ def pr_z(fluid, p):
     return Z.value, dZ.value, bad
 
 
+ACCUM_FORMS = {"conservative": 0, "chain_rule": 1}
+
+
+def pr_z2_ab(a, b, T, R, p):
+    """Z, dZ/dp, d2Z/dp2 and d2m/dp2 (m = p/Z) at scalar pressure p."""
+    Z, dZ, d2Z, d2m = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    lib().orc_pr_z2(a, b, T, R, float(p), C.byref(Z), C.byref(dZ), C.byref(d2Z), C.byref(d2m))
+    return Z.value, dZ.value, d2Z.value, d2m.value
+
+
 def pr_z_ab(a, b, T, R, p):
     Z, dZ = C.c_double(), C.c_double()
     bad = lib().orc_pr_z(a, b, T, R, float(p), C.byref(Z), C.byref(dZ))
@@ -200,6 +215,9 @@ class Problem:
         for f, (t, v) in enumerate(zip(rec.bc_type, rec.bc_value)):
             if lib().orc_problem_set_bc(self.h, f, int(t), float(v)) != 0:
                 raise ValueError(f"bad boundary condition on face {f}: type {t}, value {v}")
+        form = ACCUM_FORMS[getattr(rec, "accum", "conservative")]
+        if lib().orc_problem_set_accum(self.h, form) != 0:
+            raise ValueError(f"bad accumulation form {rec.accum}")
         self.N = rec.N
 
     def __del__(self):
@@ -269,6 +287,7 @@ def mg_desc(s):
     d.coarse_restart = s.coarse_restart
     d.tx, d.ty, d.tz = s.tile
     d.fill = s.fill
+    d.ratio = getattr(s, "ratio", 2)
     return d
 
 
@@ -373,12 +392,12 @@ def gmres(J, b, M=None, x0=None, restart=30, rtol=1e-5, atol=1e-8, maxit=10000,
     return x, its.value, res.value, st
 
 
-def interp_1d(nf, order):
+def interp_1d(nf, order, ratio=2):
     rp = np.zeros(nf + 1, np.int32)
     ci = np.zeros(4 * nf, np.int32)
     w = np.zeros(4 * nf)
-    lib().orc_interp_1d(nf, order, _i(rp), _i(ci), _d(w))
-    return CSR(rp, ci[:rp[-1]], w[:rp[-1]], ncols=(nf + 1) // 2)
+    lib().orc_interp_1d_r(nf, order, ratio, _i(rp), _i(ci), _d(w))
+    return CSR(rp, ci[:rp[-1]], w[:rp[-1]], ncols=(nf + ratio - 1) // ratio)
 
 
 def ilu0(A):

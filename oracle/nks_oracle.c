@@ -60,6 +60,7 @@ struct orc_problem {
     double a, b, mpr;   /* PR a(T), b and m(omega) */
     int bct[6];         /* boundary faces -x,+x,-y,+y,-z,+z: ORC_BC_* (zero: closed) */
     double bcv[6];      /* p^D (Pa) or q^N (m/s, outward normal) */
+    int accum;          /* ORC_ACCUM_CONSERVATIVE or ORC_ACCUM_CHAIN_RULE */
 };
 
 orc_problem *orc_problem_new(int nx, int ny, int nz, double dx, double dy, double dz,
@@ -101,6 +102,16 @@ int orc_problem_set_bc(orc_problem *pr, int face, int type, double value) {
     if (type == ORC_BC_DIRICHLET && !(value > 0.0)) return -1;
     pr->bct[face] = type;
     pr->bcv[face] = type == ORC_BC_CLOSED ? 0.0 : value;
+    return 0;
+}
+
+/* Accumulation form: ORC_ACCUM_CONSERVATIVE (the reading this oracle takes by
+ * default) or ORC_ACCUM_CHAIN_RULE (the BDF1 and BDF2 equations of Section 2
+ * as printed: the coefficient of dp/dt at the new level times the difference
+ * quotient of p).  Returns 0, or -1 for an unknown form. */
+int orc_problem_set_accum(orc_problem *pr, int form) {
+    if (form != ORC_ACCUM_CONSERVATIVE && form != ORC_ACCUM_CHAIN_RULE) return -1;
+    pr->accum = form;
     return 0;
 }
 
@@ -201,6 +212,41 @@ static int pr_m(const orc_problem *pr, double p, double *m, double *dm) {
     int bad = orc_pr_z(pr->a, pr->b, pr->T, pr->R, p, &Z, &dZ);
     *m = p / Z;
     *dm = 1.0 / Z - p * dZ / (Z * Z);
+    return bad;
+}
+
+/* Second pressure derivatives of Z and of m = p/Z, by differentiating the
+ * cubic G(Z, p) = Z^3 + c2 Z^2 + c1 Z + c0 = 0 of Section 2 twice along its
+ * root (A = alpha p, B = beta p):
+ *   Z'  = -G_p / G_Z,
+ *   Z'' = -(G_pp + 2 G_Zp Z' + G_ZZ Z'^2) / G_Z,
+ *   m'' = -(2 Z' + p Z'') / Z^2 + 2 p Z'^2 / Z^3.
+ * Needed by the Jacobian of the chain-rule accumulation, whose coefficient is
+ * m' itself. */
+int orc_pr_z2(double a, double b, double T, double R, double p, double *Z, double *dZ, double *d2Z,
+              double *d2m) {
+    double RT = R * T;
+    double al = a / (RT * RT), be = b / RT;
+    double z, dz;
+    int bad = orc_pr_z(a, b, T, R, p, &z, &dz);
+    double B = be * p;
+    double c2 = -(1.0 - B);
+    double c1p = al - 6.0 * be * be * p - 2.0 * be, c1pp = -6.0 * be * be;
+    double c0p = -(2.0 * al * be * p - 2.0 * be * be * p - 3.0 * be * be * be * p * p);
+    double c0pp = -(2.0 * al * be - 2.0 * be * be - 6.0 * be * be * be * p);
+    double c1 = al * p - 3.0 * B * B - 2.0 * B;
+    double GZ = 3.0 * z * z + 2.0 * c2 * z + c1;
+    double GZZ = 6.0 * z + 2.0 * c2;
+    double Gp = be * z * z + c1p * z + c0p;
+    double GZp = 2.0 * be * z + c1p;
+    double Gpp = c1pp * z + c0pp;
+    double z1 = -Gp / GZ;
+    double z2 = -(Gpp + 2.0 * GZp * z1 + GZZ * z1 * z1) / GZ;
+    if (Z) *Z = z;
+    if (dZ) *dZ = z1;
+    if (d2Z) *d2Z = z2;
+    if (d2m) *d2m = -(2.0 * z1 + p * z2) / (z * z) + 2.0 * p * z1 * z1 / (z * z * z);
+    (void)dz;
     return bad;
 }
 
@@ -323,6 +369,16 @@ static void accumulation(const orc_problem *pr, int order, double p, double pn, 
                          double *acc, double *dacc) {
     double m, dm, mn, dmn, mnm1, dmnm1;
     pr_m(pr, p, &m, &dm);
+    if (pr->accum == ORC_ACCUM_CHAIN_RULE) {
+        /* the printed form: [phi p/Z (1/p - Z'/Z)]^{l+1} times the BDF
+         * difference of p, so the bracket is m'(p^{l+1}) D_t p */
+        double d2m;
+        orc_pr_z2(pr->a, pr->b, pr->T, pr->R, p, NULL, NULL, NULL, &d2m);
+        double dtp = order == 2 ? (3.0 * p - 4.0 * pn + pnm1) / 2.0 : p - pn;
+        *acc = dm * dtp;
+        *dacc = d2m * dtp + (order == 2 ? 1.5 : 1.0) * dm;
+        return;
+    }
     pr_m(pr, pn, &mn, &dmn);
     if (order == 2) {
         pr_m(pr, pnm1, &mnm1, &dmnm1);
@@ -590,14 +646,25 @@ static double keys_w(double s) {
     return 0.0;
 }
 
-/* One-dimensional factor of the interpolation from ceil(nf/2) coarse cells to
- * nf fine cells (coarse-to-fine ratio 2, cell-centred).  Fine centre
- * x_i = i + 1/2 (fine cell units); coarse cell J covers fine cells 2J, 2J+1
- * and sits at their centroid.  Coarse indices beyond the domain are clamped to
+/* One-dimensional factor of the interpolation from nc = ceil(nf/r) coarse
+ * cells to nf fine cells, coarse-to-fine ratio r (Section 3.2 with its mesh
+ * ratios; cell-centred nesting).  Fine centre x_i = i + 1/2 (fine cell units);
+ * coarse cell J covers fine cells rJ .. min(rJ + r, nf) - 1 and sits at their
+ * centroid c_J (the last one is short when r does not divide nf).
+ *
+ * Orders 2 and 3 interpolate in the coarse index coordinate s(x): piecewise
+ * linear through the points (c_J, J), continued beyond both ends with slope
+ * 1/r (virtual centroids one coarse spacing outside).  Order 2 is the linear
+ * interpolant between the two centroids around x (the hat function in s);
+ * order 3 weights coarse cells J0-1 .. J0+2 (J0 = floor(s)) by the cubic
+ * convolution kernel W(s - J).  On uniform spacing s = (x - c_0)/r and these
+ * are the printed weights; at a short last cell they use its actual centroid.
+ * Order 1: the parent cell.  Coarse indices beyond the domain are clamped to
  * the edge cell and their weights merged, so every row sums to 1.
  * Row i holds at most 4 entries (sorted columns); rp has nf+1 entries. */
-void orc_interp_1d(int nf, int order, int *rp, int *ci, double *w) {
-    int nc = (nf + 1) / 2;
+void orc_interp_1d_r(int nf, int order, int ratio, int *rp, int *ci, double *w) {
+    int r = ratio;
+    int nc = (nf + r - 1) / r;
     int nnz = 0;
     rp[0] = 0;
     for (int i = 0; i < nf; ++i) {
@@ -608,35 +675,36 @@ void orc_interp_1d(int nf, int order, int *rp, int *ci, double *w) {
         if (nf == 1) {
             cj[0] = 0; cw[0] = 1.0; cnt = 1;
         } else if (order == 1) {
-            /* nearest coarse centroid: the parent cell (the first-order interpolation of Section 3.2) */
-            cj[0] = i / 2; cw[0] = 1.0; cnt = 1;
-        } else if (order == 2) {
-            /* the second-order interpolation of Section 3.2 along one direction: linear between the two
-             * coarse centroids that bracket x (virtual ones at spacing 2
-             * beyond the ends) */
-            double cen_last = ((nf % 2) ? (nf - 0.5) : (nf - 1.0));
-            int J0;
-            double c0, c1;
-            if (x < 1.0) { J0 = -1; c0 = -1.0; c1 = 1.0; }
-            else {
-                J0 = (int)floor((x - 1.0) / 2.0);
-                if (J0 > nc - 1) J0 = nc - 1;
-                c0 = (J0 == nc - 1) ? cen_last : 2.0 * J0 + 1.0;
-                if (J0 + 1 <= nc - 1) c1 = (J0 + 1 == nc - 1) ? cen_last : 2.0 * (J0 + 1) + 1.0;
-                else c1 = c0 + 2.0;
-            }
-            double h = c1 - c0;
-            cj[0] = J0; cw[0] = (c1 - x) / h;
-            cj[1] = J0 + 1; cw[1] = (x - c0) / h;
-            cnt = 2;
+            /* the parent cell (the first-order interpolation of Section 3.2) */
+            cj[0] = i / r; cw[0] = 1.0; cnt = 1;
         } else {
-            /* the third-order interpolation of Section 3.2 along one direction: 4 coarse cells J0-1..J0+2
-             * with weights W((x - c_J)/2) (uniform coarse spacing, even nf) */
-            int J0 = (int)floor((x - 1.0) / 2.0);
-            for (int l = -1; l <= 2; ++l) {
-                int J = J0 + l;
-                double cJ = 2.0 * J + 1.0;
-                cj[cnt] = J; cw[cnt] = keys_w((x - cJ) / 2.0); cnt++;
+            /* index coordinate of x */
+            double first = 0.5 * (double)(r < nf ? r : nf);
+            int lo_last = r * (nc - 1);
+            double last = 0.5 * (double)(lo_last + nf);
+            double sx;
+            if (x <= first) sx = (x - first) / r;
+            else if (x >= last) sx = (nc - 1) + (x - last) / r;
+            else {
+                /* c_J = rJ + r/2 for every full cell, and x < last <= c_{nc-2} + r */
+                int J = (int)floor((x - first) / r);
+                if (J > nc - 2) J = nc - 2;
+                double cJ = r * J + 0.5 * r;
+                double cJ1 = (J + 1 == nc - 1) ? last : cJ + r;
+                sx = J + (x - cJ) / (cJ1 - cJ);
+            }
+            int J0 = (int)floor(sx);
+            double t = sx - J0;
+            if (order == 2) {
+                /* the second-order interpolation of Section 3.2 along one direction */
+                cj[0] = J0; cw[0] = 1.0 - t;
+                cj[1] = J0 + 1; cw[1] = t;
+                cnt = 2;
+            } else {
+                /* the third-order interpolation of Section 3.2 along one direction */
+                for (int l = -1; l <= 2; ++l) {
+                    cj[cnt] = J0 + l; cw[cnt] = keys_w(sx - (J0 + l)); cnt++;
+                }
             }
         }
         /* clamp out-of-range coarse indices and merge equal columns */
@@ -648,14 +716,14 @@ void orc_interp_1d(int nf, int order, int *rp, int *ci, double *w) {
             if (J < 0) J = 0;
             if (J > nc - 1) J = nc - 1;
             int f = -1;
-            for (int r = 0; r < oc; ++r) if (oj[r] == J) f = r;
+            for (int rr = 0; rr < oc; ++rr) if (oj[rr] == J) f = rr;
             if (f < 0) { oj[oc] = J; ow[oc] = cw[q]; oc++; }
             else ow[f] += cw[q];
         }
         /* sort by column, drop exact zeros */
         for (int a = 0; a < oc; ++a)
             for (int b = a + 1; b < oc; ++b)
-                if (oj[b] < oj[a]) { int t = oj[a]; oj[a] = oj[b]; oj[b] = t; double u = ow[a]; ow[a] = ow[b]; ow[b] = u; }
+                if (oj[b] < oj[a]) { int tt = oj[a]; oj[a] = oj[b]; oj[b] = tt; double u = ow[a]; ow[a] = ow[b]; ow[b] = u; }
         for (int q = 0; q < oc; ++q) {
             if (ow[q] == 0.0) continue;
             ci[nnz] = oj[q]; w[nnz++] = ow[q];
@@ -664,11 +732,16 @@ void orc_interp_1d(int nf, int order, int *rp, int *ci, double *w) {
     }
 }
 
+/* ratio 2 */
+void orc_interp_1d(int nf, int order, int *rp, int *ci, double *w) {
+    orc_interp_1d_r(nf, order, 2, rp, ci, w);
+}
+
 /* Tensor product of the 1D factors: P (nf x nc) on the cell-centred grid */
-static csr interp_matrix(int nx, int ny, int nz, int order, int *cnx, int *cny, int *cnz) {
-    int ncx = nx > 1 ? (nx + 1) / 2 : 1;
-    int ncy = ny > 1 ? (ny + 1) / 2 : 1;
-    int ncz = nz > 1 ? (nz + 1) / 2 : 1;
+static csr interp_matrix(int nx, int ny, int nz, int order, int ratio, int *cnx, int *cny, int *cnz) {
+    int ncx = nx > 1 ? (nx + ratio - 1) / ratio : 1;
+    int ncy = ny > 1 ? (ny + ratio - 1) / ratio : 1;
+    int ncz = nz > 1 ? (nz + ratio - 1) / ratio : 1;
     *cnx = ncx; *cny = ncy; *cnz = ncz;
     int *rx = (int *)xcalloc(nx + 1, sizeof(int)), *cx = (int *)xcalloc(4 * nx, sizeof(int));
     int *ry = (int *)xcalloc(ny + 1, sizeof(int)), *cy = (int *)xcalloc(4 * ny, sizeof(int));
@@ -676,9 +749,9 @@ static csr interp_matrix(int nx, int ny, int nz, int order, int *cnx, int *cny, 
     double *wx = (double *)xcalloc(4 * nx, sizeof(double));
     double *wy = (double *)xcalloc(4 * ny, sizeof(double));
     double *wz = (double *)xcalloc(4 * nz, sizeof(double));
-    orc_interp_1d(nx, order, rx, cx, wx);
-    orc_interp_1d(ny, order, ry, cy, wy);
-    orc_interp_1d(nz, order, rz, cz, wz);
+    orc_interp_1d_r(nx, order, ratio, rx, cx, wx);
+    orc_interp_1d_r(ny, order, ratio, ry, cy, wy);
+    orc_interp_1d_r(nz, order, ratio, rz, cz, wz);
     csr P;
     P.n = nx * ny * nz;
     P.m = ncx * ncy * ncz;
@@ -1240,7 +1313,8 @@ orc_mg *orc_mg_new(int nx, int ny, int nz, int n, const int *rp, const int *ci,
     memcpy(f->A.v, v, nnz * sizeof(double));
     for (int l = 0; l + 1 < mg->L; ++l) {
         level *fl = &mg->lev[l], *cl = &mg->lev[l + 1];
-        fl->P = interp_matrix(fl->nx, fl->ny, fl->nz, d->interp_order, &cl->nx, &cl->ny, &cl->nz);
+        fl->P = interp_matrix(fl->nx, fl->ny, fl->nz, d->interp_order, d->ratio > 0 ? d->ratio : 2,
+                              &cl->nx, &cl->ny, &cl->nz);
         fl->has_p = 1;
         cl->n = cl->nx * cl->ny * cl->nz;
         /* Galerkin coarse operator A_c = P^T A P */

@@ -34,6 +34,7 @@ typedef struct {
     int coarse_restart;
     int tx, ty, tz;         /* > 0: box edge in cells on the finest level (boxes = ceil(n/t)) */
     int fill;               /* subdomain ILU level of fill k (0: ILU(0)): ILU on the level-k pattern */
+    int ratio;              /* coarse-to-fine mesh ratio per direction (0: 2) */
 } orc_mg_desc;
 
 typedef struct {
@@ -72,6 +73,10 @@ void orc_problem_free(orc_problem *pr);
 #define ORC_BC_DIRICHLET 1   /* value: p^D in Pa */
 #define ORC_BC_NEUMANN 2     /* value: q^N = v.n in m/s, n the outward normal */
 int orc_problem_set_bc(orc_problem *pr, int face, int type, double value);
+/* accumulation forms */
+#define ORC_ACCUM_CONSERVATIVE 0   /* phi V (m(p^{l+1}) - m(p^l))/dt and its BDF2 analogue */
+#define ORC_ACCUM_CHAIN_RULE 1     /* phi V m'(p^{l+1}) (p^{l+1} - p^l)/dt, as Section 2 prints it */
+int orc_problem_set_accum(orc_problem *pr, int form);
 
 /* PR-EOS */
 void orc_pr_params(double Tc, double pc, double omega, double T, double R,
@@ -79,6 +84,8 @@ void orc_pr_params(double Tc, double pc, double omega, double T, double R,
 void orc_acentric_terms(double Tr, double *f0, double *f1);
 double orc_acentric(double pc, double Tc, double Tb);
 int orc_pr_z(double a, double b, double T, double R, double p, double *Z, double *dZdp);
+int orc_pr_z2(double a, double b, double T, double R, double p, double *Z, double *dZ, double *d2Z,
+              double *d2m);
 void orc_pr_eval(const orc_problem *pr, int n, const double *p, double *Z, double *dZ,
                  double *msc, double *dmsc);
 
@@ -108,6 +115,7 @@ void orc_mg_sub_factors(const orc_mg *mg, int level, int s, int *cells, int *own
 /* Sparse utilities */
 void orc_csr_matvec(int n, const int *rp, const int *ci, const double *v, const double *x, double *y);
 void orc_interp_1d(int nf, int order, int *rp, int *ci, double *w);  /* rows nf, cols ceil(nf/2), <=4 per row */
+void orc_interp_1d_r(int nf, int order, int ratio, int *rp, int *ci, double *w);  /* cols ceil(nf/ratio) */
 void orc_ilu0(int n, const int *rp, const int *ci, double *v);        /* in place, sorted columns */
 void orc_ilu0_solve(int n, const int *rp, const int *ci, const double *v, const double *r, double *z);
 

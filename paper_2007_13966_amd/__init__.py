@@ -7,6 +7,7 @@ converts results.  There is no CPU fallback: without the built library the
 import of :mod:`paper_2007_13966_amd._lib` raises.
 """
 import ctypes as C
+import sys
 
 import numpy as np
 
@@ -84,6 +85,7 @@ def ras_desc(s):
     d.precision = PRECISIONS[s.precision]
     d.tx, d.ty, d.tz = s.tile
     d.fill = getattr(s, "fill", 0)
+    d.ratio = getattr(s, "ratio", 2)
     return d
 
 
@@ -162,6 +164,7 @@ class Grid:
         d.res = res
         d.fluid = L.nks_fluid(fl.Tc, fl.pc, fl.omega, fl.T, fl.W, fl.R, fl.mu, getattr(fl, "Tb", None) or 0.0)
         d.gravity = 1 if problems[0].gravity else 0
+        d.accum = L.ACCUM_FORMS[getattr(problems[0], "accum", "conservative")]
         d.g = problems[0].g
         d.stream = self.stream.cuda_stream
         self.allocator = TorchAllocator(self.device, self.stream) if torch_allocator else None
@@ -181,7 +184,9 @@ class Grid:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h and _handle is not None:
+        # at interpreter exit the allocator behind the handle (torch's) may
+        # already be gone: the process is ending, leave the memory to it
+        if h and _handle is not None and not sys.is_finalizing():
             _handle.nks_destroy_grid(h)
             self.h = None
 
@@ -305,6 +310,10 @@ class Grid:
 
     def newton_step(self, p, pn, pnm1, dt, order, settings, raise_on_fail=True):
         st = L.nks_newton_stats()
+        why = (C.c_int * self.B)()
+        rel = (C.c_double * self.B)()
+        st.stop_reason = C.cast(why, C.POINTER(C.c_int))
+        st.rel_res = C.cast(rel, C.POINTER(C.c_double))
         nd, rd = newton_desc(settings), ras_desc(settings)
         with _Ordered(self):
             code = lib().nks_newton_step(self.h, _vp(p), _vp(pn), _vp(pnm1 if pnm1 is not None else pn),
@@ -316,7 +325,8 @@ class Grid:
                     fnorm=st.fnorm, fnorms=list(st.fnorms[:min(k, 64)]),
                     lits=list(st.lits[:min(k, 64)]), lambdas=list(st.lambdas[:min(k, 64)]),
                     t_residual=st.t_residual, t_jacobian=st.t_jacobian, t_setup=st.t_setup,
-                    t_gmres=st.t_gmres, t_linesearch=st.t_linesearch)
+                    t_gmres=st.t_gmres, t_linesearch=st.t_linesearch,
+                    stop_reason=[L.STOP_REASONS[int(w)] for w in why], rel_res=list(rel))
 
 
 class Matrix:
@@ -330,7 +340,9 @@ class Matrix:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h and _handle is not None:
+        # at interpreter exit the allocator behind the handle (torch's) may
+        # already be gone: the process is ending, leave the memory to it
+        if h and _handle is not None and not sys.is_finalizing():
             _handle.nks_destroy_matrix(h)
             self.h = None
 
@@ -384,7 +396,9 @@ class Ras:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h and _handle is not None:
+        # at interpreter exit the allocator behind the handle (torch's) may
+        # already be gone: the process is ending, leave the memory to it
+        if h and _handle is not None and not sys.is_finalizing():
             _handle.nks_destroy_ras(h)
             self.h = None
 

@@ -37,7 +37,10 @@ class nks_reservoir_desc(C.Structure):
 class nks_grid_desc(C.Structure):
     _fields_ = [("nres", C.c_int), ("res", C.POINTER(nks_reservoir_desc)), ("fluid", nks_fluid),
                 ("gravity", C.c_int), ("g", C.c_double), ("stream", C.c_void_p),
-                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p)]
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p), ("accum", C.c_int)]
+
+
+ACCUM_FORMS = {"conservative": 0, "chain_rule": 1}
 
 
 class nks_ras_desc(C.Structure):
@@ -46,7 +49,8 @@ class nks_ras_desc(C.Structure):
                 ("cycle", C.c_int), ("mu", C.c_int), ("nu", C.c_int),
                 ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int),
                 ("coarse_restart", C.c_int), ("precision", C.c_int),
-                ("tx", C.c_int), ("ty", C.c_int), ("tz", C.c_int), ("fill", C.c_int)]
+                ("tx", C.c_int), ("ty", C.c_int), ("tz", C.c_int), ("fill", C.c_int),
+                ("ratio", C.c_int)]
 
 
 class nks_gmres_desc(C.Structure):
@@ -73,7 +77,11 @@ class nks_newton_stats(C.Structure):
                 ("fnorm0", C.c_double), ("fnorm", C.c_double), ("fnorms", C.c_double * 64),
                 ("lits", C.c_int * 64), ("lambdas", C.c_double * 64),
                 ("t_residual", C.c_double), ("t_jacobian", C.c_double), ("t_setup", C.c_double),
-                ("t_gmres", C.c_double), ("t_linesearch", C.c_double)]
+                ("t_gmres", C.c_double), ("t_linesearch", C.c_double),
+                ("stop_reason", C.POINTER(C.c_int)), ("rel_res", C.POINTER(C.c_double))]
+
+
+STOP_REASONS = {0: "none", 1: "tolerance", 2: "floor", 3: "step"}
 
 
 class nks_adjoint_stats(C.Structure):

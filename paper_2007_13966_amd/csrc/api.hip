@@ -503,8 +503,12 @@ int nks_setup_grid(const nks_grid_desc *d, nks_grid **out) {
             g.bct.upload(&g.al, bct, g.s);
             g.bcv.upload(&g.al, bcv, g.s);
         }
+        if (d->accum != NKS_ACCUM_CONSERVATIVE && d->accum != NKS_ACCUM_CHAIN_RULE)
+            fail(NKS_EINVAL, "unknown accumulation form %d", d->accum);
+        g.accum = d->accum;
         g.m.alloc(&g.al, N);
         g.dm.alloc(&g.al, N);
+        if (g.accum == NKS_ACCUM_CHAIN_RULE) g.d2m.alloc(&g.al, N);
         g.hist.alloc(&g.al, N);
         g.tmp.alloc(&g.al, N);
         g.flags.alloc(&g.al, B);
@@ -682,7 +686,7 @@ static void check_ras_desc(const nks_ras_desc *d) {
     if (d->variant < 0 || d->variant > 2 || d->interp_order < 1 || d->interp_order > 3 || d->cycle < 0 ||
         d->cycle > 4 || d->mu < 0 || d->nu < 0 || d->precision < 0 || d->precision > 2 ||
         d->coarse_restart < 1 || d->coarse_maxit < 1 || d->tx < 0 || d->ty < 0 || d->tz < 0 || d->fill < 0 ||
-        d->fill > 4)
+        d->fill > 4 || d->ratio < 0 || d->ratio == 1 || d->ratio > 16)
         fail(NKS_EINVAL, "bad preconditioner option");
 }
 
@@ -815,6 +819,10 @@ int nks_gmres_solve(nks_matrix *J, nks_ras *M, const double *b, double *x, const
         std::vector<int> its, conv;
         std::vector<double> res;
         gm.stats(its, res, conv, g.s);
+        if (M) {
+            if (d->transpose) M->t.MT->check_pivots();
+            else M->r.check_pivots();
+        }
         if (st) {
             st->iterations = 0;
             st->total_iterations = 0;
@@ -883,7 +891,7 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
         HIPC(hipMemsetAsync(g.flags.p, 0, sizeof(int) * B, s));
         launch_history(g, pn, pnm1, order);
         std::vector<double> hn(B), hs(B), ht(B), hslope(B), lam(B), lam_prev(B), f_prev(B), stop(B);
-        std::vector<int> act(B), flags(B), acc(B);
+        std::vector<int> act(B), flags(B), acc(B), why(B, 0);
         // per-reservoir norms and non-physical flags: one round trip through
         // pinned memory (it also completes any copy queued before it)
         auto norms = [&](const double *x, std::vector<double> &out) {
@@ -905,11 +913,13 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
         launch_props(g, p);
         launch_flux(g, p, dt, order, W.F.p, nullptr);
         norms(W.F.p, hn);
+        const std::vector<double> f0 = hn;
         S.t_residual += now() - t0;
         for (int b = 0; b < B; ++b) {
             if (flags[b] || !std::isfinite(hn[b])) fail(NKS_ENONPHYSICAL, "reservoir %d: non-physical initial state", b);
             stop[b] = std::max(nd->eps_r * hn[b], nd->eps_a);
             act[b] = hn[b] > stop[b];
+            if (!act[b]) why[b] = NKS_STOP_TOL;
             S.fnorm0 = std::max(S.fnorm0, hn[b]);
         }
         int status = 0;
@@ -934,6 +944,7 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
                 for (int b = 0; b < B; ++b) {
                     if (act[b] && hn[b] <= std::ldexp(fl[b], -53)) {
                         act[b] = 0;
+                        why[b] = NKS_STOP_FLOOR;
                         changed = true;
                     }
                     left |= act[b] != 0;
@@ -1062,8 +1073,12 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             for (int b = 0; b < B; ++b) {
                 if (act[b]) {
                     hn[b] = ht[b];
-                    if (hn[b] <= stop[b] || (small[b] && lam[b] == 1.0)) act[b] = 0;
-                    if (nd->stol > 0.0 && lam[b] * snorm[b] <= nd->stol * xnorm[b]) act[b] = 0;
+                    if (hn[b] <= stop[b]) { act[b] = 0; why[b] = NKS_STOP_TOL; }
+                    else if (small[b] && lam[b] == 1.0) { act[b] = 0; why[b] = NKS_STOP_STEP; }
+                    if (act[b] && nd->stol > 0.0 && lam[b] * snorm[b] <= nd->stol * xnorm[b]) {
+                        act[b] = 0;
+                        why[b] = NKS_STOP_STEP;
+                    }
                 }
                 fmax = std::max(fmax, hn[b]);
             }
@@ -1083,7 +1098,15 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
         for (int b = 0; b < B; ++b) S.fnorm = std::max(S.fnorm, hn[b]);
         S.status = status;
         HIPC(hipStreamSynchronize(s));
-        if (st) *st = S;
+        if (st) {
+            S.stop_reason = st->stop_reason;
+            S.rel_res = st->rel_res;
+            for (int b = 0; b < B; ++b) {
+                if (S.stop_reason) S.stop_reason[b] = why[b];
+                if (S.rel_res) S.rel_res[b] = f0[b] > 0.0 ? hn[b] / f0[b] : 0.0;
+            }
+            *st = S;
+        }
         if (status != 0) fail(NKS_ENOTCONVERGED, status == 2 ? "line search failed" : "Newton iteration limit");
     });
 }
@@ -1099,6 +1122,8 @@ int nks_adjoint(nks_grid *gh, int nsteps, const double *const *p_hist, const int
             fail(NKS_EINVAL, "bad arguments");
         if (gd->restart < 1 || gd->restart > 30 || gd->maxit < 1) fail(NKS_EINVAL, "bad GMRES descriptor");
         check_ras_desc(rd);
+        if (gh->g.accum != NKS_ACCUM_CONSERVATIVE)
+            fail(NKS_EINVAL, "the discrete adjoint is defined for the conservative accumulation only");
         for (int n = 0; n <= nsteps; ++n)
             if (!p_hist[n]) fail(NKS_EINVAL, "p_hist[%d] is null", n);
         for (int n = 1; n <= nsteps; ++n)

@@ -144,8 +144,10 @@ struct Grid {
     DBuf<int> bct;                       // 6*B boundary types (-x,+x,-y,+y,-z,+z), empty: all closed
     DBuf<double> bcv;                    // 6*B boundary values
     double a = 0, b = 0, RT = 0, W = 0, mu = 0, g = 0;
+    int accum = NKS_ACCUM_CONSERVATIVE;
     // scratch
     DBuf<double> m, dm, hist, tmp;
+    DBuf<double> d2m;                    // chain-rule accumulation only
     DBuf<int> flags;                     // per block: non-physical state
 };
 

@@ -114,10 +114,29 @@ __global__ void k_pore_volume(const Blk *blk, int B, int N, const double *geo, c
     pv[i] = geo[3 * b] * geo[3 * b + 1] * geo[3 * b + 2] * phi[i];
 }
 
+// d2m/dp2 for m = p/Z, from the second derivative of the cubic along its
+// root: with f(Z, p) = Z^3 + c2 Z^2 + c1 Z + c0 (A = a p/(RT)^2, B = b p/RT),
+// Z' = -f_p/f_Z and Z'' = -(f_pp + 2 f_Zp Z' + f_ZZ Z'^2)/f_Z, then
+// m'' = 2 p Z'^2/Z^3 - (2 Z' + p Z'')/Z^2.  Only the chain-rule
+// accumulation's Jacobian needs it (its coefficient is m' itself).
+__device__ __forceinline__ double density_curvature(double a, double b, double RT, double p) {
+    const PRState s = pr_solve(a, b, RT, p);
+    const double z = s.Z, z1 = s.dZ;
+    const double al = a / (RT * RT), be = b / RT;
+    const double B = be * p;
+    const double fZ = (3.0 * z + 2.0 * (B - 1.0)) * z + (al * p - B * (3.0 * B + 2.0));
+    const double fZZ = 6.0 * z + 2.0 * (B - 1.0);
+    const double c1p = al - 2.0 * be - 6.0 * be * B;
+    const double fZp = 2.0 * be * z + c1p;
+    const double fpp = -6.0 * be * be * z - 2.0 * be * (al - be - 3.0 * be * B);
+    const double z2 = -(fpp + 2.0 * fZp * z1 + fZZ * z1 * z1) / fZ;
+    return 2.0 * p * z1 * z1 / (z * z * z) - (2.0 * z1 + p * z2) / (z * z);
+}
+
 // ---------------------------------------------------------------- PR per cell
-// m, dm at p; flags[b] |= 1 on a non-physical state.
+// m, dm at p (and d2m when asked); flags[b] |= 1 on a non-physical state.
 __global__ void k_props(const Blk *blk, int B, int N, double a, double b, double RT,
-                        const double *p, double *m, double *dm, int *flags) {
+                        const double *p, double *m, double *dm, double *d2m, int *flags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double mi, dmi;
@@ -125,14 +144,21 @@ __global__ void k_props(const Blk *blk, int B, int N, double a, double b, double
     scaled_density(a, b, RT, p[i], mi, dmi, bad);
     m[i] = mi;
     dm[i] = dmi;
+    if (d2m) d2m[i] = density_curvature(a, b, RT, p[i]);
     if (bad && flags) atomicOr(&flags[find_blk(blk, B, i)], 1);
 }
 
-// history part of the accumulation: order 1: -m(p_n); order 2: (-4 m(p_n) + m(p_nm1))/2
+// history part of the accumulation.  Conservative form: order 1: -m(p_n);
+// order 2: (-4 m(p_n) + m(p_nm1))/2.  Chain-rule form (the printed BDF
+// equations): the same combinations of p instead of m.
 __global__ void k_history(int N, double a, double b, double RT, const double *pn,
-                          const double *pnm1, int order, double *hist) {
+                          const double *pnm1, int order, int chain, double *hist) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
+    if (chain) {
+        hist[i] = order == 2 ? 0.5 * (pnm1[i] - 4.0 * pn[i]) : -pn[i];
+        return;
+    }
     double mn, d;
     bool bad;
     scaled_density(a, b, RT, pn[i], mn, d, bad);
@@ -151,6 +177,8 @@ struct FluxArgs {
     int B, N, dim;
     const double *geo, *tx, *ty, *tz, *pv, *src;
     const double *p, *m, *dm, *hist;
+    const double *d2m;                     // chain-rule accumulation: m'' per cell, else unused
+    int chain;                             // 1: accumulation m'(p) D_t p (the printed BDF form)
     double cacc, inv_dt, inv_mu, crho_g;   // crho_g = g W/(RT)
     double *F;
     double *J;                             // K*N stencil coefficients or nullptr
@@ -228,8 +256,17 @@ __global__ void k_flux(FluxArgs A) {
     const int sx = 1, sy = c.nx, sz = c.nx * c.ny;
     const double dz = A.geo[3 * c.b + 2];
     const double pi = A.p[i], mi = A.m[i], dmi = A.dm[i];
-    double Fi = A.pv[i] * A.inv_dt * (A.cacc * mi + A.hist[i]);
-    double diag = A.pv[i] * A.inv_dt * A.cacc * dmi;
+    double Fi, diag;
+    if (A.chain) {
+        // [phi m'(p)]^{l+1} times the BDF difference of p; its p derivative
+        // adds m''(p) times that difference
+        const double dtp = A.cacc * pi + A.hist[i];
+        Fi = A.pv[i] * A.inv_dt * dmi * dtp;
+        diag = A.J ? A.pv[i] * A.inv_dt * (A.d2m[i] * dtp + A.cacc * dmi) : 0.0;
+    } else {
+        Fi = A.pv[i] * A.inv_dt * (A.cacc * mi + A.hist[i]);
+        diag = A.pv[i] * A.inv_dt * A.cacc * dmi;
+    }
     double o[6] = {0, 0, 0, 0, 0, 0};
     // neighbour order -z, -y, -x, +x, +y, +z (increasing cell index)
     if (A.dim == 3 && c.z > 0) face(A, pi, mi, dmi, i - sz, A.tz[i - sz], dz, Fi, diag, o[0]);
@@ -381,6 +418,8 @@ static FluxArgs flux_args(Grid &g, const double *p, double dt, int order, double
     A.m = g.m.p;
     A.dm = g.dm.p;
     A.hist = g.hist.p;
+    A.d2m = g.d2m.p;
+    A.chain = g.accum == NKS_ACCUM_CHAIN_RULE ? 1 : 0;
     A.cacc = order == 2 ? 1.5 : 1.0;
     A.inv_dt = 1.0 / dt;
     A.inv_mu = 1.0 / g.mu;
@@ -397,14 +436,15 @@ static FluxArgs flux_args(Grid &g, const double *p, double dt, int order, double
 void launch_history(Grid &g, const double *pn, const double *pnm1, int order) {
     const int N = g.sp.N;
     k_history<<<nblk(N, 256), 256, 0, g.s>>>(N, g.a, g.b, g.RT, pn, order == 2 ? pnm1 : pn,
-                                             order, g.hist.p);
+                                             order, g.accum == NKS_ACCUM_CHAIN_RULE ? 1 : 0, g.hist.p);
     KCHECK();
 }
 
 void launch_props(Grid &g, const double *p) {
     const int N = g.sp.N;
     k_props<<<nblk(N, 256), 256, 0, g.s>>>(g.sp.blk.p, g.sp.B, N, g.a, g.b, g.RT, p, g.m.p,
-                                           g.dm.p, g.flags.p);
+                                           g.dm.p, g.accum == NKS_ACCUM_CHAIN_RULE ? g.d2m.p : nullptr,
+                                           g.flags.p);
     KCHECK();
 }
 

@@ -33,9 +33,10 @@ struct Interp1 {
     // fine index row (block-local index + row offset of the block): <= 4 (coarse, w)
     std::vector<int> rcnt, rj;
     std::vector<double> rw;
-    // coarse index column: <= 8 (fine, w)
+    // coarse index column: up to cs (fine, w), cs the longest column
     std::vector<int> ccnt, ci;
     std::vector<double> cw;
+    int cs = 1;
     std::vector<int> roff, coff;   // per block offsets into rows / cols
     DBuf<int> d_rcnt, d_rj, d_ccnt, d_ci, d_roff, d_coff;
     DBuf<double> d_rw, d_cw;

@@ -322,50 +322,52 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
 }
 
 // ---------------------------------------------------------------- host: interpolation
-// One direction of the interpolation from ceil(nf/2) coarse cells to nf fine
-// cells.  Fine centre x_i = i + 1/2 in fine-cell units; coarse cell J covers
-// fine 2J and 2J+1 and sits at their centroid.  Order 1: the parent cell
-// (nearest centroid, the first-order interpolation of Section 3.2).  Order 2:
-// linear between the two bracketing centroids (one factor of the second-order
-// interpolation).  Order 3: cubic convolution with the kernel W(s) of the
-// third-order interpolation over four coarse cells at spacing 2.  Indices beyond the domain are clamped to the edge cell and
-// their weights merged.
-static void interp_weights(int nf, int order, int i, std::vector<std::pair<int, double>> &out) {
+// One direction of the interpolation from nc = ceil(nf/r) coarse cells to nf
+// fine cells, coarse-to-fine ratio r.  Fine centre x_i = i + 1/2 in fine-cell
+// units; coarse cell J covers fine cells rJ .. min(rJ + r, nf) - 1 and sits at
+// their centroid.  Order 1: the parent cell (the first-order interpolation of
+// Section 3.2).  Orders 2 and 3 work in the coarse index coordinate s(x),
+// linear between consecutive centroids and continued one coarse spacing r
+// past each end: order 2 is linear between the two centroids around x (one
+// factor of the second-order interpolation), order 3 the cubic convolution
+// W(s - J) over four coarse cells (the third-order interpolation).  Indices
+// beyond the domain are clamped to the edge cell and their weights merged.
+static double keys_kernel(double t) {
+    t = std::fabs(t);
+    if (t < 1.0) return (1.5 * t - 2.5) * t * t + 1.0;
+    if (t < 2.0) return ((-0.5 * t + 2.5) * t - 4.0) * t + 2.0;
+    return 0.0;
+}
+
+static void interp_weights(int nf, int order, int ratio, int i, std::vector<std::pair<int, double>> &out) {
     out.clear();
-    const int nc = (nf + 1) / 2;
+    const int nc = (nf + ratio - 1) / ratio;
     if (nf == 1) {
         out.push_back({0, 1.0});
         return;
     }
-    const double x = i + 0.5;
     std::vector<std::pair<int, double>> raw;
     if (order == 1) {
-        raw.push_back({i / 2, 1.0});
-    } else if (order == 2) {
-        // bracketing centroids
-        int J0 = (int)std::floor((x - 1.0) / 2.0);
-        if (x < 1.0) J0 = -1;
-        if (J0 > nc - 1) J0 = nc - 1;
-        const double cl = (nf & 1) ? nf - 0.5 : nf - 1.0;   // last centroid
-        auto cen = [&](int J) -> double {
-            if (J < 0) return -1.0;
-            if (J == nc - 1) return cl;
-            if (J > nc - 1) return cl + 2.0;
-            return 2.0 * J + 1.0;
-        };
-        const double c0 = cen(J0), c1 = cen(J0 + 1);
-        const double h = c1 - c0;
-        raw.push_back({J0, (c1 - x) / h});
-        raw.push_back({J0 + 1, (x - c0) / h});
+        raw.push_back({i / ratio, 1.0});
     } else {
-        const int J0 = (int)std::floor((x - 1.0) / 2.0);
-        for (int l = -1; l <= 2; ++l) {
-            const int J = J0 + l;
-            const double s = std::fabs((x - (2.0 * J + 1.0)) / 2.0);
-            double w = 0.0;
-            if (s < 1.0) w = 1.5 * s * s * s - 2.5 * s * s + 1.0;
-            else if (s < 2.0) w = -0.5 * s * s * s + 2.5 * s * s - 4.0 * s + 2.0;
-            raw.push_back({J, w});
+        // centroids with a virtual one a coarse spacing past each end:
+        // knot k of the list is coarse index k - 1
+        std::vector<double> knot(nc + 2);
+        for (int J = 0; J < nc; ++J) knot[J + 1] = 0.5 * (ratio * J + std::min(ratio * (J + 1), nf));
+        knot[0] = knot[1] - ratio;
+        knot[nc + 1] = knot[nc] + ratio;
+        const double x = i + 0.5;
+        // the knot interval [knot[k], knot[k+1]) holding x
+        int k = (int)(std::upper_bound(knot.begin(), knot.end(), x) - knot.begin()) - 1;
+        k = std::min(std::max(k, 0), nc);
+        const double sx = (k - 1) + (x - knot[k]) / (knot[k + 1] - knot[k]);
+        const int J0 = (int)std::floor(sx);
+        const double t = sx - J0;
+        if (order == 2) {
+            raw.push_back({J0, 1.0 - t});
+            raw.push_back({J0 + 1, t});
+        } else {
+            for (int l = -1; l <= 2; ++l) raw.push_back({J0 + l, keys_kernel(sx - (J0 + l))});
         }
     }
     for (auto &p : raw) {
@@ -380,36 +382,46 @@ static void interp_weights(int nf, int order, int i, std::vector<std::pair<int, 
               out.end());
 }
 
-static void build_interp(Interp1 &ip, const std::vector<int> &nfs, int order, Alloc *al, hipStream_t s) {
+static void build_interp(Interp1 &ip, const std::vector<int> &nfs, int order, int ratio, Alloc *al, hipStream_t s) {
     ip.rcnt.clear(); ip.rj.clear(); ip.rw.clear();
     ip.ccnt.clear(); ip.ci.clear(); ip.cw.clear();
     ip.roff.clear(); ip.coff.clear();
     std::vector<std::pair<int, double>> w;
+    // rows first; the column lists are the transposed rows, with a stride of
+    // the longest column
+    std::vector<std::vector<std::pair<int, double>>> cols;
     for (int nf : nfs) {
-        const int nc = nf > 1 ? (nf + 1) / 2 : 1;
-        const int r0 = (int)ip.rcnt.size(), c0 = (int)ip.ccnt.size();
+        const int nc = nf > 1 ? (nf + ratio - 1) / ratio : 1;
+        const int r0 = (int)ip.rcnt.size(), c0 = (int)cols.size();
         ip.roff.push_back(r0);
         ip.coff.push_back(c0);
         ip.rcnt.resize(r0 + nf, 0);
         ip.rj.resize((size_t)(r0 + nf) * 4, 0);
         ip.rw.resize((size_t)(r0 + nf) * 4, 0.0);
-        ip.ccnt.resize(c0 + nc, 0);
-        ip.ci.resize((size_t)(c0 + nc) * 8, 0);
-        ip.cw.resize((size_t)(c0 + nc) * 8, 0.0);
+        cols.resize(c0 + nc);
         for (int i = 0; i < nf; ++i) {
-            interp_weights(nf, order, i, w);
+            interp_weights(nf, order, ratio, i, w);
             if (w.size() > 4) fail(NKS_EINVAL, "interpolation row with %zu entries", w.size());
             for (auto &p : w) {
                 const int r = r0 + i;
                 ip.rj[(size_t)r * 4 + ip.rcnt[r]] = p.first;
                 ip.rw[(size_t)r * 4 + ip.rcnt[r]] = p.second;
                 ip.rcnt[r]++;
-                const int c = c0 + p.first;
-                if (ip.ccnt[c] >= 8) fail(NKS_EINVAL, "interpolation column overflow");
-                ip.ci[(size_t)c * 8 + ip.ccnt[c]] = i;
-                ip.cw[(size_t)c * 8 + ip.ccnt[c]] = p.second;
-                ip.ccnt[c]++;
+                cols[c0 + p.first].push_back({i, p.second});
             }
+        }
+    }
+    size_t cs = 1;
+    for (auto &c : cols) cs = std::max(cs, c.size());
+    ip.cs = (int)cs;
+    ip.ccnt.assign(cols.size(), 0);
+    ip.ci.assign(cols.size() * cs, 0);
+    ip.cw.assign(cols.size() * cs, 0.0);
+    for (size_t c = 0; c < cols.size(); ++c) {
+        ip.ccnt[c] = (int)cols[c].size();
+        for (size_t q = 0; q < cols[c].size(); ++q) {
+            ip.ci[c * cs + q] = cols[c][q].first;
+            ip.cw[c * cs + q] = cols[c][q].second;
         }
     }
     ip.d_rcnt.upload(al, ip.rcnt, s);
@@ -1324,6 +1336,7 @@ struct Rows3Args {
     const double *r;
     double *z, *zext;
     const int *mask;
+    int *err;             // the level's error word: bit 2 set when a bounded wait gives up
     int variant, accumulate;
     int kmap[16];         // run slot -> stencil index: lower (z, y, x) then upper (x, y, z); -1 padding
 };
@@ -1392,10 +1405,18 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
     const int pz = MULTI ? 64 / ey : ez;          // planes per sweeping wavefront
     const int W = MULTI ? (ez + pz - 1) / pz : 1;
     const int w = threadIdx.x >> 6;
+    // a wait that reaches the spin limit marks the level's error word, so the
+    // next check reports the call as failed instead of returning a sweep over
+    // stale values
     auto wait_for = [&](const int *p, int need) {
         int spins = 0;
-        while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need && ++spins < (1 << 22))
+        while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
+            if (++spins >= (1 << 22)) {
+                if ((threadIdx.x & 63) == 0) atomicOr(a.err, 2);
+                break;
+            }
             __builtin_amdgcn_s_sleep(1);
+        }
     };
     if (w < W) {
         const int r = threadIdx.x & 63;
@@ -1685,6 +1706,7 @@ struct XferArgs {
     int B, Nf, Nc;
     const int *rcnt[3], *rj[3], *ccnt[3], *ci[3], *roff[3], *coff[3];
     const double *rw[3], *cw[3];
+    int cs[3];            // column stride of ci / cw per direction
     const int *mask;
 };
 
@@ -1700,14 +1722,14 @@ __global__ void k_restrict(XferArgs a, const double *rf, double *rc) {
     const int cx = a.coff[0][b] + X, cy = a.coff[1][b] + Y, cz = a.coff[2][b] + Z;
     double s = 0.0;
     for (int qz = 0; qz < a.ccnt[2][cz]; ++qz) {
-        const int fz = a.ci[2][cz * 8 + qz];
-        const double wz = a.cw[2][cz * 8 + qz];
+        const int fz = a.ci[2][cz * a.cs[2] + qz];
+        const double wz = a.cw[2][cz * a.cs[2] + qz];
         for (int qy = 0; qy < a.ccnt[1][cy]; ++qy) {
-            const int fy = a.ci[1][cy * 8 + qy];
-            const double wy = a.cw[1][cy * 8 + qy];
+            const int fy = a.ci[1][cy * a.cs[1] + qy];
+            const double wy = a.cw[1][cy * a.cs[1] + qy];
             for (int qx = 0; qx < a.ccnt[0][cx]; ++qx) {
-                const int fx = a.ci[0][cx * 8 + qx];
-                const double wx = a.cw[0][cx * 8 + qx];
+                const int fx = a.ci[0][cx * a.cs[0] + qx];
+                const double wx = a.cw[0][cx * a.cs[0] + qx];
                 s += (wx * wy * wz) * rf[fb.off + fx + fb.nx * (fy + fb.ny * fz)];
             }
         }
@@ -1757,14 +1779,14 @@ __global__ void k_rap(XferArgs a, const double *Af, int Kf, const int8_t *offf, 
     const int cx = a.coff[0][b] + X, cy = a.coff[1][b] + Y, cz = a.coff[2][b] + Z;
     const int S = 2 * Rc + 1;
     for (int qz = 0; qz < a.ccnt[2][cz]; ++qz) {
-        const int fz = a.ci[2][cz * 8 + qz];
-        const double wz = a.cw[2][cz * 8 + qz];
+        const int fz = a.ci[2][cz * a.cs[2] + qz];
+        const double wz = a.cw[2][cz * a.cs[2] + qz];
         for (int qy = 0; qy < a.ccnt[1][cy]; ++qy) {
-            const int fy = a.ci[1][cy * 8 + qy];
-            const double wy = a.cw[1][cy * 8 + qy];
+            const int fy = a.ci[1][cy * a.cs[1] + qy];
+            const double wy = a.cw[1][cy * a.cs[1] + qy];
             for (int qx = 0; qx < a.ccnt[0][cx]; ++qx) {
-                const int fx = a.ci[0][cx * 8 + qx];
-                const double wf = a.cw[0][cx * 8 + qx] * wy * wz;
+                const int fx = a.ci[0][cx * a.cs[0] + qx];
+                const double wf = a.cw[0][cx * a.cs[0] + qx] * wy * wz;
                 const int f = fb.off + fx + fb.nx * (fy + fb.ny * fz);
                 for (int k = 0; k < Kf; ++k) {
                     const int gx = fx + offf[3 * k], gy = fy + offf[3 * k + 1], gz = fz + offf[3 * k + 2];
@@ -1816,6 +1838,7 @@ static XferArgs xfer_args(Level &F, Level &C, const int *mask) {
         a.cw[d] = F.ip[d].d_cw.p;
         a.roff[d] = F.ip[d].d_roff.p;
         a.coff[d] = F.ip[d].d_coff.p;
+        a.cs[d] = F.ip[d].cs;
     }
     a.mask = mask;
     return a;
@@ -1846,6 +1869,7 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     lev.emplace_back(new Level());
     lev[0]->spp = &g->sp;
     lev[0]->A = &Jm->op;
+    const int rt = d.ratio > 0 ? d.ratio : 2;
     for (int l = 0; l + 1 < L; ++l) {
         Level &F = *lev[l];
         lev.emplace_back(new Level());
@@ -1853,17 +1877,17 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
         std::vector<Blk> cb;
         std::vector<int> nfx, nfy, nfz;
         for (const Blk &k : F.spp->hblk) {
-            cb.push_back({k.nx > 1 ? (k.nx + 1) / 2 : 1, k.ny > 1 ? (k.ny + 1) / 2 : 1,
-                          k.nz > 1 ? (k.nz + 1) / 2 : 1, 0});
+            cb.push_back({k.nx > 1 ? (k.nx + rt - 1) / rt : 1, k.ny > 1 ? (k.ny + rt - 1) / rt : 1,
+                          k.nz > 1 ? (k.nz + rt - 1) / rt : 1, 0});
             nfx.push_back(k.nx);
             nfy.push_back(k.ny);
             nfz.push_back(k.nz);
         }
         C.sp.build(al, cb, s);
         C.spp = &C.sp;
-        build_interp(F.ip[0], nfx, d.interp_order, al, s);
-        build_interp(F.ip[1], nfy, d.interp_order, al, s);
-        build_interp(F.ip[2], nfz, d.interp_order, al, s);
+        build_interp(F.ip[0], nfx, d.interp_order, rt, al, s);
+        build_interp(F.ip[1], nfy, d.interp_order, rt, al, s);
+        build_interp(F.ip[2], nfz, d.interp_order, rt, al, s);
         // coarse stencil: union over fine offsets of the tensor 1D coupling sets
         const Stencil &fs = F.A->st;
         std::set<std::tuple<int, int, int>> offs;
@@ -2044,8 +2068,10 @@ void Ras::check_pivots() {
     HIPC(hipStreamSynchronize(g->s));
     for (int l = 0; l < L; ++l)
         if (hpiv[l]) {
+            const int bits = hpiv[l];
             HIPC(hipMemsetAsync(lev[l]->err.p, 0, sizeof(int), g->s));
-            fail(NKS_EZEROPIVOT, "zero pivot in a subdomain ILU(0) factorization on level %d", l);
+            if (bits & 1) fail(NKS_EZEROPIVOT, "zero pivot in a subdomain ILU(0) factorization on level %d", l);
+            fail(NKS_EHIP, "a 3D subdomain sweep on level %d gave up waiting for its neighbouring slab", l);
         }
 }
 
@@ -2152,6 +2178,7 @@ static void launch_rows3d(Ras &M, Level &V, const double *r, double *z, const in
     a.z = z;
     a.zext = V.zext.p;
     a.mask = mask;
+    a.err = V.err.p;
     a.variant = M.d.variant;
     a.accumulate = accumulate ? 1 : 0;
     const size_t sh = rows3d_lds(M.d.precision, V.max_next);

@@ -59,6 +59,10 @@ class Problem:
     # 2 Neumann (value q^N = v.n, m/s, n the outward normal: inflow < 0)
     bc_type: Tuple[int, ...] = (0, 0, 0, 0, 0, 0)
     bc_value: Tuple[float, ...] = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)
+    # accumulation form: "conservative" (phi V (m(p) - m(p^n))/dt) or "chain_rule"
+    # (phi V m'(p) (p - p^n)/dt, the BDF equations as printed); every
+    # reservoir of one GPU grid shares the first reservoir's form
+    accum: str = "conservative"
 
     @property
     def N(self):
@@ -84,6 +88,7 @@ class SolverSettings:
     variant: str = "left_ras"            # left_ras | as | right_ras
     subsolve: str = "ilu0"               # ilu0 | lu (oracle only)
     fill: int = 0                        # subdomain ILU level of fill k: ILU(k) (0: ILU(0))
+    ratio: int = 2                       # coarse-to-fine mesh ratio per direction between levels
     mu: int = 1
     nu: int = 1
     coarse_rtol: float = 0.2
@@ -233,7 +238,7 @@ def case_3d_128(nx=128, ny=128, nz=64, precision="fp32"):
                 case_3d_128.__doc__)
 
 
-def case_batch64(nres=64, nmin=64, nmax=256, tile=16, overlap=1):
+def case_batch64(nres=64, nmin=64, nmax=256, tile=32, overlap=1):
     """64 independent 2D reservoirs, side n_b uniform in {64..256}, sigma_b
     uniform in [0.5, 2], corr. length 8, mean 100 mD, phi 0.2, one injector and
     one producer (+-1e-3 kg/s) at seeded cells at least n_b/4 apart

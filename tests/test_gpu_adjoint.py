@@ -143,10 +143,13 @@ def test_adjoint_parity_against_oracle(nks, orc, cfg, levels):
 def test_adjoint_gradient_fd_3d_96(nks):
     # the channelised 96x96x48 workload: gradient of the producer-column mean
     # pressure after 3 steps with respect to ln K, against central differences
-    # of the GPU forward solve at 20 seeded cells.  G is ~2e7 Pa, so a central
-    # difference with step h resolves gradients only down to ~ulp(2e7)/(2h);
-    # the cells are drawn among those whose gradient is at least 1e-3 of the
-    # largest, and the difference is taken state by state before the weights
+    # of the GPU forward solve at 20 cells drawn uniformly (seed 55), chosen
+    # without looking at the adjoint.  G is ~2e7 Pa, so a central difference
+    # with step h resolves a gradient only to about the forward solves'
+    # convergence noise over 2h; each cell is judged as |grad - fd| <=
+    # 2e-3 |fd| + 1e-6 max|grad|, so a cell whose true gradient is above that
+    # floor and where the adjoint returned ~0 fails.  The difference is taken
+    # state by state before the weights
     base = S.case_3d_96_adjoint()
     case = S.with_solver(base, eps_r=1e-12, eps_a=0.0, eta_r=1e-10, eta_a=0.0)
     rec = case.problems[0]
@@ -160,8 +163,7 @@ def test_adjoint_gradient_fd_3d_96(nks):
     scale = np.max(np.abs(grad))
     say("adjoint its", st["linear_its"], "seconds", round(st["seconds"], 3), "max |grad|", scale,
         "quantiles", np.quantile(np.abs(grad), [0.5, 0.9, 0.99, 0.999]))
-    big = np.flatnonzero(np.abs(grad) >= 1e-3 * scale)
-    cells = np.random.default_rng(55).choice(big, size=20, replace=False)
+    cells = np.random.default_rng(55).choice(rec.N, size=20, replace=False)
     h = 1e-2
 
     def final_state(c, hh):
@@ -174,14 +176,18 @@ def test_adjoint_gradient_fd_3d_96(nks):
         hp, _ = gp.simulate(case.nsteps, case.dt, case.solver)
         return hp[-1].cpu().numpy()
 
-    worst = 0.0
+    worst, resolved = 0.0, 0
+    floor = 1e-6 * scale
     for c in cells:
         fd = float(w @ (final_state(c, h) - final_state(c, -h))) / (2 * h)
-        err = abs(grad[c] - fd) / abs(fd)
-        worst = max(worst, err)
+        err = abs(grad[c] - fd) / max(abs(fd), 1e-300)
+        if abs(fd) > 100 * floor:
+            resolved += 1
+            worst = max(worst, err)
         say(f"  cell {c}: adjoint {grad[c]:.6e} fd {fd:.6e} rel {err:.1e}")
-        assert abs(grad[c] - fd) <= 2e-3 * abs(fd) + 1e-6 * scale, (c, grad[c], fd)
-    say("worst relative difference", worst)
+        assert abs(grad[c] - fd) <= 2e-3 * abs(fd) + floor, (c, grad[c], fd)
+    say(f"worst relative difference {worst:.2e} over {resolved} of {len(cells)} cells whose gradient is "
+        f"resolved (|fd| > 100 x the absolute floor {floor:.2e})")
 
 
 def test_autograd_function_matches_adjoint(nks):

@@ -80,16 +80,59 @@ def test_flood_512_first_step(nks, orc):
     _check(orc, case, 0, p0[0], p[0])
 
 
-def test_3d_128_first_step(nks, orc):
-    case = S.with_solver(S.case_3d_128(), **PARITY)
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_3d_128_first_step(nks, orc, precision):
+    # FP32 factors (the workload's form) and BF16 off-diagonal factors with
+    # FP32 accumulation: the Newton fixed point is the FP64 residual's, so the
+    # bar is the FP64 one
+    case = S.with_solver(S.case_3d_128(), precision=precision, **PARITY)
     say("3d 128x128x64", case.solver.precision)
     p0, p, st = _gpu_first_step(nks, case)
     say("  gpu", st["newton_its"], "newton,", st["linear_its"], "gmres")
     _check(orc, case, 0, p0[0], p[0])
 
 
-def test_batch64_first_step(nks, orc):
-    case = S.with_solver(S.case_batch64(), **PARITY)
+def _gpu_two_steps(nks, case):
+    g = nks.Grid(case.problems)
+    hist, stats = g.simulate(2, case.dt, case.solver)
+    return [g.split(h) for h in hist], stats
+
+
+def _check_second_step(orc, case, k, hg):
+    """The BDF2 step: the change p^2 - p^0 against the oracle's own two
+    steps, and the oracle's BDF2 residual at the GPU's p^2 (with the GPU's
+    p^1 and p^0 as history) against the same bar as the first step."""
+    rec = case.problems[k]
+    prob = orc.Problem(rec)
+    q0 = prob.initial_pressure()
+    q1, st1 = orc.newton_step(prob, case.solver, q0, q0, q0, case.dt, 1)
+    q2, st2 = orc.newton_step(prob, case.solver, q1, q1, q0, case.dt, 2)
+    assert st1["status"] == 0 and st2["status"] == 0
+    p0, p1, p2 = hg[0][k], hg[1][k], hg[2][k]
+    dq, dg = q2 - q0, p2 - q0
+    err = np.linalg.norm(dg - dq) / np.linalg.norm(dq)
+    f0 = np.linalg.norm(prob.residual(p1, p1, p0, case.dt, 2))
+    fg = np.linalg.norm(prob.residual(p2, p1, p0, case.dt, 2))
+    fo = np.linalg.norm(prob.residual(q2, q1, q0, case.dt, 2))
+    say(f"  reservoir {k}: BDF2 step dp error {err:.2e}, ||F|| gpu {fg:.3e} oracle {fo:.3e} "
+        f"initial {f0:.3e}")
+    assert err <= 1e-6
+    assert fg <= max(1e-8 * f0, 2.0 * fo, case.solver.eps_a)
+
+
+@pytest.mark.parametrize("name", ["2d512", "3d128"])
+def test_fullsize_second_step_bdf2(nks, orc, name):
+    case = {"2d512": S.case_2d_512, "3d128": S.case_3d_128}[name]()
+    case = S.with_solver(case, **PARITY)
+    say("BDF2 second step", name, case.solver.precision)
+    hg, stats = _gpu_two_steps(nks, case)
+    say("  gpu", [x["newton_its"] for x in stats], "newton,", [x["linear_its"] for x in stats], "gmres")
+    _check_second_step(orc, case, 0, hg)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp64"])
+def test_batch64_first_step(nks, orc, precision):
+    case = S.with_solver(S.case_batch64(), precision=precision, **PARITY)
     say("batch", len(case.problems), "reservoirs,", case.solver.precision)
     p0, p, st = _gpu_first_step(nks, case)
     say("  gpu", st["newton_its"], "newton,", st["linear_its"], "gmres")

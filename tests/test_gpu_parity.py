@@ -174,6 +174,13 @@ GALERKIN = [
     dict(nx=41, ny=27, nz=1, levels=2, interp_order=1),
     dict(nx=32, ny=24, nz=1, levels=2, interp_order=3),
     dict(nx=16, ny=12, nz=10, levels=3, interp_order=2, gravity=True),
+    # odd sizes under third order: the short last coarse cell at its centroid
+    dict(nx=41, ny=27, nz=1, levels=3, interp_order=3),
+    # coarse-to-fine ratios 4, 8 and 16 (Section 4.2), sizes they do not divide
+    dict(nx=64, ny=50, nz=1, levels=2, interp_order=2, ratio=4),
+    dict(nx=70, ny=45, nz=1, levels=2, interp_order=3, ratio=8),
+    dict(nx=100, ny=64, nz=1, levels=2, interp_order=1, ratio=16),
+    dict(nx=20, ny=18, nz=13, levels=2, interp_order=2, ratio=4, gravity=True),
 ]
 
 
@@ -246,6 +253,25 @@ def test_multilevel_transpose_apply_parity(nks, orc, cycle, mu, nu, levels):
     g = nks.Grid([rec])
     M = nks.Ras(_gpu_jac(nks, g, p, pn, case.dt), case.solver)
     zg = M.apply_transpose(g.from_numpy(r)).cpu().numpy()
+    assert np.max(np.abs(zg - zo)) <= 1e-9 * np.max(np.abs(zo))
+
+
+@pytest.mark.parametrize("ratio,order", [(4, 2), (8, 2), (16, 3)])
+def test_multilevel_ratio_apply_parity(nks, orc, ratio, order):
+    # two-level V-cycle with coarse-to-fine ratio r, fixed coarse iterations
+    cfg = dict(nx=96, ny=80, nz=1, px=4, py=4, levels=2, overlap=(2, 1), ratio=ratio,
+               interp_order=order, coarse_rtol=0.0, coarse_maxit=5)
+    say("multilevel ratio", ratio, "order", order)
+    case = S.small_case(**cfg)
+    rec = case.problems[0]
+    op = orc.Problem(rec)
+    p, pn, _ = _state(op, 21)
+    Jo = op.jacobian(p, pn, pn, case.dt, 1)
+    r = np.sin(0.37 * np.arange(op.N))
+    zo = orc.Multilevel(rec, Jo, case.solver).apply(r)
+    g = nks.Grid([rec])
+    M = nks.Ras(_gpu_jac(nks, g, p, pn, case.dt), case.solver)
+    zg = M.apply(g.from_numpy(r)).cpu().numpy()
     assert np.max(np.abs(zg - zo)) <= 1e-9 * np.max(np.abs(zo))
 
 

@@ -227,6 +227,93 @@ def test_interp_polynomial_reproduction(orc):
     assert P[8, 4] == 1.0
 
 
+def _centroids(nf, r):
+    # coarse cell J covers fine cells rJ .. min(rJ + r, nf) - 1
+    nc = -(-nf // r)
+    return np.array([(r * J + min(r * (J + 1), nf)) / 2.0 for J in range(nc)])
+
+
+def test_interp_ratio_closed_forms(orc):
+    # ratio 4: the fine cells of a coarse cell sit at -3/8, -1/8, 1/8, 3/8 of a
+    # coarse spacing from its centroid, so the linear weights are 5/8 and 3/8,
+    # 7/8 and 1/8, ...
+    P = orc.interp_1d(16, 2, ratio=4).dense()
+    assert P.shape == (16, 4)
+    assert np.allclose(P[4, 0:3], [0.375, 0.625, 0.0])
+    assert np.allclose(P[5, 0:3], [0.125, 0.875, 0.0])
+    assert np.allclose(P[6, 0:3], [0.0, 0.875, 0.125])
+    assert np.allclose(P[7, 0:3], [0.0, 0.625, 0.375])
+    # ratio 8, first order: each coarse cell is the parent of 8 fine cells
+    P1 = orc.interp_1d(20, 1, ratio=8).dense()
+    assert P1.shape == (20, 3)
+    assert np.array_equal(P1.argmax(1), np.arange(20) // 8) and np.all(P1.max(1) == 1.0)
+    # ratio 16, third order on uniform spacing: the cubic convolution kernel at
+    # the fine centres' offsets (k + 1/2 - 8)/16
+    P3 = orc.interp_1d(96, 3, ratio=16).dense()
+    W = lambda t: (1.5 * abs(t) ** 3 - 2.5 * t * t + 1) if abs(t) < 1 else \
+        ((-0.5 * abs(t) ** 3 + 2.5 * t * t - 4 * abs(t) + 2) if abs(t) < 2 else 0.0)
+    for k in range(16):
+        i = 2 * 16 + k
+        sx = (i + 0.5 - 8.0) / 16.0
+        ref = np.array([W(sx - J) for J in range(6)])
+        assert np.allclose(P3[i], ref, atol=1e-15), (k, P3[i], ref)
+    for M in (P, P1, P3):
+        assert np.allclose(M.sum(1), 1.0, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("nf,r", [(9, 2), (13, 2), (21, 4), (30, 4), (37, 8), (50, 16), (64, 16)])
+def test_interp_uses_actual_centroids(orc, nf, r):
+    # readings for sizes r does not divide: the short last coarse cell sits at
+    # its centroid, and orders 2 and 3 interpolate in the coordinate that is
+    # linear between consecutive centroids.  Order 2 then reproduces linear
+    # functions of x between the first and last centroids; order 3 reproduces
+    # s, s^2 (s the index coordinate) wherever its four cells are in range
+    c = _centroids(nf, r)
+    nc = len(c)
+    x = np.arange(nf) + 0.5
+    P2 = orc.interp_1d(nf, 2, ratio=r).dense()
+    P3 = orc.interp_1d(nf, 3, ratio=r).dense()
+    assert P2.shape == (nf, nc) and P3.shape == (nf, nc)
+    inside = (x >= c[0]) & (x <= c[-1])
+    assert np.allclose((P2 @ c)[inside], x[inside], atol=1e-12)
+    s = np.interp(x, c, np.arange(nc, dtype=float))
+    J = np.arange(nc, dtype=float)
+    rows = (np.floor(s) >= 1) & (np.floor(s) <= nc - 3)
+    for k in (0, 1, 2):
+        assert np.allclose((P3 @ J ** k)[rows], (s ** k)[rows], atol=1e-12), k
+    for M in (P2, P3):
+        assert np.allclose(M.sum(1), 1.0, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("ratio,order,K", [(4, 2, 21), (8, 2, 21), (4, 1, 5), (16, 1, 5)])
+def test_galerkin_with_ratio(orc, ratio, order, K):
+    # P^T A P with coarse-to-fine ratio r: the same Galerkin definition, and
+    # the coarse stencil keeps its reach (the supports of P's columns scale
+    # with r like the coarse spacing does)
+    case, prob, J = _jac(orc, nx=64, ny=48, px=2, py=2, levels=2, ratio=ratio, interp_order=order)
+    mg = orc.Multilevel(prob.rec, J, case.solver)
+    info = mg.level_info(1)
+    assert info["dims"][:2] == (-(-64 // ratio), -(-48 // ratio))
+    P = mg.level_prolong(0).dense()
+    Ac = mg.level_matrix(1).dense()
+    assert np.allclose(Ac, P.T @ J.dense() @ P, rtol=1e-12, atol=1e-12 * np.abs(Ac).max())
+    assert np.diff(mg.level_matrix(1).rp).max() == K
+
+
+def test_vcycle_identity_with_ratio_4(orc):
+    case, prob, J = _jac(orc, nx=24, ny=20, px=2, py=2, levels=2, overlap=(1, 1), ratio=4,
+                         coarse_rtol=1e-14, coarse_maxit=400)
+    mg = orc.Multilevel(prob.rec, J, case.solver)
+    B = _apply_dense(mg.apply, J.n)
+    M = _apply_dense(lambda e: mg.apply_onelevel(0, e), J.n)
+    P = mg.level_prolong(0).dense()
+    assert P.shape == (J.n, 6 * 5)
+    A = J.dense()
+    C = P @ np.linalg.inv(P.T @ A @ P) @ P.T
+    I = np.eye(A.shape[0])
+    assert np.allclose(I - A @ B, (I - A @ M) @ (I - A @ C) @ (I - A @ M), atol=1e-8)
+
+
 def test_galerkin_stencil_sizes(orc):
     # bilinear P^T A P on a 5-point / 7-point operator: 21 / 81 points on the
     # first coarse level, 25 / 125 on the next (interior rows)
