@@ -133,6 +133,22 @@ int nks_hydrostatic_init(nks_grid *g, double p_top, double *p);
 int nks_residual(nks_grid *g, const double *p, const double *p_n, const double *p_nm1,
                  double dt, int bdf_order, double *F);
 
+/* Allocation-free form of nks_residual, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments and the same F, bit for bit; its
+ * intermediates (the BDF history term and the PR properties m, dm/dp of each
+ * cell, the per-reservoir non-physical flags) live in one fixed device array
+ * of the library instead of the grid's buffers.  That array holds
+ * NKS_NOALLOC_MAX_CELLS cells (60 MiB plus 16 KiB), is kept on every GPU the
+ * library runs on until the process ends, and is shared by all calls on that
+ * GPU, which keep the last call's contents: calls that overlap on one GPU
+ * (other streams or threads) race.  Larger grids (or more than 4096
+ * reservoirs): NKS_EINVAL.  Calls no device or pinned-host allocation.
+ * Asynchronous on the grid's stream. */
+#define NKS_NOALLOC_MAX_CELLS 2621440
+int nks_residual_noalloc(nks_grid *g, const double *p, const double *p_n, const double *p_nm1,
+                         double dt, int bdf_order, double *F);
+
 /* Sparse Jacobian dF/dp of nks_residual (Section 3, the Jacobian entries), stored
  * as a structured stencil (5 points in 2D, 7 in 3D), FP64.  Writes F too
  * when F != NULL.  J must come from nks_matrix_create on the same grid. */

@@ -227,6 +227,15 @@ class Grid:
                                      float(dt), int(order), _vp(F)))
         return F
 
+    def residual_noalloc(self, p, pn, pnm1=None, dt=86400.0, order=1, out=None):
+        """nks_residual_noalloc: the residual with the library's fixed device
+        scratch (no allocation inside the call; `out` must be given for that)."""
+        F = self.zeros() if out is None else out
+        with _Ordered(self):
+            check(lib().nks_residual_noalloc(self.h, _vp(p), _vp(pn), _vp(pnm1 if pnm1 is not None else pn),
+                                             float(dt), int(order), _vp(F)))
+        return F
+
     def matrix(self):
         return Matrix(self)
 

@@ -126,6 +126,7 @@ PROTOTYPES = {
     "nks_gmres_solve": [_P, _P, _P, _P, C.POINTER(nks_gmres_desc), C.POINTER(nks_gmres_stats)],
     "nks_newton_step": [_P, _P, _P, _P, _D, _I, C.POINTER(nks_newton_desc),
                         C.POINTER(nks_ras_desc), C.POINTER(nks_newton_stats)],
+    "nks_residual_noalloc": [_P, _P, _P, _P, _D, _I, _P],
     "nks_matrix_transpose": [_P, _P],
     "nks_adjoint": [_P, _I, C.POINTER(C.c_void_p), _IP, _D, C.POINTER(C.c_void_p),
                     C.POINTER(nks_ras_desc), C.POINTER(nks_gmres_desc), _P, C.POINTER(C.c_void_p),

@@ -143,6 +143,8 @@ void launch_history(Grid &g, const double *pn, const double *pnm1, int order);
 void launch_props(Grid &g, const double *p);
 void launch_flux(Grid &g, const double *p, double dt, int order, double *F, double *J);
 void launch_hydrostatic(Grid &g, double p_top, double *p);
+void launch_residual_into(Grid &g, const double *p, const double *pn, const double *pnm1, double dt,
+                          int order, double *F, double *hist, double *m, double *dm, int *flags);
 void launch_dlogk_t(Grid &g, const double *p, const double *lam, double *out, bool accumulate);
 void launch_adj_rhs(Grid &g, const double *pn, double dt, double c1, const double *l1, double c2,
                     const double *l2, const double *dg, double *out);
@@ -554,6 +556,63 @@ int nks_residual(nks_grid *g, const double *p, const double *pn, const double *p
         launch_history(g->g, pn, pnm1, order);
         launch_props(g->g, p);
         launch_flux(g->g, p, dt, order, F, nullptr);
+    });
+}
+
+}  // extern "C"
+
+namespace nks {
+
+// Fixed device scratch of nks_residual_noalloc: the history term, m and dm/dp
+// (NKS_NOALLOC_MAX_CELLS doubles each), then MAXB ints of non-physical flags.
+// Host code never passes the symbol itself to a kernel: each device's address
+// of its copy comes from hipGetSymbolAddress, looked up once per device.
+constexpr size_t NOALLOC_CELLS = NKS_NOALLOC_MAX_CELLS;
+constexpr size_t NOALLOC_DOUBLES = 3 * NOALLOC_CELLS + MAXB / 2;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, double *> g_scratch_ptr;
+
+// Address of `scratch` on the device of stream s (looked up with that device current).
+static double *scratch_on(hipStream_t s) {
+    int dev = 0;
+    HIPC(hipStreamGetDevice(s, &dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) return it->second;
+    int cur = 0;
+    HIPC(hipGetDevice(&cur));
+    if (cur != dev) HIPC(hipSetDevice(dev));
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) HIPC(hipSetDevice(cur));
+    HIPC(e);
+    if (!ptr) fail(NKS_EHIP, "no device address for the residual scratch on device %d", dev);
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    return static_cast<double *>(ptr);
+}
+
+}  // namespace nks
+
+extern "C" {
+
+int nks_residual_noalloc(nks_grid *g, const double *p, const double *pn, const double *pnm1, double dt,
+                         int order, double *F) {
+    return guard([&] {
+        if (!g || !p || !pn || !F || !(dt > 0) || (order != 1 && order != 2) || (order == 2 && !pnm1))
+            fail(NKS_EINVAL, "bad arguments");
+        Grid &G = g->g;
+        if ((size_t)G.sp.N > NOALLOC_CELLS)
+            fail(NKS_EINVAL, "nks_residual_noalloc: %d cells exceed the fixed scratch of %zu cells", G.sp.N,
+                 NOALLOC_CELLS);
+        if (G.sp.B > MAXB) fail(NKS_EINVAL, "nks_residual_noalloc: %d reservoirs exceed %d", G.sp.B, MAXB);
+        double *base = scratch_on(G.s);
+        double *hist = base;
+        double *m = base + NOALLOC_CELLS;
+        double *dm = base + 2 * NOALLOC_CELLS;
+        int *flags = reinterpret_cast<int *>(base + 3 * NOALLOC_CELLS);
+        launch_residual_into(G, p, pn, pnm1, dt, order, F, hist, m, dm, flags);
     });
 }
 

@@ -455,6 +455,25 @@ void launch_flux(Grid &g, const double *p, double dt, int order, double *F, doub
     KCHECK();
 }
 
+// The residual with caller-provided intermediates: the history term into
+// hist, the PR properties at p into m / dm and the non-physical flags into
+// flags (B ints), then F from those (the grid's own buffers are not touched).
+void launch_residual_into(Grid &g, const double *p, const double *pn, const double *pnm1, double dt,
+                          int order, double *F, double *hist, double *m, double *dm, int *flags) {
+    const int N = g.sp.N;
+    k_history<<<nblk(N, 256), 256, 0, g.s>>>(N, g.a, g.b, g.RT, pn, order == 2 ? pnm1 : pn, order,
+                                             g.accum == NKS_ACCUM_CHAIN_RULE ? 1 : 0, hist);
+    KCHECK();
+    k_props<<<nblk(N, 256), 256, 0, g.s>>>(g.sp.blk.p, g.sp.B, N, g.a, g.b, g.RT, p, m, dm, nullptr, flags);
+    KCHECK();
+    FluxArgs A = flux_args(g, p, dt, order, F, nullptr);
+    A.m = m;
+    A.dm = dm;
+    A.hist = hist;
+    k_flux<<<nblk(A.N, 256), 256, 0, g.s>>>(A);
+    KCHECK();
+}
+
 void launch_hydrostatic(Grid &g, double p_top, double *p) {
     std::vector<int> cs(g.sp.B);
     int tot = 0;
