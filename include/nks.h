@@ -113,6 +113,10 @@ typedef struct {
  * (two-point flux of the cell-centred scheme, Section 2 Remark 1), pore
  * volumes and the well source term Q R T / W.  Copies what it needs. */
 int nks_setup_grid(const nks_grid_desc *desc, nks_grid **out);
+/* Handles may be destroyed in any order: a grid's memory is released once its
+ * own handle and every matrix and preconditioner made on it are destroyed
+ * (they hold a reference to it), and a matrix's once its handle and every
+ * preconditioner set up on it are; until then those stay usable. */
 int nks_destroy_grid(nks_grid *g);
 /* ncells: total cells; nres: reservoirs; offsets: HOST array of nres+1
  * (may be NULL). */
@@ -214,11 +218,23 @@ typedef struct {
                                     fine cells rJ .. min(rJ + r, n) - 1 and sits at their
                                     centroid; orders 2 and 3 interpolate in the coordinate
                                     linear between consecutive centroids */
+    int coarse_op;               /* NKS_COARSE_GALERKIN (0): P^T A P on every coarse level;
+                                    NKS_COARSE_REDISCRETIZED: the Jacobian of the upscaled
+                                    coarse problem (cells of r^d fine cells, each permeability
+                                    component their mean, pore volume their sum, the fine
+                                    stencil) at the coarsened state (the mean of the children)
+                                    of the last nks_jacobian; every size above one must be a
+                                    multiple of r on every coarse level; not for the transpose */
 } nks_ras_desc;
+
+#define NKS_COARSE_GALERKIN 0
+#define NKS_COARSE_REDISCRETIZED 1
 
 /* Creates (*inout == NULL) or refactors in place (*inout from an earlier
  * call on a matrix of the same grid and an identical descriptor).  Keeps a
- * reference to J: J must outlive the preconditioner.  Asynchronous.  A zero
+ * reference to J (the finest level's operator), which therefore lives until
+ * the preconditioner is destroyed or set up on another matrix; J's values are
+ * read at every apply.  Asynchronous.  A zero
  * pivot is reported by the next synchronising call as NKS_EZEROPIVOT.  The 3D
  * sweeps of boxes split into slabs wait on their neighbouring slab with a
  * spin limit; a wait that reaches it marks the level, and the next call that

@@ -37,7 +37,7 @@ class MgDesc(C.Structure):
                 ("interp_order", C.c_int), ("cycle", C.c_int), ("mu", C.c_int), ("nu", C.c_int),
                 ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int),
                 ("coarse_restart", C.c_int), ("tx", C.c_int), ("ty", C.c_int), ("tz", C.c_int),
-                ("fill", C.c_int), ("ratio", C.c_int)]
+                ("fill", C.c_int), ("ratio", C.c_int), ("coarse_op", C.c_int)]
 
 
 class NewtonDesc(C.Structure):
@@ -72,6 +72,8 @@ def lib():
         L.orc_problem_set_bc.restype = C.c_int
         L.orc_problem_set_accum.argtypes = [C.c_void_p, C.c_int]
         L.orc_problem_set_accum.restype = C.c_int
+        L.orc_mg_new_problem.restype = C.c_void_p
+        L.orc_mg_new_problem.argtypes = [C.c_void_p, _D, C.c_double, C.c_int, _I, _I, _D, C.POINTER(MgDesc)]
         L.orc_pr_z2.argtypes = [C.c_double] * 5 + [_D] * 4
         L.orc_pr_z2.restype = C.c_int
         L.orc_pr_params.argtypes = [C.c_double] * 5 + [_D] * 3
@@ -158,6 +160,7 @@ def pr_z(fluid, p):
 
 
 ACCUM_FORMS = {"conservative": 0, "chain_rule": 1}
+COARSE_OPS = {"galerkin": 0, "rediscretised": 1}
 
 
 def pr_z2_ab(a, b, T, R, p):
@@ -288,6 +291,7 @@ def mg_desc(s):
     d.tx, d.ty, d.tz = s.tile
     d.fill = s.fill
     d.ratio = getattr(s, "ratio", 2)
+    d.coarse_op = COARSE_OPS[getattr(s, "coarse_op", "galerkin")]
     return d
 
 
@@ -308,15 +312,27 @@ def newton_desc(s):
 class Multilevel:
     """Oracle multilevel Schwarz preconditioner built from a fine CSR matrix."""
 
-    def __init__(self, rec_or_dims, J, settings):
+    def __init__(self, rec_or_dims, J, settings, state=None):
+        """state = (p, dt, order): the state rediscretised coarse levels are
+        evaluated at (needs a reservoir record, not bare dimensions)."""
         if hasattr(rec_or_dims, "nx"):
             dims = (rec_or_dims.nx, rec_or_dims.ny, rec_or_dims.nz)
         else:
             dims = tuple(rec_or_dims)
         self.J = J
         self.desc = mg_desc(settings)
-        self.h = lib().orc_mg_new(dims[0], dims[1], dims[2], J.n, _i(J.rp), _i(J.ci), _d(J.v),
-                                  C.byref(self.desc))
+        if state is not None:
+            self._prob = Problem(rec_or_dims)
+            p, dt, order = state
+            self._p = _f64(p)
+            self.h = lib().orc_mg_new_problem(self._prob.h, _d(self._p), float(dt), int(order), _i(J.rp),
+                                              _i(J.ci), _d(J.v), C.byref(self.desc))
+        else:
+            self.h = lib().orc_mg_new(dims[0], dims[1], dims[2], J.n, _i(J.rp), _i(J.ci), _d(J.v),
+                                      C.byref(self.desc))
+        if not self.h:
+            raise ValueError("the preconditioner could not be built (rediscretised coarse levels need the "
+                             "problem and sizes the ratio divides)")
         self.L = settings.levels
 
     def __del__(self):

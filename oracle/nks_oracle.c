@@ -971,14 +971,25 @@ struct orc_mg {
     int L;
     level lev[MAXLEV];   /* lev[0] is the finest, lev[L-1] the coarsest */
     double *work[MAXLEV][4];
+    /* rediscretised coarse operators: the upscaled problem of each coarse
+     * level (cprob[0] unused: the fine problem is the caller's) */
+    orc_problem *cprob[MAXLEV];
+    double odt;
+    int oorder;
 };
 
 /* Lagged refactorisation: the current Jacobian's values (same pattern) on the
  * finest level and fresh Galerkin products P^T A P below it; the subdomain
  * ILU factors of the last build are kept. */
-static void mg_refresh_operators(orc_mg *mg, const double *v) {
+static void rediscretise(orc_mg *mg, const orc_problem *pr, const double *p);
+
+static void mg_refresh_operators(orc_mg *mg, const double *v, const orc_problem *pr, const double *p) {
     level *f = &mg->lev[0];
     memcpy(f->A.v, v, (size_t)f->A.rp[f->A.n] * sizeof(double));
+    if (mg->d.coarse_op == ORC_COARSE_REDISCRETISED) {
+        if (mg->L > 1) rediscretise(mg, pr, p);
+        return;
+    }
     for (int l = 0; l + 1 < mg->L; ++l) {
         level *fl = &mg->lev[l], *cl = &mg->lev[l + 1];
         csr AP = csr_matmul(&fl->A, &fl->P);
@@ -1296,11 +1307,99 @@ static void mg_cycle(orc_mg *mg, int li, const double *b, double *x, int trans) 
     }
 }
 
-orc_mg *orc_mg_new(int nx, int ny, int nz, int n, const int *rp, const int *ci,
-                   const double *v, const orc_mg_desc *d) {
+/* Rediscretised coarse problem (the alternative to the Galerkin product for
+ * the coarse matrices of Section 3.2): cells of r x r (x r) fine cells, each
+ * permeability component the arithmetic mean of the children's, porosity the
+ * mean (so the pore volume is the children's sum), r times the cell size,
+ * the same fluid, gravity, outer-face conditions and wells (moved to the
+ * coarse cell holding them).  Every size above one must be a multiple of r;
+ * returns NULL otherwise. */
+orc_problem *orc_problem_coarsen(const orc_problem *pr, int r) {
+    int n[3] = {pr->nx, pr->ny, pr->nz}, nc[3], rr[3];
+    for (int k = 0; k < 3; ++k) {
+        rr[k] = n[k] > 1 ? r : 1;
+        if (n[k] % rr[k]) return NULL;
+        nc[k] = n[k] / rr[k];
+    }
+    int Nc = nc[0] * nc[1] * nc[2];
+    double *kx = (double *)xcalloc(Nc, sizeof(double)), *ky = (double *)xcalloc(Nc, sizeof(double));
+    double *kz = (double *)xcalloc(Nc, sizeof(double)), *ph = (double *)xcalloc(Nc, sizeof(double));
+    double inv = 1.0 / (rr[0] * rr[1] * rr[2]);
+    for (int z = 0; z < n[2]; ++z)
+        for (int y = 0; y < n[1]; ++y)
+            for (int x = 0; x < n[0]; ++x) {
+                int i = x + n[0] * (y + n[1] * z);
+                int I = x / rr[0] + nc[0] * (y / rr[1] + nc[1] * (z / rr[2]));
+                kx[I] += inv * pr->kx[i];
+                ky[I] += inv * pr->ky[i];
+                kz[I] += inv * pr->kz[i];
+                ph[I] += inv * pr->phi[i];
+            }
+    int *wc = (int *)xcalloc(pr->nw, sizeof(int));
+    for (int w = 0; w < pr->nw; ++w) {
+        int i = pr->wcell[w];
+        int x = i % n[0], y = (i / n[0]) % n[1], z = i / (n[0] * n[1]);
+        wc[w] = x / rr[0] + nc[0] * (y / rr[1] + nc[1] * (z / rr[2]));
+    }
+    orc_problem *c = orc_problem_new(nc[0], nc[1], nc[2], pr->dx * rr[0], pr->dy * rr[1], pr->dz * rr[2],
+                                     kx, ky, kz, ph, pr->nw, wc, pr->wrate, pr->Tc, pr->pc, pr->omega, pr->T,
+                                     pr->W, pr->R, pr->mu, pr->g != 0.0, pr->g);
+    for (int f = 0; f < 6; ++f) c->bct[f] = pr->bct[f], c->bcv[f] = pr->bcv[f];
+    c->accum = pr->accum;
+    /* the fine problem's constants as they are (omega may have come from T_b) */
+    c->a = pr->a; c->b = pr->b; c->mpr = pr->mpr;
+    free(kx); free(ky); free(kz); free(ph); free(wc);
+    return c;
+}
+
+/* the coarse state: each coarse cell takes the mean of its children */
+static void coarsen_state(const orc_problem *f, const orc_problem *c, const double *pf, double *pc) {
+    int rx = f->nx / c->nx, ry = f->ny / c->ny, rz = f->nz / c->nz;
+    for (int I = 0; I < c->N; ++I) pc[I] = 0.0;
+    double inv = 1.0 / (rx * ry * rz);
+    for (int z = 0; z < f->nz; ++z)
+        for (int y = 0; y < f->ny; ++y)
+            for (int x = 0; x < f->nx; ++x)
+                pc[x / rx + c->nx * (y / ry + c->ny * (z / rz))] += inv * pf[x + f->nx * (y + f->ny * z)];
+}
+
+/* coarse matrices of the rediscretised hierarchy: the Jacobian of each
+ * coarse problem at the coarsened state, with no BDF difference (the
+ * accumulation enters through its coefficient alone) */
+static void rediscretise(orc_mg *mg, const orc_problem *pr, const double *p) {
+    const orc_problem *fp = pr;
+    double *ps = (double *)xcalloc(pr->N, sizeof(double));
+    memcpy(ps, p, pr->N * sizeof(double));
+    for (int l = 1; l < mg->L; ++l) {
+        const orc_problem *cp = mg->cprob[l];
+        double *pc = (double *)xcalloc(cp->N, sizeof(double));
+        coarsen_state(fp, cp, ps, pc);
+        level *cl = &mg->lev[l];
+        csr_free(&cl->A);
+        cl->A.n = cl->A.m = cp->N;
+        cl->A.rp = (int *)xcalloc(cp->N + 1, sizeof(int));
+        cl->A.ci = (int *)xcalloc((size_t)7 * cp->N, sizeof(int));
+        cl->A.v = (double *)xcalloc((size_t)7 * cp->N, sizeof(double));
+        orc_jacobian(cp, pc, pc, pc, mg->odt, mg->oorder, cl->A.rp, cl->A.ci, cl->A.v);
+        free(ps);
+        ps = pc;
+        fp = cp;
+    }
+    free(ps);
+}
+
+/* The level hierarchy: the fine matrix, interpolation to each coarser level,
+ * coarse matrices (Galerkin P^T A P, or the rediscretised problems' Jacobians
+ * at the coarsened state when pr and p are given), then every level's
+ * subdomains and their factors.  NULL when rediscretisation is asked for
+ * without a problem or on sizes the ratio does not divide. */
+static orc_mg *mg_build(int nx, int ny, int nz, int n, const int *rp, const int *ci, const double *v,
+                        const orc_mg_desc *d, const orc_problem *pr, const double *p, double dt, int order) {
     orc_mg *mg = (orc_mg *)xcalloc(1, sizeof(orc_mg));
     mg->d = *d;
     mg->L = d->levels < 1 ? 1 : (d->levels > MAXLEV ? MAXLEV : d->levels);
+    int ratio = d->ratio > 0 ? d->ratio : 2;
+    int redisc = d->coarse_op == ORC_COARSE_REDISCRETISED && mg->L > 1;
     level *f = &mg->lev[0];
     f->nx = nx; f->ny = ny; f->nz = nz; f->n = n;
     f->A.n = f->A.m = n;
@@ -1313,15 +1412,25 @@ orc_mg *orc_mg_new(int nx, int ny, int nz, int n, const int *rp, const int *ci,
     memcpy(f->A.v, v, nnz * sizeof(double));
     for (int l = 0; l + 1 < mg->L; ++l) {
         level *fl = &mg->lev[l], *cl = &mg->lev[l + 1];
-        fl->P = interp_matrix(fl->nx, fl->ny, fl->nz, d->interp_order, d->ratio > 0 ? d->ratio : 2,
-                              &cl->nx, &cl->ny, &cl->nz);
+        fl->P = interp_matrix(fl->nx, fl->ny, fl->nz, d->interp_order, ratio, &cl->nx, &cl->ny, &cl->nz);
         fl->has_p = 1;
         cl->n = cl->nx * cl->ny * cl->nz;
+        if (redisc) {
+            const orc_problem *fine = l == 0 ? pr : mg->cprob[l];
+            mg->cprob[l + 1] = fine ? orc_problem_coarsen(fine, ratio) : NULL;
+            if (!mg->cprob[l + 1]) { orc_mg_free(mg); return NULL; }
+            continue;
+        }
         /* Galerkin coarse operator A_c = P^T A P */
         csr AP = csr_matmul(&fl->A, &fl->P);
         csr Pt = csr_transpose(&fl->P);
         cl->A = csr_matmul(&Pt, &AP);
         csr_free(&AP); csr_free(&Pt);
+    }
+    if (redisc) {
+        mg->odt = dt;
+        mg->oorder = order;
+        rediscretise(mg, pr, p);
     }
     /* the same box grid on every level: box counts from the finest level */
     int Pbox[3] = {d->px, d->py, d->pz};
@@ -1338,8 +1447,21 @@ orc_mg *orc_mg_new(int nx, int ny, int nz, int n, const int *rp, const int *ci,
     return mg;
 }
 
+orc_mg *orc_mg_new(int nx, int ny, int nz, int n, const int *rp, const int *ci,
+                   const double *v, const orc_mg_desc *d) {
+    return mg_build(nx, ny, nz, n, rp, ci, v, d, NULL, NULL, 0.0, 1);
+}
+
+/* As orc_mg_new on the problem's grid, with the problem and the state p (and
+ * dt, BDF order) that rediscretised coarse levels are evaluated from. */
+orc_mg *orc_mg_new_problem(const orc_problem *pr, const double *p, double dt, int order, const int *rp,
+                           const int *ci, const double *v, const orc_mg_desc *d) {
+    return mg_build(pr->nx, pr->ny, pr->nz, pr->N, rp, ci, v, d, pr, p, dt, order);
+}
+
 void orc_mg_free(orc_mg *mg) {
     if (!mg) return;
+    for (int l = 0; l < MAXLEV; ++l) orc_problem_free(mg->cprob[l]);
     for (int l = 0; l < mg->L; ++l) {
         level *lv = &mg->lev[l];
         csr_free(&lv->A);
@@ -1507,9 +1629,10 @@ int orc_newton_step(const orc_problem *pr, const orc_mg_desc *md, const orc_newt
         }
         if (!M || nd->lag <= 1 || k % nd->lag == 0) {
             orc_mg_free(M);
-            M = orc_mg_new(pr->nx, pr->ny, pr->nz, N, rp, ci, v, md);
+            M = orc_mg_new_problem(pr, p, dt, order, rp, ci, v, md);
+            if (!M) { status = 4; break; }
         } else {
-            mg_refresh_operators(M, v);
+            mg_refresh_operators(M, v, pr, p);
         }
         for (int i = 0; i < N; ++i) { b[i] = -F[i]; s[i] = 0.0; }
         double lres;

@@ -35,7 +35,11 @@ typedef struct {
     int tx, ty, tz;         /* > 0: box edge in cells on the finest level (boxes = ceil(n/t)) */
     int fill;               /* subdomain ILU level of fill k (0: ILU(0)): ILU on the level-k pattern */
     int ratio;              /* coarse-to-fine mesh ratio per direction (0: 2) */
+    int coarse_op;          /* ORC_COARSE_GALERKIN or ORC_COARSE_REDISCRETISED */
 } orc_mg_desc;
+
+#define ORC_COARSE_GALERKIN 0        /* P^T A P */
+#define ORC_COARSE_REDISCRETISED 1   /* Jacobian of the upscaled coarse problem */
 
 typedef struct {
     double eps_r, eps_a;    /* Newton stopping */
@@ -101,6 +105,10 @@ void orc_residual_dlogk_t(const orc_problem *pr, const double *p, const double *
 /* Multilevel Schwarz preconditioner built from a fine CSR matrix on the problem grid */
 orc_mg *orc_mg_new(int nx, int ny, int nz, int n, const int *rp, const int *ci,
                    const double *v, const orc_mg_desc *d);
+/* with rediscretised coarse levels: the problem and the state they are evaluated from */
+orc_mg *orc_mg_new_problem(const orc_problem *pr, const double *p, double dt, int order, const int *rp,
+                           const int *ci, const double *v, const orc_mg_desc *d);
+orc_problem *orc_problem_coarsen(const orc_problem *pr, int ratio);
 void orc_mg_free(orc_mg *mg);
 void orc_mg_apply(orc_mg *mg, const double *r, double *z);
 void orc_mg_apply_transpose(orc_mg *mg, const double *r, double *z);

@@ -86,6 +86,7 @@ def ras_desc(s):
     d.tx, d.ty, d.tz = s.tile
     d.fill = getattr(s, "fill", 0)
     d.ratio = getattr(s, "ratio", 2)
+    d.coarse_op = {"galerkin": 0, "rediscretised": 1}[getattr(s, "coarse_op", "galerkin")]
     return d
 
 

@@ -50,7 +50,7 @@ class nks_ras_desc(C.Structure):
                 ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int),
                 ("coarse_restart", C.c_int), ("precision", C.c_int),
                 ("tx", C.c_int), ("ty", C.c_int), ("tz", C.c_int), ("fill", C.c_int),
-                ("ratio", C.c_int)]
+                ("ratio", C.c_int), ("coarse_op", C.c_int)]
 
 
 class nks_gmres_desc(C.Structure):

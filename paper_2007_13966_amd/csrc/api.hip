@@ -261,6 +261,8 @@ struct TransposedRas {
     bool stale = true;
     void refresh(Matrix &J, const nks_ras_desc &dd) {
         Grid &g = *J.g;
+        if (dd.coarse_op != NKS_COARSE_GALERKIN)
+            fail(NKS_EINVAL, "the transposed preconditioner needs Galerkin coarse operators");
         if (!MT || !same_desc(d, dd)) {
             fine_matrix(JT, g);
             std::vector<int> o = opposite_slots(J.op.st);
@@ -299,20 +301,46 @@ struct AdjointWork {
 
 using namespace nks;
 
+// A grid's memory backs its matrices and preconditioners (their buffers come
+// from its allocator), so each of them holds a reference to the grid; a
+// preconditioner reads its matrix (the finest level's operator), so it holds
+// a reference to that matrix too.  Each object goes when its own handle and
+// the last reference to it are gone, in whatever order the caller destroys
+// the handles.
 struct nks_grid {
     Grid g;
     std::unique_ptr<NewtonWork> nw;
     std::unique_ptr<AdjointWork> aw;
+    int refs = 1;
 };
 struct nks_matrix {
     Matrix m;
     nks_grid *owner;
     DBuf<int> opp;       // opposite stencil slots, for transposes
+    int refs = 1;
 };
 struct nks_ras {
     Ras r;
     TransposedRas t;     // built on first use of the transpose
+    nks_grid *owner = nullptr;
+    nks_matrix *mat = nullptr;   // the matrix the finest level reads
 };
+
+static void grid_release(nks_grid *g) {
+    if (--g->refs == 0) {
+        (void)hipStreamSynchronize(g->g.s);
+        delete g;
+    }
+}
+
+static void matrix_release(nks_matrix *J) {
+    if (--J->refs == 0) {
+        nks_grid *owner = J->owner;
+        (void)hipStreamSynchronize(J->m.g->s);
+        delete J;
+        grid_release(owner);
+    }
+}
 
 template <typename F>
 static int guard(F &&f) {
@@ -522,10 +550,7 @@ int nks_setup_grid(const nks_grid_desc *d, nks_grid **out) {
 
 int nks_destroy_grid(nks_grid *g) {
     return guard([&] {
-        if (g) {
-            (void)hipStreamSynchronize(g->g.s);
-            delete g;
-        }
+        if (g) grid_release(g);
     });
 }
 
@@ -619,7 +644,8 @@ int nks_residual_noalloc(nks_grid *g, const double *p, const double *pn, const d
 int nks_matrix_create(nks_grid *g, nks_matrix **out) {
     return guard([&] {
         if (!g || !out) fail(NKS_EINVAL, "bad arguments");
-        auto *m = new nks_matrix();
+        std::unique_ptr<nks_matrix> hold(new nks_matrix());
+        nks_matrix *m = hold.get();
         m->owner = g;
         m->m.g = &g->g;
         m->m.op.sp = &g->g.sp;
@@ -627,16 +653,14 @@ int nks_matrix_create(nks_grid *g, nks_matrix **out) {
         m->m.op.coef.alloc(&g->g.al, (size_t)m->m.op.st.K * g->g.sp.N);
         HIPC(hipMemsetAsync(m->m.op.coef.p, 0, sizeof(double) * m->m.op.st.K * g->g.sp.N, g->g.s));
         sync_upload_done(g->g.s);
-        *out = m;
+        g->refs++;
+        *out = hold.release();
     });
 }
 
 int nks_destroy_matrix(nks_matrix *J) {
     return guard([&] {
-        if (J) {
-            (void)hipStreamSynchronize(J->m.g->s);
-            delete J;
-        }
+        if (J) matrix_release(J);
     });
 }
 
@@ -649,6 +673,7 @@ int nks_jacobian(nks_grid *g, const double *p, const double *pn, const double *p
         launch_history(g->g, pn, pnm1, order);
         launch_props(g->g, p);
         launch_flux(g->g, p, dt, order, F, J->m.op.coef.p);
+        remember_state(J->m, p, dt, order);
     });
 }
 
@@ -745,7 +770,8 @@ static void check_ras_desc(const nks_ras_desc *d) {
     if (d->variant < 0 || d->variant > 2 || d->interp_order < 1 || d->interp_order > 3 || d->cycle < 0 ||
         d->cycle > 4 || d->mu < 0 || d->nu < 0 || d->precision < 0 || d->precision > 2 ||
         d->coarse_restart < 1 || d->coarse_maxit < 1 || d->tx < 0 || d->ty < 0 || d->tz < 0 || d->fill < 0 ||
-        d->fill > 4 || d->ratio < 0 || d->ratio == 1 || d->ratio > 16)
+        d->fill > 4 || d->ratio < 0 || d->ratio == 1 || d->ratio > 16 ||
+        (d->coarse_op != NKS_COARSE_GALERKIN && d->coarse_op != NKS_COARSE_REDISCRETIZED))
         fail(NKS_EINVAL, "bad preconditioner option");
 }
 
@@ -755,6 +781,7 @@ int nks_ras_setup(nks_matrix *J, const nks_ras_desc *d, nks_ras **inout) {
         check_ras_desc(d);
         nks_ras *M = *inout;
         std::unique_ptr<nks_ras> hold;
+        if (M && M->owner != J->owner) fail(NKS_EINVAL, "the preconditioner belongs to another grid");
         if (!M) {
             hold.reset(new nks_ras());
             M = hold.get();
@@ -764,15 +791,28 @@ int nks_ras_setup(nks_matrix *J, const nks_ras_desc *d, nks_ras **inout) {
         }
         M->r.factor();
         M->t.stale = true;
-        if (hold) *inout = hold.release();
+        if (M->mat != J) {
+            J->refs++;
+            if (M->mat) matrix_release(M->mat);
+            M->mat = J;
+        }
+        if (hold) {
+            M->owner = J->owner;
+            J->owner->refs++;
+            *inout = hold.release();
+        }
     });
 }
 
 int nks_destroy_ras(nks_ras *M) {
     return guard([&] {
         if (M) {
+            nks_grid *owner = M->owner;
+            nks_matrix *mat = M->mat;
             (void)hipStreamSynchronize(M->r.g->s);
             delete M;
+            if (mat) matrix_release(mat);
+            if (owner) grid_release(owner);
         }
     });
 }
@@ -992,6 +1032,7 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             {
                 ProfScope ps("residual_jacobian", s);
                 launch_flux(g, p, dt, order, nullptr, W.J->op.coef.p);   // props at p are current
+                if (rd->coarse_op == NKS_COARSE_REDISCRETIZED) remember_state(*W.J, p, dt, order);
             }
             // rounding floor: ||F|| <= u || |J| |p| || means p solves F = 0 as
             // well as F can be evaluated in binary64
@@ -1280,6 +1321,7 @@ int nks_ras_autotune(nks_grid *gh, const double *p, const double *pn, const doub
         launch_history(g, pn, pnm1 ? pnm1 : pn, order);
         launch_props(g, p);
         launch_flux(g, p, dt, order, F.p, J.op.coef.p);
+        remember_state(J, p, dt, order);
         launch_axpby(g.sp, -1.0, F.p, 0.0, b.p, nullptr, s);
         Gmres gm;
         gm.ensure(al, g.sp, gd->restart, gd->flexible != 0, s);

@@ -154,7 +154,27 @@ struct Grid {
 struct Matrix {
     Grid *g = nullptr;
     Op op;
+    // the state the Jacobian was last evaluated at (rediscretised coarse
+    // levels are evaluated from it)
+    DBuf<double> state;
+    double dt = 0.0;
+    int order = 1;
+    bool has_state = false;
 };
+
+// Jacobian evaluation bookkeeping: copy p into J.state (asynchronous)
+void remember_state(Matrix &J, const double *p, double dt, int order);
+
+// ------------------------------------------------------------------ rediscretised coarse grids
+// The grid of ratio r coarser than f: every size above one a multiple of r,
+// each permeability component the mean of the children's, pore volume their
+// sum, cells r times larger, the same fluid, gravity and outer faces, no
+// wells, conservative accumulation.  Fails with NKS_EINVAL otherwise.
+void coarsen_grid(const Grid &f, int ratio, Grid &c);
+// pc = mean of each coarse cell's children in pf
+void launch_coarsen_mean(const Grid &f, const Grid &c, const double *pf, double *pc);
+void launch_props(Grid &g, const double *p);
+void launch_flux(Grid &g, const double *p, double dt, int order, double *F, double *J);
 
 // ------------------------------------------------------------------ reductions
 // Per-block sums, deterministic (fixed order), results on the device.

@@ -474,6 +474,120 @@ void launch_residual_into(Grid &g, const double *p, const double *pn, const doub
     KCHECK();
 }
 
+// ---------------------------------------------------------------- rediscretised coarse grids
+// coarse cell I of a block whose fine sizes are r times its own (1 where a
+// size is 1): permeabilities averaged over the children, pore volumes summed
+__global__ void k_upscale(const Blk *fblk, const Blk *cblk, int B, int Nc, const double *kx, const double *ky,
+                          const double *kz, const double *pv, double *ckx, double *cky, double *ckz, double *cpv) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= Nc) return;
+    const int b = find_blk(cblk, B, I);
+    const Blk cb = cblk[b], fb = fblk[b];
+    const int l = I - cb.off;
+    const int X = l % cb.nx, Y = (l / cb.nx) % cb.ny, Z = l / (cb.nx * cb.ny);
+    const int rx = fb.nx / cb.nx, ry = fb.ny / cb.ny, rz = fb.nz / cb.nz;
+    double sx = 0.0, sy = 0.0, sz = 0.0, sv = 0.0;
+    for (int z = Z * rz; z < (Z + 1) * rz; ++z)
+        for (int y = Y * ry; y < (Y + 1) * ry; ++y)
+            for (int x = X * rx; x < (X + 1) * rx; ++x) {
+                const int i = fb.off + x + fb.nx * (y + fb.ny * z);
+                sx += kx[i];
+                sy += ky[i];
+                sz += kz[i];
+                sv += pv[i];
+            }
+    const double inv = 1.0 / (rx * ry * rz);
+    ckx[I] = sx * inv;
+    cky[I] = sy * inv;
+    ckz[I] = sz * inv;
+    cpv[I] = sv;
+}
+
+__global__ void k_coarsen_mean(const Blk *fblk, const Blk *cblk, int B, int Nc, const double *pf, double *pc) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= Nc) return;
+    const int b = find_blk(cblk, B, I);
+    const Blk cb = cblk[b], fb = fblk[b];
+    const int l = I - cb.off;
+    const int X = l % cb.nx, Y = (l / cb.nx) % cb.ny, Z = l / (cb.nx * cb.ny);
+    const int rx = fb.nx / cb.nx, ry = fb.ny / cb.ny, rz = fb.nz / cb.nz;
+    double s = 0.0;
+    for (int z = Z * rz; z < (Z + 1) * rz; ++z)
+        for (int y = Y * ry; y < (Y + 1) * ry; ++y)
+            for (int x = X * rx; x < (X + 1) * rx; ++x) s += pf[fb.off + x + fb.nx * (y + fb.ny * z)];
+    pc[I] = s / (rx * ry * rz);
+}
+
+void coarsen_grid(const Grid &f, int ratio, Grid &c) {
+    std::vector<Blk> cb;
+    std::vector<double> geo(3 * (size_t)f.sp.B);
+    std::vector<double> fgeo(3 * (size_t)f.sp.B);
+    HIPC(hipMemcpyAsync(fgeo.data(), f.geo.p, fgeo.size() * 8, hipMemcpyDeviceToHost, f.s));
+    HIPC(hipStreamSynchronize(f.s));
+    for (int b = 0; b < f.sp.B; ++b) {
+        const Blk &k = f.sp.hblk[b];
+        const int n[3] = {k.nx, k.ny, k.nz};
+        int m[3];
+        for (int a = 0; a < 3; ++a) {
+            const int r = n[a] > 1 ? ratio : 1;
+            if (n[a] % r) fail(NKS_EINVAL, "rediscretised coarse level: reservoir %d size %d is not a multiple of %d",
+                               b, n[a], r);
+            m[a] = n[a] / r;
+            geo[3 * b + a] = fgeo[3 * b + a] * r;
+        }
+        cb.push_back({m[0], m[1], m[2], 0});
+    }
+    c.al = f.al;
+    c.s = f.s;
+    c.dim = f.dim;
+    c.sp.build(&c.al, cb, c.s);
+    const int N = c.sp.N;
+    c.geo.upload(&c.al, geo, c.s);
+    c.kx.alloc(&c.al, N); c.ky.alloc(&c.al, N); c.kz.alloc(&c.al, N);
+    c.pv.alloc(&c.al, N);
+    c.tx.alloc(&c.al, N); c.ty.alloc(&c.al, N); c.tz.alloc(&c.al, N);
+    k_upscale<<<nblk(N, 256), 256, 0, c.s>>>(f.sp.blk.p, c.sp.blk.p, c.sp.B, N, f.kx.p, f.ky.p, f.kz.p, f.pv.p,
+                                             c.kx.p, c.ky.p, c.kz.p, c.pv.p);
+    KCHECK();
+    k_transmissibility<<<nblk(N, 256), 256, 0, c.s>>>(c.sp.blk.p, c.sp.B, N, c.geo.p, c.kx.p, c.ky.p, c.kz.p,
+                                                      c.tx.p, c.ty.p, c.tz.p);
+    KCHECK();
+    c.src.alloc(&c.al, N);
+    HIPC(hipMemsetAsync(c.src.p, 0, sizeof(double) * N, c.s));
+    if (f.bct.p) {
+        std::vector<int> bct(f.bct.n);
+        std::vector<double> bcv(f.bcv.n);
+        HIPC(hipMemcpyAsync(bct.data(), f.bct.p, bct.size() * 4, hipMemcpyDeviceToHost, f.s));
+        HIPC(hipMemcpyAsync(bcv.data(), f.bcv.p, bcv.size() * 8, hipMemcpyDeviceToHost, f.s));
+        HIPC(hipStreamSynchronize(f.s));
+        c.bct.upload(&c.al, bct, c.s);
+        c.bcv.upload(&c.al, bcv, c.s);
+    }
+    c.a = f.a; c.b = f.b; c.RT = f.RT; c.W = f.W; c.mu = f.mu; c.g = f.g;
+    c.accum = NKS_ACCUM_CONSERVATIVE;
+    c.m.alloc(&c.al, N);
+    c.dm.alloc(&c.al, N);
+    c.hist.alloc(&c.al, N);
+    c.tmp.alloc(&c.al, N);
+    c.flags.alloc(&c.al, c.sp.B);
+    HIPC(hipMemsetAsync(c.flags.p, 0, sizeof(int) * c.sp.B, c.s));
+}
+
+void launch_coarsen_mean(const Grid &f, const Grid &c, const double *pf, double *pc) {
+    const int N = c.sp.N;
+    k_coarsen_mean<<<nblk(N, 256), 256, 0, c.s>>>(f.sp.blk.p, c.sp.blk.p, c.sp.B, N, pf, pc);
+    KCHECK();
+}
+
+void remember_state(Matrix &J, const double *p, double dt, int order) {
+    Grid &g = *J.g;
+    J.state.alloc(&g.al, g.sp.N);
+    HIPC(hipMemcpyAsync(J.state.p, p, sizeof(double) * g.sp.N, hipMemcpyDeviceToDevice, g.s));
+    J.dt = dt;
+    J.order = order;
+    J.has_state = true;
+}
+
 void launch_hydrostatic(Grid &g, double p_top, double *p) {
     std::vector<int> cs(g.sp.B);
     int tot = 0;

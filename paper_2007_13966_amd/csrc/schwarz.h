@@ -96,6 +96,8 @@ struct Level {
     // interpolation from the next coarser level to this one
     Interp1 ip[3];
     DBuf<int> rap_slot;          // coarse offset -> slot table for the Galerkin product
+    std::unique_ptr<Grid> cg;    // rediscretised coarse levels: this level's upscaled grid
+    DBuf<double> cstate;         // and the coarsened state its Jacobian is taken at
     int rap_R = 0;
     // work vectors
     DBuf<double> r, t, bc, xc;

@@ -1883,11 +1883,27 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
             nfy.push_back(k.ny);
             nfz.push_back(k.nz);
         }
-        C.sp.build(al, cb, s);
-        C.spp = &C.sp;
         build_interp(F.ip[0], nfx, d.interp_order, rt, al, s);
         build_interp(F.ip[1], nfy, d.interp_order, rt, al, s);
         build_interp(F.ip[2], nfz, d.interp_order, rt, al, s);
+        if (d.coarse_op == NKS_COARSE_REDISCRETIZED) {
+            // the coarse matrix is the Jacobian of the upscaled problem: the
+            // fine stencil on the coarse grid's own space
+            C.cg.reset(new Grid());
+            coarsen_grid(l == 0 ? *g : *F.cg, rt, *C.cg);
+            C.spp = &C.cg->sp;
+            C.cstate.alloc(al, C.spp->N);
+            C.own.sp = C.spp;
+            std::vector<std::tuple<int, int, int>> offs;
+            for (int k = 0; k < F.A->st.K; ++k)
+                offs.push_back({F.A->st.off[3 * k], F.A->st.off[3 * k + 1], F.A->st.off[3 * k + 2]});
+            set_stencil(C.own.st, offs, al, s);
+            C.own.coef.alloc(al, (size_t)C.own.st.K * C.spp->N);
+            C.A = &C.own;
+            continue;
+        }
+        C.sp.build(al, cb, s);
+        C.spp = &C.sp;
         // coarse stencil: union over fine offsets of the tensor 1D coupling sets
         const Stencil &fs = F.A->st;
         std::set<std::tuple<int, int, int>> offs;
@@ -1965,9 +1981,19 @@ static bool use_rows3d(const Ras &M, const Level &V);
 
 void Ras::factor(bool ilu) {
     hipStream_t s = g->s;
+    const bool redisc = d.coarse_op == NKS_COARSE_REDISCRETIZED && L > 1;
+    if (redisc && !J->has_state)
+        fail(NKS_EINVAL, "rediscretised coarse levels need the state of the Jacobian (nks_jacobian)");
     for (int l = 0; l < L; ++l) {
         Level &V = *lev[l];
-        if (l > 0) {
+        if (l > 0 && redisc) {
+            // coarsened state, then the upscaled problem's Jacobian at it
+            const Grid &fg = l == 1 ? *g : *lev[l - 1]->cg;
+            const double *pf = l == 1 ? J->state.p : lev[l - 1]->cstate.p;
+            launch_coarsen_mean(fg, *V.cg, pf, V.cstate.p);
+            launch_props(*V.cg, V.cstate.p);
+            launch_flux(*V.cg, V.cstate.p, J->dt, J->order, nullptr, V.own.coef.p);
+        } else if (l > 0) {
             Level &F = *lev[l - 1];
             XferArgs a = xfer_args(F, V, nullptr);
             const int Kc = V.own.st.K;

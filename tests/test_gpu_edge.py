@@ -106,3 +106,28 @@ def test_bad_descriptors_are_errors(nks):
             nks.Ras(J, S.SolverSettings(**kw))
     with pytest.raises(nks.NksError):
         g.newton_step(p0.clone(), p0, p0, -1.0, 1, S.SolverSettings(px=2, py=2))
+
+
+def test_handles_destroyed_in_any_order(nks):
+    # a matrix and a preconditioner keep their grid's memory: destroying the
+    # grid handle first (as a garbage collector may when the three sit in a
+    # reference cycle) leaves them usable, and the last one frees the grid
+    import ctypes as C
+    case = S.small_case(nx=24, ny=20, px=2, py=2, levels=2, overlap=(1, 1))
+    g = nks.Grid(case.problems)
+    p = g.initial_pressure()
+    J = g.jacobian(p, p, None, case.dt, 1)
+    M = nks.Ras(J, case.solver)
+    r = g.from_numpy(np.cos(np.arange(g.N)))
+    z_ref = M.apply(r).cpu().numpy()
+    lib = nks.lib()
+    assert lib.nks_destroy_grid(g.h) == 0
+    g.h = None
+    z = M.apply(r).cpu().numpy()
+    assert np.array_equal(z, z_ref)
+    assert lib.nks_destroy_matrix(J.h) == 0
+    J.h = None
+    z = M.apply(r).cpu().numpy()
+    assert np.array_equal(z, z_ref)
+    assert lib.nks_destroy_ras(M.h) == 0
+    M.h = None

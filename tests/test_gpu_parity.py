@@ -129,6 +129,26 @@ ILUK = [
 ]
 
 
+@pytest.mark.parametrize("variant", ["left_ras", "as"])
+def test_full_fill_is_the_exact_lu_subsolve(nks, orc, variant):
+    # exact (LU) subdomain solves (Section 4.2 compares ILU(k) with LU): with
+    # boxes at most 4 cells wide, ILU(4) keeps every entry of each box's LU
+    # band, so the library's ILU(4) apply equals the oracle's dense-LU apply
+    cfg = dict(nx=10, ny=8, px=5, py=2, overlap=(1,), seed=3, variant=variant)
+    say("ILU(4) as LU", cfg)
+    case = S.small_case(fill=4, **cfg)
+    rec = case.problems[0]
+    op = orc.Problem(rec)
+    p, pn, _ = _state(op, 23)
+    Jo = op.jacobian(p, pn, pn, case.dt, 1)
+    r = np.random.default_rng(8).standard_normal(op.N)
+    zo = orc.Multilevel(rec, Jo, S.with_solver(case, subsolve="lu", fill=0).solver).apply(r)
+    g = nks.Grid([rec])
+    M = nks.Ras(_gpu_jac(nks, g, p, pn, case.dt), case.solver)
+    zg = M.apply(g.from_numpy(r)).cpu().numpy()
+    assert np.max(np.abs(zg - zo)) <= 1e-10 * np.max(np.abs(zo))
+
+
 @pytest.mark.parametrize("cfg", ILUK)
 def test_iluk_apply_parity(nks, orc, cfg):
     # ILU(k) subdomain solves: the oracle factors each box on its own
