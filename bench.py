@@ -34,7 +34,8 @@ sys.path.insert(0, HERE)
 METRIC = "time/implicit step + ras_apply GB/s, mixed-prec vs FP64 at rel.res 1e-6"
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128",
-             "batch64": "case_batch64", "3d96": "case_3d_96_adjoint", "flood512": "case_2d_flood_512"}
+             "batch64": "case_batch64", "3d96": "case_3d_96_adjoint", "flood512": "case_2d_flood_512",
+             "hzone512": "case_2d_hzone", "layered128": "case_3d_layered_flood"}
 
 # HBM bytes moved per active fine-level launch of the FP64 2D sweep kernel on
 # the 512x512 workload, from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0 and
@@ -410,14 +411,15 @@ def main():
     if autotune:
         g0 = P.Grid(case.problems)
         p0 = g0.initial_pressure()
-        tuned, table = g0.autotune(p0, p0, p0, case.dt, 1, case.solver)
+        ratios = (2, 4, 8) if case.solver.levels > 1 else None
+        tuned, table = g0.autotune(p0, p0, p0, case.dt, 1, case.solver, ratios=ratios)
         del g0
-        case = S.with_solver(case, tile=tuned.tile, overlap=tuned.overlap)
-        tuning = dict(tile=list(tuned.tile), overlap=list(tuned.overlap), table=table)
-        log(f"autotuned: tile {tuned.tile}, overlap {tuned.overlap}")
+        case = S.with_solver(case, tile=tuned.tile, overlap=tuned.overlap, ratio=tuned.ratio)
+        tuning = dict(tile=list(tuned.tile), overlap=list(tuned.overlap), ratio=tuned.ratio, table=table)
+        log(f"autotuned: tile {tuned.tile}, overlap {tuned.overlap}, ratio {tuned.ratio}")
         for e in table:
-            log(f"  tile {e['tile']:3d} overlap {e['overlap']}: ok {e['ok']} its {e['iterations']:3d} "
-                f"setup {e['setup_ms']:.2f} ms solve {e['solve_ms']:.2f} ms")
+            log(f"  tile {e['tile']:3d} overlap {e['overlap']} ratio {e['ratio']:2d}: ok {e['ok']} "
+                f"its {e['iterations']:3d} setup {e['setup_ms']:.2f} ms solve {e['solve_ms']:.2f} ms")
     head = case.solver.precision
     forms = [head] if args.no_mixed else [head] + [f for f in ("fp64", "fp32", "bf16") if f != head]
     log(f"workload {case.name}: {sum(r.N for r in case.problems)} cells, forms {forms}")
@@ -468,6 +470,7 @@ def main():
             "subdomains": int(sum(np.prod(boxes(r, s_head)) for r in case.problems)),
             "overlap": list(s_head.overlap), "precision": head,
             "tile": list(s_head.tile),
+            "ratio": s_head.ratio,
             "autotune": tuning,
             "timed_steps": f"steps 1..{args.steps} from the initial state (BDF1 first, BDF2 after), "
                            f"after {args.warmup} untimed warm-up steps from the same state",

@@ -389,27 +389,30 @@ int nks_adjoint(nks_grid *g, int nsteps, const double *const *p_hist, const int 
                 const double *const *dGdp, const nks_ras_desc *rd, const nks_gmres_desc *gd,
                 double *grad, double *const *lam_out, nks_adjoint_stats *st);
 
-/* Autotuner of the subdomain tile edge and fine-level overlap for the batch
- * form.  At the state (p, p_n, p_nm1, dt, order) it forms the first Newton
- * system J s = -F, and for every (tile, overlap) pair builds the
- * preconditioner base describes with tx = ty (= tz in 3D) = tile and
- * overlap[0] = overlap, then times, averaged over `repeats` runs after one
- * untimed run: the factorisation (setup) and one (F)GMRES solve to gd's
- * tolerance (solve).  best receives the descriptor with the smallest
- * setup + solve time.  table (optional HOST array of ntiles * noverlaps,
- * tile-major) receives every candidate's times; candidates that cannot be
- * set up (e.g. a box larger than LDS allows) have ok = 0.  Synchronous. */
+/* Autotuner of the subdomain tile edge, fine-level overlap and coarse-to-fine
+ * ratio for the batch form.  At the state (p, p_n, p_nm1, dt, order) it
+ * forms the first Newton system J s = -F, and for every (tile, overlap,
+ * ratio) triple builds the preconditioner base describes with tx = ty (= tz
+ * in 3D) = tile, overlap[0] = overlap and ratio = ratio (ratios NULL or
+ * nratios 0: base's ratio only), then times, averaged over `repeats` runs
+ * after one untimed run: the factorisation (setup) and one (F)GMRES solve to
+ * gd's tolerance (solve).  best receives the descriptor with the smallest
+ * setup + solve time.  table (optional HOST array of ntiles * noverlaps *
+ * nratios, tile-major then overlap) receives every candidate's times;
+ * candidates that cannot be set up (e.g. a box larger than LDS allows) have
+ * ok = 0.  Synchronous. */
 typedef struct {
     int tile, overlap;
     int ok;
     int iterations;              /* of the timed solve, max over reservoirs */
     double setup_ms, solve_ms;
+    int ratio;
 } nks_autotune_entry;
 
 int nks_ras_autotune(nks_grid *g, const double *p, const double *p_n, const double *p_nm1, double dt,
                      int bdf_order, const nks_ras_desc *base, const int *tiles, int ntiles,
-                     const int *overlaps, int noverlaps, const nks_gmres_desc *gd, int repeats,
-                     nks_ras_desc *best, nks_autotune_entry *table);
+                     const int *overlaps, int noverlaps, const int *ratios, int nratios,
+                     const nks_gmres_desc *gd, int repeats, nks_ras_desc *best, nks_autotune_entry *table);
 
 /* Kernel timing with HIP events on the launching stream.  Single-kernel
  * records carry the events on the dispatch itself (the kernel's own

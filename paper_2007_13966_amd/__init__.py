@@ -292,10 +292,11 @@ class Grid:
             out["lambda"] = lams
         return grad, out
 
-    def autotune(self, p, pn, pnm1, dt, order, settings, tiles=(8, 16, 32), overlaps=(1, 2), repeats=2,
-                 rtol=None, atol=None):
-        """nks_ras_autotune: returns (settings with the best tile and fine
-        overlap, list of per-candidate timings)."""
+    def autotune(self, p, pn, pnm1, dt, order, settings, tiles=(8, 16, 32), overlaps=(1, 2), ratios=None,
+                 repeats=2, rtol=None, atol=None):
+        """nks_ras_autotune: returns (settings with the best tile, fine
+        overlap and coarse-to-fine ratio, list of per-candidate timings);
+        ratios None: the settings' ratio only."""
         import dataclasses
         rd = ras_desc(settings)
         nd = newton_desc(settings)
@@ -304,17 +305,21 @@ class Grid:
                               settings.eta_a if atol is None else atol, nd.maxit, flex, 0)
         ti = (C.c_int * len(tiles))(*tiles)
         ov = (C.c_int * len(overlaps))(*overlaps)
+        ratios = list(ratios) if ratios else [getattr(settings, "ratio", 2)]
+        ra = (C.c_int * len(ratios))(*ratios)
         best = L.nks_ras_desc()
-        tab = (L.nks_autotune_entry * (len(tiles) * len(overlaps)))()
+        tab = (L.nks_autotune_entry * (len(tiles) * len(overlaps) * len(ratios)))()
         with _Ordered(self):
             check(lib().nks_ras_autotune(self.h, _vp(p), _vp(pn), _vp(pnm1 if pnm1 is not None else pn),
                                          float(dt), int(order), C.byref(rd), ti, len(tiles), ov,
-                                         len(overlaps), C.byref(gd), int(repeats), C.byref(best), tab))
+                                         len(overlaps), ra, len(ratios), C.byref(gd), int(repeats),
+                                         C.byref(best), tab))
         ovl = list(settings.overlap)
         ovl[0] = best.overlap[0]
         tz = best.tz if best.tz > 0 else 0
-        tuned = dataclasses.replace(settings, tile=(best.tx, best.ty, tz), overlap=tuple(ovl))
-        table = [dict(tile=e.tile, overlap=e.overlap, ok=bool(e.ok), iterations=e.iterations,
+        tuned = dataclasses.replace(settings, tile=(best.tx, best.ty, tz), overlap=tuple(ovl),
+                                    ratio=best.ratio if best.ratio > 0 else 2)
+        table = [dict(tile=e.tile, overlap=e.overlap, ratio=e.ratio, ok=bool(e.ok), iterations=e.iterations,
                       setup_ms=e.setup_ms, solve_ms=e.solve_ms) for e in tab]
         return tuned, table
 

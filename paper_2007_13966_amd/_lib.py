@@ -91,7 +91,7 @@ class nks_adjoint_stats(C.Structure):
 
 class nks_autotune_entry(C.Structure):
     _fields_ = [("tile", C.c_int), ("overlap", C.c_int), ("ok", C.c_int), ("iterations", C.c_int),
-                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("ratio", C.c_int)]
 
 
 _P = C.c_void_p
@@ -131,7 +131,7 @@ PROTOTYPES = {
     "nks_adjoint": [_P, _I, C.POINTER(C.c_void_p), _IP, _D, C.POINTER(C.c_void_p),
                     C.POINTER(nks_ras_desc), C.POINTER(nks_gmres_desc), _P, C.POINTER(C.c_void_p),
                     C.POINTER(nks_adjoint_stats)],
-    "nks_ras_autotune": [_P, _P, _P, _P, _D, _I, C.POINTER(nks_ras_desc), _IP, _I, _IP, _I,
+    "nks_ras_autotune": [_P, _P, _P, _P, _D, _I, C.POINTER(nks_ras_desc), _IP, _I, _IP, _I, _IP, _I,
                          C.POINTER(nks_gmres_desc), _I, C.POINTER(nks_ras_desc),
                          C.POINTER(nks_autotune_entry)],
     "nks_profile_enable": [_I],

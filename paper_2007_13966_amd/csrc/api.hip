@@ -1296,11 +1296,20 @@ int nks_adjoint(nks_grid *gh, int nsteps, const double *const *p_hist, const int
 // ------------------------------------------------------------------ tile / overlap autotuner
 int nks_ras_autotune(nks_grid *gh, const double *p, const double *pn, const double *pnm1, double dt, int order,
                      const nks_ras_desc *base, const int *tiles, int ntiles, const int *overlaps, int noverlaps,
-                     const nks_gmres_desc *gd, int repeats, nks_ras_desc *best, nks_autotune_entry *table) {
+                     const int *ratios, int nratios, const nks_gmres_desc *gd, int repeats, nks_ras_desc *best,
+                     nks_autotune_entry *table) {
     return guard([&] {
         if (!gh || !p || !pn || !(dt > 0) || (order != 1 && order != 2) || (order == 2 && !pnm1) || !base ||
-            !tiles || ntiles < 1 || !overlaps || noverlaps < 1 || !gd || !best || repeats < 1)
+            !tiles || ntiles < 1 || !overlaps || noverlaps < 1 || !gd || !best || repeats < 1 ||
+            (nratios > 0 && !ratios))
             fail(NKS_EINVAL, "bad arguments");
+        const int base_ratio = base->ratio;
+        if (nratios < 1) {
+            ratios = &base_ratio;
+            nratios = 1;
+        }
+        for (int i = 0; i < nratios; ++i)
+            if (ratios[i] != 0 && (ratios[i] < 2 || ratios[i] > 16)) fail(NKS_EINVAL, "ratios must be 2..16");
         if (gd->restart < 1 || gd->restart > 30 || gd->maxit < 1) fail(NKS_EINVAL, "bad GMRES descriptor");
         check_ras_desc(base);
         for (int i = 0; i < ntiles; ++i)
@@ -1329,14 +1338,16 @@ int nks_ras_autotune(nks_grid *gh, const double *p, const double *pn, const doub
         int k = 0;
         bool any = false;
         for (int it = 0; it < ntiles; ++it) {
-            for (int io = 0; io < noverlaps; ++io, ++k) {
+            for (int io = 0; io < noverlaps; ++io) for (int ir = 0; ir < nratios; ++ir, ++k) {
                 nks_ras_desc d = *base;
                 d.tx = d.ty = tiles[it];
                 d.tz = g.dim == 3 ? tiles[it] : 0;
                 d.overlap[0] = overlaps[io];
+                d.ratio = ratios[ir];
                 nks_autotune_entry e{};
                 e.tile = tiles[it];
                 e.overlap = overlaps[io];
+                e.ratio = ratios[ir] > 0 ? ratios[ir] : 2;
                 e.ok = 0;
                 try {
                     Ras M;

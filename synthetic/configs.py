@@ -15,7 +15,7 @@ from typing import List, Optional, Tuple
 
 import numpy as np
 
-from .fields import lognormal_perm, layered_perm, channel_perm
+from .fields import lognormal_perm, layered_perm, channel_perm, hzone_mask
 
 MD = 9.869233e-16     # m^2 per millidarcy
 DAY = 86400.0         # s
@@ -174,6 +174,54 @@ def case_2d_flood_512():
     return replace(case, nsteps=10, description=case_2d_flood_512.__doc__)
 
 
+# permeabilities of the H-zone stand-ins: a jump of two orders of magnitude
+HZONE_IN_MD = 500.0
+HZONE_OUT_MD = 5.0
+
+
+def case_2d_hzone(n=512, anisotropic=False, px=16, py=16, nsteps=100):
+    """Stand-in for the paper's first 2D test (its H-zone field is shown only as
+    a figure): the (0, 100 m)^2 square on n x n cells, an H-shaped zone of
+    500 mD in a 5 mD background (isotropic), or with k_yy = k_xx/10 inside the
+    zone (anisotropic: the two domains differ in isotropy); gas at 1 atm and
+    298 K with the paper's methane constants; p^D = 10 atm on the -y face and
+    1 atm on the +y face, x faces closed, no wells, no gravity; phi 0.2;
+    steps of 0.1 day (100 steps to 10 days); two-level V-cycle, 16x16
+    subdomains, overlap 2 on both levels, FP64."""
+    mask = hzone_mask(n, n).ravel()
+    kx = np.where(mask, HZONE_IN_MD, HZONE_OUT_MD) * MD
+    ky = kx * np.where(mask, 0.1, 1.0) if anisotropic else kx.copy()
+    h = 100.0 / n
+    prob = Problem(n, n, 1, h, h, h, kx, ky, kx.copy(), np.full(n * n, 0.2), *_wells([], []),
+                   p_init=ATM, bc_type=(0, 0, 1, 1, 0, 0), bc_value=(0.0, 0.0, 10 * ATM, ATM, 0.0, 0.0))
+    prob.fluid = replace(prob.fluid, T=298.0, Tc=190.58, pc=4.604e6, Tb=111.67)
+    s = SolverSettings(px=px, py=py, pz=1, overlap=(2, 2), levels=2)
+    kind = "aniso" if anisotropic else "iso"
+    return Case(f"2d_{n}x{n}_hzone_{kind}", [prob], 0.1 * DAY, nsteps, s, case_2d_hzone.__doc__)
+
+
+def case_3d_layered_flood(n=128, px=8, py=8, pz=8, nsteps=5):
+    """Stand-in for the paper's 3D layered test: the (0, 100 m)^3 cube on n^3
+    cells whose layers with z in [25, 75] m carry the H-zone field of the 2D
+    stand-in (isotropic, 500 mD in 5 mD) and the others the 5 mD background;
+    gas at 1 atm and 298 K (paper's methane constants), gravity on with the
+    hydrostatic state from 1 atm at the top; p^D = 10 atm on the +y face (the
+    behind face) and 1 atm on the -y face (the front), the other faces
+    closed, no wells; phi 0.2; steps of 0.1 day; three-level V-cycle with
+    first-order interpolation, 8x8x8 subdomains, overlap 1, FP64."""
+    mask2 = hzone_mask(n, n)
+    zc = (np.arange(n) + 0.5) / n
+    layer = (zc >= 0.25) & (zc <= 0.75)
+    k = np.where(layer[:, None, None] & mask2[None, :, :], HZONE_IN_MD, HZONE_OUT_MD).ravel() * MD
+    h = 100.0 / n
+    prob = Problem(n, n, n, h, h, h, k, k.copy(), k.copy(), np.full(n ** 3, 0.2), *_wells([], []),
+                   gravity=True, p_init=ATM, bc_type=(0, 0, 1, 1, 0, 0),
+                   bc_value=(0.0, 0.0, ATM, 10 * ATM, 0.0, 0.0))
+    prob.fluid = replace(prob.fluid, T=298.0, Tc=190.58, pc=4.604e6, Tb=111.67)
+    s = SolverSettings(px=px, py=py, pz=pz, overlap=(1, 1, 1), levels=3, interp_order=1)
+    return Case(f"3d_{n}x{n}x{n}_layered_flood", [prob], 0.1 * DAY, nsteps, s, case_3d_layered_flood.__doc__)
+
+
 def case_2d_32():
     """2D 32x32, homogeneous 100 mD, phi 0.2, p0 20 MPa, injector (0,0) and
     producer (31,31) at 1e-3 kg/s, no gravity, 2 steps of 1 day (BDF1 then BDF2),
@@ -239,12 +287,14 @@ def case_3d_128(nx=128, ny=128, nz=64, precision="fp32"):
                 case_3d_128.__doc__)
 
 
-def case_batch64(nres=64, nmin=64, nmax=256, tile=32, overlap=1):
+def case_batch64(nres=64, nmin=64, nmax=256, tile=32, overlap=1, ratio=4):
     """64 independent 2D reservoirs, side n_b uniform in {64..256}, sigma_b
     uniform in [0.5, 2], corr. length 8, mean 100 mD, phi 0.2, one injector and
     one producer (+-1e-3 kg/s) at seeded cells at least n_b/4 apart
     (seeds 400..463), 3 steps of 5 days, two-level V-cycle, FP32 preconditioner
-    with FP64 outer solve.  Subdomain tile side and overlap are tunable."""
+    with FP64 outer solve.  Subdomain tile side, overlap and coarse-to-fine
+    ratio are tunable; the defaults are the autotuner's choice on MI355X
+    (tile 32, overlap 1, ratio 4)."""
     rng = np.random.Generator(np.random.PCG64(4000))
     probs = []
     for b in range(nres):
@@ -261,7 +311,7 @@ def case_batch64(nres=64, nmin=64, nmax=256, tile=32, overlap=1):
         probs.append(Problem(n, n, 1, 10.0, 10.0, 10.0, k.copy(), k.copy(), k.copy(),
                              np.full(n * n, 0.2), wc, wr))
     s = SolverSettings(px=1, py=1, pz=1, tile=(tile, tile, 0), overlap=(overlap, 1), levels=2,
-                       precision="fp32")
+                       precision="fp32", ratio=ratio)
     return Case(f"batch{nres}_2d_fp32prec", probs, 5 * DAY, 3, s, case_batch64.__doc__)
 
 

@@ -73,3 +73,15 @@ def channel_perm(nx, ny, nz, k_bg, k_ch, nchan, seed):
         mask2 = np.abs(y[:, None] - yc[None, :]) <= 0.5 * width  # (ny, nx)
         out[z0:z0 + band][:, mask2] = k_ch
     return out
+
+
+def hzone_mask(nx, ny):
+    """Cells of an H-shaped zone on the unit square (x fastest): two bars at
+    x in [0.20, 0.35] and [0.65, 0.80] for y in [0.15, 0.85], joined by a
+    crossbar x in [0.35, 0.65], y in [0.425, 0.575] (cell centres)."""
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+    bars = (((X >= 0.20) & (X <= 0.35)) | ((X >= 0.65) & (X <= 0.80))) & (Y >= 0.15) & (Y <= 0.85)
+    cross = (X > 0.35) & (X < 0.65) & (Y >= 0.425) & (Y <= 0.575)
+    return bars | cross

@@ -34,13 +34,17 @@ def test_autotune_then_newton_parity(nks, orc):
     case = S.Case("batch", recs, S.DAY, 1, settings)
     g = nks.Grid(recs)
     p0 = g.initial_pressure()
-    tuned, table = g.autotune(p0, p0, p0, case.dt, 1, settings, tiles=(8, 12, 24), overlaps=(1, 2))
+    tuned, table = g.autotune(p0, p0, p0, case.dt, 1, settings, tiles=(8, 12, 24), overlaps=(1, 2),
+                              ratios=(2, 4))
     for e in table:
         say(e)
     ok = [e for e in table if e["ok"]]
-    assert len(ok) == len(table)
+    assert len(ok) == len(table) == 12
+    assert [(e["tile"], e["overlap"], e["ratio"]) for e in table] == \
+        [(t, o, r) for t in (8, 12, 24) for o in (1, 2) for r in (2, 4)]
     best = min(ok, key=lambda e: e["setup_ms"] + e["solve_ms"])
     assert tuned.tile[:2] == (best["tile"], best["tile"]) and tuned.overlap[0] == best["overlap"]
+    assert tuned.ratio == best["ratio"]
     p = p0.clone()
     st = g.newton_step(p, p0, p0, case.dt, 1, tuned)
     assert st["status"] == 0
