@@ -37,29 +37,62 @@ WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128
              "batch64": "case_batch64", "3d96": "case_3d_96_adjoint", "flood512": "case_2d_flood_512",
              "hzone512": "case_2d_hzone", "layered128": "case_3d_layered_flood"}
 
-# HBM bytes moved per active fine-level launch of the FP64 2D sweep kernel on
-# the 512x512 workload, from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0 and
-# WRITE_SIZE x 1.0, the factors that make a 256 MiB device copy read and write
-# 256 MiB).  Valid only for the kernel source it was taken on: any edit of that
-# file drops it to null until the counters are taken again.
-PMC_TRAFFIC = {
-    "workload": "2d_512x512_twolevel_fp64",
-    "source": "paper_2007_13966_amd/csrc/schwarz.hip",
-    "sha1": "412546ad8237521c76a11623611ee6fb4fcfc343",
-    "fetch_kib": 8854.3, "fetch_scale": 2.0,
-    "write_kib": 2048.0, "write_scale": 1.0,
-}
+# HBM bytes per launch of a sweep kernel over a whole level (no reservoir
+# masked out), from two rocprofv3 --pmc passes over `bench.py --apply-level L`
+# (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by the factors that
+# make a 256 MiB device copy read and write 256 MiB), keyed by workload and
+# level.  Valid only for the kernel source they were taken on: any edit of
+# that file drops them to null until the counters are taken again.
+PMC_SOURCE = "paper_2007_13966_amd/csrc/schwarz.hip"
+PMC_TRAFFIC = {}
 
 
-def pmc_traffic(workload):
+def pmc_traffic(workload, level):
     import hashlib
-    t = PMC_TRAFFIC
-    if workload != t["workload"]:
+    t = PMC_TRAFFIC.get((workload, level))
+    if t is None:
         return None
-    with open(os.path.join(HERE, t["source"]), "rb") as f:
+    with open(os.path.join(HERE, PMC_SOURCE), "rb") as f:
         if hashlib.sha1(f.read()).hexdigest() != t["sha1"]:
             return None
-    return 1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+    hbm = 1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+    return {"hbm_bytes_per_full_launch": hbm, "algorithmic_bytes_per_full_launch": t["algorithmic"],
+            "ratio": hbm / t["algorithmic"], "kernel": t["kernel"]}
+
+
+def apply_level_mode(P, S, case, level, repeats):
+    """One-level sweeps of `level` over the whole grid (no masks), `repeats`
+    times at the initial state, for counter passes; prints the swept cells
+    and algorithmic bytes of one launch."""
+    import ctypes as C
+    import torch
+    s = case.solver
+    g = P.Grid(case.problems)
+    p0 = g.initial_pressure()
+    J = g.jacobian(p0, p0, None, case.dt, 1)
+    M = P.Ras(J, s)
+    K = M.level_info(level)["K"]
+    r = torch.ones(M.level_info(level)["n"], dtype=torch.float64, device=p0.device)
+    M.apply_level(level, r)
+    torch.cuda.synchronize()
+    P.check(P.lib().nks_profile_filter(f"ras_apply_l{level}".encode()))
+    P.check(P.lib().nks_profile_enable(1))
+    for _ in range(repeats):
+        M.apply_level(level, r)
+    torch.cuda.synchronize()
+    cells = (C.c_double * 2)()
+    P.check(P.lib().nks_profile_units(f"ras_apply_l{level}".encode(), cells))
+    c = C.c_int()
+    t = C.c_double()
+    P.check(P.lib().nks_profile_query(f"ras_apply_l{level}".encode(), C.byref(c), C.byref(t)))
+    P.check(P.lib().nks_profile_enable(0))
+    fb = {"fp64": 8, "fp32": 4, "bf16": 2}[s.precision]
+    db = 8 if s.precision == "fp64" else 4
+    ext, owned = cells[0] / repeats, cells[1] / repeats
+    nbytes = ext * ((K - 1) * fb + db + 8) + owned * 8
+    print(json.dumps({"workload": case.name, "level": level, "precision": s.precision, "launches": repeats,
+                      "ext_cells": ext, "owned_cells": owned, "stencil_points": K,
+                      "algorithmic_bytes": nbytes, "avg_launch_us": 1e3 * t.value / max(1, c.value)}))
 
 
 def log(*a):
@@ -113,23 +146,37 @@ def launch_split(d):
     return d[d >= np.median(d) / 2]
 
 
-def level_bytes(P, case, s, level):
-    """Algorithmic bytes of one FP64 one-level apply on `level` (coarse
-    levels: the same boxes on the coarsened grids, that level's overlap and
-    its Galerkin stencil size from the library)."""
+def level_stencils(P, case, s):
+    """Stencil points of every level's operator (the Jacobian's on the
+    finest, the coarse operators' below) for the preconditioner s builds."""
     g = P.Grid(case.problems)
     p0 = g.initial_pressure()
     J = g.jacobian(p0, p0, None, case.dt, 1)
-    info = P.Ras(J, s).level_info(level)
-    K, n = info["K"], info["n"]
-    ne = 0
-    for rec in case.problems:
-        d = [rec.nx, rec.ny, rec.nz]
-        for _ in range(level):
-            d = [-(-x // s.ratio) if x > 1 else 1 for x in d]
-        nb = boxes(rec, s)
-        ne += ext_cells(d[0], d[1], d[2], *nb, s.overlap[min(level, len(s.overlap) - 1)])
-    return ne * ((K - 1) * 8 + 8 + 8) + n * 8, K
+    M = P.Ras(J, s)
+    return [M.level_info(l)["K"] for l in range(s.levels)]
+
+
+def sweep_roofline(run, name, K, precision):
+    """Achieved bandwidth of one sweep record over its profiled launches: the
+    algorithmic bytes of the cells they swept (per extended cell the K-1
+    off-diagonal factors, 1/u and the gathered residual; per owned cell the
+    written correction) over their summed duration."""
+    d = run["breakdown"].get(name, np.zeros(0))
+    ext, owned = run["units"].get(name, (0.0, 0.0))
+    if d.size == 0 or ext == 0:
+        return None
+    fb = {"fp64": 8, "fp32": 4, "bf16": 2}[precision]
+    db = 8 if precision == "fp64" else 4
+    nbytes = ext * ((K - 1) * fb + db + 8) + owned * 8
+    sec = float(d.sum()) / 1e3
+    ach = nbytes / sec / 1e9
+    act = launch_split(d)
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "stencil_points": K, "launches": int(d.size), "masked_launches": int(d.size - act.size),
+            "avg_launch_us": 1e3 * float(d.mean()), "total_ms": float(d.sum()),
+            "bytes_total": nbytes, "bytes_per_launch": nbytes / d.size,
+            "ext_cells_swept": ext, "owned_cells_swept": owned,
+            "bytes_per_ext_cell": (K - 1) * fb + db + 8, "bytes_per_owned_cell": 8}
 
 
 def copy_bandwidth(torch, mib=1024, reps=5):
@@ -151,9 +198,9 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return 2 * 8 * n / sec / 1e9
 
 
-ROOFLINE_RECORDS = ["ras_apply_l0", "ras_apply_l1"]
-BREAKDOWN_RECORDS = ["ras_apply_l0", "ras_apply_l1", "ras_apply_l2", "spmv_l0", "spmv_l1", "gmres_arnoldi",
-                     "residual_jacobian", "ilu_factor_l0", "ilu_factor_l1", "ilu_factor_l2", "rap_l1", "rap_l2"]
+SWEEP_RECORDS = ["ras_apply_l0", "ras_apply_l1", "ras_apply_l2"]
+BREAKDOWN_RECORDS = SWEEP_RECORDS + ["spmv_l0", "spmv_l1", "gmres_arnoldi", "residual_jacobian", "ilu_factor_l0",
+                                     "ilu_factor_l1", "ilu_factor_l2", "rap_l1", "rap_l2"]
 
 
 def step_record(st):
@@ -170,7 +217,11 @@ def step_record(st):
 def run_gpu(P, case, settings, warmup, steps, keep_states=0, profile=True, breakdown_steps=2):
     """Warm-up steps from the initial state (untimed; the first keep_states
     states kept for the oracle comparison), then `steps` timed steps from the
-    initial state again, then optional profiled steps for the breakdown."""
+    initial state again (no profiling), then `breakdown_steps` profiled steps
+    continuing the trajectory: every launch recorded with HIP events on its
+    dispatch (the coarse iterations otherwise replayed from captured graphs
+    run as plain launches there), and the cells each sweep launch swept counted
+    on the device."""
     import torch
     g = P.Grid(case.problems)
     p_init = g.initial_pressure()
@@ -210,30 +261,26 @@ def run_gpu(P, case, settings, warmup, steps, keep_states=0, profile=True, break
             states.append(pnew.cpu().numpy())
     torch.cuda.synchronize()
     step = trajectory()
-    if profile:
-        # inside the timed region only the sweeps behind the roofline figures
-        # carry events; the other launches take no host bookkeeping
-        P.check(P.lib().nks_profile_filter(",".join(ROOFLINE_RECORDS).encode()))
-        P.check(P.lib().nks_profile_enable(1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = [step(k)[0] for k in range(steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof, breakdown = {}, {}
-    if profile:
-        prof = collect(ROOFLINE_RECORDS)
+    breakdown, units = {}, {}
+    if profile and breakdown_steps:
+        import ctypes as C
+        P.check(P.lib().nks_profile_filter(None))
+        P.check(P.lib().nks_profile_enable(2))
+        for k in range(breakdown_steps):
+            step(steps + k)
+        torch.cuda.synchronize()
+        breakdown = collect(BREAKDOWN_RECORDS)
+        for name in SWEEP_RECORDS:
+            cells = (C.c_double * 2)()
+            P.check(P.lib().nks_profile_units(name.encode(), cells))
+            units[name] = (cells[0], cells[1])
         P.check(P.lib().nks_profile_enable(0))
-        if breakdown_steps:
-            # every record, over separate steps after the timed ones
-            P.check(P.lib().nks_profile_filter(None))
-            P.check(P.lib().nks_profile_enable(1))
-            for k in range(breakdown_steps):
-                step(steps + k)
-            torch.cuda.synchronize()
-            breakdown = collect(BREAKDOWN_RECORDS)
-            P.check(P.lib().nks_profile_enable(0))
-    return dict(seconds=t1 - t0, stats=stats, prof=prof, breakdown=breakdown, states=states,
+    return dict(seconds=t1 - t0, stats=stats, breakdown=breakdown, units=units, states=states,
                 p_init=p_init.cpu().numpy(), offsets=g.offsets.copy())
 
 
@@ -323,11 +370,8 @@ def oracle_errors(run, orc, nsteps):
                 steps_compared=min(nsteps, len(run["states"])))
 
 
-def form_summary(case, settings, run, steps, orc, ncheck):
+def form_summary(case, settings, run, steps, orc, ncheck, stencils):
     sec = run["seconds"] / steps
-    nbytes, nexts = apply_bytes(case.problems, settings, settings.precision)
-    act = launch_split(run["prof"].get("ras_apply_l0", np.zeros(0)))
-    ach = nbytes / (float(act.mean()) / 1e3) / 1e9 if act.size else None
     recs = [step_record(x) for x in run["stats"]]
     out = {
         "s_per_step": sec,
@@ -335,10 +379,12 @@ def form_summary(case, settings, run, steps, orc, ncheck):
         "gmres_its_per_newton": float(sum(r["gmres"] for r in recs) / max(1, sum(r["newton"] for r in recs))),
         "rel_res_reached_max": max(r["rel_res_max"] for r in recs),
         "steps": recs,
-        "ras_apply_l0_gbs": ach,
-        "ras_apply_l0_frac": (ach / HBM_PEAK_GBS) if ach else None,
-        "ras_apply_l0_bytes": nbytes,
     }
+    for lvl, K in enumerate(stencils[:2]):
+        rf = sweep_roofline(run, f"ras_apply_l{lvl}", K, settings.precision)
+        if rf:
+            out[f"ras_apply_l{lvl}_gbs"] = rf["achieved"]
+            out[f"ras_apply_l{lvl}_frac"] = rf["frac"]
     if orc is not None:
         out["vs_oracle"] = oracle_errors(run, orc, ncheck)
     return out
@@ -365,6 +411,10 @@ def main():
     ap.add_argument("--autotune", type=int, default=-1, choices=[-1, 0, 1],
                     help="choose the subdomain tile edge (8, 16, 32) and fine overlap (1, 2) with "
                          "nks_ras_autotune at the initial state (-1: on for the batch workload)")
+    ap.add_argument("--apply-level", type=int, default=-1, metavar="L",
+                    help="only run the one-level sweeps of level L over the whole workload (the tuned "
+                         "defaults, no masks) --repeats times, for hardware counter passes, and exit")
+    ap.add_argument("--repeats", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB five times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
@@ -386,7 +436,7 @@ def main():
 
     # the oracle first: its workers are forked before anything touches the GPU
     orc = None
-    if not args.no_cpu_baseline and not args.copy_calibration:
+    if not args.no_cpu_baseline and not args.copy_calibration and args.apply_level < 0:
         workers = cpu_cores()
         log(f"oracle: {len(case.problems)} reservoirs x {ncheck} steps on {workers} worker processes")
         orc = oracle_run(case, ncheck, workers)
@@ -406,6 +456,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 5}))
         return
+    if args.apply_level >= 0:
+        apply_level_mode(P, S, case, args.apply_level, args.repeats)
+        return
     autotune = args.autotune if args.autotune >= 0 else int(args.workload == "batch64")
     tuning = None
     if autotune:
@@ -423,12 +476,13 @@ def main():
     head = case.solver.precision
     forms = [head] if args.no_mixed else [head] + [f for f in ("fp64", "fp32", "bf16") if f != head]
     log(f"workload {case.name}: {sum(r.N for r in case.problems)} cells, forms {forms}")
+    stencils = level_stencils(P, case, case.solver)
     runs, summ = {}, {}
     for f in forms:
         sf = S.with_solver(case, precision=f).solver
         runs[f] = run_gpu(P, case, sf, args.warmup, args.steps, keep_states=ncheck if orc else 0,
-                          breakdown_steps=2 if f == head else 0)
-        summ[f] = form_summary(case, sf, runs[f], args.steps, orc, ncheck)
+                          breakdown_steps=2)
+        summ[f] = form_summary(case, sf, runs[f], args.steps, orc, ncheck, stencils)
         e = summ[f].get("vs_oracle", {})
         log(f"{f}: {summ[f]['s_per_step']:.4f} s/step, newton {[r['newton'] for r in summ[f]['steps']]}, "
             f"gmres {[r['gmres'] for r in summ[f]['steps']]}, rel.res reached <= "
@@ -436,14 +490,20 @@ def main():
     s_head = S.with_solver(case, precision=head).solver
     r_head = runs[head]
     sec = summ[head]["s_per_step"]
-    nbytes, nexts = apply_bytes(case.problems, s_head, head)
-    allv = r_head["prof"].get("ras_apply_l0", np.zeros(0))
-    act = launch_split(allv)
-    cnt = int(act.size)
-    avg_s = float(act.mean()) / 1e3 if cnt else 0.0
-    achieved = nbytes / avg_s / 1e9 if cnt else None
     tname = {"fp64": "double, double, double", "fp32": "float, float, float",
              "bf16": "uint16_t, float, float"}[head]
+    # the dominant kernel of the step: the sweep record with the most time in
+    # the profiled steps (the coarse level's sweeps run inside every coarse
+    # GMRES iteration; the finest level's twice per V-cycle)
+    sweeps = {}
+    for lvl, K in enumerate(stencils):
+        rf = sweep_roofline(r_head, f"ras_apply_l{lvl}", K, head)
+        if rf:
+            two_d = all(r.nz == 1 for r in case.problems)
+            kern = f"k_ras_rows<{tname}, ...>" if two_d else f"k_ras_apply / k_ras_rows3d <{tname}, ...>"
+            rf["kernel"] = f"{kern}: level-{lvl} one-level left-RAS sweeps, {K}-point operator, ILU(0) factors"
+            sweeps[lvl] = rf
+    dom = max(sweeps, key=lambda l: sweeps[l]["total_ms"]) if sweeps else None
     out = {
         "metric": METRIC,
         "value": sec,
@@ -481,23 +541,11 @@ def main():
             "per_step": summ[head]["steps"],
         },
         "forms": summ,
-        "roofline": {
-            "kernel": (f"k_ras_apply<{tname}, 3> (fine level 3D 7-point sweeps: one-level left-RAS, "
-                       "ILU(0) factors)" if case.problems[0].nz > 1 else
-                       f"k_ras_rows<{tname}, 0, ...> (fine level 2D sweeps: one-level left-RAS, ILU(0) factors)"),
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": pmc_traffic(case.name),
-            "bytes_per_launch": nbytes,
-            "ext_cells": nexts,
-            "launches": cnt,
-            "masked_launches": int(allv.size - cnt),
-            "avg_launch_us": avg_s * 1e6,
-        },
-        "roofline_coarse": None,
+        "roofline": dict(sweeps[dom], traffic=pmc_traffic(case.name, dom),
+                         measured="the profiled steps after the timed ones: every launch of the record "
+                                  "with HIP events on its dispatch, bytes from the cells the launches swept "
+                                  "(counted on the device)") if dom is not None else None,
+        "roofline_sweeps": {f"level_{l}": v for l, v in sweeps.items()},
         "roofline_spmv": None,
         "stream_copy_gbs": None,
         # launches outside captured graphs, over 2 profiled steps after the timed ones
@@ -507,18 +555,6 @@ def main():
     }
     if "fp64" in summ and head != "fp64":
         out["mixed_vs_fp64_speedup"] = summ["fp64"]["s_per_step"] / sec
-    if s_head.levels > 1:
-        # the coarse level's sweeps run inside every coarse GMRES iteration
-        cb, ck = level_bytes(P, case, S.with_solver(case, precision="fp64").solver, 1)
-        cl = launch_split(r_head["prof"].get("ras_apply_l1", np.zeros(0)))
-        ca = cb / (float(cl.mean()) / 1e3) / 1e9 if cl.size else None
-        out["roofline_coarse"] = {
-            "kernel": f"level-1 one-level sweeps ({ck}-point Galerkin stencil), launches outside graphs; "
-                      f"bytes counted at FP64",
-            "bound": "hbm", "achieved": ca, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (ca / HBM_PEAK_GBS) if ca else None, "bytes_per_launch": cb,
-            "launches": int(cl.size), "avg_launch_us": float(cl.mean()) * 1e3 if cl.size else None,
-        }
     sp = r_head["breakdown"].get("spmv_l0", np.zeros(0))
     if sp.size and all(r.nz == 1 for r in case.problems):
         # 2D: the 5-point launches are the fine level's residuals r = b - A x

@@ -389,11 +389,11 @@ int nks_adjoint(nks_grid *g, int nsteps, const double *const *p_hist, const int 
                 const double *const *dGdp, const nks_ras_desc *rd, const nks_gmres_desc *gd,
                 double *grad, double *const *lam_out, nks_adjoint_stats *st);
 
-/* Autotuner of the subdomain tile edge, fine-level overlap and coarse-to-fine
+/* Autotuner of the subdomain tile edge, overlap and coarse-to-fine
  * ratio for the batch form.  At the state (p, p_n, p_nm1, dt, order) it
  * forms the first Newton system J s = -F, and for every (tile, overlap,
  * ratio) triple builds the preconditioner base describes with tx = ty (= tz
- * in 3D) = tile, overlap[0] = overlap and ratio = ratio (ratios NULL or
+ * in 3D) = tile, the overlap on every level = overlap and ratio = ratio (ratios NULL or
  * nratios 0: base's ratio only), then times, averaged over `repeats` runs
  * after one untimed run: the factorisation (setup) and one (F)GMRES solve to
  * gd's tolerance (solve).  best receives the descriptor with the smallest
@@ -420,7 +420,9 @@ int nks_ras_autotune(nks_grid *g, const double *p, const double *p_n, const doub
  * "ilu_factor_l<level>", "rap_l<level>", "spmv_l<0|1>" (7-or-fewer-point /
  * wider stencils).  Span records bracket several kernels: "gmres_arnoldi"
  * (the Arnoldi step after the preconditioner), "residual_jacobian".  Launches inside captured graphs are not recorded.
- * enable != 0 clears the records and starts recording, 0 stops.  query
+ * enable != 0 clears the records and starts recording, 0 stops; enable = 2
+ * also runs the iterations otherwise replayed from captured graphs (the
+ * coarse GMRES chunks) as plain launches, so every launch is recorded.  query
  * synchronises and returns the number of launches and their summed duration
  * (ms); unknown names give 0.  durations writes the first min(cap, count)
  * per-launch durations (ms, launch order) to host array ms and the record
@@ -433,6 +435,12 @@ int nks_profile_enable(int enable);
 int nks_profile_filter(const char *names);
 int nks_profile_query(const char *name, int *count, double *total_ms);
 int nks_profile_durations(const char *name, double *ms, int cap, int *count);
+/* For the one-level Schwarz sweep records ("ras_apply_l<level>"): cells[0] =
+ * extended cells and cells[1] = owned cells of the subdomains the recorded
+ * launches swept, summed over those launches (subdomains of reservoirs masked
+ * out are not counted), so the bytes a launch moves follow from the per-cell
+ * factor and vector bytes.  Synchronises the device; 0 for unknown names. */
+int nks_profile_units(const char *name, double *cells);
 
 /* Thread-local message of the last failing call (empty when none). */
 const char *nks_last_error(void);

@@ -294,9 +294,9 @@ class Grid:
 
     def autotune(self, p, pn, pnm1, dt, order, settings, tiles=(8, 16, 32), overlaps=(1, 2), ratios=None,
                  repeats=2, rtol=None, atol=None):
-        """nks_ras_autotune: returns (settings with the best tile, fine
-        overlap and coarse-to-fine ratio, list of per-candidate timings);
-        ratios None: the settings' ratio only."""
+        """nks_ras_autotune: returns (settings with the best tile, overlap
+        (the same on every level) and coarse-to-fine ratio, list of
+        per-candidate timings); ratios None: the settings' ratio only."""
         import dataclasses
         rd = ras_desc(settings)
         nd = newton_desc(settings)
@@ -314,8 +314,7 @@ class Grid:
                                          float(dt), int(order), C.byref(rd), ti, len(tiles), ov,
                                          len(overlaps), ra, len(ratios), C.byref(gd), int(repeats),
                                          C.byref(best), tab))
-        ovl = list(settings.overlap)
-        ovl[0] = best.overlap[0]
+        ovl = [best.overlap[0]] * len(settings.overlap)
         tz = best.tz if best.tz > 0 else 0
         tuned = dataclasses.replace(settings, tile=(best.tx, best.ty, tz), overlap=tuple(ovl),
                                     ratio=best.ratio if best.ratio > 0 else 2)

@@ -138,6 +138,7 @@ PROTOTYPES = {
     "nks_profile_filter": [C.c_char_p],
     "nks_profile_query": [C.c_char_p, _IP, _DP],
     "nks_profile_durations": [C.c_char_p, _DP, _I, _IP],
+    "nks_profile_units": [C.c_char_p, _DP],
     "nks_last_error": [],
     "nks_version": [],
 }

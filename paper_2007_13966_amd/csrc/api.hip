@@ -65,15 +65,19 @@ void Alloc::put(void *p) {
 struct ProfRec {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
 };
+// device cell counters per record (two each), kept across enable / disable
+static std::map<std::string, unsigned long long *> g_prof_units;
 static std::mutex g_prof_mu;
 static std::map<std::string, ProfRec> g_prof;
 static bool g_prof_on = false;
+static bool g_prof_direct = false;           // mode 2: captured chunks run as plain launches
 static std::set<std::string> g_prof_keep;   // record names kept (empty: all)
 static std::vector<hipEvent_t> g_event_pool;
 
 static bool prof_wanted(const std::string &key) { return g_prof_keep.empty() || g_prof_keep.count(key) != 0; }
 
 bool prof_on() { return g_prof_on; }
+bool prof_direct() { return g_prof_on && g_prof_direct; }
 
 void set_lds(const void *fn, size_t bytes) {
     static std::mutex mu;
@@ -128,7 +132,25 @@ bool prof_pair(const char *nm, int lvl, hipStream_t s, hipEvent_t *a, hipEvent_t
     return true;
 }
 
+unsigned long long *prof_units(const char *nm, int lvl) {
+    std::string key = lvl >= 0 ? fmt("%s_l%d", nm, lvl) : std::string(nm);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    unsigned long long *&u = g_prof_units[key];
+    if (!u) {
+        const size_t bytes = 2 * PROF_UNIT_SLOTS * sizeof(unsigned long long);
+        if (hipMalloc((void **)&u, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            u = nullptr;
+            return nullptr;
+        }
+        HIPC(hipMemset(u, 0, bytes));
+    }
+    return u;
+}
+
 static void prof_clear() {
+    for (auto &kv : g_prof_units)
+        if (kv.second) HIPC(hipMemset(kv.second, 0, 2 * PROF_UNIT_SLOTS * sizeof(unsigned long long)));
     for (auto &kv : g_prof)
         for (auto &p : kv.second.ev) {
             g_event_pool.push_back(p.first);
@@ -371,8 +393,10 @@ int nks_profile_enable(int enable) {
             prof_clear();
         }
         g_prof_on = enable != 0;
+        g_prof_direct = enable == 2;
     });
 }
+
 
 int nks_profile_filter(const char *names) {
     return guard([&] {
@@ -426,6 +450,27 @@ int nks_profile_durations(const char *name, double *ms, int cap, int *count) {
         for (int i = 0; i < cap && i < (int)d.size(); ++i) ms[i] = d[i];
     });
 }
+int nks_profile_units(const char *name, double *cells) {
+    return guard([&] {
+        if (!name || !cells) fail(NKS_EINVAL, "bad arguments");
+        cells[0] = cells[1] = 0.0;
+        unsigned long long *u = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            auto it = g_prof_units.find(name);
+            if (it != g_prof_units.end()) u = it->second;
+        }
+        if (!u) return;
+        HIPC(hipDeviceSynchronize());
+        std::vector<unsigned long long> h(2 * PROF_UNIT_SLOTS);
+        HIPC(hipMemcpy(h.data(), u, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        for (int k = 0; k < PROF_UNIT_SLOTS; ++k) {
+            cells[0] += (double)h[2 * k];
+            cells[1] += (double)h[2 * k + 1];
+        }
+    });
+}
+
 const char *nks_version(void) { return "libnks 0.1 (gfx950)"; }
 
 int nks_setup_grid(const nks_grid_desc *d, nks_grid **out) {
@@ -1342,7 +1387,7 @@ int nks_ras_autotune(nks_grid *gh, const double *p, const double *pn, const doub
                 nks_ras_desc d = *base;
                 d.tx = d.ty = tiles[it];
                 d.tz = g.dim == 3 ? tiles[it] : 0;
-                d.overlap[0] = overlaps[io];
+                for (int l = 0; l < 8; ++l) d.overlap[l] = overlaps[io];
                 d.ratio = ratios[ir];
                 nks_autotune_entry e{};
                 e.tile = tiles[it];

@@ -809,7 +809,7 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
             KCHECK();
         });
     };
-    const int kc = (o.graph_chunk > 0 && graphs_ok && s != nullptr) ? std::min(o.graph_chunk, m) : 0;
+    const int kc = (o.graph_chunk > 0 && graphs_ok && s != nullptr && !prof_direct()) ? std::min(o.graph_chunk, m) : 0;
     if (kc && kc != gchunk) invalidate_graphs();
     gchunk = kc;
     // Captured chunks: a lead chunk of 2*kc iterations, then chunks of kc

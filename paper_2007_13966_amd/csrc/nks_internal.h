@@ -208,6 +208,9 @@ void set_lds(const void *fn, size_t bytes);
 
 // Event timing of named launches (active only after nks_profile_enable(1)).
 bool prof_on();
+// nks_profile_enable(2): work otherwise replayed from captured graphs runs as
+// plain launches, so every launch is recorded
+bool prof_direct();
 // Events around a span of stream work (several kernels); includes any idle
 // time between them.
 struct ProfScope {
@@ -222,6 +225,25 @@ struct ProfScope {
 // An event pair to be bound to one kernel dispatch; false when profiling is
 // off or the stream is being captured.
 bool prof_pair(const char *name, int level, hipStream_t s, hipEvent_t *a, hipEvent_t *b);
+
+// Device counters of a record's profiled launches ([0] extended cells, [1]
+// owned cells of the subdomains a sweep did not find masked out); zeroed when
+// recording starts.  Valid for a launch whose prof_pair returned true.
+constexpr int PROF_UNIT_SLOTS = 256;   // counter pairs per record, summed when read
+unsigned long long *prof_units(const char *name, int level);
+
+// A subdomain sweep: as launch_timed, and while that launch is profiled its
+// arguments carry the record's cell counters (args.units), so the swept cells
+// of each profiled launch are counted on the device.
+template <typename Args>
+inline void launch_sweep(const char *name, int level, void (*kernel)(Args), dim3 grid, dim3 block, size_t sh,
+                         hipStream_t s, Args args) {
+    hipEvent_t a = nullptr, b = nullptr;
+    args.units = nullptr;
+    if (prof_pair(name, level, s, &a, &b)) args.units = prof_units(name, level);
+    else a = b = nullptr;
+    hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)sh, s, a, b, 0u, args);
+}
 
 // Launch one kernel; while profiling, the events ride on the dispatch packet
 // itself, so the recorded time is the kernel's execution alone.

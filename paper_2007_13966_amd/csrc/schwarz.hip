@@ -772,6 +772,7 @@ struct ApplyArgs {
     const double *r;
     double *z, *zext;
     const int *mask;
+    unsigned long long *units;   // profiled launches: swept extended / owned cells
     int variant, accumulate, cap;
     int lin7[7];          // 7-point kernel: tile offsets of the stencil entries
 };
@@ -787,6 +788,13 @@ __global__ void __launch_bounds__(256) k_ras_apply(ApplyArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const SubDev sd = a.sub[blockIdx.x];
     if (a.mask && !a.mask[sd.blk]) return;
+    if (a.units && threadIdx.x == 0) {
+        // spread over PROF_UNIT_SLOTS counter pairs, so the workgroups of a
+        // launch do not queue on one address
+        unsigned long long *u = a.units + 2 * (blockIdx.x % PROF_UNIT_SLOTS);
+        atomicAdd(u, (unsigned long long)sd.next);
+        atomicAdd(u + 1, (unsigned long long)((sd.lx1 - sd.lx0) * (sd.ly1 - sd.ly0) * (sd.lz1 - sd.lz0)));
+    }
     const Blk bk = a.blk[sd.blk];
     const int ncl = NC ? NC : a.diag, ncu = NC ? NC : a.K - a.diag - 1;
     const int ncmax = ncl > ncu ? ncl : ncu;
@@ -995,6 +1003,7 @@ struct RowsArgs {
     const double *r;
     double *z, *zext;
     const int *mask;
+    unsigned long long *units;   // profiled launches: swept extended / owned cells
     int variant, accumulate;
     int kmap[32];         // slot of the padded per-cell run -> stencil index (-1: absent or padding)
 };
@@ -1072,6 +1081,13 @@ __global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const SubDev sd = a.sub[blockIdx.x];
     if (a.mask && !a.mask[sd.blk]) return;
+    if (a.units && threadIdx.x == 0) {
+        // spread over PROF_UNIT_SLOTS counter pairs, so the workgroups of a
+        // launch do not queue on one address
+        unsigned long long *u = a.units + 2 * (blockIdx.x % PROF_UNIT_SLOTS);
+        atomicAdd(u, (unsigned long long)sd.next);
+        atomicAdd(u + 1, (unsigned long long)((sd.lx1 - sd.lx0) * (sd.ly1 - sd.ly0) * (sd.lz1 - sd.lz0)));
+    }
     const int n = sd.next, ex = sd.ex, ey = sd.ey;
     // LDS: rv[n + 1] (slot n takes the stores of masked steps), cf[n * CS],
     // id[n], each with PAD guard cells on both sides for the padded steps
@@ -1336,6 +1352,7 @@ struct Rows3Args {
     const double *r;
     double *z, *zext;
     const int *mask;
+    unsigned long long *units;   // profiled launches: swept extended / owned cells
     int *err;             // the level's error word: bit 2 set when a bounded wait gives up
     int variant, accumulate;
     int kmap[16];         // run slot -> stencil index: lower (z, y, x) then upper (x, y, z); -1 padding
@@ -1352,6 +1369,13 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
     __shared__ int prog[2][4];                       // steps done per slab: forward, backward
     const SubDev sd = a.sub[blockIdx.x];
     if (a.mask && !a.mask[sd.blk]) return;
+    if (a.units && threadIdx.x == 0) {
+        // spread over PROF_UNIT_SLOTS counter pairs, so the workgroups of a
+        // launch do not queue on one address
+        unsigned long long *u = a.units + 2 * (blockIdx.x % PROF_UNIT_SLOTS);
+        atomicAdd(u, (unsigned long long)sd.next);
+        atomicAdd(u + 1, (unsigned long long)((sd.lx1 - sd.lx0) * (sd.ly1 - sd.ly0) * (sd.lz1 - sd.lz0)));
+    }
     const int n = sd.next, ex = sd.ex, ey = sd.ey, ez = sd.ez;
     if (MULTI && threadIdx.x < 8) prog[threadIdx.x >> 2][threadIdx.x & 3] = 0;
     VT *rv = reinterpret_cast<VT *>(smem3);
@@ -1764,56 +1788,75 @@ __global__ void k_prolong_add(XferArgs a, const double *ec, double *zf) {
     zf[i] += s;
 }
 
-// Galerkin A_c = P^T A P: one thread per coarse cell, accumulators in LDS.
-__global__ void k_rap(XferArgs a, const double *Af, int Kf, const int8_t *offf, double *Ac, int Kc,
-                      const int *slot, int Rc) {
-    extern __shared__ double acc_s[];
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    double *acc = acc_s + (size_t)threadIdx.x * Kc;
-    if (I >= a.Nc) return;
+// Galerkin A_c = P^T A P, one wavefront per coarse cell I: the lanes share
+// the fine cells f of I's interpolation support (the column of P), each lane
+// adding P(f,I) A(f,g) P(g,J) into its own LDS row of Kc slots (slot of the
+// offset J - I); then lane k sums slot k over the wavefront's 64 rows in a
+// fixed order, so the product is deterministic.  The tables a lane walks per
+// term (P rows of g, the offset-to-slot map) are read through the per-block
+// LDS copy of the slot map and a handful of global loads per fine cell.
+template <int W>
+__global__ void __launch_bounds__(64 * W) k_rap(XferArgs a, const double *Af, int Kf, const int8_t *offf,
+                                                double *Ac, int Kc, const int *slot, int Rc) {
+    extern __shared__ double rap_s[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int S = 2 * Rc + 1, S3 = S * S * S;
+    int *slot_s = reinterpret_cast<int *>(rap_s + (size_t)64 * W * Kc);
+    for (int t = threadIdx.x; t < S3; t += 64 * W) slot_s[t] = slot[t];
+    double *acc = rap_s + (size_t)threadIdx.x * Kc;
     for (int k = 0; k < Kc; ++k) acc[k] = 0.0;
-    const int b = find_blk(a.cblk, a.B, I);
-    const Blk cb = a.cblk[b], fb = a.fblk[b];
-    const int l = I - cb.off;
-    const int X = l % cb.nx, Y = (l / cb.nx) % cb.ny, Z = l / (cb.nx * cb.ny);
-    const int cx = a.coff[0][b] + X, cy = a.coff[1][b] + Y, cz = a.coff[2][b] + Z;
-    const int S = 2 * Rc + 1;
-    for (int qz = 0; qz < a.ccnt[2][cz]; ++qz) {
-        const int fz = a.ci[2][cz * a.cs[2] + qz];
-        const double wz = a.cw[2][cz * a.cs[2] + qz];
-        for (int qy = 0; qy < a.ccnt[1][cy]; ++qy) {
-            const int fy = a.ci[1][cy * a.cs[1] + qy];
-            const double wy = a.cw[1][cy * a.cs[1] + qy];
-            for (int qx = 0; qx < a.ccnt[0][cx]; ++qx) {
-                const int fx = a.ci[0][cx * a.cs[0] + qx];
-                const double wf = a.cw[0][cx * a.cs[0] + qx] * wy * wz;
-                const int f = fb.off + fx + fb.nx * (fy + fb.ny * fz);
-                for (int k = 0; k < Kf; ++k) {
-                    const int gx = fx + offf[3 * k], gy = fy + offf[3 * k + 1], gz = fz + offf[3 * k + 2];
-                    if (gx < 0 || gx >= fb.nx || gy < 0 || gy >= fb.ny || gz < 0 || gz >= fb.nz) continue;
-                    const double av = Af[(size_t)k * a.Nf + f];
-                    if (av == 0.0) continue;
-                    const double wa = wf * av;
-                    const int rx = a.roff[0][b] + gx, ry = a.roff[1][b] + gy, rz = a.roff[2][b] + gz;
-                    for (int pz = 0; pz < a.rcnt[2][rz]; ++pz) {
-                        const int Jz = a.rj[2][rz * 4 + pz];
-                        const double vz = a.rw[2][rz * 4 + pz];
-                        for (int py = 0; py < a.rcnt[1][ry]; ++py) {
-                            const int Jy = a.rj[1][ry * 4 + py];
-                            const double vy = a.rw[1][ry * 4 + py];
-                            for (int px = 0; px < a.rcnt[0][rx]; ++px) {
-                                const int Jx = a.rj[0][rx * 4 + px];
-                                const double vx = a.rw[0][rx * 4 + px];
-                                const int sl = slot[(Jx - X + Rc) + S * ((Jy - Y + Rc) + S * (Jz - Z + Rc))];
-                                acc[sl] += wa * (vx * vy * vz);
-                            }
+    __syncthreads();
+    const int I = blockIdx.x * W + w;
+    int b = 0, X = 0, Y = 0, Z = 0;
+    if (I < a.Nc) {
+        b = find_blk(a.cblk, a.B, I);
+        const Blk cb = a.cblk[b], fb = a.fblk[b];
+        const int l = I - cb.off;
+        X = l % cb.nx;
+        Y = (l / cb.nx) % cb.ny;
+        Z = l / (cb.nx * cb.ny);
+        const int cx = a.coff[0][b] + X, cy = a.coff[1][b] + Y, cz = a.coff[2][b] + Z;
+        const int nqx = a.ccnt[0][cx], nqy = a.ccnt[1][cy], nqz = a.ccnt[2][cz];
+        const int tot = nqx * nqy * nqz;
+        for (int q = lane; q < tot; q += 64) {
+            const int qx = q % nqx, qy = (q / nqx) % nqy, qz = q / (nqx * nqy);
+            const int fx = a.ci[0][cx * a.cs[0] + qx], fy = a.ci[1][cy * a.cs[1] + qy],
+                      fz = a.ci[2][cz * a.cs[2] + qz];
+            const double wf = a.cw[0][cx * a.cs[0] + qx] * a.cw[1][cy * a.cs[1] + qy] * a.cw[2][cz * a.cs[2] + qz];
+            const int f = fb.off + fx + fb.nx * (fy + fb.ny * fz);
+            for (int k = 0; k < Kf; ++k) {
+                const int gx = fx + offf[3 * k], gy = fy + offf[3 * k + 1], gz = fz + offf[3 * k + 2];
+                if (gx < 0 || gx >= fb.nx || gy < 0 || gy >= fb.ny || gz < 0 || gz >= fb.nz) continue;
+                const double av = Af[(size_t)k * a.Nf + f];
+                if (av == 0.0) continue;
+                const double wa = wf * av;
+                const int rx = a.roff[0][b] + gx, ry = a.roff[1][b] + gy, rz = a.roff[2][b] + gz;
+                const int npx = a.rcnt[0][rx], npy = a.rcnt[1][ry], npz = a.rcnt[2][rz];
+                for (int pz = 0; pz < npz; ++pz) {
+                    const int Jz = a.rj[2][rz * 4 + pz];
+                    const double vz = wa * a.rw[2][rz * 4 + pz];
+                    for (int py = 0; py < npy; ++py) {
+                        const int Jy = a.rj[1][ry * 4 + py];
+                        const double vyz = vz * a.rw[1][ry * 4 + py];
+                        const int row = S * ((Jy - Y + Rc) + S * (Jz - Z + Rc)) + Rc - X;
+                        for (int px = 0; px < npx; ++px) {
+                            const int sl = slot_s[row + a.rj[0][rx * 4 + px]];
+                            acc[sl] += vyz * a.rw[0][rx * 4 + px];
                         }
                     }
                 }
             }
         }
     }
-    for (int k = 0; k < Kc; ++k) Ac[(size_t)k * a.Nc + I] = acc[k];
+    __syncthreads();
+    if (I < a.Nc) {
+        const double *rows = rap_s + (size_t)w * 64 * Kc;
+        for (int k = lane; k < Kc; k += 64) {
+            double sum = 0.0;
+            for (int r = 0; r < 64; ++r) sum += rows[(size_t)r * Kc + k];
+            Ac[(size_t)k * a.Nc + I] = sum;
+        }
+    }
 }
 
 __global__ void k_fill(int N, double v, double *x) {
@@ -1997,11 +2040,16 @@ void Ras::factor(bool ilu) {
             Level &F = *lev[l - 1];
             XferArgs a = xfer_args(F, V, nullptr);
             const int Kc = V.own.st.K;
-            const int bs = 64;
-            const size_t sh = (size_t)bs * Kc * sizeof(double);
-            set_lds((const void *)k_rap, sh);
-            launch_timed("rap", l, k_rap, dim3(nblk(V.spp->N, bs)), dim3(bs), sh, s, a, F.A->coef.p, F.A->st.K,
-                         F.A->st.doff.p, V.own.coef.p, Kc, F.rap_slot.p, F.rap_R);
+            const int S = 2 * F.rap_R + 1;
+            // as many coarse cells (wavefronts) per workgroup as LDS allows
+            auto lds_for = [&](int w) { return (size_t)64 * w * Kc * sizeof(double) + sizeof(int) * S * S * S; };
+            const int W = lds_for(4) <= (size_t)lds_bytes ? 4 : (lds_for(2) <= (size_t)lds_bytes ? 2 : 1);
+            if (lds_for(W) > (size_t)lds_bytes) fail(NKS_EINVAL, "coarse stencil of %d points exceeds the LDS", Kc);
+            void (*fr)(XferArgs, const double *, int, const int8_t *, double *, int, const int *, int) =
+                W == 4 ? k_rap<4> : (W == 2 ? k_rap<2> : k_rap<1>);
+            set_lds((const void *)fr, lds_for(W));
+            launch_timed("rap", l, fr, dim3(nblk(V.spp->N, W)), dim3(64 * W), lds_for(W), s, a, F.A->coef.p,
+                         F.A->st.K, F.A->st.doff.p, V.own.coef.p, Kc, F.rap_slot.p, F.rap_R);
             KCHECK();
         }
         if (!ilu) continue;
@@ -2159,7 +2207,7 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     const bool one = occ1 >= 2 * occ4 && V.nsub > M.n_cu * occ4;
     void (*fn)(RowsArgs) = one ? fn1 : fn4;
     set_lds((const void *)fn, sh);
-    launch_timed("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(one ? 64 : 256), sh, M.g->s, a);
+    launch_sweep("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(one ? 64 : 256), sh, M.g->s, a);
     KCHECK();
     if (M.d.variant != NKS_LEFT_RAS) {
         k_ras_gather<<<nblk(V.spp->N, 256), 256, 0, M.g->s>>>(V.spp->blk.p, V.spp->B, V.spp->N, V.part.p,
@@ -2210,7 +2258,7 @@ static void launch_rows3d(Ras &M, Level &V, const double *r, double *z, const in
     const size_t sh = rows3d_lds(M.d.precision, V.max_next);
     void (*fn)(Rows3Args) = V.rows3d_multi ? k_ras_rows3d<FT, VT, DT, true> : k_ras_rows3d<FT, VT, DT, false>;
     set_lds((const void *)fn, sh);
-    launch_timed("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(256), sh, M.g->s, a);
+    launch_sweep("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(256), sh, M.g->s, a);
     KCHECK();
     if (M.d.variant != NKS_LEFT_RAS) {
         k_ras_gather<<<nblk(V.spp->N, 256), 256, 0, M.g->s>>>(V.spp->blk.p, V.spp->B, V.spp->N, V.part.p,
@@ -2282,9 +2330,9 @@ static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, 
     const int bs = V.max_lvl <= 64 ? 64 : (V.max_lvl <= 128 ? 128 : 256);
     {
         if (seven)
-            launch_timed("ras_apply", level_index(M, V), k_ras_apply<FT, VT, DT, 3>, dim3(V.nsub), dim3(bs), sh, M.g->s, a);
+            launch_sweep("ras_apply", level_index(M, V), k_ras_apply<FT, VT, DT, 3>, dim3(V.nsub), dim3(bs), sh, M.g->s, a);
         else
-            launch_timed("ras_apply", level_index(M, V), k_ras_apply<FT, VT, DT, 0>, dim3(V.nsub), dim3(bs), sh, M.g->s, a);
+            launch_sweep("ras_apply", level_index(M, V), k_ras_apply<FT, VT, DT, 0>, dim3(V.nsub), dim3(bs), sh, M.g->s, a);
         KCHECK();
     }
     if (M.d.variant != NKS_LEFT_RAS) {

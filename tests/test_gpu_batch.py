@@ -43,7 +43,7 @@ def test_autotune_then_newton_parity(nks, orc):
     assert [(e["tile"], e["overlap"], e["ratio"]) for e in table] == \
         [(t, o, r) for t in (8, 12, 24) for o in (1, 2) for r in (2, 4)]
     best = min(ok, key=lambda e: e["setup_ms"] + e["solve_ms"])
-    assert tuned.tile[:2] == (best["tile"], best["tile"]) and tuned.overlap[0] == best["overlap"]
+    assert tuned.tile[:2] == (best["tile"], best["tile"]) and tuned.overlap == (best["overlap"],) * 2
     assert tuned.ratio == best["ratio"]
     p = p0.clone()
     st = g.newton_step(p, p0, p0, case.dt, 1, tuned)
