@@ -225,10 +225,26 @@ typedef struct {
                                     stencil) at the coarsened state (the mean of the children)
                                     of the last nks_jacobian; every size above one must be a
                                     multiple of r on every coarse level; not for the transpose */
+    int coarse_kernel;           /* how the coarsest level's GMRES runs (the same iteration
+                                    either way): NKS_COARSE_AUTO (0) the persistent form where
+                                    the level allows it and each reservoir's factors on it take
+                                    at most 256 KiB (one CU streams them every sweep), else
+                                    chunks; NKS_COARSE_CHUNKED one
+                                    launch per kernel step, replayed in captured chunks of
+                                    iterations with a host test of convergence after each;
+                                    NKS_COARSE_PERSISTENT one launch for the whole solve, a
+                                    workgroup per reservoir iterating until its own test
+                                    stops it (no host round trip), which needs a 2D coarsest
+                                    level swept by rows, the left-RAS variant and at most
+                                    4096 cells per reservoir on that level (NKS_EINVAL
+                                    otherwise) */
 } nks_ras_desc;
 
 #define NKS_COARSE_GALERKIN 0
 #define NKS_COARSE_REDISCRETIZED 1
+#define NKS_COARSE_AUTO 0
+#define NKS_COARSE_CHUNKED 1
+#define NKS_COARSE_PERSISTENT 2
 
 /* Creates (*inout == NULL) or refactors in place (*inout from an earlier
  * call on a matrix of the same grid and an identical descriptor).  Keeps a
@@ -242,12 +258,22 @@ typedef struct {
  * with NKS_EHIP instead of returning a correction built on stale values. */
 int nks_ras_setup(nks_matrix *J, const nks_ras_desc *d, nks_ras **inout);
 int nks_destroy_ras(nks_ras *M);
-/* z = M^{-1} r on the finest level (device).  Runs the coarse GMRES, so it
- * synchronises when levels > 1. */
+/* z = M^{-1} r on the finest level (device).  With levels > 1 it runs the
+ * coarse GMRES: asynchronous in the persistent form, synchronising in the
+ * chunked one (coarse_kernel). */
 int nks_ras_apply(nks_ras *M, const double *r, double *z);
 /* One-level Schwarz apply on `level` (0 = finest) with vectors of that
  * level's size (device).  Asynchronous. */
 int nks_ras_apply_level(nks_ras *M, int level, const double *r, double *z);
+/* x = the coarsest level's GMRES solve of A_c x = b (Remark 2: x0 = 0, the
+ * one-level preconditioner, stopped at coarse_rtol ||b|| or coarse_maxit
+ * iterations) with vectors of that level's size (device); levels > 1.
+ * Asynchronous in the persistent form. */
+int nks_ras_coarse_solve(nks_ras *M, const double *b, double *x);
+/* Per reservoir, the iterations and the last residual estimate of the
+ * latest coarse solve (host arrays of one entry per reservoir; either may be
+ * NULL).  Synchronises the grid's stream. */
+int nks_ras_coarse_stats(nks_ras *M, int *its, double *res);
 /* z = M^{-T} r (device): the preconditioner with the same boxes and levels
  * built on J^T, left- and right-RAS exchanged (AS stays AS).  ILU(0) of A^T
  * on a symmetric pattern is the transpose of ILU(0) of A, and the Galerkin
@@ -340,6 +366,10 @@ typedef struct {
     int *stop_reason;            /* optional HOST array [nres] (caller-owned, NULL: not wanted):
                                     why each reservoir stopped, NKS_STOP_* */
     double *rel_res;             /* optional HOST array [nres]: final ||F|| / ||F(X^0)|| */
+    int host_waits;              /* times the host waited on the device during the step */
+    int graph_chunk;             /* FGMRES iterations per captured graph in the step (0: none;
+                                    captured when the preconditioner runs without host
+                                    round trips: one level, or the persistent coarse solve) */
 } nks_newton_stats;
 
 #define NKS_STOP_NONE 0          /* still iterating when the call returned (limit or failure) */
@@ -422,7 +452,8 @@ int nks_ras_autotune(nks_grid *g, const double *p, const double *p_n, const doub
  * (the Arnoldi step after the preconditioner), "residual_jacobian".  Launches inside captured graphs are not recorded.
  * enable != 0 clears the records and starts recording, 0 stops; enable = 2
  * also runs the iterations otherwise replayed from captured graphs (the
- * coarse GMRES chunks) as plain launches, so every launch is recorded.  query
+ * chunked coarse GMRES, the captured FGMRES iterations) as plain launches,
+ * so every launch is recorded.  query
  * synchronises and returns the number of launches and their summed duration
  * (ms); unknown names give 0.  durations writes the first min(cap, count)
  * per-launch durations (ms, launch order) to host array ms and the record

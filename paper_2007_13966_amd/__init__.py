@@ -87,6 +87,7 @@ def ras_desc(s):
     d.fill = getattr(s, "fill", 0)
     d.ratio = getattr(s, "ratio", 2)
     d.coarse_op = {"galerkin": 0, "rediscretised": 1}[getattr(s, "coarse_op", "galerkin")]
+    d.coarse_kernel = L.COARSE_KERNELS[getattr(s, "coarse_kernel", "auto")]
     return d
 
 
@@ -340,7 +341,8 @@ class Grid:
                     lits=list(st.lits[:min(k, 64)]), lambdas=list(st.lambdas[:min(k, 64)]),
                     t_residual=st.t_residual, t_jacobian=st.t_jacobian, t_setup=st.t_setup,
                     t_gmres=st.t_gmres, t_linesearch=st.t_linesearch,
-                    stop_reason=[L.STOP_REASONS[int(w)] for w in why], rel_res=list(rel))
+                    stop_reason=[L.STOP_REASONS[int(w)] for w in why], rel_res=list(rel),
+                    host_waits=st.host_waits, graph_chunk=st.graph_chunk)
 
 
 class Matrix:
@@ -444,6 +446,23 @@ class Ras:
         with _Ordered(self.grid):
             check(lib().nks_ras_apply_level(self.h, int(level), _vp(r), _vp(z)))
         return z
+
+    def coarse_solve(self, b, out=None):
+        """The coarsest level's GMRES solve (vectors of that level's size)."""
+        x = self._vec(self.desc.levels - 1) if out is None else out
+        with _Ordered(self.grid):
+            check(lib().nks_ras_coarse_solve(self.h, _vp(b), _vp(x)))
+        return x
+
+    def coarse_stats(self):
+        """Per reservoir: iterations and last residual estimate of the latest
+        coarse solve."""
+        B = len(self.grid.offsets) - 1
+        its = (C.c_int * B)()
+        res = (C.c_double * B)()
+        with _Ordered(self.grid):
+            check(lib().nks_ras_coarse_stats(self.h, its, res))
+        return list(its), list(res)
 
     def restrict(self, level, rf):
         rc = self._vec(level + 1)

@@ -41,6 +41,7 @@ class nks_grid_desc(C.Structure):
 
 
 ACCUM_FORMS = {"conservative": 0, "chain_rule": 1}
+COARSE_KERNELS = {"auto": 0, "chunked": 1, "persistent": 2}
 
 
 class nks_ras_desc(C.Structure):
@@ -50,7 +51,7 @@ class nks_ras_desc(C.Structure):
                 ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int),
                 ("coarse_restart", C.c_int), ("precision", C.c_int),
                 ("tx", C.c_int), ("ty", C.c_int), ("tz", C.c_int), ("fill", C.c_int),
-                ("ratio", C.c_int), ("coarse_op", C.c_int)]
+                ("ratio", C.c_int), ("coarse_op", C.c_int), ("coarse_kernel", C.c_int)]
 
 
 class nks_gmres_desc(C.Structure):
@@ -78,7 +79,8 @@ class nks_newton_stats(C.Structure):
                 ("lits", C.c_int * 64), ("lambdas", C.c_double * 64),
                 ("t_residual", C.c_double), ("t_jacobian", C.c_double), ("t_setup", C.c_double),
                 ("t_gmres", C.c_double), ("t_linesearch", C.c_double),
-                ("stop_reason", C.POINTER(C.c_int)), ("rel_res", C.POINTER(C.c_double))]
+                ("stop_reason", C.POINTER(C.c_int)), ("rel_res", C.POINTER(C.c_double)),
+                ("host_waits", C.c_int), ("graph_chunk", C.c_int)]
 
 
 STOP_REASONS = {0: "none", 1: "tolerance", 2: "floor", 3: "step"}
@@ -118,6 +120,8 @@ PROTOTYPES = {
     "nks_destroy_ras": [_P],
     "nks_ras_apply": [_P, _P, _P],
     "nks_ras_apply_level": [_P, _I, _P, _P],
+    "nks_ras_coarse_solve": [_P, _P, _P],
+    "nks_ras_coarse_stats": [_P, _IP, _DP],
     "nks_ras_apply_transpose": [_P, _P, _P],
     "nks_ras_level_info": [_P, _I, _IP],
     "nks_ras_level_export": [_P, _I, _IP, _IP, _DP],

@@ -1,5 +1,6 @@
 // C ABI of libnks: argument checks, handle lifetime, error translation, and
 // the host-side control of the inexact Newton step (Section 3).
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <map>
@@ -78,6 +79,10 @@ static bool prof_wanted(const std::string &key) { return g_prof_keep.empty() || 
 
 bool prof_on() { return g_prof_on; }
 bool prof_direct() { return g_prof_on && g_prof_direct; }
+
+static std::atomic<long> g_host_waits{0};
+void count_host_wait() { g_host_waits.fetch_add(1, std::memory_order_relaxed); }
+long host_waits() { return g_host_waits.load(std::memory_order_relaxed); }
 
 void set_lds(const void *fn, size_t bytes) {
     static std::mutex mu;
@@ -296,6 +301,8 @@ struct TransposedRas {
             dt.nu = dd.mu;
             dt.cycle = dd.cycle == NKS_LEFT_KASKADE ? NKS_RIGHT_KASKADE
                                                     : (dd.cycle == NKS_RIGHT_KASKADE ? NKS_LEFT_KASKADE : dd.cycle);
+            // the exchanged variant may rule out the persistent coarse solve
+            if (dt.coarse_kernel == NKS_COARSE_PERSISTENT) dt.coarse_kernel = NKS_COARSE_AUTO;
             MT.reset(new Ras());
             MT->build(&JT, dt);
             d = dd;
@@ -816,7 +823,8 @@ static void check_ras_desc(const nks_ras_desc *d) {
         d->cycle > 4 || d->mu < 0 || d->nu < 0 || d->precision < 0 || d->precision > 2 ||
         d->coarse_restart < 1 || d->coarse_maxit < 1 || d->tx < 0 || d->ty < 0 || d->tz < 0 || d->fill < 0 ||
         d->fill > 4 || d->ratio < 0 || d->ratio == 1 || d->ratio > 16 ||
-        (d->coarse_op != NKS_COARSE_GALERKIN && d->coarse_op != NKS_COARSE_REDISCRETIZED))
+        (d->coarse_op != NKS_COARSE_GALERKIN && d->coarse_op != NKS_COARSE_REDISCRETIZED) ||
+        d->coarse_kernel < NKS_COARSE_AUTO || d->coarse_kernel > NKS_COARSE_PERSISTENT)
         fail(NKS_EINVAL, "bad preconditioner option");
 }
 
@@ -873,6 +881,34 @@ int nks_ras_apply_level(nks_ras *M, int level, const double *r, double *z) {
     return guard([&] {
         if (!M || !r || !z || level < 0 || level >= M->r.L) fail(NKS_EINVAL, "bad arguments");
         M->r.apply_level(level, r, z, nullptr, false);
+    });
+}
+
+int nks_ras_coarse_solve(nks_ras *M, const double *b, double *x) {
+    return guard([&] {
+        if (!M || !b || !x || M->r.L < 2) fail(NKS_EINVAL, "bad arguments");
+        M->r.coarse_solve(b, x, nullptr);
+    });
+}
+
+int nks_ras_coarse_stats(nks_ras *M, int *its, double *res) {
+    return guard([&] {
+        if (!M || M->r.L < 2) fail(NKS_EINVAL, "bad arguments");
+        Ras &R = M->r;
+        const int B = R.lev[R.L - 1]->spp->B;
+        std::vector<int> hi(B, 0), conv;
+        std::vector<double> hr(B, 0.0);
+        if (R.cp.on) {
+            HIPC(hipMemcpyAsync(hi.data(), R.cp.its.p, sizeof(int) * B, hipMemcpyDeviceToHost, R.g->s));
+            HIPC(hipMemcpyAsync(hr.data(), R.cp.res.p, sizeof(double) * B, hipMemcpyDeviceToHost, R.g->s));
+            HIPC(hipStreamSynchronize(R.g->s));
+        } else {
+            R.coarse.stats(hi, hr, conv, R.g->s);
+        }
+        for (int b = 0; b < B; ++b) {
+            if (its) its[b] = hi[b];
+            if (res) res[b] = hr[b];
+        }
     });
 }
 
@@ -1018,6 +1054,8 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             W.J->op.coef.alloc(al, (size_t)W.J->op.st.K * N);
         }
         if (!W.M || !same_desc(W.rd, *rd)) {
+            // captured FGMRES chunks hold the old preconditioner's buffers
+            W.gm.invalidate_graphs();
             W.M.reset(new Ras());
             W.M->build(W.J.get(), *rd);
             W.rd = *rd;
@@ -1030,6 +1068,7 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             W.ysp_host = W.Js.p;
         }
         nks_newton_stats S{};
+        const long waits0 = host_waits();
         double t0 = now();
         // residual and norms at the initial guess
         HIPC(hipMemsetAsync(g.flags.p, 0, sizeof(int) * B, s));
@@ -1043,6 +1082,7 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             HIPC(hipMemcpyAsync(W.h_norm, W.red2.p, 8 * B, hipMemcpyDeviceToHost, s));
             HIPC(hipMemcpyAsync(W.h_flags, g.flags.p, 4 * B, hipMemcpyDeviceToHost, s));
             HIPC(hipStreamSynchronize(s));
+            count_host_wait();
             for (int b = 0; b < B; ++b) {
                 out[b] = std::sqrt(W.h_norm[b]);
                 flags[b] = W.h_flags[b];
@@ -1118,7 +1158,11 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             o.maxit = nd->maxit;
             o.flexible = flex;
             o.check_every = 1;
+            // a preconditioner without host round trips is captured with the
+            // Arnoldi step, two iterations per graph
+            o.graph_chunk = W.M->capturable() ? 2 : 0;
             W.gm.solve(A, P, W.b.p, W.s.p, true, o, W.mask.p, s, &W.J->op);
+            S.graph_chunk = W.gm.gchunk;
             std::vector<int> its, conv;
             std::vector<double> res;
             W.gm.stats(its, res, conv, s);
@@ -1243,6 +1287,8 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
         for (int b = 0; b < B; ++b) S.fnorm = std::max(S.fnorm, hn[b]);
         S.status = status;
         HIPC(hipStreamSynchronize(s));
+        count_host_wait();
+        S.host_waits = (int)(host_waits() - waits0);
         if (st) {
             S.stop_reason = st->stop_reason;
             S.rel_res = st->rel_res;

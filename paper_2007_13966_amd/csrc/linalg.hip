@@ -734,6 +734,7 @@ GmDev Gmres::dev(double rtol, double atol, int maxit) {
 bool Gmres::any_active(hipStream_t s) {
     HIPC(hipMemcpyAsync(hint, ints.p, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
+    count_host_wait();
     for (int b = 0; b < nb; ++b) if (hint[b]) return true;
     return false;
 }
@@ -749,6 +750,7 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
     // restart (or at maxit)
     auto any_flag = [&](int slot) -> bool {
         HIPC(hipEventSynchronize(ev[slot]));
+        count_host_wait();
         for (int k = 0; k < nb; ++k)
             if (hflag[slot * nb + k] == 1) return true;
         return false;
@@ -904,6 +906,7 @@ void Gmres::stats(std::vector<int> &its, std::vector<double> &res, std::vector<i
     HIPC(hipMemcpyAsync(hi, ints.p, sizeof(int) * 5 * B, hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(hd, scal.p, sizeof(double) * 3 * B, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
+    count_host_wait();
     its.assign(hi + 3 * B, hi + 4 * B);
     conv.assign(hi + B, hi + 2 * B);
     res.assign(hd + 2 * B, hd + 3 * B);

@@ -229,6 +229,10 @@ bool prof_pair(const char *name, int level, hipStream_t s, hipEvent_t *a, hipEve
 // Device counters of a record's profiled launches ([0] extended cells, [1]
 // owned cells of the subdomains a sweep did not find masked out); zeroed when
 // recording starts.  Valid for a launch whose prof_pair returned true.
+// host waits on the device (synchronisations and event waits on the solver
+// paths), counted for the step statistics
+void count_host_wait();
+long host_waits();
 constexpr int PROF_UNIT_SLOTS = 256;   // counter pairs per record, summed when read
 unsigned long long *prof_units(const char *name, int level);
 

@@ -107,6 +107,23 @@ struct TileDims {
     int PX, PY, PZ, R, Rz;       // padded LDS tile and stencil reach
 };
 
+// The coarsest level's GMRES as one persistent launch (a workgroup per
+// reservoir): lane groups of packed boxes, index maps between the cells and
+// the boxes' extended cells, per-cell factor runs, the Krylov basis.
+struct CoarsePersist {
+    bool on = false;
+    int ncap = 0;                // cells of the largest reservoir on the level
+    int max_ne = 0;              // extended cells of the largest reservoir's boxes
+    size_t lds = 0;
+    DBuf<int> efirst, gfirst, gsteps, ext2loc, own2ext, kmap;
+    DBuf<int2> glane;
+    DBuf<double> r64;            // per-cell factor runs, in the preconditioner's precision
+    DBuf<float> r32;
+    DBuf<uint16_t> r16;
+    DBuf<double> V, res;
+    DBuf<int> its;
+};
+
 struct Ras {
     Grid *g = nullptr;
     Matrix *J = nullptr;
@@ -129,6 +146,12 @@ struct Ras {
     void apply_level(int l, const double *r, double *z, const int *mask, bool accumulate);
     void vcycle(int l, const double *b, double *x, const int *mask);
     void coarse_solve(const double *b, double *x, const int *mask);
+    CoarsePersist cp;
+    void setup_persistent();                           // decides cp.on (after build)
+    void pack_runs();                                  // per-cell runs of the coarsest factors
+    void coarse_persistent(const double *b, double *x, const int *mask);
+    // no host round trip inside apply: one level, or the persistent coarse solve
+    bool capturable() const { return L == 1 || cp.on; }
     void restrict_to(int l, const double *rf, double *rc, const int *mask);
     void prolong_add(int l, const double *ec, double *zf, const int *mask);
     void check_pivots();

@@ -1333,6 +1333,489 @@ __global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- kernel: persistent coarse solve
+// The coarsest level's GMRES (right-preconditioned by the level's one-level
+// left-RAS, restarted every m iterations, one Gram-Schmidt pass, stopped at
+// rtol ||b|| or maxit iterations; Remark 2) for every reservoir at once, one
+// workgroup per reservoir, with the whole iteration on the device: the
+// convergence tests are workgroup-uniform branches, so no host round trip
+// and no launch separates two iterations.  The Krylov basis lives in global
+// memory (cached); z = M^{-1} v, w = A z and the boxes' extended values in
+// LDS.
+
+// One wavefront sweeps a group of boxes packed into its lanes: lane l holds
+// row y of one box (the rows of a box on consecutive lanes).  Step t of the
+// forward sweep handles x = t - LB*y in every row, the schedule of the
+// one-box row sweep; a row's lower neighbours come from its own earlier
+// steps and, through the wavefront shifts, from the two rows below.  A lane
+// zeroes what it passes on from its box's last row (forward; its first row
+// backward), so boxes side by side in one wavefront never exchange values;
+// the masks act before each shift, so every shift runs with all lanes of the
+// wavefront enabled (a shift that reads a disabled lane gets zero).  The
+// group runs for its longest box.
+// Factors are read from per-cell runs in global memory (lower run, then
+// upper run), RB steps ahead of the arithmetic; steps outside a row's range
+// read a cell clamped into the box and are masked.  Lanes without a row
+// (y < 0) compute nothing visible.
+template <typename FT, typename VT, typename DT, int BOX, int RB>
+__device__ __forceinline__ void packed_sweep(const SubDev &sd, int y, int T, VT *rb, VT *spare, const FT *Fb,
+                                             const DT *Ib) {
+    using S = RowStencil<BOX>;
+    constexpr int NS = S::NS, NL = S::NL, NU = NS - NL, LB = S::LB;
+    constexpr int PER = (int)(16 / sizeof(FT));
+    constexpr int NLP = (NL + PER - 1) / PER * PER, NUP = (NU + PER - 1) / PER * PER;
+    constexpr int RUN = NLP + NUP;
+    constexpr int RU = rows_unroll(BOX), NB = RU / RB;
+    static_assert(NB % 2 == 0 && NB * RB == RU, "an even number of prefetch blocks per ring cycle");
+    const bool on = y >= 0;
+    const int ex = sd.ex, ey = sd.ey, n = sd.next;
+    const int ye = on ? y : 0;
+    const int Ts = (ex - 1) + LB * (ey - 1) + 1;
+    const int cb = ye * (ex - LB);
+    {
+        const int tlo = on ? LB * ye : (1 << 28);
+        const bool fw = on && ye + 1 < ey;   // the next lane holds the next row of this box
+        VT r0[RU], r1[RU], r2[RU];
+#pragma unroll
+        for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
+        VT coA[RB][NLP], rinA[RB], coB[RB][NLP], rinB[RB];
+        int ccA[RB], ccB[RB];
+        bool aaA[RB], aaB[RB];
+        auto load = [&](int tb, VT(&co)[RB][NLP], VT(&rin)[RB], int(&cc)[RB], bool(&aa)[RB]) {
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int c = min(max(cb + tb + u, 0), n - 1);
+                aa[u] = (unsigned)(tb + u - tlo) < (unsigned)ex;
+                cc[u] = c;
+                load_run<FT, VT, NLP>(Fb + (size_t)c * RUN, co[u]);
+                rin[u] = rb[c];
+            }
+        };
+        auto step = [&](int b0, VT(&co)[RB][NLP], VT(&rin)[RB], int(&cc)[RB], bool(&aa)[RB]) {
+            VT outv[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int uu = b0 + u;
+                VT v = rin[u];
+#pragma unroll
+                for (int pass = 0; pass < 3; ++pass) {
+#pragma unroll
+                    for (int q = 0; q < NL; ++q) {
+                        const int h = -(S::DX[q] + LB * S::DY[q]) - 1;
+                        if (pass != (h != 0 ? 0 : (S::DY[q] == 0 ? 1 : 2))) continue;
+                        const int slot = (uu - 1 - h + 2 * RU) % RU;
+                        const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == -1 ? r1[slot] : r2[slot]);
+                        v -= co[u][q] * val;
+                    }
+                }
+                const VT out = aa[u] ? v : (VT)0;
+                outv[u] = out;
+                r0[uu] = out;
+                const VT s1 = lane_shr(fw ? out : (VT)0);
+                r1[uu] = s1;
+                r2[uu] = lane_shr(fw ? s1 : (VT)0);
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u) *(aa[u] ? rb + cc[u] : spare) = outv[u];
+        };
+        load(0, coA, rinA, ccA, aaA);
+        for (int t0 = 0; t0 < T; t0 += RU) {
+#pragma unroll
+            for (int q = 0; q < NB; q += 2) {
+                load(t0 + (q + 1) * RB, coB, rinB, ccB, aaB);
+                __builtin_amdgcn_sched_barrier(0);
+                step(q * RB, coA, rinA, ccA, aaA);
+                load(t0 + (q + 2) * RB, coA, rinA, ccA, aaA);
+                __builtin_amdgcn_sched_barrier(0);
+                step((q + 1) * RB, coB, rinB, ccB, aaB);
+            }
+        }
+    }
+    {
+        // backward: x = Ts - 1 - t - LB*y, upper neighbours from the rows above
+        const int cbb = cb + Ts - 1;
+        const int tlob = on ? Ts - LB * ye - ex : (1 << 28);
+        const bool bw = on && ye >= 1;   // the previous lane holds the previous row of this box
+        VT r0[RU], r1[RU], r2[RU];
+#pragma unroll
+        for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
+        VT coA[RB][NUP], rinA[RB], dgA[RB], coB[RB][NUP], rinB[RB], dgB[RB];
+        int ccA[RB], ccB[RB];
+        bool aaA[RB], aaB[RB];
+        auto load = [&](int tb, VT(&co)[RB][NUP], VT(&rin)[RB], VT(&dg)[RB], int(&cc)[RB], bool(&aa)[RB]) {
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int c = min(max(cbb - tb - u, 0), n - 1);
+                aa[u] = (unsigned)(tb + u - tlob) < (unsigned)ex;
+                cc[u] = c;
+                load_run<FT, VT, NUP>(Fb + (size_t)c * RUN + NLP, co[u]);
+                rin[u] = rb[c];
+                dg[u] = (VT)Ib[c];
+            }
+        };
+        auto step = [&](int b0, VT(&co)[RB][NUP], VT(&rin)[RB], VT(&dg)[RB], int(&cc)[RB], bool(&aa)[RB]) {
+            VT outv[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int uu = b0 + u;
+                VT v = rin[u];
+#pragma unroll
+                for (int pass = 0; pass < 3; ++pass) {
+#pragma unroll
+                    for (int q = NL; q < NS; ++q) {
+                        const int h = S::DX[q] + LB * S::DY[q] - 1;
+                        if (pass != (h != 0 ? 0 : (S::DY[q] == 0 ? 1 : 2))) continue;
+                        const int slot = (uu - 1 - h + 2 * RU) % RU;
+                        const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == 1 ? r1[slot] : r2[slot]);
+                        v -= co[u][q - NL] * val;
+                    }
+                }
+                const VT out = aa[u] ? v * dg[u] : (VT)0;
+                outv[u] = out;
+                r0[uu] = out;
+                const VT s1 = lane_shl(bw ? out : (VT)0);
+                r1[uu] = s1;
+                r2[uu] = lane_shl(bw ? s1 : (VT)0);
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u) *(aa[u] ? rb + cc[u] : spare) = outv[u];
+        };
+        load(0, coA, rinA, dgA, ccA, aaA);
+        for (int t0 = 0; t0 < T; t0 += RU) {
+#pragma unroll
+            for (int q = 0; q < NB; q += 2) {
+                load(t0 + (q + 1) * RB, coB, rinB, dgB, ccB, aaB);
+                __builtin_amdgcn_sched_barrier(0);
+                step(q * RB, coA, rinA, dgA, ccA, aaA);
+                load(t0 + (q + 2) * RB, coA, rinA, dgA, ccA, aaA);
+                __builtin_amdgcn_sched_barrier(0);
+                step((q + 1) * RB, coB, rinB, dgB, ccB, aaB);
+            }
+        }
+    }
+}
+
+constexpr int COARSE_CELLS = 4096;   // cells of a reservoir on the coarsest level, at most
+constexpr size_t COARSE_AUTO_RUN_BYTES = 256 * 1024;   // factor runs of a reservoir, automatic choice
+
+struct CoarseArgs {
+    const Blk *blk;          // the level's reservoirs (2D)
+    const SubDev *sub;       // the level's boxes
+    const int *efirst;       // per reservoir: first extended cell (B + 1 entries)
+    const int *gfirst;       // per reservoir: first lane group (B + 1 entries)
+    const int2 *glane;       // per group: 64 lanes of {box, row} (row -1: idle)
+    const int *gsteps;       // per group: the steps of its longest box
+    const int *ext2loc;      // per extended cell: the reservoir-local cell it copies
+    const int *own2ext;      // per cell: the extended cell of the box that owns it
+    const void *runs;        // per extended cell: the padded lower and upper factor runs (FT)
+    const void *invd;        // per extended cell: 1/u_ii (DT)
+    const double *coef;      // the level's operator, K x N
+    int K, N;
+    int offp[25];            // the operator's (dx, dy) in the low two bytes
+    const double *b;
+    double *x;
+    double *V;               // basis: reservoir b's m + 1 columns of n_b at V + (m + 1) off_b
+    const int *mask;
+    int *its;                // per reservoir: iterations taken
+    double *res;             // per reservoir: the last residual estimate
+    int m, maxit;
+    double rtol, atol;
+    int ncap;                // cells of the largest reservoir (LDS sizing)
+};
+
+// Workgroup sums of eight per-thread columns in a fixed order: within a
+// wavefront by recursive halving over the lane bits (after the exchange
+// across bit k a lane keeps the half of its columns that bit selects, so
+// lane l ends with column (l >> 3) & 7 summed over the wavefront), then the
+// wavefront totals in wavefront order into out[0..7].  red holds eight
+// doubles per wavefront.  Every thread of the workgroup calls it.
+template <int NT>
+__device__ __forceinline__ void workgroup_sum8(double (&a)[8], double *red, double *out) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool hi = lane & 32;
+        const double keep = hi ? a[k + 4] : a[k], send = hi ? a[k] : a[k + 4];
+        a[k] = keep + __shfl_xor(send, 32);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const bool hi = lane & 16;
+        const double keep = hi ? a[k + 2] : a[k], send = hi ? a[k] : a[k + 2];
+        a[k] = keep + __shfl_xor(send, 16);
+    }
+    {
+        const bool hi = lane & 8;
+        const double keep = hi ? a[1] : a[0], send = hi ? a[0] : a[1];
+        a[0] = keep + __shfl_xor(send, 8);
+    }
+    a[0] += __shfl_xor(a[0], 4);
+    a[0] += __shfl_xor(a[0], 2);
+    a[0] += __shfl_xor(a[0], 1);
+    if ((lane & 7) == 0) red[wid * 8 + (lane >> 3)] = a[0];
+    __syncthreads();
+    if ((int)threadIdx.x < 8) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w * 8 + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// stencil points of the coarse operator per row template (5-point cross,
+// 5x5 box, 21-point)
+template <int BOX> constexpr int coarse_kmax() { return BOX == 0 ? 5 : (BOX == 1 ? 25 : 21); }
+
+template <typename FT, typename VT, typename DT, int BOX, int NT>
+__global__ void __launch_bounds__(NT) k_coarse_gmres(CoarseArgs a) {
+    constexpr int NW = NT / 64;
+    constexpr int RB = BOX == 0 ? 4 : 2;
+    constexpr int CPT = COARSE_CELLS / NT;   // cells per thread at most
+    constexpr int KMAX = coarse_kmax<BOX>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int bi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const Blk k = a.blk[bi];
+    const int n = k.nx * k.ny, nx = k.nx;
+    double *xg = a.x + k.off;
+    const double *bg = a.b + k.off;
+    if (a.mask && !a.mask[bi]) {
+        for (int i = tid; i < n; i += NT) xg[i] = 0.0;
+        if (tid == 0) {
+            a.its[bi] = 0;
+            a.res[bi] = 0.0;
+        }
+        return;
+    }
+    const int m = a.m;
+    // LDS: z and w (ncap doubles each), column totals, the rotated
+    // Hessenberg columns (m x m), rotations, g, y, wavefront partials,
+    // flags, extended values
+    double *zl = reinterpret_cast<double *>(smem);
+    double *wl = zl + a.ncap;
+    double *hc = wl + a.ncap;
+    double *H = hc + 40;
+    double *cs = H + m * m, *sn = cs + m, *g = sn + m, *yv = g + m + 1;
+    double *red = yv + m;
+    int *flag = reinterpret_cast<int *>(red + 8 * NW);
+    VT *rv = reinterpret_cast<VT *>(flag + 4);
+    const int e0 = a.efirst[bi], ne = a.efirst[bi + 1] - e0;
+    VT *spare = rv + ne;
+    const FT *runs = reinterpret_cast<const FT *>(a.runs);
+    const DT *ID = reinterpret_cast<const DT *>(a.invd);
+    double *Vb = a.V + (size_t)(m + 1) * k.off;
+    const int K = a.K;
+    const double *coef = a.coef + k.off;
+    // dst_i = (A src)_i (minus from b_i when b is given) for the cells of
+    // this thread, every coefficient load of a cell issued together; a
+    // neighbour outside the reservoir has a zero coefficient, so its index
+    // is only clamped
+    auto spmv = [&](const double *src, double *dst, const double *bb) {
+#pragma unroll 1
+        for (int u = 0; u < CPT; ++u) {
+            int i = tid + u * NT;
+            if (i < n) {
+                // the empty asm keeps the address arithmetic here (hoisted out
+                // of the solve it would hold a register per point); rows past
+                // K load row K - 1 and are dropped by a select, so every load
+                // of the cell is issued together
+                asm volatile("" : "+v"(i));
+                double cv[KMAX];
+#pragma unroll
+                for (int q = 0; q < KMAX; ++q) cv[q] = coef[(unsigned)(min(q, K - 1) * a.N + i)];
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < KMAX; ++q) {
+                    const int o = a.offp[q];
+                    const int lq = (int)(int8_t)(o & 0xff) + nx * (int)(int8_t)((o >> 8) & 0xff);
+                    const double t = cv[q] * src[(unsigned)min(max(i + lq, 0), n - 1)];
+                    s += q < K ? t : 0.0;
+                }
+                dst[i] = bb ? bb[i] - s : s;
+            }
+        }
+    };
+    // zl = M^{-1} src: restricted input on every box, sweeps, owned cells
+    auto precondition = [&](const double *src) {
+        // four cells per thread per pass: the index loads, then the value loads
+        for (int eb = 0; eb < ne; eb += 4 * NT) {
+            int ix[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ix[u] = a.ext2loc[e0 + min(eb + tid + u * NT, ne - 1)];
+            double xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = src[ix[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (eb + tid + u * NT < ne) rv[eb + tid + u * NT] = (VT)xv[u];
+        }
+        __syncthreads();
+        for (int q = a.gfirst[bi] + wid; q < a.gfirst[bi + 1]; q += NW) {
+            const int2 ln = a.glane[(size_t)q * 64 + lane];
+            const SubDev sd = a.sub[ln.x];
+            packed_sweep<FT, VT, DT, BOX, RB>(sd, ln.y, a.gsteps[q], rv + (sd.fac_off - e0), spare,
+                                              runs + (size_t)sd.fac_off * row_run<BOX, FT>(), ID + sd.fac_off);
+        }
+        __syncthreads();
+        int ox[CPT];
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) ox[u] = a.own2ext[k.off + min(tid + u * NT, n - 1)];
+#pragma unroll
+        for (int u = 0; u < CPT; ++u)
+            if (tid + u * NT < n) zl[tid + u * NT] = (double)rv[ox[u] - e0];
+        __syncthreads();
+    };
+    // hc[c] = wl . V_c for c < nv, and hc[nv] = wl . wl: eight columns at a
+    // time, every load of a thread's cells issued together, fixed-order sums
+    auto dots = [&](int nv) {
+        for (int c0 = 0; c0 <= nv; c0 += 8) {
+            double acc[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+#pragma unroll 1
+            for (int u = 0; u < CPT; ++u) {
+                int i = tid + u * NT;
+                if (i < n) {
+                    asm volatile("" : "+v"(i));
+                    const double w = wl[i];
+                    // columns past the basis load column 0 (allocated, possibly
+                    // never written) and are dropped by a select
+                    double v[8];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) v[c] = Vb[(unsigned)((c0 + c < nv ? c0 + c : 0) * n + i)];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const int cc = c0 + c;
+                        acc[c] += cc < nv ? w * v[c] : (cc == nv ? w * w : 0.0);
+                    }
+                }
+            }
+            workgroup_sum8<NT>(acc, red, hc + c0);
+        }
+    };
+    // dst_i = scale (base_i - sum_{c < nc} coefs[c] V_c[i]), or
+    // scale sum_{c < nc} coefs[c] V_c[i] without a base
+    auto combine = [&](const double *base, const double *coefs, int nc, double scale, double *dst) {
+#pragma unroll 1
+        for (int u = 0; u < CPT; ++u) {
+            int i = tid + u * NT;
+            if (i < n) {
+                asm volatile("" : "+v"(i));
+                double t = 0.0;
+                for (int c0 = 0; c0 < nc; c0 += 8) {
+                    double v[8];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) v[c] = Vb[(unsigned)((c0 + c < nc ? c0 + c : 0) * n + i)];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) t += c0 + c < nc ? coefs[c0 + c] * v[c] : 0.0;
+                }
+                dst[i] = (base ? base[i] - t : t) * scale;
+            }
+        }
+    };
+    // x = 0, r = b
+    for (int i = tid; i < n; i += NT) {
+        xg[i] = 0.0;
+        wl[i] = bg[i];
+    }
+    __syncthreads();
+    dots(0);
+    double beta = sqrt(hc[0]);
+    const double tol = fmax(a.rtol * beta, a.atol);
+    int its = 0;
+    double res = beta;
+    for (;;) {
+        if (beta <= tol || its >= a.maxit) break;
+        const double ib = 1.0 / beta;
+        for (int i = tid; i < n; i += NT) Vb[i] = wl[i] * ib;
+        if (tid == 0) {
+            g[0] = beta;
+            for (int j = 1; j <= m; ++j) g[j] = 0.0;
+        }
+        __syncthreads();
+        int kdim = 0, conv = 0;
+        for (int j = 0; j < m; ++j) {
+            precondition(Vb + (size_t)j * n);
+            // w = A z; h = V[0..j]^T w and w.w (one pass)
+            spmv(zl, wl, nullptr);
+            __syncthreads();
+            dots(j + 1);
+            double h2 = 0.0;
+            for (int c = 0; c <= j; ++c) h2 += hc[c] * hc[c];
+            const double hn = sqrt(fmax(hc[j + 1] - h2, 0.0));
+            if (hn > 0.0) combine(wl, hc, j + 1, 1.0 / hn, Vb + (size_t)(j + 1) * n);
+            if (tid == 0) {
+                // column j: h, the earlier rotations, then the new one
+                double *col = H + (size_t)j * m;
+                for (int c = 0; c <= j; ++c) col[c] = hc[c];
+                for (int c = 0; c < j; ++c) {
+                    const double a0 = col[c], a1 = col[c + 1];
+                    col[c] = cs[c] * a0 + sn[c] * a1;
+                    col[c + 1] = -sn[c] * a0 + cs[c] * a1;
+                }
+                const double a0 = col[j];
+                const double den = sqrt(a0 * a0 + hn * hn);
+                const double c = den > 0.0 ? a0 / den : 1.0;
+                const double s = den > 0.0 ? hn / den : 0.0;
+                col[j] = den;
+                cs[j] = c;
+                sn[j] = s;
+                const double gj = g[j];
+                g[j + 1] = -s * gj;
+                g[j] = c * gj;
+                const double r = fabs(s * gj);
+                flag[0] = (r <= tol || hn == 0.0) ? 1 : 0;
+                hc[39] = r;   // read back after the barrier
+            }
+            __syncthreads();
+            ++its;
+            kdim = j + 1;
+            conv = flag[0];
+            res = hc[39];
+            __syncthreads();   // hc and flag are rewritten by the next iteration
+            if (conv || its >= a.maxit) break;
+        }
+        // y = R^{-1} g by columns, then u = V y into column kdim (no longer
+        // needed), x += M^{-1} u
+        if (tid == 0) {
+            for (int c = 0; c < kdim; ++c) yv[c] = g[c];
+            for (int c = kdim - 1; c >= 0; --c) {
+                const double yc = yv[c] / H[(size_t)c * m + c];
+                yv[c] = yc;
+                for (int i = 0; i < c; ++i) yv[i] -= H[(size_t)c * m + i] * yc;
+            }
+        }
+        __syncthreads();
+        combine(nullptr, yv, kdim, 1.0, Vb + (size_t)kdim * n);
+        __syncthreads();
+        precondition(Vb + (size_t)kdim * n);
+        for (int i = tid; i < n; i += NT) xg[i] += zl[i];
+        if (conv || its >= a.maxit) break;
+        __syncthreads();
+        // restart: r = b - A x
+        spmv(xg, wl, bg);
+        __syncthreads();
+        dots(0);
+        beta = sqrt(hc[0]);
+        res = beta;
+    }
+    if (tid == 0) {
+        a.its[bi] = its;
+        a.res[bi] = res;
+    }
+}
+
+// per-cell factor runs for the persistent coarse solve: run[e][q] = F[kmap[q]][e]
+template <typename FT, int RUN>
+__global__ void k_pack_runs(const FT *F, int NE, const int *kmap, FT *runs) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= NE) return;
+#pragma unroll
+    for (int q = 0; q < RUN; ++q) {
+        const int k = kmap[q];
+        runs[(size_t)e * RUN + q] = k >= 0 ? F[(size_t)k * NE + e] : (FT)0;
+    }
+}
+
 // ---------------------------------------------------------------- kernel: 3D row sweep
 // 3D boxes with the 7-point stencil and rows of at most 64 cells: lane
 // r = y + ey*z owns row (y, z) (boxes of more than 64 rows are split into
@@ -2018,6 +2501,7 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     // widens a cell's run) takes the hyperplane kernels
     for (auto &V : lev)
         if (V->rows2d && rows_sweep_lds(*V, d.precision) > (size_t)lds_bytes) V->rows2d = false;
+    setup_persistent();
 }
 
 static bool use_rows3d(const Ras &M, const Level &V);
@@ -2128,6 +2612,7 @@ void Ras::factor(bool ilu) {
             k_ilu_store<uint16_t, float><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, V.f16.p, V.invd32.p, perm);
         }
         KCHECK();
+        if (l == L - 1 && cp.on) pack_runs();
     }
 }
 
@@ -2140,6 +2625,7 @@ void Ras::check_pivots() {
     for (int l = 0; l < L; ++l)
         HIPC(hipMemcpyAsync(hpiv + l, lev[l]->err.p, sizeof(int), hipMemcpyDeviceToHost, g->s));
     HIPC(hipStreamSynchronize(g->s));
+    count_host_wait();
     for (int l = 0; l < L; ++l)
         if (hpiv[l]) {
             const int bits = hpiv[l];
@@ -2362,12 +2848,218 @@ void Ras::prolong_add(int l, const double *ec, double *zf, const int *mask) {
     KCHECK();
 }
 
+// ---------------------------------------------------------------- persistent coarse solve (host)
+// Whether the coarsest level's GMRES runs as one persistent launch, and its
+// tables: per reservoir its boxes packed into lane groups (a box's rows on
+// consecutive lanes of one wavefront, a new group when the next box's rows
+// no longer fit), the map from every extended cell to the reservoir cell it
+// copies and from every cell to the extended cell of the box that owns it.
+
+void Ras::setup_persistent() {
+    cp.on = false;
+    if (L < 2 || d.coarse_kernel == NKS_COARSE_CHUNKED) return;
+    Level &C = *lev[L - 1];
+    const Space &S = *C.spp;
+    const bool need = d.coarse_kernel == NKS_COARSE_PERSISTENT;
+    auto refuse = [&](const char *why) {
+        if (need) fail(NKS_EINVAL, "persistent coarse solve: %s", why);
+    };
+    if (!C.rows2d) return refuse("the coarsest level is not a 2D level swept by rows");
+    if (d.variant != NKS_LEFT_RAS) return refuse("it runs the left-RAS variant only");
+    if (C.A->st.K > 25) return refuse("coarse stencil wider than 5x5");
+    int ncap = 0;
+    for (int b = 0; b < S.B; ++b) {
+        if (S.hblk[b].nz != 1) return refuse("the coarsest level is not 2D");
+        ncap = std::max(ncap, S.hblk[b].nx * S.hblk[b].ny);
+    }
+    if (ncap > COARSE_CELLS) return refuse("more than 4096 cells per reservoir on the coarsest level");
+    const int LB = C.box == 0 ? RowStencil<0>::LB : (C.box == 1 ? RowStencil<1>::LB : RowStencil<2>::LB);
+    std::vector<int> efirst(S.B + 1, 0), gfirst(S.B + 1, 0), gsteps, ext2loc(C.next_total, -1),
+        own2ext(S.N, -1);
+    std::vector<int2> glane;
+    int max_ne = 0;
+    for (int b = 0; b < S.B; ++b) {
+        const Blk &k = S.hblk[b];
+        const BlkPart &pt = C.hpart[b];
+        const int nbox = pt.px * pt.py * pt.pz;
+        const SubDev &last = C.hsub[pt.first + nbox - 1];
+        efirst[b] = C.hsub[pt.first].fac_off;
+        max_ne = std::max(max_ne, last.fac_off + last.next - efirst[b]);
+        gfirst[b] = (int)gsteps.size();
+        int used = 64;
+        for (int q = pt.first; q < pt.first + nbox; ++q) {
+            const SubDev &sd = C.hsub[q];
+            if (sd.ey > 64) return refuse("a coarse box of more than 64 rows");
+            if (used + sd.ey > 64) {
+                glane.resize(glane.size() + 64, int2{q, -1});
+                gsteps.push_back(0);
+                used = 0;
+            }
+            const size_t gq = gsteps.size() - 1;
+            for (int y = 0; y < sd.ey; ++y) glane[gq * 64 + used + y] = int2{q, y};
+            used += sd.ey;
+            gsteps[gq] = std::max(gsteps[gq], (sd.ex - 1) + LB * (sd.ey - 1) + 1);
+            for (int y = 0; y < sd.ey; ++y)
+                for (int x = 0; x < sd.ex; ++x) {
+                    const int loc = (sd.gorg - k.off) + x + k.nx * y;
+                    ext2loc[sd.fac_off + x + sd.ex * y] = loc;
+                    if (x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1) {
+                        if (own2ext[k.off + loc] >= 0) fail(NKS_EINVAL, "coarse cell owned twice");
+                        own2ext[k.off + loc] = sd.fac_off + x + sd.ex * y;
+                    }
+                }
+        }
+    }
+    efirst[S.B] = C.next_total;
+    gfirst[S.B] = (int)gsteps.size();
+    for (int i = 0; i < S.N; ++i)
+        if (own2ext[i] < 0) fail(NKS_EINVAL, "coarse cell %d owned by no box", i);
+    const int m = coarse.m;
+    const size_t vt = d.precision == NKS_FP64 ? 8 : 4;
+    const int nw = (d.precision == NKS_FP64 ? 512 : 1024) / 64;
+    const size_t lds = sizeof(double) * (2 * (size_t)ncap + 40 + (size_t)m * m + 4 * m + 1 + 8 * nw) +
+                       4 * sizeof(int) + vt * ((size_t)max_ne + 1);
+    if (lds > (size_t)lds_bytes) return refuse("the largest reservoir's boxes do not fit in LDS");
+    // One workgroup streams its reservoir's factor runs through one CU in
+    // every sweep; measured on MI355X, that outruns the chunked launches only
+    // while they stay small (a 64 x 64 coarse level of 12 x 12 boxes, 0.9 MB
+    // of FP32 runs, sweeps at about 1.4 us per wavefront step).  The
+    // automatic choice takes the persistent form up to 256 KiB of runs.
+    const size_t run_bytes =
+        d.precision == NKS_FP64
+            ? (C.box == 0 ? row_run<0, double>() : (C.box == 1 ? row_run<1, double>() : row_run<2, double>())) * 8
+            : (d.precision == NKS_FP32
+                   ? (C.box == 0 ? row_run<0, float>() : (C.box == 1 ? row_run<1, float>() : row_run<2, float>())) * 4
+                   : (C.box == 0 ? row_run<0, uint16_t>()
+                                 : (C.box == 1 ? row_run<1, uint16_t>() : row_run<2, uint16_t>())) * 2);
+    if (!need && (size_t)max_ne * run_bytes > COARSE_AUTO_RUN_BYTES) return;
+    hipStream_t s = g->s;
+    cp.ncap = ncap;
+    cp.max_ne = max_ne;
+    cp.lds = lds;
+    cp.efirst.upload(&g->al, efirst, s);
+    cp.gfirst.upload(&g->al, gfirst, s);
+    cp.gsteps.upload(&g->al, gsteps, s);
+    cp.glane.upload(&g->al, glane, s);
+    cp.ext2loc.upload(&g->al, ext2loc, s);
+    cp.own2ext.upload(&g->al, own2ext, s);
+    // the padded runs depend on the factor type
+    int km[32];
+    std::vector<int> kv(32);
+    const int NE = C.next_total;
+    if (d.precision == NKS_FP64) {
+        if (C.box == 0) row_kmap<0, double>(C.hslot, km);
+        else if (C.box == 1) row_kmap<1, double>(C.hslot, km);
+        else row_kmap<2, double>(C.hslot, km);
+        const int run = C.box == 0 ? row_run<0, double>() : (C.box == 1 ? row_run<1, double>() : row_run<2, double>());
+        cp.r64.alloc(&g->al, (size_t)NE * run);
+    } else if (d.precision == NKS_FP32) {
+        if (C.box == 0) row_kmap<0, float>(C.hslot, km);
+        else if (C.box == 1) row_kmap<1, float>(C.hslot, km);
+        else row_kmap<2, float>(C.hslot, km);
+        const int run = C.box == 0 ? row_run<0, float>() : (C.box == 1 ? row_run<1, float>() : row_run<2, float>());
+        cp.r32.alloc(&g->al, (size_t)NE * run);
+    } else {
+        if (C.box == 0) row_kmap<0, uint16_t>(C.hslot, km);
+        else if (C.box == 1) row_kmap<1, uint16_t>(C.hslot, km);
+        else row_kmap<2, uint16_t>(C.hslot, km);
+        const int run =
+            C.box == 0 ? row_run<0, uint16_t>() : (C.box == 1 ? row_run<1, uint16_t>() : row_run<2, uint16_t>());
+        cp.r16.alloc(&g->al, (size_t)NE * run);
+    }
+    for (int q = 0; q < 32; ++q) kv[q] = km[q];
+    cp.kmap.upload(&g->al, kv, s);
+    cp.V.alloc(&g->al, (size_t)(m + 1) * S.N);
+    cp.its.alloc(&g->al, S.B);
+    cp.res.alloc(&g->al, S.B);
+    cp.on = true;
+}
+
+template <typename FT, int BOX>
+static void pack_runs_t(Ras &M, Level &C, const FT *F, FT *runs) {
+    constexpr int RUN = row_run<BOX, FT>();
+    k_pack_runs<FT, RUN><<<nblk(C.next_total, 256), 256, 0, M.g->s>>>(F, C.next_total, M.cp.kmap.p, runs);
+    KCHECK();
+}
+
+void Ras::pack_runs() {
+    Level &C = *lev[L - 1];
+    if (d.precision == NKS_FP64) {
+        if (C.box == 0) pack_runs_t<double, 0>(*this, C, C.f64.p, cp.r64.p);
+        else if (C.box == 1) pack_runs_t<double, 1>(*this, C, C.f64.p, cp.r64.p);
+        else pack_runs_t<double, 2>(*this, C, C.f64.p, cp.r64.p);
+    } else if (d.precision == NKS_FP32) {
+        if (C.box == 0) pack_runs_t<float, 0>(*this, C, C.f32.p, cp.r32.p);
+        else if (C.box == 1) pack_runs_t<float, 1>(*this, C, C.f32.p, cp.r32.p);
+        else pack_runs_t<float, 2>(*this, C, C.f32.p, cp.r32.p);
+    } else {
+        if (C.box == 0) pack_runs_t<uint16_t, 0>(*this, C, C.f16.p, cp.r16.p);
+        else if (C.box == 1) pack_runs_t<uint16_t, 1>(*this, C, C.f16.p, cp.r16.p);
+        else pack_runs_t<uint16_t, 2>(*this, C, C.f16.p, cp.r16.p);
+    }
+}
+
+template <typename FT, typename VT, typename DT>
+static void launch_coarse(Ras &M, Level &C, CoarseArgs &a) {
+    // 1024 threads (four wavefronts per SIMD, 128 registers each) for the
+    // FP32 sweeps, 512 for the FP64 ones, whose runs take twice the registers
+    constexpr int NT = sizeof(VT) == 8 ? 512 : 1024;
+    void (*fn)(CoarseArgs) = C.box == 0 ? k_coarse_gmres<FT, VT, DT, 0, NT>
+                                        : (C.box == 1 ? k_coarse_gmres<FT, VT, DT, 1, NT> : k_coarse_gmres<FT, VT, DT, 2, NT>);
+    set_lds((const void *)fn, M.cp.lds);
+    launch_timed("coarse_gmres", M.L - 1, fn, dim3(C.spp->B), dim3(NT), M.cp.lds, M.g->s, a);
+    KCHECK();
+}
+
+void Ras::coarse_persistent(const double *b, double *x, const int *mask) {
+    Level &C = *lev[L - 1];
+    const Op &A = *C.A;
+    CoarseArgs a{};
+    a.blk = C.spp->blk.p;
+    a.sub = C.sub.p;
+    a.efirst = cp.efirst.p;
+    a.gfirst = cp.gfirst.p;
+    a.glane = cp.glane.p;
+    a.gsteps = cp.gsteps.p;
+    a.ext2loc = cp.ext2loc.p;
+    a.own2ext = cp.own2ext.p;
+    a.invd = d.precision == NKS_FP64 ? (const void *)C.invd64.p : (const void *)C.invd32.p;
+    a.runs = d.precision == NKS_FP64 ? (const void *)cp.r64.p
+                                     : (d.precision == NKS_FP32 ? (const void *)cp.r32.p : (const void *)cp.r16.p);
+    a.coef = A.coef.p;
+    a.K = A.st.K;
+    a.N = C.spp->N;
+    for (int q = 0; q < 25; ++q) {
+        const int qq = std::min(q, A.st.K - 1);
+        a.offp[q] = (A.st.off[3 * qq] & 0xff) | ((A.st.off[3 * qq + 1] & 0xff) << 8);
+    }
+    a.b = b;
+    a.x = x;
+    a.V = cp.V.p;
+    a.mask = mask;
+    a.its = cp.its.p;
+    a.res = cp.res.p;
+    a.m = coarse.m;
+    a.maxit = d.coarse_maxit;
+    a.rtol = d.coarse_rtol;
+    a.atol = 0.0;
+    a.ncap = cp.ncap;
+    if (d.precision == NKS_FP64) launch_coarse<double, double, double>(*this, C, a);
+    else if (d.precision == NKS_FP32) launch_coarse<float, float, float>(*this, C, a);
+    else launch_coarse<uint16_t, float, float>(*this, C, a);
+}
+
 static void zero(const Space &S, double *x, hipStream_t s) {
     k_fill<<<nblk(S.N, 256), 256, 0, s>>>(S.N, 0.0, x);
     KCHECK();
 }
 
 void Ras::coarse_solve(const double *b, double *x, const int *mask) {
+    if (cp.on) {
+        coarse_persistent(b, x, mask);
+        ++coarse_calls;
+        return;
+    }
     Level &C = *lev[L - 1];
     const Space &S = *C.spp;
     hipStream_t s = g->s;

@@ -90,6 +90,7 @@ class SolverSettings:
     fill: int = 0                        # subdomain ILU level of fill k: ILU(k) (0: ILU(0))
     ratio: int = 2                       # coarse-to-fine mesh ratio per direction between levels
     coarse_op: str = "galerkin"          # galerkin (P^T A P) | rediscretised (upscaled coarse problem)
+    coarse_kernel: str = "auto"          # coarsest GMRES: auto | chunked (captured launches) | persistent
     mu: int = 1
     nu: int = 1
     coarse_rtol: float = 0.2
