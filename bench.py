@@ -40,16 +40,19 @@ WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128
 # HBM bytes per launch of a sweep kernel over a whole level (no reservoir
 # masked out), from two rocprofv3 --pmc passes over `bench.py --apply-level L`
 # (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by the factors that
-# make a 256 MiB device copy read and write 256 MiB), keyed by workload and
-# level.  Valid only for the kernel source they were taken on: any edit of
-# that file drops them to null until the counters are taken again.
+# make a 256 MiB device copy read and write 256 MiB), keyed by workload,
+# level, tile edge, that level's overlap and the coarse-to-fine ratio.  Valid
+# only for the kernel source they were taken on: any edit of that file drops
+# them to null until the counters are taken again.
 PMC_SOURCE = "paper_2007_13966_amd/csrc/schwarz.hip"
 PMC_TRAFFIC = {}
 
 
-def pmc_traffic(workload, level):
+def pmc_traffic(workload, level, settings):
     import hashlib
-    t = PMC_TRAFFIC.get((workload, level))
+    key = (workload, level, settings.tile[0], settings.overlap[min(level, len(settings.overlap) - 1)],
+           settings.ratio)
+    t = PMC_TRAFFIC.get(key)
     if t is None:
         return None
     with open(os.path.join(HERE, PMC_SOURCE), "rb") as f:
@@ -90,7 +93,8 @@ def apply_level_mode(P, S, case, level, repeats):
     db = 8 if s.precision == "fp64" else 4
     ext, owned = cells[0] / repeats, cells[1] / repeats
     nbytes = ext * ((K - 1) * fb + db + 8) + owned * 8
-    print(json.dumps({"workload": case.name, "level": level, "precision": s.precision, "launches": repeats,
+    print(json.dumps({"workload": case.name, "level": level, "precision": s.precision, "tile": s.tile[0],
+                      "overlap": s.overlap[min(level, len(s.overlap) - 1)], "ratio": s.ratio, "launches": repeats,
                       "ext_cells": ext, "owned_cells": owned, "stencil_points": K,
                       "algorithmic_bytes": nbytes, "avg_launch_us": 1e3 * t.value / max(1, c.value)}))
 
@@ -211,7 +215,7 @@ def step_record(st):
         reasons[w] = reasons.get(w, 0) + 1
     rr = st.get("rel_res") or [st["fnorm"] / st["fnorm0"] if st["fnorm0"] else 0.0]
     return dict(newton=st["newton_its"], gmres=st["linear_its"], rel_res_max=float(max(rr)),
-                stop=reasons)
+                stop=reasons, host_waits=st.get("host_waits"), fgmres_graph_chunk=st.get("graph_chunk"))
 
 
 def run_gpu(P, case, settings, warmup, steps, keep_states=0, profile=True, breakdown_steps=2):
@@ -408,9 +412,13 @@ def main():
                     help="subdomain ILU level of fill k: ILU(k) instead of ILU(0)")
     ap.add_argument("--interp-order", type=int, default=0, choices=[0, 1, 2, 3],
                     help="interpolation order between levels (0: the workload's own)")
-    ap.add_argument("--autotune", type=int, default=-1, choices=[-1, 0, 1],
-                    help="choose the subdomain tile edge (8, 16, 32) and fine overlap (1, 2) with "
-                         "nks_ras_autotune at the initial state (-1: on for the batch workload)")
+    ap.add_argument("--autotune", type=int, default=0, choices=[0, 1],
+                    help="choose the subdomain tile edge (8, 16, 32), overlap (1, 2) and coarse-to-fine "
+                         "ratio (2, 4, 8) with nks_ras_autotune at the initial state and run with its "
+                         "choice (0: the workload's settings, for the batch the tuner's choice on MI355X)")
+    ap.add_argument("--tile", type=int, default=0, help="subdomain tile edge (0: the workload's)")
+    ap.add_argument("--overlap", type=int, default=-1, help="overlap on every level (-1: the workload's)")
+    ap.add_argument("--ratio", type=int, default=0, help="coarse-to-fine ratio (0: the workload's)")
     ap.add_argument("--apply-level", type=int, default=-1, metavar="L",
                     help="only run the one-level sweeps of level L over the whole workload (the tuned "
                          "defaults, no masks) --repeats times, for hardware counter passes, and exit")
@@ -432,6 +440,13 @@ def main():
         case = S.with_solver(case, fill=args.fill)
     if args.lag != 1:
         case = S.with_solver(case, lag=args.lag)
+    if args.tile:
+        case = S.with_solver(case, tile=(args.tile, args.tile, 0 if all(r.nz == 1 for r in case.problems)
+                                         else args.tile))
+    if args.overlap >= 0:
+        case = S.with_solver(case, overlap=(args.overlap,) * case.solver.levels)
+    if args.ratio:
+        case = S.with_solver(case, ratio=args.ratio)
     ncheck = min(case.nsteps, 3) if args.cpu_steps <= 0 else args.cpu_steps
 
     # the oracle first: its workers are forked before anything touches the GPU
@@ -459,7 +474,7 @@ def main():
     if args.apply_level >= 0:
         apply_level_mode(P, S, case, args.apply_level, args.repeats)
         return
-    autotune = args.autotune if args.autotune >= 0 else int(args.workload == "batch64")
+    autotune = args.autotune
     tuning = None
     if autotune:
         g0 = P.Grid(case.problems)
@@ -487,6 +502,31 @@ def main():
         log(f"{f}: {summ[f]['s_per_step']:.4f} s/step, newton {[r['newton'] for r in summ[f]['steps']]}, "
             f"gmres {[r['gmres'] for r in summ[f]['steps']]}, rel.res reached <= "
             f"{summ[f]['rel_res_reached_max']:.2e}, dp error vs oracle {e.get('max_rel_dp_error')}")
+    # the coarse GMRES in both forms at the same settings: captured chunks of
+    # launches with host convergence tests, and the persistent per-reservoir
+    # launch (no host round trip; the FGMRES iterations then captured too)
+    coarse_forms = None
+    if case.solver.levels > 1 and all(r.nz == 1 for r in case.problems) and args.apply_level < 0:
+        coarse_forms = {}
+        # each form at the settings the tuner picks for it on MI355X (the
+        # persistent one wants small coarse boxes: ratio 8, overlap 1)
+        best = {"chunked": {}, "persistent": dict(tile=(32, 32, 0), overlap=(1, 1), ratio=8)}
+        for kind in ("chunked", "persistent"):
+            kw = best[kind] if args.workload == "batch64" and not args.tile and not args.ratio else {}
+            sk = S.with_solver(case, precision=head, coarse_kernel=kind, **kw).solver
+            try:
+                rk = run_gpu(P, case, sk, args.warmup, args.steps, profile=False, breakdown_steps=0)
+            except P.NksError as e:
+                coarse_forms[kind] = {"error": str(e)[:160]}
+                continue
+            recs = [step_record(x) for x in rk["stats"]]
+            coarse_forms[kind] = {"s_per_step": rk["seconds"] / args.steps,
+                                  "tile": list(sk.tile), "overlap": list(sk.overlap), "ratio": sk.ratio,
+                                  "host_waits_per_step": [r["host_waits"] for r in recs],
+                                  "fgmres_graph_chunk": [r["fgmres_graph_chunk"] for r in recs],
+                                  "newton": [r["newton"] for r in recs], "gmres": [r["gmres"] for r in recs]}
+            log(f"coarse {kind}: {coarse_forms[kind]['s_per_step']:.4f} s/step, host waits "
+                f"{coarse_forms[kind]['host_waits_per_step']}")
     s_head = S.with_solver(case, precision=head).solver
     r_head = runs[head]
     sec = summ[head]["s_per_step"]
@@ -541,7 +581,7 @@ def main():
             "per_step": summ[head]["steps"],
         },
         "forms": summ,
-        "roofline": dict(sweeps[dom], traffic=pmc_traffic(case.name, dom),
+        "roofline": dict(sweeps[dom], traffic=pmc_traffic(case.name, dom, case.solver),
                          measured="the profiled steps after the timed ones: every launch of the record "
                                   "with HIP events on its dispatch, bytes from the cells the launches swept "
                                   "(counted on the device)") if dom is not None else None,
@@ -555,6 +595,8 @@ def main():
     }
     if "fp64" in summ and head != "fp64":
         out["mixed_vs_fp64_speedup"] = summ["fp64"]["s_per_step"] / sec
+    if coarse_forms:
+        out["coarse_forms"] = coarse_forms
     sp = r_head["breakdown"].get("spmv_l0", np.zeros(0))
     if sp.size and all(r.nz == 1 for r in case.problems):
         # 2D: the 5-point launches are the fine level's residuals r = b - A x

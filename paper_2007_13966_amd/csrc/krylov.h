@@ -2,6 +2,8 @@
 #pragma once
 
 #include <functional>
+#include <map>
+#include <tuple>
 
 #include "nks_internal.h"
 
@@ -22,7 +24,7 @@ struct GmDev {
     double *tol, *beta, *res;
     int *active, *conv, *kdim, *its, *upd;
     int *active2;     // second activity buffer: iteration j reads buffer j%2, writes the other
-    int *flag;        // host-mapped, 4 slots of nb: iteration j (slot j%3) and restart (slot 3) activity
+    int *flag;        // host-mapped, m + 1 slots of nb: iteration j's activity (slot j), a cycle's start (slot m)
     int nb;
     int m, maxit;
     double rtol, atol;
@@ -35,6 +37,7 @@ struct GmOpts {
     bool flexible = false;
     int check_every = 1;
     int graph_chunk = 0;   // > 0: replay captured chunks of this many iterations (A and M must be capturable)
+    int lead = 0;          // > 0: iterations in the first chunk of a cycle (default 2 graph_chunk)
     bool single_pass = false;   // classical Gram-Schmidt without reorthogonalisation (loose solves)
 };
 
@@ -56,11 +59,15 @@ struct Gmres {
     int *hint = nullptr;
     volatile int *hflag = nullptr;   // mapped pinned flags (host view)
     int *dflag = nullptr;            // device view
-    int flag_b = 0;
+    int flag_b = 0, flag_m = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    // captured iteration chunks (valid while the buffers behind A and M are)
-    std::vector<hipGraphExec_t> gexec;
+    // captured iteration chunks [j0, j1) (valid while the buffers behind A and M are)
+    std::map<std::pair<int, int>, hipGraphExec_t> gexec;
     int gchunk = 0;
+    // what the captured kernels hold by value besides the buffers: the
+    // iteration limit, the Gram-Schmidt form, flexibility, the operator
+    std::tuple<int, int, int, const void *> gkey{-1, -1, -1, nullptr};
+    int last_k = 0;              // iterations of the last solve's first cycle, until no reservoir iterated
     bool graphs_ok = true;
     void invalidate_graphs();
 

@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_begin(const Chunk *chunks, c
         for (int k = 0; k <= st.m; ++k) st.g[(size_t)b * (st.m + 1) + k] = 0.0;
         st.g[(size_t)b * (st.m + 1)] = beta;
         st.active[b] = act;
-        st.flag[3 * st.nb + b] = act ? 1 : (conv ? 2 : 0);
+        st.flag[st.m * st.nb + b] = act ? 1 : (conv ? 2 : 0);
     }
 }
 
@@ -692,14 +692,16 @@ void Gmres::ensure(Alloc *al_, const Space &sp_, int m_, bool flexible, hipStrea
         // pinned staging for stats(): the 6*B ints, then the 3*B doubles
         HIPC(hipHostMalloc((void **)&hint, sizeof(int) * 6 * B + sizeof(double) * 3 * B + 64));
     }
-    if (!hflag || flag_b < B) {
+    if (!hflag || flag_b < B || flag_m < m) {
+        // one slot of B flags per iteration of a cycle, and slot m for its start
         if (hflag) HIPC(hipHostFree((void *)hflag));
         int *h = nullptr;
-        HIPC(hipHostMalloc((void **)&h, 4 * sizeof(int) * B, hipHostMallocMapped));
+        HIPC(hipHostMalloc((void **)&h, (size_t)(m + 1) * sizeof(int) * B, hipHostMallocMapped));
         HIPC(hipHostGetDevicePointer((void **)&dflag, h, 0));
-        for (int k = 0; k < 4 * B; ++k) h[k] = 0;
+        for (int k = 0; k < (m + 1) * B; ++k) h[k] = 0;
         hflag = h;
         flag_b = B;
+        flag_m = m;
         if (!ev[0])
             for (auto &e : ev) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
@@ -746,11 +748,9 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
     GmDev st = dev(o.rtol, o.atol, o.maxit);
     const int NB = nblk(S.N, 256);
     double *P0 = red.part.p, *P1 = red.part.p + (size_t)nch * MAXCOL;
-    // host flags per reservoir: 1 iterating, 2 converged, 0 stopped for a
-    // restart (or at maxit)
+    // host flags per reservoir and iteration slot: 1 iterating, 2 converged,
+    // 0 stopped for a restart (or at maxit); slot m: the start of a cycle
     auto any_flag = [&](int slot) -> bool {
-        HIPC(hipEventSynchronize(ev[slot]));
-        count_host_wait();
         for (int k = 0; k < nb; ++k)
             if (hflag[slot * nb + k] == 1) return true;
         return false;
@@ -759,6 +759,10 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
         for (int k = 0; k < nb; ++k)
             if (hflag[slot * nb + k] != 2) return false;
         return true;
+    };
+    auto wait = [&](hipEvent_t e) {
+        HIPC(hipEventSynchronize(e));
+        count_host_wait();
     };
     const double *r0 = b;
     if (!x_zero) {
@@ -778,8 +782,8 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
     const double *const *Vp = vptr.p;
     const double *vb = V[0].p;   // the basis: m + 1 columns of stride ld
     const bool flex = o.flexible;
-    // one GMRES iteration j; its activity flags go to `slot`
-    auto iteration = [&](int j, int slot) {
+    // one GMRES iteration j; its activity flags go to slot j
+    auto iteration = [&](int j) {
         double *zj = flex ? Z[j].p : t.p;
         const int *act = (j & 1) ? st.active2 : st.active;
         int *act_next = (j & 1) ? st.active : st.active2;
@@ -807,67 +811,89 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
                 KCHECK();
             }
             k_gm_finish<NC><<<nch, RED_THREADS, 0, s>>>(S.chunk.p, S.cfirst.p, w.p, vb, ld, j, one ? P0 : P1,
-                                                        V[j + 1].p, st, act, act_next, slot, one);
+                                                        V[j + 1].p, st, act, act_next, j, one);
             KCHECK();
         });
     };
     const int kc = (o.graph_chunk > 0 && graphs_ok && s != nullptr && !prof_direct()) ? std::min(o.graph_chunk, m) : 0;
-    if (kc && kc != gchunk) invalidate_graphs();
+    const std::tuple<int, int, int, const void *> key{o.maxit, o.single_pass ? 1 : 0, flex ? 1 : 0, Aop};
+    if ((kc && kc != gchunk) || key != gkey) invalidate_graphs();
     gchunk = kc;
-    // Captured chunks: a lead chunk of 2*kc iterations, then chunks of kc
-    // (each graph launch costs a boundary of several microseconds; the
-    // chunk queued past convergence, the look-ahead, runs as no-ops).
-    const int lead = kc ? std::min(m, 2 * kc) : 1, tail = kc ? kc : 1;
+    gkey = key;
+    // Chunks of iterations [j0, j1): a lead chunk (o.lead iterations, or 2 kc),
+    // then chunks of kc, each captured once and replayed (a graph launch costs
+    // a boundary of a few microseconds; iterations queued past convergence
+    // run as no-ops).  Without graphs every chunk is one iteration.
+    const int lead = kc ? std::max(1, std::min(m, o.lead > 0 ? o.lead : 2 * kc)) : 1, tail = kc ? kc : 1;
     auto chunk_begin = [&](int c) { return c == 0 ? 0 : std::min(m, lead + (c - 1) * tail); };
-    const int nchunk = kc ? 1 + (m - lead + tail - 1) / tail : m;
-    if (kc && (int)gexec.size() < nchunk) gexec.resize(nchunk, nullptr);
+    const int nchunk = 1 + (m - lead + tail - 1) / tail;
     auto launch_chunk = [&](int c) {
-        const int j0 = kc ? chunk_begin(c) : c, j1 = kc ? chunk_begin(c + 1) : c + 1;
+        const int j0 = chunk_begin(c), j1 = chunk_begin(c + 1);
         if (!kc) {
-            iteration(j0, c % 3);
+            iteration(j0);
             return;
         }
-        if (!gexec[c]) {
+        hipGraphExec_t &ge = gexec[{j0, j1}];
+        if (!ge) {
             hipGraph_t gr = nullptr;
             if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
                 (void)hipGetLastError();
                 graphs_ok = false;   // e.g. the legacy default stream: plain launches from now on
-                for (int j = j0; j < j1; ++j) iteration(j, c % 3);
+                gexec.erase({j0, j1});
+                for (int j = j0; j < j1; ++j) iteration(j);
                 return;
             }
             try {
-                for (int j = j0; j < j1; ++j) iteration(j, c % 3);
+                for (int j = j0; j < j1; ++j) iteration(j);
             } catch (...) {
                 (void)hipStreamEndCapture(s, &gr);
                 if (gr) (void)hipGraphDestroy(gr);
+                gexec.erase({j0, j1});
                 throw;
             }
             HIPC(hipStreamEndCapture(s, &gr));
-            HIPC(hipGraphInstantiate(&gexec[c], gr, nullptr, nullptr, 0));
+            HIPC(hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0));
             HIPC(hipGraphDestroy(gr));
         }
-        HIPC(hipGraphLaunch(gexec[c], s));
+        HIPC(hipGraphLaunch(ge, s));
     };
+    last_k = 0;
+    bool first_cycle = true;
     for (;;) {
         // The first chunk of a cycle is queued before the cycle's start flag
-        // is read (a cycle with nothing to do runs it as no-ops).  The cycle
-        // ends when a finished chunk leaves no reservoir iterating; when all
-        // of them converged, the solve ends without recomputing the residual.
+        // is read (a cycle with nothing to do runs it as no-ops), and each
+        // later chunk before the flags of the one ahead of it are read (with
+        // graphs one chunk ahead, each graph launch costing a boundary; two
+        // without).  The cycle ends when a finished chunk leaves no reservoir
+        // iterating; when all of them converged, the solve ends without
+        // recomputing the residual.
         bool finished = false;
         for (int c = 0; c < nchunk; ++c) {
             launch_chunk(c);
             HIPC(hipEventRecord(ev[c % 3], s));
-            if (c == 0 && !any_flag(3)) {
-                finished = true;
-                break;
+            if (c == 0) {
+                wait(ev[3]);
+                if (!any_flag(m)) {
+                    finished = true;
+                    break;
+                }
             }
-            // look-ahead (with graphs one chunk: each graph launch costs a boundary)
             const int back = kc ? 1 : 2;
-            if (c >= back && !any_flag((c - back) % 3)) {
-                finished = all_converged((c - back) % 3);
-                break;
+            if (c >= back) {
+                const int cb = c - back, last = chunk_begin(cb + 1) - 1;
+                wait(ev[cb % 3]);
+                if (!any_flag(last)) {
+                    // the iteration after which no reservoir iterated
+                    int k = chunk_begin(cb);
+                    while (k < last && any_flag(k)) ++k;
+                    if (first_cycle) last_k = k + 1;
+                    finished = all_converged(last);
+                    break;
+                }
             }
         }
+        if (first_cycle && last_k == 0) last_k = m;
+        first_cycle = false;
         k_gm_solve_y<<<S.B, 64, 0, s>>>(S.B, st);
         KCHECK();
         if (flex) {
@@ -892,7 +918,7 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
 
 void Gmres::invalidate_graphs() {
     for (auto &g : gexec)
-        if (g) (void)hipGraphExecDestroy(g);
+        if (g.second) (void)hipGraphExecDestroy(g.second);
     gexec.clear();
 }
 

@@ -134,7 +134,8 @@ struct Ras {
     Gmres coarse;
     int lds_bytes = 65536;
     int n_cu = 1;                // compute units of the device
-    int graph_chunk = 4;         // coarse GMRES iterations per captured graph (0: plain launches)
+    int graph_chunk = 2;         // coarse GMRES iterations per captured graph after the first chunk
+    int coarse_lead = 8;         // iterations of the first chunk: the last coarse solve's count
     int coarse_its_last = 0;
     long coarse_its_total = 0;
     long coarse_calls = 0;
