@@ -37,7 +37,6 @@ struct GmOpts {
     bool flexible = false;
     int check_every = 1;
     int graph_chunk = 0;   // > 0: replay captured chunks of this many iterations (A and M must be capturable)
-    int lead = 0;          // > 0: iterations in the first chunk of a cycle (default 2 graph_chunk)
     bool single_pass = false;   // classical Gram-Schmidt without reorthogonalisation (loose solves)
 };
 
@@ -67,7 +66,6 @@ struct Gmres {
     // what the captured kernels hold by value besides the buffers: the
     // iteration limit, the Gram-Schmidt form, flexibility, the operator
     std::tuple<int, int, int, const void *> gkey{-1, -1, -1, nullptr};
-    int last_k = 0;              // iterations of the last solve's first cycle, until no reservoir iterated
     bool graphs_ok = true;
     void invalidate_graphs();
 

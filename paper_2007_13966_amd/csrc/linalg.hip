@@ -820,11 +820,11 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
     if ((kc && kc != gchunk) || key != gkey) invalidate_graphs();
     gchunk = kc;
     gkey = key;
-    // Chunks of iterations [j0, j1): a lead chunk (o.lead iterations, or 2 kc),
-    // then chunks of kc, each captured once and replayed (a graph launch costs
-    // a boundary of a few microseconds; iterations queued past convergence
-    // run as no-ops).  Without graphs every chunk is one iteration.
-    const int lead = kc ? std::max(1, std::min(m, o.lead > 0 ? o.lead : 2 * kc)) : 1, tail = kc ? kc : 1;
+    // Chunks of iterations [j0, j1): a lead chunk of 2 kc, then chunks of kc,
+    // each captured once and replayed (a graph launch costs a boundary of a
+    // few microseconds; iterations queued past convergence run as no-ops).
+    // Without graphs every chunk is one iteration.
+    const int lead = kc ? std::min(m, 2 * kc) : 1, tail = kc ? kc : 1;
     auto chunk_begin = [&](int c) { return c == 0 ? 0 : std::min(m, lead + (c - 1) * tail); };
     const int nchunk = 1 + (m - lead + tail - 1) / tail;
     auto launch_chunk = [&](int c) {
@@ -857,8 +857,6 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
         }
         HIPC(hipGraphLaunch(ge, s));
     };
-    last_k = 0;
-    bool first_cycle = true;
     for (;;) {
         // The first chunk of a cycle is queued before the cycle's start flag
         // is read (a cycle with nothing to do runs it as no-ops), and each
@@ -883,17 +881,11 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
                 const int cb = c - back, last = chunk_begin(cb + 1) - 1;
                 wait(ev[cb % 3]);
                 if (!any_flag(last)) {
-                    // the iteration after which no reservoir iterated
-                    int k = chunk_begin(cb);
-                    while (k < last && any_flag(k)) ++k;
-                    if (first_cycle) last_k = k + 1;
                     finished = all_converged(last);
                     break;
                 }
             }
         }
-        if (first_cycle && last_k == 0) last_k = m;
-        first_cycle = false;
         k_gm_solve_y<<<S.B, 64, 0, s>>>(S.B, st);
         KCHECK();
         if (flex) {

@@ -134,8 +134,11 @@ struct Ras {
     Gmres coarse;
     int lds_bytes = 65536;
     int n_cu = 1;                // compute units of the device
-    int graph_chunk = 2;         // coarse GMRES iterations per captured graph after the first chunk
-    int coarse_lead = 8;         // iterations of the first chunk: the last coarse solve's count
+    // coarse GMRES iterations per captured graph after a first chunk of twice
+    // as many (measured on the batch: shorter chunks, or a first chunk sized
+    // to the previous solve, cost more in host polls and graph instances
+    // than the iterations they save)
+    int graph_chunk = 4;
     int coarse_its_last = 0;
     long coarse_its_total = 0;
     long coarse_calls = 0;

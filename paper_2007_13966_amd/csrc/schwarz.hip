@@ -3075,13 +3075,9 @@ void Ras::coarse_solve(const double *b, double *x, const int *mask) {
     o.flexible = false;
     o.check_every = 1;
     o.graph_chunk = graph_chunk;
-    // the first chunk as long as the last solve took: the host waits on it
-    // once and few iterations run as no-ops past convergence
-    o.lead = coarse_lead;
     // one Gram-Schmidt pass: a handful of iterations to a loose tolerance
     o.single_pass = true;
     coarse.solve(A, P, b, x, true, o, mask, s, C.A);
-    coarse_lead = std::max(1, coarse.last_k);
     ++coarse_calls;
 }
 
