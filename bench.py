@@ -45,7 +45,14 @@ WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128
 # only for the kernel source they were taken on: any edit of that file drops
 # them to null until the counters are taken again.
 PMC_SOURCE = "paper_2007_13966_amd/csrc/schwarz.hip"
-PMC_TRAFFIC = {}
+PMC_TRAFFIC = {
+    ("batch64_2d_fp32prec", 0, 32, 2, 4): dict(
+        fetch_kib=40624.04, fetch_scale=2.0, write_kib=18313.61, write_scale=1.0, algorithmic=90197384.0,
+        sha1="d99de20fff8e7d0714806ceee2bd13024704f8a0", kernel="k_ras_rows<float, float, float, 0, 256>"),
+    ("batch64_2d_fp32prec", 1, 32, 2, 4): dict(
+        fetch_kib=17032.88, fetch_scale=2.0, write_kib=1607.49, write_scale=1.0, algorithmic=26957568.0,
+        sha1="d99de20fff8e7d0714806ceee2bd13024704f8a0", kernel="k_ras_rows<float, float, float, 2, 64>"),
+}
 
 
 def pmc_traffic(workload, level, settings):

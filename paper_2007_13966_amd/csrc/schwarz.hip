@@ -97,6 +97,16 @@ constexpr int row_stride() {
     return (R * sizeof(FT) / 16) % 2 ? R : R + (int)(16 / sizeof(FT));
 }
 
+// LDS stride of a cell's lower or upper run alone (the one-wavefront sweep
+// holds one of them at a time), an odd number of 16-byte words as above
+template <int BOX, typename FT>
+constexpr int row_half_stride() {
+    constexpr int PER = (int)(16 / sizeof(FT));
+    constexpr int NL = RowStencil<BOX>::NL, NU = RowStencil<BOX>::NS - NL;
+    constexpr int R = ((NL > NU ? NL : NU) + PER - 1) / PER * PER;
+    return (R * sizeof(FT) / 16) % 2 ? R : R + PER;
+}
+
 // stencil index of every slot of the padded run (lower run, then upper
 // run), from the 25 box slots of the level's stencil; -1 for absent slots
 // and padding
@@ -1064,19 +1074,20 @@ __global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
     constexpr int PER = (int)(16 / sizeof(FT));
     constexpr int NLP = (NL + PER - 1) / PER * PER, NUP = (NU + PER - 1) / PER * PER;
     constexpr int NSP = NLP + NUP;   // padded run per cell: lower run, then upper run
-    constexpr int CS = row_stride<BOX, FT>();   // LDS stride of a cell's run
+    // NT = 256: one wavefront sweeps while the other three stage the upper
+    // runs beside the lower ones; NT = 64: the lower runs are staged, the
+    // forward sweep runs, then the upper runs take their place in LDS
+    constexpr bool ONE = NT == 64;
+    constexpr int CS = ONE ? row_half_stride<BOX, FT>() : row_stride<BOX, FT>();   // LDS stride of a cell
+    constexpr int UOFF = ONE ? 0 : NLP;   // the upper run's offset in a cell's LDS slot
     constexpr int RU = rows_unroll(BOX);   // unroll = ring length (>= the deepest history used)
     constexpr int PAD = rows_pad(BOX);
-    // NT = 256: one wavefront sweeps while the other three stage the upper
-    // runs; NT = 64 (launches of many small boxes, several per CU): the one
-    // wavefront stages everything, then sweeps.
     static_assert(NT == 256 || NT == 64, "one or four wavefronts");
-    constexpr bool ONE = NT == 64;
     // cells per staging thread per pass: a 36x36 cross-stencil box in one
     // pass, so its loads pay the memory latency once
     constexpr int CPT = ONE ? 2 : (BOX == 0 ? 6 : 2);
     constexpr int CPU = 2;           // the same for the upper runs (staged during the forward sweep)
-    constexpr int NST = ONE ? NSP : NLP;   // slots staged before the forward sweep
+    constexpr int NST = NLP;         // slots staged before the forward sweep
     static_assert(NSP <= 32, "stencil map fits the argument block");
     extern __shared__ __align__(16) unsigned char smem[];
     const SubDev sd = a.sub[blockIdx.x];
@@ -1136,10 +1147,11 @@ __global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
         }
     }
     __syncthreads();
-    // one wavefront sweeps, lane = row.  For the 5-point cross, lanes past
-    // the box's rows stay disabled (no LDS traffic; a DPP read from them
-    // returns zero, the value of a row outside the box); for the box
-    // stencils all lanes run and rows past the box are masked.
+    // one wavefront sweeps, lane = row.  Lanes past the box's rows stay
+    // disabled: they take no LDS traffic (a 12-row box leaves 52 of 64 lanes
+    // idle), and a lane shift that reads them returns zero, the value of a
+    // row outside the box, also through the two-row shifts of the box
+    // stencils.
     const int T = (ex - 1) + LB * (ey - 1) + 1;
     const int y = threadIdx.x;
     const bool rowok = y < ey;
@@ -1151,7 +1163,7 @@ __global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
     // may run ahead of the current block's stores because an active step
     // reads only its own cell, which no other step writes.
     constexpr int RB = RU / 2;
-    if (wid == 0 && (BOX || rowok)) {
+    if (wid == 0 && rowok) {
         // rings: own outputs, outputs of lane y-1 and y-2
         VT r0[RU], r1[RU], r2[RU];
 #pragma unroll
@@ -1240,7 +1252,32 @@ __global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
         }
     }
     __syncthreads();
-    if (wid == 0 && (BOX || rowok)) {
+    if (ONE) {
+        // the upper runs over the lower ones, now that the forward sweep is done
+        for (int c0 = threadIdx.x; c0 < n; c0 += CPT * NT) {
+            FT v[CPT][NUP];
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = min(c0 + u * NT, n - 1);
+#pragma unroll
+                for (int q = 0; q < NUP; ++q) {
+                    const int k = a.kmap[NLP + q];
+                    const FT x = F[(size_t)max(k, 0) * a.NE + fo + c];
+                    v[u][q] = k >= 0 ? x : (FT)0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = c0 + u * NT;
+                if (c < n) {
+#pragma unroll
+                    for (int q = 0; q < NUP; ++q) cf[(size_t)c * CS + q] = v[u][q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (wid == 0 && rowok) {
         // backward: z_i = (y_i - sum_{upper} U_ik z_k) / u_ii, step t at cell cb + (T - 1 - t)
         VT r0[RU], r1[RU], r2[RU];
 #pragma unroll
@@ -1253,7 +1290,7 @@ __global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
         auto load = [&](int tb, VT(&co)[RB][NUP], VT(&rin)[RB], VT(&dg)[RB], int(&cc)[RB], bool(&aa)[RB]) {
             // cells cbb - tb - u, addressed from the block's lowest cell
             const int cl = cbb - tb - (RB - 1);
-            const FT *cfb = cf + (ptrdiff_t)cl * CS + NLP;
+            const FT *cfb = cf + (ptrdiff_t)cl * CS + UOFF;
             const VT *rvb = rv + cl;
             const DT *idb = id + cl;
 #pragma unroll
@@ -2677,21 +2714,32 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     a.mask = mask;
     a.variant = M.d.variant;
     a.accumulate = accumulate ? 1 : 0;
-    const int NSP = V.box == 0 ? row_stride<0, FT>() : (V.box == 1 ? row_stride<1, FT>() : row_stride<2, FT>());
+    // LDS strides: both runs of a cell side by side (four wavefronts), or one
+    // run at a time (one wavefront)
+    const int CS4 = V.box == 0 ? row_stride<0, FT>() : (V.box == 1 ? row_stride<1, FT>() : row_stride<2, FT>());
+    const int CS1 = V.box == 0 ? row_half_stride<0, FT>()
+                               : (V.box == 1 ? row_half_stride<1, FT>() : row_half_stride<2, FT>());
     const size_t n = V.max_next;
-    const size_t sh = rows_lds(sizeof(VT), sizeof(FT), sizeof(DT), NSP, rows_pad(V.box), n).total;
+    const size_t sh4 = rows_lds(sizeof(VT), sizeof(FT), sizeof(DT), CS4, rows_pad(V.box), n).total;
+    const size_t sh1 = rows_lds(sizeof(VT), sizeof(FT), sizeof(DT), CS1, rows_pad(V.box), n).total;
     if (V.max_next >= (1 << 16)) fail(NKS_EINVAL, "2D subdomain of %zu cells exceeds 65535", n);
-    if (sh > (size_t)M.lds_bytes) fail(NKS_EINVAL, "2D subdomain of %zu cells does not fit in LDS", n);
+    if (sh4 > (size_t)M.lds_bytes) fail(NKS_EINVAL, "2D subdomain of %zu cells does not fit in LDS", n);
     void (*fn4)(RowsArgs) = V.box == 0 ? k_ras_rows<FT, VT, DT, 0, 256>
                                        : (V.box == 1 ? k_ras_rows<FT, VT, DT, 1, 256> : k_ras_rows<FT, VT, DT, 2, 256>);
     void (*fn1)(RowsArgs) = V.box == 0 ? k_ras_rows<FT, VT, DT, 0, 64>
                                        : (V.box == 1 ? k_ras_rows<FT, VT, DT, 1, 64> : k_ras_rows<FT, VT, DT, 2, 64>);
-    // One-wavefront workgroups when they let at least twice as many boxes
-    // sweep at once on a CU (the four-wavefront form is bound by its idle
-    // staging wavefronts' registers) and the launch has the boxes to use it.
-    const int occ4 = rows_occupancy((const void *)fn4, 256, sh), occ1 = rows_occupancy((const void *)fn1, 64, sh);
+    // One-wavefront workgroups when, holding both runs, they would let at
+    // least twice as many boxes sweep at once on a CU (the four-wavefront
+    // form is bound by its idle staging wavefronts' registers) and the launch
+    // has the boxes to use it: small boxes, whose staging is short.  Large
+    // boxes keep the four-wavefront form, which stages the upper runs during
+    // the forward sweep (measured on MI355X: 36 x 36 boxes sweep 20% slower
+    // with one wavefront).  The one-wavefront form then holds one run at a
+    // time, which lets more of its boxes sweep at once.
+    const int occ4 = rows_occupancy((const void *)fn4, 256, sh4), occ1 = rows_occupancy((const void *)fn1, 64, sh4);
     const bool one = occ1 >= 2 * occ4 && V.nsub > M.n_cu * occ4;
     void (*fn)(RowsArgs) = one ? fn1 : fn4;
+    const size_t sh = one ? sh1 : sh4;
     set_lds((const void *)fn, sh);
     launch_sweep("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(one ? 64 : 256), sh, M.g->s, a);
     KCHECK();

@@ -469,3 +469,30 @@ def test_determinism(nks, orc):
     h1, _, _ = _run_steps(nks, orc, case, 1)
     h2, _, _ = _run_steps(nks, orc, case, 1)
     assert np.array_equal(h1[-1], h2[-1])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 2e-5), ("bf16", 5e-2)])
+def test_many_small_boxes_apply_parity(nks, orc, precision, tol):
+    # 32 x 32 = 1024 boxes per level, more than four per CU: the sweeps run
+    # one wavefront per box, staging a box's lower factors for the forward
+    # sweep and then its upper factors in their place; one level (5-point)
+    # and two levels (21-point coarse operator, fixed coarse iterations)
+    for levels in (1, 2):
+        cfg = dict(nx=128, ny=128, nz=1, px=32, py=32, levels=levels, overlap=(1, 1), coarse_rtol=0.0,
+                   coarse_maxit=4, seed=31)
+        case = S.small_case(**cfg)
+        case64 = case
+        case = S.with_solver(case, precision=precision)
+        say("many small boxes", precision, "levels", levels)
+        rec = case.problems[0]
+        op = orc.Problem(rec)
+        p, pn, _ = _state(op, 31)
+        Jo = op.jacobian(p, pn, pn, case.dt, 1)
+        r = np.sin(0.29 * np.arange(op.N))
+        zo = orc.Multilevel(rec, Jo, case64.solver).apply(r)
+        g = nks.Grid([rec])
+        M = nks.Ras(_gpu_jac(nks, g, p, pn, case.dt), case.solver)
+        zg = M.apply(g.from_numpy(r)).cpu().numpy()
+        err = np.max(np.abs(zg - zo)) / np.max(np.abs(zo))
+        say("  relative error", err)
+        assert err <= tol
