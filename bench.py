@@ -426,6 +426,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="subdomain tile edge (0: the workload's)")
     ap.add_argument("--overlap", type=int, default=-1, help="overlap on every level (-1: the workload's)")
     ap.add_argument("--ratio", type=int, default=0, help="coarse-to-fine ratio (0: the workload's)")
+    ap.add_argument("--coarse-op", default="", choices=["", "galerkin", "rediscretised"],
+                    help="coarse operators: Galerkin products or the upscaled problem's Jacobian")
     ap.add_argument("--apply-level", type=int, default=-1, metavar="L",
                     help="only run the one-level sweeps of level L over the whole workload (the tuned "
                          "defaults, no masks) --repeats times, for hardware counter passes, and exit")
@@ -454,6 +456,8 @@ def main():
         case = S.with_solver(case, overlap=(args.overlap,) * case.solver.levels)
     if args.ratio:
         case = S.with_solver(case, ratio=args.ratio)
+    if args.coarse_op:
+        case = S.with_solver(case, coarse_op=args.coarse_op)
     ncheck = min(case.nsteps, 3) if args.cpu_steps <= 0 else args.cpu_steps
 
     # the oracle first: its workers are forked before anything touches the GPU

@@ -1,8 +1,8 @@
 """Variant matrix of the Schwarz preconditioner on one workload (the trends of
 the paper's Section 4.2 tables: AS, left- and right-RAS with overlaps 0..3,
 V-cycle, Kaskade, additive and coarse-only compositions, interpolation orders
-1..3, coarse-to-fine ratios 2..16, ILU(k) subdomain solves), measured on one
-GPU through the library.
+1..3, coarse-to-fine ratios 2..16, ILU(k) subdomain solves, Galerkin against
+rediscretised coarse operators), measured on one GPU through the library.
 
     python -m paper_2007_13966_amd.variants [--workload 2d512] [--steps 3] [--json out.json]
 
@@ -31,6 +31,8 @@ def _variants():
             out.append((f"order {order}, ratio {ratio}", dict(interp_order=order, ratio=ratio)))
     for fill in (0, 1, 2):
         out.append((f"ILU({fill})", dict(fill=fill)))
+    out.append(("rediscretised coarse operator", dict(coarse_op="rediscretised")))
+    out.append(("rediscretised coarse operator, order 1", dict(coarse_op="rediscretised", interp_order=1)))
     return out
 
 
