@@ -159,12 +159,19 @@ def launch_split(d):
 
 def level_stencils(P, case, s):
     """Stencil points of every level's operator (the Jacobian's on the
-    finest, the coarse operators' below) for the preconditioner s builds."""
+    finest, the coarse operators' below) for the preconditioner s builds,
+    and the kernel form and workgroups of each level's one-level sweep."""
+    import torch
     g = P.Grid(case.problems)
     p0 = g.initial_pressure()
     J = g.jacobian(p0, p0, None, case.dt, 1)
     M = P.Ras(J, s)
-    return [M.level_info(l)["K"] for l in range(s.levels)]
+    forms = []
+    for l in range(s.levels):
+        r = torch.ones(M.level_info(l)["n"], dtype=torch.float64, device=g.device)
+        M.apply_level(l, r)
+        forms.append(M.level_sweep(l))
+    return [M.level_info(l)["K"] for l in range(s.levels)], forms
 
 
 def sweep_roofline(run, name, K, precision):
@@ -502,7 +509,7 @@ def main():
     head = case.solver.precision
     forms = [head] if args.no_mixed else [head] + [f for f in ("fp64", "fp32", "bf16") if f != head]
     log(f"workload {case.name}: {sum(r.N for r in case.problems)} cells, forms {forms}")
-    stencils = level_stencils(P, case, case.solver)
+    stencils, sweep_forms = level_stencils(P, case, case.solver)
     runs, summ = {}, {}
     for f in forms:
         sf = S.with_solver(case, precision=f).solver
@@ -550,9 +557,12 @@ def main():
     for lvl, K in enumerate(stencils):
         rf = sweep_roofline(r_head, f"ras_apply_l{lvl}", K, head)
         if rf:
-            two_d = all(r.nz == 1 for r in case.problems)
-            kern = f"k_ras_rows<{tname}, ...>" if two_d else f"k_ras_apply / k_ras_rows3d <{tname}, ...>"
-            rf["kernel"] = f"{kern}: level-{lvl} one-level left-RAS sweeps, {K}-point operator, ILU(0) factors"
+            form, wgs = sweep_forms[lvl]
+            kern = {"packed": "k_ras_packed", "rows4": "k_ras_rows", "rows1": "k_ras_rows",
+                    "rows3d": "k_ras_rows3d", "hyperplane": "k_ras_apply"}.get(form, "?")
+            rf["kernel"] = (f"{kern}<{tname}, ...> ({form}, {wgs} workgroups): level-{lvl} one-level "
+                            f"left-RAS sweeps, {K}-point operator, ILU(0) factors")
+            rf["form"] = form
             sweeps[lvl] = rf
     dom = max(sweeps, key=lambda l: sweeps[l]["total_ms"]) if sweeps else None
     out = {

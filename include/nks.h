@@ -286,6 +286,15 @@ int nks_ras_apply_transpose(nks_ras *M, const double *r, double *z);
 /* info[0..7] = n, stencil points, subdomains, nx, ny, nz (first reservoir),
  * number of levels, nnz of the level operator. Synchronises. */
 int nks_ras_level_info(nks_ras *M, int level, int *info);
+/* Kernel form of the level's last one-level sweep, for reports: *form =
+ * one of NKS_SWEEP_* (NKS_SWEEP_NONE before the level's first sweep), and
+ * the workgroups it launched.  The form follows from the boxes' shapes, the
+ * precision and the device's occupancy: hyperplane kernel; 2D row sweep of
+ * one box per workgroup with four or one wavefronts; packed 2D row sweep
+ * (several small boxes in one wavefront); 3D row sweep. */
+enum { NKS_SWEEP_NONE = 0, NKS_SWEEP_HYPERPLANE = 1, NKS_SWEEP_ROWS4 = 2, NKS_SWEEP_ROWS1 = 3,
+       NKS_SWEEP_PACKED = 4, NKS_SWEEP_ROWS3D = 5 };
+int nks_ras_level_sweep(nks_ras *M, int level, int *form, int *workgroups);
 /* Level operator (Galerkin product on coarse levels) as CSR in HOST arrays. */
 int nks_ras_level_export(nks_ras *M, int level, int *rowptr, int *col, double *val);
 /* Restriction P^T (fine level -> level+1) and prolongation-add

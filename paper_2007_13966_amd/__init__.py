@@ -424,6 +424,15 @@ class Ras:
         return dict(n=info[0], K=info[1], nsub=info[2], dims=(info[3], info[4], info[5]),
                     levels=info[6], nnz=info[7])
 
+    SWEEP_FORMS = {0: "none", 1: "hyperplane", 2: "rows4", 3: "rows1", 4: "packed", 5: "rows3d"}
+
+    def level_sweep(self, level):
+        """Kernel form of the level's last sweep ("none" before the first)
+        and its workgroups."""
+        form, wgs = C.c_int(), C.c_int()
+        check(lib().nks_ras_level_sweep(self.h, int(level), C.byref(form), C.byref(wgs)))
+        return self.SWEEP_FORMS[form.value], wgs.value
+
     def _vec(self, level):
         torch = _torch()
         n = self.level_info(level)["n"]

@@ -124,6 +124,7 @@ PROTOTYPES = {
     "nks_ras_coarse_stats": [_P, _IP, _DP],
     "nks_ras_apply_transpose": [_P, _P, _P],
     "nks_ras_level_info": [_P, _I, _IP],
+    "nks_ras_level_sweep": [_P, _I, _IP, _IP],
     "nks_ras_level_export": [_P, _I, _IP, _IP, _DP],
     "nks_ras_restrict": [_P, _I, _P, _P],
     "nks_ras_prolong_add": [_P, _I, _P, _P],

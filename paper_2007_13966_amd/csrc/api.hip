@@ -937,6 +937,14 @@ int nks_ras_level_info(nks_ras *M, int level, int *info) {
     });
 }
 
+int nks_ras_level_sweep(nks_ras *M, int level, int *form, int *workgroups) {
+    return guard([&] {
+        if (!M || !form || !workgroups || level < 0 || level >= M->r.L) fail(NKS_EINVAL, "bad arguments");
+        *form = M->r.lev[level]->form;
+        *workgroups = M->r.lev[level]->form_wgs;
+    });
+}
+
 int nks_ras_level_export(nks_ras *M, int level, int *rp, int *ci, double *v) {
     return guard([&] {
         if (!M || !rp || !ci || !v || level < 0 || level >= M->r.L) fail(NKS_EINVAL, "bad arguments");

@@ -86,6 +86,15 @@ struct Level {
     DBuf<double> invd64;         // 1/u_ii
     DBuf<float> invd32;
     DBuf<double> zext;           // per extended cell solution (AS / right-RAS gather)
+    int form = 0, form_wgs = 0;  // kernel form (NKS_SWEEP_*) and workgroups of the last sweep
+    // 2D levels of small boxes: groups of consecutive boxes of one block
+    // swept together, their rows packed into one wavefront
+    int pk_groups = 0;           // 0: one box per workgroup
+    size_t pk_max_n = 0;         // most extended cells of a group
+    DBuf<int2> pk_lane;          // per group: 64 lanes of {box, row} (row -1: idle)
+    DBuf<int> pk_steps;          // per group: sweep steps of its longest box
+    DBuf<int> pk_box;            // per group: first box (groups + 1 entries)
+    DBuf<int> pk_e2g;            // per extended cell: cell of the level's space, high bit where owned
     DBuf<int> err;               // zero-pivot flag
     // ILU(0) elimination table of the stencil: for lower offset k, pairs (k2, t)
     // with off[k] + off[k2] = off[t], k2 an upper offset

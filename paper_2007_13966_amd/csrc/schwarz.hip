@@ -79,13 +79,28 @@ template <> struct RowStencil<2> {
     static constexpr int DY[NS] = {-2, -2, -2, -1, -1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2};
 };
 
-// padded per-cell factor run of a row template: lower run, then upper run,
-// each a whole number of 16-byte words of FT
+// Per-cell factor runs of a row template: the lower run, then the upper
+// run, each padded to whole 16-byte words of FT; where the two fit one word
+// together (the 5-point cross in FP32 and BF16) they share it unpadded,
+// which shrinks a box's LDS footprint by half or more.
+template <int BOX, typename FT>
+constexpr bool row_tight() {
+    return RowStencil<BOX>::NS * sizeof(FT) <= 16;
+}
+template <int BOX, typename FT>
+constexpr int row_lpad() {
+    constexpr int PER = (int)(16 / sizeof(FT)), NL = RowStencil<BOX>::NL;
+    return row_tight<BOX, FT>() ? NL : (NL + PER - 1) / PER * PER;
+}
+template <int BOX, typename FT>
+constexpr int row_upad() {
+    constexpr int PER = (int)(16 / sizeof(FT)), NU = RowStencil<BOX>::NS - RowStencil<BOX>::NL;
+    return row_tight<BOX, FT>() ? NU : (NU + PER - 1) / PER * PER;
+}
+// padded run of a cell (both runs), whole 16-byte words
 template <int BOX, typename FT>
 constexpr int row_run() {
-    constexpr int PER = (int)(16 / sizeof(FT));
-    return (RowStencil<BOX>::NL + PER - 1) / PER * PER +
-           (RowStencil<BOX>::NS - RowStencil<BOX>::NL + PER - 1) / PER * PER;
+    return row_tight<BOX, FT>() ? (int)(16 / sizeof(FT)) : row_lpad<BOX, FT>() + row_upad<BOX, FT>();
 }
 
 // LDS stride of a cell's run in FT elements: an odd number of 16-byte
@@ -104,7 +119,7 @@ constexpr int row_half_stride() {
     constexpr int PER = (int)(16 / sizeof(FT));
     constexpr int NL = RowStencil<BOX>::NL, NU = RowStencil<BOX>::NS - NL;
     constexpr int R = ((NL > NU ? NL : NU) + PER - 1) / PER * PER;
-    return (R * sizeof(FT) / 16) % 2 ? R : R + PER;
+    return row_tight<BOX, FT>() ? row_stride<BOX, FT>() : ((R * sizeof(FT) / 16) % 2 ? R : R + PER);
 }
 
 // stencil index of every slot of the padded run (lower run, then upper
@@ -113,9 +128,8 @@ constexpr int row_half_stride() {
 template <int BOX, typename FT>
 static void row_kmap(const std::vector<int> &slot, int (&kmap)[32]) {
     using S = RowStencil<BOX>;
-    constexpr int PER = (int)(16 / sizeof(FT));
     constexpr int NL = S::NL, NU = S::NS - S::NL;
-    constexpr int NLP = (NL + PER - 1) / PER * PER;
+    constexpr int NLP = row_lpad<BOX, FT>();
     for (int r = 0; r < 32; ++r) kmap[r] = -1;
     for (int q = 0; q < NL; ++q) kmap[q] = slot[(S::DX[q] + 2) + 5 * (S::DY[q] + 2)];
     for (int q = 0; q < NU; ++q) kmap[NLP + q] = slot[(S::DX[NL + q] + 2) + 5 * (S::DY[NL + q] + 2)];
@@ -1018,21 +1032,32 @@ struct RowsArgs {
     int kmap[32];         // slot of the padded per-cell run -> stencil index (-1: absent or padding)
 };
 
-// coefficients of one cell: N consecutive FT values (16-byte aligned runs)
+// coefficients of one cell: N consecutive FT values, in 16-byte words, or
+// one 8- or 4-byte word (the runs of the 5-point cross in FP32 and BF16)
 template <typename FT, typename VT, int N>
 __device__ __forceinline__ void load_run(const FT *p, VT (&out)[N]) {
-    static_assert((N * sizeof(FT)) % 16 == 0, "runs are whole 16-byte words");
-    constexpr int W = (int)(N * sizeof(FT) / 16);
-    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+    constexpr int B = (int)(N * sizeof(FT));
+    static_assert(B % 16 == 0 || B == 8 || B == 4, "runs are whole 16-byte words, or one smaller word");
+    auto put = [&](const FT *f, int k0, int cnt) {
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-        const uint4 u = q[w];
-        const FT *f = reinterpret_cast<const FT *>(&u);
-        constexpr int PER = (int)(16 / sizeof(FT));
+        for (int k = 0; k < cnt; ++k) {
+            if constexpr (sizeof(FT) == 2) out[k0 + k] = (VT)from_bf16(f[k]);
+            else out[k0 + k] = (VT)f[k];
+        }
+    };
+    if constexpr (B == 8) {
+        const uint2 u = *reinterpret_cast<const uint2 *>(p);
+        put(reinterpret_cast<const FT *>(&u), 0, N);
+    } else if constexpr (B == 4) {
+        const uint32_t u = *reinterpret_cast<const uint32_t *>(p);
+        put(reinterpret_cast<const FT *>(&u), 0, N);
+    } else {
+        constexpr int W = B / 16, PER = (int)(16 / sizeof(FT));
+        const uint4 *q = reinterpret_cast<const uint4 *>(p);
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            if constexpr (sizeof(FT) == 2) out[w * PER + k] = (VT)from_bf16(f[k]);
-            else out[w * PER + k] = (VT)f[k];
+        for (int w = 0; w < W; ++w) {
+            const uint4 u = q[w];
+            put(reinterpret_cast<const FT *>(&u), w * PER, PER);
         }
     }
 }
@@ -1072,7 +1097,7 @@ __global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
     using S = RowStencil<BOX>;
     constexpr int NS = S::NS, NL = S::NL, NU = NS - NL, LB = S::LB;
     constexpr int PER = (int)(16 / sizeof(FT));
-    constexpr int NLP = (NL + PER - 1) / PER * PER, NUP = (NU + PER - 1) / PER * PER;
+    constexpr int NLP = row_lpad<BOX, FT>(), NUP = row_upad<BOX, FT>();
     constexpr int NSP = NLP + NUP;   // padded run per cell: lower run, then upper run
     // NT = 256: one wavefront sweeps while the other three stage the upper
     // runs beside the lower ones; NT = 64: the lower runs are staged, the
@@ -1106,7 +1131,7 @@ __global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
     const RowsLds L = rows_lds(sizeof(VT), sizeof(FT), sizeof(DT), CS, PAD, n);
     VT *rv = reinterpret_cast<VT *>(smem + L.rv) + PAD;
     FT *cf = reinterpret_cast<FT *>(smem + L.cf) + (size_t)PAD * CS;
-    static_assert(sizeof(FT) * NSP % 16 == 0, "cell runs are whole 16-byte words");
+    static_assert(sizeof(FT) * row_run<BOX, FT>() % 16 == 0, "cell runs are whole 16-byte words");
     DT *id = reinterpret_cast<DT *>(smem + L.id) + PAD;
     const FT *F = reinterpret_cast<const FT *>(a.F);
     const DT *ID = reinterpret_cast<const DT *>(a.invd);
@@ -1394,14 +1419,18 @@ __global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
 // upper run), RB steps ahead of the arithmetic; steps outside a row's range
 // read a cell clamped into the box and are masked.  Lanes without a row
 // (y < 0) compute nothing visible.
-template <typename FT, typename VT, typename DT, int BOX, int RB>
-__device__ __forceinline__ void packed_sweep(const SubDev &sd, int y, int T, VT *rb, VT *spare, const FT *Fb,
-                                             const DT *Ib) {
+// Forward and backward halves of the packed sweep.  The cell runs are read
+// from Fb at a stride of CS FT values (0: the lower and upper runs back to
+// back), the upper run at offset UOFF (-1: after the lower run), so the same
+// code reads per-cell runs in global memory or runs staged in LDS.
+template <typename FT, typename VT, typename DT, int BOX, int RB, int CS = 0, int UOFF = -1>
+__device__ __forceinline__ void packed_forward(const SubDev &sd, int y, int T, VT *rb, VT *spare, const FT *Fb) {
     using S = RowStencil<BOX>;
     constexpr int NS = S::NS, NL = S::NL, NU = NS - NL, LB = S::LB;
     constexpr int PER = (int)(16 / sizeof(FT));
-    constexpr int NLP = (NL + PER - 1) / PER * PER, NUP = (NU + PER - 1) / PER * PER;
-    constexpr int RUN = NLP + NUP;
+    constexpr int NLP = row_lpad<BOX, FT>(), NUP = row_upad<BOX, FT>();
+    constexpr int RUN = CS > 0 ? CS : row_run<BOX, FT>();   // stride of a cell's runs
+    constexpr int UP = UOFF >= 0 ? UOFF : NLP;     // offset of the upper run
     constexpr int RU = rows_unroll(BOX), NB = RU / RB;
     static_assert(NB % 2 == 0 && NB * RB == RU, "an even number of prefetch blocks per ring cycle");
     const bool on = y >= 0;
@@ -1468,6 +1497,24 @@ __device__ __forceinline__ void packed_sweep(const SubDev &sd, int y, int T, VT 
             }
         }
     }
+}
+
+template <typename FT, typename VT, typename DT, int BOX, int RB, int CS = 0, int UOFF = -1>
+__device__ __forceinline__ void packed_backward(const SubDev &sd, int y, int T, VT *rb, VT *spare, const FT *Fb,
+                                                const DT *Ib) {
+    using S = RowStencil<BOX>;
+    constexpr int NS = S::NS, NL = S::NL, NU = NS - NL, LB = S::LB;
+    constexpr int PER = (int)(16 / sizeof(FT));
+    constexpr int NLP = row_lpad<BOX, FT>(), NUP = row_upad<BOX, FT>();
+    constexpr int RUN = CS > 0 ? CS : row_run<BOX, FT>();   // stride of a cell's runs
+    constexpr int UP = UOFF >= 0 ? UOFF : NLP;     // offset of the upper run
+    constexpr int RU = rows_unroll(BOX), NB = RU / RB;
+    static_assert(NB % 2 == 0 && NB * RB == RU, "an even number of prefetch blocks per ring cycle");
+    const bool on = y >= 0;
+    const int ex = sd.ex, ey = sd.ey, n = sd.next;
+    const int ye = on ? y : 0;
+    const int Ts = (ex - 1) + LB * (ey - 1) + 1;
+    const int cb = ye * (ex - LB);
     {
         // backward: x = Ts - 1 - t - LB*y, upper neighbours from the rows above
         const int cbb = cb + Ts - 1;
@@ -1485,7 +1532,7 @@ __device__ __forceinline__ void packed_sweep(const SubDev &sd, int y, int T, VT 
                 const int c = min(max(cbb - tb - u, 0), n - 1);
                 aa[u] = (unsigned)(tb + u - tlob) < (unsigned)ex;
                 cc[u] = c;
-                load_run<FT, VT, NUP>(Fb + (size_t)c * RUN + NLP, co[u]);
+                load_run<FT, VT, NUP>(Fb + (size_t)c * RUN + UP, co[u]);
                 rin[u] = rb[c];
                 dg[u] = (VT)Ib[c];
             }
@@ -1529,6 +1576,158 @@ __device__ __forceinline__ void packed_sweep(const SubDev &sd, int y, int T, VT 
                 step((q + 1) * RB, coB, rinB, dgB, ccB, aaB);
             }
         }
+    }
+}
+
+template <typename FT, typename VT, typename DT, int BOX, int RB>
+__device__ __forceinline__ void packed_sweep(const SubDev &sd, int y, int T, VT *rb, VT *spare, const FT *Fb,
+                                             const DT *Ib) {
+    packed_forward<FT, VT, DT, BOX, RB>(sd, y, T, rb, spare, Fb);
+    packed_backward<FT, VT, DT, BOX, RB>(sd, y, T, rb, spare, Fb, Ib);
+}
+
+// ---------------------------------------------------------------- kernel: packed 2D sweep
+// Launches of small boxes (a coarse level's boxes are a dozen rows tall, a
+// wavefront sweeping one of them leaves most lanes idle): a workgroup takes
+// a group of boxes of one reservoir packed into 64 lanes, the rows of each
+// box on consecutive lanes, swept on the schedule of the one-box sweep (see
+// packed_forward).  All four wavefronts stage the lower runs and R_i^delta r;
+// the first sweeps forward while the others stage the upper runs and
+// 1/u_ii; it sweeps back; all write back.  The group's extended cells are
+// contiguous in the factor storage, and a per-cell map gives each one's
+// global cell (the high bit marks the cells the box owns).
+struct PackArgs {
+    const SubDev *sub;
+    const int2 *glane;      // per group: 64 lanes of {box, row} (row -1: idle)
+    const int *gsteps;      // per group: the steps of its longest box
+    const int *gbox;        // per group: first box (G + 1 entries)
+    const int *ext2glob;    // per extended cell: global cell, high bit set where owned
+    const void *F;          // K*NE off-diagonal factors (FT), lexicographic per subdomain
+    const void *invd;       // NE (DT)
+    int NE;
+    const double *r;
+    double *z, *zext;
+    const int *mask;
+    unsigned long long *units;   // profiled launches: swept extended / owned cells
+    int variant, accumulate;
+    int kmap[32];
+};
+
+// LDS of a packed group of n extended cells: rv[n + 1], runs[n * cs], id[n]
+__host__ __device__ inline RowsLds packed_lds(size_t vt, size_t ft, size_t dt, int cs, size_t n) {
+    return rows_lds(vt, ft, dt, cs, 0, n);
+}
+
+template <typename FT, typename VT, typename DT, int BOX>
+__global__ void __launch_bounds__(256) k_ras_packed(PackArgs a) {
+    using S = RowStencil<BOX>;
+    constexpr int NL = S::NL, NU = S::NS - NL;
+    constexpr int PER = (int)(16 / sizeof(FT));
+    constexpr int NLP = row_lpad<BOX, FT>(), NUP = row_upad<BOX, FT>();
+    constexpr int CS = row_stride<BOX, FT>();
+    constexpr int RB = rows_unroll(BOX) / 2;
+    constexpr int CPT = 2;   // cells per thread per staging pass
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int g = blockIdx.x, tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const int b0 = a.gbox[g], b1 = a.gbox[g + 1];
+    const SubDev first = a.sub[b0];
+    if (a.mask && !a.mask[first.blk]) return;
+    const SubDev last = a.sub[b1 - 1];
+    const int e0 = first.fac_off, n = last.fac_off + last.next - e0;
+    const RowsLds L = packed_lds(sizeof(VT), sizeof(FT), sizeof(DT), CS, n);
+    VT *rv = reinterpret_cast<VT *>(smem + L.rv);
+    FT *cf = reinterpret_cast<FT *>(smem + L.cf);
+    DT *id = reinterpret_cast<DT *>(smem + L.id);
+    const FT *F = reinterpret_cast<const FT *>(a.F);
+    const DT *ID = reinterpret_cast<const DT *>(a.invd);
+    const int *e2g = a.ext2glob + e0;
+    // the lower runs and R_i^delta r (right-RAS: zero off the owned cells)
+    for (int c0 = tid; c0 < n; c0 += CPT * 256) {
+        FT v[CPT][NLP];
+        double rr[CPT];
+        int gg[CPT];
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = min(c0 + u * 256, n - 1);
+#pragma unroll
+            for (int q = 0; q < NLP; ++q) {
+                const int k = a.kmap[q];
+                const FT x = F[(size_t)max(k, 0) * a.NE + e0 + c];
+                v[u][q] = k >= 0 ? x : (FT)0;
+            }
+            gg[u] = e2g[c];
+            rr[u] = a.r[gg[u] & 0x7fffffff];
+        }
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = c0 + u * 256;
+            if (c < n) {
+#pragma unroll
+                for (int q = 0; q < NLP; ++q) cf[(size_t)c * CS + q] = v[u][q];
+                rv[c] = (VT)((a.variant == NKS_RIGHT_RAS && gg[u] >= 0) ? 0.0 : rr[u]);
+            }
+        }
+    }
+    __syncthreads();
+    const int2 ln = a.glane[(size_t)g * 64 + lane];
+    const SubDev sd = a.sub[ln.x];
+    const int T = a.gsteps[g];
+    if (wid == 0) {
+        packed_forward<FT, VT, DT, BOX, RB, CS, NLP>(sd, ln.y, T, rv + (sd.fac_off - e0), rv + n,
+                                                     cf + (size_t)(sd.fac_off - e0) * CS);
+    } else {
+        // the upper runs and 1/u_ii meanwhile
+        for (int c0 = tid - 64; c0 < n; c0 += CPT * 192) {
+            FT v[CPT][NUP];
+            DT d[CPT];
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = min(c0 + u * 192, n - 1);
+#pragma unroll
+                for (int q = 0; q < NUP; ++q) {
+                    const int k = a.kmap[NLP + q];
+                    const FT x = F[(size_t)max(k, 0) * a.NE + e0 + c];
+                    v[u][q] = k >= 0 ? x : (FT)0;
+                }
+                d[u] = ID[e0 + c];
+            }
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = c0 + u * 192;
+                if (c < n) {
+#pragma unroll
+                    for (int q = 0; q < NUP; ++q) cf[(size_t)c * CS + NLP + q] = v[u][q];
+                    id[c] = d[u];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (wid == 0)
+        packed_backward<FT, VT, DT, BOX, RB, CS, NLP>(sd, ln.y, T, rv + (sd.fac_off - e0), rv + n,
+                                                      cf + (size_t)(sd.fac_off - e0) * CS, id + (sd.fac_off - e0));
+    __syncthreads();
+    // write back: the owned cells (left-RAS), or every extended cell for the gather
+    unsigned long long own = 0;
+    for (int c = tid; c < n; c += 256) {
+        if (a.variant == NKS_LEFT_RAS) {
+            const int gg = e2g[c];
+            if (gg < 0) {
+                const size_t gi = (size_t)(gg & 0x7fffffff);
+                const double v = (double)rv[c];
+                a.z[gi] = a.accumulate ? a.z[gi] + v : v;
+                ++own;
+            }
+        } else {
+            a.zext[e0 + c] = (double)rv[c];
+        }
+    }
+    if (a.units) {
+        // spread over PROF_UNIT_SLOTS counter pairs, so the workgroups of a
+        // launch do not queue on one address
+        unsigned long long *u = a.units + 2 * (blockIdx.x % PROF_UNIT_SLOTS);
+        if (tid == 0) atomicAdd(u, (unsigned long long)n);
+        if (own) atomicAdd(u + 1, own);
     }
 }
 
@@ -2419,6 +2618,76 @@ static size_t rows_sweep_lds(const Level &V, int precision) {
     return rows_sweep_lds_t<uint16_t, float, float>(V);
 }
 
+// Groups for the packed sweep of a 2D level: consecutive boxes of one
+// block, their rows filling at most 64 lanes and their runs at most half
+// the LDS (two groups per CU).  Levels whose groups would average fewer
+// than two boxes keep one box per workgroup.
+template <int BOX, typename FT>
+static size_t packed_group_lds(int precision, size_t n) {
+    const size_t vt = precision == NKS_FP64 ? 8 : 4;
+    return packed_lds(vt, sizeof(FT), vt, row_stride<BOX, FT>(), n).total;
+}
+static size_t packed_group_lds(const Level &V, int precision, size_t n) {
+    if (precision == NKS_FP64)
+        return V.box == 0 ? packed_group_lds<0, double>(precision, n)
+                          : (V.box == 1 ? packed_group_lds<1, double>(precision, n) : packed_group_lds<2, double>(precision, n));
+    if (precision == NKS_FP32)
+        return V.box == 0 ? packed_group_lds<0, float>(precision, n)
+                          : (V.box == 1 ? packed_group_lds<1, float>(precision, n) : packed_group_lds<2, float>(precision, n));
+    return V.box == 0 ? packed_group_lds<0, uint16_t>(precision, n)
+                      : (V.box == 1 ? packed_group_lds<1, uint16_t>(precision, n)
+                                    : packed_group_lds<2, uint16_t>(precision, n));
+}
+
+static void build_packed(Level &V, int precision, int lds_bytes, Alloc *al, hipStream_t s) {
+    V.pk_groups = 0;
+    V.pk_max_n = 0;
+    if (!V.rows2d || V.nsub == 0) return;
+    const int LB = V.box == 0 ? RowStencil<0>::LB : (V.box == 1 ? RowStencil<1>::LB : RowStencil<2>::LB);
+    const size_t budget = (size_t)lds_bytes / 2;
+    std::vector<int2> lane;
+    std::vector<int> steps, first;
+    size_t max_n = 0;
+    int used = 64, blk = -1;
+    size_t n = 0;
+    for (int q = 0; q < V.nsub; ++q) {
+        const SubDev &sd = V.hsub[q];
+        if (sd.ez != 1 || sd.ey > 64) return;
+        if (q > 0 && sd.fac_off != V.hsub[q - 1].fac_off + V.hsub[q - 1].next) return;
+        if (used + sd.ey > 64 || sd.blk != blk || packed_group_lds(V, precision, n + sd.next) > budget) {
+            lane.resize(lane.size() + 64, int2{q, -1});
+            steps.push_back(0);
+            first.push_back(q);
+            used = 0;
+            n = 0;
+            blk = sd.blk;
+        }
+        const size_t g = steps.size() - 1;
+        for (int y = 0; y < sd.ey; ++y) lane[g * 64 + used + y] = int2{q, y};
+        used += sd.ey;
+        n += sd.next;
+        max_n = std::max(max_n, n);
+        steps[g] = std::max(steps[g], (sd.ex - 1) + LB * (sd.ey - 1) + 1);
+    }
+    const int G = (int)steps.size();
+    if (2 * G > V.nsub || packed_group_lds(V, precision, max_n) > (size_t)lds_bytes) return;
+    first.push_back(V.nsub);
+    std::vector<int> e2g(V.next_total, 0);
+    for (const SubDev &sd : V.hsub)
+        for (int y = 0; y < sd.ey; ++y)
+            for (int x = 0; x < sd.ex; ++x) {
+                const bool own = x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1;
+                const long gc = (long)sd.gorg + x + (long)sd.gnx * y;
+                e2g[sd.fac_off + x + sd.ex * y] = (int)gc | (own ? (int)0x80000000u : 0);
+            }
+    V.pk_lane.upload(al, lane, s);
+    V.pk_steps.upload(al, steps, s);
+    V.pk_box.upload(al, first, s);
+    V.pk_e2g.upload(al, e2g, s);
+    V.pk_groups = G;
+    V.pk_max_n = max_n;
+}
+
 void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     J = Jm;
     g = Jm->g;
@@ -2538,6 +2807,7 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     // widens a cell's run) takes the hyperplane kernels
     for (auto &V : lev)
         if (V->rows2d && rows_sweep_lds(*V, d.precision) > (size_t)lds_bytes) V->rows2d = false;
+    for (auto &V : lev) build_packed(*V, d.precision, lds_bytes, al, s);
     setup_persistent();
 }
 
@@ -2696,6 +2966,15 @@ static int rows_occupancy(const void *fn, int threads, size_t sh) {
     return std::max(nb, 1);
 }
 
+// AS / right-RAS: sum the boxes' extended values into z (left-RAS writes
+// the owned cells in the sweep)
+static void gather_ext(Ras &M, Level &V, double *z, const int *mask, bool accumulate) {
+    if (M.d.variant == NKS_LEFT_RAS) return;
+    k_ras_gather<<<nblk(V.spp->N, 256), 256, 0, M.g->s>>>(V.spp->blk.p, V.spp->B, V.spp->N, V.part.p, V.sub.p,
+                                                          V.zext.p, z, mask, accumulate ? 1 : 0);
+    KCHECK();
+}
+
 template <typename FT, typename VT, typename DT>
 static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int *mask, bool accumulate) {
     RowsArgs a{};
@@ -2738,16 +3017,48 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     // time, which lets more of its boxes sweep at once.
     const int occ4 = rows_occupancy((const void *)fn4, 256, sh4), occ1 = rows_occupancy((const void *)fn1, 64, sh4);
     const bool one = occ1 >= 2 * occ4 && V.nsub > M.n_cu * occ4;
+    const int occ = one ? rows_occupancy((const void *)fn1, 64, sh1) : occ4;
+    void (*fnp)(PackArgs) = V.box == 0 ? k_ras_packed<FT, VT, DT, 0>
+                                       : (V.box == 1 ? k_ras_packed<FT, VT, DT, 1> : k_ras_packed<FT, VT, DT, 2>);
+    const size_t shp = packed_lds(sizeof(VT), sizeof(FT), sizeof(DT), CS4, V.pk_max_n).total;
+    // A packed group sweeps about as long as one of its boxes (the sweep is
+    // bound by its step latency, measured on MI355X), so groups pay off when
+    // they take fewer rounds of workgroups over the CUs than single boxes.
+    auto rounds = [&](int wgs, int per_cu) { return (wgs + M.n_cu * per_cu - 1) / (M.n_cu * per_cu); };
+    if (V.pk_groups > 0 && rounds(V.pk_groups, rows_occupancy((const void *)fnp, 256, shp)) <= rounds(V.nsub, occ)) {
+        // small boxes: groups of them packed into one sweeping wavefront
+        PackArgs p{};
+        p.sub = V.sub.p;
+        p.glane = V.pk_lane.p;
+        p.gsteps = V.pk_steps.p;
+        p.gbox = V.pk_box.p;
+        p.ext2glob = V.pk_e2g.p;
+        p.F = a.F;
+        p.invd = a.invd;
+        p.NE = a.NE;
+        p.r = r;
+        p.z = z;
+        p.zext = a.zext;
+        p.mask = mask;
+        p.variant = a.variant;
+        p.accumulate = a.accumulate;
+        for (int q = 0; q < 32; ++q) p.kmap[q] = a.kmap[q];
+        set_lds((const void *)fnp, shp);
+        V.form = NKS_SWEEP_PACKED;
+        V.form_wgs = V.pk_groups;
+        launch_sweep("ras_apply", level_index(M, V), fnp, dim3(V.pk_groups), dim3(256), shp, M.g->s, p);
+        KCHECK();
+        gather_ext(M, V, z, mask, accumulate);
+        return;
+    }
     void (*fn)(RowsArgs) = one ? fn1 : fn4;
     const size_t sh = one ? sh1 : sh4;
     set_lds((const void *)fn, sh);
+    V.form = one ? NKS_SWEEP_ROWS1 : NKS_SWEEP_ROWS4;
+    V.form_wgs = V.nsub;
     launch_sweep("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(one ? 64 : 256), sh, M.g->s, a);
     KCHECK();
-    if (M.d.variant != NKS_LEFT_RAS) {
-        k_ras_gather<<<nblk(V.spp->N, 256), 256, 0, M.g->s>>>(V.spp->blk.p, V.spp->B, V.spp->N, V.part.p,
-                                                              V.sub.p, V.zext.p, z, mask, accumulate ? 1 : 0);
-        KCHECK();
-    }
+    gather_ext(M, V, z, mask, accumulate);
 }
 
 // LDS of the 3D row sweep for boxes of n cells: rv[n + 1], the
@@ -2792,13 +3103,11 @@ static void launch_rows3d(Ras &M, Level &V, const double *r, double *z, const in
     const size_t sh = rows3d_lds(M.d.precision, V.max_next);
     void (*fn)(Rows3Args) = V.rows3d_multi ? k_ras_rows3d<FT, VT, DT, true> : k_ras_rows3d<FT, VT, DT, false>;
     set_lds((const void *)fn, sh);
+    V.form = NKS_SWEEP_ROWS3D;
+    V.form_wgs = V.nsub;
     launch_sweep("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(256), sh, M.g->s, a);
     KCHECK();
-    if (M.d.variant != NKS_LEFT_RAS) {
-        k_ras_gather<<<nblk(V.spp->N, 256), 256, 0, M.g->s>>>(V.spp->blk.p, V.spp->B, V.spp->N, V.part.p,
-                                                              V.sub.p, V.zext.p, z, mask, accumulate ? 1 : 0);
-        KCHECK();
-    }
+    gather_ext(M, V, z, mask, accumulate);
 }
 
 template <typename FT, typename VT, typename DT>
@@ -2862,6 +3171,8 @@ static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, 
     // stencils have many short hyperplanes, where one wavefront's barriers
     // are the cheap ones
     const int bs = V.max_lvl <= 64 ? 64 : (V.max_lvl <= 128 ? 128 : 256);
+    V.form = NKS_SWEEP_HYPERPLANE;
+    V.form_wgs = V.nsub;
     {
         if (seven)
             launch_sweep("ras_apply", level_index(M, V), k_ras_apply<FT, VT, DT, 3>, dim3(V.nsub), dim3(bs), sh, M.g->s, a);
@@ -2869,11 +3180,7 @@ static void launch_apply(Ras &M, Level &V, const TileDims &td, const double *r, 
             launch_sweep("ras_apply", level_index(M, V), k_ras_apply<FT, VT, DT, 0>, dim3(V.nsub), dim3(bs), sh, M.g->s, a);
         KCHECK();
     }
-    if (M.d.variant != NKS_LEFT_RAS) {
-        k_ras_gather<<<nblk(V.spp->N, 256), 256, 0, M.g->s>>>(V.spp->blk.p, V.spp->B, V.spp->N, V.part.p,
-                                                              V.sub.p, V.zext.p, z, mask, accumulate ? 1 : 0);
-        KCHECK();
-    }
+    gather_ext(M, V, z, mask, accumulate);
 }
 
 void Ras::apply_level(int l, const double *r, double *z, const int *mask, bool accumulate) {
