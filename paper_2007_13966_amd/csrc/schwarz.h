@@ -108,6 +108,9 @@ struct Level {
     std::unique_ptr<Grid> cg;    // rediscretised coarse levels: this level's upscaled grid
     DBuf<double> cstate;         // and the coarsened state its Jacobian is taken at
     int rap_R = 0;
+    // 2D levels: column-wise Galerkin product, windows of at most
+    // rap_wx x rap_wy fine cells (0: the general kernel)
+    int rap_wx = 0, rap_wy = 0;
     // work vectors
     DBuf<double> r, t, bc, xc;
 };

@@ -2578,6 +2578,133 @@ __global__ void __launch_bounds__(64 * W) k_rap(XferArgs a, const double *Af, in
     }
 }
 
+// Galerkin A_c = P^T A P on 2D levels, one wavefront per coarse column J:
+// first AP(f, J) = sum_k A(f, f + o_k) P(f + o_k, J) over the window of
+// fine cells f that reach J's interpolation support, then every entry of
+// the column, A_c(I, J) = sum_f P(f, I) AP(f, J) for I = J - o over the
+// coarse stencil offsets o, with the tensor weights
+// P(f, I) = p_x(f_x, I_x) p_y(f_y, I_y) summed one direction at a time:
+// U(o_x, f_y) = sum_{f_x} p_x(f_x, J_x - o_x) AP(f_x, f_y), then
+// A_c(J - o, J) = sum_{f_y} p_y(f_y, J_y - o_y) U(o_x, f_y).  Every sum runs
+// in a fixed order, so the product is deterministic.  Each entry of A_c is
+// written by the wavefront of its column; entries whose column lies outside
+// the block stay as the caller zeroed them.
+struct Rap2Lds {
+    int wxg, wyg, wx, wy, per;   // table extents and doubles per wavefront
+};
+__host__ __device__ inline Rap2Lds rap2_lds(int wx, int wy, int Rf, int Rc) {
+    Rap2Lds L;
+    L.wx = wx;
+    L.wy = wy;
+    L.wxg = wx + 2 * Rf;
+    L.wyg = wy + 2 * Rf;
+    const int nc = 2 * Rc + 1;
+    L.per = L.wxg + L.wyg + nc * wx + nc * wy + wx * wy + nc * wy;
+    return L;
+}
+
+template <int W>
+__global__ void __launch_bounds__(64 * W) k_rap2d(XferArgs a, const double *Af, int Kf, const int8_t *offf, int Rf,
+                                                  double *Ac, int Kc, const int8_t *offc, int Rc, int wxm, int wym) {
+    extern __shared__ double rap2_s[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const Rap2Lds L = rap2_lds(wxm, wym, Rf, Rc);
+    const int nc = 2 * Rc + 1;
+    double *tJx = rap2_s + (size_t)w * L.per;       // p_x(g_x, J_x), g_x from wx0 - Rf
+    double *tJy = tJx + L.wxg;
+    double *tIx = tJy + L.wyg;                      // [o_x + Rc][f_x - wx0]: p_x(f_x, J_x - o_x)
+    double *tIy = tIx + nc * L.wx;
+    double *AP = tIy + nc * L.wy;                   // [f_y - wy0][f_x - wx0]
+    double *U = AP + L.wx * L.wy;                   // [o_x + Rc][f_y - wy0]
+    const int J = blockIdx.x * W + w;
+    const bool on = J < a.Nc;
+    int b = 0, Jx = 0, Jy = 0, wx0 = 0, wy0 = 0, WX = 0, WY = 0;
+    Blk cb{}, fb{};
+    if (on) {
+        b = find_blk(a.cblk, a.B, J);
+        cb = a.cblk[b];
+        fb = a.fblk[b];
+        const int l = J - cb.off;
+        Jx = l % cb.nx;
+        Jy = l / cb.nx;
+        const int cx = a.coff[0][b] + Jx, cy = a.coff[1][b] + Jy;
+        // J's fine support in each direction is a run of consecutive cells
+        const int xlo = a.ci[0][cx * a.cs[0]], xhi = a.ci[0][cx * a.cs[0] + a.ccnt[0][cx] - 1];
+        const int ylo = a.ci[1][cy * a.cs[1]], yhi = a.ci[1][cy * a.cs[1] + a.ccnt[1][cy] - 1];
+        wx0 = max(0, xlo - Rf);
+        wy0 = max(0, ylo - Rf);
+        WX = min(fb.nx, xhi + Rf + 1) - wx0;
+        WY = min(fb.ny, yhi + Rf + 1) - wy0;
+    }
+    // tables: zero, then scatter the interpolation columns
+    for (int t = lane; t < L.wxg + L.wyg + nc * (L.wx + L.wy); t += 64) tJx[t] = 0.0;
+    __syncthreads();
+    if (on) {
+        const int cx = a.coff[0][b] + Jx, cy = a.coff[1][b] + Jy;
+        for (int q = lane; q < a.ccnt[0][cx]; q += 64)
+            tJx[a.ci[0][cx * a.cs[0] + q] - (wx0 - Rf)] = a.cw[0][cx * a.cs[0] + q];
+        for (int q = lane; q < a.ccnt[1][cy]; q += 64)
+            tJy[a.ci[1][cy * a.cs[1] + q] - (wy0 - Rf)] = a.cw[1][cy * a.cs[1] + q];
+        // one (column, entry) pair per lane, every load of a pass in flight at once
+        for (int t = lane; t < nc * (a.cs[0] + a.cs[1]); t += 64) {
+            const int d = t < nc * a.cs[0] ? 0 : 1;
+            const int u = d == 0 ? t : t - nc * a.cs[0];
+            const int o = u / a.cs[d], q = u % a.cs[d];
+            const int Ic = (d == 0 ? Jx : Jy) - (o - Rc), n = d == 0 ? cb.nx : cb.ny;
+            if (Ic < 0 || Ic >= n) continue;
+            const int c = a.coff[d][b] + Ic;
+            if (q >= a.ccnt[d][c]) continue;
+            const int fi = a.ci[d][c * a.cs[d] + q] - (d == 0 ? wx0 : wy0);
+            if (fi >= 0 && fi < (d == 0 ? WX : WY)) (d == 0 ? tIx + o * L.wx : tIy + o * L.wy)[fi] = a.cw[d][c * a.cs[d] + q];
+        }
+    }
+    __syncthreads();
+    if (on) {
+        // AP over the window.  A's coefficients towards neighbours outside
+        // the block are zero and the J tables are zero off J's support (which
+        // lies inside the block), so no term needs a bounds test: the Kf
+        // loads of a cell go out together.
+        constexpr int KM = 25;
+        for (int t = lane; t < WX * WY; t += 64) {
+            const int ux = t % WX, uy = t / WX;
+            const int fx = wx0 + ux, fy = wy0 + uy;
+            const size_t f = (size_t)fb.off + fx + (size_t)fb.nx * fy;
+            double av[KM];
+#pragma unroll
+            for (int k = 0; k < KM; ++k) av[k] = k < Kf ? Af[(size_t)k * a.Nf + f] : 0.0;
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                if (k < Kf) {
+                    const int gx = fx + offf[3 * k], gy = fy + offf[3 * k + 1];
+                    s += av[k] * (tJx[gx - (wx0 - Rf)] * tJy[gy - (wy0 - Rf)]);
+                }
+            }
+            AP[uy * L.wx + ux] = s;
+        }
+    }
+    __syncthreads();
+    if (on) {
+        for (int t = lane; t < nc * WY; t += 64) {
+            const int ox = t / WY, uy = t % WY;
+            double s = 0.0;
+            for (int ux = 0; ux < WX; ++ux) s += tIx[ox * L.wx + ux] * AP[uy * L.wx + ux];
+            U[ox * L.wy + uy] = s;
+        }
+    }
+    __syncthreads();
+    if (on) {
+        for (int k = lane; k < Kc; k += 64) {
+            const int ox = offc[3 * k], oy = offc[3 * k + 1];
+            const int Ix = Jx - ox, Iy = Jy - oy;
+            if (Ix < 0 || Ix >= cb.nx || Iy < 0 || Iy >= cb.ny) continue;
+            double s = 0.0;
+            for (int uy = 0; uy < WY; ++uy) s += tIy[(oy + Rc) * L.wy + uy] * U[(ox + Rc) * L.wy + uy];
+            Ac[(size_t)k * a.Nc + cb.off + Ix + (size_t)cb.nx * Iy] = s;
+        }
+    }
+}
+
 __global__ void k_fill(int N, double v, double *x) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < N) x[i] = v;
@@ -2761,6 +2888,24 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
             slot[(C.own.st.off[3 * k] + Rc) + S * ((C.own.st.off[3 * k + 1] + Rc) + S * (C.own.st.off[3 * k + 2] + Rc))] = k;
         F.rap_slot.upload(al, slot, s);
         F.rap_R = Rc;
+        // 2D: windows of the column-wise product (J's support widened by the
+        // fine stencil's reach)
+        bool flat = fs.R >= 0;
+        for (const Blk &k : F.spp->hblk) flat = flat && k.nz == 1;
+        for (int k = 0; k < fs.K; ++k) flat = flat && fs.off[3 * k + 2] == 0;
+        F.rap_wx = F.rap_wy = 0;
+        if (flat) {
+            for (int d = 0; d < 2; ++d) {
+                const Interp1 &ip = F.ip[d];
+                int wmax = 0;
+                for (size_t c = 0; c < ip.ccnt.size(); ++c) {
+                    if (ip.ccnt[c] < 1) continue;
+                    const int lo = ip.ci[c * ip.cs], hi = ip.ci[c * ip.cs + ip.ccnt[c] - 1];
+                    wmax = std::max(wmax, hi - lo + 1 + 2 * fs.R);
+                }
+                (d == 0 ? F.rap_wx : F.rap_wy) = wmax;
+            }
+        }
     }
     // the same box grid on every level: box counts per reservoir from the finest level
     std::vector<std::array<int, 3>> boxes;
@@ -2827,6 +2972,23 @@ void Ras::factor(bool ilu) {
             launch_coarsen_mean(fg, *V.cg, pf, V.cstate.p);
             launch_props(*V.cg, V.cstate.p);
             launch_flux(*V.cg, V.cstate.p, J->dt, J->order, nullptr, V.own.coef.p);
+        } else if (l > 0 && lev[l - 1]->rap_wx > 0 && lev[l - 1]->A->st.K <= 25 &&
+                   (size_t)rap2_lds(lev[l - 1]->rap_wx, lev[l - 1]->rap_wy, lev[l - 1]->A->st.R, lev[l - 1]->rap_R).per *
+                           sizeof(double) <= (size_t)lds_bytes) {
+            Level &F = *lev[l - 1];
+            XferArgs a = xfer_args(F, V, nullptr);
+            const int Kc = V.own.st.K, Nc = V.spp->N;
+            const size_t per = (size_t)rap2_lds(F.rap_wx, F.rap_wy, F.A->st.R, F.rap_R).per * sizeof(double);
+            const int W = 4 * per <= (size_t)lds_bytes ? 4 : (2 * per <= (size_t)lds_bytes ? 2 : 1);
+            k_fill<<<nblk((int)std::min<size_t>((size_t)Kc * Nc, INT32_MAX), 256), 256, 0, s>>>(Kc * Nc, 0.0,
+                                                                                               V.own.coef.p);
+            KCHECK();
+            void (*fr)(XferArgs, const double *, int, const int8_t *, int, double *, int, const int8_t *, int, int,
+                       int) = W == 4 ? k_rap2d<4> : (W == 2 ? k_rap2d<2> : k_rap2d<1>);
+            set_lds((const void *)fr, W * per);
+            launch_timed("rap", l, fr, dim3(nblk(Nc, W)), dim3(64 * W), W * per, s, a, F.A->coef.p, F.A->st.K,
+                         F.A->st.doff.p, F.A->st.R, V.own.coef.p, Kc, V.own.st.doff.p, F.rap_R, F.rap_wx, F.rap_wy);
+            KCHECK();
         } else if (l > 0) {
             Level &F = *lev[l - 1];
             XferArgs a = xfer_args(F, V, nullptr);
