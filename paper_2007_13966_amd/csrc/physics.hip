@@ -195,10 +195,13 @@ struct FluxArgs {
 // mobility from the upwind side; Neumann: scaled mass flux m_i q^N A through
 // the face (q^N along the outward normal).  Adds the outward flux to Fi, its
 // p_i derivative to diag and, for dF/dlnK, the part linear in K_i to dlk.
-__device__ __noinline__ void boundary_faces(const FluxArgs &A, const CellPos &c, int i, double pi, double mi,
+// Inlined: a call would take the argument block by reference, which puts a
+// copy of it in every lane's private memory.
+__device__ __forceinline__ void boundary_faces(const FluxArgs &A, const CellPos &c, int i, double pi, double mi,
                                             double dmi, double &Fi, double &diag, double &dlk) {
     const double dx = A.geo[3 * c.b], dy = A.geo[3 * c.b + 1], dz = A.geo[3 * c.b + 2];
     const bool at[6] = {c.x == 0, c.x + 1 == c.nx, c.y == 0, c.y + 1 == c.ny, c.z == 0, c.z + 1 == c.nz};
+#pragma unroll
     for (int f = 0; f < 6; ++f) {
         const int t = A.bct[6 * c.b + f];
         if (t == 0 || !at[f]) continue;
