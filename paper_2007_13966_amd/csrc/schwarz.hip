@@ -1613,9 +1613,191 @@ struct PackArgs {
     int kmap[32];
 };
 
-// LDS of a packed group of n extended cells: rv[n + 1], runs[n * cs], id[n]
-__host__ __device__ inline RowsLds packed_lds(size_t vt, size_t ft, size_t dt, int cs, size_t n) {
-    return rows_lds(vt, ft, dt, cs, 0, n);
+// LDS of a packed group of n extended cells: rv[n + 1], runs[n * cs], id[n],
+// each with guard cells on both sides for the blocks of steps that straddle
+// the group's first or last cell
+__host__ __device__ constexpr int packed_pad(int box) { return rows_unroll(box) / 2; }
+__host__ __device__ inline RowsLds packed_lds(size_t vt, size_t ft, size_t dt, int cs, int box, size_t n) {
+    return rows_lds(vt, ft, dt, cs, packed_pad(box), n);
+}
+
+// The packed sweeps on LDS-resident runs.  Lane (box, row y) steps through
+// the group's cells cg + t (forward; cg = the box's first cell in the group
+// plus y (ex - LB)) or cgb - t (backward).  A block of RB steps is addressed
+// from one base cell, clamped into the guard cells when the whole block lies
+// outside the group (then none of its steps is active), so every load and
+// store of a step takes a constant offset from that base; masked steps
+// store into the guard cells past the group's end, which no active step
+// reads.  The rest follows packed_forward / packed_backward.
+template <typename FT, typename VT, typename DT, int BOX, int RB, int CS, int UP>
+__device__ __forceinline__ void lds_forward(int n, int cg, int tlo, int ex, bool fw, int T, VT *rv, const FT *cf) {
+    using S = RowStencil<BOX>;
+    constexpr int NL = S::NL, LB = S::LB;
+    constexpr int NLP = row_lpad<BOX, FT>();
+    constexpr int RU = rows_unroll(BOX), NB = RU / RB;
+    static_assert(NB % 2 == 0 && NB * RB == RU, "an even number of prefetch blocks per ring cycle");
+    VT *const dum = rv + n;
+    VT r0[RU], r1[RU], r2[RU];
+#pragma unroll
+    for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
+    VT coA[RB][NLP], rinA[RB], coB[RB][NLP], rinB[RB];
+    int cbA, cbB;
+    bool aaA[RB], aaB[RB];
+    auto load = [&](int tb, VT(&co)[RB][NLP], VT(&rin)[RB], int &cb0, bool(&aa)[RB]) {
+        cb0 = min(max(cg + tb, -RB), n);
+        const FT *cfb = cf + cb0 * CS;
+        const VT *rvb = rv + cb0;
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            aa[u] = (unsigned)(tb + u - tlo) < (unsigned)ex;
+            load_run<FT, VT, NLP>(cfb + u * CS, co[u]);
+            rin[u] = rvb[u];
+        }
+    };
+    // the terms of step u on outputs at least two steps old (available
+    // before step u - 1 ends), subtracted from R_i^delta r
+    auto older = [&](int uu, const VT(&co)[NLP], VT rin) {
+        VT v = rin;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int h = -(S::DX[q] + LB * S::DY[q]) - 1;
+            if (h == 0) continue;
+            const int slot = (uu - 1 - h + 2 * RU) % RU;
+            const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == -1 ? r1[slot] : r2[slot]);
+            v -= co[q] * val;
+        }
+        return v;
+    };
+    auto step = [&](int b0, VT(&co)[RB][NLP], VT(&rin)[RB], int cb0, bool(&aa)[RB]) {
+        VT outv[RB], old[RB];
+        old[0] = older(b0, co[0], rin[0]);
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            const int uu = b0 + u;
+            // the next step's older terms are independent of this step: the
+            // two chains interleave
+            if (u + 1 < RB) old[u + 1] = older(uu + 1, co[u + 1], rin[u + 1]);
+            VT v = old[u];
+#pragma unroll
+            for (int pass = 1; pass < 3; ++pass) {
+#pragma unroll
+                for (int q = 0; q < NL; ++q) {
+                    const int h = -(S::DX[q] + LB * S::DY[q]) - 1;
+                    if (pass != (h != 0 ? 0 : (S::DY[q] == 0 ? 1 : 2))) continue;
+                    const int slot = (uu - 1 - h + 2 * RU) % RU;
+                    const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == -1 ? r1[slot] : r2[slot]);
+                    v -= co[u][q] * val;
+                }
+            }
+            const VT out = aa[u] ? v : (VT)0;
+            outv[u] = out;
+            r0[uu] = out;
+            const VT s1 = lane_shr(fw ? out : (VT)0);
+            r1[uu] = s1;
+            r2[uu] = lane_shr(fw ? s1 : (VT)0);
+        }
+        VT *const rvb = rv + cb0;
+#pragma unroll
+        for (int u = 0; u < RB; ++u) (aa[u] ? rvb : dum)[u] = outv[u];
+    };
+    load(0, coA, rinA, cbA, aaA);
+    for (int t0 = 0; t0 < T; t0 += RU) {
+#pragma unroll
+        for (int q = 0; q < NB; q += 2) {
+            load(t0 + (q + 1) * RB, coB, rinB, cbB, aaB);
+            __builtin_amdgcn_sched_barrier(0);
+            step(q * RB, coA, rinA, cbA, aaA);
+            load(t0 + (q + 2) * RB, coA, rinA, cbA, aaA);
+            __builtin_amdgcn_sched_barrier(0);
+            step((q + 1) * RB, coB, rinB, cbB, aaB);
+        }
+    }
+}
+
+template <typename FT, typename VT, typename DT, int BOX, int RB, int CS, int UP>
+__device__ __forceinline__ void lds_backward(int n, int cgb, int tlob, int ex, bool bw, int T, VT *rv, const FT *cf,
+                                             const DT *id) {
+    using S = RowStencil<BOX>;
+    constexpr int NS = S::NS, NL = S::NL, LB = S::LB;
+    constexpr int NUP = row_upad<BOX, FT>();
+    constexpr int RU = rows_unroll(BOX), NB = RU / RB;
+    static_assert(NB % 2 == 0 && NB * RB == RU, "an even number of prefetch blocks per ring cycle");
+    VT *const dum = rv + n;
+    VT r0[RU], r1[RU], r2[RU];
+#pragma unroll
+    for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
+    VT coA[RB][NUP], rinA[RB], dgA[RB], coB[RB][NUP], rinB[RB], dgB[RB];
+    int clA, clB;
+    bool aaA[RB], aaB[RB];
+    // block of steps tb .. tb + RB - 1 at cells cgb - tb - u, addressed from
+    // its lowest cell
+    auto load = [&](int tb, VT(&co)[RB][NUP], VT(&rin)[RB], VT(&dg)[RB], int &cl, bool(&aa)[RB]) {
+        cl = min(max(cgb - tb - (RB - 1), -RB), n);
+        const FT *cfb = cf + cl * CS + UP;
+        const VT *rvb = rv + cl;
+        const DT *idb = id + cl;
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            aa[u] = (unsigned)(tb + u - tlob) < (unsigned)ex;
+            load_run<FT, VT, NUP>(cfb + (RB - 1 - u) * CS, co[u]);
+            rin[u] = rvb[RB - 1 - u];
+            dg[u] = (VT)idb[RB - 1 - u];
+        }
+    };
+    auto older = [&](int uu, const VT(&co)[NUP], VT rin) {
+        VT v = rin;
+#pragma unroll
+        for (int q = NL; q < NS; ++q) {
+            const int h = S::DX[q] + LB * S::DY[q] - 1;
+            if (h == 0) continue;
+            const int slot = (uu - 1 - h + 2 * RU) % RU;
+            const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == 1 ? r1[slot] : r2[slot]);
+            v -= co[q - NL] * val;
+        }
+        return v;
+    };
+    auto step = [&](int b0, VT(&co)[RB][NUP], VT(&rin)[RB], VT(&dg)[RB], int cl, bool(&aa)[RB]) {
+        VT outv[RB], old[RB];
+        old[0] = older(b0, co[0], rin[0]);
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            const int uu = b0 + u;
+            if (u + 1 < RB) old[u + 1] = older(uu + 1, co[u + 1], rin[u + 1]);
+            VT v = old[u];
+#pragma unroll
+            for (int pass = 1; pass < 3; ++pass) {
+#pragma unroll
+                for (int q = NL; q < NS; ++q) {
+                    const int h = S::DX[q] + LB * S::DY[q] - 1;
+                    if (pass != (h != 0 ? 0 : (S::DY[q] == 0 ? 1 : 2))) continue;
+                    const int slot = (uu - 1 - h + 2 * RU) % RU;
+                    const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == 1 ? r1[slot] : r2[slot]);
+                    v -= co[u][q - NL] * val;
+                }
+            }
+            const VT out = aa[u] ? v * dg[u] : (VT)0;
+            outv[u] = out;
+            r0[uu] = out;
+            const VT s1 = lane_shl(bw ? out : (VT)0);
+            r1[uu] = s1;
+            r2[uu] = lane_shl(bw ? s1 : (VT)0);
+        }
+        VT *const rvb = rv + cl;
+#pragma unroll
+        for (int u = 0; u < RB; ++u) (aa[u] ? rvb : dum)[RB - 1 - u] = outv[u];
+    };
+    load(0, coA, rinA, dgA, clA, aaA);
+    for (int t0 = 0; t0 < T; t0 += RU) {
+#pragma unroll
+        for (int q = 0; q < NB; q += 2) {
+            load(t0 + (q + 1) * RB, coB, rinB, dgB, clB, aaB);
+            __builtin_amdgcn_sched_barrier(0);
+            step(q * RB, coA, rinA, dgA, clA, aaA);
+            load(t0 + (q + 2) * RB, coA, rinA, dgA, clA, aaA);
+            __builtin_amdgcn_sched_barrier(0);
+            step((q + 1) * RB, coB, rinB, dgB, clB, aaB);
+        }
+    }
 }
 
 template <typename FT, typename VT, typename DT, int BOX>
@@ -1634,10 +1816,11 @@ __global__ void __launch_bounds__(256) k_ras_packed(PackArgs a) {
     if (a.mask && !a.mask[first.blk]) return;
     const SubDev last = a.sub[b1 - 1];
     const int e0 = first.fac_off, n = last.fac_off + last.next - e0;
-    const RowsLds L = packed_lds(sizeof(VT), sizeof(FT), sizeof(DT), CS, n);
-    VT *rv = reinterpret_cast<VT *>(smem + L.rv);
-    FT *cf = reinterpret_cast<FT *>(smem + L.cf);
-    DT *id = reinterpret_cast<DT *>(smem + L.id);
+    constexpr int PAD = packed_pad(BOX);
+    const RowsLds L = packed_lds(sizeof(VT), sizeof(FT), sizeof(DT), CS, BOX, n);
+    VT *rv = reinterpret_cast<VT *>(smem + L.rv) + PAD;
+    FT *cf = reinterpret_cast<FT *>(smem + L.cf) + PAD * CS;
+    DT *id = reinterpret_cast<DT *>(smem + L.id) + PAD;
     const FT *F = reinterpret_cast<const FT *>(a.F);
     const DT *ID = reinterpret_cast<const DT *>(a.invd);
     const int *e2g = a.ext2glob + e0;
@@ -1672,9 +1855,16 @@ __global__ void __launch_bounds__(256) k_ras_packed(PackArgs a) {
     const int2 ln = a.glane[(size_t)g * 64 + lane];
     const SubDev sd = a.sub[ln.x];
     const int T = a.gsteps[g];
+    // this lane's row: first group cell of its forward and backward steps,
+    // the step at which its row starts, whether the neighbouring lane holds
+    // the next (forward) or previous (backward) row of the same box
+    const bool on = ln.y >= 0;
+    const int ye = on ? ln.y : 0, ex = sd.ex, ey = sd.ey;
+    const int Ts = (ex - 1) + S::LB * (ey - 1) + 1;
+    const int cg = (sd.fac_off - e0) + ye * (ex - S::LB);
+    const int tlo = on ? S::LB * ye : (1 << 28), tlob = on ? Ts - S::LB * ye - ex : (1 << 28);
     if (wid == 0) {
-        packed_forward<FT, VT, DT, BOX, RB, CS, NLP>(sd, ln.y, T, rv + (sd.fac_off - e0), rv + n,
-                                                     cf + (size_t)(sd.fac_off - e0) * CS);
+        lds_forward<FT, VT, DT, BOX, RB, CS, NLP>(n, cg, tlo, ex, on && ye + 1 < ey, T, rv, cf);
     } else {
         // the upper runs and 1/u_ii meanwhile
         for (int c0 = tid - 64; c0 < n; c0 += CPT * 192) {
@@ -1704,8 +1894,7 @@ __global__ void __launch_bounds__(256) k_ras_packed(PackArgs a) {
     }
     __syncthreads();
     if (wid == 0)
-        packed_backward<FT, VT, DT, BOX, RB, CS, NLP>(sd, ln.y, T, rv + (sd.fac_off - e0), rv + n,
-                                                      cf + (size_t)(sd.fac_off - e0) * CS, id + (sd.fac_off - e0));
+        lds_backward<FT, VT, DT, BOX, RB, CS, NLP>(n, cg + Ts - 1, tlob, ex, on && ye >= 1, T, rv, cf, id);
     __syncthreads();
     // write back: the owned cells (left-RAS), or every extended cell for the gather
     unsigned long long own = 0;
@@ -2752,7 +2941,7 @@ static size_t rows_sweep_lds(const Level &V, int precision) {
 template <int BOX, typename FT>
 static size_t packed_group_lds(int precision, size_t n) {
     const size_t vt = precision == NKS_FP64 ? 8 : 4;
-    return packed_lds(vt, sizeof(FT), vt, row_stride<BOX, FT>(), n).total;
+    return packed_lds(vt, sizeof(FT), vt, row_stride<BOX, FT>(), BOX, n).total;
 }
 static size_t packed_group_lds(const Level &V, int precision, size_t n) {
     if (precision == NKS_FP64)
@@ -3182,7 +3371,7 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
     const int occ = one ? rows_occupancy((const void *)fn1, 64, sh1) : occ4;
     void (*fnp)(PackArgs) = V.box == 0 ? k_ras_packed<FT, VT, DT, 0>
                                        : (V.box == 1 ? k_ras_packed<FT, VT, DT, 1> : k_ras_packed<FT, VT, DT, 2>);
-    const size_t shp = packed_lds(sizeof(VT), sizeof(FT), sizeof(DT), CS4, V.pk_max_n).total;
+    const size_t shp = packed_lds(sizeof(VT), sizeof(FT), sizeof(DT), CS4, V.box, V.pk_max_n).total;
     // A packed group sweeps about as long as one of its boxes (the sweep is
     // bound by its step latency, measured on MI355X), so groups pay off when
     // they take fewer rounds of workgroups over the CUs than single boxes.
