@@ -1208,17 +1208,33 @@ __global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
                 rin[u] = rvb[u];
             }
         };
-        // forward: y_i = r_i - sum_{lower} L_ik y_k
+        // forward: y_i = r_i - sum_{lower} L_ik y_k.  The terms on outputs at
+        // least two steps old do not wait for the previous step: the next
+        // step's are summed while this step's dependent chain runs.
+        auto older = [&](int uu, const VT(&co)[NLP], VT rin) {
+            VT v = rin;
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                const int h = -(S::DX[q] + LB * S::DY[q]) - 1;
+                if (h == 0) continue;
+                const int slot = (uu - 1 - h + 2 * RU) % RU;
+                const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == -1 ? r1[slot] : r2[slot]);
+                v -= co[q] * val;
+            }
+            return v;
+        };
         auto step = [&](int b0, VT(&co)[RB][NLP], VT(&rin)[RB], int(&cc)[RB], bool(&aa)[RB]) {
-            VT outv[RB];
+            VT outv[RB], old[RB];
+            old[0] = older(b0, co[0], rin[0]);
 #pragma unroll
             for (int u = 0; u < RB; ++u) {
                 const int uu = b0 + u;
-                VT v = rin[u];
-                // older terms first, then the one-step-old terms of this lane,
-                // and last those that wait for a lane shift (the critical path)
+                if (u + 1 < RB) old[u + 1] = older(uu + 1, co[u + 1], rin[u + 1]);
+                VT v = old[u];
+                // the one-step-old terms of this lane, then those that wait
+                // for a lane shift (the critical path)
 #pragma unroll
-                for (int pass = 0; pass < 3; ++pass) {
+                for (int pass = 1; pass < 3; ++pass) {
 #pragma unroll
                     for (int q = 0; q < NL; ++q) {
                         const int h = -(S::DX[q] + LB * S::DY[q]) - 1;
@@ -1327,14 +1343,28 @@ __global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
                 dg[u] = (VT)idb[RB - 1 - u];
             }
         };
+        auto older = [&](int uu, const VT(&co)[NUP], VT rin) {
+            VT v = rin;
+#pragma unroll
+            for (int q = NL; q < NS; ++q) {
+                const int h = S::DX[q] + LB * S::DY[q] - 1;
+                if (h == 0) continue;
+                const int slot = (uu - 1 - h + 2 * RU) % RU;
+                const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == 1 ? r1[slot] : r2[slot]);
+                v -= co[q - NL] * val;
+            }
+            return v;
+        };
         auto step = [&](int b0, VT(&co)[RB][NUP], VT(&rin)[RB], VT(&dg)[RB], int(&cc)[RB], bool(&aa)[RB]) {
-            VT outv[RB];
+            VT outv[RB], old[RB];
+            old[0] = older(b0, co[0], rin[0]);
 #pragma unroll
             for (int u = 0; u < RB; ++u) {
                 const int uu = b0 + u;
-                VT v = rin[u];
+                if (u + 1 < RB) old[u + 1] = older(uu + 1, co[u + 1], rin[u + 1]);
+                VT v = old[u];
 #pragma unroll
-                for (int pass = 0; pass < 3; ++pass) {
+                for (int pass = 1; pass < 3; ++pass) {
 #pragma unroll
                     for (int q = NL; q < NS; ++q) {
                         const int h = S::DX[q] + LB * S::DY[q] - 1;
