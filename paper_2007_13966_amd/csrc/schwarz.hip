@@ -2672,7 +2672,10 @@ struct XferArgs {
     const int *mask;
 };
 
-// r_c = P^T r_f (gather over the fine support of each coarse cell)
+// r_c = P^T r_f (gather over the fine support of each coarse cell).  The
+// x list of the coarse column sits in registers (up to XM entries) so that a
+// fine row's loads go out together; longer lists take the plain loops.
+constexpr int XM = 16;
 __global__ void k_restrict(XferArgs a, const double *rf, double *rc) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= a.Nc) return;
@@ -2682,14 +2685,42 @@ __global__ void k_restrict(XferArgs a, const double *rf, double *rc) {
     const int l = I - cb.off;
     const int X = l % cb.nx, Y = (l / cb.nx) % cb.ny, Z = l / (cb.nx * cb.ny);
     const int cx = a.coff[0][b] + X, cy = a.coff[1][b] + Y, cz = a.coff[2][b] + Z;
+    const int nqx = a.ccnt[0][cx];
     double s = 0.0;
+    if (nqx <= XM) {
+        int fxs[XM];
+        double wxs[XM];
+#pragma unroll
+        for (int q = 0; q < XM; ++q) {
+            const int qq = max(0, min(q, nqx - 1));
+            fxs[q] = a.ci[0][cx * a.cs[0] + qq];
+            wxs[q] = q < nqx ? a.cw[0][cx * a.cs[0] + qq] : 0.0;
+        }
+        for (int qz = 0; qz < a.ccnt[2][cz]; ++qz) {
+            const int fz = a.ci[2][cz * a.cs[2] + qz];
+            const double wz = a.cw[2][cz * a.cs[2] + qz];
+            for (int qy = 0; qy < a.ccnt[1][cy]; ++qy) {
+                const int fy = a.ci[1][cy * a.cs[1] + qy];
+                const double wyz = a.cw[1][cy * a.cs[1] + qy] * wz;
+                const double *row = rf + fb.off + (size_t)fb.nx * (fy + (size_t)fb.ny * fz);
+                double v[XM];
+#pragma unroll
+                for (int q = 0; q < XM; ++q) v[q] = q < nqx ? row[fxs[q]] : 0.0;
+#pragma unroll
+                for (int q = 0; q < XM; ++q)
+                    if (q < nqx) s += (wxs[q] * wyz) * v[q];
+            }
+        }
+        rc[I] = s;
+        return;
+    }
     for (int qz = 0; qz < a.ccnt[2][cz]; ++qz) {
         const int fz = a.ci[2][cz * a.cs[2] + qz];
         const double wz = a.cw[2][cz * a.cs[2] + qz];
         for (int qy = 0; qy < a.ccnt[1][cy]; ++qy) {
             const int fy = a.ci[1][cy * a.cs[1] + qy];
             const double wy = a.cw[1][cy * a.cs[1] + qy];
-            for (int qx = 0; qx < a.ccnt[0][cx]; ++qx) {
+            for (int qx = 0; qx < nqx; ++qx) {
                 const int fx = a.ci[0][cx * a.cs[0] + qx];
                 const double wx = a.cw[0][cx * a.cs[0] + qx];
                 s += (wx * wy * wz) * rf[fb.off + fx + fb.nx * (fy + fb.ny * fz)];
@@ -2699,7 +2730,8 @@ __global__ void k_restrict(XferArgs a, const double *rf, double *rc) {
     rc[I] = s;
 }
 
-// z_f += P e_c
+// z_f += P e_c: rows of P hold at most four entries per direction, all
+// loaded before the sum
 __global__ void k_prolong_add(XferArgs a, const double *ec, double *zf) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.Nf) return;
@@ -2709,21 +2741,37 @@ __global__ void k_prolong_add(XferArgs a, const double *ec, double *zf) {
     const int l = i - fb.off;
     const int x = l % fb.nx, y = (l / fb.nx) % fb.ny, z = l / (fb.nx * fb.ny);
     const int rx = a.roff[0][b] + x, ry = a.roff[1][b] + y, rz = a.roff[2][b] + z;
-    double s = 0.0;
-    for (int qz = 0; qz < a.rcnt[2][rz]; ++qz) {
-        const int Jz = a.rj[2][rz * 4 + qz];
-        const double wz = a.rw[2][rz * 4 + qz];
-        for (int qy = 0; qy < a.rcnt[1][ry]; ++qy) {
-            const int Jy = a.rj[1][ry * 4 + qy];
-            const double wy = a.rw[1][ry * 4 + qy];
-            for (int qx = 0; qx < a.rcnt[0][rx]; ++qx) {
-                const int Jx = a.rj[0][rx * 4 + qx];
-                const double wx = a.rw[0][rx * 4 + qx];
-                s += (wx * wy * wz) * ec[cb.off + Jx + cb.nx * (Jy + cb.ny * Jz)];
-            }
+    int n[3], J[3][4];
+    double w[3][4];
+    const int r[3] = {rx, ry, rz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        n[d] = a.rcnt[d][r[d]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            J[d][q] = a.rj[d][r[d] * 4 + q];
+            w[d][q] = a.rw[d][r[d] * 4 + q];
         }
     }
-    zf[i] += s;
+    const double zi = zf[i];
+    double s = 0.0;
+#pragma unroll
+    for (int qz = 0; qz < 4; ++qz) {
+        if (qz >= n[2]) break;
+#pragma unroll
+        for (int qy = 0; qy < 4; ++qy) {
+            if (qy >= n[1]) break;
+            const double wyz = w[2][qz] * w[1][qy];
+            const double *row = ec + cb.off + (size_t)cb.nx * (J[1][qy] + (size_t)cb.ny * J[2][qz]);
+            double v[4];
+#pragma unroll
+            for (int qx = 0; qx < 4; ++qx) v[qx] = row[qx < n[0] ? J[0][qx] : J[0][0]];
+#pragma unroll
+            for (int qx = 0; qx < 4; ++qx)
+                if (qx < n[0]) s += (w[0][qx] * wyz) * v[qx];
+        }
+    }
+    zf[i] = zi + s;
 }
 
 // Galerkin A_c = P^T A P, one wavefront per coarse cell I: the lanes share
