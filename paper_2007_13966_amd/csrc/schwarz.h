@@ -111,6 +111,13 @@ struct Level {
     // 2D levels: column-wise Galerkin product, windows of at most
     // rap_wx x rap_wy fine cells (0: the general kernel)
     int rap_wx = 0, rap_wy = 0;
+    // its tables, fixed by the interpolation: per coarse cell {block, x and y
+    // column, J_x | J_y << 16}; per column its window {first cell, width};
+    // per column and coarse offset o the weights p(f, column - o) over the
+    // window widened by the fine stencil's reach
+    DBuf<int4> rap_cell;
+    DBuf<int2> rap_win[2];
+    DBuf<double> rap_tab[2];
     // work vectors
     DBuf<double> r, t, bc, xc;
 };

@@ -1091,9 +1091,11 @@ __host__ __device__ inline RowsLds rows_lds(size_t vt, size_t ft, size_t dt, int
 // a row's range read a neighbouring row's cell and are masked; rows past
 // the box repeat the last row), stores of masked steps go to a spare slot,
 // and the stencil map arrives in the kernel arguments.  The upper factors and 1/u_ii are
-// staged by the other wavefronts while the forward sweep runs.
+// staged by the other wavefronts while the forward sweep runs.  The
+// cross-stencil form in FP32 / BF16 is held to five wavefronts per SIMD: its
+// boxes then fit five to a CU in registers as in LDS.
 template <typename FT, typename VT, typename DT, int BOX, int NT>
-__global__ void __launch_bounds__(NT) k_ras_rows(RowsArgs a) {
+__global__ void __launch_bounds__(NT, (BOX == 0 && NT == 256 && sizeof(VT) == 4) ? 5 : 1) k_ras_rows(RowsArgs a) {
     using S = RowStencil<BOX>;
     constexpr int NS = S::NS, NL = S::NL, NU = NS - NL, LB = S::LB;
     constexpr int PER = (int)(16 / sizeof(FT));
@@ -2857,81 +2859,64 @@ __global__ void __launch_bounds__(64 * W) k_rap(XferArgs a, const double *Af, in
 // written by the wavefront of its column; entries whose column lies outside
 // the block stay as the caller zeroed them.
 struct Rap2Lds {
-    int wxg, wyg, wx, wy, per;   // table extents and doubles per wavefront
+    int wg[2], wx, wy, per;   // table widths (window + reach) and doubles per wavefront
 };
 __host__ __device__ inline Rap2Lds rap2_lds(int wx, int wy, int Rf, int Rc) {
     Rap2Lds L;
     L.wx = wx;
     L.wy = wy;
-    L.wxg = wx + 2 * Rf;
-    L.wyg = wy + 2 * Rf;
+    L.wg[0] = wx + 2 * Rf;
+    L.wg[1] = wy + 2 * Rf;
     const int nc = 2 * Rc + 1;
-    L.per = L.wxg + L.wyg + nc * wx + nc * wy + wx * wy + nc * wy;
+    L.per = nc * (L.wg[0] + L.wg[1]) + wx * wy + nc * wy;
     return L;
 }
 
+struct Rap2Tabs {
+    const int4 *cell;
+    const int2 *win[2];
+    const double *tab[2];
+};
+
 template <int W>
-__global__ void __launch_bounds__(64 * W) k_rap2d(XferArgs a, const double *Af, int Kf, const int8_t *offf, int Rf,
-                                                  double *Ac, int Kc, const int8_t *offc, int Rc, int wxm, int wym) {
+__global__ void __launch_bounds__(64 * W) k_rap2d(XferArgs a, Rap2Tabs tb, const double *Af, int Kf,
+                                                  const int8_t *offf, int Rf, double *Ac, int Kc, const int8_t *offc,
+                                                  int Rc, int wxm, int wym) {
     extern __shared__ double rap2_s[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const Rap2Lds L = rap2_lds(wxm, wym, Rf, Rc);
     const int nc = 2 * Rc + 1;
-    double *tJx = rap2_s + (size_t)w * L.per;       // p_x(g_x, J_x), g_x from wx0 - Rf
-    double *tJy = tJx + L.wxg;
-    double *tIx = tJy + L.wyg;                      // [o_x + Rc][f_x - wx0]: p_x(f_x, J_x - o_x)
-    double *tIy = tIx + nc * L.wx;
-    double *AP = tIy + nc * L.wy;                   // [f_y - wy0][f_x - wx0]
+    double *Tx = rap2_s + (size_t)w * L.per;        // [o][f_x - (wx0 - Rf)]: p_x(f_x, J_x - (o - Rc))
+    double *Ty = Tx + nc * L.wg[0];
+    double *AP = Ty + nc * L.wg[1];                 // [f_y - wy0][f_x - wx0]
     double *U = AP + L.wx * L.wy;                   // [o_x + Rc][f_y - wy0]
     const int J = blockIdx.x * W + w;
     const bool on = J < a.Nc;
-    int b = 0, Jx = 0, Jy = 0, wx0 = 0, wy0 = 0, WX = 0, WY = 0;
+    int4 ci = make_int4(0, 0, 0, 0);
+    int2 wxn = make_int2(0, 0), wyn = make_int2(0, 0);
     Blk cb{}, fb{};
     if (on) {
-        b = find_blk(a.cblk, a.B, J);
-        cb = a.cblk[b];
-        fb = a.fblk[b];
-        const int l = J - cb.off;
-        Jx = l % cb.nx;
-        Jy = l / cb.nx;
-        const int cx = a.coff[0][b] + Jx, cy = a.coff[1][b] + Jy;
-        // J's fine support in each direction is a run of consecutive cells
-        const int xlo = a.ci[0][cx * a.cs[0]], xhi = a.ci[0][cx * a.cs[0] + a.ccnt[0][cx] - 1];
-        const int ylo = a.ci[1][cy * a.cs[1]], yhi = a.ci[1][cy * a.cs[1] + a.ccnt[1][cy] - 1];
-        wx0 = max(0, xlo - Rf);
-        wy0 = max(0, ylo - Rf);
-        WX = min(fb.nx, xhi + Rf + 1) - wx0;
-        WY = min(fb.ny, yhi + Rf + 1) - wy0;
+        ci = tb.cell[J];
+        cb = a.cblk[ci.x];
+        fb = a.fblk[ci.x];
+        wxn = tb.win[0][ci.y];
+        wyn = tb.win[1][ci.z];
+        // the column's weight tables, as laid out in memory
+        const double *gx = tb.tab[0] + (size_t)ci.y * nc * L.wg[0];
+        const double *gy = tb.tab[1] + (size_t)ci.z * nc * L.wg[1];
+        for (int t = lane; t < nc * L.wg[0]; t += 64) Tx[t] = gx[t];
+        for (int t = lane; t < nc * L.wg[1]; t += 64) Ty[t] = gy[t];
     }
-    // tables: zero, then scatter the interpolation columns
-    for (int t = lane; t < L.wxg + L.wyg + nc * (L.wx + L.wy); t += 64) tJx[t] = 0.0;
-    __syncthreads();
-    if (on) {
-        const int cx = a.coff[0][b] + Jx, cy = a.coff[1][b] + Jy;
-        for (int q = lane; q < a.ccnt[0][cx]; q += 64)
-            tJx[a.ci[0][cx * a.cs[0] + q] - (wx0 - Rf)] = a.cw[0][cx * a.cs[0] + q];
-        for (int q = lane; q < a.ccnt[1][cy]; q += 64)
-            tJy[a.ci[1][cy * a.cs[1] + q] - (wy0 - Rf)] = a.cw[1][cy * a.cs[1] + q];
-        // one (column, entry) pair per lane, every load of a pass in flight at once
-        for (int t = lane; t < nc * (a.cs[0] + a.cs[1]); t += 64) {
-            const int d = t < nc * a.cs[0] ? 0 : 1;
-            const int u = d == 0 ? t : t - nc * a.cs[0];
-            const int o = u / a.cs[d], q = u % a.cs[d];
-            const int Ic = (d == 0 ? Jx : Jy) - (o - Rc), n = d == 0 ? cb.nx : cb.ny;
-            if (Ic < 0 || Ic >= n) continue;
-            const int c = a.coff[d][b] + Ic;
-            if (q >= a.ccnt[d][c]) continue;
-            const int fi = a.ci[d][c * a.cs[d] + q] - (d == 0 ? wx0 : wy0);
-            if (fi >= 0 && fi < (d == 0 ? WX : WY)) (d == 0 ? tIx + o * L.wx : tIy + o * L.wy)[fi] = a.cw[d][c * a.cs[d] + q];
-        }
-    }
+    const int Jx = ci.w & 0xffff, Jy = ci.w >> 16;
+    const int wx0 = wxn.x, WX = wxn.y, wy0 = wyn.x, WY = wyn.y;
     __syncthreads();
     if (on) {
         // AP over the window.  A's coefficients towards neighbours outside
-        // the block are zero and the J tables are zero off J's support (which
-        // lies inside the block), so no term needs a bounds test: the Kf
+        // the block are zero and the tables are zero off the supports (which
+        // lie inside the block), so no term needs a bounds test: the Kf
         // loads of a cell go out together.
         constexpr int KM = 25;
+        const double *TJx = Tx + Rc * L.wg[0], *TJy = Ty + Rc * L.wg[1];
         for (int t = lane; t < WX * WY; t += 64) {
             const int ux = t % WX, uy = t / WX;
             const int fx = wx0 + ux, fy = wy0 + uy;
@@ -2943,8 +2928,8 @@ __global__ void __launch_bounds__(64 * W) k_rap2d(XferArgs a, const double *Af, 
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
                 if (k < Kf) {
-                    const int gx = fx + offf[3 * k], gy = fy + offf[3 * k + 1];
-                    s += av[k] * (tJx[gx - (wx0 - Rf)] * tJy[gy - (wy0 - Rf)]);
+                    const int gx = ux + Rf + offf[3 * k], gy = uy + Rf + offf[3 * k + 1];
+                    s += av[k] * (TJx[gx] * TJy[gy]);
                 }
             }
             AP[uy * L.wx + ux] = s;
@@ -2953,10 +2938,11 @@ __global__ void __launch_bounds__(64 * W) k_rap2d(XferArgs a, const double *Af, 
     __syncthreads();
     if (on) {
         for (int t = lane; t < nc * WY; t += 64) {
-            const int ox = t / WY, uy = t % WY;
+            const int o = t / WY, uy = t % WY;
+            const double *tx = Tx + o * L.wg[0] + Rf;
             double s = 0.0;
-            for (int ux = 0; ux < WX; ++ux) s += tIx[ox * L.wx + ux] * AP[uy * L.wx + ux];
-            U[ox * L.wy + uy] = s;
+            for (int ux = 0; ux < WX; ++ux) s += tx[ux] * AP[uy * L.wx + ux];
+            U[o * L.wy + uy] = s;
         }
     }
     __syncthreads();
@@ -2965,8 +2951,9 @@ __global__ void __launch_bounds__(64 * W) k_rap2d(XferArgs a, const double *Af, 
             const int ox = offc[3 * k], oy = offc[3 * k + 1];
             const int Ix = Jx - ox, Iy = Jy - oy;
             if (Ix < 0 || Ix >= cb.nx || Iy < 0 || Iy >= cb.ny) continue;
+            const double *ty = Ty + (oy + Rc) * L.wg[1] + Rf;
             double s = 0.0;
-            for (int uy = 0; uy < WY; ++uy) s += tIy[(oy + Rc) * L.wy + uy] * U[(ox + Rc) * L.wy + uy];
+            for (int uy = 0; uy < WY; ++uy) s += ty[uy] * U[(ox + Rc) * L.wy + uy];
             Ac[(size_t)k * a.Nc + cb.off + Ix + (size_t)cb.nx * Iy] = s;
         }
     }
@@ -3082,6 +3069,50 @@ static void build_packed(Level &V, int precision, int lds_bytes, Alloc *al, hipS
     V.pk_max_n = max_n;
 }
 
+// Tables of the column-wise 2D Galerkin product (see k_rap2d)
+static void build_rap_tables(Level &F, Level &C, const std::vector<int> &nfx, const std::vector<int> &nfy, int Rf,
+                             int Rc, Alloc *al, hipStream_t s) {
+    const int nc = 2 * Rc + 1;
+    const std::vector<int> *nfs[2] = {&nfx, &nfy};
+    for (int d = 0; d < 2; ++d) {
+        const Interp1 &ip = F.ip[d];
+        const int wg = (d == 0 ? F.rap_wx : F.rap_wy) + 2 * Rf;
+        const int ncols = (int)ip.ccnt.size();
+        std::vector<int2> win(ncols, int2{0, 0});
+        std::vector<double> tab((size_t)ncols * nc * wg, 0.0);
+        for (size_t b = 0; b < nfs[d]->size(); ++b) {
+            const int nf = (*nfs[d])[b], c0 = ip.coff[b];
+            const int ncb = (b + 1 < nfs[d]->size() ? ip.coff[b + 1] : ncols) - c0;
+            for (int Ic = 0; Ic < ncb; ++Ic) {
+                const int c = c0 + Ic;
+                if (ip.ccnt[c] < 1) continue;
+                const int lo = ip.ci[(size_t)c * ip.cs], hi = ip.ci[(size_t)c * ip.cs + ip.ccnt[c] - 1];
+                const int w0 = std::max(0, lo - Rf);
+                win[c] = int2{w0, std::min(nf, hi + Rf + 1) - w0};
+                for (int o = 0; o < nc; ++o) {
+                    const int Io = Ic - (o - Rc);
+                    if (Io < 0 || Io >= ncb) continue;
+                    const int co = c0 + Io;
+                    for (int q = 0; q < ip.ccnt[co]; ++q) {
+                        const int k = ip.ci[(size_t)co * ip.cs + q] - (w0 - Rf);
+                        if (k >= 0 && k < wg) tab[((size_t)c * nc + o) * wg + k] = ip.cw[(size_t)co * ip.cs + q];
+                    }
+                }
+            }
+        }
+        F.rap_win[d].upload(al, win, s);
+        F.rap_tab[d].upload(al, tab, s);
+    }
+    std::vector<int4> cell(C.spp->N);
+    for (int b = 0; b < C.spp->B; ++b) {
+        const Blk &k = C.spp->hblk[b];
+        for (int y = 0; y < k.ny; ++y)
+            for (int x = 0; x < k.nx; ++x)
+                cell[k.off + x + k.nx * y] = int4{b, F.ip[0].coff[b] + x, F.ip[1].coff[b] + y, x | (y << 16)};
+    }
+    F.rap_cell.upload(al, cell, s);
+}
+
 void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
     J = Jm;
     g = Jm->g;
@@ -3172,6 +3203,7 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
                 }
                 (d == 0 ? F.rap_wx : F.rap_wy) = wmax;
             }
+            build_rap_tables(F, C, nfx, nfy, fs.R, Rc, al, s);
         }
     }
     // the same box grid on every level: box counts per reservoir from the finest level
@@ -3250,10 +3282,11 @@ void Ras::factor(bool ilu) {
             k_fill<<<nblk((int)std::min<size_t>((size_t)Kc * Nc, INT32_MAX), 256), 256, 0, s>>>(Kc * Nc, 0.0,
                                                                                                V.own.coef.p);
             KCHECK();
-            void (*fr)(XferArgs, const double *, int, const int8_t *, int, double *, int, const int8_t *, int, int,
-                       int) = W == 4 ? k_rap2d<4> : (W == 2 ? k_rap2d<2> : k_rap2d<1>);
+            Rap2Tabs tb{F.rap_cell.p, {F.rap_win[0].p, F.rap_win[1].p}, {F.rap_tab[0].p, F.rap_tab[1].p}};
+            void (*fr)(XferArgs, Rap2Tabs, const double *, int, const int8_t *, int, double *, int, const int8_t *,
+                       int, int, int) = W == 4 ? k_rap2d<4> : (W == 2 ? k_rap2d<2> : k_rap2d<1>);
             set_lds((const void *)fr, W * per);
-            launch_timed("rap", l, fr, dim3(nblk(Nc, W)), dim3(64 * W), W * per, s, a, F.A->coef.p, F.A->st.K,
+            launch_timed("rap", l, fr, dim3(nblk(Nc, W)), dim3(64 * W), W * per, s, a, tb, F.A->coef.p, F.A->st.K,
                          F.A->st.doff.p, F.A->st.R, V.own.coef.p, Kc, V.own.st.doff.p, F.rap_R, F.rap_wx, F.rap_wy);
             KCHECK();
         } else if (l > 0) {
