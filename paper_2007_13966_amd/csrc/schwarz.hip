@@ -1660,9 +1660,13 @@ __host__ __device__ inline RowsLds packed_lds(size_t vt, size_t ft, size_t dt, i
 // outside the group (then none of its steps is active), so every load and
 // store of a step takes a constant offset from that base; masked steps
 // store into the guard cells past the group's end, which no active step
-// reads.  The rest follows packed_forward / packed_backward.
+// reads.  Unlike packed_forward / packed_backward, values cross from one box
+// to the next through the lane shifts unmasked: a box's factors towards
+// rows outside it are exact zeros (those couplings are not in A_i) and every
+// shifted value is finite (masked steps give zero), so the neighbouring
+// box's rows contribute nothing.
 template <typename FT, typename VT, typename DT, int BOX, int RB, int CS, int UP>
-__device__ __forceinline__ void lds_forward(int n, int cg, int tlo, int ex, bool fw, int T, VT *rv, const FT *cf) {
+__device__ __forceinline__ void lds_forward(int n, int cg, int tlo, int ex, int T, VT *rv, const FT *cf) {
     using S = RowStencil<BOX>;
     constexpr int NL = S::NL, LB = S::LB;
     constexpr int NLP = row_lpad<BOX, FT>();
@@ -1675,9 +1679,11 @@ __device__ __forceinline__ void lds_forward(int n, int cg, int tlo, int ex, bool
     VT coA[RB][NLP], rinA[RB], coB[RB][NLP], rinB[RB];
     int cbA, cbB;
     bool aaA[RB], aaB[RB];
+    // run addresses from the first guard cell: a non-negative 24-bit product
+    const FT *const cfg = cf - RB * CS;
     auto load = [&](int tb, VT(&co)[RB][NLP], VT(&rin)[RB], int &cb0, bool(&aa)[RB]) {
         cb0 = min(max(cg + tb, -RB), n);
-        const FT *cfb = cf + cb0 * CS;
+        const FT *cfb = cfg + __umul24((unsigned)(cb0 + RB), (unsigned)CS);
         const VT *rvb = rv + cb0;
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
@@ -1724,9 +1730,8 @@ __device__ __forceinline__ void lds_forward(int n, int cg, int tlo, int ex, bool
             const VT out = aa[u] ? v : (VT)0;
             outv[u] = out;
             r0[uu] = out;
-            const VT s1 = lane_shr(fw ? out : (VT)0);
-            r1[uu] = s1;
-            r2[uu] = lane_shr(fw ? s1 : (VT)0);
+            r1[uu] = lane_shr(out);
+            r2[uu] = lane_shr(r1[uu]);
         }
         VT *const rvb = rv + cb0;
 #pragma unroll
@@ -1747,7 +1752,7 @@ __device__ __forceinline__ void lds_forward(int n, int cg, int tlo, int ex, bool
 }
 
 template <typename FT, typename VT, typename DT, int BOX, int RB, int CS, int UP>
-__device__ __forceinline__ void lds_backward(int n, int cgb, int tlob, int ex, bool bw, int T, VT *rv, const FT *cf,
+__device__ __forceinline__ void lds_backward(int n, int cgb, int tlob, int ex, int T, VT *rv, const FT *cf,
                                              const DT *id) {
     using S = RowStencil<BOX>;
     constexpr int NS = S::NS, NL = S::NL, LB = S::LB;
@@ -1763,9 +1768,10 @@ __device__ __forceinline__ void lds_backward(int n, int cgb, int tlob, int ex, b
     bool aaA[RB], aaB[RB];
     // block of steps tb .. tb + RB - 1 at cells cgb - tb - u, addressed from
     // its lowest cell
+    const FT *const cfg = cf - RB * CS + UP;
     auto load = [&](int tb, VT(&co)[RB][NUP], VT(&rin)[RB], VT(&dg)[RB], int &cl, bool(&aa)[RB]) {
         cl = min(max(cgb - tb - (RB - 1), -RB), n);
-        const FT *cfb = cf + cl * CS + UP;
+        const FT *cfb = cfg + __umul24((unsigned)(cl + RB), (unsigned)CS);
         const VT *rvb = rv + cl;
         const DT *idb = id + cl;
 #pragma unroll
@@ -1810,9 +1816,8 @@ __device__ __forceinline__ void lds_backward(int n, int cgb, int tlob, int ex, b
             const VT out = aa[u] ? v * dg[u] : (VT)0;
             outv[u] = out;
             r0[uu] = out;
-            const VT s1 = lane_shl(bw ? out : (VT)0);
-            r1[uu] = s1;
-            r2[uu] = lane_shl(bw ? s1 : (VT)0);
+            r1[uu] = lane_shl(out);
+            r2[uu] = lane_shl(r1[uu]);
         }
         VT *const rvb = rv + cl;
 #pragma unroll
@@ -1887,16 +1892,15 @@ __global__ void __launch_bounds__(256) k_ras_packed(PackArgs a) {
     const int2 ln = a.glane[(size_t)g * 64 + lane];
     const SubDev sd = a.sub[ln.x];
     const int T = a.gsteps[g];
-    // this lane's row: first group cell of its forward and backward steps,
-    // the step at which its row starts, whether the neighbouring lane holds
-    // the next (forward) or previous (backward) row of the same box
+    // this lane's row: first group cell of its forward and backward steps and
+    // the steps at which its row starts
     const bool on = ln.y >= 0;
     const int ye = on ? ln.y : 0, ex = sd.ex, ey = sd.ey;
     const int Ts = (ex - 1) + S::LB * (ey - 1) + 1;
     const int cg = (sd.fac_off - e0) + ye * (ex - S::LB);
     const int tlo = on ? S::LB * ye : (1 << 28), tlob = on ? Ts - S::LB * ye - ex : (1 << 28);
     if (wid == 0) {
-        lds_forward<FT, VT, DT, BOX, RB, CS, NLP>(n, cg, tlo, ex, on && ye + 1 < ey, T, rv, cf);
+        lds_forward<FT, VT, DT, BOX, RB, CS, NLP>(n, cg, tlo, ex, T, rv, cf);
     } else {
         // the upper runs and 1/u_ii meanwhile
         for (int c0 = tid - 64; c0 < n; c0 += CPT * 192) {
@@ -1926,7 +1930,7 @@ __global__ void __launch_bounds__(256) k_ras_packed(PackArgs a) {
     }
     __syncthreads();
     if (wid == 0)
-        lds_backward<FT, VT, DT, BOX, RB, CS, NLP>(n, cg + Ts - 1, tlob, ex, on && ye >= 1, T, rv, cf, id);
+        lds_backward<FT, VT, DT, BOX, RB, CS, NLP>(n, cg + Ts - 1, tlob, ex, T, rv, cf, id);
     __syncthreads();
     // write back: the owned cells (left-RAS), or every extended cell for the gather
     unsigned long long own = 0;
