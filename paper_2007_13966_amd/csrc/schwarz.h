@@ -79,6 +79,7 @@ struct Level {
     // factors stored in lexicographic order
     bool rows3d = false;
     bool rows3d_multi = false;   // more than 64 (y, z) rows: slabs of z planes, one wavefront each
+    int rows3d_slabs = 1;        // most slabs of a box
     std::vector<int> hkmap3;     // 3D sweep: lower (z, y, x) and upper (x, y, z) slots -> stencil index
     int box = 0;                 // 0: 5-point cross, 1: 5x5 box, 2: 21-point (5x5 without corners)
     DBuf<int> slotmap;           // box slot -> stencil index (-1: absent)

@@ -293,11 +293,11 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
             L.rows2d = true;
         }
     }
-    // 3D row sweep: the 7-point stencil, rows of at most 64 cells, at most four
-    // slabs of z planes with at most 64 (y, z) rows each
+    // 3D row sweep: the 7-point stencil, rows of at most 64 cells, at most
+    // eight slabs of z planes with at most 64 (y, z) rows each
     L.rows3d = false;
     const int pzmin = 64 / std::max(mey, 1);
-    if (nofill && Rz == 1 && R == 1 && st.K == 7 && mey <= 64 && mex <= 64 && (mez + pzmin - 1) / pzmin <= 4) {
+    if (nofill && Rz == 1 && R == 1 && st.K == 7 && mey <= 64 && mex <= 64 && (mez + pzmin - 1) / pzmin <= 8) {
         bool cross = true;
         for (int k = 0; k < st.K; ++k)
             if (std::abs(st.off[3 * k]) + std::abs(st.off[3 * k + 1]) + std::abs(st.off[3 * k + 2]) > 1) cross = false;
@@ -310,6 +310,7 @@ static void build_partition(Level &L, const std::vector<std::array<int, 3>> &box
             L.hkmap3 = {find(0, 0, -1), find(0, -1, 0), find(-1, 0, 0), find(1, 0, 0), find(0, 1, 0), find(0, 0, 1)};
             L.rows3d = true;
             L.rows3d_multi = mey * mez > 64;
+            L.rows3d_slabs = (mez + pzmin - 1) / pzmin;
         }
     }
     // stencil tables
@@ -2288,6 +2289,14 @@ __global__ void k_pack_runs(const FT *F, int NE, const int *kmap, FT *runs) {
 // be finite; rows past the box and steps outside a row's range are masked
 // to zero.  The backward sweep mirrors this with the upper neighbours.
 // Factors, 1/u_ii and R_i^delta r are staged in LDS as in the 2D sweep.
+// padded length of a cell's lower (and of its upper) run in the 3D row
+// sweep: a whole 16-byte word of FT, or, where both runs of three fit one
+// word (BF16), four values each, so a box's runs take 16 B per cell
+template <typename FT>
+__host__ __device__ constexpr int rows3d_lpad() {
+    return 6 * sizeof(FT) <= 16 ? 4 : (3 + (int)(16 / sizeof(FT)) - 1) / (int)(16 / sizeof(FT)) * (int)(16 / sizeof(FT));
+}
+
 struct Rows3Args {
     const SubDev *sub;
     const void *F;        // K*NE off-diagonal factors (FT), lexicographic per subdomain
@@ -2302,15 +2311,15 @@ struct Rows3Args {
     int kmap[16];         // run slot -> stencil index: lower (z, y, x) then upper (x, y, z); -1 padding
 };
 
-template <typename FT, typename VT, typename DT, bool MULTI>
-__global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
-    constexpr int PER = (int)(16 / sizeof(FT));
-    constexpr int NLP = (3 + PER - 1) / PER * PER;   // lower run: Lz, Ly, Lx, padding
+template <typename FT, typename VT, typename DT, bool MULTI, int NT>
+__global__ void __launch_bounds__(NT) k_ras_rows3d(Rows3Args a) {
+    constexpr int NLP = rows3d_lpad<FT>();           // lower run: Lz, Ly, Lx, padding
     constexpr int NSP = 2 * NLP;                     // then the upper run: Ux, Uy, Uz, padding
+    constexpr int NWV = NT / 64;                     // wavefronts: at most this many slabs
     constexpr int RB = MULTI ? 4 : 8;                // steps per block of LDS reads
     constexpr int CPT = 2;
     extern __shared__ __align__(16) unsigned char smem3[];
-    __shared__ int prog[2][4];                       // steps done per slab: forward, backward
+    __shared__ int prog[2][NWV];                     // steps done per slab: forward, backward
     const SubDev sd = a.sub[blockIdx.x];
     if (a.mask && !a.mask[sd.blk]) return;
     if (a.units && threadIdx.x == 0) {
@@ -2321,7 +2330,7 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
         atomicAdd(u + 1, (unsigned long long)((sd.lx1 - sd.lx0) * (sd.ly1 - sd.ly0) * (sd.lz1 - sd.lz0)));
     }
     const int n = sd.next, ex = sd.ex, ey = sd.ey, ez = sd.ez;
-    if (MULTI && threadIdx.x < 8) prog[threadIdx.x >> 2][threadIdx.x & 3] = 0;
+    if (MULTI && threadIdx.x < 2 * NWV) prog[threadIdx.x / NWV][threadIdx.x % NWV] = 0;
     VT *rv = reinterpret_cast<VT *>(smem3);
     FT *cf = reinterpret_cast<FT *>(smem3 + al16(sizeof(VT) * (size_t)(n + 1)));
     DT *id = reinterpret_cast<DT *>(smem3 + al16(sizeof(VT) * (size_t)(n + 1)) + al16(sizeof(FT) * (size_t)NSP * n));
@@ -2331,13 +2340,13 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
     const float inv_ex = 1.0f / (float)ex, inv_ey = 1.0f / (float)ey;
     // stage every cell's runs, 1/u_ii and R_i^delta r; every load of a pass
     // is issued before its first LDS store
-    for (int c0 = threadIdx.x; c0 < n; c0 += CPT * 256) {
+    for (int c0 = threadIdx.x; c0 < n; c0 += CPT * NT) {
         FT v[CPT][NSP];
         DT d[CPT];
         double rr[CPT];
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
-            const int c = min(c0 + u * 256, n - 1);
+            const int c = min(c0 + u * NT, n - 1);
 #pragma unroll
             for (int q = 0; q < NSP; ++q) {
                 const int k = a.kmap[q];
@@ -2351,7 +2360,7 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
         }
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
-            const int c = c0 + u * 256;
+            const int c = c0 + u * NT;
             if (c < n) {
 #pragma unroll
                 for (int q = 0; q < NSP; ++q) cf[(size_t)c * NSP + q] = v[u][q];
@@ -2469,12 +2478,12 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
         const float inv_oxn = 1.0f / (float)oxn, inv_oyn = 1.0f / (float)oyn;
         constexpr int WB = 4;
         const int no = oxn * oyn * ozn;
-        for (int k0 = threadIdx.x; k0 < no; k0 += WB * 256) {
+        for (int k0 = threadIdx.x; k0 < no; k0 += WB * NT) {
             size_t g[WB];
             double v[WB];
 #pragma unroll
             for (int u = 0; u < WB; ++u) {
-                const int k = min(k0 + u * 256, no - 1);
+                const int k = min(k0 + u * NT, no - 1);
                 const int row = row_of(k, inv_oxn), xx = k - row * oxn;
                 const int zz = row_of(row, inv_oyn), yy = row - zz * oyn;
                 const int x = sd.lx0 + xx, y = sd.ly0 + yy, z = sd.lz0 + zz;
@@ -2487,7 +2496,7 @@ __global__ void __launch_bounds__(256) k_ras_rows3d(Rows3Args a) {
             }
 #pragma unroll
             for (int u = 0; u < WB; ++u)
-                if (k0 + u * 256 < no) a.z[g[u]] = v[u];
+                if (k0 + u * NT < no) a.z[g[u]] = v[u];
         }
     } else {
         for (int c = threadIdx.x; c < n; c += blockDim.x) a.zext[fo + c] = (double)rv[c];
@@ -3532,7 +3541,8 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
 static size_t rows3d_lds(int precision, size_t n) {
     const size_t ft = precision == NKS_FP64 ? 8 : (precision == NKS_FP32 ? 4 : 2);
     const size_t vt = precision == NKS_FP64 ? 8 : 4, dt = vt;
-    const size_t per = 16 / ft, nlp = (3 + per - 1) / per * per;
+    const size_t nlp = precision == NKS_FP64 ? rows3d_lpad<double>()
+                                             : (precision == NKS_FP32 ? rows3d_lpad<float>() : rows3d_lpad<uint16_t>());
     return al16(vt * (n + 1)) + al16(ft * 2 * nlp * n) + al16(dt * n);
 }
 
@@ -3546,8 +3556,7 @@ template <typename FT, typename VT, typename DT>
 static void launch_rows3d(Ras &M, Level &V, const double *r, double *z, const int *mask, bool accumulate) {
     Rows3Args a{};
     a.sub = V.sub.p;
-    constexpr int PER = (int)(16 / sizeof(FT));
-    constexpr int NLP = (3 + PER - 1) / PER * PER;
+    constexpr int NLP = rows3d_lpad<FT>();
     static_assert(2 * NLP <= 16, "run map fits the argument block");
     for (int q = 0; q < 16; ++q) a.kmap[q] = -1;
     for (int q = 0; q < 3; ++q) {
@@ -3567,11 +3576,15 @@ static void launch_rows3d(Ras &M, Level &V, const double *r, double *z, const in
     a.variant = M.d.variant;
     a.accumulate = accumulate ? 1 : 0;
     const size_t sh = rows3d_lds(M.d.precision, V.max_next);
-    void (*fn)(Rows3Args) = V.rows3d_multi ? k_ras_rows3d<FT, VT, DT, true> : k_ras_rows3d<FT, VT, DT, false>;
+    // a wavefront per slab: four per workgroup, or eight for boxes of five
+    // to eight slabs
+    const bool eight = V.rows3d_multi && V.rows3d_slabs > 4;
+    void (*fn)(Rows3Args) = !V.rows3d_multi ? k_ras_rows3d<FT, VT, DT, false, 256>
+                                            : (eight ? k_ras_rows3d<FT, VT, DT, true, 512> : k_ras_rows3d<FT, VT, DT, true, 256>);
     set_lds((const void *)fn, sh);
     V.form = NKS_SWEEP_ROWS3D;
     V.form_wgs = V.nsub;
-    launch_sweep("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(256), sh, M.g->s, a);
+    launch_sweep("ras_apply", level_index(M, V), fn, dim3(V.nsub), dim3(eight ? 512 : 256), sh, M.g->s, a);
     KCHECK();
     gather_ext(M, V, z, mask, accumulate);
 }

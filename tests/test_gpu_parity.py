@@ -189,6 +189,39 @@ def test_mixed_precision_apply_error(nks, orc, prec, tol, cfg):
     assert err <= tol
 
 
+@pytest.mark.parametrize("prec,tol,cfg", [
+    # 17^3 extended boxes: 17 (y) rows per z plane, three planes per slab, six
+    # slabs (an eight-wavefront workgroup); the BF16 runs (16 B per cell) fit
+    # in LDS, the FP32 ones do not (hyperplane kernel)
+    ("bf16", 5e-2, dict(nx=32, ny=32, nz=32, px=2, py=2, pz=2, overlap=(1,), gravity=True)),
+    ("fp32", 2e-5, dict(nx=32, ny=32, nz=32, px=2, py=2, pz=2, overlap=(1,), gravity=True)),
+    # 11 x 11 x 31 extended boxes: five planes per slab, seven slabs; both fit
+    ("fp32", 2e-5, dict(nx=20, ny=20, nz=60, px=2, py=2, pz=2, overlap=(1,))),
+    ("bf16", 5e-2, dict(nx=20, ny=20, nz=60, px=2, py=2, pz=2, overlap=(1,))),
+    ("fp64", 1e-11, dict(nx=20, ny=20, nz=60, px=2, py=2, pz=2, overlap=(1,))),
+])
+def test_rows3d_many_slabs_apply_parity(nks, orc, prec, tol, cfg):
+    case = S.small_case(precision=prec, **cfg)
+    case64 = S.small_case(**cfg)
+    rec = case.problems[0]
+    op = orc.Problem(rec)
+    p, pn, _ = _state(op, 12)
+    Jo = op.jacobian(p, pn, pn, case.dt, 1)
+    r = np.cos(0.37 * np.arange(op.N))
+    zo = orc.Multilevel(rec, Jo, case64.solver).apply(r)
+    g = nks.Grid([rec])
+    M = nks.Ras(_gpu_jac(nks, g, p, pn, case.dt), case.solver)
+    zg = M.apply(g.from_numpy(r)).cpu().numpy()
+    form = M.level_sweep(0)
+    err = np.max(np.abs(zg - zo)) / np.max(np.abs(zo))
+    say(prec, cfg["nx"], cfg["nz"], "form", form, "relative error vs FP64 oracle", err)
+    assert err <= tol
+    if prec == "bf16" or cfg["nz"] == 60 and prec == "fp32":
+        assert form[0] == "rows3d"
+    zg2 = M.apply(g.from_numpy(r)).cpu().numpy()
+    assert np.array_equal(zg, zg2)
+
+
 GALERKIN = [
     dict(nx=40, ny=36, nz=1, levels=3, interp_order=2),
     dict(nx=41, ny=27, nz=1, levels=2, interp_order=1),
