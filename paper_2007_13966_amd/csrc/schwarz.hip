@@ -2311,10 +2311,15 @@ struct Rows3Args {
     int kmap[16];         // run slot -> stencil index: lower (z, y, x) then upper (x, y, z); -1 padding
 };
 
-template <typename FT, typename VT, typename DT, bool MULTI, int NT>
+// HALF: LDS holds one run per cell at a time (boxes whose two runs do not
+// fit): the lower runs are staged for the forward sweep, then the upper runs
+// and 1/u_ii take their place for the backward sweep.
+template <typename FT, typename VT, typename DT, bool MULTI, int NT, bool HALF>
 __global__ void __launch_bounds__(NT) k_ras_rows3d(Rows3Args a) {
     constexpr int NLP = rows3d_lpad<FT>();           // lower run: Lz, Ly, Lx, padding
     constexpr int NSP = 2 * NLP;                     // then the upper run: Ux, Uy, Uz, padding
+    constexpr int CST = HALF ? NLP : NSP;            // LDS stride of a cell's runs
+    constexpr int NST = HALF ? NLP : NSP;            // run slots staged before the forward sweep
     constexpr int NWV = NT / 64;                     // wavefronts: at most this many slabs
     constexpr int RB = MULTI ? 4 : 8;                // steps per block of LDS reads
     constexpr int CPT = 2;
@@ -2333,7 +2338,7 @@ __global__ void __launch_bounds__(NT) k_ras_rows3d(Rows3Args a) {
     if (MULTI && threadIdx.x < 2 * NWV) prog[threadIdx.x / NWV][threadIdx.x % NWV] = 0;
     VT *rv = reinterpret_cast<VT *>(smem3);
     FT *cf = reinterpret_cast<FT *>(smem3 + al16(sizeof(VT) * (size_t)(n + 1)));
-    DT *id = reinterpret_cast<DT *>(smem3 + al16(sizeof(VT) * (size_t)(n + 1)) + al16(sizeof(FT) * (size_t)NSP * n));
+    DT *id = reinterpret_cast<DT *>(smem3 + al16(sizeof(VT) * (size_t)(n + 1)) + al16(sizeof(FT) * (size_t)CST * n));
     const FT *F = reinterpret_cast<const FT *>(a.F);
     const DT *ID = reinterpret_cast<const DT *>(a.invd);
     const size_t fo = sd.fac_off;
@@ -2341,19 +2346,19 @@ __global__ void __launch_bounds__(NT) k_ras_rows3d(Rows3Args a) {
     // stage every cell's runs, 1/u_ii and R_i^delta r; every load of a pass
     // is issued before its first LDS store
     for (int c0 = threadIdx.x; c0 < n; c0 += CPT * NT) {
-        FT v[CPT][NSP];
+        FT v[CPT][NST];
         DT d[CPT];
         double rr[CPT];
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const int c = min(c0 + u * NT, n - 1);
 #pragma unroll
-            for (int q = 0; q < NSP; ++q) {
+            for (int q = 0; q < NST; ++q) {
                 const int k = a.kmap[q];
                 const FT x = F[(size_t)max(k, 0) * a.NE + fo + c];
                 v[u][q] = k >= 0 ? x : (FT)0;
             }
-            d[u] = ID[fo + c];
+            if (!HALF) d[u] = ID[fo + c];
             const int row = row_of(c, inv_ex), x = c - row * ex;
             const int z = row_of(row, inv_ey), y = row - z * ey;
             rr[u] = a.r[(size_t)sd.gorg + x + (size_t)sd.gnx * (y + (size_t)sd.gny * z)];
@@ -2363,8 +2368,8 @@ __global__ void __launch_bounds__(NT) k_ras_rows3d(Rows3Args a) {
             const int c = c0 + u * NT;
             if (c < n) {
 #pragma unroll
-                for (int q = 0; q < NSP; ++q) cf[(size_t)c * NSP + q] = v[u][q];
-                id[c] = d[u];
+                for (int q = 0; q < NST; ++q) cf[(size_t)c * CST + q] = v[u][q];
+                if (!HALF) id[c] = d[u];
                 const int row = row_of(c, inv_ex), x = c - row * ex;
                 const int z = row_of(row, inv_ey), y = row - z * ey;
                 const bool own = x >= sd.lx0 && x < sd.lx1 && y >= sd.ly0 && y < sd.ly1 && z >= sd.lz0 && z < sd.lz1;
@@ -2395,19 +2400,19 @@ __global__ void __launch_bounds__(NT) k_ras_rows3d(Rows3Args a) {
             __builtin_amdgcn_s_sleep(1);
         }
     };
+    const int r = threadIdx.x & 63;
+    const int zl = r / ey, y0 = r - zl * ey;
+    const int nzw = min(pz, ez - w * pz);        // planes of this slab
+    const bool rowok = zl < nzw;
+    const int y = rowok ? y0 : 0, z = w * pz + (rowok ? zl : 0);
+    const int exy = ex * ey;
+    const int T = (ex - 1) + (ey - 1) + (ez - 1) + 1;
+    const int lo = rowok ? y + z : (1 << 28);     // steps with x inside the row
+    const int cb = ex * (y + ey * z) - y - z;     // cell of forward step t: cb + t
+    const int pz_f = ((r - ey) & 63) << 2, pz_b = ((r + ey) & 63) << 2;   // permute sources
+    const bool zfirst = MULTI && w > 0 && zl == 0;             // z-1 from the slab below
+    const bool zlast = MULTI && w < W - 1 && zl == nzw - 1;    // z+1 from the slab above
     if (w < W) {
-        const int r = threadIdx.x & 63;
-        const int zl = r / ey, y0 = r - zl * ey;
-        const int nzw = min(pz, ez - w * pz);        // planes of this slab
-        const bool rowok = zl < nzw;
-        const int y = rowok ? y0 : 0, z = w * pz + (rowok ? zl : 0);
-        const int exy = ex * ey;
-        const int T = (ex - 1) + (ey - 1) + (ez - 1) + 1;
-        const int lo = rowok ? y + z : (1 << 28);     // steps with x inside the row
-        const int cb = ex * (y + ey * z) - y - z;     // cell of forward step t: cb + t
-        const int pz_f = ((r - ey) & 63) << 2, pz_b = ((r + ey) & 63) << 2;   // permute sources
-        const bool zfirst = MULTI && w > 0 && zl == 0;             // z-1 from the slab below
-        const bool zlast = MULTI && w < W - 1 && zl == nzw - 1;    // z+1 from the slab above
         // forward: y_i = r_i - Lz y_(z-1) - Ly y_(y-1) - Lx y_(x-1)
         VT prev = (VT)0;
         for (int t0 = 0; t0 < T; t0 += RB) {
@@ -2420,7 +2425,7 @@ __global__ void __launch_bounds__(NT) k_ras_rows3d(Rows3Args a) {
                 const int t = t0 + u;
                 aa[u] = (unsigned)(t - lo) < (unsigned)ex;
                 cc[u] = min(max(cb + t, 0), n - 1);
-                load_run<FT, VT, NLP>(cf + (size_t)cc[u] * NSP, co[u]);
+                load_run<FT, VT, NLP>(cf + (size_t)cc[u] * CST, co[u]);
                 rin[u] = rv[cc[u]];
                 if (MULTI) rz[u] = rv[max(cc[u] - exy, 0)];
             }
@@ -2438,8 +2443,39 @@ __global__ void __launch_bounds__(NT) k_ras_rows3d(Rows3Args a) {
             }
             if (MULTI) __hip_atomic_store(&prog[0][w], t0 + RB, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+    }
+    if (HALF) {
+        // the upper runs and 1/u_ii over the lower runs
+        __syncthreads();
+        for (int c0 = threadIdx.x; c0 < n; c0 += CPT * NT) {
+            FT v[CPT][NLP];
+            DT d[CPT];
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = min(c0 + u * NT, n - 1);
+#pragma unroll
+                for (int q = 0; q < NLP; ++q) {
+                    const int k = a.kmap[NLP + q];
+                    const FT x = F[(size_t)max(k, 0) * a.NE + fo + c];
+                    v[u][q] = k >= 0 ? x : (FT)0;
+                }
+                d[u] = ID[fo + c];
+            }
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = c0 + u * NT;
+                if (c < n) {
+#pragma unroll
+                    for (int q = 0; q < NLP; ++q) cf[(size_t)c * CST + q] = v[u][q];
+                    id[c] = d[u];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (w < W) {
         // backward: z_i = (y_i - Ux z_(x+1) - Uy z_(y+1) - Uz z_(z+1)) / u_ii, step t at x = T-1-t - y - z
-        prev = (VT)0;
+        VT prev = (VT)0;
         const int lob = rowok ? T - ex - y - z : (1 << 28);
         const int cbb = cb + T - 1;
         for (int t0 = 0; t0 < T; t0 += RB) {
@@ -2452,7 +2488,7 @@ __global__ void __launch_bounds__(NT) k_ras_rows3d(Rows3Args a) {
                 const int t = t0 + u;
                 aa[u] = (unsigned)(t - lob) < (unsigned)ex;
                 cc[u] = min(max(cbb - t, 0), n - 1);
-                load_run<FT, VT, NLP>(cf + (size_t)cc[u] * NSP + NLP, co[u]);
+                load_run<FT, VT, NLP>(cf + (size_t)cc[u] * CST + (HALF ? 0 : NLP), co[u]);
                 rin[u] = rv[cc[u]];
                 dg[u] = (VT)id[cc[u]];
                 if (MULTI) rz[u] = rv[min(cc[u] + exy, n - 1)];
@@ -3538,18 +3574,18 @@ static void launch_rows(Ras &M, Level &V, const double *r, double *z, const int 
 
 // LDS of the 3D row sweep for boxes of n cells: rv[n + 1], the
 // padded lower and upper runs, 1/u_ii
-static size_t rows3d_lds(int precision, size_t n) {
+static size_t rows3d_lds(int precision, size_t n, bool half = false) {
     const size_t ft = precision == NKS_FP64 ? 8 : (precision == NKS_FP32 ? 4 : 2);
     const size_t vt = precision == NKS_FP64 ? 8 : 4, dt = vt;
     const size_t nlp = precision == NKS_FP64 ? rows3d_lpad<double>()
                                              : (precision == NKS_FP32 ? rows3d_lpad<float>() : rows3d_lpad<uint16_t>());
-    return al16(vt * (n + 1)) + al16(ft * 2 * nlp * n) + al16(dt * n);
+    return al16(vt * (n + 1)) + al16(ft * (half ? 1 : 2) * nlp * n) + al16(dt * n);
 }
 
 // whether a level runs the 3D row sweep (its factors are then
 // stored in lexicographic order)
 static bool use_rows3d(const Ras &M, const Level &V) {
-    return V.rows3d && V.max_next < (1 << 16) && rows3d_lds(M.d.precision, V.max_next) <= (size_t)M.lds_bytes;
+    return V.rows3d && V.max_next < (1 << 16) && rows3d_lds(M.d.precision, V.max_next, true) <= (size_t)M.lds_bytes;
 }
 
 template <typename FT, typename VT, typename DT>
@@ -3575,12 +3611,16 @@ static void launch_rows3d(Ras &M, Level &V, const double *r, double *z, const in
     a.err = V.err.p;
     a.variant = M.d.variant;
     a.accumulate = accumulate ? 1 : 0;
-    const size_t sh = rows3d_lds(M.d.precision, V.max_next);
     // a wavefront per slab: four per workgroup, or eight for boxes of five
-    // to eight slabs
+    // to eight slabs; both runs of every cell in LDS, or one at a time where
+    // both do not fit
+    const bool half = rows3d_lds(M.d.precision, V.max_next) > (size_t)M.lds_bytes;
+    const size_t sh = rows3d_lds(M.d.precision, V.max_next, half);
     const bool eight = V.rows3d_multi && V.rows3d_slabs > 4;
-    void (*fn)(Rows3Args) = !V.rows3d_multi ? k_ras_rows3d<FT, VT, DT, false, 256>
-                                            : (eight ? k_ras_rows3d<FT, VT, DT, true, 512> : k_ras_rows3d<FT, VT, DT, true, 256>);
+    void (*fn)(Rows3Args) =
+        !V.rows3d_multi ? (half ? k_ras_rows3d<FT, VT, DT, false, 256, true> : k_ras_rows3d<FT, VT, DT, false, 256, false>)
+        : eight ? (half ? k_ras_rows3d<FT, VT, DT, true, 512, true> : k_ras_rows3d<FT, VT, DT, true, 512, false>)
+                : (half ? k_ras_rows3d<FT, VT, DT, true, 256, true> : k_ras_rows3d<FT, VT, DT, true, 256, false>);
     set_lds((const void *)fn, sh);
     V.form = NKS_SWEEP_ROWS3D;
     V.form_wgs = V.nsub;

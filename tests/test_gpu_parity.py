@@ -192,10 +192,11 @@ def test_mixed_precision_apply_error(nks, orc, prec, tol, cfg):
 @pytest.mark.parametrize("prec,tol,cfg", [
     # 17^3 extended boxes: 17 (y) rows per z plane, three planes per slab, six
     # slabs (an eight-wavefront workgroup); the BF16 runs (16 B per cell) fit
-    # in LDS, the FP32 ones do not (hyperplane kernel)
+    # in LDS, the FP32 ones one run at a time
     ("bf16", 5e-2, dict(nx=32, ny=32, nz=32, px=2, py=2, pz=2, overlap=(1,), gravity=True)),
     ("fp32", 2e-5, dict(nx=32, ny=32, nz=32, px=2, py=2, pz=2, overlap=(1,), gravity=True)),
-    # 11 x 11 x 31 extended boxes: five planes per slab, seven slabs; both fit
+    # 11 x 11 x 31 extended boxes: five planes per slab, seven slabs; FP32 and
+    # BF16 hold both runs, FP64 takes the hyperplane kernel
     ("fp32", 2e-5, dict(nx=20, ny=20, nz=60, px=2, py=2, pz=2, overlap=(1,))),
     ("bf16", 5e-2, dict(nx=20, ny=20, nz=60, px=2, py=2, pz=2, overlap=(1,))),
     ("fp64", 1e-11, dict(nx=20, ny=20, nz=60, px=2, py=2, pz=2, overlap=(1,))),
@@ -216,7 +217,7 @@ def test_rows3d_many_slabs_apply_parity(nks, orc, prec, tol, cfg):
     err = np.max(np.abs(zg - zo)) / np.max(np.abs(zo))
     say(prec, cfg["nx"], cfg["nz"], "form", form, "relative error vs FP64 oracle", err)
     assert err <= tol
-    if prec == "bf16" or cfg["nz"] == 60 and prec == "fp32":
+    if prec != "fp64":
         assert form[0] == "rows3d"
     zg2 = M.apply(g.from_numpy(r)).cpu().numpy()
     assert np.array_equal(zg, zg2)
