@@ -3391,7 +3391,10 @@ void Ras::factor(bool ilu) {
             void (*fr)(IluRowsArgs) =
                 V.box == 0 ? k_ilu_rows<0> : (V.box == 1 ? k_ilu_rows<1> : k_ilu_rows<2>);
             set_lds((const void *)fr, sh_rows);
-            launch_timed("ilu_factor", l, fr, dim3(V.nsub), dim3(256), sh_rows, s, ia);
+            // one wavefront eliminates; the box stencils' elimination holds
+            // about 230 registers, so their workgroups are that one wavefront
+            // alone (two rounds of the batch's coarse boxes instead of five)
+            launch_timed("ilu_factor", l, fr, dim3(V.nsub), dim3(V.box == 0 ? 256 : 64), sh_rows, s, ia);
             KCHECK();
             perm = nullptr;
         } else {
