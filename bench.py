@@ -70,13 +70,13 @@ def pmc_traffic(workload, level, settings):
             "ratio": hbm / t["algorithmic"], "kernel": t["kernel"]}
 
 
-def apply_level_mode(P, S, case, level, repeats):
+def full_launches(P, case, level, repeats, settings=None):
     """One-level sweeps of `level` over the whole grid (no masks), `repeats`
-    times at the initial state, for counter passes; prints the swept cells
-    and algorithmic bytes of one launch."""
+    times at the initial state: the swept cells, algorithmic bytes and mean
+    duration (HIP events bound to each dispatch) of one launch."""
     import ctypes as C
     import torch
-    s = case.solver
+    s = settings or case.solver
     g = P.Grid(case.problems)
     p0 = g.initial_pressure()
     J = g.jacobian(p0, p0, None, case.dt, 1)
@@ -96,14 +96,23 @@ def apply_level_mode(P, S, case, level, repeats):
     t = C.c_double()
     P.check(P.lib().nks_profile_query(f"ras_apply_l{level}".encode(), C.byref(c), C.byref(t)))
     P.check(P.lib().nks_profile_enable(0))
+    P.check(P.lib().nks_profile_filter(None))
+    form = M.level_sweep(level)
     fb = {"fp64": 8, "fp32": 4, "bf16": 2}[s.precision]
     db = 8 if s.precision == "fp64" else 4
     ext, owned = cells[0] / repeats, cells[1] / repeats
     nbytes = ext * ((K - 1) * fb + db + 8) + owned * 8
-    print(json.dumps({"workload": case.name, "level": level, "precision": s.precision, "tile": s.tile[0],
-                      "overlap": s.overlap[min(level, len(s.overlap) - 1)], "ratio": s.ratio, "launches": repeats,
-                      "ext_cells": ext, "owned_cells": owned, "stencil_points": K,
-                      "algorithmic_bytes": nbytes, "avg_launch_us": 1e3 * t.value / max(1, c.value)}))
+    us = 1e3 * t.value / max(1, c.value)
+    return {"workload": case.name, "level": level, "precision": s.precision, "tile": s.tile[0],
+            "overlap": s.overlap[min(level, len(s.overlap) - 1)], "ratio": s.ratio, "launches": repeats,
+            "form": form[0], "workgroups": form[1], "ext_cells": ext, "owned_cells": owned, "stencil_points": K,
+            "algorithmic_bytes": nbytes, "avg_launch_us": us,
+            "achieved": nbytes / (us * 1e-6) / 1e9, "frac": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+
+
+def apply_level_mode(P, S, case, level, repeats):
+    """`full_launches` for counter passes: prints its record."""
+    print(json.dumps(full_launches(P, case, level, repeats)))
 
 
 def log(*a):
@@ -630,6 +639,15 @@ def main():
             "bound": "hbm", "achieved": ga, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ga / HBM_PEAK_GBS,
             "bytes_per_launch": nb, "launches": int(sp.size), "avg_launch_us": float(sp.mean()) * 1e3,
         }
+    # every sweep level alone over the whole grid (no reservoir masked out):
+    # the kernels against their roofline without the coarse solve's partly
+    # masked launches
+    out["roofline_full_launches"] = {}
+    for lvl in sweeps:
+        fl = full_launches(P, case, lvl, 20, s_head)
+        out["roofline_full_launches"][f"level_{lvl}"] = fl
+        log(f"level {lvl} full launch ({fl['form']}): {fl['avg_launch_us']:.1f} us, "
+            f"{fl['achieved']:.0f} GB/s ({100 * fl['frac']:.1f}%)")
     out["stream_copy_gbs"] = copy_bandwidth(torch)
     log(f"device copy: {out['stream_copy_gbs']:.0f} GB/s")
     if orc is not None:
