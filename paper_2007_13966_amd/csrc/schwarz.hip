@@ -1442,12 +1442,14 @@ __global__ void __launch_bounds__(NT, (BOX == 0 && NT == 256 && sizeof(VT) == 4)
 // row y of one box (the rows of a box on consecutive lanes).  Step t of the
 // forward sweep handles x = t - LB*y in every row, the schedule of the
 // one-box row sweep; a row's lower neighbours come from its own earlier
-// steps and, through the wavefront shifts, from the two rows below.  A lane
-// zeroes what it passes on from its box's last row (forward; its first row
-// backward), so boxes side by side in one wavefront never exchange values;
-// the masks act before each shift, so every shift runs with all lanes of the
-// wavefront enabled (a shift that reads a disabled lane gets zero).  The
-// group runs for its longest box.
+// steps and, through the wavefront shifts, from the two rows below.  Every
+// shift runs with all lanes of the wavefront enabled, and values cross from
+// one box to the next unmasked: a box's factors towards rows outside it are
+// exact zeros (those couplings are not in A_i) and every shifted value is
+// finite (masked steps give zero), so a neighbouring box's rows contribute
+// nothing.  The group runs for its longest box.  The terms of a step on
+// outputs at least two steps old are summed for the next step while the
+// current step's dependent chain runs.
 // Factors are read from per-cell runs in global memory (lower run, then
 // upper run), RB steps ahead of the arithmetic; steps outside a row's range
 // read a cell clamped into the box and are masked.  Lanes without a row
@@ -1473,7 +1475,6 @@ __device__ __forceinline__ void packed_forward(const SubDev &sd, int y, int T, V
     const int cb = ye * (ex - LB);
     {
         const int tlo = on ? LB * ye : (1 << 28);
-        const bool fw = on && ye + 1 < ey;   // the next lane holds the next row of this box
         VT r0[RU], r1[RU], r2[RU];
 #pragma unroll
         for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
@@ -1490,14 +1491,30 @@ __device__ __forceinline__ void packed_forward(const SubDev &sd, int y, int T, V
                 rin[u] = rb[c];
             }
         };
+        // the terms on outputs at least two steps old, summed for the next
+        // step while this step's dependent chain runs
+        auto older = [&](int uu, const VT(&co)[NLP], VT rin) {
+            VT v = rin;
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                const int h = -(S::DX[q] + LB * S::DY[q]) - 1;
+                if (h == 0) continue;
+                const int slot = (uu - 1 - h + 2 * RU) % RU;
+                const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == -1 ? r1[slot] : r2[slot]);
+                v -= co[q] * val;
+            }
+            return v;
+        };
         auto step = [&](int b0, VT(&co)[RB][NLP], VT(&rin)[RB], int(&cc)[RB], bool(&aa)[RB]) {
-            VT outv[RB];
+            VT outv[RB], old[RB];
+            old[0] = older(b0, co[0], rin[0]);
 #pragma unroll
             for (int u = 0; u < RB; ++u) {
                 const int uu = b0 + u;
-                VT v = rin[u];
+                if (u + 1 < RB) old[u + 1] = older(uu + 1, co[u + 1], rin[u + 1]);
+                VT v = old[u];
 #pragma unroll
-                for (int pass = 0; pass < 3; ++pass) {
+                for (int pass = 1; pass < 3; ++pass) {
 #pragma unroll
                     for (int q = 0; q < NL; ++q) {
                         const int h = -(S::DX[q] + LB * S::DY[q]) - 1;
@@ -1510,9 +1527,8 @@ __device__ __forceinline__ void packed_forward(const SubDev &sd, int y, int T, V
                 const VT out = aa[u] ? v : (VT)0;
                 outv[u] = out;
                 r0[uu] = out;
-                const VT s1 = lane_shr(fw ? out : (VT)0);
-                r1[uu] = s1;
-                r2[uu] = lane_shr(fw ? s1 : (VT)0);
+                r1[uu] = lane_shr(out);
+                r2[uu] = lane_shr(r1[uu]);
             }
 #pragma unroll
             for (int u = 0; u < RB; ++u) *(aa[u] ? rb + cc[u] : spare) = outv[u];
@@ -1552,7 +1568,6 @@ __device__ __forceinline__ void packed_backward(const SubDev &sd, int y, int T, 
         // backward: x = Ts - 1 - t - LB*y, upper neighbours from the rows above
         const int cbb = cb + Ts - 1;
         const int tlob = on ? Ts - LB * ye - ex : (1 << 28);
-        const bool bw = on && ye >= 1;   // the previous lane holds the previous row of this box
         VT r0[RU], r1[RU], r2[RU];
 #pragma unroll
         for (int k = 0; k < RU; ++k) r0[k] = r1[k] = r2[k] = (VT)0;
@@ -1570,14 +1585,28 @@ __device__ __forceinline__ void packed_backward(const SubDev &sd, int y, int T, 
                 dg[u] = (VT)Ib[c];
             }
         };
+        auto older = [&](int uu, const VT(&co)[NUP], VT rin) {
+            VT v = rin;
+#pragma unroll
+            for (int q = NL; q < NS; ++q) {
+                const int h = S::DX[q] + LB * S::DY[q] - 1;
+                if (h == 0) continue;
+                const int slot = (uu - 1 - h + 2 * RU) % RU;
+                const VT val = S::DY[q] == 0 ? r0[slot] : (S::DY[q] == 1 ? r1[slot] : r2[slot]);
+                v -= co[q - NL] * val;
+            }
+            return v;
+        };
         auto step = [&](int b0, VT(&co)[RB][NUP], VT(&rin)[RB], VT(&dg)[RB], int(&cc)[RB], bool(&aa)[RB]) {
-            VT outv[RB];
+            VT outv[RB], old[RB];
+            old[0] = older(b0, co[0], rin[0]);
 #pragma unroll
             for (int u = 0; u < RB; ++u) {
                 const int uu = b0 + u;
-                VT v = rin[u];
+                if (u + 1 < RB) old[u + 1] = older(uu + 1, co[u + 1], rin[u + 1]);
+                VT v = old[u];
 #pragma unroll
-                for (int pass = 0; pass < 3; ++pass) {
+                for (int pass = 1; pass < 3; ++pass) {
 #pragma unroll
                     for (int q = NL; q < NS; ++q) {
                         const int h = S::DX[q] + LB * S::DY[q] - 1;
@@ -1590,9 +1619,8 @@ __device__ __forceinline__ void packed_backward(const SubDev &sd, int y, int T, 
                 const VT out = aa[u] ? v * dg[u] : (VT)0;
                 outv[u] = out;
                 r0[uu] = out;
-                const VT s1 = lane_shl(bw ? out : (VT)0);
-                r1[uu] = s1;
-                r2[uu] = lane_shl(bw ? s1 : (VT)0);
+                r1[uu] = lane_shl(out);
+                r2[uu] = lane_shl(r1[uu]);
             }
 #pragma unroll
             for (int u = 0; u < RB; ++u) *(aa[u] ? rb + cc[u] : spare) = outv[u];
