@@ -444,6 +444,8 @@ def main():
     ap.add_argument("--ratio", type=int, default=0, help="coarse-to-fine ratio (0: the workload's)")
     ap.add_argument("--coarse-op", default="", choices=["", "galerkin", "rediscretised"],
                     help="coarse operators: Galerkin products or the upscaled problem's Jacobian")
+    ap.add_argument("--coarse-kernel", default="", choices=["", "auto", "chunked", "persistent"],
+                    help="form of the coarsest level's GMRES (empty: the workload's)")
     ap.add_argument("--apply-level", type=int, default=-1, metavar="L",
                     help="only run the one-level sweeps of level L over the whole workload (the tuned "
                          "defaults, no masks) --repeats times, for hardware counter passes, and exit")
@@ -474,6 +476,8 @@ def main():
         case = S.with_solver(case, ratio=args.ratio)
     if args.coarse_op:
         case = S.with_solver(case, coarse_op=args.coarse_op)
+    if args.coarse_kernel:
+        case = S.with_solver(case, coarse_kernel=args.coarse_kernel)
     ncheck = min(case.nsteps, 3) if args.cpu_steps <= 0 else args.cpu_steps
 
     # the oracle first: its workers are forked before anything touches the GPU
