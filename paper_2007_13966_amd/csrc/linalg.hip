@@ -97,15 +97,17 @@ __device__ __forceinline__ double stencil_dot(const int *offp, int K, const doub
     return s;
 }
 
+// a workgroup per reduction chunk (a run of cells of one reservoir), so the
+// reservoir comes with the chunk
 template <int BS>
-__global__ void __launch_bounds__(256) k_spmv(SpmvArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
-    const int bi = find_blk(a.blk, a.B, i);
-    if (a.mask && !a.mask[bi]) return;
-    const Blk k = a.blk[bi];
-    const double s = stencil_dot<BS>(a.offp, a.K, a.coef, a.N, a.x, i, k);
-    a.y[i] = a.b ? a.b[i] - s : s;
+__global__ void __launch_bounds__(256) k_spmv(SpmvArgs a, const Chunk *chunks) {
+    const Chunk ch = chunks[blockIdx.x];
+    if (a.mask && !a.mask[ch.blk]) return;
+    const Blk k = a.blk[ch.blk];
+    for (int i = ch.start + (int)threadIdx.x; i < ch.end; i += blockDim.x) {
+        const double s = stencil_dot<BS>(a.offp, a.K, a.coef, a.N, a.x, i, k);
+        a.y[i] = a.b ? a.b[i] - s : s;
+    }
 }
 
 // y = |A| |x| (the componentwise magnitude of the product)
@@ -188,10 +190,11 @@ static SpmvArgs spmv_args(const Op &A, const double *x, double *y, const double 
 void launch_spmv(const Op &A, const double *x, double *y, const double *b, const int *mask,
                  hipStream_t s) {
     SpmvArgs a = spmv_args(A, x, y, b, mask);
+    const dim3 grid((unsigned)A.sp->hchunk.size());
     if (stencil_batch(a.K) == 8)
-        launch_timed("spmv", A.st.K <= 7 ? 0 : 1, k_spmv<8>, dim3(nblk(a.N, 256)), dim3(256), 0, s, a);
+        launch_timed("spmv", A.st.K <= 7 ? 0 : 1, k_spmv<8>, grid, dim3(256), 0, s, a, A.sp->chunk.p);
     else
-        launch_timed("spmv", A.st.K <= 7 ? 0 : 1, k_spmv<24>, dim3(nblk(a.N, 256)), dim3(256), 0, s, a);
+        launch_timed("spmv", A.st.K <= 7 ? 0 : 1, k_spmv<24>, grid, dim3(256), 0, s, a, A.sp->chunk.p);
     KCHECK();
 }
 
@@ -634,18 +637,19 @@ __global__ void __launch_bounds__(64) k_gm_solve_y(int B, GmDev st) {
     if (i == 0) st.upd[b] = k > 0;
 }
 
-// x += sum_{c < kdim} y[c] Zc   (or u = sum y[c] Vc when accumulate == 0)
-__global__ void k_gm_combine(const Blk *blk, int B, int N, const double *const *Z, double *x,
-                             GmDev st, int accumulate) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int b = find_blk(blk, B, i);
+// x += sum_{c < kdim} y[c] Zc   (or u = sum y[c] Vc when accumulate == 0),
+// a workgroup per reduction chunk
+__global__ void k_gm_combine(const Chunk *chunks, const double *const *Z, double *x, GmDev st, int accumulate) {
+    const Chunk ch = chunks[blockIdx.x];
+    const int b = ch.blk;
     const int k = st.kdim[b];
     if (k == 0) return;
     const double *y = st.y + (size_t)b * st.m;
-    double s = 0.0;
-    for (int c = 0; c < k; ++c) s += y[c] * Z[c][i];
-    x[i] = accumulate ? x[i] + s : s;
+    for (int i = ch.start + (int)threadIdx.x; i < ch.end; i += blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < k; ++c) s += y[c] * Z[c][i];
+        x[i] = accumulate ? x[i] + s : s;
+    }
 }
 
 // ---------------------------------------------------------------- host driver
@@ -746,7 +750,6 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
     const Space &S = *sp;
     const int nch = (int)S.hchunk.size();
     GmDev st = dev(o.rtol, o.atol, o.maxit);
-    const int NB = nblk(S.N, 256);
     double *P0 = red.part.p, *P1 = red.part.p + (size_t)nch * MAXCOL;
     // host flags per reservoir and iteration slot: 1 iterating, 2 converged,
     // 0 stopped for a restart (or at maxit); slot m: the start of a cycle
@@ -889,10 +892,10 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
         k_gm_solve_y<<<S.B, 64, 0, s>>>(S.B, st);
         KCHECK();
         if (flex) {
-            k_gm_combine<<<NB, 256, 0, s>>>(S.blk.p, S.B, S.N, zptr.p, x, st, 1);
+            k_gm_combine<<<nch, 256, 0, s>>>(S.chunk.p, zptr.p, x, st, 1);
             KCHECK();
         } else {
-            k_gm_combine<<<NB, 256, 0, s>>>(S.blk.p, S.B, S.N, Vp, w.p, st, 0);
+            k_gm_combine<<<nch, 256, 0, s>>>(S.chunk.p, Vp, w.p, st, 0);
             KCHECK();
             M(w.p, t.p, st.upd);
             launch_axpby(S, 1.0, t.p, 1.0, x, st.upd, s);   // x += M^{-1} V y

@@ -2754,13 +2754,11 @@ struct XferArgs {
 // r_c = P^T r_f (gather over the fine support of each coarse cell).  The
 // x list of the coarse column sits in registers (up to XM entries) so that a
 // fine row's loads go out together; longer lists take the plain loops.
+// A workgroup per reduction chunk of the coarse level (a run of cells of one
+// reservoir), so the reservoir comes with the chunk.
 constexpr int XM = 16;
-__global__ void k_restrict(XferArgs a, const double *rf, double *rc) {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= a.Nc) return;
-    const int b = find_blk(a.cblk, a.B, I);
-    if (a.mask && !a.mask[b]) return;
-    const Blk cb = a.cblk[b], fb = a.fblk[b];
+__device__ __forceinline__ void restrict_cell(const XferArgs &a, int b, const Blk &cb, const Blk &fb, int I,
+                                              const double *rf, double *rc) {
     const int l = I - cb.off;
     const int X = l % cb.nx, Y = (l / cb.nx) % cb.ny, Z = l / (cb.nx * cb.ny);
     const int cx = a.coff[0][b] + X, cy = a.coff[1][b] + Y, cz = a.coff[2][b] + Z;
@@ -2809,14 +2807,18 @@ __global__ void k_restrict(XferArgs a, const double *rf, double *rc) {
     rc[I] = s;
 }
 
-// z_f += P e_c: rows of P hold at most four entries per direction, all
-// loaded before the sum
-__global__ void k_prolong_add(XferArgs a, const double *ec, double *zf) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.Nf) return;
-    const int b = find_blk(a.fblk, a.B, i);
+__global__ void k_restrict(XferArgs a, const Chunk *chunks, const double *rf, double *rc) {
+    const Chunk ch = chunks[blockIdx.x];
+    const int b = ch.blk;
     if (a.mask && !a.mask[b]) return;
     const Blk cb = a.cblk[b], fb = a.fblk[b];
+    for (int I = ch.start + (int)threadIdx.x; I < ch.end; I += blockDim.x) restrict_cell(a, b, cb, fb, I, rf, rc);
+}
+
+// z_f += P e_c: rows of P hold at most four entries per direction, all
+// loaded before the sum; a workgroup per reduction chunk of the fine level
+__device__ __forceinline__ void prolong_cell(const XferArgs &a, int b, const Blk &cb, const Blk &fb, int i,
+                                             const double *ec, double *zf) {
     const int l = i - fb.off;
     const int x = l % fb.nx, y = (l / fb.nx) % fb.ny, z = l / (fb.nx * fb.ny);
     const int rx = a.roff[0][b] + x, ry = a.roff[1][b] + y, rz = a.roff[2][b] + z;
@@ -2851,6 +2853,14 @@ __global__ void k_prolong_add(XferArgs a, const double *ec, double *zf) {
         }
     }
     zf[i] = zi + s;
+}
+
+__global__ void k_prolong_add(XferArgs a, const Chunk *chunks, const double *ec, double *zf) {
+    const Chunk ch = chunks[blockIdx.x];
+    const int b = ch.blk;
+    if (a.mask && !a.mask[b]) return;
+    const Blk cb = a.cblk[b], fb = a.fblk[b];
+    for (int i = ch.start + (int)threadIdx.x; i < ch.end; i += blockDim.x) prolong_cell(a, b, cb, fb, i, ec, zf);
 }
 
 // Galerkin A_c = P^T A P, one wavefront per coarse cell I: the lanes share
@@ -3743,13 +3753,15 @@ void Ras::apply_level(int l, const double *r, double *z, const int *mask, bool a
 
 void Ras::restrict_to(int l, const double *rf, double *rc, const int *mask) {
     XferArgs a = xfer_args(*lev[l], *lev[l + 1], mask);
-    k_restrict<<<nblk(a.Nc, 256), 256, 0, g->s>>>(a, rf, rc);
+    const Space &C = *lev[l + 1]->spp;
+    k_restrict<<<(int)C.hchunk.size(), 256, 0, g->s>>>(a, C.chunk.p, rf, rc);
     KCHECK();
 }
 
 void Ras::prolong_add(int l, const double *ec, double *zf, const int *mask) {
     XferArgs a = xfer_args(*lev[l], *lev[l + 1], mask);
-    k_prolong_add<<<nblk(a.Nf, 256), 256, 0, g->s>>>(a, ec, zf);
+    const Space &F = *lev[l]->spp;
+    k_prolong_add<<<(int)F.hchunk.size(), 256, 0, g->s>>>(a, F.chunk.p, ec, zf);
     KCHECK();
 }
 
