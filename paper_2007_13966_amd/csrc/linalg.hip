@@ -250,15 +250,18 @@ __global__ void k_scale_blk(const Blk *blk, int B, int N, const double *x, const
 // workgroup of a reservoir obtains bitwise the same totals, independent of
 // the other reservoirs.  The first chunk of each reservoir commits shared
 // state.  The workgroup sums live in reduce.h.
-// partial dots of x with ncols vectors ys[c] (or ||x||^2 when square)
+// partial dots of x with ncols <= NC vectors ys[c] (or ||x||^2 when
+// square).  NC is a compile-time bound: the column reduction's LDS grows
+// with it, and a single column needs none of the wide form's
+template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_partials(const Chunk *chunks, const double *x,
                                                           const double *const *ys, int ncols, double *part,
                                                           const int *mask, int square) {
     const Chunk ch = chunks[blockIdx.x];
     const bool on = !mask || mask[ch.blk];
-    double acc[MAXCOL];
+    double acc[NC];
 #pragma unroll
-    for (int c = 0; c < MAXCOL; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     if (on) {
         for (int i = ch.start + threadIdx.x; i < ch.end; i += blockDim.x) {
             const double xi = x[i];
@@ -266,39 +269,42 @@ __global__ void __launch_bounds__(RED_THREADS) k_partials(const Chunk *chunks, c
                 acc[0] += xi * xi;
             } else {
 #pragma unroll
-                for (int c = 0; c < MAXCOL; ++c)
+                for (int c = 0; c < NC; ++c)
                     if (c < ncols) acc[c] += xi * ys[c][i];
             }
         }
     }
-    if (ncols == 1) chunk_columns<1>(acc, 1, part, gridDim.x);
-    else chunk_columns<MAXCOL>(acc, ncols, part, gridDim.x);
+    chunk_columns<NC>(acc, ncols, part, gridDim.x);
 }
 
 // one workgroup per reservoir: out[b*ncols + c]
+template <int NC>
 __global__ void __launch_bounds__(RED_THREADS) k_totals(const int *cfirst, const double *part, int ncols,
                                                         double *out, int ns) {
-    __shared__ double tot[MAXCOL];
+    __shared__ double tot[NC];
     const int b = blockIdx.x;
-    if (ncols == 1) block_totals<1>(part, cfirst[b], cfirst[b + 1], 1, tot, ns);
-    else block_totals<MAXCOL>(part, cfirst[b], cfirst[b + 1], ncols, tot, ns);
+    block_totals<NC>(part, cfirst[b], cfirst[b + 1], ncols, tot, ns);
     if ((int)threadIdx.x < ncols) out[(size_t)b * ncols + threadIdx.x] = tot[threadIdx.x];
 }
 
 void launch_block_dots(const Space &sp, Reducer &R, const double *x, const double *const *ys,
                        int ncols, double *out, const int *mask, hipStream_t s) {
     if (ncols > MAXCOL) fail(NKS_EINVAL, "at most %d columns per reduction", MAXCOL);
-    k_partials<<<(int)sp.hchunk.size(), RED_THREADS, 0, s>>>(sp.chunk.p, x, ys, ncols, R.part.p, mask, 0);
+    if (ncols == 1)
+        k_partials<1><<<(int)sp.hchunk.size(), RED_THREADS, 0, s>>>(sp.chunk.p, x, ys, 1, R.part.p, mask, 0);
+    else
+        k_partials<MAXCOL><<<(int)sp.hchunk.size(), RED_THREADS, 0, s>>>(sp.chunk.p, x, ys, ncols, R.part.p, mask, 0);
     KCHECK();
-    k_totals<<<sp.B, RED_THREADS, 0, s>>>(sp.cfirst.p, R.part.p, ncols, out, (int)sp.hchunk.size());
+    if (ncols == 1) k_totals<1><<<sp.B, RED_THREADS, 0, s>>>(sp.cfirst.p, R.part.p, 1, out, (int)sp.hchunk.size());
+    else k_totals<MAXCOL><<<sp.B, RED_THREADS, 0, s>>>(sp.cfirst.p, R.part.p, ncols, out, (int)sp.hchunk.size());
     KCHECK();
 }
 
 void launch_block_norm2(const Space &sp, Reducer &R, const double *x, double *out, const int *mask,
                         hipStream_t s) {
-    k_partials<<<(int)sp.hchunk.size(), RED_THREADS, 0, s>>>(sp.chunk.p, x, nullptr, 1, R.part.p, mask, 1);
+    k_partials<1><<<(int)sp.hchunk.size(), RED_THREADS, 0, s>>>(sp.chunk.p, x, nullptr, 1, R.part.p, mask, 1);
     KCHECK();
-    k_totals<<<sp.B, RED_THREADS, 0, s>>>(sp.cfirst.p, R.part.p, 1, out, (int)sp.hchunk.size());
+    k_totals<1><<<sp.B, RED_THREADS, 0, s>>>(sp.cfirst.p, R.part.p, 1, out, (int)sp.hchunk.size());
     KCHECK();
 }
 
@@ -530,35 +536,20 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_finish(const Chunk *chunks, 
     // the lead chunk's first thread applies the rotations before its share
     // of the vector work (the Givens step needs only the totals)
     if (lead && threadIdx.x == 0) {
-        // column j (h1 + h2) and the previous rotations in registers;
-        // out-of-range entries are replaced
-        double hcol[NC + 1], cc[NC], ss[NC];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            hcol[k] = k <= j ? gv[k] + hc[k] : 0.0;
-            cc[k] = k < j ? gv[NC + k] : 1.0;
-            ss[k] = k < j ? gv[2 * NC + k] : 0.0;
+        // column j (h1 + h2) down the previous rotations, one pair of
+        // entries at a time (entry k + 1 is still unrotated when rotation k
+        // reaches it), straight from LDS: no register copy of the column
+        double a0 = gv[0] + hc[0];
+        for (int k = 0; k < j; ++k) {
+            const double a1 = gv[k + 1] + hc[k + 1];
+            const double ck = gv[NC + k], sk = gv[2 * NC + k];
+            H[(size_t)k * m + j] = ck * a0 + sk * a1;
+            a0 = -sk * a0 + ck * a1;
         }
-        hcol[NC] = 0.0;
         const double gj = gv[3 * NC];
-#pragma unroll
-        for (int k = 0; k < NC - 1; ++k) {
-            if (k < j) {
-                const double a0 = hcol[k], a1 = hcol[k + 1];
-                hcol[k] = cc[k] * a0 + ss[k] * a1;
-                hcol[k + 1] = -ss[k] * a0 + cc[k] * a1;
-            }
-        }
-        double a0 = 0.0;
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-            if (k == j) a0 = hcol[k];
         const double den = sqrt(a0 * a0 + hn * hn);
         const double c = den > 0.0 ? a0 / den : 1.0;
         const double sg = den > 0.0 ? hn / den : 0.0;
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-            if (k < j) H[(size_t)k * m + j] = hcol[k];
         H[(size_t)j * m + j] = den;
         H[(size_t)(j + 1) * m + j] = 0.0;
         cs[j] = c;
