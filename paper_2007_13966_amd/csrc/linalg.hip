@@ -22,6 +22,7 @@ void Space::build(Alloc *al, const std::vector<Blk> &b, hipStream_t s) {
     N = 0;
     hchunk.clear();
     hcfirst.assign(B + 1, 0);
+    htile.clear();
     for (int k = 0; k < B; ++k) {
         hblk[k].off = N;
         const int n = b[k].nx * b[k].ny * b[k].nz;
@@ -30,12 +31,14 @@ void Space::build(Alloc *al, const std::vector<Blk> &b, hipStream_t s) {
         const int cs = (n + nch - 1) / nch;
         hcfirst[k] = (int)hchunk.size();
         for (int c = 0; c < n; c += cs) hchunk.push_back({k, N + c, N + std::min(n, c + cs), 0});
+        for (int c = 0; c < n; c += TILE) htile.push_back({k, N + c, N + std::min(n, c + TILE), 0});
         N += n;
     }
     hcfirst[B] = (int)hchunk.size();
     blk.upload(al, hblk, s);
     chunk.upload(al, hchunk, s);
     cfirst.upload(al, hcfirst, s);
+    tile.upload(al, htile, s);
 }
 
 void Reducer::ensure(Alloc *al, const Space &sp, int cols, hipStream_t s) {
@@ -72,7 +75,7 @@ static inline int stencil_batch(int K) { return K <= 8 ? 8 : 24; }
 // skipped.  Loads are issued B points at a time; the linear offsets of the
 // points are uniform (scalar) and the coefficient rows are addressed from
 // scalar bases.
-template <int B>
+template <int B, bool ABS = false>
 __device__ __forceinline__ double stencil_dot(const int *offp, int K, const double *coef, size_t N,
                                               const double *x, int i, const Blk &k) {
     double s = 0.0;
@@ -88,8 +91,8 @@ __device__ __forceinline__ double stencil_dot(const int *offp, int K, const doub
                       dz = (int)(int8_t)((o >> 16) & 0xff);
             const int j = min(max(i + dx + nx * dy + nxy * dz, lo), hi);
             const double c = coef[(size_t)q * N + i];
-            xv[u] = x[j];
-            cv[u] = q0 + u < K ? c : 0.0;
+            xv[u] = ABS ? fabs(x[j]) : x[j];
+            cv[u] = q0 + u < K ? (ABS ? fabs(c) : c) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < B; ++u) s += cv[u] * xv[u];
@@ -97,8 +100,8 @@ __device__ __forceinline__ double stencil_dot(const int *offp, int K, const doub
     return s;
 }
 
-// a workgroup per reduction chunk (a run of cells of one reservoir), so the
-// reservoir comes with the chunk
+// a workgroup per tile (a run of at most TILE cells of one reservoir), so the
+// reservoir comes with the tile
 template <int BS>
 __global__ void __launch_bounds__(256) k_spmv(SpmvArgs a, const Chunk *chunks) {
     const Chunk ch = chunks[blockIdx.x];
@@ -110,22 +113,14 @@ __global__ void __launch_bounds__(256) k_spmv(SpmvArgs a, const Chunk *chunks) {
     }
 }
 
-// y = |A| |x| (the componentwise magnitude of the product)
-__global__ void k_spmv_abs(SpmvArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
-    const int bi = find_blk(a.blk, a.B, i);
-    const Blk k = a.blk[bi];
-    const int l = i - k.off;
-    const int x = l % k.nx, y = (l / k.nx) % k.ny, z = l / (k.nx * k.ny);
-    double s = 0.0;
-    for (int q = 0; q < a.K; ++q) {
-        const int dx = a.off[3 * q], dy = a.off[3 * q + 1], dz = a.off[3 * q + 2];
-        const int xx = x + dx, yy = y + dy, zz = z + dz;
-        if (xx < 0 || xx >= k.nx || yy < 0 || yy >= k.ny || zz < 0 || zz >= k.nz) continue;
-        s += fabs(a.coef[(size_t)q * a.N + i]) * fabs(a.x[i + dx + k.nx * (dy + k.ny * dz)]);
-    }
-    a.y[i] = s;
+// y = |A| |x| (the componentwise magnitude of the product), a workgroup
+// per tile; a neighbour outside the reservoir adds |0| |x_j|
+template <int BS>
+__global__ void __launch_bounds__(256) k_spmv_abs(SpmvArgs a, const Chunk *chunks) {
+    const Chunk ch = chunks[blockIdx.x];
+    const Blk k = a.blk[ch.blk];
+    for (int i = ch.start + (int)threadIdx.x; i < ch.end; i += blockDim.x)
+        a.y[i] = stencil_dot<BS, true>(a.offp, a.K, a.coef, a.N, a.x, i, k);
 }
 
 // AT = A^T on the same stencil: AT[q][i] = A[opp(q)][i + off_q] (zero where the
@@ -190,17 +185,19 @@ static SpmvArgs spmv_args(const Op &A, const double *x, double *y, const double 
 void launch_spmv(const Op &A, const double *x, double *y, const double *b, const int *mask,
                  hipStream_t s) {
     SpmvArgs a = spmv_args(A, x, y, b, mask);
-    const dim3 grid((unsigned)A.sp->hchunk.size());
+    const dim3 grid((unsigned)A.sp->htile.size());
     if (stencil_batch(a.K) == 8)
-        launch_timed("spmv", A.st.K <= 7 ? 0 : 1, k_spmv<8>, grid, dim3(256), 0, s, a, A.sp->chunk.p);
+        launch_timed("spmv", A.st.K <= 7 ? 0 : 1, k_spmv<8>, grid, dim3(TILE), 0, s, a, A.sp->tile.p);
     else
-        launch_timed("spmv", A.st.K <= 7 ? 0 : 1, k_spmv<24>, grid, dim3(256), 0, s, a, A.sp->chunk.p);
+        launch_timed("spmv", A.st.K <= 7 ? 0 : 1, k_spmv<24>, grid, dim3(TILE), 0, s, a, A.sp->tile.p);
     KCHECK();
 }
 
 void launch_spmv_abs(const Op &A, const double *x, double *y, hipStream_t s) {
     SpmvArgs a = spmv_args(A, x, y, nullptr, nullptr);
-    k_spmv_abs<<<nblk(a.N, 256), 256, 0, s>>>(a);
+    const int nt = (int)A.sp->htile.size();
+    if (stencil_batch(a.K) == 8) k_spmv_abs<8><<<nt, TILE, 0, s>>>(a, A.sp->tile.p);
+    else k_spmv_abs<24><<<nt, TILE, 0, s>>>(a, A.sp->tile.p);
     KCHECK();
 }
 
@@ -629,7 +626,7 @@ __global__ void __launch_bounds__(64) k_gm_solve_y(int B, GmDev st) {
 }
 
 // x += sum_{c < kdim} y[c] Zc   (or u = sum y[c] Vc when accumulate == 0),
-// a workgroup per reduction chunk
+// a workgroup per tile
 __global__ void k_gm_combine(const Chunk *chunks, const double *const *Z, double *x, GmDev st, int accumulate) {
     const Chunk ch = chunks[blockIdx.x];
     const int b = ch.blk;
@@ -883,10 +880,10 @@ void Gmres::solve(const MatVec &A, const Precond &M, const double *b, double *x,
         k_gm_solve_y<<<S.B, 64, 0, s>>>(S.B, st);
         KCHECK();
         if (flex) {
-            k_gm_combine<<<nch, 256, 0, s>>>(S.chunk.p, zptr.p, x, st, 1);
+            k_gm_combine<<<(int)S.htile.size(), TILE, 0, s>>>(S.tile.p, zptr.p, x, st, 1);
             KCHECK();
         } else {
-            k_gm_combine<<<nch, 256, 0, s>>>(S.chunk.p, Vp, w.p, st, 0);
+            k_gm_combine<<<(int)S.htile.size(), TILE, 0, s>>>(S.tile.p, Vp, w.p, st, 0);
             KCHECK();
             M(w.p, t.p, st.upd);
             launch_axpby(S, 1.0, t.p, 1.0, x, st.upd, s);   // x += M^{-1} V y

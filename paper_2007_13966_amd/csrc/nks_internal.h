@@ -86,6 +86,7 @@ struct Chunk {
 constexpr int CHUNK = 256;       // minimum cells per reduction chunk
 constexpr int MAXCH = 256;       // at most this many chunks per reservoir (one per reduction thread)
 constexpr int RED_THREADS = 256;
+constexpr int TILE = 256;        // cells per elementwise workgroup
 constexpr int MAXB = 4096;       // reservoirs per grid
 
 // Vector space of one level: N cells in B blocks plus its reduction chunks.
@@ -97,6 +98,10 @@ struct Space {
     DBuf<Chunk> chunk;
     std::vector<int> hcfirst;    // first chunk of each block, B+1 entries
     DBuf<int> cfirst;
+    // runs of at most TILE cells inside one block: a workgroup each for the
+    // elementwise and stencil kernels (chunks can be much longer)
+    std::vector<Chunk> htile;
+    DBuf<Chunk> tile;
     void build(Alloc *al, const std::vector<Blk> &b, hipStream_t s);
 };
 

@@ -2754,8 +2754,8 @@ struct XferArgs {
 // r_c = P^T r_f (gather over the fine support of each coarse cell).  The
 // x list of the coarse column sits in registers (up to XM entries) so that a
 // fine row's loads go out together; longer lists take the plain loops.
-// A workgroup per reduction chunk of the coarse level (a run of cells of one
-// reservoir), so the reservoir comes with the chunk.
+// A workgroup per tile of the coarse level (a run of at most TILE cells of
+// one reservoir), so the reservoir comes with the tile.
 constexpr int XM = 16;
 __device__ __forceinline__ void restrict_cell(const XferArgs &a, int b, const Blk &cb, const Blk &fb, int I,
                                               const double *rf, double *rc) {
@@ -2816,7 +2816,7 @@ __global__ void k_restrict(XferArgs a, const Chunk *chunks, const double *rf, do
 }
 
 // z_f += P e_c: rows of P hold at most four entries per direction, all
-// loaded before the sum; a workgroup per reduction chunk of the fine level
+// loaded before the sum; a workgroup per tile of the fine level
 __device__ __forceinline__ void prolong_cell(const XferArgs &a, int b, const Blk &cb, const Blk &fb, int i,
                                              const double *ec, double *zf) {
     const int l = i - fb.off;
@@ -3754,14 +3754,14 @@ void Ras::apply_level(int l, const double *r, double *z, const int *mask, bool a
 void Ras::restrict_to(int l, const double *rf, double *rc, const int *mask) {
     XferArgs a = xfer_args(*lev[l], *lev[l + 1], mask);
     const Space &C = *lev[l + 1]->spp;
-    k_restrict<<<(int)C.hchunk.size(), 256, 0, g->s>>>(a, C.chunk.p, rf, rc);
+    k_restrict<<<(int)C.htile.size(), TILE, 0, g->s>>>(a, C.tile.p, rf, rc);
     KCHECK();
 }
 
 void Ras::prolong_add(int l, const double *ec, double *zf, const int *mask) {
     XferArgs a = xfer_args(*lev[l], *lev[l + 1], mask);
     const Space &F = *lev[l]->spp;
-    k_prolong_add<<<(int)F.hchunk.size(), 256, 0, g->s>>>(a, F.chunk.p, ec, zf);
+    k_prolong_add<<<(int)F.htile.size(), TILE, 0, g->s>>>(a, F.tile.p, ec, zf);
     KCHECK();
 }
 
