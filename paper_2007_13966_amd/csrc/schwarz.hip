@@ -24,6 +24,7 @@
 #include <mutex>
 #include <set>
 #include <tuple>
+#include <type_traits>
 
 #include "schwarz.h"
 
@@ -2965,7 +2966,9 @@ struct Rap2Tabs {
     const double *tab[2];
 };
 
-template <int W>
+// KM: the fine stencil's compile-time bound (its loads for a cell go out
+// together; a 5-point operator keeps its registers, and its occupancy, low)
+template <int W, int KM>
 __global__ void __launch_bounds__(64 * W) k_rap2d(XferArgs a, Rap2Tabs tb, const double *Af, int Kf,
                                                   const int8_t *offf, int Rf, double *Ac, int Kc, const int8_t *offc,
                                                   int Rc, int wxm, int wym) {
@@ -3002,7 +3005,6 @@ __global__ void __launch_bounds__(64 * W) k_rap2d(XferArgs a, Rap2Tabs tb, const
         // the block are zero and the tables are zero off the supports (which
         // lie inside the block), so no term needs a bounds test: the Kf
         // loads of a cell go out together.
-        constexpr int KM = 25;
         const double *TJx = Tx + Rc * L.wg[0], *TJy = Ty + Rc * L.wg[1];
         for (int t = lane; t < WX * WY; t += 64) {
             const int ux = t % WX, uy = t / WX;
@@ -3370,8 +3372,15 @@ void Ras::factor(bool ilu) {
                                                                                                V.own.coef.p);
             KCHECK();
             Rap2Tabs tb{F.rap_cell.p, {F.rap_win[0].p, F.rap_win[1].p}, {F.rap_tab[0].p, F.rap_tab[1].p}};
-            void (*fr)(XferArgs, Rap2Tabs, const double *, int, const int8_t *, int, double *, int, const int8_t *,
-                       int, int, int) = W == 4 ? k_rap2d<4> : (W == 2 ? k_rap2d<2> : k_rap2d<1>);
+            using RapFn = void (*)(XferArgs, Rap2Tabs, const double *, int, const int8_t *, int, double *, int,
+                                   const int8_t *, int, int, int);
+            auto pick = [&](auto km) -> RapFn {
+                constexpr int KM = decltype(km)::value;
+                return W == 4 ? k_rap2d<4, KM> : (W == 2 ? k_rap2d<2, KM> : k_rap2d<1, KM>);
+            };
+            const int Kf = F.A->st.K;
+            RapFn fr = Kf <= 5 ? pick(std::integral_constant<int, 5>{})
+                               : (Kf <= 9 ? pick(std::integral_constant<int, 9>{}) : pick(std::integral_constant<int, 25>{}));
             set_lds((const void *)fr, W * per);
             launch_timed("rap", l, fr, dim3(nblk(Nc, W)), dim3(64 * W), W * per, s, a, tb, F.A->coef.p, F.A->st.K,
                          F.A->st.doff.p, F.A->st.R, V.own.coef.p, Kc, V.own.st.doff.p, F.rap_R, F.rap_wx, F.rap_wy);
