@@ -75,9 +75,9 @@ struct CellPos {
     int b, x, y, z, nx, ny, nz;
 };
 
-__device__ __forceinline__ CellPos cell_pos(const Blk *blk, int B, int i) {
+__device__ __forceinline__ CellPos cell_pos_in(const Blk *blk, int b, int i) {
     CellPos c;
-    c.b = find_blk(blk, B, i);
+    c.b = b;
     const Blk k = blk[c.b];
     const int l = i - k.off;
     c.nx = k.nx; c.ny = k.ny; c.nz = k.nz;
@@ -85,6 +85,10 @@ __device__ __forceinline__ CellPos cell_pos(const Blk *blk, int B, int i) {
     c.y = (l / k.nx) % k.ny;
     c.z = l / (k.nx * k.ny);
     return c;
+}
+
+__device__ __forceinline__ CellPos cell_pos(const Blk *blk, int B, int i) {
+    return cell_pos_in(blk, find_blk(blk, B, i), i);
 }
 
 // ---------------------------------------------------------------- setup kernels
@@ -174,6 +178,7 @@ __global__ void k_history(int N, double a, double b, double RT, const double *pn
 // ---------------------------------------------------------------- residual + Jacobian
 struct FluxArgs {
     const Blk *blk;
+    const Chunk *tiles;                    // k_flux: a workgroup per tile (a run of cells of one block)
     int B, N, dim;
     const double *geo, *tx, *ty, *tz, *pv, *src;
     const double *p, *m, *dm, *hist;
@@ -253,9 +258,10 @@ __device__ __forceinline__ void face(const FluxArgs &A, double pi, double mi, do
 }
 
 __global__ void k_flux(FluxArgs A) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.N) return;
-    const CellPos c = cell_pos(A.blk, A.B, i);
+    const Chunk ch = A.tiles[blockIdx.x];
+    const int i = ch.start + (int)threadIdx.x;
+    if (i >= ch.end) return;
+    const CellPos c = cell_pos_in(A.blk, ch.blk, i);
     const int sx = 1, sy = c.nx, sz = c.nx * c.ny;
     const double dz = A.geo[3 * c.b + 2];
     const double pi = A.p[i], mi = A.m[i], dmi = A.dm[i];
@@ -410,6 +416,7 @@ void grid_setup_kernels(Grid &g, const double *kx, const double *ky, const doubl
 static FluxArgs flux_args(Grid &g, const double *p, double dt, int order, double *F, double *J) {
     FluxArgs A;
     A.blk = g.sp.blk.p;
+    A.tiles = g.sp.tile.p;
     A.B = g.sp.B;
     A.N = g.sp.N;
     A.dim = g.dim;
@@ -454,7 +461,7 @@ void launch_props(Grid &g, const double *p) {
 // F (and J) at p, with the history term already in g.hist and props at p in g.m/g.dm
 void launch_flux(Grid &g, const double *p, double dt, int order, double *F, double *J) {
     FluxArgs A = flux_args(g, p, dt, order, F, J);
-    k_flux<<<nblk(A.N, 256), 256, 0, g.s>>>(A);
+    k_flux<<<(int)g.sp.htile.size(), TILE, 0, g.s>>>(A);
     KCHECK();
 }
 
@@ -473,7 +480,7 @@ void launch_residual_into(Grid &g, const double *p, const double *pn, const doub
     A.m = m;
     A.dm = dm;
     A.hist = hist;
-    k_flux<<<nblk(A.N, 256), 256, 0, g.s>>>(A);
+    k_flux<<<(int)g.sp.htile.size(), TILE, 0, g.s>>>(A);
     KCHECK();
 }
 
