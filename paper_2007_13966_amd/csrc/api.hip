@@ -178,13 +178,11 @@ void launch_adj_rhs(Grid &g, const double *pn, double dt, double c1, const doubl
 
 static inline int nblk(int n, int t) { return (n + t - 1) / t; }
 
-// pt = p + lam[b] s
-__global__ void k_trial(const Blk *blk, int B, int N, const double *p, const double *s, const double *lam,
-                        double *pt) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int b = find_blk(blk, B, i);
-    pt[i] = p[i] + lam[b] * s[i];
+// pt = p + lam[b] s, a workgroup per tile (a run of cells of one reservoir)
+__global__ void k_trial(const Chunk *tiles, const double *p, const double *s, const double *lam, double *pt) {
+    const Chunk ch = tiles[blockIdx.x];
+    const int i = ch.start + (int)threadIdx.x;
+    if (i < ch.end) pt[i] = p[i] + lam[ch.blk] * s[i];
 }
 
 __global__ void k_neg(int N, const double *x, double *y) {
@@ -192,10 +190,11 @@ __global__ void k_neg(int N, const double *x, double *y) {
     if (i < N) y[i] = -x[i];
 }
 
-__global__ void k_copy_mask(const Blk *blk, int B, int N, const double *x, double *y, const int *mask) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    if (mask[find_blk(blk, B, i)]) y[i] = x[i];
+// y = x on the reservoirs with mask[b] set, a workgroup per tile
+__global__ void k_copy_mask(const Chunk *tiles, const double *x, double *y, const int *mask) {
+    const Chunk ch = tiles[blockIdx.x];
+    const int i = ch.start + (int)threadIdx.x;
+    if (i < ch.end && mask[ch.blk]) y[i] = x[i];
 }
 
 __global__ void k_zero(int N, double *x) {
@@ -1207,7 +1206,7 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
             for (;; ++bt) {
                 for (int b = 0; b < B; ++b) W.h_lam[b] = lam[b];
                 HIPC(hipMemcpyAsync(W.lam.p, W.h_lam, 8 * B, hipMemcpyHostToDevice, s));
-                k_trial<<<nblk(N, 256), 256, 0, s>>>(g.sp.blk.p, B, N, p, W.s.p, W.lam.p, W.pt.p);
+                k_trial<<<(int)g.sp.htile.size(), TILE, 0, s>>>(g.sp.tile.p, p, W.s.p, W.lam.p, W.pt.p);
                 HIPC(hipMemsetAsync(g.flags.p, 0, sizeof(int) * B, s));
                 launch_props(g, W.pt.p);
                 launch_flux(g, W.pt.p, dt, order, W.Ft.p, nullptr);
@@ -1263,8 +1262,8 @@ int nks_newton_step(nks_grid *gh, double *p, const double *pn, const double *pnm
                 break;
             }
             // accept: p, F <- trial values on the active reservoirs
-            k_copy_mask<<<nblk(N, 256), 256, 0, s>>>(g.sp.blk.p, B, N, W.pt.p, p, W.mask.p);
-            k_copy_mask<<<nblk(N, 256), 256, 0, s>>>(g.sp.blk.p, B, N, W.Ft.p, W.F.p, W.mask.p);
+            k_copy_mask<<<(int)g.sp.htile.size(), TILE, 0, s>>>(g.sp.tile.p, W.pt.p, p, W.mask.p);
+            k_copy_mask<<<(int)g.sp.htile.size(), TILE, 0, s>>>(g.sp.tile.p, W.Ft.p, W.F.p, W.mask.p);
             if (nd->stol > 0.0) norms(p, xnorm);
             double fmax = 0.0;
             for (int b = 0; b < B; ++b) {

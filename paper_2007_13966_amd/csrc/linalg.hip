@@ -214,17 +214,17 @@ void launch_spmv_t(const Op &A, const double *x, double *y, const int *opp, hipS
 }
 
 // ---------------------------------------------------------------- elementwise
-__global__ void k_axpby(const Blk *blk, int B, int N, double a, const double *x, double b,
-                        double *y, const int *mask) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    if (mask && !mask[find_blk(blk, B, i)]) return;
+// a workgroup per tile (a run of cells of one reservoir)
+__global__ void k_axpby(const Chunk *tiles, double a, const double *x, double b, double *y, const int *mask) {
+    const Chunk ch = tiles[blockIdx.x];
+    const int i = ch.start + (int)threadIdx.x;
+    if (i >= ch.end || (mask && !mask[ch.blk])) return;
     y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
 }
 
 void launch_axpby(const Space &sp, double a, const double *x, double b, double *y, const int *mask,
                   hipStream_t s) {
-    k_axpby<<<nblk(sp.N, 256), 256, 0, s>>>(sp.blk.p, sp.B, sp.N, a, x, b, y, mask);
+    k_axpby<<<(int)sp.htile.size(), TILE, 0, s>>>(sp.tile.p, a, x, b, y, mask);
     KCHECK();
 }
 
