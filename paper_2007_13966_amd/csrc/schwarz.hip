@@ -2581,7 +2581,9 @@ __global__ void __launch_bounds__(NT) k_ras_rows3d(Rows3Args a) {
 // a_ij -= l u_qj for every upper slot of the neighbour's row whose column is
 // a template slot of row i.  Slots absent from the stencil take no
 // elimination and are stored as zero, so fill outside the pattern never
-// reaches a factor.  Factors are written k-major in lexicographic order.
+// reaches a factor.  Factors are written k-major in lexicographic order,
+// straight in their storage precision (off-diagonals FT, 1/u_ii DT),
+// rounded from the FP64 elimination.
 struct IluRowsArgs {
     const SubDev *sub;
     const Blk *blk;
@@ -2589,7 +2591,8 @@ struct IluRowsArgs {
     const int *amap;      // factor stencil index -> operator index (-1: fill, starts at zero)
     const double *A;      // K*N operator
     int N, NE, diag;      // diag: factor stencil index of the diagonal
-    double *w;            // K*NE factors (lexicographic per subdomain)
+    void *f;              // K*NE off-diagonal factors, FT (lexicographic per subdomain)
+    void *invd;           // NE reciprocal pivots, DT
     int *err;
 };
 
@@ -2603,7 +2606,7 @@ __host__ __device__ constexpr int row_slot(int dx, int dy) {
 }
 
 // LDS: next * (NS + 2) doubles
-template <int BOX>
+template <int BOX, typename FT, typename DT>
 __global__ void __launch_bounds__(256) k_ilu_rows(IluRowsArgs a) {
     using S = RowStencil<BOX>;
     constexpr int NS = S::NS, NL = S::NL, LB = S::LB;
@@ -2698,13 +2701,19 @@ __global__ void __launch_bounds__(256) k_ilu_rows(IluRowsArgs a) {
         if (bad) atomicOr(a.err, 1);
     }
     __syncthreads();
-    // factors out, k-major, cells contiguous
+    // factors out, k-major, cells contiguous; the diagonal as 1/u_ii
     const size_t fo = sd.fac_off;
-    for (int i = threadIdx.x; i < (NS + 1) * n; i += blockDim.x) {
+    FT *F = reinterpret_cast<FT *>(a.f);
+    DT *ID = reinterpret_cast<DT *>(a.invd);
+    for (int i = threadIdx.x; i < NS * n; i += blockDim.x) {
         const int q = i / n, c = i - q * n;
         const int k = kmap[q];
-        if (k >= 0) a.w[(size_t)k * a.NE + fo + c] = Wr[(size_t)c * RL + q];
+        if (k < 0) continue;
+        const double v = Wr[(size_t)c * RL + q];
+        if constexpr (sizeof(FT) == 2) F[(size_t)k * a.NE + fo + c] = to_bf16((float)v);
+        else F[(size_t)k * a.NE + fo + c] = (FT)v;
     }
+    for (int c = threadIdx.x; c < n; c += blockDim.x) ID[fo + c] = (DT)Wr[(size_t)c * RL + NS + 1];
 }
 
 // AS / right-RAS: z_g = sum over the boxes whose extension holds g (box order)
@@ -3428,22 +3437,41 @@ void Ras::factor(bool ilu) {
         fa.w = V.w64.p;
         fa.err = V.err.p;
         const int *perm = (V.rows2d || use_rows3d(*this, V)) ? V.lexg.p : nullptr;
+        bool stored = false;
         const int rl = V.box == 0 ? RowStencil<0>::NS + 2 : (V.box == 1 ? RowStencil<1>::NS + 2 : RowStencil<2>::NS + 2);
         const size_t sh_rows = sizeof(double) * (size_t)rl * V.max_next;
         if (V.rows2d && sh_rows <= (size_t)lds_bytes) {
             // 2D box in LDS, factored on the sweeps' wavefront schedule;
             // factors come out in lexicographic order
             IluRowsArgs ia{V.sub.p, V.spp->blk.p, V.slotmap.p, V.amap.p, V.A->coef.p, V.spp->N, V.next_total,
-                           V.fst.diag, V.w64.p, V.err.p};
-            void (*fr)(IluRowsArgs) =
-                V.box == 0 ? k_ilu_rows<0> : (V.box == 1 ? k_ilu_rows<1> : k_ilu_rows<2>);
+                           V.fst.diag, nullptr, nullptr, V.err.p};
+            auto pick = [&](auto ft, auto dt) -> void (*)(IluRowsArgs) {
+                using FT = decltype(ft);
+                using DT = decltype(dt);
+                return V.box == 0 ? k_ilu_rows<0, FT, DT>
+                                  : (V.box == 1 ? k_ilu_rows<1, FT, DT> : k_ilu_rows<2, FT, DT>);
+            };
+            void (*fr)(IluRowsArgs) = nullptr;
+            if (d.precision == NKS_FP64) {
+                fr = pick(double{}, double{});
+                ia.f = V.f64.p;
+                ia.invd = V.invd64.p;
+            } else if (d.precision == NKS_FP32) {
+                fr = pick(float{}, float{});
+                ia.f = V.f32.p;
+                ia.invd = V.invd32.p;
+            } else {
+                fr = pick(uint16_t{}, float{});
+                ia.f = V.f16.p;
+                ia.invd = V.invd32.p;
+            }
             set_lds((const void *)fr, sh_rows);
             // one wavefront eliminates; the box stencils' elimination holds
             // about 230 registers, so their workgroups are that one wavefront
             // alone (two rounds of the batch's coarse boxes instead of five)
             launch_timed("ilu_factor", l, fr, dim3(V.nsub), dim3(V.box == 0 ? 256 : 64), sh_rows, s, ia);
             KCHECK();
-            perm = nullptr;
+            stored = true;
         } else {
         const size_t sh_lds = sizeof(double) * (size_t)fa.K * V.max_next +
                               sizeof(int) * ((size_t)V.max_tile + V.max_nlev + 1 + 2 * (size_t)fa.K + 1 +
@@ -3472,7 +3500,9 @@ void Ras::factor(bool ilu) {
         }
         }
         const int NE = V.next_total;
-        if (d.precision == NKS_FP64) {
+        if (stored) {
+            // the row factorisation wrote the storage precision itself
+        } else if (d.precision == NKS_FP64) {
             k_ilu_store<double, double><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, V.f64.p, V.invd64.p, perm);
         } else if (d.precision == NKS_FP32) {
             k_ilu_store<float, float><<<nblk(NE, 256), 256, 0, s>>>(V.w64.p, NE, fa.K, fa.diag, V.f32.p, V.invd32.p, perm);
