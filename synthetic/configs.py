@@ -297,7 +297,7 @@ def case_batch64(nres=64, nmin=64, nmax=256, tile=32, overlap=2, ratio=4, coarse
     ratio are tunable (one overlap on both levels); the defaults are among the
     autotuner's choice on MI355X (tile 32, overlap 2, ratio 4).  The coarse
     GMRES runs in captured chunks of launches; its persistent form, at its own
-    best settings (ratio 8, overlap 1), runs about 8% slower here with a third
+    best settings (ratio 8, overlap 1), runs about 9% slower here with a third
     of the host waits."""
     rng = np.random.Generator(np.random.PCG64(4000))
     probs = []
