@@ -2783,9 +2783,12 @@ __device__ __forceinline__ void restrict_cell(const XferArgs &a, int b, const Bl
             fxs[q] = a.ci[0][cx * a.cs[0] + qq];
             wxs[q] = q < nqx ? a.cw[0][cx * a.cs[0] + qq] : 0.0;
         }
-        for (int qz = 0; qz < a.ccnt[2][cz]; ++qz) {
-            const int fz = a.ci[2][cz * a.cs[2] + qz];
-            const double wz = a.cw[2][cz * a.cs[2] + qz];
+        // a 2D reservoir's z column is the single entry (0, 1): not loaded
+        const bool flat = fb.nz == 1;
+        const int nqz = flat ? 1 : a.ccnt[2][cz];
+        for (int qz = 0; qz < nqz; ++qz) {
+            const int fz = flat ? 0 : a.ci[2][cz * a.cs[2] + qz];
+            const double wz = flat ? 1.0 : a.cw[2][cz * a.cs[2] + qz];
             for (int qy = 0; qy < a.ccnt[1][cy]; ++qy) {
                 const int fy = a.ci[1][cy * a.cs[1] + qy];
                 const double wyz = a.cw[1][cy * a.cs[1] + qy] * wz;
@@ -2835,13 +2838,24 @@ __device__ __forceinline__ void prolong_cell(const XferArgs &a, int b, const Blk
     int n[3], J[3][4];
     double w[3][4];
     const int r[3] = {rx, ry, rz};
+    // a 2D reservoir's z row is the single entry (0, 1): not loaded
+    const int nd = fb.nz == 1 ? 2 : 3;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        n[d] = a.rcnt[d][r[d]];
+        if (d < nd) {
+            n[d] = a.rcnt[d][r[d]];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            J[d][q] = a.rj[d][r[d] * 4 + q];
-            w[d][q] = a.rw[d][r[d] * 4 + q];
+            for (int q = 0; q < 4; ++q) {
+                J[d][q] = a.rj[d][r[d] * 4 + q];
+                w[d][q] = a.rw[d][r[d] * 4 + q];
+            }
+        } else {
+            n[d] = 1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                J[d][q] = 0;
+                w[d][q] = q == 0 ? 1.0 : 0.0;
+            }
         }
     }
     const double zi = zf[i];
