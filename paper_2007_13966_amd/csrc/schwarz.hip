@@ -2766,7 +2766,8 @@ struct XferArgs {
 // fine row's loads go out together; longer lists take the plain loops.
 // A workgroup per tile of the coarse level (a run of at most TILE cells of
 // one reservoir), so the reservoir comes with the tile.
-constexpr int XM = 16;
+// XM is 8 or 16, the smallest that holds the level's longest x column.
+template <int XM>
 __device__ __forceinline__ void restrict_cell(const XferArgs &a, int b, const Blk &cb, const Blk &fb, int I,
                                               const double *rf, double *rc) {
     const int l = I - cb.off;
@@ -2820,12 +2821,14 @@ __device__ __forceinline__ void restrict_cell(const XferArgs &a, int b, const Bl
     rc[I] = s;
 }
 
+template <int XM>
 __global__ void k_restrict(XferArgs a, const Chunk *chunks, const double *rf, double *rc) {
     const Chunk ch = chunks[blockIdx.x];
     const int b = ch.blk;
     if (a.mask && !a.mask[b]) return;
     const Blk cb = a.cblk[b], fb = a.fblk[b];
-    for (int I = ch.start + (int)threadIdx.x; I < ch.end; I += blockDim.x) restrict_cell(a, b, cb, fb, I, rf, rc);
+    for (int I = ch.start + (int)threadIdx.x; I < ch.end; I += blockDim.x)
+        restrict_cell<XM>(a, b, cb, fb, I, rf, rc);
 }
 
 // z_f += P e_c: rows of P hold at most four entries per direction, all
@@ -3807,7 +3810,8 @@ void Ras::apply_level(int l, const double *r, double *z, const int *mask, bool a
 void Ras::restrict_to(int l, const double *rf, double *rc, const int *mask) {
     XferArgs a = xfer_args(*lev[l], *lev[l + 1], mask);
     const Space &C = *lev[l + 1]->spp;
-    k_restrict<<<(int)C.htile.size(), TILE, 0, g->s>>>(a, C.tile.p, rf, rc);
+    if (a.cs[0] <= 8) k_restrict<8><<<(int)C.htile.size(), TILE, 0, g->s>>>(a, C.tile.p, rf, rc);
+    else k_restrict<16><<<(int)C.htile.size(), TILE, 0, g->s>>>(a, C.tile.p, rf, rc);
     KCHECK();
 }
 
