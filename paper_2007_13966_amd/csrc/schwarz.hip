@@ -3354,7 +3354,8 @@ void Ras::build(Matrix *Jm, const nks_ras_desc &dd) {
         // geometry for kernels kept in hsub / lin_pad; remember tile dims
         tiles_.push_back(geo);
     }
-    if (L > 1) coarse.ensure(al, *lev[L - 1]->spp, std::max(1, std::min(d.coarse_restart, 30)), false, s);
+    // the coarse GMRES keeps M v_j per iteration (see coarse_solve)
+    if (L > 1) coarse.ensure(al, *lev[L - 1]->spp, std::max(1, std::min(d.coarse_restart, 30)), true, s);
     int dev = 0, maxlds = 65536;
     HIPC(hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -4046,7 +4047,11 @@ void Ras::coarse_solve(const double *b, double *x, const int *mask) {
     o.rtol = d.coarse_rtol;
     o.atol = 0.0;
     o.maxit = d.coarse_maxit;
-    o.flexible = false;
+    // the preconditioned basis z_j = M v_j is kept, so a cycle ends with
+    // x0 + Z y (the iterate x0 + M V y of right preconditioning, by the
+    // linearity of the fixed M) instead of a combination, one more sweep and
+    // an update
+    o.flexible = true;
     o.check_every = 1;
     o.graph_chunk = graph_chunk;
     // one Gram-Schmidt pass: a handful of iterations to a loose tolerance
