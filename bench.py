@@ -47,11 +47,11 @@ WORKLOADS = {"2d32": "case_2d_32", "2d512": "case_2d_512", "3d128": "case_3d_128
 PMC_SOURCE = "paper_2007_13966_amd/csrc/schwarz.hip"
 PMC_TRAFFIC = {
     ("batch64_2d_fp32prec", 0, 32, 2, 4): dict(
-        fetch_kib=40616.31, fetch_scale=2.0, write_kib=18313.65, write_scale=1.0, algorithmic=90197384.0,
-        sha1="4074cb2a5693d510dd0fa653c7a735a32119de42", kernel="k_ras_rows<float, float, float, 0, 256>"),
+        fetch_kib=40616.25, fetch_scale=2.0, write_kib=18313.64, write_scale=1.0, algorithmic=90197384.0,
+        sha1="542cfbcd8dcd61c81d7ff6a10d39e39cc7686e0a", kernel="k_ras_rows<float, float, float, 0, 256>"),
     ("batch64_2d_fp32prec", 1, 32, 2, 4): dict(
-        fetch_kib=14381.04, fetch_scale=2.0, write_kib=1240.42, write_scale=1.0, algorithmic=26957568.0,
-        sha1="4074cb2a5693d510dd0fa653c7a735a32119de42", kernel="k_ras_packed<float, float, float, 2>"),
+        fetch_kib=14383.76, fetch_scale=2.0, write_kib=1240.42, write_scale=1.0, algorithmic=26957568.0,
+        sha1="542cfbcd8dcd61c81d7ff6a10d39e39cc7686e0a", kernel="k_ras_packed<float, float, float, 2>"),
 }
 
 
